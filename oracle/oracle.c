@@ -1,0 +1,627 @@
+/* CPU oracle for SciFi Seeding + VELO-SciFi Matching (FP64).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path.
+ *
+ * It follows the paper's steps in the paper's order, one plain loop per step:
+ *   Sec. 3.3   XZ seeding: T1 x T3 doublets in the window of eq. tolHp shifted
+ *              by eq. alphacorr, third hit in T2 around the prediction of
+ *              Delta x2 = k3 c_x, extension to the remaining x-layers (1 mm),
+ *              least-squares fit of eq. trackequation with d_ratio fixed;
+ *   Sec. 3.3.4 O(n) clone killing with the score of eq. seed_clone_score;
+ *   Sec. 3.4   iterative UV seeding (2 mm, t_y averaging, y-z line fit);
+ *   Sec. 4     Matching: kink plane of eq. z_match (Table 1), y plane at
+ *              10 m, preselection, chi2_match, final clone removal.
+ * Where the paper is silent the documented reading is taken; each is marked
+ * READING below.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Layer roles (Sec. 1: x-u-v-x per station). */
+static const int X_LAYERS[6] = {0, 3, 4, 7, 8, 11};
+static const int UV_LAYERS[6] = {1, 2, 5, 6, 9, 10};
+/* READING: iteration 0 starts from the first x-layer of each station,
+ * iteration 1 from the last one (disjoint sets, Sec. 3.3). Order T1, T2, T3. */
+static const int INIT_LAYERS[2][3] = {{0, 4, 8}, {3, 7, 11}};
+static const int EXT_LAYERS[2][3] = {{3, 7, 11}, {0, 4, 8}};
+
+void orc_default_geom(orc_geom *g) {
+  static const double z[ORC_NL] = {7826.0, 7896.0, 7966.0, 8036.0, 8527.5, 8597.5,
+                                   8667.5, 8737.5, 9229.0, 9299.0, 9369.0, 9439.0};
+  const double t5 = tan(5.0 * M_PI / 180.0);
+  for (int l = 0; l < ORC_NL; ++l) {
+    g->z[l] = z[l];
+    int kind = l % 4; /* x u v x */
+    g->tan_a[l] = kind == 1 ? t5 : (kind == 2 ? -t5 : 0.0);
+  }
+  g->z_ref = 8525.0; /* Sec. 3.1 */
+}
+
+void orc_default_params(orc_params *p) {
+  memset(p, 0, sizeof(*p));
+  p->p_min = 3000.0;          /* Sec. 3.2: p_min > 3 GeV/c, in MeV */
+  p->invp_a = 1.6322e-7;      /* eq. invp; READING: per MeV/c (see DESIGN) */
+  p->invp_b = -5.0217e-12;
+  p->alpha0 = 2.180e6;        /* eq. alphacorr */
+  p->alpha1 = -1073.0;
+  p->d_ratio = -3.0e-4;       /* READING: value not printed */
+  p->kappa_c = 3.0e-3;        /* READING: third-hit band centre */
+  p->t2_tol0 = 0.5;           /* READING: third-hit band width */
+  p->t2_tol1 = 0.5;
+  p->ext_tol = 1.0;           /* Sec. 3.2: 1 mm */
+  p->min_x_hits = 5;          /* Sec. 3.2: at least 5 of 6 x-layers */
+  p->sigma_x = 0.07;          /* READING: hit resolution */
+  p->chi2x_max = 6.0;         /* READING: "bad chi2" */
+  p->uv_tol = 2.0;            /* Sec. 3.4: 2 mm */
+  p->y_max = 2500.0;          /* READING: selection window = the half's y range */
+  p->min_uv_hits = 4;         /* READING */
+  p->chi2y_max = 6.0;         /* READING */
+  p->zm[0] = 5287.6;          /* Table 1 */
+  p->zm[1] = -7.98878;
+  p->zm[2] = 317.683;
+  p->zm[3] = 0.0119379;
+  p->zm[4] = -1418.42;
+  p->z_ymatch = 10000.0;      /* Sec. 4: y matched at 10 m */
+  p->z_state = 9439.0;        /* READING: SciFi state at the last layer */
+  p->max_dx = 20.0;           /* Sec. 4.2 preselection */
+  p->max_dy = 150.0;
+  p->max_dtx = 1.5;
+  p->max_dty = 0.02;
+  p->tolx_scale = 4.0 / 5.0;  /* Sec. 4.2 tolerances */
+  p->tolx_a = 10.12;
+  p->tolx_b = 101.0;
+  p->toly_scale = 1.0 / 5.0;
+  p->toly_a = 1.59;
+  p->toly_b = 212.1;
+  p->tol_tx = 0.5;
+  p->tol_ty = 1.0 / 937.5;
+  p->chi2m_max = 2.0;
+  p->polarity = 1.0;
+}
+
+/* ---------------------------------------------------------- helpers ----- */
+
+/* g(u) = u^2 (1 + d_ratio u): the non-linear part of eq. trackequation. */
+static double gfun(double u, double d) { return u * u * (1.0 + d * u); }
+
+/* x(z) of eq. trackequation. */
+static double xmodel(double a, double b, double c, double z, double zref, double d) {
+  double u = z - zref;
+  return a + b * u + c * gfun(u, d);
+}
+
+/* First index i in [lo, hi) with x[i] >= v (x sorted ascending), else hi. */
+static int first_at_least(const float *x, int lo, int hi, double v) {
+  while (lo < hi) {
+    int mid = lo + (hi - lo) / 2;
+    if ((double)x[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+/* Closest hit to `pred` among hits of [lo, hi) inside [pred - tol, pred + tol];
+ * ties go to the lower position (READING).  Returns -1 if none. */
+static int closest_in_window(const float *x, int lo, int hi, double pred, double tol) {
+  int best = -1;
+  double bestd = 0.0;
+  for (int i = first_at_least(x, lo, hi, pred - tol); i < hi && (double)x[i] <= pred + tol; ++i) {
+    double d = fabs((double)x[i] - pred);
+    if (best < 0 || d < bestd) { best = i; bestd = d; }
+  }
+  return best;
+}
+
+/* Solve the 3x3 system A p = r by Gaussian elimination with partial pivoting. */
+static int solve3(double A[3][3], double r[3], double p[3]) {
+  for (int k = 0; k < 3; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < 3; ++i) if (fabs(A[i][k]) > fabs(A[piv][k])) piv = i;
+    if (A[piv][k] == 0.0) return -1;
+    if (piv != k) {
+      for (int j = 0; j < 3; ++j) { double t = A[k][j]; A[k][j] = A[piv][j]; A[piv][j] = t; }
+      double t = r[k]; r[k] = r[piv]; r[piv] = t;
+    }
+    for (int i = k + 1; i < 3; ++i) {
+      double f = A[i][k] / A[k][k];
+      for (int j = k; j < 3; ++j) A[i][j] -= f * A[k][j];
+      r[i] -= f * r[k];
+    }
+  }
+  for (int k = 2; k >= 0; --k) {
+    double s = r[k];
+    for (int j = k + 1; j < 3; ++j) s -= A[k][j] * p[j];
+    p[k] = s / A[k][k];
+  }
+  return 0;
+}
+
+/* Least-squares fit of eq. trackequation, x = a + b u + c g(u), u = z - z_ref,
+ * d_ratio fixed, equal weights (Sec. 3.2 last step).  The normal equations are
+ * written for the scaled basis [1, u/S, g(u)/S^2] (S = 1 m) so that they are
+ * well conditioned; the parameters are unscaled on return. */
+static int fit_xz(const double *z, const double *x, int n, double zref, double d,
+                  double *a, double *b, double *c) {
+  const double S = 1000.0;
+  double A[3][3] = {{0}}, r[3] = {0}, q[3];
+  for (int i = 0; i < n; ++i) {
+    double u = z[i] - zref;
+    double f[3] = {1.0, u / S, gfun(u, d) / (S * S)};
+    for (int j = 0; j < 3; ++j) {
+      r[j] += f[j] * x[i];
+      for (int k = 0; k < 3; ++k) A[j][k] += f[j] * f[k];
+    }
+  }
+  if (solve3(A, r, q)) return -1;
+  *a = q[0];
+  *b = q[1] / S;
+  *c = q[2] / (S * S);
+  return 0;
+}
+
+/* Weighted least-squares straight line y = y0 + t (z - z_ref) (Sec. 3.4). */
+static void fit_line(const double *z, const double *y, const double *w, int n, double zref,
+                     double *y0, double *t) {
+  double s0 = 0, s1 = 0, s2 = 0, r0 = 0, r1 = 0;
+  for (int i = 0; i < n; ++i) {
+    double u = z[i] - zref;
+    s0 += w[i]; s1 += w[i] * u; s2 += w[i] * u * u;
+    r0 += w[i] * y[i]; r1 += w[i] * u * y[i];
+  }
+  double det = s0 * s2 - s1 * s1;
+  *y0 = (r0 * s2 - r1 * s1) / det;
+  *t = (s0 * r1 - s1 * r0) / det;
+}
+
+/* ------------------------------------------------------ XZ seeding ------ */
+
+/* Window constants of one iteration, from the nominal z of its T1 and T3
+ * layers: out[0] = Delta x3^max of eq. tolHp (the T3 half-width for tracks
+ * above p_min), out[1] = alpha_corr of eq. alphacorr (the window-centre
+ * shift, READING: in mm). */
+static void window_constants(const orc_geom *g, const orc_params *P, int it, double out[2]) {
+  const double z1 = g->z[INIT_LAYERS[it][0]], z3 = g->z[INIT_LAYERS[it][2]];
+  const double a = P->invp_a, b = P->invp_b;
+  out[0] = (z3 - z1) / (2.0 * z1 * b) * (-a + sqrt(a * a + 4.0 * b / P->p_min));
+  const double k = z1 / (z3 - z1);
+  out[1] = P->alpha0 / (k * (P->p_min - P->alpha1));
+}
+
+/* Geometric factor of the third hit (Sec. 3.3.3), READING: the exact one of
+ * eq. trackequation: the deviation of the T2 hit from the T1-T3 chord is
+ * K3 * c_x with K3 = g(zb2) - g(zb1) - (z2 - z1)/(z3 - z1) (g(zb3) - g(zb1)). */
+static double k3_factor(double z1, double z2, double z3, double zr, double d) {
+  return gfun(z2 - zr, d) - gfun(z1 - zr, d) -
+         (z2 - z1) / (z3 - z1) * (gfun(z3 - zr, d) - gfun(z1 - zr, d));
+}
+
+void orc_window_constants(const orc_geom *g, const orc_params *p, int it, double out[3]) {
+  window_constants(g, p, it, out);
+  out[2] = k3_factor(g->z[INIT_LAYERS[it][0]], g->z[INIT_LAYERS[it][1]],
+                     g->z[INIT_LAYERS[it][2]], g->z_ref, p->d_ratio);
+}
+
+typedef struct { void *p; int n, cap; size_t sz; } dyn;
+static void *dyn_push(dyn *v) {
+  if (v->n == v->cap) {
+    v->cap = v->cap ? 2 * v->cap : 64;
+    v->p = realloc(v->p, (size_t)v->cap * v->sz);
+  }
+  return (char *)v->p + (size_t)(v->n++) * v->sz;
+}
+
+/* One iteration of the XZ seeding of one half of one event (Sec. 3.2, 3.3).
+ * Appends every three-hit combination, with the outcome of its extension and
+ * fit, to `out`, in the order (T1 hit, T3 hit, T2 hit). */
+static void xz_iteration(const orc_geom *g, const orc_params *P, const int32_t *off,
+                         const float *X, const float *Z, int half, int it, dyn *out) {
+  const int L1 = INIT_LAYERS[it][0], L2 = INIT_LAYERS[it][1], L3 = INIT_LAYERS[it][2];
+  const double z2 = g->z[L2], z3 = g->z[L3], zr = g->z_ref, d = P->d_ratio;
+  const double a = P->invp_a, b = P->invp_b;
+  double wc[2];
+  window_constants(g, P, it, wc);
+  const double dx3max = wc[0], alpha_corr = wc[1];
+  const int b1 = off[half * 12 + L1], e1 = off[half * 12 + L1 + 1];
+  const int b2 = off[half * 12 + L2], e2 = off[half * 12 + L2 + 1];
+  const int b3 = off[half * 12 + L3], e3 = off[half * 12 + L3 + 1];
+
+  for (int i1 = b1; i1 < e1; ++i1) {
+    const double x1 = X[i1], zh1 = Z[i1];
+    /* Two-hit window around the straight line from the origin through the T1
+     * hit, x3_inf = x1 z3 / z1, shifted by alpha_corr (Sec. 3.3.2). */
+    const double centre = (z3 + alpha_corr) / zh1 * x1;
+    const double lo3 = centre - dx3max, hi3 = centre + dx3max;
+    for (int i3 = first_at_least(X, b3, e3, lo3); i3 < e3 && (double)X[i3] <= hi3; ++i3) {
+      const double x3 = X[i3], zh3 = Z[i3];
+      /* Back-propagated x0 and the momentum estimate of eq. invp. */
+      const double t13 = (x3 - x1) / (zh3 - zh1);
+      const double x0 = x1 - zh1 * t13;
+      const double invp = a * fabs(x0) + b * x0 * x0;
+      /* Third-hit window (Sec. 3.3.3): Delta x2 = K3 c_x with K3 the exact
+       * geometric factor of eq. trackequation; c_x predicted from 1/p with
+       * the sign s = sign(x0) removed (READING: band centre kappa_c/p). */
+      const double s = x0 >= 0.0 ? 1.0 : -1.0;
+      const double c_pred = -s * P->kappa_c * invp;
+      const double K3 = k3_factor(zh1, z2, zh3, zr, d);
+      const double pred2 = x1 + (z2 - zh1) * t13 + K3 * c_pred;
+      const double tol2 = P->t2_tol0 + P->t2_tol1 * fabs(K3 * c_pred);
+      for (int i2 = first_at_least(X, b2, e2, pred2 - tol2); i2 < e2 && (double)X[i2] <= pred2 + tol2; ++i2) {
+        orc_cand *cd = (orc_cand *)dyn_push(out);
+        memset(cd, 0, sizeof(*cd));
+        cd->half = half;
+        cd->it = it;
+        for (int l = 0; l < ORC_NL; ++l) cd->pos[l] = -1;
+        cd->pos[L1] = i1; cd->pos[L2] = i2; cd->pos[L3] = i3;
+        /* Track model through the three hits (exact 3-point solve). */
+        const double x2 = X[i2], zh2 = Z[i2];
+        double zz[6], xx[6];
+        zz[0] = zh1; zz[1] = zh2; zz[2] = zh3;
+        xx[0] = x1; xx[1] = x2; xx[2] = x3;
+        double pa, pb, pc;
+        if (fit_xz(zz, xx, 3, zr, d, &pa, &pb, &pc)) { cd->status = 1; continue; }
+        /* Extension to the three remaining x-layers: closest hit within
+         * ext_tol of the model at the layer (Sec. 3.2). */
+        int n = 3;
+        for (int j = 0; j < 3; ++j) {
+          const int L = EXT_LAYERS[it][j];
+          const int lo = off[half * 12 + L], hi = off[half * 12 + L + 1];
+          const int h = closest_in_window(X, lo, hi, xmodel(pa, pb, pc, g->z[L], zr, d), P->ext_tol);
+          if (h >= 0) { cd->pos[L] = h; ++n; }
+        }
+        cd->n = n;
+        if (n < P->min_x_hits) { cd->status = 1; continue; }
+        /* Least-squares fit over all x hits in layer order. */
+        int m = 0;
+        for (int j = 0; j < 6; ++j) {
+          const int h = cd->pos[X_LAYERS[j]];
+          if (h >= 0) { zz[m] = Z[h]; xx[m] = X[h]; ++m; }
+        }
+        if (fit_xz(zz, xx, m, zr, d, &pa, &pb, &pc)) { cd->status = 2; continue; }
+        double chi2 = 0.0;
+        for (int j = 0; j < m; ++j) {
+          const double r = (xx[j] - xmodel(pa, pb, pc, zz[j], zr, d)) / P->sigma_x;
+          chi2 += r * r;
+        }
+        chi2 /= (double)(m - 3);
+        cd->a = pa; cd->b = pb; cd->c = pc; cd->chi2 = chi2;
+        /* eq. seed_clone_score, READING: |c_x| so that the score is >= 0. */
+        cd->score = (m == 6 ? 1.0 : 10.0) * (1000.0 * chi2 + fabs(pc));
+        cd->status = chi2 < P->chi2x_max ? 0 : 2;
+      }
+    }
+  }
+}
+
+int orc_xz_candidates(const orc_geom *g, const orc_params *p, const int32_t *zone_off,
+                      const float *x, const float *z, int half, int it,
+                      orc_cand *out, int cap) {
+  dyn v = {NULL, 0, 0, sizeof(orc_cand)};
+  xz_iteration(g, p, zone_off, x, z, half, it, &v);
+  int n = v.n;
+  if (out) memcpy(out, v.p, sizeof(orc_cand) * (size_t)(n < cap ? n : cap));
+  free(v.p);
+  return n;
+}
+
+/* ---------------------------------------------------- clone killing ----- */
+
+/* O(n) clone killing of Sec. 3.3.4 over the candidates of one half (both
+ * iterations).  Pass 1: every hit keeps the lowest score of the tracks that use
+ * it.  Pass 2: a track keeps the hits that still carry its own score, and
+ * survives with >= 3 of them, or >= 2 if it has 6 hits.  Then the repeated
+ * tracks of the two iterations (identical x-hit sets, Sec. 3) are removed,
+ * keeping the first iteration's copy.  n_pos bounds the hit positions used. */
+void orc_clone_vote(const orc_cand *c, int n, int n_pos, int32_t *keep) {
+  double *T = (double *)malloc(sizeof(double) * (size_t)(n_pos > 0 ? n_pos : 1));
+  for (int i = 0; i < n_pos; ++i) T[i] = INFINITY;
+  for (int i = 0; i < n; ++i)
+    for (int l = 0; l < ORC_NL; ++l) {
+      const int h = c[i].pos[l];
+      if (h >= 0 && c[i].score < T[h]) T[h] = c[i].score;
+    }
+  for (int i = 0; i < n; ++i) {
+    int own = 0;
+    for (int l = 0; l < ORC_NL; ++l) {
+      const int h = c[i].pos[l];
+      if (h >= 0 && T[h] == c[i].score) ++own;
+    }
+    keep[i] = own >= 3 || (own >= 2 && c[i].n == 6);
+  }
+  for (int i = 0; i < n; ++i) {
+    if (!keep[i] || c[i].it == 0) continue;
+    for (int j = 0; j < n; ++j) {
+      if (!keep[j] || c[j].it != 0) continue;
+      if (memcmp(c[i].pos, c[j].pos, sizeof(c[i].pos)) == 0) { keep[i] = 0; break; }
+    }
+  }
+  free(T);
+}
+
+/* -------------------------------------------------------- UV seeding ---- */
+
+/* Iterative UV seeding of Sec. 3.4 for one x-z track.  Two passes, from the
+ * u-layer then the v-layer of T1 (READING), each trying every hit of the
+ * initial layer whose y lies in the half; t_y from the origin, then the
+ * closest hit within uv_tol in each of the five other stereo layers in
+ * ascending z, averaging t_y after each found hit.  Each combination gets a
+ * weighted y-z line fit; the best has most hits, then lowest chi2_y, then the
+ * earlier (pass, initial hit).  Returns 1 and fills `out` if a seed is made. */
+int orc_uv(const orc_geom *g, const orc_params *P, const int32_t *off, const float *X,
+           const float *Z, const int32_t *ID, const orc_cand *cd, orc_seed *out) {
+  const int half = cd->half;
+  const double zr = g->z_ref, d = P->d_ratio;
+  const double ylo = half == 0 ? 0.0 : -P->y_max, yhi = half == 0 ? P->y_max : 0.0;
+  int best_n = 0;
+  double best_chi2 = 0.0, best_y0 = 0.0, best_ty = 0.0;
+  int best_pos[ORC_NL];
+  for (int pass = 0; pass < 2; ++pass) {
+    const int L0 = pass == 0 ? 1 : 2;
+    const double t0 = g->tan_a[L0];
+    const double xp = xmodel(cd->a, cd->b, cd->c, g->z[L0], zr, d);
+    const double e1 = xp - yhi * t0, e2 = xp - ylo * t0;
+    const double lo = e1 < e2 ? e1 : e2, hi = e1 < e2 ? e2 : e1;
+    const int b0 = off[half * 12 + L0], en0 = off[half * 12 + L0 + 1];
+    for (int h0 = first_at_least(X, b0, en0, lo); h0 < en0 && (double)X[h0] <= hi; ++h0) {
+      double zs[6], ys[6], ws[6];
+      int pos[ORC_NL];
+      for (int l = 0; l < ORC_NL; ++l) pos[l] = -1;
+      int n = 0;
+      const double zh0 = Z[h0];
+      const double y0h = (xmodel(cd->a, cd->b, cd->c, zh0, zr, d) - X[h0]) / t0;
+      double ty = y0h / zh0;
+      pos[L0] = h0;
+      zs[n] = zh0; ys[n] = y0h; ws[n] = t0 * t0 / (P->sigma_x * P->sigma_x); ++n;
+      for (int j = 0; j < 6; ++j) {
+        const int L = UV_LAYERS[j];
+        if (L == L0) continue;
+        const double zl = g->z[L], tl = g->tan_a[L];
+        const double pred = xmodel(cd->a, cd->b, cd->c, zl, zr, d) - ty * zl * tl;
+        const int h = closest_in_window(X, off[half * 12 + L], off[half * 12 + L + 1], pred, P->uv_tol);
+        if (h < 0) continue;
+        const double zh = Z[h];
+        const double yl = (xmodel(cd->a, cd->b, cd->c, zh, zr, d) - X[h]) / tl;
+        ty = 0.5 * (ty + yl / zh);
+        pos[L] = h;
+        zs[n] = zh; ys[n] = yl; ws[n] = tl * tl / (P->sigma_x * P->sigma_x); ++n;
+      }
+      if (n < P->min_uv_hits) continue;
+      double fy0, fty;
+      fit_line(zs, ys, ws, n, zr, &fy0, &fty);
+      double chi2 = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const double r = ys[i] - (fy0 + fty * (zs[i] - zr));
+        chi2 += ws[i] * r * r;
+      }
+      chi2 /= (double)(n - 2);
+      if (!(chi2 < P->chi2y_max)) continue;
+      if (n > best_n || (n == best_n && chi2 < best_chi2)) {
+        best_n = n; best_chi2 = chi2; best_y0 = fy0; best_ty = fty;
+        memcpy(best_pos, pos, sizeof(pos));
+      }
+    }
+  }
+  if (best_n == 0) return 0;
+  memset(out, 0, sizeof(*out));
+  out->a = cd->a; out->b = cd->b; out->c = cd->c;
+  out->y0 = best_y0; out->ty = best_ty;
+  out->chi2x = cd->chi2; out->chi2y = best_chi2; out->score = cd->score;
+  out->nx = cd->n; out->nuv = best_n; out->half = cd->half; out->it = cd->it;
+  for (int l = 0; l < ORC_NL; ++l) {
+    const int h = (g->tan_a[l] == 0.0) ? cd->pos[l] : best_pos[l];
+    out->pos[l] = h;
+    out->id[l] = h >= 0 ? ID[h] : -1;
+  }
+  return 1;
+}
+
+/* ---------------------------------------------------------- Matching ---- */
+
+typedef struct {
+  double chi2, zm, dx, dy, dtx, dty, qop;
+  int ok;
+} pair_eval;
+
+/* One VELO-seed combination (Sec. 4.1, 4.2). */
+static pair_eval eval_pair(const orc_params *P, const orc_geom *g, const orc_seed *s,
+                           double xv, double yv, double zv, double txv, double tyv) {
+  pair_eval r;
+  memset(&r, 0, sizeof(r));
+  const double zr = g->z_ref, d = P->d_ratio, zs = P->z_state;
+  /* SciFi state at z_s: position and slope of eq. trackequation. */
+  const double us = zs - zr;
+  const double xs = xmodel(s->a, s->b, s->c, zs, zr, d);
+  const double txs = s->b + s->c * (2.0 * us + 3.0 * d * us * us);
+  const double dtx = txs - txv;
+  /* eq. z_match: z of the kink. */
+  const double zm = P->zm[0] + P->zm[1] * fabs(dtx) + P->zm[2] * dtx * dtx +
+                    P->zm[3] * fabs(xs) + P->zm[4] * txv * txv;
+  const double dx = (xs + (zm - zs) * txs) - (xv + (zm - zv) * txv);
+  /* y: straight lines compared at z_y_match. */
+  const double dy = (s->y0 + s->ty * (P->z_ymatch - zr)) - (yv + tyv * (P->z_ymatch - zv));
+  const double dty = s->ty - tyv;
+  r.zm = zm; r.dx = dx; r.dy = dy; r.dtx = dtx; r.dty = dty;
+  if (!(fabs(dx) < P->max_dx && fabs(dy) < P->max_dy && fabs(dtx) < P->max_dtx &&
+        fabs(dty) < P->max_dty))
+    return r;
+  const double tolx = P->tolx_scale * (P->tolx_a * P->tolx_a + P->tolx_b * P->tolx_b * dtx * dtx);
+  const double rho = txv * txv + tyv * tyv;
+  const double toly = P->toly_scale * (P->toly_a * P->toly_a + P->toly_b * P->toly_b * rho);
+  const double chi2 = dx * dx / tolx + dy * dy / toly + dtx * dtx / P->tol_tx + dty * dty / P->tol_ty;
+  r.chi2 = chi2;
+  if (!(chi2 < P->chi2m_max)) return r;
+  /* Momentum from the kick (READING): eq. invp evaluated on the distance at
+   * z = 0 between the SciFi and VELO straight lines. */
+  const double x0 = (xs - zs * txs) - (xv - zv * txv);
+  const double invp = P->invp_a * fabs(x0) + P->invp_b * x0 * x0;
+  const double q = -(x0 >= 0.0 ? 1.0 : -1.0) * P->polarity;
+  r.qop = q * invp;
+  r.ok = 1;
+  return r;
+}
+
+/* All VELO x seed combinations of one event; a combination is kept when its
+ * chi2_match is the smallest both among the survivors sharing its seed and
+ * among those sharing its VELO track (READING of the final clone removal of
+ * Sec. 4.4, with chi2_match in place of the ghost probability). */
+int orc_match(const orc_geom *g, const orc_params *P, const orc_seed *seeds, int ns, int nv,
+              const float *vx, const float *vy, const float *vz, const float *vtx,
+              const float *vty, const int32_t *vid, orc_long *out, int cap) {
+  if (ns == 0 || nv == 0) return 0;
+  pair_eval *pe = (pair_eval *)malloc(sizeof(pair_eval) * (size_t)ns * (size_t)nv);
+  double *best_v = (double *)malloc(sizeof(double) * (size_t)nv);
+  double *best_s = (double *)malloc(sizeof(double) * (size_t)ns);
+  for (int v = 0; v < nv; ++v) best_v[v] = INFINITY;
+  for (int s = 0; s < ns; ++s) best_s[s] = INFINITY;
+  for (int v = 0; v < nv; ++v)
+    for (int s = 0; s < ns; ++s) {
+      pair_eval r = eval_pair(P, g, &seeds[s], vx[v], vy[v], vz[v], vtx[v], vty[v]);
+      pe[(size_t)v * ns + s] = r;
+      if (r.ok) {
+        if (r.chi2 < best_v[v]) best_v[v] = r.chi2;
+        if (r.chi2 < best_s[s]) best_s[s] = r.chi2;
+      }
+    }
+  int n = 0;
+  for (int v = 0; v < nv; ++v)
+    for (int s = 0; s < ns; ++s) {
+      const pair_eval *r = &pe[(size_t)v * ns + s];
+      if (!r->ok || r->chi2 != best_v[v] || r->chi2 != best_s[s]) continue;
+      if (n < cap) {
+        orc_long *L = &out[n];
+        L->velo_idx = v; L->velo_id = vid[v]; L->seed_idx = s; L->pad = 0;
+        L->qop = r->qop; L->chi2 = r->chi2; L->zm = r->zm;
+        L->dx = r->dx; L->dy = r->dy; L->dtx = r->dtx; L->dty = r->dty;
+      }
+      ++n;
+    }
+  free(pe); free(best_v); free(best_s);
+  return n;
+}
+
+/* ------------------------------------------------------- whole event ---- */
+
+typedef struct { dyn seeds, longs; } ev_out;
+
+static void run_event(const orc_geom *g, const orc_params *P, const int32_t *off,
+                      const float *X, const float *Z, const int32_t *ID, int nv,
+                      const float *vx, const float *vy, const float *vz, const float *vtx,
+                      const float *vty, const int32_t *vid, ev_out *o) {
+  o->seeds = (dyn){NULL, 0, 0, sizeof(orc_seed)};
+  o->longs = (dyn){NULL, 0, 0, sizeof(orc_long)};
+  const int n_pos = off[24];
+  for (int half = 0; half < 2; ++half) {
+    dyn c = {NULL, 0, 0, sizeof(orc_cand)};
+    xz_iteration(g, P, off, X, Z, half, 0, &c);
+    xz_iteration(g, P, off, X, Z, half, 1, &c);
+    /* the clone vote sees the candidates that passed the fit */
+    int m = 0;
+    orc_cand *cs = (orc_cand *)c.p;
+    for (int i = 0; i < c.n; ++i) if (cs[i].status == 0) cs[m++] = cs[i];
+    int32_t *keep = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    orc_clone_vote(cs, m, n_pos, keep);
+    for (int i = 0; i < m; ++i) {
+      if (!keep[i]) continue;
+      orc_seed sd;
+      if (orc_uv(g, P, off, X, Z, ID, &cs[i], &sd)) *(orc_seed *)dyn_push(&o->seeds) = sd;
+    }
+    free(keep);
+    free(c.p);
+  }
+  const int ns = o->seeds.n;
+  if (ns > 0 && nv > 0) {
+    int cap = ns < nv ? ns : nv;
+    cap = cap * 4 + 16;
+    orc_long *tmp = (orc_long *)malloc(sizeof(orc_long) * (size_t)cap);
+    int n = orc_match(g, P, (orc_seed *)o->seeds.p, ns, nv, vx, vy, vz, vtx, vty, vid, tmp, cap);
+    if (n > cap) {
+      free(tmp);
+      tmp = (orc_long *)malloc(sizeof(orc_long) * (size_t)n);
+      orc_match(g, P, (orc_seed *)o->seeds.p, ns, nv, vx, vy, vz, vtx, vty, vid, tmp, n);
+    }
+    for (int i = 0; i < n; ++i) *(orc_long *)dyn_push(&o->longs) = tmp[i];
+    free(tmp);
+  }
+}
+
+typedef struct {
+  const orc_geom *g;
+  const orc_params *P;
+  int n_events;
+  const int32_t *zone_off;
+  const float *hx, *hz;
+  const int32_t *hid;
+  const int32_t *velo_off;
+  const float *vx, *vy, *vz, *vtx, *vty;
+  const int32_t *vid;
+  ev_out *outs;
+  int next;
+  pthread_mutex_t mu;
+} job;
+
+static void *worker(void *arg) {
+  job *J = (job *)arg;
+  for (;;) {
+    pthread_mutex_lock(&J->mu);
+    int e = J->next++;
+    pthread_mutex_unlock(&J->mu);
+    if (e >= J->n_events) break;
+    int32_t off[25];
+    const int base = J->zone_off[e * 24];
+    for (int k = 0; k <= 24; ++k) off[k] = J->zone_off[e * 24 + k] - base;
+    const int v0 = J->velo_off[e], nv = J->velo_off[e + 1] - v0;
+    run_event(J->g, J->P, off, J->hx + base, J->hz + base, J->hid + base, nv,
+              J->vx + v0, J->vy + v0, J->vz + v0, J->vtx + v0, J->vty + v0, J->vid + v0,
+              &J->outs[e]);
+  }
+  return NULL;
+}
+
+int orc_run(const orc_geom *g, const orc_params *p, int n_events, const int32_t *zone_off,
+            const float *hx, const float *hz, const int32_t *hid, const int32_t *velo_off,
+            const float *vx, const float *vy, const float *vz, const float *vtx,
+            const float *vty, const int32_t *vid, int n_threads, orc_result *res) {
+  memset(res, 0, sizeof(*res));
+  if (n_events < 0) return -1;
+  job J = {g, p, n_events, zone_off, hx, hz, hid, velo_off, vx, vy, vz, vtx, vty, vid,
+           NULL, 0, PTHREAD_MUTEX_INITIALIZER};
+  J.outs = (ev_out *)calloc((size_t)(n_events > 0 ? n_events : 1), sizeof(ev_out));
+  if (n_threads < 1) n_threads = 1;
+  if (n_threads > 256) n_threads = 256;
+  pthread_t th[256];
+  for (int t = 0; t < n_threads; ++t) pthread_create(&th[t], NULL, worker, &J);
+  for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+  int64_t ns = 0, nl = 0;
+  for (int e = 0; e < n_events; ++e) { ns += J.outs[e].seeds.n; nl += J.outs[e].longs.n; }
+  res->n_seeds = ns;
+  res->n_longs = nl;
+  res->seed_off = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_events + 1));
+  res->long_off = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_events + 1));
+  res->seeds = (orc_seed *)malloc(sizeof(orc_seed) * (size_t)(ns > 0 ? ns : 1));
+  res->longs = (orc_long *)malloc(sizeof(orc_long) * (size_t)(nl > 0 ? nl : 1));
+  int64_t is = 0, il = 0;
+  for (int e = 0; e < n_events; ++e) {
+    res->seed_off[e] = (int32_t)is;
+    res->long_off[e] = (int32_t)il;
+    if (J.outs[e].seeds.n)
+      memcpy(res->seeds + is, J.outs[e].seeds.p, sizeof(orc_seed) * (size_t)J.outs[e].seeds.n);
+    if (J.outs[e].longs.n)
+      memcpy(res->longs + il, J.outs[e].longs.p, sizeof(orc_long) * (size_t)J.outs[e].longs.n);
+    is += J.outs[e].seeds.n;
+    il += J.outs[e].longs.n;
+    free(J.outs[e].seeds.p);
+    free(J.outs[e].longs.p);
+  }
+  res->seed_off[n_events] = (int32_t)is;
+  res->long_off[n_events] = (int32_t)il;
+  free(J.outs);
+  return 0;
+}
+
+void orc_free(orc_result *res) {
+  free(res->seed_off); free(res->seeds); free(res->long_off); free(res->longs);
+  memset(res, 0, sizeof(*res));
+}

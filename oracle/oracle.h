@@ -1,0 +1,116 @@
+/* CPU oracle for SciFi Seeding + VELO-SciFi Matching, in FP64.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The product path (the
+ * HIP library under paper_2606_14480_amd/) never links, imports or calls it,
+ * and shares no header, helper or constant table with it.
+ *
+ * Every float input is widened exactly to double; every quantity is then
+ * computed in double.  Layout of the inputs is the same as the product's
+ * batch: hits grouped in zones zone = (event*2 + half)*12 + layer, x-sorted
+ * inside each zone.
+ */
+#ifndef SM_ORACLE_H
+#define SM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_NL 12
+
+typedef struct {
+  double z[ORC_NL];      /* nominal layer z [mm] */
+  double tan_a[ORC_NL];  /* tan of the stereo angle (0 for x-layers) */
+  double z_ref;          /* eq. trackequation reference point */
+} orc_geom;
+
+typedef struct {
+  /* XZ seeding (Sec. 3.2, 3.3) */
+  double p_min;            /* MeV */
+  double invp_a, invp_b;   /* eq. invp */
+  double alpha0, alpha1;   /* eq. alphacorr */
+  double d_ratio;          /* eq. trackequation */
+  double kappa_c;          /* c_x per unit 1/p, for the third-hit window */
+  double t2_tol0, t2_tol1; /* third-hit window tol0 + tol1*|K3 c_pred| */
+  double ext_tol;          /* x-layer extension window */
+  int32_t min_x_hits;
+  int32_t pad0;
+  double sigma_x;          /* hit resolution */
+  double chi2x_max;        /* reduced chi2 cut of the x-z fit */
+  /* UV seeding (Sec. 3.4) */
+  double uv_tol, y_max;
+  int32_t min_uv_hits;
+  int32_t pad1;
+  double chi2y_max;
+  /* Matching (Sec. 4) */
+  double zm[5];            /* A_x .. E_x of eq. z_match */
+  double z_ymatch, z_state;
+  double max_dx, max_dy, max_dtx, max_dty;
+  double tolx_scale, tolx_a, tolx_b;
+  double toly_scale, toly_a, toly_b;
+  double tol_tx, tol_ty;
+  double chi2m_max;
+  double polarity;
+} orc_params;
+
+/* One three-hit combination and what became of it. */
+typedef struct {
+  int32_t half, it, status; /* status 0: passed the fit cut; 1: < min_x_hits; 2: chi2 cut */
+  int32_t n;                /* number of x hits */
+  int32_t pos[ORC_NL];      /* event-relative hit positions by layer, -1 if none */
+  double a, b, c, chi2, score;
+} orc_cand;
+
+typedef struct {
+  double a, b, c, y0, ty, chi2x, chi2y, score;
+  int32_t nx, nuv, half, it;
+  int32_t pos[ORC_NL];
+  int32_t id[ORC_NL];
+} orc_seed;
+
+typedef struct {
+  int32_t velo_idx, velo_id, seed_idx, pad;
+  double qop, chi2, zm, dx, dy, dtx, dty;
+} orc_long;
+
+typedef struct {
+  int64_t n_seeds, n_longs;
+  int32_t *seed_off;   /* [n_events + 1] */
+  orc_seed *seeds;
+  int32_t *long_off;   /* [n_events + 1] */
+  orc_long *longs;
+} orc_result;
+
+void orc_default_geom(orc_geom *g);
+void orc_default_params(orc_params *p);
+
+/* out[0] = Delta x3^max, out[1] = alpha_corr, out[2] = K3 of iteration `it`
+ * at the nominal layer z. */
+void orc_window_constants(const orc_geom *g, const orc_params *p, int it, double out[3]);
+
+/* Stage entry points on ONE event (event-local zone offsets [25], hits). */
+int orc_xz_candidates(const orc_geom *g, const orc_params *p, const int32_t *zone_off,
+                      const float *x, const float *z, int half, int it,
+                      orc_cand *out, int cap);
+void orc_clone_vote(const orc_cand *c, int n, int n_pos, int32_t *keep);
+int orc_uv(const orc_geom *g, const orc_params *p, const int32_t *zone_off,
+           const float *x, const float *z, const int32_t *id, const orc_cand *cand,
+           orc_seed *out);
+int orc_match(const orc_geom *g, const orc_params *p, const orc_seed *seeds, int ns,
+              int nv, const float *vx, const float *vy, const float *vz,
+              const float *vtx, const float *vty, const int32_t *vid,
+              orc_long *out, int cap);
+
+/* Whole batch; returns 0 on success.  Results are malloc'd; free with orc_free. */
+int orc_run(const orc_geom *g, const orc_params *p, int n_events, const int32_t *zone_off,
+            const float *hx, const float *hz, const int32_t *hid, const int32_t *velo_off,
+            const float *vx, const float *vy, const float *vz, const float *vtx,
+            const float *vty, const int32_t *vid, int n_threads, orc_result *res);
+void orc_free(orc_result *res);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

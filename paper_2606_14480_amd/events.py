@@ -1,0 +1,363 @@
+"""Seeded synthetic SciFi + VELO events (input generator only).
+
+This module simulates the detector, it does not reconstruct anything: it
+draws charged tracks, bends them at a magnet kink, propagates them through the
+twelve SciFi layers (Sec. 1: three stations of x-u-v-x layers, stereo angle
++-5 deg, vertical field bending in x-z) and emits the hit SoA and VELO states
+that both the CPU oracle and the HIP library consume.  Neither side imports
+anything else from here.
+
+Forward model of one track (truth -> hits), all in mm and MeV:
+
+* origin (x_o, y_o, z_o), slopes tx, ty ~ U(-0.25, 0.25), momentum p
+  log-uniform, charge q = +-1;
+* the magnet is a single kink at z_k.  The kink size follows the inverse
+  momentum parametrisation of Sec. 3.3.1 (eq. invp) read backwards:
+  |x0| solves a|x0| + b x0^2 = 1/p, and the slope change is
+  dtx = q * pol * |x0| / z_k, so the straight SciFi line meets z = 0 at
+  x0 = -q pol |x0| relative to the VELO line;
+* z_k is placed where the kink-position parametrisation of Sec. 4.1
+  (eq. z_match, Table 1) puts it for this very track, found by fixed-point
+  iteration (the parametrisation depends on the SciFi state, which depends on
+  z_k);
+* inside the SciFi the x trajectory is the tangent line at the last layer
+  plus the residual-field term of eq. trackequation,
+  c * [g(zb) - g(zb_s) - g'(zb_s) (z - z_s)], g(u) = u^2 (1 + d_ratio u),
+  with c = q * pol * kappa_c / p, so x(z) = a + b zb + c g(zb) exactly;
+* y is a straight line (Sec. 4: no bending in y-z).
+
+Hits: x-layers measure x(z) + N(0, sigma); stereo layers measure
+x(z) - y(z) tan(alpha) + N(0, sigma).  Each hit is dropped with probability
+`ineff`; `noise` * n_signal uniformly placed noise hits are added.  Hits are
+grouped in zones ``zone = (event*2 + half)*12 + layer`` (half 0: y > 0,
+half 1: y < 0), sorted by x inside each zone.  Hit ids are a seeded
+permutation of 0..n-1 inside each event, so an id never equals a position by
+accident.
+
+Every event has its own PCG64 stream seeded with
+``1_000_000 * config + event_index``, so any subset regenerates identically.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# ---------------------------------------------------------------- detector --
+N_LAYERS = 12
+N_HALVES = 2
+ZONES_PER_EVENT = N_LAYERS * N_HALVES
+# 3 stations x (x, u, v, x); 70 mm layer pitch inside a station (Sec. 1: the
+# layers of a station are 50 mm apart through air), spanning 7826-9439 mm.
+LAYER_Z = np.array([7826.0, 7896.0, 7966.0, 8036.0,
+                    8527.5, 8597.5, 8667.5, 8737.5,
+                    9229.0, 9299.0, 9369.0, 9439.0])
+_T5 = math.tan(math.radians(5.0))
+LAYER_TAN = np.array([0.0, _T5, -_T5, 0.0] * 3)
+Z_REF = 8525.0           # eq. trackequation reference point
+X_ACC = 3200.0           # |x| acceptance at every layer
+Y_ACC_MIN = 2.5          # |y| acceptance (beam hole)
+Y_ACC_MAX = 2500.0
+Z_VELO = 770.0           # z of the VELO end-state
+
+# physics constants of the forward model (Sec. 3.3.1 eq. invp, Table 1)
+INVP_A = 1.6322e-7
+INVP_B = -5.0217e-12
+ZM = (5287.6, -7.98878, 317.683, 0.0119379, -1418.42)
+D_RATIO = -3.0e-4        # residual-field cubic term, mm^-1
+KAPPA_C = 3.0e-3         # curvature scale c = q pol kappa_c / p, MeV / mm
+POLARITY = 1.0
+
+
+@dataclasses.dataclass
+class GenConfig:
+    n_events: int
+    config_id: int
+    mult: str = "poisson"          # "fixed" | "poisson" | "negbin"
+    mean_tracks: float = 120.0
+    nb_k: float = 1.0
+    clip: tuple = (0, 10 ** 9)
+    p_range: tuple = (1500.0, 100000.0)
+    sigma: float = 0.07
+    ineff: float = 0.0
+    noise: float = 0.0
+    ghost_velo: float = 0.0
+    velo_sigma_x: float = 0.0
+    velo_sigma_t: float = 0.0
+    first_event: int = 0
+
+
+def config(n: int, n_events: int | None = None, first_event: int = 0) -> GenConfig:
+    """The five workloads: 1 tiny, 2 min-bias, 3 uneven, 4 stress, 5 serving."""
+    if n == 1:
+        return GenConfig(n_events=n_events or 1, config_id=1, mult="fixed",
+                         mean_tracks=20, p_range=(2000.0, 100000.0),
+                         first_event=first_event)
+    if n in (2, 5):
+        return GenConfig(n_events=n_events or 1000, config_id=n, mult="poisson",
+                         mean_tracks=120, ineff=0.02, noise=0.10,
+                         ghost_velo=0.05, velo_sigma_x=0.01, velo_sigma_t=2e-4,
+                         first_event=first_event)
+    if n == 3:
+        return GenConfig(n_events=n_events or 10000, config_id=3, mult="negbin",
+                         mean_tracks=120, clip=(10, 600), ineff=0.02,
+                         noise=0.10, ghost_velo=0.05, velo_sigma_x=0.01,
+                         velo_sigma_t=2e-4, first_event=first_event)
+    if n == 4:
+        return GenConfig(n_events=n_events or 50000, config_id=4, mult="negbin",
+                         mean_tracks=240, clip=(20, 3000), ineff=0.05,
+                         noise=0.20, ghost_velo=0.05, velo_sigma_x=0.01,
+                         velo_sigma_t=2e-4, first_event=first_event)
+    raise ValueError(f"unknown config {n}")
+
+
+@dataclasses.dataclass
+class Batch:
+    """Host-side batch in the layout of the C-ABI (all numpy)."""
+    zone_off: np.ndarray     # int32 [n_events*24 + 1]
+    hit_x: np.ndarray        # float32 [n_hits]
+    hit_z: np.ndarray        # float32 [n_hits]
+    hit_id: np.ndarray       # int32 [n_hits]
+    velo_off: np.ndarray     # int32 [n_events + 1]
+    velo_x: np.ndarray       # float32 [n_velo]
+    velo_y: np.ndarray
+    velo_z: np.ndarray
+    velo_tx: np.ndarray
+    velo_ty: np.ndarray
+    velo_id: np.ndarray      # int32 [n_velo]
+    truth: dict | None = None
+
+    @property
+    def n_events(self) -> int:
+        return (len(self.zone_off) - 1) // ZONES_PER_EVENT
+
+    @property
+    def n_hits(self) -> int:
+        return int(self.zone_off[-1])
+
+    @property
+    def n_velo(self) -> int:
+        return int(self.velo_off[-1])
+
+    def event_hits(self) -> np.ndarray:
+        o = self.zone_off[::ZONES_PER_EVENT]
+        return np.diff(o)
+
+    def subset(self, idx) -> "Batch":
+        return concat([self.event(int(i)) for i in idx])
+
+    def event(self, e: int) -> "Batch":
+        z0 = e * ZONES_PER_EVENT
+        h0, h1 = int(self.zone_off[z0]), int(self.zone_off[z0 + ZONES_PER_EVENT])
+        v0, v1 = int(self.velo_off[e]), int(self.velo_off[e + 1])
+        truth = None
+        if self.truth is not None:
+            t0, t1 = self.truth["track_off"][e], self.truth["track_off"][e + 1]
+            truth = {k: (v[t0:t1] if k != "track_off" else np.array([0, t1 - t0]))
+                     for k, v in self.truth.items()}
+        return Batch(
+            zone_off=(self.zone_off[z0:z0 + ZONES_PER_EVENT + 1] - h0).astype(np.int32),
+            hit_x=self.hit_x[h0:h1], hit_z=self.hit_z[h0:h1], hit_id=self.hit_id[h0:h1],
+            velo_off=np.array([0, v1 - v0], np.int32),
+            velo_x=self.velo_x[v0:v1], velo_y=self.velo_y[v0:v1],
+            velo_z=self.velo_z[v0:v1], velo_tx=self.velo_tx[v0:v1],
+            velo_ty=self.velo_ty[v0:v1], velo_id=self.velo_id[v0:v1], truth=truth)
+
+
+def concat(events: list) -> Batch:
+    """Concatenate single- or multi-event batches (offsets are rebased)."""
+    zo, vo = [np.zeros(1, np.int32)], [np.zeros(1, np.int32)]
+    hbase = vbase = 0
+    for b in events:
+        zo.append(b.zone_off[1:] + hbase)
+        vo.append(b.velo_off[1:] + vbase)
+        hbase += b.n_hits
+        vbase += b.n_velo
+    cat = lambda name, dt: (np.concatenate([getattr(b, name) for b in events]).astype(dt)
+                            if events else np.zeros(0, dt))
+    truth = None
+    if events and all(b.truth is not None for b in events):
+        keys = [k for k in events[0].truth if k != "track_off"]
+        truth = {k: np.concatenate([b.truth[k] for b in events]) for k in keys}
+        counts = [len(b.truth["p"]) for b in events]
+        truth["track_off"] = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    return Batch(zone_off=np.concatenate(zo).astype(np.int32),
+                 hit_x=cat("hit_x", np.float32), hit_z=cat("hit_z", np.float32),
+                 hit_id=cat("hit_id", np.int32),
+                 velo_off=np.concatenate(vo).astype(np.int32),
+                 velo_x=cat("velo_x", np.float32), velo_y=cat("velo_y", np.float32),
+                 velo_z=cat("velo_z", np.float32), velo_tx=cat("velo_tx", np.float32),
+                 velo_ty=cat("velo_ty", np.float32), velo_id=cat("velo_id", np.int32),
+                 truth=truth)
+
+
+# ------------------------------------------------------------- the physics --
+def _g(u):
+    return u * u * (1.0 + D_RATIO * u)
+
+
+def _dg(u):
+    return 2.0 * u + 3.0 * D_RATIO * u * u
+
+
+def _draw_tracks(rng, n, p_range, pol):
+    """Draw n candidate tracks; returns a dict of per-track arrays."""
+    lp = rng.uniform(math.log(p_range[0]), math.log(p_range[1]), n)
+    p = np.exp(lp)
+    q = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    xo = rng.normal(0.0, 0.03, n)
+    yo = rng.normal(0.0, 0.03, n)
+    zo = rng.normal(0.0, 50.0, n)
+    tx = rng.uniform(-0.25, 0.25, n)
+    ty = rng.uniform(-0.25, 0.25, n)
+    # |x0| from 1/p = a|x0| + b x0^2 (smaller positive root)
+    ax0 = (-INVP_A + np.sqrt(INVP_A ** 2 + 4.0 * INVP_B / p)) / (2.0 * INVP_B)
+    zs = LAYER_Z[-1]
+    xv = lambda z: xo + tx * (z - zo)
+    zk = np.full(n, ZM[0])
+    for _ in range(30):
+        dtx = q * pol * ax0 / zk
+        xs = xv(zk) + (tx + dtx) * (zs - zk)
+        znew = (ZM[0] + ZM[1] * np.abs(dtx) + ZM[2] * dtx * dtx
+                + ZM[3] * np.abs(xs) + ZM[4] * tx * tx)
+        done = np.max(np.abs(znew - zk)) < 1e-10
+        zk = znew
+        if done:
+            break
+    dtx = q * pol * ax0 / zk
+    txs = tx + dtx
+    xs = xv(zk) + txs * (zs - zk)
+    c = q * pol * KAPPA_C / p
+    ubs = zs - Z_REF
+    b = txs - c * _dg(ubs)
+    a = xs - b * ubs - c * _g(ubs)
+    y0 = yo + ty * (Z_REF - zo)
+    return dict(p=p, q=q, xo=xo, yo=yo, zo=zo, tx=tx, ty=ty, zk=zk, dtx=dtx,
+                a=a, b=b, c=c, y0=y0)
+
+
+def _track_xy(t, z):
+    u = z[None, :] - Z_REF
+    x = t["a"][:, None] + t["b"][:, None] * u + t["c"][:, None] * _g(u)
+    y = t["y0"][:, None] + t["ty"][:, None] * u
+    return x, y
+
+
+def _accepted(t):
+    x, y = _track_xy(t, LAYER_Z)
+    ok = np.all(np.abs(x) <= X_ACC, axis=1)
+    ok &= np.all((np.abs(y) >= Y_ACC_MIN) & (np.abs(y) <= Y_ACC_MAX), axis=1)
+    ok &= np.all(np.sign(y) == np.sign(y[:, :1]), axis=1)
+    return ok
+
+
+def _n_tracks(rng, cfg: GenConfig) -> int:
+    if cfg.mult == "fixed":
+        n = int(cfg.mean_tracks)
+    elif cfg.mult == "poisson":
+        n = int(rng.poisson(cfg.mean_tracks))
+    elif cfg.mult == "negbin":
+        k = cfg.nb_k
+        n = int(rng.negative_binomial(k, k / (k + cfg.mean_tracks)))
+    else:
+        raise ValueError(cfg.mult)
+    return int(min(max(n, cfg.clip[0]), cfg.clip[1]))
+
+
+def generate_event(cfg: GenConfig, e: int, pol: float = POLARITY) -> Batch:
+    """One event of workload `cfg` (event index `e` within the workload)."""
+    rng = np.random.Generator(np.random.PCG64(1_000_000 * cfg.config_id + e))
+    n = _n_tracks(rng, cfg)
+    parts, have = [], 0
+    while have < n:
+        t = _draw_tracks(rng, max(2 * (n - have), 8), cfg.p_range, pol)
+        ok = _accepted(t)
+        t = {k: v[ok] for k, v in t.items()}
+        parts.append(t)
+        have += len(t["p"])
+    t = {k: np.concatenate([pp[k] for pp in parts])[:n] for k in parts[0]}
+
+    x, y = _track_xy(t, LAYER_Z)                          # [n, 12]
+    meas = x - y * LAYER_TAN[None, :]
+    meas = meas + rng.normal(0.0, cfg.sigma, meas.shape) if cfg.sigma > 0 else meas
+    keep = rng.random(meas.shape) >= cfg.ineff if cfg.ineff > 0 else np.ones(meas.shape, bool)
+    half = np.where(y > 0, 0, 1)
+    trk = np.repeat(np.arange(n), N_LAYERS).reshape(n, N_LAYERS)
+    lay = np.tile(np.arange(N_LAYERS), (n, 1))
+    hx, hl, hh, ht = meas[keep], lay[keep], half[keep], trk[keep]
+    n_sig = len(hx)
+    n_noise = int(round(cfg.noise * n_sig))
+    if n_noise:
+        hx = np.concatenate([hx, rng.uniform(-X_ACC, X_ACC, n_noise)])
+        hl = np.concatenate([hl, rng.integers(0, N_LAYERS, n_noise)])
+        hh = np.concatenate([hh, rng.integers(0, N_HALVES, n_noise)])
+        ht = np.concatenate([ht, np.full(n_noise, -1)])
+    hx32 = hx.astype(np.float32)
+    zone = hh * N_LAYERS + hl
+    order = np.lexsort((np.arange(len(hx32)), hx32, zone))
+    hx32, zone, hl, ht = hx32[order], zone[order], hl[order], ht[order]
+    counts = np.bincount(zone, minlength=ZONES_PER_EVENT)
+    zone_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    nh = len(hx32)
+    hit_id = rng.permutation(nh).astype(np.int32)
+    hit_z = LAYER_Z[hl].astype(np.float32)
+
+    # truth: hit ids of each track by layer (-1 where inefficient)
+    thits = np.full((n, N_LAYERS), -1, np.int32)
+    sig = ht >= 0
+    thits[ht[sig], hl[sig]] = hit_id[sig]
+
+    # VELO end-states: one per track (+ ghosts), in a seeded random order
+    vx = t["xo"] + t["tx"] * (Z_VELO - t["zo"])
+    vy = t["yo"] + t["ty"] * (Z_VELO - t["zo"])
+    vtx, vty = t["tx"].copy(), t["ty"].copy()
+    if cfg.velo_sigma_x > 0:
+        vx = vx + rng.normal(0, cfg.velo_sigma_x, n)
+        vy = vy + rng.normal(0, cfg.velo_sigma_x, n)
+    if cfg.velo_sigma_t > 0:
+        vtx = vtx + rng.normal(0, cfg.velo_sigma_t, n)
+        vty = vty + rng.normal(0, cfg.velo_sigma_t, n)
+    n_ghost = int(round(cfg.ghost_velo * n))
+    vtrk = np.arange(n)
+    if n_ghost:
+        gtx = rng.uniform(-0.25, 0.25, n_ghost)
+        gty = rng.uniform(-0.25, 0.25, n_ghost)
+        gzo = rng.normal(0, 50.0, n_ghost)
+        vx = np.concatenate([vx, rng.normal(0, 0.03, n_ghost) + gtx * (Z_VELO - gzo)])
+        vy = np.concatenate([vy, rng.normal(0, 0.03, n_ghost) + gty * (Z_VELO - gzo)])
+        vtx = np.concatenate([vtx, gtx])
+        vty = np.concatenate([vty, gty])
+        vtrk = np.concatenate([vtrk, np.full(n_ghost, -1)])
+    vperm = rng.permutation(len(vx))
+    nv = len(vx)
+    velo_id = rng.permutation(nv).astype(np.int32)
+    vx, vy, vtx, vty, vtrk = vx[vperm], vy[vperm], vtx[vperm], vty[vperm], vtrk[vperm]
+    velo_of_track = np.full(n, -1, np.int64)
+    velo_of_track[vtrk[vtrk >= 0]] = np.nonzero(vtrk >= 0)[0]
+
+    truth = dict(p=t["p"], q=t["q"], a=t["a"], b=t["b"], c=t["c"], y0=t["y0"],
+                 ty=t["ty"], tx=t["tx"], zk=t["zk"], dtx=t["dtx"], hits=thits,
+                 velo=velo_of_track, track_off=np.array([0, n], np.int64))
+    return Batch(zone_off=zone_off, hit_x=hx32, hit_z=hit_z, hit_id=hit_id,
+                 velo_off=np.array([0, nv], np.int32),
+                 velo_x=vx.astype(np.float32), velo_y=vy.astype(np.float32),
+                 velo_z=np.full(nv, Z_VELO, np.float32),
+                 velo_tx=vtx.astype(np.float32), velo_ty=vty.astype(np.float32),
+                 velo_id=velo_id, truth=truth)
+
+
+def generate(cfg: GenConfig, pol: float = POLARITY) -> Batch:
+    return concat([generate_event(cfg, cfg.first_event + i, pol) for i in range(cfg.n_events)])
+
+
+def empty_event() -> Batch:
+    return Batch(zone_off=np.zeros(ZONES_PER_EVENT + 1, np.int32),
+                 hit_x=np.zeros(0, np.float32), hit_z=np.zeros(0, np.float32),
+                 hit_id=np.zeros(0, np.int32), velo_off=np.zeros(2, np.int32),
+                 velo_x=np.zeros(0, np.float32), velo_y=np.zeros(0, np.float32),
+                 velo_z=np.zeros(0, np.float32), velo_tx=np.zeros(0, np.float32),
+                 velo_ty=np.zeros(0, np.float32), velo_id=np.zeros(0, np.int32),
+                 truth={k: np.zeros((0, 12) if k == "hits" else 0)
+                        for k in ("p", "q", "a", "b", "c", "y0", "ty", "tx", "zk",
+                                  "dtx", "hits", "velo")} | {"track_off": np.array([0, 0])})
