@@ -1,0 +1,199 @@
+/* sm.h — C-ABI of the MI355X SciFi Seeding + VELO-SciFi Matching library.
+ *
+ * The calls follow the paper's problem statement: SciFi hits and VELO track
+ * states go in, T-tracks ("seeds", Sec. 3, output of the UV step of Sec. 3.4)
+ * and Long tracks (Sec. 4, output of the final selection of Sec. 4.4) come
+ * out.  All compute runs in HIP kernels for gfx950; this header has no torch
+ * or HIP types.
+ *
+ * Conventions shared by every call
+ *  - Pointers inside sm_batch / sm_out are DEVICE pointers on the context's
+ *    device, owned by the caller, and must stay valid until the call (or, for
+ *    sm_submit, the matching sm_poll) returns SM_OK or an error.  Inputs are
+ *    never written.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *  - Every call returns an sm_status; nothing aborts the process.  When an
+ *    output buffer is too small the call returns SM_ERR_CAPACITY, fills
+ *    sm_out.n_seeds / n_longs with the sizes needed, and the content of the
+ *    output arrays is unspecified; nothing is truncated silently.  Internal
+ *    scratch that proves too small is grown and the batch re-run inside the
+ *    call.
+ *  - Results are deterministic: the same batch gives bit-identical outputs
+ *    whatever the batch composition, launch form or grid shape.
+ */
+#ifndef SM_H
+#define SM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SM_N_LAYERS 12
+#define SM_ZONES_PER_EVENT 24
+
+typedef enum {
+  SM_OK = 0,
+  SM_ERR_INVALID = -1,   /* bad argument or malformed batch */
+  SM_ERR_UNSORTED = -2,  /* hits not x-sorted inside a zone (validate mode) */
+  SM_ERR_CAPACITY = -3,  /* an output buffer is too small; sizes in sm_out */
+  SM_ERR_OOM = -4,       /* device allocation failed */
+  SM_ERR_DEVICE = -5,    /* a HIP runtime call failed */
+  SM_ERR_BUSY = -6,      /* sm_submit: every serving slot is in use */
+  SM_ERR_NOT_READY = -7, /* sm_poll: the batch is still running */
+  SM_ERR_LIMIT = -8      /* an event exceeds the library's hard per-event limit */
+} sm_status;
+
+typedef struct sm_ctx sm_ctx; /* opaque, library-owned */
+
+/* Detector description (Sec. 1): nominal z of the 12 SciFi layers (3
+ * stations x {x, u, v, x}), tan of each layer's stereo angle (0 for x-layers,
+ * +-tan 5 deg for u/v) and the reference z of eq. trackequation. */
+typedef struct {
+  double z[SM_N_LAYERS];
+  double tan_stereo[SM_N_LAYERS];
+  double z_ref;
+} sm_geometry;
+
+/* Every constant of the method.  sm_default_params() fills the paper's values
+ * and the documented readings where the paper gives none. */
+typedef struct {
+  /* XZ seeding, Sec. 3.2-3.3 */
+  double p_min;            /* MeV/c, minimum momentum the windows are opened for */
+  double invp_a, invp_b;   /* eq. invp, per MeV/c per mm and per mm^2 */
+  double alpha0, alpha1;   /* eq. alphacorr */
+  double d_ratio;          /* eq. trackequation cubic term, 1/mm */
+  double kappa_c;          /* third-hit window centre: c_x = kappa_c / p */
+  double t2_tol0, t2_tol1; /* third-hit half-width tol0 + tol1 |K3 c_pred| (mm) */
+  double ext_tol;          /* x-layer extension window (mm), Sec. 3.2 */
+  int32_t min_x_hits;      /* Sec. 3.2 */
+  int32_t pad0;
+  double sigma_x;          /* hit resolution used in both chi2 (mm) */
+  double chi2x_max;        /* reduced chi2 cut of the x-z fit */
+  /* UV seeding, Sec. 3.4 */
+  double uv_tol;           /* mm */
+  double y_max;            /* |y| range of a detector half (mm) */
+  int32_t min_uv_hits;
+  int32_t pad1;
+  double chi2y_max;        /* reduced chi2 cut of the y-z fit */
+  /* Matching, Sec. 4 */
+  double zm[5];            /* A_x, B_x, C_x, D_x, E_x of eq. z_match (Table 1) */
+  double z_ymatch;         /* z of the y matching plane (mm) */
+  double z_state;          /* z of the SciFi state used for matching (mm) */
+  double max_dx, max_dy, max_dtx, max_dty;   /* preselection, Sec. 4.2 */
+  double tolx_scale, tolx_a, tolx_b;         /* tol_x = s (a^2 + b^2 dtx^2) */
+  double toly_scale, toly_a, toly_b;         /* tol_y = s (a^2 + b^2 rho) */
+  double tol_tx, tol_ty;
+  double chi2m_max;        /* chi2_match cut */
+  double polarity;         /* +1 or -1, magnet polarity */
+} sm_params;
+
+/* Library resources; zero fields take defaults. */
+typedef struct {
+  int32_t device;          /* HIP device ordinal */
+  int32_t n_slots;         /* concurrent serving slots (sm_submit), default 2 */
+  int32_t seed_wgs;        /* persistent workgroups of the seeding kernel (0: auto) */
+  int32_t match_wgs;       /* persistent workgroups of the matching kernel (0: auto) */
+  int32_t lds_hits;        /* per-workgroup LDS hit budget (0: auto) */
+  int32_t validate;        /* 1: check offsets and x-sorting before each batch */
+  int64_t mem_budget;      /* bytes of device memory the context may hold (0: no cap) */
+} sm_config;
+
+/* One batch of events.  Hits of event e, detector half h (0: y > 0,
+ * 1: y < 0) and layer l form zone k = (e*2 + h)*12 + l and occupy
+ * [zone_off[k], zone_off[k+1]) of the hit arrays, x-sorted ascending.
+ * VELO end-states of event e occupy [velo_off[e], velo_off[e+1]). */
+typedef struct {
+  int32_t n_events;
+  int32_t pad;
+  int64_t n_hits;          /* = zone_off[n_events*24] (host-side size of the hit arrays) */
+  int64_t n_velo;          /* = velo_off[n_events] (host-side size of the VELO arrays) */
+  const int32_t *zone_off; /* [n_events*24 + 1], non-decreasing, zone_off[0] = 0 */
+  const float *hit_x;      /* measured x (mm); local coordinate for u/v layers */
+  const float *hit_z;      /* z of the hit (mm) */
+  const int32_t *hit_id;   /* caller's id, reported back in seeds */
+  const int32_t *velo_off; /* [n_events + 1] */
+  const float *velo_x, *velo_y, *velo_z, *velo_tx, *velo_ty;
+  const int32_t *velo_id;
+} sm_batch;
+
+/* A T-track (Sec. 3): x(z) = ax + bx u + cx u^2 (1 + d_ratio u) and
+ * y(z) = y0 + ty u with u = z - z_ref. */
+typedef struct {
+  float ax, bx, cx;
+  float y0, ty;
+  float chi2_x, chi2_y;   /* reduced */
+  float score;            /* eq. seed_clone_score, rounded to float */
+  int32_t n_x, n_uv;      /* hits on x and on stereo layers */
+  int32_t half, iter;     /* detector half and XZ iteration that found it */
+  int32_t hits[SM_N_LAYERS]; /* hit_id per layer, -1 where none */
+} sm_seed;                /* 96 bytes */
+
+/* A Long track (Sec. 4): one VELO state joined with one seed. */
+typedef struct {
+  int32_t velo_idx;       /* index of the VELO state inside its event */
+  int32_t seed_idx;       /* index of the seed inside its event's seed list */
+  int32_t velo_id;
+  float qop;              /* q/p from the magnet kick, 1/MeV */
+  float chi2;             /* chi2_match */
+  float z_match;          /* eq. z_match */
+  float dx, dy, dtx, dty; /* matching residuals */
+} sm_long;                /* 40 bytes */
+
+/* Outputs, caller-allocated on the device.  Seeds of event e are
+ * seeds[seed_off[e] .. seed_off[e+1]) in canonical order (half, iteration,
+ * then the positions of the T1, T3 and T2 hits); long tracks of event e are
+ * longs[long_off[e] .. long_off[e+1]) ordered by (velo_idx, seed_idx). */
+typedef struct {
+  int64_t seed_cap, long_cap; /* capacity of seeds[] and longs[] */
+  int32_t *seed_off;          /* [n_events + 1] */
+  sm_seed *seeds;
+  int32_t *long_off;          /* [n_events + 1] */
+  sm_long *longs;
+  int64_t n_seeds, n_longs;   /* written by the library (host fields) */
+} sm_out;
+
+/* Defaults: the geometry of the synthetic detector and the paper's
+ * constants (Sec. 3.3.1 eq. invp, eq. alphacorr, Table 1, Sec. 4.2) plus
+ * the readings for the values the paper does not print. */
+void sm_default_geometry(sm_geometry *g);
+void sm_default_params(sm_params *p);
+
+/* Creates a context on cfg->device (NULL cfg: all defaults).  Allocates the
+ * scratch, serving slots and streams it owns.  SM_ERR_OOM if the device
+ * memory or cfg->mem_budget is too small. */
+sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *cfg,
+                    sm_ctx **out);
+
+/* Seeding + Matching of a whole batch as ONE persistent launch per kernel,
+ * replayed from a captured HIP graph, with workgroups pulling (event, half)
+ * items longest-first from a device work queue.  Blocks until done
+ * (stream-ordered after prior work on `stream`). */
+sm_status sm_run(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream);
+
+/* The same computation launched as one kernel sequence per event (the plain
+ * form); bit-identical results to sm_run.  Blocks until done. */
+sm_status sm_run_plain(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream);
+
+/* Serving: starts the batch on a free slot (its own stream) and returns at
+ * once with a ticket; SM_ERR_BUSY if no slot is free.  batch and out must stay
+ * valid until sm_poll reports completion. */
+sm_status sm_submit(sm_ctx *ctx, const sm_batch *batch, sm_out *out, int64_t *ticket);
+
+/* SM_OK once the ticket's batch is done (out->n_seeds / n_longs filled),
+ * SM_ERR_NOT_READY while it runs (wait = 0), or its error.  wait != 0 blocks.
+ * A ticket is reported complete exactly once; the slot is then free. */
+sm_status sm_poll(sm_ctx *ctx, int64_t ticket, int wait);
+
+/* Device bytes a batch with these totals needs in a serving slot (used for
+ * admission by free memory). */
+int64_t sm_batch_bytes(const sm_ctx *ctx, int32_t n_events, int64_t n_hits, int64_t n_velo);
+
+sm_status sm_destroy(sm_ctx *ctx);
+const char *sm_status_str(sm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

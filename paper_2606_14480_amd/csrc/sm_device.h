@@ -1,0 +1,150 @@
+// Device side of the Seeding + Matching library (gfx950, wave64).
+//
+// Kernels, in launch order for one batch:
+//   k_init     clear queue heads, pool tops and status words (a fill kernel,
+//              so the sequence can live in a captured graph)
+//   k_order    order the (event, half) items by hit count, largest first
+//   k_seed     persistent: each workgroup pulls items from the queue and runs
+//              XZ seeding (both iterations), the clone vote and UV seeding of
+//              one detector half of one event, hits staged in LDS
+//   k_seed_off per-event seed offsets (exclusive scan)
+//   k_match    persistent over events: copy the event's seeds to the output in
+//              canonical order and match them with the VELO states
+//   k_long_off per-event long-track offsets, then k_long_copy
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sm.h"
+
+namespace smk {
+
+constexpr int kNL = 12;
+constexpr int kSeedWG = 256;        // threads of the seeding workgroup (4 waves)
+constexpr int kMatchWG = 256;
+constexpr int kLdsHits = 4096;      // hits (x, z) one seeding workgroup keeps in LDS
+constexpr int kPosBits = 21;        // item-relative hit positions < 2^21
+constexpr int kMaxItemHits = 1 << kPosBits;
+
+// status flags (Counters::flags)
+enum : unsigned {
+  F_TRIP = 1u << 0,      // triplet scratch too small
+  F_CAND = 1u << 1,      // candidate scratch too small
+  F_TBL = 1u << 2,       // clone table scratch too small
+  F_SST = 1u << 3,       // per-item seed staging too small
+  F_POOL = 1u << 4,      // seed pool too small
+  F_LPOOL = 1u << 5,     // long-track pool too small
+  F_MS = 1u << 6,        // per-event matching scratch too small (seeds)
+  F_VS = 1u << 7,        // per-event matching scratch too small (VELO)
+  F_SURV = 1u << 8,      // matching survivor list too small
+  F_OUT_SEED = 1u << 9,  // caller's seed buffer too small
+  F_OUT_LONG = 1u << 10, // caller's long buffer too small
+  F_LIMIT = 1u << 11,    // an item has >= 2^21 hits
+  F_INVALID = 1u << 12,  // malformed offsets
+  F_UNSORTED = 1u << 13, // hits not sorted in a zone
+};
+
+struct Counters {
+  unsigned seed_queue, match_queue;
+  unsigned flags, pad0;
+  unsigned long long pool_top, lpool_top;
+  unsigned need_trip, need_cand, need_tbl, need_sst;
+  unsigned need_ms, need_vs, need_surv, pad1;
+  long long total_seeds, total_longs;
+};
+
+// Everything a batch needs that changes from call to call; lives in device
+// memory so a captured graph can be replayed for any batch.
+struct Desc {
+  sm_batch b;
+  sm_seed *seeds;
+  sm_long *longs;
+  int32_t *seed_off;
+  int32_t *long_off;
+  long long seed_cap, long_cap;
+  int n_events, n_items;
+};
+
+// Parameters in the precision each kernel uses.
+struct DevParams {
+  float zf[kNL];
+  double zd[kNL], tand[kNL];
+  double zref, d;
+  float zreff, df;
+  // XZ, FP32 search
+  float dx3f[2], alphaf[2];
+  float invp_af, invp_bf, kappa_cf, t2_tol0f, t2_tol1f;
+  // XZ, FP64 extension + fit
+  double ext_tol, inv_sigma2, chi2x_max;
+  int min_x_hits, min_uv_hits;
+  // UV
+  double uv_tol, y_max, chi2y_max;
+  // Matching
+  double zm[5], z_ymatch, z_state;
+  double max_dx, max_dy, max_dtx, max_dty;
+  double tolx_scale, tolx_a, tolx_b, toly_scale, toly_a, toly_b, tol_tx, tol_ty;
+  double chi2m_max, polarity, invp_a, invp_b;
+  float pre_dx, pre_dy, pre_dtx, pre_dty;  // FP32 prefilter, slightly wider
+  float zmf[5], z_ymatchf, z_statef;
+};
+
+// An x-z candidate (Sec. 3.2) in per-workgroup scratch.
+struct Cand {
+  double a, b, c, chi2;
+  unsigned long long score;  // bits of the non-negative FP64 score
+  unsigned long long key;    // (iteration, T1, T3, T2 positions)
+  int32_t pos[6];            // x-layer hits (item-relative), -1 if none
+  int32_t n, it;
+};
+
+struct SeedStage {
+  sm_seed s;
+  unsigned long long key;
+};
+
+// Per-seed state for Matching (Sec. 4.1).
+struct MState {
+  double xs, txs, y_m, ty, x0s;
+  float xsf, txsf, y_mf, tyf;
+};
+
+struct Surv {
+  int v, s;
+  double chi2;
+};
+
+// Library-owned scratch of one slot.
+struct Scratch {
+  unsigned long long *trip;  // [seed_wgs][trip_cap]
+  Cand *cand;                // [seed_wgs][cand_cap]
+  unsigned long long *tbl;   // [seed_wgs][tbl_cap]
+  SeedStage *sst;            // [seed_wgs][sst_cap]
+  int trip_cap, cand_cap, tbl_cap, sst_cap;
+  int *item_order, *item_cnt, *item_base;  // [items_cap]
+  int *ev_lcnt, *ev_lbase;                 // [events_cap]
+  sm_seed *pool;
+  sm_long *lpool;
+  long long pool_cap, lpool_cap;
+  MState *ms;                 // [match_wgs][ms_cap]
+  unsigned long long *best_s; // [match_wgs][ms_cap]
+  unsigned long long *best_v; // [match_wgs][vs_cap]
+  Surv *surv;                 // [match_wgs][surv_cap]
+  int ms_cap, vs_cap, surv_cap, pad;
+  Counters *cnt;
+};
+
+}  // namespace smk
+
+extern "C" {
+// Launchers (sm_device.hip); each returns the hipError_t of its launch.
+int smk_launch_init(const smk::Desc *d, smk::Scratch s, int plain, hipStream_t st);
+int smk_launch_order(const smk::Desc *d, smk::Scratch s, hipStream_t st);
+int smk_launch_seed(const smk::Desc *d, smk::Scratch s, smk::DevParams p, int item_begin,
+                    int item_count, int use_queue, int grid, hipStream_t st);
+int smk_launch_seed_off(const smk::Desc *d, smk::Scratch s, hipStream_t st);
+int smk_launch_match(const smk::Desc *d, smk::Scratch s, smk::DevParams p, int ev_begin,
+                     int ev_count, int plain, int grid, hipStream_t st);
+int smk_launch_long_off(const smk::Desc *d, smk::Scratch s, hipStream_t st);
+int smk_launch_long_copy(const smk::Desc *d, smk::Scratch s, int grid, hipStream_t st);
+int smk_launch_validate(const smk::Desc *d, smk::Scratch s, int grid, hipStream_t st);
+}

@@ -1,0 +1,895 @@
+// HIP kernels of SciFi Seeding (Sec. 3) and VELO-SciFi Matching (Sec. 4)
+// for gfx950 (CDNA4, wave64).
+//
+// Precision: hits are FP32.  The combinatorial search (T1 x T3 doublets, T2
+// third hit, Sec. 3.3.2-3.3.3) runs in FP32; the per-triplet work (3-point
+// model, 1 mm extension, least-squares fit, score), UV seeding and the
+// chi2_match of the preselected pairs run in FP64, so that fits and the
+// clone-vote scores keep the digits the vote compares.
+#include "sm_device.h"
+
+namespace smk {
+
+// x-layer slots 0..5 <-> layers 0, 3, 4, 7, 8, 11; stereo slots 0..5 <->
+// layers 1, 2, 5, 6, 9, 10 (Sec. 1: x-u-v-x in each station).
+__device__ __forceinline__ int xlayer(int slot) { return (slot >> 1) * 4 + (slot & 1) * 3; }
+__device__ __forceinline__ int uvlayer(int slot) { return (slot >> 1) * 4 + 1 + (slot & 1); }
+
+__device__ __forceinline__ float gf(float u, float d) { return u * u * (1.0f + d * u); }
+__device__ __forceinline__ double gd(double u, double d) { return u * u * (1.0 + d * u); }
+
+__device__ __forceinline__ double xm(double a, double b, double c, double z, const DevParams &P) {
+  const double u = z - P.zref;
+  return a + b * u + c * gd(u, P.d);
+}
+
+// popcount of the set bits of m below this lane
+__device__ __forceinline__ unsigned lane_rank(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// Wave-aggregated append: every active lane gets its own slot of *counter
+// with one atomic per wave (ballot + prefix of the active mask).
+__device__ __forceinline__ unsigned wave_append(unsigned *counter) {
+  const unsigned long long m = __ballot(1);
+  const unsigned r = lane_rank(m);
+  unsigned base = 0;
+  if (r == 0) base = atomicAdd(counter, (unsigned)__popcll(m));
+  base = __builtin_amdgcn_readfirstlane(base);
+  return base + r;
+}
+
+// Exclusive scan of one int per thread over a workgroup of NT threads.
+template <int NT>
+__device__ __forceinline__ int block_excl_scan(int v, int *s_tmp, int &total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_tmp[w] = x;
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    const int t = s_tmp[i];
+    pre += i < w ? t : 0;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + x - v;
+}
+
+// first i in [lo, hi) with X[i] >= v
+__device__ __forceinline__ int lower_f(const float *X, int lo, int hi, float v) {
+  while (lo < hi) {
+    const int m = (lo + hi) >> 1;
+    if (X[m] < v) lo = m + 1; else hi = m;
+  }
+  return lo;
+}
+// first i in [lo, hi) with X[i] > v
+__device__ __forceinline__ int upper_f(const float *X, int lo, int hi, float v) {
+  while (lo < hi) {
+    const int m = (lo + hi) >> 1;
+    if (X[m] <= v) lo = m + 1; else hi = m;
+  }
+  return lo;
+}
+__device__ __forceinline__ int lower_d(const float *X, int lo, int hi, double v) {
+  while (lo < hi) {
+    const int m = (lo + hi) >> 1;
+    if ((double)X[m] < v) lo = m + 1; else hi = m;
+  }
+  return lo;
+}
+// Closest hit to pred inside [pred - tol, pred + tol], lower position on ties.
+__device__ __forceinline__ int closest_d(const float *X, int lo, int hi, double pred, double tol) {
+  int best = -1;
+  double bd = 0.0;
+  for (int i = lower_d(X, lo, hi, pred - tol); i < hi; ++i) {
+    const double x = X[i];
+    if (x > pred + tol) break;
+    const double d = fabs(x - pred);
+    if (best < 0 || d < bd) { best = i; bd = d; }
+  }
+  return best;
+}
+
+__device__ __forceinline__ void raise_flag(Counters *c, unsigned f) { atomicOr(&c->flags, f); }
+
+// Least-squares fit of eq. trackequation over the x-layer hits present in
+// `pos` (d_ratio fixed).  Coordinates are taken relative to the first hit and
+// the basis is scaled by 1 m so that the normal equations stay well
+// conditioned; the 3x3 system is solved by cofactors.  Returns false if it is
+// singular.
+__device__ __forceinline__ bool fit_x(const float *X, const float *Z, const int (&pos)[6],
+                                      const DevParams &P, double &a, double &b, double &c,
+                                      double &chi2, int &n) {
+  const double S = 1e-3, S2 = 1e-6;
+  double A00 = 0, A01 = 0, A02 = 0, A11 = 0, A12 = 0, A22 = 0, r0 = 0, r1 = 0, r2 = 0;
+  double xref = 0.0;
+  n = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    if (pos[k] < 0) continue;
+    const double x = X[pos[k]], z = Z[pos[k]];
+    if (n == 0) xref = x;
+    const double u = z - P.zref;
+    const double f1 = u * S, f2 = gd(u, P.d) * S2, xr = x - xref;
+    A00 += 1.0; A01 += f1; A02 += f2; A11 += f1 * f1; A12 += f1 * f2; A22 += f2 * f2;
+    r0 += xr; r1 += f1 * xr; r2 += f2 * xr;
+    ++n;
+  }
+  const double C00 = A11 * A22 - A12 * A12, C01 = A02 * A12 - A01 * A22, C02 = A01 * A12 - A02 * A11;
+  const double det = A00 * C00 + A01 * C01 + A02 * C02;
+  if (det == 0.0) return false;
+  const double C11 = A00 * A22 - A02 * A02, C12 = A01 * A02 - A00 * A12, C22 = A00 * A11 - A01 * A01;
+  const double inv = 1.0 / det;
+  const double q0 = (C00 * r0 + C01 * r1 + C02 * r2) * inv;
+  const double q1 = (C01 * r0 + C11 * r1 + C12 * r2) * inv;
+  const double q2 = (C02 * r0 + C12 * r1 + C22 * r2) * inv;
+  a = q0 + xref;
+  b = q1 * S;
+  c = q2 * S2;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    if (pos[k] < 0) continue;
+    const double r = (double)X[pos[k]] - xm(a, b, c, Z[pos[k]], P);
+    s += r * r;
+  }
+  chi2 = s * P.inv_sigma2 / (double)(n - 3);
+  return true;
+}
+
+// ---------------------------------------------------------------- XZ ------
+
+// T1 x T3 doublets and T2 third hits of one iteration (Sec. 3.3.2-3.3.3), in
+// FP32.  The T1 hits are taken 256 at a time; each thread finds the T3 window
+// of its T1 hit by binary search, a workgroup scan flattens the doublets so
+// that every thread then gets an equal share of them, and the T2 hits found
+// for a doublet are appended to the triplet list with one atomic per wave.
+__device__ __forceinline__ void xz_triplets(const float *X, const float *Z, const int *zoff,
+                                            const DevParams &P, int it, unsigned long long *trip,
+                                            int trip_cap, unsigned *s_ntrip, int *s_scan,
+                                            int *s_start, int *s_tmp, Counters *cnt) {
+  const int L1 = it ? 3 : 0, L2 = it ? 7 : 4, L3 = it ? 11 : 8;
+  const int b1 = zoff[L1], n1 = zoff[L1 + 1] - b1;
+  const int b2 = zoff[L2], e2 = zoff[L2 + 1];
+  const int b3 = zoff[L3], e3 = zoff[L3 + 1];
+  const float zr = P.zreff, dd = P.df;
+  const float z2n = P.zf[L2];
+  const float shift = P.zf[L3] + P.alphaf[it], dx3 = P.dx3f[it];
+  const float g2 = gf(z2n - zr, dd);
+  const unsigned long long itbit = (unsigned long long)it << 63;
+  for (int c0 = 0; c0 < n1; c0 += kSeedWG) {
+    const int j = c0 + (int)threadIdx.x;
+    int st = 0, cnt_j = 0;
+    if (j < n1) {
+      const float x1 = X[b1 + j], z1 = Z[b1 + j];
+      // window around x1 (z3 + alpha_corr) / z1, half-width Delta x3^max
+      const float centre = shift / z1 * x1;
+      st = lower_f(X, b3, e3, centre - dx3);
+      cnt_j = upper_f(X, st, e3, centre + dx3) - st;
+    }
+    int total;
+    const int excl = block_excl_scan<kSeedWG>(cnt_j, s_tmp, total);
+    s_scan[threadIdx.x] = excl;
+    s_start[threadIdx.x] = st;
+    __syncthreads();
+    const int nj = min(kSeedWG, n1 - c0);
+    for (int d0 = 0; d0 < total; d0 += kSeedWG) {
+      const int d = d0 + (int)threadIdx.x;
+      if (d < total) {
+        int lo = 0, hi = nj;
+        while (lo < hi) {
+          const int m = (lo + hi) >> 1;
+          if (s_scan[m] <= d) lo = m + 1; else hi = m;
+        }
+        const int jj = lo - 1;
+        const int i1 = b1 + c0 + jj;
+        const int i3 = s_start[jj] + (d - s_scan[jj]);
+        const float x1 = X[i1], z1 = Z[i1], x3 = X[i3], z3 = Z[i3];
+        const float t13 = (x3 - x1) / (z3 - z1);
+        const float x0 = x1 - z1 * t13;
+        const float ip = P.invp_af * fabsf(x0) + P.invp_bf * x0 * x0;
+        const float cpred = (x0 >= 0.0f ? -1.0f : 1.0f) * P.kappa_cf * ip;
+        const float g1 = gf(z1 - zr, dd), g3 = gf(z3 - zr, dd);
+        const float k3 = g2 - g1 - (z2n - z1) / (z3 - z1) * (g3 - g1);
+        const float dev = k3 * cpred;
+        const float pred = x1 + (z2n - z1) * t13 + dev;
+        const float tol = P.t2_tol0f + P.t2_tol1f * fabsf(dev);
+        const float hi2 = pred + tol;
+        int k = lower_f(X, b2, e2, pred - tol);
+        bool more = k < e2 && X[k] <= hi2;
+        const unsigned long long head = itbit | ((unsigned long long)i1 << 42) | ((unsigned long long)i3 << 21);
+        while (more) {
+          const unsigned slot = wave_append(s_ntrip);
+          if (slot < (unsigned)trip_cap) trip[slot] = head | (unsigned long long)k;
+          ++k;
+          more = k < e2 && X[k] <= hi2;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Extension, fit and score of one triplet (Sec. 3.2, eq. seed_clone_score).
+__device__ __forceinline__ bool xz_candidate(const float *X, const float *Z, const int *zoff,
+                                             const DevParams &P, unsigned long long key, Cand &cd) {
+  const unsigned msk = (1u << kPosBits) - 1u;
+  const int it = (int)(key >> 63);
+  const int i1 = (int)(key >> 42) & msk, i3 = (int)(key >> 21) & msk, i2 = (int)key & msk;
+  const double x1 = X[i1], z1 = Z[i1], x2 = X[i2], z2 = Z[i2], x3 = X[i3], z3 = Z[i3];
+  const double u1 = z1 - P.zref, g1 = gd(u1, P.d), g2 = gd(z2 - P.zref, P.d), g3 = gd(z3 - P.zref, P.d);
+  // model through the three hits: c from the T2 deviation of the T1-T3 chord
+  const double t13 = (x3 - x1) / (z3 - z1);
+  const double k3 = (g2 - g1) - (z2 - z1) / (z3 - z1) * (g3 - g1);
+  double c = ((x2 - x1) - (z2 - z1) * t13) / k3;
+  double b = t13 - c * (g3 - g1) / (z3 - z1);
+  double a = x1 - b * u1 - c * g1;
+  int pos[6];
+  // slots of the initial layers: it 0 -> layers 0, 4, 8 (slots 0, 2, 4)
+  const int s1 = it ? 1 : 0, s2 = it ? 3 : 2, s3 = it ? 5 : 4;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) pos[k] = -1;
+  int n = 3;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    if (k == s1) pos[k] = i1;
+    else if (k == s2) pos[k] = i2;
+    else if (k == s3) pos[k] = i3;
+    else if ((k & 1) != it) {
+      const int L = xlayer(k);
+      const int h = closest_d(X, zoff[L], zoff[L + 1], xm(a, b, c, P.zd[L], P), P.ext_tol);
+      if (h >= 0) { pos[k] = h; ++n; }
+    }
+  }
+  if (n < P.min_x_hits) return false;
+  double chi2;
+  int m;
+  if (!fit_x(X, Z, pos, P, a, b, c, chi2, m)) return false;
+  if (!(chi2 < P.chi2x_max)) return false;
+  const double score = (m == 6 ? 1.0 : 10.0) * (1000.0 * chi2 + fabs(c));
+  cd.a = a; cd.b = b; cd.c = c; cd.chi2 = chi2;
+  cd.score = (unsigned long long)__double_as_longlong(score);
+  cd.key = key;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) cd.pos[k] = pos[k];
+  cd.n = m;
+  cd.it = it;
+  return true;
+}
+
+// ---------------------------------------------------------------- UV ------
+
+// Iterative UV seeding of Sec. 3.4 for one x-z track, FP64.
+__device__ __forceinline__ bool uv_track(const float *X, const float *Z, const int *zoff,
+                                         const DevParams &P, int half, const Cand &cd,
+                                         int (&bpos)[6], int &bn, double &by0, double &bty,
+                                         double &bchi2) {
+  const double a = cd.a, b = cd.b, c = cd.c;
+  const double ylo = half == 0 ? 0.0 : -P.y_max, yhi = half == 0 ? P.y_max : 0.0;
+  bn = 0;
+  bchi2 = 0.0; by0 = 0.0; bty = 0.0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int L0 = 1 + pass;  // u then v layer of T1
+    const double t0 = P.tand[L0];
+    const double xp = xm(a, b, c, P.zd[L0], P);
+    const double e1 = xp - yhi * t0, e2 = xp - ylo * t0;
+    const double lo = fmin(e1, e2), hi = fmax(e1, e2);
+    const int ez = zoff[L0 + 1];
+    for (int h0 = lower_d(X, zoff[L0], ez, lo); h0 < ez; ++h0) {
+      const double xh0 = X[h0];
+      if (xh0 > hi) break;
+      int pos[6];
+      double ys[6], zs[6];
+      const double zh0 = Z[h0];
+      const double y0h = (xm(a, b, c, zh0, P) - xh0) / t0;
+      double ty = y0h / zh0;
+      int n = 1;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        pos[k] = -1;
+        ys[k] = 0.0;
+        zs[k] = 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const int L = uvlayer(k);
+        if (L == L0) {
+          pos[k] = h0; ys[k] = y0h; zs[k] = zh0;
+          continue;
+        }
+        const double zl = P.zd[L], tl = P.tand[L];
+        const double pred = xm(a, b, c, zl, P) - ty * zl * tl;
+        const int h = closest_d(X, zoff[L], zoff[L + 1], pred, P.uv_tol);
+        if (h < 0) continue;
+        const double zh = Z[h];
+        const double yl = (xm(a, b, c, zh, P) - (double)X[h]) / tl;
+        ty = 0.5 * (ty + yl / zh);
+        pos[k] = h; ys[k] = yl; zs[k] = zh;
+        ++n;
+      }
+      if (n < P.min_uv_hits) continue;
+      // weighted straight line y = y0 + t (z - z_ref), weights tan^2 / sigma^2
+      double s0 = 0, s1 = 0, s2 = 0, q0 = 0, q1 = 0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        if (pos[k] < 0) continue;
+        const double w = P.tand[uvlayer(k)] * P.tand[uvlayer(k)];
+        const double u = zs[k] - P.zref;
+        s0 += w; s1 += w * u; s2 += w * u * u; q0 += w * ys[k]; q1 += w * u * ys[k];
+      }
+      const double det = s0 * s2 - s1 * s1;
+      const double fy0 = (q0 * s2 - q1 * s1) / det;
+      const double fty = (s0 * q1 - s1 * q0) / det;
+      double chi2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        if (pos[k] < 0) continue;
+        const double w = P.tand[uvlayer(k)] * P.tand[uvlayer(k)];
+        const double r = ys[k] - (fy0 + fty * (zs[k] - P.zref));
+        chi2 += w * r * r;
+      }
+      chi2 = chi2 * P.inv_sigma2 / (double)(n - 2);
+      if (!(chi2 < P.chi2y_max)) continue;
+      if (n > bn || (n == bn && chi2 < bchi2)) {
+        bn = n; bchi2 = chi2; by0 = fy0; bty = fty;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) bpos[k] = pos[k];
+      }
+    }
+  }
+  return bn > 0;
+}
+
+// -------------------------------------------------------- seed kernel -----
+
+__device__ __forceinline__ void seed_item(const float *X, const float *Z, const int *zoff,
+                                          const int32_t *hid, int item, int nh,
+                                          const DevParams &P, const Scratch &S,
+                                          unsigned long long *trip, Cand *cand,
+                                          unsigned long long *tbl, SeedStage *sst,
+                                          unsigned *s_ntrip, unsigned *s_ncand,
+                                          unsigned *s_nseed, unsigned long long *s_pbase,
+                                          int *s_scan, int *s_start, int *s_tmp) {
+  const int tid = threadIdx.x;
+  const int half = item & 1;
+  Counters *cnt = S.cnt;
+
+  // XZ seeding: two independent iterations (Sec. 3)
+  xz_triplets(X, Z, zoff, P, 0, trip, S.trip_cap, s_ntrip, s_scan, s_start, s_tmp, cnt);
+  xz_triplets(X, Z, zoff, P, 1, trip, S.trip_cap, s_ntrip, s_scan, s_start, s_tmp, cnt);
+  __syncthreads();
+  unsigned ntrip = *s_ntrip;
+  if (ntrip > (unsigned)S.trip_cap) {
+    if (tid == 0) { raise_flag(cnt, F_TRIP); atomicMax(&cnt->need_trip, ntrip); }
+    ntrip = S.trip_cap;
+  }
+  for (unsigned t = tid; t < ntrip; t += kSeedWG) {
+    Cand cd;
+    if (xz_candidate(X, Z, zoff, P, trip[t], cd)) {
+      const unsigned slot = wave_append(s_ncand);
+      if (slot < (unsigned)S.cand_cap) cand[slot] = cd;
+    }
+  }
+  __syncthreads();
+  unsigned nc = *s_ncand;
+  if (nc > (unsigned)S.cand_cap) {
+    if (tid == 0) { raise_flag(cnt, F_CAND); atomicMax(&cnt->need_cand, nc); }
+    nc = S.cand_cap;
+  }
+
+  // O(n) clone killing (Sec. 3.3.4): per-hit minimum score, then own counts
+  if (nh > S.tbl_cap) {
+    if (tid == 0) { raise_flag(cnt, F_TBL); atomicMax(&cnt->need_tbl, (unsigned)nh); }
+    nc = 0;
+  }
+  for (int i = tid; i < nh && nc > 0; i += kSeedWG) tbl[i] = ~0ull;
+  __syncthreads();
+  for (unsigned i = tid; i < nc; i += kSeedWG) {
+    const unsigned long long sc = cand[i].score;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int p = cand[i].pos[k];
+      if (p >= 0) atomicMin(&tbl[p], sc);
+    }
+  }
+  __syncthreads();
+  for (unsigned i = tid; i < nc; i += kSeedWG) {
+    const unsigned long long sc = cand[i].score;
+    int own = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int p = cand[i].pos[k];
+      if (p >= 0 && tbl[p] == sc) ++own;
+    }
+    const bool keep = own >= 3 || (own >= 2 && cand[i].n == 6);
+    cand[i].n = keep ? cand[i].n : -cand[i].n;   // negative n: lost the vote
+  }
+  __syncthreads();
+  // repeated tracks of the two iterations: a kept second-iteration track
+  // whose x-hit set equals a kept first-iteration track's is dropped.  Equal
+  // hit sets have bit-identical scores, which filters the comparison.
+  for (unsigned i = tid; i < nc; i += kSeedWG) {
+    if (cand[i].it != 1 || cand[i].n < 0) continue;
+    const unsigned long long sc = cand[i].score;
+    bool dup = false;
+    for (unsigned j = 0; j < nc && !dup; ++j) {
+      if (cand[j].score != sc || cand[j].it != 0 || cand[j].n < 0) continue;
+      bool same = true;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) same = same && cand[j].pos[k] == cand[i].pos[k];
+      dup = same;
+    }
+    if (dup) cand[i].it = 2;  // it 2: repeated track
+  }
+  __syncthreads();
+
+  // UV seeding of every surviving x-z track (Sec. 3.4)
+  for (unsigned i = tid; i < nc; i += kSeedWG) {
+    const Cand cd = cand[i];
+    if (cd.n < 0 || cd.it == 2) continue;
+    int upos[6];
+    int nuv;
+    double y0, ty, chi2y;
+    if (!uv_track(X, Z, zoff, P, half, cd, upos, nuv, y0, ty, chi2y)) continue;
+    SeedStage st;
+    st.key = cd.key;
+    st.s.ax = (float)cd.a; st.s.bx = (float)cd.b; st.s.cx = (float)cd.c;
+    st.s.y0 = (float)y0; st.s.ty = (float)ty;
+    st.s.chi2_x = (float)cd.chi2; st.s.chi2_y = (float)chi2y;
+    st.s.score = (float)__longlong_as_double((long long)cd.score);
+    st.s.n_x = cd.n; st.s.n_uv = nuv; st.s.half = half; st.s.iter = cd.it;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      st.s.hits[xlayer(k)] = cd.pos[k] >= 0 ? hid[cd.pos[k]] : -1;
+      st.s.hits[uvlayer(k)] = upos[k] >= 0 ? hid[upos[k]] : -1;
+    }
+    const unsigned slot = wave_append(s_nseed);
+    if (slot < (unsigned)S.sst_cap) sst[slot] = st;
+  }
+  __syncthreads();
+  unsigned ns = *s_nseed;
+  if (ns > (unsigned)S.sst_cap) {
+    if (tid == 0) { raise_flag(cnt, F_SST); atomicMax(&cnt->need_sst, ns); }
+    ns = S.sst_cap;
+  }
+  if (tid == 0) {
+    unsigned long long base = atomicAdd(&cnt->pool_top, (unsigned long long)ns);
+    if (base + ns > (unsigned long long)S.pool_cap) raise_flag(cnt, F_POOL);
+    *s_pbase = base;
+    S.item_cnt[item] = (int)ns;
+    S.item_base[item] = (int)(base < (unsigned long long)S.pool_cap ? base : 0);
+  }
+  __syncthreads();
+  const unsigned long long base = *s_pbase;
+  if (base + ns <= (unsigned long long)S.pool_cap) {
+    // canonical order: rank of each seed's (iteration, T1, T3, T2) key
+    for (unsigned i = tid; i < ns; i += kSeedWG) {
+      const unsigned long long key = sst[i].key;
+      unsigned r = 0;
+      for (unsigned j = 0; j < ns; ++j) r += sst[j].key < key;
+      S.pool[base + r] = sst[i].s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kSeedWG) void k_seed(const Desc *__restrict__ D, Scratch S,
+                                                  DevParams P, int item_begin, int item_count,
+                                                  int use_queue) {
+  __shared__ float s_x[kLdsHits];
+  __shared__ float s_z[kLdsHits];
+  __shared__ int s_zoff[kNL + 1];
+  __shared__ int s_scan[kSeedWG];
+  __shared__ int s_start[kSeedWG];
+  __shared__ int s_tmp[8];
+  __shared__ int s_item;
+  __shared__ unsigned s_ntrip, s_ncand, s_nseed;
+  __shared__ unsigned long long s_pbase;
+
+  const int tid = threadIdx.x;
+  const size_t wg = blockIdx.x;
+  unsigned long long *trip = S.trip + wg * (size_t)S.trip_cap;
+  Cand *cand = S.cand + wg * (size_t)S.cand_cap;
+  unsigned long long *tbl = S.tbl + wg * (size_t)S.tbl_cap;
+  SeedStage *sst = S.sst + wg * (size_t)S.sst_cap;
+  const int32_t *zone_off = D->b.zone_off;
+  const float *hx = D->b.hit_x, *hz = D->b.hit_z;
+  const int32_t *hid = D->b.hit_id;
+  const int n_items = item_count < 0 ? D->n_items : item_count;
+  bool first = true;
+  for (;;) {
+    if (tid == 0) {
+      int q;
+      if (use_queue) q = (int)atomicAdd(&S.cnt->seed_queue, 1u);
+      else q = first ? (int)blockIdx.x : n_items;
+      s_item = q < n_items ? (use_queue ? S.item_order[q] : item_begin + q) : -1;
+      s_ntrip = 0; s_ncand = 0; s_nseed = 0;
+    }
+    first = false;
+    __syncthreads();
+    const int item = s_item;
+    if (item < 0) break;
+    const int k0 = item * kNL;
+    const int base = zone_off[k0];
+    const int nh = zone_off[k0 + kNL] - base;
+    if (tid <= kNL) s_zoff[tid] = zone_off[k0 + tid] - base;
+    if (nh >= kMaxItemHits || nh < 0) {
+      if (tid == 0) {
+        raise_flag(S.cnt, nh < 0 ? F_INVALID : F_LIMIT);
+        S.item_cnt[item] = 0;
+        S.item_base[item] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+    if (nh <= kLdsHits) {
+      for (int i = tid; i < nh; i += kSeedWG) {
+        s_x[i] = hx[base + i];
+        s_z[i] = hz[base + i];
+      }
+      __syncthreads();
+      seed_item(s_x, s_z, s_zoff, hid + base, item, nh, P, S, trip, cand, tbl, sst, &s_ntrip,
+                &s_ncand, &s_nseed, &s_pbase, s_scan, s_start, s_tmp);
+    } else {
+      __syncthreads();
+      seed_item(hx + base, hz + base, s_zoff, hid + base, item, nh, P, S, trip, cand, tbl, sst,
+                &s_ntrip, &s_ncand, &s_nseed, &s_pbase, s_scan, s_start, s_tmp);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ ordering ----
+
+// Items by descending hit count (16 log2 buckets), so the longest items start
+// first and the persistent grid drains evenly.
+__global__ __launch_bounds__(1024) void k_order(const Desc *__restrict__ D, Scratch S) {
+  __shared__ int hist[32], base[32];
+  const int n = D->n_items;
+  const int32_t *zo = D->b.zone_off;
+  if (threadIdx.x < 32) hist[threadIdx.x] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int sz = max(zo[(i + 1) * kNL] - zo[i * kNL], 0);
+    atomicAdd(&hist[31 - __clz(sz + 1)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = 31; b >= 0; --b) { base[b] = acc; acc += hist[b]; }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int sz = max(zo[(i + 1) * kNL] - zo[i * kNL], 0);
+    const int p = atomicAdd(&base[31 - __clz(sz + 1)], 1);
+    S.item_order[p] = i;
+  }
+}
+
+// ---------------------------------------------------------------- init ----
+
+__global__ void k_init(const Desc *__restrict__ D, Scratch S, int plain) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    Counters *c = S.cnt;
+    c->seed_queue = 0; c->match_queue = 0; c->flags = 0;
+    c->pool_top = 0; c->lpool_top = 0;
+    c->need_trip = c->need_cand = c->need_tbl = c->need_sst = 0;
+    c->need_ms = c->need_vs = c->need_surv = 0;
+    c->total_seeds = 0; c->total_longs = 0;
+    if (plain) { D->seed_off[0] = 0; D->long_off[0] = 0; }
+  }
+}
+
+// exclusive scan of per-event counts into off[0..n] (one workgroup)
+__device__ __forceinline__ void scan_counts(const int *c0, const int *c1, int stride, int n,
+                                            int32_t *off, int *s_tmp, long long *total) {
+  int carry = 0;
+  for (int b0 = 0; b0 < n; b0 += 1024) {
+    const int e = b0 + (int)threadIdx.x;
+    const int v = e < n ? (c1 ? c0[e * stride] + c1[e * stride] : c0[e * stride]) : 0;
+    int tot;
+    const int ex = block_excl_scan<1024>(v, s_tmp, tot);
+    if (e < n) off[e] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    off[n] = carry;
+    *total = carry;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_seed_off(const Desc *__restrict__ D, Scratch S) {
+  __shared__ int s_tmp[16];
+  const int n = D->n_events;
+  scan_counts(S.item_cnt, S.item_cnt + 1, 2, n, D->seed_off, s_tmp, &S.cnt->total_seeds);
+  if (threadIdx.x == 0 && S.cnt->total_seeds > D->seed_cap) raise_flag(S.cnt, F_OUT_SEED);
+}
+
+__global__ __launch_bounds__(1024) void k_long_off(const Desc *__restrict__ D, Scratch S) {
+  __shared__ int s_tmp[16];
+  const int n = D->n_events;
+  scan_counts(S.ev_lcnt, nullptr, 1, n, D->long_off, s_tmp, &S.cnt->total_longs);
+  if (threadIdx.x == 0 && S.cnt->total_longs > D->long_cap) raise_flag(S.cnt, F_OUT_LONG);
+}
+
+__global__ __launch_bounds__(256) void k_long_copy(const Desc *__restrict__ D, Scratch S) {
+  const int n = D->n_events;
+  if (S.cnt->flags & (F_OUT_LONG | F_LPOOL)) return;
+  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+    const int m = S.ev_lcnt[e];
+    const long long src = S.ev_lbase[e], dst = D->long_off[e];
+    for (int i = threadIdx.x; i < m; i += blockDim.x) D->longs[dst + i] = S.lpool[src + i];
+  }
+}
+
+// zone offsets non-decreasing from 0, hits x-sorted inside each zone
+__global__ __launch_bounds__(256) void k_validate(const Desc *__restrict__ D, Scratch S) {
+  const int nz = D->n_events * 24;
+  const int32_t *zo = D->b.zone_off;
+  const float *x = D->b.hit_x;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nz; k += gridDim.x * blockDim.x) {
+    if ((k == 0 && zo[0] != 0) || zo[k + 1] < zo[k]) {
+      raise_flag(S.cnt, F_INVALID);
+      continue;
+    }
+    for (int i = zo[k] + 1; i < zo[k + 1]; ++i)
+      if (!(x[i] >= x[i - 1])) { raise_flag(S.cnt, F_UNSORTED); break; }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int32_t *vo = D->b.velo_off;
+    for (int e = 0; e < D->n_events; ++e)
+      if (vo[e + 1] < vo[e]) { raise_flag(S.cnt, F_INVALID); break; }
+    if (D->n_events > 0 && vo[0] != 0) raise_flag(S.cnt, F_INVALID);
+  }
+}
+
+// ------------------------------------------------------------ Matching ----
+
+struct PairEval {
+  double chi2, zm, dx, dy, dtx, dty, qop;
+  bool ok;
+};
+
+// One VELO-seed combination (Sec. 4.1-4.2), FP64.
+__device__ __forceinline__ PairEval eval_pair(const MState &m, double xv, double yv, double zv,
+                                              double txv, double tyv, const DevParams &P) {
+  PairEval r;
+  r.ok = false;
+  const double dtx = m.txs - txv;
+  const double zm = P.zm[0] + P.zm[1] * fabs(dtx) + P.zm[2] * dtx * dtx + P.zm[3] * fabs(m.xs) +
+                    P.zm[4] * txv * txv;
+  const double dx = (m.xs + (zm - P.z_state) * m.txs) - (xv + (zm - zv) * txv);
+  const double dy = m.y_m - (yv + tyv * (P.z_ymatch - zv));
+  const double dty = m.ty - tyv;
+  r.zm = zm; r.dx = dx; r.dy = dy; r.dtx = dtx; r.dty = dty;
+  r.chi2 = 0.0; r.qop = 0.0;
+  if (!(fabs(dx) < P.max_dx && fabs(dy) < P.max_dy && fabs(dtx) < P.max_dtx &&
+        fabs(dty) < P.max_dty))
+    return r;
+  const double tolx = P.tolx_scale * (P.tolx_a * P.tolx_a + P.tolx_b * P.tolx_b * dtx * dtx);
+  const double rho = txv * txv + tyv * tyv;
+  const double toly = P.toly_scale * (P.toly_a * P.toly_a + P.toly_b * P.toly_b * rho);
+  r.chi2 = dx * dx / tolx + dy * dy / toly + dtx * dtx / P.tol_tx + dty * dty / P.tol_ty;
+  if (!(r.chi2 < P.chi2m_max)) return r;
+  // momentum from the kick: eq. invp on the z = 0 distance of the two lines
+  const double x0 = m.x0s - (xv - zv * txv);
+  const double ip = P.invp_a * fabs(x0) + P.invp_b * x0 * x0;
+  r.qop = (x0 >= 0.0 ? -1.0 : 1.0) * P.polarity * ip;
+  r.ok = true;
+  return r;
+}
+
+__device__ __forceinline__ MState seed_state(const sm_seed &s, const DevParams &P) {
+  MState m;
+  const double a = s.ax, b = s.bx, c = s.cx;
+  const double us = P.z_state - P.zref;
+  m.xs = a + b * us + c * gd(us, P.d);
+  m.txs = b + c * (2.0 * us + 3.0 * P.d * us * us);
+  m.y_m = (double)s.y0 + (double)s.ty * (P.z_ymatch - P.zref);
+  m.ty = s.ty;
+  m.x0s = m.xs - P.z_state * m.txs;
+  m.xsf = (float)m.xs; m.txsf = (float)m.txs; m.y_mf = (float)m.y_m; m.tyf = (float)m.ty;
+  return m;
+}
+
+__global__ __launch_bounds__(kMatchWG) void k_match(const Desc *__restrict__ D, Scratch S,
+                                                    DevParams P, int ev_begin, int ev_count,
+                                                    int plain) {
+  __shared__ int s_ev;
+  __shared__ int s_tmp[8];
+  __shared__ unsigned s_nsurv, s_nkeep;
+  __shared__ unsigned long long s_lbase;
+  const int tid = threadIdx.x;
+  const size_t wg = blockIdx.x;
+  MState *ms = S.ms + wg * (size_t)S.ms_cap;
+  unsigned long long *best_s = S.best_s + wg * (size_t)S.ms_cap;
+  unsigned long long *best_v = S.best_v + wg * (size_t)S.vs_cap;
+  Surv *surv = S.surv + wg * (size_t)(2 * S.surv_cap);
+  Surv *kept = surv + S.surv_cap;
+  Counters *cnt = S.cnt;
+  const int n_ev = ev_count < 0 ? D->n_events : ev_count;
+  bool first = true;
+  for (;;) {
+    if (tid == 0) {
+      int q;
+      if (plain) q = first ? 0 : n_ev;
+      else q = (int)atomicAdd(&cnt->match_queue, 1u);
+      s_ev = q < n_ev ? ev_begin + q : -1;
+      s_nsurv = 0;
+      s_nkeep = 0;
+    }
+    first = false;
+    __syncthreads();
+    const int e = s_ev;
+    if (e < 0) break;
+    const int n0 = S.item_cnt[2 * e], n1 = S.item_cnt[2 * e + 1];
+    const int b0 = S.item_base[2 * e], b1 = S.item_base[2 * e + 1];
+    const int ns = n0 + n1;
+    const int so = D->seed_off[e];
+    const int v0 = D->b.velo_off[e], nv = D->b.velo_off[e + 1] - v0;
+    const bool pool_ok = !(cnt->flags & F_POOL);
+    if (tid == 0 && plain) D->seed_off[e + 1] = so + ns;
+    const bool fits = ns <= S.ms_cap && nv <= S.vs_cap && pool_ok;
+    if (tid == 0 && !fits && pool_ok) {
+      if (ns > S.ms_cap) { raise_flag(cnt, F_MS); atomicMax(&cnt->need_ms, (unsigned)ns); }
+      if (nv > S.vs_cap) { raise_flag(cnt, F_VS); atomicMax(&cnt->need_vs, (unsigned)nv); }
+    }
+    // seeds to the output in canonical order: half 0 then half 1
+    for (int i = tid; i < ns && pool_ok; i += kMatchWG) {
+      const sm_seed sd = i < n0 ? S.pool[b0 + i] : S.pool[b1 + i - n0];
+      if ((long long)so + i < D->seed_cap) D->seeds[so + i] = sd;
+      if (fits) {
+        ms[i] = seed_state(sd, P);
+        best_s[i] = ~0ull;
+      }
+    }
+    if (fits)
+      for (int v = tid; v < nv; v += kMatchWG) best_v[v] = ~0ull;
+    __syncthreads();
+    if (fits && ns > 0) {
+      // all VELO x seed combinations: FP32 prefilter, FP64 decision
+      for (int v = tid; v < nv; v += kMatchWG) {
+        const float xvf = D->b.velo_x[v0 + v], yvf = D->b.velo_y[v0 + v], zvf = D->b.velo_z[v0 + v];
+        const float txvf = D->b.velo_tx[v0 + v], tyvf = D->b.velo_ty[v0 + v];
+        const float yvm = yvf + tyvf * (P.z_ymatchf - zvf);
+        const float zmv = P.zmf[0] + P.zmf[4] * txvf * txvf;
+        for (int s = 0; s < ns; ++s) {
+          const MState &m = ms[s];
+          const float dtx = m.txsf - txvf;
+          if (!(fabsf(dtx) < P.pre_dtx)) continue;
+          if (!(fabsf(m.tyf - tyvf) < P.pre_dty)) continue;
+          if (!(fabsf(m.y_mf - yvm) < P.pre_dy)) continue;
+          const float adtx = fabsf(dtx);
+          const float zm = zmv + P.zmf[1] * adtx + P.zmf[2] * dtx * dtx + P.zmf[3] * fabsf(m.xsf);
+          const float dx = (m.xsf + (zm - P.z_statef) * m.txsf) - (xvf + (zm - zvf) * txvf);
+          if (!(fabsf(dx) < P.pre_dx)) continue;
+          const PairEval r = eval_pair(m, xvf, yvf, zvf, txvf, tyvf, P);
+          if (!r.ok) continue;
+          const unsigned long long bits = (unsigned long long)__double_as_longlong(r.chi2);
+          atomicMin(&best_v[v], bits);
+          atomicMin(&best_s[s], bits);
+          const unsigned slot = wave_append(&s_nsurv);
+          if (slot < (unsigned)S.surv_cap) surv[slot] = Surv{v, s, r.chi2};
+        }
+      }
+    }
+    __syncthreads();
+    unsigned nsv = s_nsurv;
+    if (nsv > (unsigned)S.surv_cap) {
+      if (tid == 0) { raise_flag(cnt, F_SURV); atomicMax(&cnt->need_surv, nsv); }
+      nsv = S.surv_cap;
+    }
+    // final selection: a pair survives if its chi2 is the best of its seed and
+    // of its VELO track
+    for (unsigned i = tid; i < nsv; i += kMatchWG) {
+      const Surv sv = surv[i];
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(sv.chi2);
+      if (best_v[sv.v] == bits && best_s[sv.s] == bits) {
+        const unsigned slot = wave_append(&s_nkeep);
+        kept[slot] = sv;
+      }
+    }
+    __syncthreads();
+    const unsigned nk = s_nkeep;
+    if (tid == 0) {
+      if (plain) {
+        const long long lo = D->long_off[e];
+        s_lbase = (unsigned long long)lo;
+        D->long_off[e + 1] = (int)(lo + nk);
+      } else {
+        const unsigned long long b = atomicAdd(&cnt->lpool_top, (unsigned long long)nk);
+        if (b + nk > (unsigned long long)S.lpool_cap) raise_flag(cnt, F_LPOOL);
+        s_lbase = b;
+        S.ev_lcnt[e] = (int)nk;
+        S.ev_lbase[e] = (int)(b < (unsigned long long)S.lpool_cap ? b : 0);
+      }
+    }
+    __syncthreads();
+    const unsigned long long lb = s_lbase;
+    const long long cap = plain ? D->long_cap : S.lpool_cap;
+    sm_long *dst = plain ? D->longs : S.lpool;
+    for (unsigned i = tid; i < nk; i += kMatchWG) {
+      const Surv sv = kept[i];
+      const long long key = ((long long)sv.v << 32) | sv.s;
+      unsigned r = 0;
+      for (unsigned j = 0; j < nk; ++j) r += (((long long)kept[j].v << 32) | kept[j].s) < key;
+      if ((long long)(lb + r) >= cap) continue;
+      const int v = v0 + sv.v;
+      const PairEval pe = eval_pair(ms[sv.s], D->b.velo_x[v], D->b.velo_y[v], D->b.velo_z[v],
+                                    D->b.velo_tx[v], D->b.velo_ty[v], P);
+      sm_long L;
+      L.velo_idx = sv.v; L.seed_idx = sv.s; L.velo_id = D->b.velo_id[v];
+      L.qop = (float)pe.qop; L.chi2 = (float)pe.chi2; L.z_match = (float)pe.zm;
+      L.dx = (float)pe.dx; L.dy = (float)pe.dy; L.dtx = (float)pe.dtx; L.dty = (float)pe.dty;
+      dst[lb + r] = L;
+    }
+    if (plain && tid == 0 && (long long)(lb + nk) > D->long_cap) raise_flag(cnt, F_OUT_LONG);
+    __syncthreads();
+  }
+}
+
+// totals of the plain form (offsets were chained event by event)
+__global__ void k_plain_totals(const Desc *__restrict__ D, Scratch S) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int n = D->n_events;
+    S.cnt->total_seeds = D->seed_off[n];
+    S.cnt->total_longs = D->long_off[n];
+    if (S.cnt->total_seeds > D->seed_cap) raise_flag(S.cnt, F_OUT_SEED);
+    if (S.cnt->total_longs > D->long_cap) raise_flag(S.cnt, F_OUT_LONG);
+  }
+}
+
+}  // namespace smk
+
+using namespace smk;
+
+extern "C" {
+int smk_launch_init(const Desc *d, Scratch s, int plain, hipStream_t st) {
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, d, s, plain);
+  return (int)hipGetLastError();
+}
+int smk_launch_order(const Desc *d, Scratch s, hipStream_t st) {
+  hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, st, d, s);
+  return (int)hipGetLastError();
+}
+int smk_launch_seed(const Desc *d, Scratch s, DevParams p, int item_begin, int item_count,
+                    int use_queue, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_seed, dim3(grid), dim3(kSeedWG), 0, st, d, s, p, item_begin, item_count,
+                     use_queue);
+  return (int)hipGetLastError();
+}
+int smk_launch_seed_off(const Desc *d, Scratch s, hipStream_t st) {
+  hipLaunchKernelGGL(k_seed_off, dim3(1), dim3(1024), 0, st, d, s);
+  return (int)hipGetLastError();
+}
+int smk_launch_match(const Desc *d, Scratch s, DevParams p, int ev_begin, int ev_count,
+                     int plain, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_match, dim3(grid), dim3(kMatchWG), 0, st, d, s, p, ev_begin, ev_count,
+                     plain);
+  return (int)hipGetLastError();
+}
+int smk_launch_long_off(const Desc *d, Scratch s, hipStream_t st) {
+  hipLaunchKernelGGL(k_long_off, dim3(1), dim3(1024), 0, st, d, s);
+  return (int)hipGetLastError();
+}
+int smk_launch_long_copy(const Desc *d, Scratch s, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_long_copy, dim3(grid), dim3(256), 0, st, d, s);
+  return (int)hipGetLastError();
+}
+int smk_launch_validate(const Desc *d, Scratch s, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_validate, dim3(grid), dim3(256), 0, st, d, s);
+  return (int)hipGetLastError();
+}
+int smk_launch_plain_totals(const Desc *d, Scratch s, hipStream_t st) {
+  hipLaunchKernelGGL(k_plain_totals, dim3(1), dim3(64), 0, st, d, s);
+  return (int)hipGetLastError();
+}
+}

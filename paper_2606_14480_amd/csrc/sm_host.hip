@@ -1,0 +1,561 @@
+// Host side of the C-ABI declared in include/sm.h: contexts, serving slots,
+// scratch sizing and growth, the captured graph of the batched form and the
+// per-event launch loop of the plain form.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "sm.h"
+#include "sm_device.h"
+
+extern "C" int smk_launch_plain_totals(const smk::Desc *d, smk::Scratch s, hipStream_t st);
+
+namespace {
+
+using smk::Counters;
+using smk::Desc;
+using smk::DevParams;
+using smk::Scratch;
+
+// Per-workgroup scratch of a slot.  Grown (doubled past the need) when a
+// batch reports that one of them was too small; the batch is then re-run.
+struct Caps {
+  int trip = 8192, cand = 2048, tbl = 8192, sst = 1024;
+  int ms = 1024, vs = 1024, surv = 2048;
+  int items = 0, events = 0;
+  long long pool = 0, lpool = 0;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  Desc *d_desc = nullptr;
+  Desc *h_desc = nullptr;     // pinned
+  Counters *h_cnt = nullptr;  // pinned
+  Scratch S{};
+  Caps caps;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  bool graph_ok = false;
+  hipEvent_t done = nullptr;
+  // serving state
+  bool busy = false;
+  int64_t ticket = -1;
+  sm_batch batch{};
+  sm_out *out = nullptr;
+  int tries = 0;
+  std::vector<void *> allocs;
+};
+
+}  // namespace
+
+struct sm_ctx {
+  int device = 0;
+  sm_geometry g{};
+  sm_params p{};
+  sm_config cfg{};
+  DevParams dp{};
+  int seed_wgs = 0, match_wgs = 0;
+  std::vector<Slot> slots;  // slots[0]: blocking calls; 1..: serving
+  int64_t next_ticket = 1;
+  std::mutex mu;
+  int64_t bytes = 0;
+};
+
+namespace {
+
+sm_status hip_status(hipError_t e) { return e == hipSuccess ? SM_OK : SM_ERR_DEVICE; }
+
+DevParams make_params(const sm_geometry &g, const sm_params &p) {
+  DevParams d{};
+  for (int l = 0; l < smk::kNL; ++l) {
+    d.zf[l] = (float)g.z[l];
+    d.zd[l] = g.z[l];
+    d.tand[l] = g.tan_stereo[l];
+  }
+  d.zref = g.z_ref;
+  d.d = p.d_ratio;
+  d.zreff = (float)g.z_ref;
+  d.df = (float)p.d_ratio;
+  // per-iteration window constants: eq. tolHp and eq. alphacorr at the
+  // nominal z of the iteration's T1 and T3 layers
+  const int l1[2] = {0, 3}, l3[2] = {8, 11};
+  for (int it = 0; it < 2; ++it) {
+    const double z1 = g.z[l1[it]], z3 = g.z[l3[it]];
+    const double a = p.invp_a, b = p.invp_b;
+    const double x0max = (-a + std::sqrt(a * a + 4.0 * b / p.p_min)) / (2.0 * b);
+    d.dx3f[it] = (float)((z3 - z1) / z1 * x0max);
+    d.alphaf[it] = (float)(p.alpha0 / ((z1 / (z3 - z1)) * (p.p_min - p.alpha1)));
+  }
+  d.invp_af = (float)p.invp_a;
+  d.invp_bf = (float)p.invp_b;
+  d.kappa_cf = (float)p.kappa_c;
+  d.t2_tol0f = (float)p.t2_tol0;
+  d.t2_tol1f = (float)p.t2_tol1;
+  d.ext_tol = p.ext_tol;
+  d.inv_sigma2 = 1.0 / (p.sigma_x * p.sigma_x);
+  d.chi2x_max = p.chi2x_max;
+  d.min_x_hits = p.min_x_hits;
+  d.min_uv_hits = p.min_uv_hits;
+  d.uv_tol = p.uv_tol;
+  d.y_max = p.y_max;
+  d.chi2y_max = p.chi2y_max;
+  for (int i = 0; i < 5; ++i) {
+    d.zm[i] = p.zm[i];
+    d.zmf[i] = (float)p.zm[i];
+  }
+  d.z_ymatch = p.z_ymatch;
+  d.z_state = p.z_state;
+  d.z_ymatchf = (float)p.z_ymatch;
+  d.z_statef = (float)p.z_state;
+  d.max_dx = p.max_dx; d.max_dy = p.max_dy; d.max_dtx = p.max_dtx; d.max_dty = p.max_dty;
+  d.tolx_scale = p.tolx_scale; d.tolx_a = p.tolx_a; d.tolx_b = p.tolx_b;
+  d.toly_scale = p.toly_scale; d.toly_a = p.toly_a; d.toly_b = p.toly_b;
+  d.tol_tx = p.tol_tx; d.tol_ty = p.tol_ty;
+  d.chi2m_max = p.chi2m_max;
+  d.polarity = p.polarity;
+  d.invp_a = p.invp_a;
+  d.invp_b = p.invp_b;
+  // FP32 prefilter of the matching preselection: wider than the FP64 cut by
+  // more than the FP32 rounding of the quantities, so it never rejects a pair
+  // the FP64 test would keep.
+  d.pre_dx = (float)(p.max_dx * (1.0 + 1e-4) + 0.05);
+  d.pre_dy = (float)(p.max_dy * (1.0 + 1e-4) + 0.1);
+  d.pre_dtx = (float)(p.max_dtx * (1.0 + 1e-4) + 1e-4);
+  d.pre_dty = (float)(p.max_dty * (1.0 + 1e-4) + 1e-4);
+  return d;
+}
+
+void free_slot_scratch(Slot &s) {
+  for (void *p : s.allocs) hipFree(p);
+  s.allocs.clear();
+  if (s.graph_ok) {
+    hipGraphExecDestroy(s.gexec);
+    hipGraphDestroy(s.graph);
+    s.graph_ok = false;
+  }
+}
+
+template <class T>
+sm_status dalloc(Slot &s, T **p, size_t n, int64_t &bytes) {
+  const size_t b = std::max<size_t>(n, 1) * sizeof(T);
+  void *q = nullptr;
+  if (hipMalloc(&q, b) != hipSuccess) {
+    hipGetLastError();
+    *p = nullptr;
+    return SM_ERR_OOM;
+  }
+  s.allocs.push_back(q);
+  bytes += (int64_t)b;
+  *p = (T *)q;
+  return SM_OK;
+}
+
+// (Re)allocate all scratch of a slot for its current caps.
+sm_status alloc_slot(sm_ctx *c, Slot &s) {
+  free_slot_scratch(s);
+  int64_t bytes = 0;
+  const size_t G = (size_t)c->seed_wgs, M = (size_t)c->match_wgs;
+  const Caps &k = s.caps;
+  Scratch &S = s.S;
+  memset(&S, 0, sizeof(S));
+  sm_status st = SM_OK;
+#define A(ptr, n)                                   \
+  if ((st = dalloc(s, &(ptr), (n), bytes)) != SM_OK) \
+    return st;
+  A(S.trip, G * k.trip);
+  A(S.cand, G * k.cand);
+  A(S.tbl, G * k.tbl);
+  A(S.sst, G * k.sst);
+  A(S.item_order, k.items);
+  A(S.item_cnt, k.items);
+  A(S.item_base, k.items);
+  A(S.ev_lcnt, k.events);
+  A(S.ev_lbase, k.events);
+  A(S.pool, (size_t)k.pool);
+  A(S.lpool, (size_t)k.lpool);
+  A(S.ms, M * k.ms);
+  A(S.best_s, M * k.ms);
+  A(S.best_v, M * k.vs);
+  A(S.surv, M * 2 * (size_t)k.surv);
+  A(S.cnt, 1);
+#undef A
+  S.trip_cap = k.trip; S.cand_cap = k.cand; S.tbl_cap = k.tbl; S.sst_cap = k.sst;
+  S.pool_cap = k.pool; S.lpool_cap = k.lpool;
+  S.ms_cap = k.ms; S.vs_cap = k.vs; S.surv_cap = k.surv;
+  c->bytes += bytes;
+  if (c->cfg.mem_budget > 0 && bytes > c->cfg.mem_budget) return SM_ERR_OOM;
+  return SM_OK;
+}
+
+bool grow(int &cap, unsigned need) {
+  if (need == 0) need = (unsigned)cap + 1;
+  long long n = cap;
+  while (n < (long long)need) n *= 2;
+  n = std::min<long long>(n * 2, (long long)smk::kMaxItemHits * 4);
+  if (n <= cap) return false;
+  cap = (int)n;
+  return true;
+}
+
+// Make the slot's batch-sized buffers large enough for this batch.
+sm_status fit_batch(sm_ctx *c, Slot &s, const sm_batch &b) {
+  Caps &k = s.caps;
+  bool re = false;
+  const int items = 2 * b.n_events;
+  if (items > k.items) { k.items = std::max(items, 2 * k.items); re = true; }
+  if (b.n_events > k.events) { k.events = std::max(b.n_events, 2 * k.events); re = true; }
+  const long long pool = b.n_hits / 4 + 1024;
+  if (pool > k.pool) { k.pool = std::max(pool, 2 * k.pool); re = true; }
+  const long long lpool = b.n_velo + 1024;
+  if (lpool > k.lpool) { k.lpool = std::max(lpool, 2 * k.lpool); re = true; }
+  if (!re && !s.allocs.empty()) return SM_OK;
+  return alloc_slot(c, s);
+}
+
+sm_status check_batch(const sm_batch *b, const sm_out *o) {
+  if (!b || !o) return SM_ERR_INVALID;
+  if (b->n_events < 0 || b->n_hits < 0 || b->n_velo < 0) return SM_ERR_INVALID;
+  if (o->seed_cap < 0 || o->long_cap < 0) return SM_ERR_INVALID;
+  if (!o->seed_off || !o->long_off) return SM_ERR_INVALID;
+  if (b->n_events > 0 && (!b->zone_off || !b->velo_off)) return SM_ERR_INVALID;
+  if (b->n_hits > 0 && (!b->hit_x || !b->hit_z || !b->hit_id)) return SM_ERR_INVALID;
+  if (b->n_velo > 0 && (!b->velo_x || !b->velo_y || !b->velo_z || !b->velo_tx || !b->velo_ty ||
+                        !b->velo_id))
+    return SM_ERR_INVALID;
+  if ((o->seed_cap > 0 && !o->seeds) || (o->long_cap > 0 && !o->longs)) return SM_ERR_INVALID;
+  if (b->n_events > (1 << 26)) return SM_ERR_LIMIT;
+  return SM_OK;
+}
+
+void fill_desc(Slot &s, const sm_batch &b, const sm_out &o) {
+  Desc &d = *s.h_desc;
+  d.b = b;
+  d.seeds = o.seeds;
+  d.longs = o.longs;
+  d.seed_off = o.seed_off;
+  d.long_off = o.long_off;
+  d.seed_cap = o.seed_cap;
+  d.long_cap = o.long_cap;
+  d.n_events = b.n_events;
+  d.n_items = 2 * b.n_events;
+}
+
+sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
+  const Scratch S = s.S;
+  const Desc *d = s.d_desc;
+  auto seq = [&](hipStream_t q) -> hipError_t {
+    int e = smk_launch_init(d, S, 0, q);
+    if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
+    if (!e) e = smk_launch_order(d, S, q);
+    if (!e) e = smk_launch_seed(d, S, c->dp, 0, -1, 1, c->seed_wgs, q);
+    if (!e) e = smk_launch_seed_off(d, S, q);
+    if (!e) e = smk_launch_match(d, S, c->dp, 0, -1, 0, c->match_wgs, q);
+    if (!e) e = smk_launch_long_off(d, S, q);
+    if (!e) e = smk_launch_long_copy(d, S, 1024, q);
+    return (hipError_t)e;
+  };
+  if (!s.graph_ok) {
+    hipStream_t cap;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return SM_ERR_DEVICE;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      hipError_t e2 = seq(cap);
+      e = hipStreamEndCapture(cap, &s.graph);
+      if (e == hipSuccess && e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&s.gexec, s.graph, nullptr, nullptr, 0);
+    hipStreamDestroy(cap);
+    if (e != hipSuccess) return SM_ERR_DEVICE;
+    s.graph_ok = true;
+  }
+  return hip_status(hipGraphLaunch(s.gexec, st));
+}
+
+sm_status enqueue_plain(sm_ctx *c, Slot &s, int n_events, hipStream_t st) {
+  const Scratch S = s.S;
+  const Desc *d = s.d_desc;
+  int e = smk_launch_init(d, S, 1, st);
+  if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, st);
+  for (int ev = 0; ev < n_events && !e; ++ev) {
+    e = smk_launch_seed(d, S, c->dp, 2 * ev, 2, 0, 2, st);
+    if (!e) e = smk_launch_match(d, S, c->dp, ev, 1, 1, 1, st);
+  }
+  if (!e) e = smk_launch_plain_totals(d, S, st);
+  return hip_status((hipError_t)e);
+}
+
+// After the counters came back: grow what overflowed (returns true to re-run)
+// or map the flags to a status.
+bool needs_rerun(sm_ctx *c, Slot &s, sm_status &st) {
+  const Counters &k = *s.h_cnt;
+  st = SM_OK;
+  const unsigned f = k.flags;
+  if (f & smk::F_INVALID) { st = SM_ERR_INVALID; return false; }
+  if (f & smk::F_UNSORTED) { st = SM_ERR_UNSORTED; return false; }
+  if (f & smk::F_LIMIT) { st = SM_ERR_LIMIT; return false; }
+  bool re = false;
+  Caps &cp = s.caps;
+  if (f & smk::F_TRIP) re |= grow(cp.trip, k.need_trip);
+  if (f & smk::F_CAND) re |= grow(cp.cand, k.need_cand);
+  if (f & smk::F_TBL) re |= grow(cp.tbl, k.need_tbl);
+  if (f & smk::F_SST) re |= grow(cp.sst, k.need_sst);
+  if (f & smk::F_MS) re |= grow(cp.ms, k.need_ms);
+  if (f & smk::F_VS) re |= grow(cp.vs, k.need_vs);
+  if (f & smk::F_SURV) re |= grow(cp.surv, k.need_surv);
+  if (f & smk::F_POOL) { cp.pool = std::max<long long>(2 * cp.pool, (long long)k.pool_top + 1024); re = true; }
+  if (f & smk::F_LPOOL) { cp.lpool = std::max<long long>(2 * cp.lpool, (long long)k.lpool_top + 1024); re = true; }
+  if (re) {
+    if (alloc_slot(c, s) != SM_OK) { st = SM_ERR_OOM; return false; }
+    return true;
+  }
+  if (f & (smk::F_OUT_SEED | smk::F_OUT_LONG)) st = SM_ERR_CAPACITY;
+  return false;
+}
+
+sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bool plain) {
+  sm_status st = check_batch(b, o);
+  if (st != SM_OK) return st;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (hipSetDevice(c->device) != hipSuccess) return SM_ERR_DEVICE;
+  Slot &s = c->slots[0];
+  hipStream_t q = (hipStream_t)stream;
+  for (int tries = 0; tries < 8; ++tries) {
+    if ((st = fit_batch(c, s, *b)) != SM_OK) return st;
+    fill_desc(s, *b, *o);
+    if (hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, q) != hipSuccess)
+      return SM_ERR_DEVICE;
+    st = plain ? enqueue_plain(c, s, b->n_events, q) : enqueue_batched(c, s, q);
+    if (st != SM_OK) return st;
+    if (hipMemcpyAsync(s.h_cnt, s.S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q) != hipSuccess)
+      return SM_ERR_DEVICE;
+    if (hipStreamSynchronize(q) != hipSuccess) return SM_ERR_DEVICE;
+    o->n_seeds = s.h_cnt->total_seeds;
+    o->n_longs = s.h_cnt->total_longs;
+    if (!needs_rerun(c, s, st)) return st;
+  }
+  return SM_ERR_CAPACITY;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sm_default_geometry(sm_geometry *g) {
+  static const double z[SM_N_LAYERS] = {7826.0, 7896.0, 7966.0, 8036.0, 8527.5, 8597.5,
+                                        8667.5, 8737.5, 9229.0, 9299.0, 9369.0, 9439.0};
+  const double t = std::tan(5.0 * M_PI / 180.0);
+  for (int l = 0; l < SM_N_LAYERS; ++l) {
+    g->z[l] = z[l];
+    const int kind = l & 3;  // x u v x
+    g->tan_stereo[l] = kind == 1 ? t : (kind == 2 ? -t : 0.0);
+  }
+  g->z_ref = 8525.0;
+}
+
+void sm_default_params(sm_params *p) {
+  memset(p, 0, sizeof(*p));
+  p->p_min = 3000.0;
+  p->invp_a = 1.6322e-7;
+  p->invp_b = -5.0217e-12;
+  p->alpha0 = 2.180e6;
+  p->alpha1 = -1073.0;
+  p->d_ratio = -3.0e-4;
+  p->kappa_c = 3.0e-3;
+  p->t2_tol0 = 0.5;
+  p->t2_tol1 = 0.5;
+  p->ext_tol = 1.0;
+  p->min_x_hits = 5;
+  p->sigma_x = 0.07;
+  p->chi2x_max = 6.0;
+  p->uv_tol = 2.0;
+  p->y_max = 2500.0;
+  p->min_uv_hits = 4;
+  p->chi2y_max = 6.0;
+  const double zm[5] = {5287.6, -7.98878, 317.683, 0.0119379, -1418.42};
+  for (int i = 0; i < 5; ++i) p->zm[i] = zm[i];
+  p->z_ymatch = 10000.0;
+  p->z_state = 9439.0;
+  p->max_dx = 20.0;
+  p->max_dy = 150.0;
+  p->max_dtx = 1.5;
+  p->max_dty = 0.02;
+  p->tolx_scale = 0.8;
+  p->tolx_a = 10.12;
+  p->tolx_b = 101.0;
+  p->toly_scale = 0.2;
+  p->toly_a = 1.59;
+  p->toly_b = 212.1;
+  p->tol_tx = 0.5;
+  p->tol_ty = 1.0 / 937.5;
+  p->chi2m_max = 2.0;
+  p->polarity = 1.0;
+}
+
+sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *cfg, sm_ctx **out) {
+  if (!out) return SM_ERR_INVALID;
+  *out = nullptr;
+  sm_ctx *c = new (std::nothrow) sm_ctx();
+  if (!c) return SM_ERR_OOM;
+  if (g) c->g = *g; else sm_default_geometry(&c->g);
+  if (p) c->p = *p; else sm_default_params(&c->p);
+  if (cfg) c->cfg = *cfg;
+  if (c->p.p_min <= 0 || c->p.sigma_x <= 0 || c->p.min_x_hits < 4 || c->p.min_x_hits > 6 ||
+      c->p.min_uv_hits < 3 || c->p.min_uv_hits > 6 ||
+      c->p.invp_a * c->p.invp_a + 4.0 * c->p.invp_b / c->p.p_min < 0) {
+    delete c;
+    return SM_ERR_INVALID;
+  }
+  c->device = c->cfg.device;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || c->device < 0 || c->device >= ndev ||
+      hipSetDevice(c->device) != hipSuccess) {
+    hipGetLastError();
+    delete c;
+    return SM_ERR_DEVICE;
+  }
+  hipDeviceProp_t prop;
+  hipGetDeviceProperties(&prop, c->device);
+  const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c->seed_wgs = c->cfg.seed_wgs > 0 ? c->cfg.seed_wgs : cus * 4;
+  c->match_wgs = c->cfg.match_wgs > 0 ? c->cfg.match_wgs : cus * 2;
+  c->dp = make_params(c->g, c->p);
+  const int n_slots = 1 + (c->cfg.n_slots > 0 ? c->cfg.n_slots : 2);
+  c->slots.resize(n_slots);
+  for (Slot &s : c->slots) {
+    if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&s.d_desc, sizeof(Desc)) != hipSuccess ||
+        hipHostMalloc(&s.h_desc, sizeof(Desc), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&s.h_cnt, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
+      hipGetLastError();
+      sm_destroy(c);
+      return SM_ERR_DEVICE;
+    }
+    s.caps.items = 2048;
+    s.caps.events = 1024;
+    s.caps.pool = 1 << 16;
+    s.caps.lpool = 1 << 15;
+    sm_status st = alloc_slot(c, s);
+    if (st != SM_OK) {
+      sm_destroy(c);
+      return st;
+    }
+  }
+  *out = c;
+  return SM_OK;
+}
+
+sm_status sm_run(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream) {
+  if (!ctx) return SM_ERR_INVALID;
+  return run_blocking(ctx, batch, out, stream, false);
+}
+
+sm_status sm_run_plain(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream) {
+  if (!ctx) return SM_ERR_INVALID;
+  return run_blocking(ctx, batch, out, stream, true);
+}
+
+static sm_status start_slot(sm_ctx *c, Slot &s) {
+  sm_status st = fit_batch(c, s, s.batch);
+  if (st != SM_OK) return st;
+  fill_desc(s, s.batch, *s.out);
+  if (hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, s.stream) != hipSuccess)
+    return SM_ERR_DEVICE;
+  if ((st = enqueue_batched(c, s, s.stream)) != SM_OK) return st;
+  if (hipMemcpyAsync(s.h_cnt, s.S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s.stream) != hipSuccess)
+    return SM_ERR_DEVICE;
+  return hip_status(hipEventRecord(s.done, s.stream));
+}
+
+sm_status sm_submit(sm_ctx *ctx, const sm_batch *batch, sm_out *out, int64_t *ticket) {
+  if (!ctx || !ticket) return SM_ERR_INVALID;
+  sm_status st = check_batch(batch, out);
+  if (st != SM_OK) return st;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (hipSetDevice(ctx->device) != hipSuccess) return SM_ERR_DEVICE;
+  for (size_t i = 1; i < ctx->slots.size(); ++i) {
+    Slot &s = ctx->slots[i];
+    if (s.busy) continue;
+    s.batch = *batch;
+    s.out = out;
+    s.tries = 0;
+    if ((st = start_slot(ctx, s)) != SM_OK) return st;
+    s.busy = true;
+    s.ticket = ctx->next_ticket++;
+    *ticket = s.ticket;
+    return SM_OK;
+  }
+  return SM_ERR_BUSY;
+}
+
+sm_status sm_poll(sm_ctx *ctx, int64_t ticket, int wait) {
+  if (!ctx) return SM_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (hipSetDevice(ctx->device) != hipSuccess) return SM_ERR_DEVICE;
+  for (size_t i = 1; i < ctx->slots.size(); ++i) {
+    Slot &s = ctx->slots[i];
+    if (!s.busy || s.ticket != ticket) continue;
+    for (;;) {
+      hipError_t e = wait ? hipEventSynchronize(s.done) : hipEventQuery(s.done);
+      if (e == hipErrorNotReady) return SM_ERR_NOT_READY;
+      if (e != hipSuccess) { s.busy = false; return SM_ERR_DEVICE; }
+      sm_status st;
+      s.out->n_seeds = s.h_cnt->total_seeds;
+      s.out->n_longs = s.h_cnt->total_longs;
+      if (needs_rerun(ctx, s, st) && ++s.tries < 8) {
+        if ((st = start_slot(ctx, s)) != SM_OK) { s.busy = false; return st; }
+        if (!wait) return SM_ERR_NOT_READY;
+        continue;
+      }
+      s.busy = false;
+      return st;
+    }
+  }
+  return SM_ERR_INVALID;
+}
+
+int64_t sm_batch_bytes(const sm_ctx *ctx, int32_t n_events, int64_t n_hits, int64_t n_velo) {
+  (void)ctx;
+  const int64_t items = 2 * (int64_t)n_events;
+  return items * 3 * 4 + (int64_t)n_events * 2 * 4 + (n_hits / 4 + 1024) * (int64_t)sizeof(sm_seed) +
+         (n_velo + 1024) * (int64_t)sizeof(sm_long);
+}
+
+sm_status sm_destroy(sm_ctx *ctx) {
+  if (!ctx) return SM_ERR_INVALID;
+  hipSetDevice(ctx->device);
+  for (Slot &s : ctx->slots) {
+    if (s.stream) hipStreamSynchronize(s.stream);
+    free_slot_scratch(s);
+    if (s.done) hipEventDestroy(s.done);
+    if (s.stream) hipStreamDestroy(s.stream);
+    if (s.d_desc) hipFree(s.d_desc);
+    if (s.h_desc) hipHostFree(s.h_desc);
+    if (s.h_cnt) hipHostFree(s.h_cnt);
+  }
+  delete ctx;
+  return SM_OK;
+}
+
+const char *sm_status_str(sm_status s) {
+  switch (s) {
+    case SM_OK: return "ok";
+    case SM_ERR_INVALID: return "invalid argument or malformed batch";
+    case SM_ERR_UNSORTED: return "hits not x-sorted inside a zone";
+    case SM_ERR_CAPACITY: return "output capacity too small";
+    case SM_ERR_OOM: return "out of device memory";
+    case SM_ERR_DEVICE: return "HIP runtime error";
+    case SM_ERR_BUSY: return "no free serving slot";
+    case SM_ERR_NOT_READY: return "not ready";
+    case SM_ERR_LIMIT: return "event exceeds the per-event hit limit";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

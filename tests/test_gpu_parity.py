@@ -1,0 +1,191 @@
+"""HIP library vs FP64 oracle, through the C-ABI (needs an MI355X).
+
+Sizes: the tiny workload, 100..1000 min-bias events, uneven and stress
+subsets — big enough to span many workgroups, LDS tiles and a ragged tail,
+small enough for the oracle to finish in seconds.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import parity as PT
+from paper_2606_14480_amd import events as ev
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2606_14480_amd import sm as S
+    return S
+
+
+@pytest.fixture(scope="module")
+def ctx(sm):
+    c = sm.Context()
+    yield c
+    c.close()
+
+
+def gpu_run(sm, ctx, b, plain=False, seed_cap=None, long_cap=None):
+    return sm.reconstruct(ctx, b, plain=plain, seed_cap=seed_cap, long_cap=long_cap)
+
+
+def check(orc, sm, ctx, b, tag, params_over=None, ctx_params=None):
+    params_over = params_over or {}
+    say(f"[gpu] {tag}: {b.n_events} events, {b.n_hits} hits, {b.n_velo} velo")
+    g = gpu_run(sm, ctx, b)
+    o = orc.run(b, orc.default_params(**params_over), threads=8)
+    st = PT.compare(o, g, b.n_events)
+    if st["mismatches"]:
+        loose = orc.run(b, PT.eps_params(orc, 1e-4, **params_over), threads=8)
+        tight = orc.run(b, PT.eps_params(orc, -1e-4, **params_over), threads=8)
+        st = PT.compare(o, g, b.n_events, band=(loose, tight))
+    say(f"[gpu] {tag}: seeds {st['seeds_o']}/{st['seeds_g']} jaccard {st['seed_jaccard']:.6f} "
+        f"longs {st['longs_o']}/{st['longs_g']} jaccard {st['long_jaccard']:.6f} "
+        f"mismatches {st['mismatches']}")
+    PT.assert_parity(st)
+    return g, o, st
+
+
+def test_tiny_config(orc, sm, ctx):
+    b = ev.generate(ev.config(1, n_events=10))
+    g, o, st = check(orc, sm, ctx, b, "tiny")
+    assert st["mismatches"] == 0
+
+
+def test_tiny_config_low_pmin(orc, sm):
+    b = ev.generate(ev.config(1, n_events=10))
+    c = sm.Context(params=sm.default_params(p_min=1800.0))
+    try:
+        g, o, st = check(orc, sm, c, b, "tiny p_min 1.8 GeV", params_over=dict(p_min=1800.0))
+        assert st["seeds_g"] >= 190
+    finally:
+        c.close()
+
+
+def test_minbias_parity(orc, sm, ctx):
+    b = ev.generate(ev.config(2, n_events=200))
+    check(orc, sm, ctx, b, "minbias 200")
+
+
+def test_minbias_full_size(orc, sm, ctx):
+    """The benchmarked workload itself: 1000 min-bias events, one batch."""
+    b = ev.generate(ev.config(2, n_events=1000))
+    check(orc, sm, ctx, b, "minbias 1000")
+
+
+def test_uneven_subset(orc, sm, ctx):
+    b = ev.generate(ev.config(3, n_events=300))
+    check(orc, sm, ctx, b, "uneven 300")
+
+
+def test_stress_subset(orc, sm, ctx):
+    b = ev.generate(ev.config(4, n_events=60))
+    say("[gpu] stress hits/event max", int(b.event_hits().max()))
+    check(orc, sm, ctx, b, "stress 60")
+
+
+def test_batched_equals_plain(sm, ctx):
+    b = ev.generate(ev.config(2, n_events=40))
+    say("[gpu] batched vs plain, 40 events")
+    g1 = gpu_run(sm, ctx, b)
+    g2 = gpu_run(sm, ctx, b, plain=True)
+    for x, y in zip(g1, g2):
+        assert x.tobytes() == y.tobytes()
+
+
+def test_grid_shape_and_batch_composition(sm, ctx):
+    """Deterministic for any grid shape, and an event's result does not depend
+    on the other events of its batch."""
+    b = ev.generate(ev.config(3, n_events=50))
+    say("[gpu] grid shapes, 50 events")
+    g1 = gpu_run(sm, ctx, b)
+    c2 = sm.Context(seed_wgs=7, match_wgs=3)
+    try:
+        g2 = gpu_run(sm, c2, b)
+    finally:
+        c2.close()
+    for x, y in zip(g1, g2):
+        assert x.tobytes() == y.tobytes()
+    sub = [3, 17, 42]
+    g3 = gpu_run(sm, ctx, b.subset(sub))
+    for i, e in enumerate(sub):
+        s1 = g1[1][g1[0][e]:g1[0][e + 1]]
+        s3 = g3[1][g3[0][i]:g3[0][i + 1]]
+        assert s1.tobytes() == s3.tobytes()
+        l1 = g1[3][g1[2][e]:g1[2][e + 1]]
+        l3 = g3[3][g3[2][i]:g3[2][i + 1]]
+        assert l1.tobytes() == l3.tobytes()
+
+
+def test_edge_cases(orc, sm, ctx):
+    say("[gpu] edge cases")
+    empty = ev.empty_event()
+    # a batch of no events
+    g = gpu_run(sm, ctx, ev.concat([]))
+    assert list(g[0]) == [0] and list(g[2]) == [0]
+    # empty events around a real one, an event with no VELO states
+    one = ev.generate(ev.config(1)).event(0)
+    novelo = ev.generate(ev.config(1, first_event=1)).event(0)
+    novelo.velo_off = np.array([0, 0], np.int32)
+    for k in ("velo_x", "velo_y", "velo_z", "velo_tx", "velo_ty"):
+        setattr(novelo, k, np.zeros(0, np.float32))
+    novelo.velo_id = np.zeros(0, np.int32)
+    b = ev.concat([empty, one, empty, novelo, empty])
+    g = gpu_run(sm, ctx, b)
+    o = orc.run(b)
+    st = PT.compare(o, g, b.n_events)
+    PT.assert_parity(st)
+    assert st["seeds_g"] > 0 and g[2][-1] == o.long_off[-1]
+    # only one half populated
+    oneh = ev.generate(ev.config(2, n_events=1)).event(0)
+    x = oneh.zone_off.copy()
+    x[12:] = x[12]
+    oneh.zone_off = x
+    n = int(x[-1])
+    oneh.hit_x, oneh.hit_z, oneh.hit_id = oneh.hit_x[:n], oneh.hit_z[:n], oneh.hit_id[:n]
+    g = gpu_run(sm, ctx, oneh)
+    o = orc.run(oneh)
+    PT.assert_parity(PT.compare(o, g, 1))
+
+
+def test_capacity_error_and_retry(sm, ctx):
+    b = ev.generate(ev.config(2, n_events=5))
+    say("[gpu] capacity errors")
+    db = sm.DeviceBatch(b)
+    out = sm.DeviceOut(b.n_events, 3, 2)
+    st = ctx.run(db, out, check=False)
+    assert st == sm.ERR_CAPACITY
+    ns, nl = out.n_seeds, out.n_longs
+    assert ns > 3 and nl > 2
+    out2 = sm.DeviceOut(b.n_events, ns, nl)
+    assert ctx.run(db, out2, check=False) == sm.OK
+    assert out2.n_seeds == ns and out2.n_longs == nl
+    g = out2.to_host()
+    g2 = gpu_run(sm, ctx, b)
+    for x, y in zip(g, g2):
+        assert x.tobytes() == y.tobytes()
+
+
+def test_scratch_growth(orc, sm):
+    """A context with tiny scratch grows it and re-runs; results unchanged."""
+    b = ev.generate(ev.config(4, n_events=8))
+    say("[gpu] scratch growth")
+    c = sm.Context(seed_wgs=16, match_wgs=8)
+    try:
+        g = gpu_run(sm, c, b)
+    finally:
+        c.close()
+    o = orc.run(b, threads=8)
+    PT.assert_parity(PT.compare(o, g, b.n_events, band=(
+        orc.run(b, PT.eps_params(orc, 1e-4), threads=8),
+        orc.run(b, PT.eps_params(orc, -1e-4), threads=8))))

@@ -1,0 +1,70 @@
+"""CPU checks of the C-ABI library: it loads, exports every function declared
+in include/sm.h, its struct layouts match the header, and its defaults equal
+the oracle's independently typed constants (no GPU calls here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "sm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sm_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    from paper_2606_14480_amd import sm
+    lib = ctypes.CDLL(sm.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(sm.EXPORTS)
+
+
+def test_struct_layouts():
+    from paper_2606_14480_amd import sm
+    assert sm.SEED_DTYPE.itemsize == 96
+    assert sm.LONG_DTYPE.itemsize == 40
+    assert ctypes.sizeof(sm.Batch) == 8 + 16 + 11 * 8
+    assert ctypes.sizeof(sm.Out) == 64
+
+
+def test_defaults_agree_with_oracle(orc):
+    from paper_2606_14480_amd import sm, events
+    p, q = sm.default_params(), orc.default_params()
+    for name, _ in sm.Params._fields_:
+        if name.startswith("pad"):
+            continue
+        a, b = getattr(p, name), getattr(q, name)
+        if name == "zm":
+            assert list(a) == list(b)
+        else:
+            assert a == b, name
+    g, h = sm.default_geometry(), orc.default_geom()
+    assert list(g.z) == list(h.z) == list(events.LAYER_Z)
+    assert list(g.tan_stereo) == list(h.tan_a)
+    np.testing.assert_allclose(list(g.tan_stereo), events.LAYER_TAN, rtol=1e-15)
+    assert g.z_ref == h.z_ref == events.Z_REF
+
+
+def test_status_strings():
+    from paper_2606_14480_amd import sm
+    for s in range(0, -9, -1):
+        assert sm.status_str(s) and sm.status_str(s) != "unknown status"
+    assert sm.status_str(7) == "unknown status"
+
+
+def test_product_does_not_touch_oracle():
+    """The product package neither imports nor links the oracle."""
+    pkg = os.path.join(ROOT, "paper_2606_14480_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                for bad in ("import oracle", "from oracle", "liboracle", "orc_"):
+                    assert bad not in txt, (f, bad)
