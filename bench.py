@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Throughput of SciFi Seeding + VELO-SciFi Matching on one MI355X.
+
+A step is one pass of the whole path (XZ seeding, clone vote, UV seeding,
+matching, output compaction) over one batch of 1000 synthetic min-bias-like
+events already resident in HBM.  `value` is events/s of the batched form
+(one captured graph of persistent kernels per batch, host sync included);
+the plain form (one kernel sequence per event) is timed beside it.  Outputs
+are checked against the FP64 oracle before timing; the per-kernel roofline
+of the seeding kernel comes from HIP events recorded around it on its stream.
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.join(ROOT, "tests"))
+
+METRIC = ("events/s seeding+matching on 1 MI355X (batched vs plain) at oracle-matched "
+          "tracks; p99 latency")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def seed_kernel_bytes(b, n_seeds: int) -> int:
+    """Algorithmic HBM bytes of one seeding launch: hit x and z (8 B/hit), the
+    zone offsets, per item one count and one pool offset, and per seed its
+    96 B record plus the 12 hit ids it reports."""
+    return 8 * b.n_hits + 4 * (24 * b.n_events + 1) + 2 * 4 * 2 * b.n_events + n_seeds * (96 + 48)
+
+
+def cpu_baseline(batch, seconds: float):
+    from oracle import oracle as O
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    O.run(batch.subset(range(min(10, batch.n_events))), threads=cores)   # warm
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        O.run(batch, threads=cores)
+        reps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    n1 = min(200, batch.n_events)
+    t1 = time.perf_counter()
+    O.run(batch.subset(range(n1)), threads=1)
+    d1 = time.perf_counter() - t1
+    return {"value": round(reps * batch.n_events / dt, 1), "unit": "events/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"the benchmark batch ({batch.n_events} events) run {reps}x on {cores} "
+                      f"threads ({dt:.1f} s wall); single thread on {n1} events: "
+                      f"{n1 / d1:.1f} events/s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--events", type=int, default=1000)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=2.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: events are independent, so more GPUs would "
+              "each run their own batches (no collective); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2606_14480_amd import events as ev
+    from paper_2606_14480_amd import sm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = ev.config(2, n_events=args.events)
+    t0 = time.perf_counter()
+    host = ev.generate(cfg)
+    log(f"[bench] generated {host.n_events} events, {host.n_hits} hits, {host.n_velo} VELO "
+        f"states in {time.perf_counter() - t0:.1f} s")
+    ctx = sm.Context()
+    db = sm.DeviceBatch(host)
+    out = sm.DeviceOut(host.n_events, host.n_hits // 4 + 1024, host.n_velo + 1024)
+    stream = torch.cuda.current_stream()
+
+    ctx.run(db, out, stream)                          # sizes scratch
+    gpu = out.to_host()
+    n_seeds, n_longs = out.n_seeds, out.n_longs
+    parity = None
+    if not args.no_parity:
+        from oracle import oracle as O
+        import parity as PT
+        o = O.run(host, threads=os.cpu_count())
+        st = PT.compare(o, gpu, host.n_events)
+        if st["mismatches"]:
+            st = PT.compare(o, gpu, host.n_events, band=(
+                O.run(host, PT.eps_params(O, 1e-4), threads=os.cpu_count()),
+                O.run(host, PT.eps_params(O, -1e-4), threads=os.cpu_count())))
+        parity = {"seed_jaccard": round(st["seed_jaccard"], 6),
+                  "long_jaccard": round(st["long_jaccard"], 6),
+                  "mismatches": st["mismatches"], "unexplained": len(st["unexplained"]),
+                  "param_failures": len(st["param_fail"])}
+        log(f"[bench] parity vs oracle: {parity}")
+
+    # ---- batched form: the timed region
+    for _ in range(args.warmup):
+        ctx.run(db, out, stream)
+    torch.cuda.synchronize()
+    lat = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        ctx.run(db, out, stream)
+        lat.append(time.perf_counter() - t1)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    value = args.steps * host.n_events / elapsed
+    lat_ms = np.array(lat) * 1e3
+    log(f"[bench] batched: {value:.0f} events/s, {elapsed / args.steps * 1e3:.3f} ms/step")
+
+    # ---- per-kernel device time from HIP events on the launch stream
+    kt = [ctx.profile(db, out, stream) for _ in range(max(5, args.steps // 5))]
+    kern = {k: float(np.mean([t[k] for t in kt])) for k in kt[0]}
+    log(f"[bench] kernel ms: {json.dumps({k: round(v, 4) for k, v in kern.items()})}")
+
+    # ---- plain form: one kernel sequence per event
+    ctx.run(db, out, stream, plain=True)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for _ in range(args.plain_steps):
+        ctx.run(db, out, stream, plain=True)
+    torch.cuda.synchronize()
+    plain = args.plain_steps * host.n_events / (time.perf_counter() - tp)
+    log(f"[bench] plain: {plain:.0f} events/s")
+
+    alg_bytes = seed_kernel_bytes(host, n_seeds)
+    achieved = alg_bytes / (kern["seed"] * 1e-3) / 1e9
+    res = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"minbias-{host.n_events}: {host.n_events} min-bias-like events "
+                               "per batch, Poisson(120) tracks in acceptance, p 1.5-100 GeV, "
+                               "2% hit inefficiency, 10% noise hits, 5% ghost VELO states",
+                   "events_per_batch": host.n_events, "hits": host.n_hits,
+                   "velo_states": host.n_velo, "seeds": n_seeds, "long_tracks": n_longs,
+                   "form": "batched: captured graph, persistent kernels, LPT work queue",
+                   "search_dtype": "f32", "fit_dtype": "f64"},
+        "plain_events_per_s": round(plain, 1),
+        "batched_over_plain": round(value / plain, 2),
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 4),
+                       "what": "per-batch latency of the batched form, call to results"},
+        "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
+        "gpu_events_per_s": round(host.n_events / (kern["total"] * 1e-3), 1),
+        "parity": parity,
+        "roofline": {"bound": "hbm", "kernel": "k_seed", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": None, "alg_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(host, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

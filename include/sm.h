@@ -186,6 +186,18 @@ sm_status sm_submit(sm_ctx *ctx, const sm_batch *batch, sm_out *out, int64_t *ti
  * A ticket is reported complete exactly once; the slot is then free. */
 sm_status sm_poll(sm_ctx *ctx, int64_t ticket, int wait);
 
+/* Per-kernel device time of one batched run, from HIP events recorded on
+ * `stream` between the kernels (milliseconds). */
+typedef struct {
+  float init, order, seed, seed_off, match, long_off, long_copy, total;
+} sm_kernel_times;
+
+/* Tracing: runs the batched form once as plain stream launches (no graph)
+ * with an event between kernels and fills `t`.  Results are identical to
+ * sm_run.  Blocks until done. */
+sm_status sm_profile(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream,
+                     sm_kernel_times *t);
+
 /* Device bytes a batch with these totals needs in a serving slot (used for
  * admission by free memory). */
 int64_t sm_batch_bytes(const sm_ctx *ctx, int32_t n_events, int64_t n_hits, int64_t n_velo);

@@ -290,6 +290,29 @@ sm_status enqueue_plain(sm_ctx *c, Slot &s, int n_events, hipStream_t st) {
   return hip_status((hipError_t)e);
 }
 
+// The batched sequence as plain launches with an event after every kernel.
+sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
+  const Scratch S = s.S;
+  const Desc *d = s.d_desc;
+  int e = hipEventRecord(ev[0], q);
+  if (!e) e = smk_launch_init(d, S, 0, q);
+  if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
+  if (!e) e = hipEventRecord(ev[1], q);
+  if (!e) e = smk_launch_order(d, S, q);
+  if (!e) e = hipEventRecord(ev[2], q);
+  if (!e) e = smk_launch_seed(d, S, c->dp, 0, -1, 1, c->seed_wgs, q);
+  if (!e) e = hipEventRecord(ev[3], q);
+  if (!e) e = smk_launch_seed_off(d, S, q);
+  if (!e) e = hipEventRecord(ev[4], q);
+  if (!e) e = smk_launch_match(d, S, c->dp, 0, -1, 0, c->match_wgs, q);
+  if (!e) e = hipEventRecord(ev[5], q);
+  if (!e) e = smk_launch_long_off(d, S, q);
+  if (!e) e = hipEventRecord(ev[6], q);
+  if (!e) e = smk_launch_long_copy(d, S, 1024, q);
+  if (!e) e = hipEventRecord(ev[7], q);
+  return hip_status((hipError_t)e);
+}
+
 // After the counters came back: grow what overflowed (returns true to re-run)
 // or map the flags to a status.
 bool needs_rerun(sm_ctx *c, Slot &s, sm_status &st) {
@@ -318,7 +341,8 @@ bool needs_rerun(sm_ctx *c, Slot &s, sm_status &st) {
   return false;
 }
 
-sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bool plain) {
+sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bool plain,
+                       sm_kernel_times *times = nullptr) {
   sm_status st = check_batch(b, o);
   if (st != SM_OK) return st;
   std::lock_guard<std::mutex> lk(c->mu);
@@ -330,11 +354,27 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
     fill_desc(s, *b, *o);
     if (hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, q) != hipSuccess)
       return SM_ERR_DEVICE;
-    st = plain ? enqueue_plain(c, s, b->n_events, q) : enqueue_batched(c, s, q);
+    hipEvent_t ev[8] = {};
+    if (times) {
+      for (auto &x : ev)
+        if (hipEventCreate(&x) != hipSuccess) return SM_ERR_DEVICE;
+      st = enqueue_timed(c, s, q, ev);
+    } else {
+      st = plain ? enqueue_plain(c, s, b->n_events, q) : enqueue_batched(c, s, q);
+    }
+    if (st == SM_OK &&
+        hipMemcpyAsync(s.h_cnt, s.S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q) != hipSuccess)
+      st = SM_ERR_DEVICE;
+    if (st == SM_OK && hipStreamSynchronize(q) != hipSuccess) st = SM_ERR_DEVICE;
+    if (times) {
+      if (st == SM_OK) {
+        float *f = &times->init;
+        for (int k = 0; k < 7; ++k) hipEventElapsedTime(&f[k], ev[k], ev[k + 1]);
+        hipEventElapsedTime(&times->total, ev[0], ev[7]);
+      }
+      for (auto &x : ev) hipEventDestroy(x);
+    }
     if (st != SM_OK) return st;
-    if (hipMemcpyAsync(s.h_cnt, s.S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q) != hipSuccess)
-      return SM_ERR_DEVICE;
-    if (hipStreamSynchronize(q) != hipSuccess) return SM_ERR_DEVICE;
     o->n_seeds = s.h_cnt->total_seeds;
     o->n_longs = s.h_cnt->total_longs;
     if (!needs_rerun(c, s, st)) return st;
@@ -459,6 +499,13 @@ sm_status sm_run(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream) 
 sm_status sm_run_plain(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream) {
   if (!ctx) return SM_ERR_INVALID;
   return run_blocking(ctx, batch, out, stream, true);
+}
+
+sm_status sm_profile(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream,
+                     sm_kernel_times *t) {
+  if (!ctx || !t) return SM_ERR_INVALID;
+  memset(t, 0, sizeof(*t));
+  return run_blocking(ctx, batch, out, stream, false, t);
 }
 
 static sm_status start_slot(sm_ctx *c, Slot &s) {

@@ -64,6 +64,14 @@ class Batch(C.Structure):
                 ("velo_tx", C.c_void_p), ("velo_ty", C.c_void_p), ("velo_id", C.c_void_p)]
 
 
+class KernelTimes(C.Structure):
+    _fields_ = [(n, C.c_float) for n in ("init", "order", "seed", "seed_off", "match",
+                                         "long_off", "long_copy", "total")]
+
+    def as_dict(self):
+        return {n: float(getattr(self, n)) for n, _ in self._fields_}
+
+
 class Out(C.Structure):
     _fields_ = [("seed_cap", C.c_int64), ("long_cap", C.c_int64), ("seed_off", C.c_void_p),
                 ("seeds", C.c_void_p), ("long_off", C.c_void_p), ("longs", C.c_void_p),
@@ -93,6 +101,8 @@ _lib.sm_submit.argtypes = [C.c_void_p, _P(Batch), _P(Out), _P(C.c_int64)]
 _lib.sm_submit.restype = C.c_int
 _lib.sm_poll.argtypes = [C.c_void_p, C.c_int64, C.c_int]
 _lib.sm_poll.restype = C.c_int
+_lib.sm_profile.argtypes = [C.c_void_p, _P(Batch), _P(Out), C.c_void_p, _P(KernelTimes)]
+_lib.sm_profile.restype = C.c_int
 _lib.sm_batch_bytes.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int64]
 _lib.sm_batch_bytes.restype = C.c_int64
 _lib.sm_destroy.argtypes = [C.c_void_p]
@@ -101,7 +111,7 @@ _lib.sm_status_str.argtypes = [C.c_int]
 _lib.sm_status_str.restype = C.c_char_p
 
 EXPORTS = ("sm_default_geometry", "sm_default_params", "sm_create", "sm_run", "sm_run_plain",
-           "sm_submit", "sm_poll", "sm_batch_bytes", "sm_destroy", "sm_status_str")
+           "sm_submit", "sm_poll", "sm_profile", "sm_batch_bytes", "sm_destroy", "sm_status_str")
 
 
 def lib():
@@ -225,6 +235,14 @@ class Context:
         if check and st != OK:
             raise SmError(st, "sm_run_plain" if plain else "sm_run")
         return st
+
+    def profile(self, batch: DeviceBatch, out: DeviceOut, stream=None) -> dict:
+        t = KernelTimes()
+        st = _lib.sm_profile(self.h, C.byref(batch.c), C.byref(out.c), _stream_ptr(stream),
+                             C.byref(t))
+        if st != OK:
+            raise SmError(st, "sm_profile")
+        return t.as_dict()
 
     def submit(self, batch: DeviceBatch, out: DeviceOut):
         t = C.c_int64()
