@@ -22,7 +22,11 @@ namespace smk {
 constexpr int kNL = 12;
 constexpr int kSeedWG = 256;        // threads of the seeding workgroup (4 waves)
 constexpr int kMatchWG = 256;
-constexpr int kLdsHits = 4096;      // hits (x, z) one seeding workgroup keeps in LDS
+constexpr int kCandLds = 512;       // x-z candidates whose vote records live in LDS
+constexpr int kSeedLds = 256;       // seeds per item ranked from LDS keys
+constexpr int kMsLds = 512;         // seeds per event whose matching state lives in LDS
+constexpr int kVsLds = 512;         // VELO states per event with LDS best-chi2 entries
+constexpr int kSurvLds = 512;       // matching survivors kept in LDS
 constexpr int kPosBits = 21;        // item-relative hit positions < 2^21
 constexpr int kMaxItemHits = 1 << kPosBits;
 
@@ -42,6 +46,7 @@ enum : unsigned {
   F_LIMIT = 1u << 11,    // an item has >= 2^21 hits
   F_INVALID = 1u << 12,  // malformed offsets
   F_UNSORTED = 1u << 13, // hits not sorted in a zone
+  F_COMBO = 1u << 14,    // UV combination scratch too small
 };
 
 struct Counters {
@@ -49,7 +54,7 @@ struct Counters {
   unsigned flags, pad0;
   unsigned long long pool_top, lpool_top;
   unsigned need_trip, need_cand, need_tbl, need_sst;
-  unsigned need_ms, need_vs, need_surv, pad1;
+  unsigned need_ms, need_vs, need_surv, need_combo;
   long long total_seeds, total_longs;
 };
 
@@ -113,19 +118,30 @@ struct Surv {
   double chi2;
 };
 
+// One (track, initial stereo hit) combination of the UV search.
+struct Combo {
+  double chi2, y0, ty;
+  int c, n, tb, pad;
+  int pos[6];
+};
+
 // Library-owned scratch of one slot.
 struct Scratch {
   unsigned long long *trip;  // [seed_wgs][trip_cap]
   Cand *cand;                // [seed_wgs][cand_cap]
   unsigned long long *tbl;   // [seed_wgs][tbl_cap]
   SeedStage *sst;            // [seed_wgs][sst_cap]
-  int trip_cap, cand_cap, tbl_cap, sst_cap;
+  Combo *combo;              // [seed_wgs][combo_cap]
+  unsigned long long *cscore, *bestchi;  // [seed_wgs][cand_cap], items with many candidates
+  int *cinfo, *bestn, *bestidx;          // [seed_wgs][cand_cap]
+  int trip_cap, cand_cap, tbl_cap, sst_cap, combo_cap, pad2;
   int *item_order, *item_cnt, *item_base;  // [items_cap]
   int *ev_lcnt, *ev_lbase;                 // [events_cap]
   sm_seed *pool;
   sm_long *lpool;
   long long pool_cap, lpool_cap;
   MState *ms;                 // [match_wgs][ms_cap]
+  float *mf;                  // [match_wgs][6 * ms_cap], events with many seeds
   unsigned long long *best_s; // [match_wgs][ms_cap]
   unsigned long long *best_v; // [match_wgs][vs_cap]
   Surv *surv;                 // [match_wgs][surv_cap]
@@ -140,7 +156,7 @@ extern "C" {
 int smk_launch_init(const smk::Desc *d, smk::Scratch s, int plain, hipStream_t st);
 int smk_launch_order(const smk::Desc *d, smk::Scratch s, hipStream_t st);
 int smk_launch_seed(const smk::Desc *d, smk::Scratch s, smk::DevParams p, int item_begin,
-                    int item_count, int use_queue, int grid, hipStream_t st);
+                    int item_count, int use_queue, int grid, int lds_hits, hipStream_t st);
 int smk_launch_seed_off(const smk::Desc *d, smk::Scratch s, hipStream_t st);
 int smk_launch_match(const smk::Desc *d, smk::Scratch s, smk::DevParams p, int ev_begin,
                      int ev_count, int plain, int grid, hipStream_t st);

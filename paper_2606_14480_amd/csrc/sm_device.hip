@@ -148,67 +148,89 @@ __device__ __forceinline__ bool fit_x(const float *X, const float *Z, const int 
 
 // ---------------------------------------------------------------- XZ ------
 
-// T1 x T3 doublets and T2 third hits of one iteration (Sec. 3.3.2-3.3.3), in
-// FP32.  The T1 hits are taken 256 at a time; each thread finds the T3 window
-// of its T1 hit by binary search, a workgroup scan flattens the doublets so
-// that every thread then gets an equal share of them, and the T2 hits found
-// for a doublet are appended to the triplet list with one atomic per wave.
-__device__ __forceinline__ void xz_triplets(const float *X, const float *Z, const int *zoff,
-                                            const DevParams &P, int it, unsigned long long *trip,
-                                            int trip_cap, unsigned *s_ntrip, int *s_scan,
-                                            int *s_start, int *s_tmp, Counters *cnt) {
-  const int L1 = it ? 3 : 0, L2 = it ? 7 : 4, L3 = it ? 11 : 8;
-  const int b1 = zoff[L1], n1 = zoff[L1 + 1] - b1;
-  const int b2 = zoff[L2], e2 = zoff[L2 + 1];
-  const int b3 = zoff[L3], e3 = zoff[L3 + 1];
+// Everything one seeding workgroup keeps in LDS besides the hits (whose
+// capacity is set per launch in dynamic LDS).
+struct SeedShared {
+  unsigned long long cscore[kCandLds];   // candidate scores (vote, repeats)
+  int cinfo[kCandLds];                   // n | it << 3 | lost << 4 | repeat << 5
+  int bestn[kCandLds];                   // UV: most hits per candidate
+  unsigned long long bestchi[kCandLds];  // UV: lowest chi2_y among those
+  int bestidx[kCandLds];                 // UV: earliest (pass, initial hit) among those
+  unsigned long long skey[kSeedLds];     // seed keys for the canonical rank
+  int scan[kSeedWG], a0[kSeedWG], a1[kSeedWG], a2[kSeedWG];
+  int tmp[16];
+  int zoff[kNL + 1];
+  int item;
+  unsigned ntrip, ncand, nseed, ncombo;
+  unsigned long long pbase;
+};
+
+// T1 x T3 doublets and T2 third hits of both iterations (Sec. 3.3.2-3.3.3),
+// FP32.  The T1 hits of both iterations form one list taken 256 at a time;
+// each thread finds the T3 window of its T1 hit by binary search, a
+// workgroup scan flattens the doublets so every thread gets an equal share,
+// and the T2 hits found for a doublet are appended with one atomic per wave.
+__device__ __forceinline__ void xz_triplets(const float *X, const float *Z, SeedShared &sh,
+                                            const DevParams &P, unsigned long long *trip,
+                                            int trip_cap) {
+  const int *zoff = sh.zoff;
+  const int n1a = zoff[1] - zoff[0], n1b = zoff[4] - zoff[3];
+  const int N1 = n1a + n1b;
   const float zr = P.zreff, dd = P.df;
-  const float z2n = P.zf[L2];
-  const float shift = P.zf[L3] + P.alphaf[it], dx3 = P.dx3f[it];
-  const float g2 = gf(z2n - zr, dd);
-  const unsigned long long itbit = (unsigned long long)it << 63;
-  for (int c0 = 0; c0 < n1; c0 += kSeedWG) {
+  for (int c0 = 0; c0 < N1; c0 += kSeedWG) {
     const int j = c0 + (int)threadIdx.x;
-    int st = 0, cnt_j = 0;
-    if (j < n1) {
-      const float x1 = X[b1 + j], z1 = Z[b1 + j];
+    int st = 0, cnt_j = 0, i1 = 0, it = 0;
+    if (j < N1) {
+      it = j >= n1a;
+      i1 = it ? zoff[3] + (j - n1a) : zoff[0] + j;
+      const int L3 = it ? 11 : 8;
+      const float x1 = X[i1], z1 = Z[i1];
       // window around x1 (z3 + alpha_corr) / z1, half-width Delta x3^max
-      const float centre = shift / z1 * x1;
-      st = lower_f(X, b3, e3, centre - dx3);
-      cnt_j = upper_f(X, st, e3, centre + dx3) - st;
+      const float centre = (P.zf[L3] + P.alphaf[it]) / z1 * x1;
+      const float dx3 = P.dx3f[it];
+      st = lower_f(X, zoff[L3], zoff[L3 + 1], centre - dx3);
+      cnt_j = upper_f(X, st, zoff[L3 + 1], centre + dx3) - st;
     }
     int total;
-    const int excl = block_excl_scan<kSeedWG>(cnt_j, s_tmp, total);
-    s_scan[threadIdx.x] = excl;
-    s_start[threadIdx.x] = st;
+    const int excl = block_excl_scan<kSeedWG>(cnt_j, sh.tmp, total);
+    sh.scan[threadIdx.x] = excl;
+    sh.a0[threadIdx.x] = st;
+    sh.a1[threadIdx.x] = i1 | (it << 30);
     __syncthreads();
-    const int nj = min(kSeedWG, n1 - c0);
+    const int nj = min(kSeedWG, N1 - c0);
     for (int d0 = 0; d0 < total; d0 += kSeedWG) {
       const int d = d0 + (int)threadIdx.x;
       if (d < total) {
         int lo = 0, hi = nj;
         while (lo < hi) {
           const int m = (lo + hi) >> 1;
-          if (s_scan[m] <= d) lo = m + 1; else hi = m;
+          if (sh.scan[m] <= d) lo = m + 1; else hi = m;
         }
         const int jj = lo - 1;
-        const int i1 = b1 + c0 + jj;
-        const int i3 = s_start[jj] + (d - s_scan[jj]);
-        const float x1 = X[i1], z1 = Z[i1], x3 = X[i3], z3 = Z[i3];
+        const int w = sh.a1[jj];
+        const int di = w >> 30, d1 = w & 0x3fffffff;
+        const int d3 = sh.a0[jj] + (d - sh.scan[jj]);
+        const int L2 = di ? 7 : 4;
+        const float z2n = P.zf[L2];
+        const float x1 = X[d1], z1 = Z[d1], x3 = X[d3], z3 = Z[d3];
         const float t13 = (x3 - x1) / (z3 - z1);
         const float x0 = x1 - z1 * t13;
         const float ip = P.invp_af * fabsf(x0) + P.invp_bf * x0 * x0;
         const float cpred = (x0 >= 0.0f ? -1.0f : 1.0f) * P.kappa_cf * ip;
         const float g1 = gf(z1 - zr, dd), g3 = gf(z3 - zr, dd);
-        const float k3 = g2 - g1 - (z2n - z1) / (z3 - z1) * (g3 - g1);
+        const float k3 = gf(z2n - zr, dd) - g1 - (z2n - z1) / (z3 - z1) * (g3 - g1);
         const float dev = k3 * cpred;
         const float pred = x1 + (z2n - z1) * t13 + dev;
         const float tol = P.t2_tol0f + P.t2_tol1f * fabsf(dev);
         const float hi2 = pred + tol;
-        int k = lower_f(X, b2, e2, pred - tol);
+        const int e2 = zoff[L2 + 1];
+        int k = lower_f(X, zoff[L2], e2, pred - tol);
         bool more = k < e2 && X[k] <= hi2;
-        const unsigned long long head = itbit | ((unsigned long long)i1 << 42) | ((unsigned long long)i3 << 21);
+        const unsigned long long head = ((unsigned long long)di << 63) |
+                                        ((unsigned long long)d1 << 42) |
+                                        ((unsigned long long)d3 << 21);
         while (more) {
-          const unsigned slot = wave_append(s_ntrip);
+          const unsigned slot = wave_append(&sh.ntrip);
           if (slot < (unsigned)trip_cap) trip[slot] = head | (unsigned long long)k;
           ++k;
           more = k < e2 && X[k] <= hi2;
@@ -268,106 +290,75 @@ __device__ __forceinline__ bool xz_candidate(const float *X, const float *Z, con
 
 // ---------------------------------------------------------------- UV ------
 
-// Iterative UV seeding of Sec. 3.4 for one x-z track, FP64.
-__device__ __forceinline__ bool uv_track(const float *X, const float *Z, const int *zoff,
-                                         const DevParams &P, int half, const Cand &cd,
-                                         int (&bpos)[6], int &bn, double &by0, double &bty,
-                                         double &bchi2) {
-  const double a = cd.a, b = cd.b, c = cd.c;
-  const double ylo = half == 0 ? 0.0 : -P.y_max, yhi = half == 0 ? P.y_max : 0.0;
-  bn = 0;
-  bchi2 = 0.0; by0 = 0.0; bty = 0.0;
-  for (int pass = 0; pass < 2; ++pass) {
-    const int L0 = 1 + pass;  // u then v layer of T1
-    const double t0 = P.tand[L0];
-    const double xp = xm(a, b, c, P.zd[L0], P);
-    const double e1 = xp - yhi * t0, e2 = xp - ylo * t0;
-    const double lo = fmin(e1, e2), hi = fmax(e1, e2);
-    const int ez = zoff[L0 + 1];
-    for (int h0 = lower_d(X, zoff[L0], ez, lo); h0 < ez; ++h0) {
-      const double xh0 = X[h0];
-      if (xh0 > hi) break;
-      int pos[6];
-      double ys[6], zs[6];
-      const double zh0 = Z[h0];
-      const double y0h = (xm(a, b, c, zh0, P) - xh0) / t0;
-      double ty = y0h / zh0;
-      int n = 1;
+// One combination of the iterative UV search of Sec. 3.4, FP64: start from
+// initial hit h0 of stereo layer L0, predict with t_y from the origin, take
+// the closest hit within uv_tol in each of the five other stereo layers in
+// ascending z, averaging t_y after each, then fit y = y0 + t_y (z - z_ref)
+// with weights tan^2(alpha) / sigma^2.  Returns false if it has too few hits
+// or fails the chi2 cut.
+__device__ __forceinline__ bool uv_combo(const float *X, const float *Z, const int *zoff,
+                                         const DevParams &P, double a, double b, double c,
+                                         int L0, int h0, Combo &r) {
+  const double xh0 = X[h0], zh0 = Z[h0];
+  const double t0 = P.tand[L0];
+  const double y0h = (xm(a, b, c, zh0, P) - xh0) / t0;
+  double ty = y0h / zh0;
+  // weighted sums of the line fit, y taken relative to the initial hit's y
+  double s0 = t0 * t0, s1 = s0 * (zh0 - P.zref), s2 = s1 * (zh0 - P.zref);
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+  int n = 1;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        pos[k] = -1;
-        ys[k] = 0.0;
-        zs[k] = 0.0;
-      }
+  for (int k = 0; k < 6; ++k) r.pos[k] = uvlayer(k) == L0 ? h0 : -1;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const int L = uvlayer(k);
-        if (L == L0) {
-          pos[k] = h0; ys[k] = y0h; zs[k] = zh0;
-          continue;
-        }
-        const double zl = P.zd[L], tl = P.tand[L];
-        const double pred = xm(a, b, c, zl, P) - ty * zl * tl;
-        const int h = closest_d(X, zoff[L], zoff[L + 1], pred, P.uv_tol);
-        if (h < 0) continue;
-        const double zh = Z[h];
-        const double yl = (xm(a, b, c, zh, P) - (double)X[h]) / tl;
-        ty = 0.5 * (ty + yl / zh);
-        pos[k] = h; ys[k] = yl; zs[k] = zh;
-        ++n;
-      }
-      if (n < P.min_uv_hits) continue;
-      // weighted straight line y = y0 + t (z - z_ref), weights tan^2 / sigma^2
-      double s0 = 0, s1 = 0, s2 = 0, q0 = 0, q1 = 0;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        if (pos[k] < 0) continue;
-        const double w = P.tand[uvlayer(k)] * P.tand[uvlayer(k)];
-        const double u = zs[k] - P.zref;
-        s0 += w; s1 += w * u; s2 += w * u * u; q0 += w * ys[k]; q1 += w * u * ys[k];
-      }
-      const double det = s0 * s2 - s1 * s1;
-      const double fy0 = (q0 * s2 - q1 * s1) / det;
-      const double fty = (s0 * q1 - s1 * q0) / det;
-      double chi2 = 0.0;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        if (pos[k] < 0) continue;
-        const double w = P.tand[uvlayer(k)] * P.tand[uvlayer(k)];
-        const double r = ys[k] - (fy0 + fty * (zs[k] - P.zref));
-        chi2 += w * r * r;
-      }
-      chi2 = chi2 * P.inv_sigma2 / (double)(n - 2);
-      if (!(chi2 < P.chi2y_max)) continue;
-      if (n > bn || (n == bn && chi2 < bchi2)) {
-        bn = n; bchi2 = chi2; by0 = fy0; bty = fty;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) bpos[k] = pos[k];
-      }
-    }
+  for (int k = 0; k < 6; ++k) {
+    const int L = uvlayer(k);
+    if (L == L0) continue;
+    const double zl = P.zd[L], tl = P.tand[L];
+    const double pred = xm(a, b, c, zl, P) - ty * zl * tl;
+    const int h = closest_d(X, zoff[L], zoff[L + 1], pred, P.uv_tol);
+    if (h < 0) continue;
+    const double zh = Z[h];
+    const double yl = (xm(a, b, c, zh, P) - (double)X[h]) / tl;
+    ty = 0.5 * (ty + yl / zh);
+    r.pos[k] = h;
+    const double w = tl * tl, u = zh - P.zref, yr = yl - y0h;
+    s0 += w; s1 += w * u; s2 += w * u * u;
+    q0 += w * yr; q1 += w * u * yr; q2 += w * yr * yr;
+    ++n;
   }
-  return bn > 0;
+  if (n < P.min_uv_hits) return false;
+  const double det = s0 * s2 - s1 * s1;
+  const double fy = (q0 * s2 - q1 * s1) / det;
+  const double ft = (s0 * q1 - s1 * q0) / det;
+  // residual sum of squares of the weighted fit
+  const double rss = fmax(q2 - fy * q0 - ft * q1, 0.0);
+  const double chi2 = rss * P.inv_sigma2 / (double)(n - 2);
+  if (!(chi2 < P.chi2y_max)) return false;
+  r.chi2 = chi2;
+  r.y0 = fy + y0h;
+  r.ty = ft;
+  r.n = n;
+  return true;
 }
 
 // -------------------------------------------------------- seed kernel -----
 
-__device__ __forceinline__ void seed_item(const float *X, const float *Z, const int *zoff,
-                                          const int32_t *hid, int item, int nh,
-                                          const DevParams &P, const Scratch &S,
-                                          unsigned long long *trip, Cand *cand,
-                                          unsigned long long *tbl, SeedStage *sst,
-                                          unsigned *s_ntrip, unsigned *s_ncand,
-                                          unsigned *s_nseed, unsigned long long *s_pbase,
-                                          int *s_scan, int *s_start, int *s_tmp) {
+__device__ __forceinline__ void seed_item(const float *X, const float *Z, const int32_t *hid,
+                                          int item, int nh, const DevParams &P,
+                                          const Scratch &S, size_t wg, SeedShared &sh) {
   const int tid = threadIdx.x;
   const int half = item & 1;
+  const int *zoff = sh.zoff;
   Counters *cnt = S.cnt;
+  unsigned long long *trip = S.trip + wg * (size_t)S.trip_cap;
+  Cand *cand = S.cand + wg * (size_t)S.cand_cap;
+  unsigned long long *tbl = S.tbl + wg * (size_t)S.tbl_cap;
+  SeedStage *sst = S.sst + wg * (size_t)S.sst_cap;
+  Combo *combo = S.combo + wg * (size_t)S.combo_cap;
 
   // XZ seeding: two independent iterations (Sec. 3)
-  xz_triplets(X, Z, zoff, P, 0, trip, S.trip_cap, s_ntrip, s_scan, s_start, s_tmp, cnt);
-  xz_triplets(X, Z, zoff, P, 1, trip, S.trip_cap, s_ntrip, s_scan, s_start, s_tmp, cnt);
-  __syncthreads();
-  unsigned ntrip = *s_ntrip;
+  xz_triplets(X, Z, sh, P, trip, S.trip_cap);
+  unsigned ntrip = sh.ntrip;
   if (ntrip > (unsigned)S.trip_cap) {
     if (tid == 0) { raise_flag(cnt, F_TRIP); atomicMax(&cnt->need_trip, ntrip); }
     ntrip = S.trip_cap;
@@ -375,26 +366,38 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   for (unsigned t = tid; t < ntrip; t += kSeedWG) {
     Cand cd;
     if (xz_candidate(X, Z, zoff, P, trip[t], cd)) {
-      const unsigned slot = wave_append(s_ncand);
+      const unsigned slot = wave_append(&sh.ncand);
       if (slot < (unsigned)S.cand_cap) cand[slot] = cd;
     }
   }
   __syncthreads();
-  unsigned nc = *s_ncand;
+  unsigned nc = sh.ncand;
   if (nc > (unsigned)S.cand_cap) {
     if (tid == 0) { raise_flag(cnt, F_CAND); atomicMax(&cnt->need_cand, nc); }
     nc = S.cand_cap;
   }
-
-  // O(n) clone killing (Sec. 3.3.4): per-hit minimum score, then own counts
   if (nh > S.tbl_cap) {
     if (tid == 0) { raise_flag(cnt, F_TBL); atomicMax(&cnt->need_tbl, (unsigned)nh); }
     nc = 0;
   }
+  // vote records in LDS, or in this workgroup's global scratch for big items
+  const bool small = nc <= (unsigned)kCandLds;
+  const size_t co = wg * (size_t)S.cand_cap;
+  unsigned long long *cscore = small ? sh.cscore : S.cscore + co;
+  int *cinfo = small ? sh.cinfo : S.cinfo + co;
+  int *bestn = small ? sh.bestn : S.bestn + co;
+  unsigned long long *bestchi = small ? sh.bestchi : S.bestchi + co;
+  int *bestidx = small ? sh.bestidx : S.bestidx + co;
+  for (unsigned i = tid; i < nc; i += kSeedWG) {
+    cscore[i] = cand[i].score;
+    cinfo[i] = cand[i].n | (cand[i].it << 3);
+  }
   for (int i = tid; i < nh && nc > 0; i += kSeedWG) tbl[i] = ~0ull;
   __syncthreads();
+
+  // O(n) clone killing (Sec. 3.3.4): per-hit minimum score, then own counts
   for (unsigned i = tid; i < nc; i += kSeedWG) {
-    const unsigned long long sc = cand[i].score;
+    const unsigned long long sc = cscore[i];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       const int p = cand[i].pos[k];
@@ -403,60 +406,131 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   }
   __syncthreads();
   for (unsigned i = tid; i < nc; i += kSeedWG) {
-    const unsigned long long sc = cand[i].score;
+    const unsigned long long sc = cscore[i];
     int own = 0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       const int p = cand[i].pos[k];
       if (p >= 0 && tbl[p] == sc) ++own;
     }
-    const bool keep = own >= 3 || (own >= 2 && cand[i].n == 6);
-    cand[i].n = keep ? cand[i].n : -cand[i].n;   // negative n: lost the vote
+    const int n = cinfo[i] & 7;
+    if (!(own >= 3 || (own >= 2 && n == 6))) cinfo[i] |= 1 << 4;
   }
   __syncthreads();
-  // repeated tracks of the two iterations: a kept second-iteration track
-  // whose x-hit set equals a kept first-iteration track's is dropped.  Equal
-  // hit sets have bit-identical scores, which filters the comparison.
+  // repeated tracks of the two iterations: a kept iteration-1 track whose
+  // x-hit set equals a kept iteration-0 track's is dropped.  Equal sets have
+  // bit-identical scores, which filters the comparison.
   for (unsigned i = tid; i < nc; i += kSeedWG) {
-    if (cand[i].it != 1 || cand[i].n < 0) continue;
-    const unsigned long long sc = cand[i].score;
+    if ((cinfo[i] & (1 << 4)) || !(cinfo[i] & (1 << 3))) continue;
+    const unsigned long long sc = cscore[i];
     bool dup = false;
     for (unsigned j = 0; j < nc && !dup; ++j) {
-      if (cand[j].score != sc || cand[j].it != 0 || cand[j].n < 0) continue;
+      if (cscore[j] != sc || (cinfo[j] & ((1 << 3) | (1 << 4)))) continue;
       bool same = true;
 #pragma unroll
       for (int k = 0; k < 6; ++k) same = same && cand[j].pos[k] == cand[i].pos[k];
       dup = same;
     }
-    if (dup) cand[i].it = 2;  // it 2: repeated track
+    if (dup) cinfo[i] |= 1 << 5;
   }
   __syncthreads();
 
-  // UV seeding of every surviving x-z track (Sec. 3.4)
-  for (unsigned i = tid; i < nc; i += kSeedWG) {
-    const Cand cd = cand[i];
-    if (cd.n < 0 || cd.it == 2) continue;
-    int upos[6];
-    int nuv;
-    double y0, ty, chi2y;
-    if (!uv_track(X, Z, zoff, P, half, cd, upos, nuv, y0, ty, chi2y)) continue;
+  // UV seeding (Sec. 3.4), one thread per (track, initial hit) combination
+  const double ylo = half == 0 ? 0.0 : -P.y_max, yhi = half == 0 ? P.y_max : 0.0;
+  for (unsigned c0 = 0; c0 < nc; c0 += kSeedWG) {
+    const unsigned ci = c0 + tid;
+    int cnt0 = 0, cnt1 = 0, st0 = 0, st1 = 0;
+    if (ci < nc && !(cinfo[ci] & ((1 << 4) | (1 << 5)))) {
+      const double a = cand[ci].a, b = cand[ci].b, c = cand[ci].c;
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass) {
+        const int L0 = 1 + pass;
+        const double t0 = P.tand[L0];
+        const double xp = xm(a, b, c, P.zd[L0], P);
+        const double e1 = xp - yhi * t0, e2 = xp - ylo * t0;
+        const double lo = fmin(e1, e2), hi = fmax(e1, e2);
+        const int s = lower_d(X, zoff[L0], zoff[L0 + 1], lo);
+        int e = s;
+        while (e < zoff[L0 + 1] && (double)X[e] <= hi) ++e;
+        if (pass == 0) { st0 = s; cnt0 = e - s; } else { st1 = s; cnt1 = e - s; }
+      }
+      bestn[ci] = 0;
+      bestchi[ci] = ~0ull;
+      bestidx[ci] = 0x7fffffff;
+    }
+    int total;
+    const int excl = block_excl_scan<kSeedWG>(cnt0 + cnt1, sh.tmp, total);
+    sh.scan[tid] = excl;
+    sh.a0[tid] = st0;
+    sh.a1[tid] = cnt0;
+    sh.a2[tid] = st1;
+    __syncthreads();
+    const int nj = min((int)kSeedWG, (int)(nc - c0));
+    for (int d0 = 0; d0 < total; d0 += kSeedWG) {
+      const int d = d0 + tid;
+      if (d >= total) continue;
+      int lo = 0, hi = nj;
+      while (lo < hi) {
+        const int m = (lo + hi) >> 1;
+        if (sh.scan[m] <= d) lo = m + 1; else hi = m;
+      }
+      const int jj = lo - 1;
+      const int k = d - sh.scan[jj];
+      const int pass = k >= sh.a1[jj];
+      const int h0 = pass ? sh.a2[jj] + (k - sh.a1[jj]) : sh.a0[jj] + k;
+      const int c = c0 + jj;
+      Combo r;
+      if (!uv_combo(X, Z, zoff, P, cand[c].a, cand[c].b, cand[c].c, 1 + pass, h0, r)) continue;
+      r.c = c;
+      r.tb = (pass << 24) | (h0 - zoff[1 + pass]);
+      const unsigned slot = wave_append(&sh.ncombo);
+      if (slot < (unsigned)S.combo_cap) combo[slot] = r;
+      atomicMax(&bestn[c], r.n);
+    }
+    __syncthreads();
+  }
+  unsigned ncb = sh.ncombo;
+  if (ncb > (unsigned)S.combo_cap) {
+    if (tid == 0) { raise_flag(cnt, F_COMBO); atomicMax(&cnt->need_combo, ncb); }
+    ncb = S.combo_cap;
+  }
+  // best combination per track: most hits, then lowest chi2_y, then the
+  // earlier (pass, initial hit)
+  for (unsigned i = tid; i < ncb; i += kSeedWG) {
+    const Combo &r = combo[i];
+    if (r.n == bestn[r.c]) atomicMin(&bestchi[r.c], (unsigned long long)__double_as_longlong(r.chi2));
+  }
+  __syncthreads();
+  for (unsigned i = tid; i < ncb; i += kSeedWG) {
+    const Combo &r = combo[i];
+    if (r.n == bestn[r.c] && (unsigned long long)__double_as_longlong(r.chi2) == bestchi[r.c])
+      atomicMin(&bestidx[r.c], r.tb);
+  }
+  __syncthreads();
+  for (unsigned i = tid; i < ncb; i += kSeedWG) {
+    const Combo r = combo[i];
+    if (r.n != bestn[r.c] || r.tb != bestidx[r.c] ||
+        (unsigned long long)__double_as_longlong(r.chi2) != bestchi[r.c])
+      continue;
+    const Cand &cd = cand[r.c];
     SeedStage st;
     st.key = cd.key;
     st.s.ax = (float)cd.a; st.s.bx = (float)cd.b; st.s.cx = (float)cd.c;
-    st.s.y0 = (float)y0; st.s.ty = (float)ty;
-    st.s.chi2_x = (float)cd.chi2; st.s.chi2_y = (float)chi2y;
+    st.s.y0 = (float)r.y0; st.s.ty = (float)r.ty;
+    st.s.chi2_x = (float)cd.chi2; st.s.chi2_y = (float)r.chi2;
     st.s.score = (float)__longlong_as_double((long long)cd.score);
-    st.s.n_x = cd.n; st.s.n_uv = nuv; st.s.half = half; st.s.iter = cd.it;
+    st.s.n_x = cd.n; st.s.n_uv = r.n; st.s.half = half; st.s.iter = cd.it;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       st.s.hits[xlayer(k)] = cd.pos[k] >= 0 ? hid[cd.pos[k]] : -1;
-      st.s.hits[uvlayer(k)] = upos[k] >= 0 ? hid[upos[k]] : -1;
+      st.s.hits[uvlayer(k)] = r.pos[k] >= 0 ? hid[r.pos[k]] : -1;
     }
-    const unsigned slot = wave_append(s_nseed);
+    const unsigned slot = wave_append(&sh.nseed);
     if (slot < (unsigned)S.sst_cap) sst[slot] = st;
+    if (slot < (unsigned)kSeedLds) sh.skey[slot] = st.key;
   }
   __syncthreads();
-  unsigned ns = *s_nseed;
+  unsigned ns = sh.nseed;
   if (ns > (unsigned)S.sst_cap) {
     if (tid == 0) { raise_flag(cnt, F_SST); atomicMax(&cnt->need_sst, ns); }
     ns = S.sst_cap;
@@ -464,18 +538,22 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   if (tid == 0) {
     unsigned long long base = atomicAdd(&cnt->pool_top, (unsigned long long)ns);
     if (base + ns > (unsigned long long)S.pool_cap) raise_flag(cnt, F_POOL);
-    *s_pbase = base;
+    sh.pbase = base;
     S.item_cnt[item] = (int)ns;
     S.item_base[item] = (int)(base < (unsigned long long)S.pool_cap ? base : 0);
   }
   __syncthreads();
-  const unsigned long long base = *s_pbase;
+  const unsigned long long base = sh.pbase;
   if (base + ns <= (unsigned long long)S.pool_cap) {
     // canonical order: rank of each seed's (iteration, T1, T3, T2) key
+    const bool lds_keys = ns <= (unsigned)kSeedLds;
     for (unsigned i = tid; i < ns; i += kSeedWG) {
-      const unsigned long long key = sst[i].key;
+      const unsigned long long key = lds_keys ? sh.skey[i] : sst[i].key;
       unsigned r = 0;
-      for (unsigned j = 0; j < ns; ++j) r += sst[j].key < key;
+      if (lds_keys)
+        for (unsigned j = 0; j < ns; ++j) r += sh.skey[j] < key;
+      else
+        for (unsigned j = 0; j < ns; ++j) r += sst[j].key < key;
       S.pool[base + r] = sst[i].s;
     }
   }
@@ -483,23 +561,14 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
 
 __global__ __launch_bounds__(kSeedWG) void k_seed(const Desc *__restrict__ D, Scratch S,
                                                   DevParams P, int item_begin, int item_count,
-                                                  int use_queue) {
-  __shared__ float s_x[kLdsHits];
-  __shared__ float s_z[kLdsHits];
-  __shared__ int s_zoff[kNL + 1];
-  __shared__ int s_scan[kSeedWG];
-  __shared__ int s_start[kSeedWG];
-  __shared__ int s_tmp[8];
-  __shared__ int s_item;
-  __shared__ unsigned s_ntrip, s_ncand, s_nseed;
-  __shared__ unsigned long long s_pbase;
+                                                  int use_queue, int lds_hits) {
+  extern __shared__ float s_dyn[];
+  __shared__ SeedShared sh;
+  float *s_x = s_dyn;
+  float *s_z = s_dyn + lds_hits;
 
   const int tid = threadIdx.x;
   const size_t wg = blockIdx.x;
-  unsigned long long *trip = S.trip + wg * (size_t)S.trip_cap;
-  Cand *cand = S.cand + wg * (size_t)S.cand_cap;
-  unsigned long long *tbl = S.tbl + wg * (size_t)S.tbl_cap;
-  SeedStage *sst = S.sst + wg * (size_t)S.sst_cap;
   const int32_t *zone_off = D->b.zone_off;
   const float *hx = D->b.hit_x, *hz = D->b.hit_z;
   const int32_t *hid = D->b.hit_id;
@@ -510,17 +579,17 @@ __global__ __launch_bounds__(kSeedWG) void k_seed(const Desc *__restrict__ D, Sc
       int q;
       if (use_queue) q = (int)atomicAdd(&S.cnt->seed_queue, 1u);
       else q = first ? (int)blockIdx.x : n_items;
-      s_item = q < n_items ? (use_queue ? S.item_order[q] : item_begin + q) : -1;
-      s_ntrip = 0; s_ncand = 0; s_nseed = 0;
+      sh.item = q < n_items ? (use_queue ? S.item_order[q] : item_begin + q) : -1;
+      sh.ntrip = 0; sh.ncand = 0; sh.nseed = 0; sh.ncombo = 0;
     }
     first = false;
     __syncthreads();
-    const int item = s_item;
+    const int item = sh.item;
     if (item < 0) break;
     const int k0 = item * kNL;
     const int base = zone_off[k0];
     const int nh = zone_off[k0 + kNL] - base;
-    if (tid <= kNL) s_zoff[tid] = zone_off[k0 + tid] - base;
+    if (tid <= kNL) sh.zoff[tid] = zone_off[k0 + tid] - base;
     if (nh >= kMaxItemHits || nh < 0) {
       if (tid == 0) {
         raise_flag(S.cnt, nh < 0 ? F_INVALID : F_LIMIT);
@@ -530,18 +599,16 @@ __global__ __launch_bounds__(kSeedWG) void k_seed(const Desc *__restrict__ D, Sc
       __syncthreads();
       continue;
     }
-    if (nh <= kLdsHits) {
+    if (nh <= lds_hits) {
       for (int i = tid; i < nh; i += kSeedWG) {
         s_x[i] = hx[base + i];
         s_z[i] = hz[base + i];
       }
       __syncthreads();
-      seed_item(s_x, s_z, s_zoff, hid + base, item, nh, P, S, trip, cand, tbl, sst, &s_ntrip,
-                &s_ncand, &s_nseed, &s_pbase, s_scan, s_start, s_tmp);
+      seed_item(s_x, s_z, hid + base, item, nh, P, S, wg, sh);
     } else {
       __syncthreads();
-      seed_item(hx + base, hz + base, s_zoff, hid + base, item, nh, P, S, trip, cand, tbl, sst,
-                &s_ntrip, &s_ncand, &s_nseed, &s_pbase, s_scan, s_start, s_tmp);
+      seed_item(hx + base, hz + base, hid + base, item, nh, P, S, wg, sh);
     }
     __syncthreads();
   }
@@ -582,7 +649,7 @@ __global__ void k_init(const Desc *__restrict__ D, Scratch S, int plain) {
     c->seed_queue = 0; c->match_queue = 0; c->flags = 0;
     c->pool_top = 0; c->lpool_top = 0;
     c->need_trip = c->need_cand = c->need_tbl = c->need_sst = 0;
-    c->need_ms = c->need_vs = c->need_surv = 0;
+    c->need_ms = c->need_vs = c->need_surv = c->need_combo = 0;
     c->total_seeds = 0; c->total_longs = 0;
     if (plain) { D->seed_off[0] = 0; D->long_off[0] = 0; }
   }
@@ -700,20 +767,27 @@ __device__ __forceinline__ MState seed_state(const sm_seed &s, const DevParams &
   return m;
 }
 
+struct MatchShared {
+  float xsf[kMsLds], txsf[kMsLds], ymf[kMsLds], tyf[kMsLds], sty[kMsLds];
+  int sidx[kMsLds];
+  unsigned long long best_s[kMsLds];
+  unsigned long long best_v[kVsLds];
+  Surv surv[kSurvLds];
+  unsigned long long kkey[kSurvLds];
+  int tmp[16];
+  int ev;
+  unsigned nsurv, nkeep;
+  unsigned long long lbase;
+};
+
 __global__ __launch_bounds__(kMatchWG) void k_match(const Desc *__restrict__ D, Scratch S,
                                                     DevParams P, int ev_begin, int ev_count,
                                                     int plain) {
-  __shared__ int s_ev;
-  __shared__ int s_tmp[8];
-  __shared__ unsigned s_nsurv, s_nkeep;
-  __shared__ unsigned long long s_lbase;
+  __shared__ MatchShared sh;
   const int tid = threadIdx.x;
   const size_t wg = blockIdx.x;
   MState *ms = S.ms + wg * (size_t)S.ms_cap;
-  unsigned long long *best_s = S.best_s + wg * (size_t)S.ms_cap;
-  unsigned long long *best_v = S.best_v + wg * (size_t)S.vs_cap;
-  Surv *surv = S.surv + wg * (size_t)(2 * S.surv_cap);
-  Surv *kept = surv + S.surv_cap;
+  float *mf = S.mf + wg * (size_t)S.ms_cap * 6;
   Counters *cnt = S.cnt;
   const int n_ev = ev_count < 0 ? D->n_events : ev_count;
   bool first = true;
@@ -722,13 +796,13 @@ __global__ __launch_bounds__(kMatchWG) void k_match(const Desc *__restrict__ D, 
       int q;
       if (plain) q = first ? 0 : n_ev;
       else q = (int)atomicAdd(&cnt->match_queue, 1u);
-      s_ev = q < n_ev ? ev_begin + q : -1;
-      s_nsurv = 0;
-      s_nkeep = 0;
+      sh.ev = q < n_ev ? ev_begin + q : -1;
+      sh.nsurv = 0;
+      sh.nkeep = 0;
     }
     first = false;
     __syncthreads();
-    const int e = s_ev;
+    const int e = sh.ev;
     if (e < 0) break;
     const int n0 = S.item_cnt[2 * e], n1 = S.item_cnt[2 * e + 1];
     const int b0 = S.item_base[2 * e], b1 = S.item_base[2 * e + 1];
@@ -742,91 +816,119 @@ __global__ __launch_bounds__(kMatchWG) void k_match(const Desc *__restrict__ D, 
       if (ns > S.ms_cap) { raise_flag(cnt, F_MS); atomicMax(&cnt->need_ms, (unsigned)ns); }
       if (nv > S.vs_cap) { raise_flag(cnt, F_VS); atomicMax(&cnt->need_vs, (unsigned)nv); }
     }
-    // seeds to the output in canonical order: half 0 then half 1
+    // per-seed arrays in LDS, or in this workgroup's global scratch for
+    // events with many seeds / VELO states
+    const bool sm_s = ns <= kMsLds, sm_v = nv <= kVsLds;
+    float *xsf = sm_s ? sh.xsf : mf, *txsf = sm_s ? sh.txsf : mf + S.ms_cap;
+    float *ymf = sm_s ? sh.ymf : mf + 2 * (size_t)S.ms_cap;
+    float *tyf = sm_s ? sh.tyf : mf + 3 * (size_t)S.ms_cap;
+    float *sty = sm_s ? sh.sty : mf + 4 * (size_t)S.ms_cap;
+    int *sidx = sm_s ? sh.sidx : (int *)(mf + 5 * (size_t)S.ms_cap);
+    unsigned long long *best_s = sm_s ? sh.best_s : S.best_s + wg * (size_t)S.ms_cap;
+    unsigned long long *best_v = sm_v ? sh.best_v : S.best_v + wg * (size_t)S.vs_cap;
+    // seeds to the output in canonical order (half 0 then half 1) and their
+    // matching state
     for (int i = tid; i < ns && pool_ok; i += kMatchWG) {
       const sm_seed sd = i < n0 ? S.pool[b0 + i] : S.pool[b1 + i - n0];
       if ((long long)so + i < D->seed_cap) D->seeds[so + i] = sd;
       if (fits) {
-        ms[i] = seed_state(sd, P);
+        const MState m = seed_state(sd, P);
+        ms[i] = m;
+        xsf[i] = m.xsf; txsf[i] = m.txsf; ymf[i] = m.y_mf; tyf[i] = m.tyf;
         best_s[i] = ~0ull;
       }
     }
-    if (fits)
-      for (int v = tid; v < nv; v += kMatchWG) best_v[v] = ~0ull;
     __syncthreads();
+    // seeds sorted by t_y, so each VELO state visits only its |dty| window
+    if (fits) {
+      for (int i = tid; i < ns; i += kMatchWG) {
+        const float t = tyf[i];
+        int r = 0;
+        for (int j = 0; j < ns; ++j) {
+          const float u = tyf[j];
+          r += (u < t) || (u == t && j < i);
+        }
+        sty[r] = t;
+        sidx[r] = i;
+      }
+    }
+    __syncthreads();
+    Surv *surv = S.surv + wg * (size_t)(2 * S.surv_cap);
     if (fits && ns > 0) {
-      // all VELO x seed combinations: FP32 prefilter, FP64 decision
       for (int v = tid; v < nv; v += kMatchWG) {
         const float xvf = D->b.velo_x[v0 + v], yvf = D->b.velo_y[v0 + v], zvf = D->b.velo_z[v0 + v];
         const float txvf = D->b.velo_tx[v0 + v], tyvf = D->b.velo_ty[v0 + v];
         const float yvm = yvf + tyvf * (P.z_ymatchf - zvf);
         const float zmv = P.zmf[0] + P.zmf[4] * txvf * txvf;
-        for (int s = 0; s < ns; ++s) {
-          const MState &m = ms[s];
-          const float dtx = m.txsf - txvf;
+        unsigned long long bv = ~0ull;
+        const float thi = tyvf + P.pre_dty;
+        for (int k = lower_f(sty, 0, ns, tyvf - P.pre_dty); k < ns && sty[k] <= thi; ++k) {
+          const int s = sidx[k];
+          const float dtx = txsf[s] - txvf;
           if (!(fabsf(dtx) < P.pre_dtx)) continue;
-          if (!(fabsf(m.tyf - tyvf) < P.pre_dty)) continue;
-          if (!(fabsf(m.y_mf - yvm) < P.pre_dy)) continue;
-          const float adtx = fabsf(dtx);
-          const float zm = zmv + P.zmf[1] * adtx + P.zmf[2] * dtx * dtx + P.zmf[3] * fabsf(m.xsf);
-          const float dx = (m.xsf + (zm - P.z_statef) * m.txsf) - (xvf + (zm - zvf) * txvf);
+          if (!(fabsf(ymf[s] - yvm) < P.pre_dy)) continue;
+          const float zm = zmv + P.zmf[1] * fabsf(dtx) + P.zmf[2] * dtx * dtx + P.zmf[3] * fabsf(xsf[s]);
+          const float dx = (xsf[s] + (zm - P.z_statef) * txsf[s]) - (xvf + (zm - zvf) * txvf);
           if (!(fabsf(dx) < P.pre_dx)) continue;
-          const PairEval r = eval_pair(m, xvf, yvf, zvf, txvf, tyvf, P);
+          const PairEval r = eval_pair(ms[s], xvf, yvf, zvf, txvf, tyvf, P);
           if (!r.ok) continue;
           const unsigned long long bits = (unsigned long long)__double_as_longlong(r.chi2);
-          atomicMin(&best_v[v], bits);
+          bv = bits < bv ? bits : bv;
           atomicMin(&best_s[s], bits);
-          const unsigned slot = wave_append(&s_nsurv);
-          if (slot < (unsigned)S.surv_cap) surv[slot] = Surv{v, s, r.chi2};
+          const unsigned slot = atomicAdd(&sh.nsurv, 1u);
+          if (slot < (unsigned)kSurvLds) sh.surv[slot] = Surv{v, s, r.chi2};
+          else if (slot < (unsigned)(kSurvLds + S.surv_cap)) surv[slot - kSurvLds] = Surv{v, s, r.chi2};
         }
+        best_v[v] = bv;
       }
     }
     __syncthreads();
-    unsigned nsv = s_nsurv;
-    if (nsv > (unsigned)S.surv_cap) {
-      if (tid == 0) { raise_flag(cnt, F_SURV); atomicMax(&cnt->need_surv, nsv); }
-      nsv = S.surv_cap;
+    unsigned nsv = sh.nsurv;
+    if (nsv > (unsigned)(kSurvLds + S.surv_cap)) {
+      if (tid == 0) { raise_flag(cnt, F_SURV); atomicMax(&cnt->need_surv, nsv - kSurvLds); }
+      nsv = kSurvLds + S.surv_cap;
     }
     // final selection: a pair survives if its chi2 is the best of its seed and
     // of its VELO track
+    unsigned long long *kkey = nsv <= (unsigned)kSurvLds ? sh.kkey : (unsigned long long *)(surv + S.surv_cap);
     for (unsigned i = tid; i < nsv; i += kMatchWG) {
-      const Surv sv = surv[i];
+      const Surv sv = i < (unsigned)kSurvLds ? sh.surv[i] : surv[i - kSurvLds];
       const unsigned long long bits = (unsigned long long)__double_as_longlong(sv.chi2);
       if (best_v[sv.v] == bits && best_s[sv.s] == bits) {
-        const unsigned slot = wave_append(&s_nkeep);
-        kept[slot] = sv;
+        const unsigned slot = atomicAdd(&sh.nkeep, 1u);
+        kkey[slot] = ((unsigned long long)sv.v << 32) | (unsigned)sv.s;
       }
     }
     __syncthreads();
-    const unsigned nk = s_nkeep;
+    const unsigned nk = sh.nkeep;
     if (tid == 0) {
       if (plain) {
         const long long lo = D->long_off[e];
-        s_lbase = (unsigned long long)lo;
+        sh.lbase = (unsigned long long)lo;
         D->long_off[e + 1] = (int)(lo + nk);
       } else {
         const unsigned long long b = atomicAdd(&cnt->lpool_top, (unsigned long long)nk);
         if (b + nk > (unsigned long long)S.lpool_cap) raise_flag(cnt, F_LPOOL);
-        s_lbase = b;
+        sh.lbase = b;
         S.ev_lcnt[e] = (int)nk;
         S.ev_lbase[e] = (int)(b < (unsigned long long)S.lpool_cap ? b : 0);
       }
     }
     __syncthreads();
-    const unsigned long long lb = s_lbase;
+    const unsigned long long lb = sh.lbase;
     const long long cap = plain ? D->long_cap : S.lpool_cap;
     sm_long *dst = plain ? D->longs : S.lpool;
     for (unsigned i = tid; i < nk; i += kMatchWG) {
-      const Surv sv = kept[i];
-      const long long key = ((long long)sv.v << 32) | sv.s;
+      const unsigned long long key = kkey[i];
       unsigned r = 0;
-      for (unsigned j = 0; j < nk; ++j) r += (((long long)kept[j].v << 32) | kept[j].s) < key;
+      for (unsigned j = 0; j < nk; ++j) r += kkey[j] < key;
       if ((long long)(lb + r) >= cap) continue;
-      const int v = v0 + sv.v;
-      const PairEval pe = eval_pair(ms[sv.s], D->b.velo_x[v], D->b.velo_y[v], D->b.velo_z[v],
+      const int vi = (int)(key >> 32), si = (int)(key & 0xffffffffu);
+      const int v = v0 + vi;
+      const PairEval pe = eval_pair(ms[si], D->b.velo_x[v], D->b.velo_y[v], D->b.velo_z[v],
                                     D->b.velo_tx[v], D->b.velo_ty[v], P);
       sm_long L;
-      L.velo_idx = sv.v; L.seed_idx = sv.s; L.velo_id = D->b.velo_id[v];
+      L.velo_idx = vi; L.seed_idx = si; L.velo_id = D->b.velo_id[v];
       L.qop = (float)pe.qop; L.chi2 = (float)pe.chi2; L.z_match = (float)pe.zm;
       L.dx = (float)pe.dx; L.dy = (float)pe.dy; L.dtx = (float)pe.dtx; L.dty = (float)pe.dty;
       dst[lb + r] = L;
@@ -861,9 +963,9 @@ int smk_launch_order(const Desc *d, Scratch s, hipStream_t st) {
   return (int)hipGetLastError();
 }
 int smk_launch_seed(const Desc *d, Scratch s, DevParams p, int item_begin, int item_count,
-                    int use_queue, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_seed, dim3(grid), dim3(kSeedWG), 0, st, d, s, p, item_begin, item_count,
-                     use_queue);
+                    int use_queue, int grid, int lds_hits, hipStream_t st) {
+  hipLaunchKernelGGL(k_seed, dim3(grid), dim3(kSeedWG), (size_t)lds_hits * 2 * sizeof(float), st,
+                     d, s, p, item_begin, item_count, use_queue, lds_hits);
   return (int)hipGetLastError();
 }
 int smk_launch_seed_off(const Desc *d, Scratch s, hipStream_t st) {

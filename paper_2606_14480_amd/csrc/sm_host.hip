@@ -26,7 +26,7 @@ using smk::Scratch;
 // Per-workgroup scratch of a slot.  Grown (doubled past the need) when a
 // batch reports that one of them was too small; the batch is then re-run.
 struct Caps {
-  int trip = 8192, cand = 2048, tbl = 8192, sst = 1024;
+  int trip = 8192, cand = 2048, tbl = 8192, sst = 1024, combo = 2048;
   int ms = 1024, vs = 1024, surv = 2048;
   int items = 0, events = 0;
   long long pool = 0, lpool = 0;
@@ -42,6 +42,7 @@ struct Slot {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   bool graph_ok = false;
+  int lds_hits = 2048;  // LDS hit capacity of the seeding workgroup for this batch
   hipEvent_t done = nullptr;
   // serving state
   bool busy = false;
@@ -172,6 +173,12 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
   A(S.cand, G * k.cand);
   A(S.tbl, G * k.tbl);
   A(S.sst, G * k.sst);
+  A(S.combo, G * k.combo);
+  A(S.cscore, G * k.cand);
+  A(S.cinfo, G * k.cand);
+  A(S.bestn, G * k.cand);
+  A(S.bestchi, G * k.cand);
+  A(S.bestidx, G * k.cand);
   A(S.item_order, k.items);
   A(S.item_cnt, k.items);
   A(S.item_base, k.items);
@@ -180,12 +187,14 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
   A(S.pool, (size_t)k.pool);
   A(S.lpool, (size_t)k.lpool);
   A(S.ms, M * k.ms);
+  A(S.mf, M * 6 * (size_t)k.ms);
   A(S.best_s, M * k.ms);
   A(S.best_v, M * k.vs);
   A(S.surv, M * 2 * (size_t)k.surv);
   A(S.cnt, 1);
 #undef A
   S.trip_cap = k.trip; S.cand_cap = k.cand; S.tbl_cap = k.tbl; S.sst_cap = k.sst;
+  S.combo_cap = k.combo;
   S.pool_cap = k.pool; S.lpool_cap = k.lpool;
   S.ms_cap = k.ms; S.vs_cap = k.vs; S.surv_cap = k.surv;
   c->bytes += bytes;
@@ -214,6 +223,22 @@ sm_status fit_batch(sm_ctx *c, Slot &s, const sm_batch &b) {
   if (pool > k.pool) { k.pool = std::max(pool, 2 * k.pool); re = true; }
   const long long lpool = b.n_velo + 1024;
   if (lpool > k.lpool) { k.lpool = std::max(lpool, 2 * k.lpool); re = true; }
+  // LDS hit capacity: the smallest power of two >= 1.5x the mean (event, half)
+  // size, 1024..4096 (items above it read their hits from global memory)
+  int h = std::min(c->cfg.lds_hits, 4096);
+  if (h <= 0) {
+    const double mean = b.n_events > 0 ? (double)b.n_hits / (2.0 * b.n_events) : 0.0;
+    h = 1024;
+    while (h < 4096 && h < 1.5 * mean) h *= 2;
+  }
+  if (h != s.lds_hits) {
+    s.lds_hits = h;
+    if (s.graph_ok) {
+      hipGraphExecDestroy(s.gexec);
+      hipGraphDestroy(s.graph);
+      s.graph_ok = false;
+    }
+  }
   if (!re && !s.allocs.empty()) return SM_OK;
   return alloc_slot(c, s);
 }
@@ -253,7 +278,7 @@ sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
     int e = smk_launch_init(d, S, 0, q);
     if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
     if (!e) e = smk_launch_order(d, S, q);
-    if (!e) e = smk_launch_seed(d, S, c->dp, 0, -1, 1, c->seed_wgs, q);
+    if (!e) e = smk_launch_seed(d, S, c->dp, 0, -1, 1, c->seed_wgs, s.lds_hits, q);
     if (!e) e = smk_launch_seed_off(d, S, q);
     if (!e) e = smk_launch_match(d, S, c->dp, 0, -1, 0, c->match_wgs, q);
     if (!e) e = smk_launch_long_off(d, S, q);
@@ -283,7 +308,7 @@ sm_status enqueue_plain(sm_ctx *c, Slot &s, int n_events, hipStream_t st) {
   int e = smk_launch_init(d, S, 1, st);
   if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, st);
   for (int ev = 0; ev < n_events && !e; ++ev) {
-    e = smk_launch_seed(d, S, c->dp, 2 * ev, 2, 0, 2, st);
+    e = smk_launch_seed(d, S, c->dp, 2 * ev, 2, 0, 2, s.lds_hits, st);
     if (!e) e = smk_launch_match(d, S, c->dp, ev, 1, 1, 1, st);
   }
   if (!e) e = smk_launch_plain_totals(d, S, st);
@@ -300,7 +325,7 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   if (!e) e = hipEventRecord(ev[1], q);
   if (!e) e = smk_launch_order(d, S, q);
   if (!e) e = hipEventRecord(ev[2], q);
-  if (!e) e = smk_launch_seed(d, S, c->dp, 0, -1, 1, c->seed_wgs, q);
+  if (!e) e = smk_launch_seed(d, S, c->dp, 0, -1, 1, c->seed_wgs, s.lds_hits, q);
   if (!e) e = hipEventRecord(ev[3], q);
   if (!e) e = smk_launch_seed_off(d, S, q);
   if (!e) e = hipEventRecord(ev[4], q);
@@ -328,6 +353,7 @@ bool needs_rerun(sm_ctx *c, Slot &s, sm_status &st) {
   if (f & smk::F_CAND) re |= grow(cp.cand, k.need_cand);
   if (f & smk::F_TBL) re |= grow(cp.tbl, k.need_tbl);
   if (f & smk::F_SST) re |= grow(cp.sst, k.need_sst);
+  if (f & smk::F_COMBO) re |= grow(cp.combo, k.need_combo);
   if (f & smk::F_MS) re |= grow(cp.ms, k.need_ms);
   if (f & smk::F_VS) re |= grow(cp.vs, k.need_vs);
   if (f & smk::F_SURV) re |= grow(cp.surv, k.need_surv);
