@@ -22,7 +22,8 @@ namespace smk {
 constexpr int kNL = 12;
 constexpr int kSeedWG = 256;        // threads of the seeding workgroup (4 waves)
 constexpr int kMatchWG = 256;
-constexpr int kCandLds = 512;       // x-z candidates whose vote records live in LDS
+constexpr int kCandLds = 256;       // x-z candidates whose vote records live in LDS
+constexpr int kXtabLds = 1024;      // x hits of an item with an LDS clone-vote entry
 constexpr int kSeedLds = 256;       // seeds per item ranked from LDS keys
 constexpr int kMsLds = 512;         // seeds per event whose matching state lives in LDS
 constexpr int kVsLds = 512;         // VELO states per event with LDS best-chi2 entries
@@ -73,7 +74,7 @@ struct Desc {
 // Parameters in the precision each kernel uses.
 struct DevParams {
   float zf[kNL];
-  double zd[kNL], tand[kNL];
+  double zd[kNL], tand[kNL], inv_tand[kNL];
   double zref, d;
   float zreff, df;
   // XZ, FP32 search
@@ -149,18 +150,25 @@ struct Scratch {
   Counters *cnt;
 };
 
+// Per-slot kernel context in device memory: kernels read scratch pointers and
+// parameters through one pointer, so no argument has to stay in registers.
+struct KCtx {
+  Scratch S;
+  DevParams P;
+};
+
 }  // namespace smk
 
 extern "C" {
 // Launchers (sm_device.hip); each returns the hipError_t of its launch.
-int smk_launch_init(const smk::Desc *d, smk::Scratch s, int plain, hipStream_t st);
-int smk_launch_order(const smk::Desc *d, smk::Scratch s, hipStream_t st);
-int smk_launch_seed(const smk::Desc *d, smk::Scratch s, smk::DevParams p, int item_begin,
+int smk_launch_init(const smk::Desc *d, const smk::KCtx *k, int plain, hipStream_t st);
+int smk_launch_order(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
+int smk_launch_seed(const smk::Desc *d, const smk::KCtx *k, int item_begin,
                     int item_count, int use_queue, int grid, int lds_hits, hipStream_t st);
-int smk_launch_seed_off(const smk::Desc *d, smk::Scratch s, hipStream_t st);
-int smk_launch_match(const smk::Desc *d, smk::Scratch s, smk::DevParams p, int ev_begin,
+int smk_launch_seed_off(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
+int smk_launch_match(const smk::Desc *d, const smk::KCtx *k, int ev_begin,
                      int ev_count, int plain, int grid, hipStream_t st);
-int smk_launch_long_off(const smk::Desc *d, smk::Scratch s, hipStream_t st);
-int smk_launch_long_copy(const smk::Desc *d, smk::Scratch s, int grid, hipStream_t st);
-int smk_launch_validate(const smk::Desc *d, smk::Scratch s, int grid, hipStream_t st);
+int smk_launch_long_off(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
+int smk_launch_long_copy(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
+int smk_launch_validate(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 }

@@ -148,28 +148,88 @@ __device__ __forceinline__ bool fit_x(const float *X, const float *Z, const int 
 
 // ---------------------------------------------------------------- XZ ------
 
+// Per-zone x-bin index of an item whose hits sit in LDS: bins[L][b] is the
+// zone-local index of the first hit whose bin number kbin(x) exceeds b.
+// kbin is a monotonic function of x, so every hit before bins[L][kbin(v)-1]
+// lies below v and a lower-bound search starts there and walks forward a
+// hit or two instead of bisecting the zone.
+constexpr int kBins = 128;
+constexpr float kBinX0 = -3600.0f;
+constexpr float kBinInv = (float)kBins / 7200.0f;
+
+__device__ __forceinline__ int kbin(float x) {
+  const float f = floorf((x - kBinX0) * kBinInv);
+  return f < 0.0f ? 0 : (f >= (float)kBins ? kBins : (int)f + 1);
+}
+
 // Everything one seeding workgroup keeps in LDS besides the hits (whose
 // capacity is set per launch in dynamic LDS).
 struct SeedShared {
-  unsigned long long cscore[kCandLds];   // candidate scores (vote, repeats)
+  unsigned short bins[kNL][kBins];
+  unsigned long long cscore[kCandLds];   // candidate scores
   int cinfo[kCandLds];                   // n | it << 3 | lost << 4 | repeat << 5
-  int bestn[kCandLds];                   // UV: most hits per candidate
-  unsigned long long bestchi[kCandLds];  // UV: lowest chi2_y among those
-  int bestidx[kCandLds];                 // UV: earliest (pass, initial hit) among those
-  unsigned long long skey[kSeedLds];     // seed keys for the canonical rank
+  unsigned short cpos[kCandLds][6];      // x-hit positions + 1 (0: none)
+  union {
+    unsigned long long xtab[kXtabLds];   // clone-vote table over the item's x hits
+    struct {
+      double cabc[kCandLds][3];          // x-z parameters for UV
+      unsigned long long bestchi[kCandLds];
+      int bestn[kCandLds];
+      int bestidx[kCandLds];
+    } uv;
+    unsigned long long skey[kSeedLds];   // seed keys for the canonical rank
+  } u;
   int scan[kSeedWG], a0[kSeedWG], a1[kSeedWG], a2[kSeedWG];
   int tmp[16];
   int zoff[kNL + 1];
+  int xb[7];                             // first compact x index of each x slot
   int item;
   unsigned ntrip, ncand, nseed, ncombo;
   unsigned long long pbase;
 };
 
+// first i of zone L with X[i] >= v
+template <bool kLds, class T>
+__device__ __forceinline__ int zlower(const float *X, const SeedShared &sh, int L, T v) {
+  const int lo = sh.zoff[L], hi = sh.zoff[L + 1];
+  if constexpr (kLds) {
+    const int k = kbin((float)v);
+    int i = lo + (k > 0 ? (int)sh.bins[L][k - 1] : 0);
+    while (i < hi && (T)X[i] < v) ++i;
+    return i;
+  } else {
+    int a = lo, b = hi;
+    while (a < b) {
+      const int m = (a + b) >> 1;
+      if ((T)X[m] < v) a = m + 1; else b = m;
+    }
+    return a;
+  }
+}
+
+// Closest hit to pred in zone L inside [pred - tol, pred + tol], lower
+// position on ties; -1 if none.
+template <bool kLds>
+__device__ __forceinline__ int zclosest(const float *X, const SeedShared &sh, int L, double pred,
+                                        double tol) {
+  const int hi = sh.zoff[L + 1];
+  int best = -1;
+  double bd = 0.0;
+  for (int i = zlower<kLds>(X, sh, L, pred - tol); i < hi; ++i) {
+    const double x = X[i];
+    if (x > pred + tol) break;
+    const double d = fabs(x - pred);
+    if (best < 0 || d < bd) { best = i; bd = d; }
+  }
+  return best;
+}
+
 // T1 x T3 doublets and T2 third hits of both iterations (Sec. 3.3.2-3.3.3),
 // FP32.  The T1 hits of both iterations form one list taken 256 at a time;
-// each thread finds the T3 window of its T1 hit by binary search, a
-// workgroup scan flattens the doublets so every thread gets an equal share,
-// and the T2 hits found for a doublet are appended with one atomic per wave.
+// each thread finds the T3 window of its T1 hit, a workgroup scan flattens
+// the doublets so every thread gets an equal share, and the T2 hits found
+// for a doublet are appended with one atomic per wave.
+template <bool kLds>
 __device__ __forceinline__ void xz_triplets(const float *X, const float *Z, SeedShared &sh,
                                             const DevParams &P, unsigned long long *trip,
                                             int trip_cap) {
@@ -188,8 +248,21 @@ __device__ __forceinline__ void xz_triplets(const float *X, const float *Z, Seed
       // window around x1 (z3 + alpha_corr) / z1, half-width Delta x3^max
       const float centre = (P.zf[L3] + P.alphaf[it]) / z1 * x1;
       const float dx3 = P.dx3f[it];
-      st = lower_f(X, zoff[L3], zoff[L3 + 1], centre - dx3);
-      cnt_j = upper_f(X, st, zoff[L3 + 1], centre + dx3) - st;
+      st = zlower<kLds>(X, sh, L3, centre - dx3);
+      const float hi3 = centre + dx3;
+      int en = st;
+      const int e3 = zoff[L3 + 1];
+      if constexpr (kLds) {
+        en = zlower<kLds>(X, sh, L3, hi3);
+        while (en < e3 && X[en] <= hi3) ++en;
+      } else {
+        int b = e3;
+        while (en < b) {
+          const int m = (en + b) >> 1;
+          if (X[m] <= hi3) en = m + 1; else b = m;
+        }
+      }
+      cnt_j = en - st;
     }
     int total;
     const int excl = block_excl_scan<kSeedWG>(cnt_j, sh.tmp, total);
@@ -224,7 +297,7 @@ __device__ __forceinline__ void xz_triplets(const float *X, const float *Z, Seed
         const float tol = P.t2_tol0f + P.t2_tol1f * fabsf(dev);
         const float hi2 = pred + tol;
         const int e2 = zoff[L2 + 1];
-        int k = lower_f(X, zoff[L2], e2, pred - tol);
+        int k = zlower<kLds>(X, sh, L2, pred - tol);
         bool more = k < e2 && X[k] <= hi2;
         const unsigned long long head = ((unsigned long long)di << 63) |
                                         ((unsigned long long)d1 << 42) |
@@ -242,7 +315,8 @@ __device__ __forceinline__ void xz_triplets(const float *X, const float *Z, Seed
 }
 
 // Extension, fit and score of one triplet (Sec. 3.2, eq. seed_clone_score).
-__device__ __forceinline__ bool xz_candidate(const float *X, const float *Z, const int *zoff,
+template <bool kLds>
+__device__ __forceinline__ bool xz_candidate(const float *X, const float *Z, const SeedShared &sh,
                                              const DevParams &P, unsigned long long key, Cand &cd) {
   const unsigned msk = (1u << kPosBits) - 1u;
   const int it = (int)(key >> 63);
@@ -250,10 +324,11 @@ __device__ __forceinline__ bool xz_candidate(const float *X, const float *Z, con
   const double x1 = X[i1], z1 = Z[i1], x2 = X[i2], z2 = Z[i2], x3 = X[i3], z3 = Z[i3];
   const double u1 = z1 - P.zref, g1 = gd(u1, P.d), g2 = gd(z2 - P.zref, P.d), g3 = gd(z3 - P.zref, P.d);
   // model through the three hits: c from the T2 deviation of the T1-T3 chord
-  const double t13 = (x3 - x1) / (z3 - z1);
-  const double k3 = (g2 - g1) - (z2 - z1) / (z3 - z1) * (g3 - g1);
+  const double r31 = 1.0 / (z3 - z1);
+  const double t13 = (x3 - x1) * r31;
+  const double k3 = (g2 - g1) - (z2 - z1) * r31 * (g3 - g1);
   double c = ((x2 - x1) - (z2 - z1) * t13) / k3;
-  double b = t13 - c * (g3 - g1) / (z3 - z1);
+  double b = t13 - c * (g3 - g1) * r31;
   double a = x1 - b * u1 - c * g1;
   int pos[6];
   // slots of the initial layers: it 0 -> layers 0, 4, 8 (slots 0, 2, 4)
@@ -268,7 +343,7 @@ __device__ __forceinline__ bool xz_candidate(const float *X, const float *Z, con
     else if (k == s3) pos[k] = i3;
     else if ((k & 1) != it) {
       const int L = xlayer(k);
-      const int h = closest_d(X, zoff[L], zoff[L + 1], xm(a, b, c, P.zd[L], P), P.ext_tol);
+      const int h = zclosest<kLds>(X, sh, L, xm(a, b, c, P.zd[L], P), P.ext_tol);
       if (h >= 0) { pos[k] = h; ++n; }
     }
   }
@@ -296,12 +371,13 @@ __device__ __forceinline__ bool xz_candidate(const float *X, const float *Z, con
 // ascending z, averaging t_y after each, then fit y = y0 + t_y (z - z_ref)
 // with weights tan^2(alpha) / sigma^2.  Returns false if it has too few hits
 // or fails the chi2 cut.
-__device__ __forceinline__ bool uv_combo(const float *X, const float *Z, const int *zoff,
+template <bool kLds>
+__device__ __forceinline__ bool uv_combo(const float *X, const float *Z, const SeedShared &sh,
                                          const DevParams &P, double a, double b, double c,
                                          int L0, int h0, Combo &r) {
   const double xh0 = X[h0], zh0 = Z[h0];
   const double t0 = P.tand[L0];
-  const double y0h = (xm(a, b, c, zh0, P) - xh0) / t0;
+  const double y0h = (xm(a, b, c, zh0, P) - xh0) * P.inv_tand[L0];
   double ty = y0h / zh0;
   // weighted sums of the line fit, y taken relative to the initial hit's y
   double s0 = t0 * t0, s1 = s0 * (zh0 - P.zref), s2 = s1 * (zh0 - P.zref);
@@ -315,10 +391,10 @@ __device__ __forceinline__ bool uv_combo(const float *X, const float *Z, const i
     if (L == L0) continue;
     const double zl = P.zd[L], tl = P.tand[L];
     const double pred = xm(a, b, c, zl, P) - ty * zl * tl;
-    const int h = closest_d(X, zoff[L], zoff[L + 1], pred, P.uv_tol);
+    const int h = zclosest<kLds>(X, sh, L, pred, P.uv_tol);
     if (h < 0) continue;
     const double zh = Z[h];
-    const double yl = (xm(a, b, c, zh, P) - (double)X[h]) / tl;
+    const double yl = (xm(a, b, c, zh, P) - (double)X[h]) * P.inv_tand[L];
     ty = 0.5 * (ty + yl / zh);
     r.pos[k] = h;
     const double w = tl * tl, u = zh - P.zref, yr = yl - y0h;
@@ -328,8 +404,9 @@ __device__ __forceinline__ bool uv_combo(const float *X, const float *Z, const i
   }
   if (n < P.min_uv_hits) return false;
   const double det = s0 * s2 - s1 * s1;
-  const double fy = (q0 * s2 - q1 * s1) / det;
-  const double ft = (s0 * q1 - s1 * q0) / det;
+  const double idet = 1.0 / det;
+  const double fy = (q0 * s2 - q1 * s1) * idet;
+  const double ft = (s0 * q1 - s1 * q0) * idet;
   // residual sum of squares of the weighted fit
   const double rss = fmax(q2 - fy * q0 - ft * q1, 0.0);
   const double chi2 = rss * P.inv_sigma2 / (double)(n - 2);
@@ -343,6 +420,10 @@ __device__ __forceinline__ bool uv_combo(const float *X, const float *Z, const i
 
 // -------------------------------------------------------- seed kernel -----
 
+// Seeding of one (event, half) item.  kLds: the item's hits are in LDS (with
+// the x-bin index); the candidate-side arrays are in LDS whenever they fit,
+// else in this workgroup's global scratch.
+template <bool kLds>
 __device__ __forceinline__ void seed_item(const float *X, const float *Z, const int32_t *hid,
                                           int item, int nh, const DevParams &P,
                                           const Scratch &S, size_t wg, SeedShared &sh) {
@@ -352,12 +433,11 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   Counters *cnt = S.cnt;
   unsigned long long *trip = S.trip + wg * (size_t)S.trip_cap;
   Cand *cand = S.cand + wg * (size_t)S.cand_cap;
-  unsigned long long *tbl = S.tbl + wg * (size_t)S.tbl_cap;
   SeedStage *sst = S.sst + wg * (size_t)S.sst_cap;
   Combo *combo = S.combo + wg * (size_t)S.combo_cap;
 
   // XZ seeding: two independent iterations (Sec. 3)
-  xz_triplets(X, Z, sh, P, trip, S.trip_cap);
+  xz_triplets<kLds>(X, Z, sh, P, trip, S.trip_cap);
   unsigned ntrip = sh.ntrip;
   if (ntrip > (unsigned)S.trip_cap) {
     if (tid == 0) { raise_flag(cnt, F_TRIP); atomicMax(&cnt->need_trip, ntrip); }
@@ -365,9 +445,15 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   }
   for (unsigned t = tid; t < ntrip; t += kSeedWG) {
     Cand cd;
-    if (xz_candidate(X, Z, zoff, P, trip[t], cd)) {
+    if (xz_candidate<kLds>(X, Z, sh, P, trip[t], cd)) {
       const unsigned slot = wave_append(&sh.ncand);
       if (slot < (unsigned)S.cand_cap) cand[slot] = cd;
+      if (slot < (unsigned)kCandLds) {
+        sh.cscore[slot] = cd.score;
+        sh.cinfo[slot] = cd.n | (cd.it << 3);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sh.cpos[slot][k] = (unsigned short)(cd.pos[k] + 1);
+      }
     }
   }
   __syncthreads();
@@ -376,32 +462,38 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
     if (tid == 0) { raise_flag(cnt, F_CAND); atomicMax(&cnt->need_cand, nc); }
     nc = S.cand_cap;
   }
-  if (nh > S.tbl_cap) {
-    if (tid == 0) { raise_flag(cnt, F_TBL); atomicMax(&cnt->need_tbl, (unsigned)nh); }
-    nc = 0;
-  }
-  // vote records in LDS, or in this workgroup's global scratch for big items
-  const bool small = nc <= (unsigned)kCandLds;
+  const int nx = sh.xb[6];
+  // vote records and table in LDS when they fit, else in global scratch
+  const bool small = kLds && nc <= (unsigned)kCandLds && nx <= kXtabLds;
   const size_t co = wg * (size_t)S.cand_cap;
   unsigned long long *cscore = small ? sh.cscore : S.cscore + co;
   int *cinfo = small ? sh.cinfo : S.cinfo + co;
-  int *bestn = small ? sh.bestn : S.bestn + co;
-  unsigned long long *bestchi = small ? sh.bestchi : S.bestchi + co;
-  int *bestidx = small ? sh.bestidx : S.bestidx + co;
-  for (unsigned i = tid; i < nc; i += kSeedWG) {
-    cscore[i] = cand[i].score;
-    cinfo[i] = cand[i].n | (cand[i].it << 3);
+  unsigned long long *xt = small ? sh.u.xtab : S.tbl + wg * (size_t)S.tbl_cap;
+  if (!small && nx > S.tbl_cap) {
+    if (tid == 0) { raise_flag(cnt, F_TBL); atomicMax(&cnt->need_tbl, (unsigned)nx); }
+    nc = 0;
   }
-  for (int i = tid; i < nh && nc > 0; i += kSeedWG) tbl[i] = ~0ull;
+  if (!small) {
+    for (unsigned i = tid; i < nc; i += kSeedWG) {
+      cscore[i] = cand[i].score;
+      cinfo[i] = cand[i].n | (cand[i].it << 3);
+    }
+  }
+  for (int i = tid; i < nx && nc > 0; i += kSeedWG) xt[i] = ~0ull;
   __syncthreads();
+  // compact x index of the hit in slot k of candidate i, or -1
+  auto xidx = [&](unsigned i, int k) -> int {
+    const int p = small ? (int)sh.cpos[i][k] - 1 : cand[i].pos[k];
+    return p < 0 ? -1 : p - zoff[xlayer(k)] + sh.xb[k];
+  };
 
   // O(n) clone killing (Sec. 3.3.4): per-hit minimum score, then own counts
   for (unsigned i = tid; i < nc; i += kSeedWG) {
     const unsigned long long sc = cscore[i];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const int p = cand[i].pos[k];
-      if (p >= 0) atomicMin(&tbl[p], sc);
+      const int p = xidx(i, k);
+      if (p >= 0) atomicMin(&xt[p], sc);
     }
   }
   __syncthreads();
@@ -410,8 +502,8 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
     int own = 0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const int p = cand[i].pos[k];
-      if (p >= 0 && tbl[p] == sc) ++own;
+      const int p = xidx(i, k);
+      if (p >= 0 && xt[p] == sc) ++own;
     }
     const int n = cinfo[i] & 7;
     if (!(own >= 3 || (own >= 2 && n == 6))) cinfo[i] |= 1 << 4;
@@ -428,7 +520,7 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
       if (cscore[j] != sc || (cinfo[j] & ((1 << 3) | (1 << 4)))) continue;
       bool same = true;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) same = same && cand[j].pos[k] == cand[i].pos[k];
+      for (int k = 0; k < 6; ++k) same = same && xidx(j, k) == xidx(i, k);
       dup = same;
     }
     if (dup) cinfo[i] |= 1 << 5;
@@ -436,12 +528,17 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   __syncthreads();
 
   // UV seeding (Sec. 3.4), one thread per (track, initial hit) combination
+  double *cabc = small ? &sh.u.uv.cabc[0][0] : nullptr;
+  int *bestn = small ? sh.u.uv.bestn : S.bestn + co;
+  unsigned long long *bestchi = small ? sh.u.uv.bestchi : S.bestchi + co;
+  int *bestidx = small ? sh.u.uv.bestidx : S.bestidx + co;
   const double ylo = half == 0 ? 0.0 : -P.y_max, yhi = half == 0 ? P.y_max : 0.0;
   for (unsigned c0 = 0; c0 < nc; c0 += kSeedWG) {
     const unsigned ci = c0 + tid;
     int cnt0 = 0, cnt1 = 0, st0 = 0, st1 = 0;
     if (ci < nc && !(cinfo[ci] & ((1 << 4) | (1 << 5)))) {
       const double a = cand[ci].a, b = cand[ci].b, c = cand[ci].c;
+      if (small) { cabc[3 * ci] = a; cabc[3 * ci + 1] = b; cabc[3 * ci + 2] = c; }
 #pragma unroll
       for (int pass = 0; pass < 2; ++pass) {
         const int L0 = 1 + pass;
@@ -449,7 +546,7 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
         const double xp = xm(a, b, c, P.zd[L0], P);
         const double e1 = xp - yhi * t0, e2 = xp - ylo * t0;
         const double lo = fmin(e1, e2), hi = fmax(e1, e2);
-        const int s = lower_d(X, zoff[L0], zoff[L0 + 1], lo);
+        const int s = zlower<kLds>(X, sh, L0, lo);
         int e = s;
         while (e < zoff[L0 + 1] && (double)X[e] <= hi) ++e;
         if (pass == 0) { st0 = s; cnt0 = e - s; } else { st1 = s; cnt1 = e - s; }
@@ -479,8 +576,11 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
       const int pass = k >= sh.a1[jj];
       const int h0 = pass ? sh.a2[jj] + (k - sh.a1[jj]) : sh.a0[jj] + k;
       const int c = c0 + jj;
+      double a, b, cc;
+      if (small) { a = cabc[3 * c]; b = cabc[3 * c + 1]; cc = cabc[3 * c + 2]; }
+      else { a = cand[c].a; b = cand[c].b; cc = cand[c].c; }
       Combo r;
-      if (!uv_combo(X, Z, zoff, P, cand[c].a, cand[c].b, cand[c].c, 1 + pass, h0, r)) continue;
+      if (!uv_combo<kLds>(X, Z, sh, P, a, b, cc, 1 + pass, h0, r)) continue;
       r.c = c;
       r.tb = (pass << 24) | (h0 - zoff[1 + pass]);
       const unsigned slot = wave_append(&sh.ncombo);
@@ -497,14 +597,16 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   // best combination per track: most hits, then lowest chi2_y, then the
   // earlier (pass, initial hit)
   for (unsigned i = tid; i < ncb; i += kSeedWG) {
-    const Combo &r = combo[i];
-    if (r.n == bestn[r.c]) atomicMin(&bestchi[r.c], (unsigned long long)__double_as_longlong(r.chi2));
+    const int c = combo[i].c;
+    if (combo[i].n == bestn[c])
+      atomicMin(&bestchi[c], (unsigned long long)__double_as_longlong(combo[i].chi2));
   }
   __syncthreads();
   for (unsigned i = tid; i < ncb; i += kSeedWG) {
-    const Combo &r = combo[i];
-    if (r.n == bestn[r.c] && (unsigned long long)__double_as_longlong(r.chi2) == bestchi[r.c])
-      atomicMin(&bestidx[r.c], r.tb);
+    const int c = combo[i].c;
+    if (combo[i].n == bestn[c] &&
+        (unsigned long long)__double_as_longlong(combo[i].chi2) == bestchi[c])
+      atomicMin(&bestidx[c], combo[i].tb);
   }
   __syncthreads();
   for (unsigned i = tid; i < ncb; i += kSeedWG) {
@@ -527,7 +629,6 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
     }
     const unsigned slot = wave_append(&sh.nseed);
     if (slot < (unsigned)S.sst_cap) sst[slot] = st;
-    if (slot < (unsigned)kSeedLds) sh.skey[slot] = st.key;
   }
   __syncthreads();
   unsigned ns = sh.nseed;
@@ -535,6 +636,8 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
     if (tid == 0) { raise_flag(cnt, F_SST); atomicMax(&cnt->need_sst, ns); }
     ns = S.sst_cap;
   }
+  const bool lds_keys = ns <= (unsigned)kSeedLds;
+  for (unsigned i = tid; i < ns && lds_keys; i += kSeedWG) sh.u.skey[i] = sst[i].key;
   if (tid == 0) {
     unsigned long long base = atomicAdd(&cnt->pool_top, (unsigned long long)ns);
     if (base + ns > (unsigned long long)S.pool_cap) raise_flag(cnt, F_POOL);
@@ -546,12 +649,11 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   const unsigned long long base = sh.pbase;
   if (base + ns <= (unsigned long long)S.pool_cap) {
     // canonical order: rank of each seed's (iteration, T1, T3, T2) key
-    const bool lds_keys = ns <= (unsigned)kSeedLds;
     for (unsigned i = tid; i < ns; i += kSeedWG) {
-      const unsigned long long key = lds_keys ? sh.skey[i] : sst[i].key;
+      const unsigned long long key = lds_keys ? sh.u.skey[i] : sst[i].key;
       unsigned r = 0;
       if (lds_keys)
-        for (unsigned j = 0; j < ns; ++j) r += sh.skey[j] < key;
+        for (unsigned j = 0; j < ns; ++j) r += sh.u.skey[j] < key;
       else
         for (unsigned j = 0; j < ns; ++j) r += sst[j].key < key;
       S.pool[base + r] = sst[i].s;
@@ -559,9 +661,11 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   }
 }
 
-__global__ __launch_bounds__(kSeedWG) void k_seed(const Desc *__restrict__ D, Scratch S,
-                                                  DevParams P, int item_begin, int item_count,
-                                                  int use_queue, int lds_hits) {
+__global__ __launch_bounds__(kSeedWG, 4) void k_seed(const Desc *__restrict__ D,
+                                                  const KCtx *__restrict__ K, int item_begin,
+                                                  int item_count, int use_queue, int lds_hits) {
+  const Scratch &S = K->S;
+  const DevParams &P = K->P;
   extern __shared__ float s_dyn[];
   __shared__ SeedShared sh;
   float *s_x = s_dyn;
@@ -590,6 +694,15 @@ __global__ __launch_bounds__(kSeedWG) void k_seed(const Desc *__restrict__ D, Sc
     const int base = zone_off[k0];
     const int nh = zone_off[k0 + kNL] - base;
     if (tid <= kNL) sh.zoff[tid] = zone_off[k0 + tid] - base;
+    if (tid == 0) {
+      int acc = 0;
+      for (int k = 0; k < 6; ++k) {
+        sh.xb[k] = acc;
+        const int L = (k >> 1) * 4 + (k & 1) * 3;
+        acc += zone_off[k0 + L + 1] - zone_off[k0 + L];
+      }
+      sh.xb[6] = acc;
+    }
     if (nh >= kMaxItemHits || nh < 0) {
       if (tid == 0) {
         raise_flag(S.cnt, nh < 0 ? F_INVALID : F_LIMIT);
@@ -600,15 +713,30 @@ __global__ __launch_bounds__(kSeedWG) void k_seed(const Desc *__restrict__ D, Sc
       continue;
     }
     if (nh <= lds_hits) {
+      // stage the item's hits; every bin entry starts at its zone's size
+      for (int i = tid; i < kNL * kBins; i += kSeedWG) {
+        const int L = i / kBins;
+        sh.bins[L][i % kBins] = (unsigned short)(zone_off[k0 + L + 1] - zone_off[k0 + L]);
+      }
       for (int i = tid; i < nh; i += kSeedWG) {
         s_x[i] = hx[base + i];
         s_z[i] = hz[base + i];
       }
       __syncthreads();
-      seed_item(s_x, s_z, hid + base, item, nh, P, S, wg, sh);
+      // hit i opens the bins in (kbin(previous hit), kbin(hit i)]
+      for (int i = tid; i < nh; i += kSeedWG) {
+        int L = 0;
+        while (sh.zoff[L + 1] <= i) ++L;
+        const int li = i - sh.zoff[L];
+        const int kc = kbin(s_x[i]);
+        const int kp = li > 0 ? kbin(s_x[i - 1]) : 0;
+        for (int b = kp; b < kc; ++b) sh.bins[L][b] = (unsigned short)li;
+      }
+      __syncthreads();
+      seed_item<true>(s_x, s_z, hid + base, item, nh, P, S, wg, sh);
     } else {
       __syncthreads();
-      seed_item(hx + base, hz + base, hid + base, item, nh, P, S, wg, sh);
+      seed_item<false>(hx + base, hz + base, hid + base, item, nh, P, S, wg, sh);
     }
     __syncthreads();
   }
@@ -618,7 +746,8 @@ __global__ __launch_bounds__(kSeedWG) void k_seed(const Desc *__restrict__ D, Sc
 
 // Items by descending hit count (16 log2 buckets), so the longest items start
 // first and the persistent grid drains evenly.
-__global__ __launch_bounds__(1024) void k_order(const Desc *__restrict__ D, Scratch S) {
+__global__ __launch_bounds__(1024) void k_order(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
+  const Scratch &S = K->S;
   __shared__ int hist[32], base[32];
   const int n = D->n_items;
   const int32_t *zo = D->b.zone_off;
@@ -643,7 +772,8 @@ __global__ __launch_bounds__(1024) void k_order(const Desc *__restrict__ D, Scra
 
 // ---------------------------------------------------------------- init ----
 
-__global__ void k_init(const Desc *__restrict__ D, Scratch S, int plain) {
+__global__ void k_init(const Desc *__restrict__ D, const KCtx *__restrict__ K, int plain) {
+  const Scratch &S = K->S;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     Counters *c = S.cnt;
     c->seed_queue = 0; c->match_queue = 0; c->flags = 0;
@@ -673,21 +803,24 @@ __device__ __forceinline__ void scan_counts(const int *c0, const int *c1, int st
   }
 }
 
-__global__ __launch_bounds__(1024) void k_seed_off(const Desc *__restrict__ D, Scratch S) {
+__global__ __launch_bounds__(1024) void k_seed_off(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
+  const Scratch &S = K->S;
   __shared__ int s_tmp[16];
   const int n = D->n_events;
   scan_counts(S.item_cnt, S.item_cnt + 1, 2, n, D->seed_off, s_tmp, &S.cnt->total_seeds);
   if (threadIdx.x == 0 && S.cnt->total_seeds > D->seed_cap) raise_flag(S.cnt, F_OUT_SEED);
 }
 
-__global__ __launch_bounds__(1024) void k_long_off(const Desc *__restrict__ D, Scratch S) {
+__global__ __launch_bounds__(1024) void k_long_off(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
+  const Scratch &S = K->S;
   __shared__ int s_tmp[16];
   const int n = D->n_events;
   scan_counts(S.ev_lcnt, nullptr, 1, n, D->long_off, s_tmp, &S.cnt->total_longs);
   if (threadIdx.x == 0 && S.cnt->total_longs > D->long_cap) raise_flag(S.cnt, F_OUT_LONG);
 }
 
-__global__ __launch_bounds__(256) void k_long_copy(const Desc *__restrict__ D, Scratch S) {
+__global__ __launch_bounds__(256) void k_long_copy(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
+  const Scratch &S = K->S;
   const int n = D->n_events;
   if (S.cnt->flags & (F_OUT_LONG | F_LPOOL)) return;
   for (int e = blockIdx.x; e < n; e += gridDim.x) {
@@ -698,7 +831,8 @@ __global__ __launch_bounds__(256) void k_long_copy(const Desc *__restrict__ D, S
 }
 
 // zone offsets non-decreasing from 0, hits x-sorted inside each zone
-__global__ __launch_bounds__(256) void k_validate(const Desc *__restrict__ D, Scratch S) {
+__global__ __launch_bounds__(256) void k_validate(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
+  const Scratch &S = K->S;
   const int nz = D->n_events * 24;
   const int32_t *zo = D->b.zone_off;
   const float *x = D->b.hit_x;
@@ -780,9 +914,11 @@ struct MatchShared {
   unsigned long long lbase;
 };
 
-__global__ __launch_bounds__(kMatchWG) void k_match(const Desc *__restrict__ D, Scratch S,
-                                                    DevParams P, int ev_begin, int ev_count,
-                                                    int plain) {
+__global__ __launch_bounds__(kMatchWG) void k_match(const Desc *__restrict__ D,
+                                                    const KCtx *__restrict__ K, int ev_begin,
+                                                    int ev_count, int plain) {
+  const Scratch &S = K->S;
+  const DevParams &P = K->P;
   __shared__ MatchShared sh;
   const int tid = threadIdx.x;
   const size_t wg = blockIdx.x;
@@ -939,7 +1075,8 @@ __global__ __launch_bounds__(kMatchWG) void k_match(const Desc *__restrict__ D, 
 }
 
 // totals of the plain form (offsets were chained event by event)
-__global__ void k_plain_totals(const Desc *__restrict__ D, Scratch S) {
+__global__ void k_plain_totals(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
+  const Scratch &S = K->S;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const int n = D->n_events;
     S.cnt->total_seeds = D->seed_off[n];
@@ -954,44 +1091,44 @@ __global__ void k_plain_totals(const Desc *__restrict__ D, Scratch S) {
 using namespace smk;
 
 extern "C" {
-int smk_launch_init(const Desc *d, Scratch s, int plain, hipStream_t st) {
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, d, s, plain);
+int smk_launch_init(const Desc *d, const KCtx *k, int plain, hipStream_t st) {
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, d, k, plain);
   return (int)hipGetLastError();
 }
-int smk_launch_order(const Desc *d, Scratch s, hipStream_t st) {
-  hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, st, d, s);
+int smk_launch_order(const Desc *d, const KCtx *k, hipStream_t st) {
+  hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, st, d, k);
   return (int)hipGetLastError();
 }
-int smk_launch_seed(const Desc *d, Scratch s, DevParams p, int item_begin, int item_count,
+int smk_launch_seed(const Desc *d, const KCtx *k, int item_begin, int item_count,
                     int use_queue, int grid, int lds_hits, hipStream_t st) {
   hipLaunchKernelGGL(k_seed, dim3(grid), dim3(kSeedWG), (size_t)lds_hits * 2 * sizeof(float), st,
-                     d, s, p, item_begin, item_count, use_queue, lds_hits);
+                     d, k, item_begin, item_count, use_queue, lds_hits);
   return (int)hipGetLastError();
 }
-int smk_launch_seed_off(const Desc *d, Scratch s, hipStream_t st) {
-  hipLaunchKernelGGL(k_seed_off, dim3(1), dim3(1024), 0, st, d, s);
+int smk_launch_seed_off(const Desc *d, const KCtx *k, hipStream_t st) {
+  hipLaunchKernelGGL(k_seed_off, dim3(1), dim3(1024), 0, st, d, k);
   return (int)hipGetLastError();
 }
-int smk_launch_match(const Desc *d, Scratch s, DevParams p, int ev_begin, int ev_count,
+int smk_launch_match(const Desc *d, const KCtx *k, int ev_begin, int ev_count,
                      int plain, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_match, dim3(grid), dim3(kMatchWG), 0, st, d, s, p, ev_begin, ev_count,
+  hipLaunchKernelGGL(k_match, dim3(grid), dim3(kMatchWG), 0, st, d, k, ev_begin, ev_count,
                      plain);
   return (int)hipGetLastError();
 }
-int smk_launch_long_off(const Desc *d, Scratch s, hipStream_t st) {
-  hipLaunchKernelGGL(k_long_off, dim3(1), dim3(1024), 0, st, d, s);
+int smk_launch_long_off(const Desc *d, const KCtx *k, hipStream_t st) {
+  hipLaunchKernelGGL(k_long_off, dim3(1), dim3(1024), 0, st, d, k);
   return (int)hipGetLastError();
 }
-int smk_launch_long_copy(const Desc *d, Scratch s, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_long_copy, dim3(grid), dim3(256), 0, st, d, s);
+int smk_launch_long_copy(const Desc *d, const KCtx *k, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_long_copy, dim3(grid), dim3(256), 0, st, d, k);
   return (int)hipGetLastError();
 }
-int smk_launch_validate(const Desc *d, Scratch s, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_validate, dim3(grid), dim3(256), 0, st, d, s);
+int smk_launch_validate(const Desc *d, const KCtx *k, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_validate, dim3(grid), dim3(256), 0, st, d, k);
   return (int)hipGetLastError();
 }
-int smk_launch_plain_totals(const Desc *d, Scratch s, hipStream_t st) {
-  hipLaunchKernelGGL(k_plain_totals, dim3(1), dim3(64), 0, st, d, s);
+int smk_launch_plain_totals(const Desc *d, const KCtx *k, hipStream_t st) {
+  hipLaunchKernelGGL(k_plain_totals, dim3(1), dim3(64), 0, st, d, k);
   return (int)hipGetLastError();
 }
 }

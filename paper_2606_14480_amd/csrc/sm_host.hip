@@ -14,7 +14,7 @@
 #include "sm.h"
 #include "sm_device.h"
 
-extern "C" int smk_launch_plain_totals(const smk::Desc *d, smk::Scratch s, hipStream_t st);
+extern "C" int smk_launch_plain_totals(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
 
 namespace {
 
@@ -36,6 +36,7 @@ struct Slot {
   hipStream_t stream = nullptr;
   Desc *d_desc = nullptr;
   Desc *h_desc = nullptr;     // pinned
+  smk::KCtx *d_kctx = nullptr;  // scratch pointers + parameters, device copy
   Counters *h_cnt = nullptr;  // pinned
   Scratch S{};
   Caps caps;
@@ -78,6 +79,7 @@ DevParams make_params(const sm_geometry &g, const sm_params &p) {
     d.zf[l] = (float)g.z[l];
     d.zd[l] = g.z[l];
     d.tand[l] = g.tan_stereo[l];
+    d.inv_tand[l] = g.tan_stereo[l] != 0.0 ? 1.0 / g.tan_stereo[l] : 0.0;
   }
   d.zref = g.z_ref;
   d.d = p.d_ratio;
@@ -198,6 +200,10 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
   S.pool_cap = k.pool; S.lpool_cap = k.lpool;
   S.ms_cap = k.ms; S.vs_cap = k.vs; S.surv_cap = k.surv;
   c->bytes += bytes;
+  smk::KCtx kc;
+  kc.S = S;
+  kc.P = c->dp;
+  if (hipMemcpy(s.d_kctx, &kc, sizeof(kc), hipMemcpyHostToDevice) != hipSuccess) return SM_ERR_DEVICE;
   if (c->cfg.mem_budget > 0 && bytes > c->cfg.mem_budget) return SM_ERR_OOM;
   return SM_OK;
 }
@@ -223,13 +229,13 @@ sm_status fit_batch(sm_ctx *c, Slot &s, const sm_batch &b) {
   if (pool > k.pool) { k.pool = std::max(pool, 2 * k.pool); re = true; }
   const long long lpool = b.n_velo + 1024;
   if (lpool > k.lpool) { k.lpool = std::max(lpool, 2 * k.lpool); re = true; }
-  // LDS hit capacity: the smallest power of two >= 1.5x the mean (event, half)
-  // size, 1024..4096 (items above it read their hits from global memory)
+  // LDS hit capacity: 1.5x the mean (event, half) size rounded up to 256,
+  // 1024..4096 (items above it read their hits from global memory)
   int h = std::min(c->cfg.lds_hits, 4096);
   if (h <= 0) {
     const double mean = b.n_events > 0 ? (double)b.n_hits / (2.0 * b.n_events) : 0.0;
-    h = 1024;
-    while (h < 4096 && h < 1.5 * mean) h *= 2;
+    h = 256 * (int)std::ceil(1.5 * mean / 256.0);
+    h = std::max(1024, std::min(h, 4096));
   }
   if (h != s.lds_hits) {
     s.lds_hits = h;
@@ -272,15 +278,15 @@ void fill_desc(Slot &s, const sm_batch &b, const sm_out &o) {
 }
 
 sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
-  const Scratch S = s.S;
+  const smk::KCtx *S = s.d_kctx;
   const Desc *d = s.d_desc;
   auto seq = [&](hipStream_t q) -> hipError_t {
     int e = smk_launch_init(d, S, 0, q);
     if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
     if (!e) e = smk_launch_order(d, S, q);
-    if (!e) e = smk_launch_seed(d, S, c->dp, 0, -1, 1, c->seed_wgs, s.lds_hits, q);
+    if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, q);
     if (!e) e = smk_launch_seed_off(d, S, q);
-    if (!e) e = smk_launch_match(d, S, c->dp, 0, -1, 0, c->match_wgs, q);
+    if (!e) e = smk_launch_match(d, S, 0, -1, 0, c->match_wgs, q);
     if (!e) e = smk_launch_long_off(d, S, q);
     if (!e) e = smk_launch_long_copy(d, S, 1024, q);
     return (hipError_t)e;
@@ -303,13 +309,13 @@ sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
 }
 
 sm_status enqueue_plain(sm_ctx *c, Slot &s, int n_events, hipStream_t st) {
-  const Scratch S = s.S;
+  const smk::KCtx *S = s.d_kctx;
   const Desc *d = s.d_desc;
   int e = smk_launch_init(d, S, 1, st);
   if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, st);
   for (int ev = 0; ev < n_events && !e; ++ev) {
-    e = smk_launch_seed(d, S, c->dp, 2 * ev, 2, 0, 2, s.lds_hits, st);
-    if (!e) e = smk_launch_match(d, S, c->dp, ev, 1, 1, 1, st);
+    e = smk_launch_seed(d, S, 2 * ev, 2, 0, 2, s.lds_hits, st);
+    if (!e) e = smk_launch_match(d, S, ev, 1, 1, 1, st);
   }
   if (!e) e = smk_launch_plain_totals(d, S, st);
   return hip_status((hipError_t)e);
@@ -317,7 +323,7 @@ sm_status enqueue_plain(sm_ctx *c, Slot &s, int n_events, hipStream_t st) {
 
 // The batched sequence as plain launches with an event after every kernel.
 sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
-  const Scratch S = s.S;
+  const smk::KCtx *S = s.d_kctx;
   const Desc *d = s.d_desc;
   int e = hipEventRecord(ev[0], q);
   if (!e) e = smk_launch_init(d, S, 0, q);
@@ -325,11 +331,11 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   if (!e) e = hipEventRecord(ev[1], q);
   if (!e) e = smk_launch_order(d, S, q);
   if (!e) e = hipEventRecord(ev[2], q);
-  if (!e) e = smk_launch_seed(d, S, c->dp, 0, -1, 1, c->seed_wgs, s.lds_hits, q);
+  if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, q);
   if (!e) e = hipEventRecord(ev[3], q);
   if (!e) e = smk_launch_seed_off(d, S, q);
   if (!e) e = hipEventRecord(ev[4], q);
-  if (!e) e = smk_launch_match(d, S, c->dp, 0, -1, 0, c->match_wgs, q);
+  if (!e) e = smk_launch_match(d, S, 0, -1, 0, c->match_wgs, q);
   if (!e) e = hipEventRecord(ev[5], q);
   if (!e) e = smk_launch_long_off(d, S, q);
   if (!e) e = hipEventRecord(ev[6], q);
@@ -497,6 +503,7 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
     if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
         hipMalloc(&s.d_desc, sizeof(Desc)) != hipSuccess ||
+        hipMalloc(&s.d_kctx, sizeof(smk::KCtx)) != hipSuccess ||
         hipHostMalloc(&s.h_desc, sizeof(Desc), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&s.h_cnt, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
       hipGetLastError();
@@ -609,6 +616,7 @@ sm_status sm_destroy(sm_ctx *ctx) {
     if (s.done) hipEventDestroy(s.done);
     if (s.stream) hipStreamDestroy(s.stream);
     if (s.d_desc) hipFree(s.d_desc);
+    if (s.d_kctx) hipFree(s.d_kctx);
     if (s.h_desc) hipHostFree(s.h_desc);
     if (s.h_cnt) hipHostFree(s.h_cnt);
   }
