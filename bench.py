@@ -31,11 +31,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def seed_kernel_bytes(b, n_seeds: int) -> int:
-    """Algorithmic HBM bytes of one seeding launch: hit x and z (8 B/hit), the
-    zone offsets, per item one count and one pool offset, and per seed its
-    96 B record plus the 12 hit ids it reports."""
-    return 8 * b.n_hits + 4 * (24 * b.n_events + 1) + 2 * 4 * 2 * b.n_events + n_seeds * (96 + 48)
+def seed_kernel_bytes(b, n_seeds: int, n_longs: int) -> int:
+    """Algorithmic HBM bytes of one launch of the fused Seeding + Matching
+    kernel: hit x and z (8 B/hit), the zone and VELO offsets, the VELO states
+    (24 B each), per item one count and one pool offset, per seed its 96 B
+    record plus the 12 hit ids it reports, and per long track its 40 B record."""
+    return (8 * b.n_hits + 4 * (24 * b.n_events + 1) + 4 * (b.n_events + 1) + 24 * b.n_velo
+            + 2 * 4 * 2 * b.n_events + n_seeds * (96 + 48) + 40 * n_longs)
 
 
 def cpu_baseline(batch, seconds: float):
@@ -61,6 +63,49 @@ def cpu_baseline(batch, seconds: float):
                       f"{n1 / d1:.1f} events/s"}
 
 
+def serve_stream(ctx, sm, host, capacity, n_req, load):
+    """Requests of 1..N events (N = the batch size) drawn from the benchmark
+    batch, Poisson arrivals at `load` x the batched capacity in events/s,
+    continuous batching over the library's serving slots; then the same
+    stream one request at a time through the plain form."""
+    import numpy as np
+    from paper_2606_14480_amd import serving
+    rng = np.random.default_rng(11)
+    sizes = rng.integers(1, host.n_events + 1, n_req)
+    starts = [int(rng.integers(0, host.n_events - k + 1)) for k in sizes]
+    mean_ev = float(np.mean(sizes))
+    rate = load * capacity / mean_ev
+    arr = serving.poisson_arrivals(rate, n_req, seed=12)
+    reqs = []
+    for i, (s, k) in enumerate(zip(starts, sizes)):
+        sub = host.subset(range(s, s + int(k)))
+        reqs.append(serving.Request(i, sub, float(arr[i]), serving.pin(sub)))
+    me = max(r.batch.n_events for r in reqs)
+    mh = max(r.batch.n_hits for r in reqs)
+    mv = max(r.batch.n_velo for r in reqs)
+    srv = serving.Server(ctx, 2, me, mh, mv)
+    srv.serve(reqs[:3])                                     # warm the slots
+    t0 = time.perf_counter()
+    res = srv.serve(reqs)
+    wall = time.perf_counter() - t0
+    s = serving.summarize(res, wall)
+    out = {"requests": n_req, "events_per_request": "uniform 1-%d" % host.n_events,
+           "offered_events_per_s": round(rate * mean_ev, 1),
+           "events_per_s": round(s["events_per_s"], 1),
+           "latency_ms_p50": round(s["latency_ms_p50"], 3),
+           "latency_ms_p99": round(s["latency_ms_p99"], 3),
+           "what": "arrival to results on the host, incl. H2D of the request and D2H of results"}
+    n_plain = min(n_req, 12)
+    t0 = time.perf_counter()
+    pres = serving.serve_plain(ctx, reqs[:n_plain], me, mh, mv)
+    wall_p = time.perf_counter() - t0
+    p = serving.summarize(pres, wall_p)
+    out["plain_stream"] = {"requests": n_plain, "events_per_s": round(p["events_per_s"], 1),
+                           "latency_ms_p50": round(p["latency_ms_p50"], 3),
+                           "latency_ms_p99": round(p["latency_ms_p99"], 3)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +116,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=2.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=60,
+                    help="requests in the served-stream measurement (0: skip)")
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="offered load as a fraction of the measured batched capacity")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run one plain copy of this many MiB (rocprof counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -136,17 +187,31 @@ def main():
     log(f"[bench] kernel ms: {json.dumps({k: round(v, 4) for k, v in kern.items()})}")
 
     # ---- plain form: one kernel sequence per event
-    ctx.run(db, out, stream, plain=True)
-    torch.cuda.synchronize()
-    tp = time.perf_counter()
-    for _ in range(args.plain_steps):
+    plain = None
+    if args.plain_steps > 0:
         ctx.run(db, out, stream, plain=True)
-    torch.cuda.synchronize()
-    plain = args.plain_steps * host.n_events / (time.perf_counter() - tp)
-    log(f"[bench] plain: {plain:.0f} events/s")
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for _ in range(args.plain_steps):
+            ctx.run(db, out, stream, plain=True)
+        torch.cuda.synchronize()
+        plain = args.plain_steps * host.n_events / (time.perf_counter() - tp)
+        log(f"[bench] plain: {plain:.0f} events/s")
 
-    alg_bytes = seed_kernel_bytes(host, n_seeds)
-    achieved = alg_bytes / (kern["seed"] * 1e-3) / 1e9
+    serve = None
+    if args.serve_requests > 0:
+        serve = serve_stream(ctx, sm, host, value, args.serve_requests, args.serve_load)
+        log(f"[bench] served: {serve}")
+    if args.calib_copy_mb > 0:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {n * 4} bytes read, {n * 4} bytes written")
+
+    alg_bytes = seed_kernel_bytes(host, n_seeds, n_longs)
+    achieved = alg_bytes / (kern["seed_match"] * 1e-3) / 1e9
     res = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -167,15 +232,16 @@ def main():
                    "velo_states": host.n_velo, "seeds": n_seeds, "long_tracks": n_longs,
                    "form": "batched: captured graph, persistent kernels, LPT work queue",
                    "search_dtype": "f32", "fit_dtype": "f64"},
-        "plain_events_per_s": round(plain, 1),
-        "batched_over_plain": round(value / plain, 2),
+        "plain_events_per_s": round(plain, 1) if plain else None,
+        "batched_over_plain": round(value / plain, 2) if plain else None,
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                        "p99": round(float(np.percentile(lat_ms, 99)), 4),
                        "what": "per-batch latency of the batched form, call to results"},
         "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
+        "served": serve,
         "gpu_events_per_s": round(host.n_events / (kern["total"] * 1e-3), 1),
         "parity": parity,
-        "roofline": {"bound": "hbm", "kernel": "k_seed", "achieved": round(achieved, 2),
+        "roofline": {"bound": "hbm", "kernel": "k_seed (seeding + matching)", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": None, "alg_bytes_per_launch": alg_bytes},

@@ -1,16 +1,15 @@
 // Device side of the Seeding + Matching library (gfx950, wave64).
 //
 // Kernels, in launch order for one batch:
-//   k_init     clear queue heads, pool tops and status words (a fill kernel,
-//              so the sequence can live in a captured graph)
-//   k_order    order the (event, half) items by hit count, largest first
+//   k_prepare  clear counters and per-event hand-off counts (a fill kernel, so
+//              the sequence can live in a captured graph) and order the
+//              (event, half) items by hit count, largest first
 //   k_seed     persistent: each workgroup pulls items from the queue and runs
 //              XZ seeding (both iterations), the clone vote and UV seeding of
-//              one detector half of one event, hits staged in LDS
-//   k_seed_off per-event seed offsets (exclusive scan)
-//   k_match    persistent over events: copy the event's seeds to the output in
-//              canonical order and match them with the VELO states
-//   k_long_off per-event long-track offsets, then k_long_copy
+//              one detector half of one event, hits staged in LDS; the
+//              workgroup that completes an event's second half matches it
+//   k_offsets  per-event seed and long-track offsets (exclusive scans)
+//   k_copy     seeds and long tracks from the pools to the caller's CSR
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -21,7 +20,6 @@ namespace smk {
 
 constexpr int kNL = 12;
 constexpr int kSeedWG = 256;        // threads of the seeding workgroup (4 waves)
-constexpr int kMatchWG = 256;
 constexpr int kCandLds = 256;       // x-z candidates whose vote records live in LDS
 constexpr int kXtabLds = 1024;      // x hits of an item with an LDS clone-vote entry
 constexpr int kSeedLds = 256;       // seeds per item ranked from LDS keys
@@ -137,15 +135,15 @@ struct Scratch {
   int *cinfo, *bestn, *bestidx;          // [seed_wgs][cand_cap]
   int trip_cap, cand_cap, tbl_cap, sst_cap, combo_cap, pad2;
   int *item_order, *item_cnt, *item_base;  // [items_cap]
-  int *ev_lcnt, *ev_lbase;                 // [events_cap]
+  int *ev_lcnt, *ev_lbase, *ev_done;       // [events_cap]
   sm_seed *pool;
   sm_long *lpool;
   long long pool_cap, lpool_cap;
-  MState *ms;                 // [match_wgs][ms_cap]
-  float *mf;                  // [match_wgs][6 * ms_cap], events with many seeds
-  unsigned long long *best_s; // [match_wgs][ms_cap]
-  unsigned long long *best_v; // [match_wgs][vs_cap]
-  Surv *surv;                 // [match_wgs][surv_cap]
+  MState *ms;                 // [seed_wgs][ms_cap]
+  float *mf;                  // [seed_wgs][6 * ms_cap], events with many seeds
+  unsigned long long *best_s; // [seed_wgs][ms_cap]
+  unsigned long long *best_v; // [seed_wgs][vs_cap]
+  Surv *surv;                 // [seed_wgs][2 * surv_cap]
   int ms_cap, vs_cap, surv_cap, pad;
   Counters *cnt;
 };
@@ -159,16 +157,16 @@ struct KCtx {
 
 }  // namespace smk
 
+// Dynamic LDS bytes of k_seed for a given LDS hit capacity.
+size_t smk_seed_lds_bytes(int lds_hits);
+
 extern "C" {
 // Launchers (sm_device.hip); each returns the hipError_t of its launch.
-int smk_launch_init(const smk::Desc *d, const smk::KCtx *k, int plain, hipStream_t st);
-int smk_launch_order(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
-int smk_launch_seed(const smk::Desc *d, const smk::KCtx *k, int item_begin,
-                    int item_count, int use_queue, int grid, int lds_hits, hipStream_t st);
-int smk_launch_seed_off(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
-int smk_launch_match(const smk::Desc *d, const smk::KCtx *k, int ev_begin,
-                     int ev_count, int plain, int grid, hipStream_t st);
-int smk_launch_long_off(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
-int smk_launch_long_copy(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
+int smk_launch_prepare(const smk::Desc *d, const smk::KCtx *k, int plain, hipStream_t st);
+int smk_launch_seed(const smk::Desc *d, const smk::KCtx *k, int item_begin, int item_count,
+                    int use_queue, int grid, int lds_hits, int plain, hipStream_t st);
+int smk_launch_offsets(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
+int smk_launch_copy(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 int smk_launch_validate(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
+int smk_launch_plain_totals(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
 }

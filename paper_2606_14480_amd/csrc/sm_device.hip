@@ -661,197 +661,6 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   }
 }
 
-__global__ __launch_bounds__(kSeedWG, 4) void k_seed(const Desc *__restrict__ D,
-                                                  const KCtx *__restrict__ K, int item_begin,
-                                                  int item_count, int use_queue, int lds_hits) {
-  const Scratch &S = K->S;
-  const DevParams &P = K->P;
-  extern __shared__ float s_dyn[];
-  __shared__ SeedShared sh;
-  float *s_x = s_dyn;
-  float *s_z = s_dyn + lds_hits;
-
-  const int tid = threadIdx.x;
-  const size_t wg = blockIdx.x;
-  const int32_t *zone_off = D->b.zone_off;
-  const float *hx = D->b.hit_x, *hz = D->b.hit_z;
-  const int32_t *hid = D->b.hit_id;
-  const int n_items = item_count < 0 ? D->n_items : item_count;
-  bool first = true;
-  for (;;) {
-    if (tid == 0) {
-      int q;
-      if (use_queue) q = (int)atomicAdd(&S.cnt->seed_queue, 1u);
-      else q = first ? (int)blockIdx.x : n_items;
-      sh.item = q < n_items ? (use_queue ? S.item_order[q] : item_begin + q) : -1;
-      sh.ntrip = 0; sh.ncand = 0; sh.nseed = 0; sh.ncombo = 0;
-    }
-    first = false;
-    __syncthreads();
-    const int item = sh.item;
-    if (item < 0) break;
-    const int k0 = item * kNL;
-    const int base = zone_off[k0];
-    const int nh = zone_off[k0 + kNL] - base;
-    if (tid <= kNL) sh.zoff[tid] = zone_off[k0 + tid] - base;
-    if (tid == 0) {
-      int acc = 0;
-      for (int k = 0; k < 6; ++k) {
-        sh.xb[k] = acc;
-        const int L = (k >> 1) * 4 + (k & 1) * 3;
-        acc += zone_off[k0 + L + 1] - zone_off[k0 + L];
-      }
-      sh.xb[6] = acc;
-    }
-    if (nh >= kMaxItemHits || nh < 0) {
-      if (tid == 0) {
-        raise_flag(S.cnt, nh < 0 ? F_INVALID : F_LIMIT);
-        S.item_cnt[item] = 0;
-        S.item_base[item] = 0;
-      }
-      __syncthreads();
-      continue;
-    }
-    if (nh <= lds_hits) {
-      // stage the item's hits; every bin entry starts at its zone's size
-      for (int i = tid; i < kNL * kBins; i += kSeedWG) {
-        const int L = i / kBins;
-        sh.bins[L][i % kBins] = (unsigned short)(zone_off[k0 + L + 1] - zone_off[k0 + L]);
-      }
-      for (int i = tid; i < nh; i += kSeedWG) {
-        s_x[i] = hx[base + i];
-        s_z[i] = hz[base + i];
-      }
-      __syncthreads();
-      // hit i opens the bins in (kbin(previous hit), kbin(hit i)]
-      for (int i = tid; i < nh; i += kSeedWG) {
-        int L = 0;
-        while (sh.zoff[L + 1] <= i) ++L;
-        const int li = i - sh.zoff[L];
-        const int kc = kbin(s_x[i]);
-        const int kp = li > 0 ? kbin(s_x[i - 1]) : 0;
-        for (int b = kp; b < kc; ++b) sh.bins[L][b] = (unsigned short)li;
-      }
-      __syncthreads();
-      seed_item<true>(s_x, s_z, hid + base, item, nh, P, S, wg, sh);
-    } else {
-      __syncthreads();
-      seed_item<false>(hx + base, hz + base, hid + base, item, nh, P, S, wg, sh);
-    }
-    __syncthreads();
-  }
-}
-
-// ------------------------------------------------------------ ordering ----
-
-// Items by descending hit count (16 log2 buckets), so the longest items start
-// first and the persistent grid drains evenly.
-__global__ __launch_bounds__(1024) void k_order(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
-  const Scratch &S = K->S;
-  __shared__ int hist[32], base[32];
-  const int n = D->n_items;
-  const int32_t *zo = D->b.zone_off;
-  if (threadIdx.x < 32) hist[threadIdx.x] = 0;
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int sz = max(zo[(i + 1) * kNL] - zo[i * kNL], 0);
-    atomicAdd(&hist[31 - __clz(sz + 1)], 1);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int b = 31; b >= 0; --b) { base[b] = acc; acc += hist[b]; }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int sz = max(zo[(i + 1) * kNL] - zo[i * kNL], 0);
-    const int p = atomicAdd(&base[31 - __clz(sz + 1)], 1);
-    S.item_order[p] = i;
-  }
-}
-
-// ---------------------------------------------------------------- init ----
-
-__global__ void k_init(const Desc *__restrict__ D, const KCtx *__restrict__ K, int plain) {
-  const Scratch &S = K->S;
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    Counters *c = S.cnt;
-    c->seed_queue = 0; c->match_queue = 0; c->flags = 0;
-    c->pool_top = 0; c->lpool_top = 0;
-    c->need_trip = c->need_cand = c->need_tbl = c->need_sst = 0;
-    c->need_ms = c->need_vs = c->need_surv = c->need_combo = 0;
-    c->total_seeds = 0; c->total_longs = 0;
-    if (plain) { D->seed_off[0] = 0; D->long_off[0] = 0; }
-  }
-}
-
-// exclusive scan of per-event counts into off[0..n] (one workgroup)
-__device__ __forceinline__ void scan_counts(const int *c0, const int *c1, int stride, int n,
-                                            int32_t *off, int *s_tmp, long long *total) {
-  int carry = 0;
-  for (int b0 = 0; b0 < n; b0 += 1024) {
-    const int e = b0 + (int)threadIdx.x;
-    const int v = e < n ? (c1 ? c0[e * stride] + c1[e * stride] : c0[e * stride]) : 0;
-    int tot;
-    const int ex = block_excl_scan<1024>(v, s_tmp, tot);
-    if (e < n) off[e] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) {
-    off[n] = carry;
-    *total = carry;
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_seed_off(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
-  const Scratch &S = K->S;
-  __shared__ int s_tmp[16];
-  const int n = D->n_events;
-  scan_counts(S.item_cnt, S.item_cnt + 1, 2, n, D->seed_off, s_tmp, &S.cnt->total_seeds);
-  if (threadIdx.x == 0 && S.cnt->total_seeds > D->seed_cap) raise_flag(S.cnt, F_OUT_SEED);
-}
-
-__global__ __launch_bounds__(1024) void k_long_off(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
-  const Scratch &S = K->S;
-  __shared__ int s_tmp[16];
-  const int n = D->n_events;
-  scan_counts(S.ev_lcnt, nullptr, 1, n, D->long_off, s_tmp, &S.cnt->total_longs);
-  if (threadIdx.x == 0 && S.cnt->total_longs > D->long_cap) raise_flag(S.cnt, F_OUT_LONG);
-}
-
-__global__ __launch_bounds__(256) void k_long_copy(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
-  const Scratch &S = K->S;
-  const int n = D->n_events;
-  if (S.cnt->flags & (F_OUT_LONG | F_LPOOL)) return;
-  for (int e = blockIdx.x; e < n; e += gridDim.x) {
-    const int m = S.ev_lcnt[e];
-    const long long src = S.ev_lbase[e], dst = D->long_off[e];
-    for (int i = threadIdx.x; i < m; i += blockDim.x) D->longs[dst + i] = S.lpool[src + i];
-  }
-}
-
-// zone offsets non-decreasing from 0, hits x-sorted inside each zone
-__global__ __launch_bounds__(256) void k_validate(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
-  const Scratch &S = K->S;
-  const int nz = D->n_events * 24;
-  const int32_t *zo = D->b.zone_off;
-  const float *x = D->b.hit_x;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nz; k += gridDim.x * blockDim.x) {
-    if ((k == 0 && zo[0] != 0) || zo[k + 1] < zo[k]) {
-      raise_flag(S.cnt, F_INVALID);
-      continue;
-    }
-    for (int i = zo[k] + 1; i < zo[k + 1]; ++i)
-      if (!(x[i] >= x[i - 1])) { raise_flag(S.cnt, F_UNSORTED); break; }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const int32_t *vo = D->b.velo_off;
-    for (int e = 0; e < D->n_events; ++e)
-      if (vo[e + 1] < vo[e]) { raise_flag(S.cnt, F_INVALID); break; }
-    if (D->n_events > 0 && vo[0] != 0) raise_flag(S.cnt, F_INVALID);
-  }
-}
-
 // ------------------------------------------------------------ Matching ----
 
 struct PairEval {
@@ -914,163 +723,363 @@ struct MatchShared {
   unsigned long long lbase;
 };
 
-__global__ __launch_bounds__(kMatchWG) void k_match(const Desc *__restrict__ D,
-                                                    const KCtx *__restrict__ K, int ev_begin,
-                                                    int ev_count, int plain) {
+// zone offsets non-decreasing from 0, hits x-sorted inside each zone
+__global__ __launch_bounds__(256) void k_validate(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
   const Scratch &S = K->S;
-  const DevParams &P = K->P;
-  __shared__ MatchShared sh;
+  const int nz = D->n_events * 24;
+  const int32_t *zo = D->b.zone_off;
+  const float *x = D->b.hit_x;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nz; k += gridDim.x * blockDim.x) {
+    if ((k == 0 && zo[0] != 0) || zo[k + 1] < zo[k]) {
+      raise_flag(S.cnt, F_INVALID);
+      continue;
+    }
+    for (int i = zo[k] + 1; i < zo[k + 1]; ++i)
+      if (!(x[i] >= x[i - 1])) { raise_flag(S.cnt, F_UNSORTED); break; }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int32_t *vo = D->b.velo_off;
+    for (int e = 0; e < D->n_events; ++e)
+      if (vo[e + 1] < vo[e]) { raise_flag(S.cnt, F_INVALID); break; }
+    if (D->n_events > 0 && vo[0] != 0) raise_flag(S.cnt, F_INVALID);
+  }
+}
+
+// Matching of one event (Sec. 4), run by the workgroup that completes the
+// second half of the event.  plain: outputs go straight to the caller's
+// buffers at offsets chained from the previous event; batched: long tracks go
+// to the pool and the seeds stay in theirs until the offsets are known.
+__device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Scratch &S,
+                                            const DevParams &P, int e, int plain, size_t wg,
+                                            MatchShared &sh) {
   const int tid = threadIdx.x;
-  const size_t wg = blockIdx.x;
   MState *ms = S.ms + wg * (size_t)S.ms_cap;
   float *mf = S.mf + wg * (size_t)S.ms_cap * 6;
   Counters *cnt = S.cnt;
-  const int n_ev = ev_count < 0 ? D->n_events : ev_count;
+  if (tid == 0) {
+    sh.nsurv = 0;
+    sh.nkeep = 0;
+  }
+  const int n0 = S.item_cnt[2 * e], n1 = S.item_cnt[2 * e + 1];
+  const int b0 = S.item_base[2 * e], b1 = S.item_base[2 * e + 1];
+  const int ns = n0 + n1;
+  const int v0 = D->b.velo_off[e], nv = D->b.velo_off[e + 1] - v0;
+  const bool pool_ok = !(cnt->flags & F_POOL);
+  const int so = plain ? D->seed_off[e] : 0;
+  if (tid == 0 && plain) D->seed_off[e + 1] = so + ns;
+  const bool fits = ns <= S.ms_cap && nv <= S.vs_cap && pool_ok;
+  if (tid == 0 && !fits && pool_ok) {
+    if (ns > S.ms_cap) { raise_flag(cnt, F_MS); atomicMax(&cnt->need_ms, (unsigned)ns); }
+    if (nv > S.vs_cap) { raise_flag(cnt, F_VS); atomicMax(&cnt->need_vs, (unsigned)nv); }
+  }
+  // per-seed arrays in LDS, or in this workgroup's global scratch for events
+  // with many seeds / VELO states
+  const bool sm_s = ns <= kMsLds, sm_v = nv <= kVsLds;
+  float *xsf = sm_s ? sh.xsf : mf, *txsf = sm_s ? sh.txsf : mf + S.ms_cap;
+  float *ymf = sm_s ? sh.ymf : mf + 2 * (size_t)S.ms_cap;
+  float *tyf = sm_s ? sh.tyf : mf + 3 * (size_t)S.ms_cap;
+  float *sty = sm_s ? sh.sty : mf + 4 * (size_t)S.ms_cap;
+  int *sidx = sm_s ? sh.sidx : (int *)(mf + 5 * (size_t)S.ms_cap);
+  unsigned long long *best_s = sm_s ? sh.best_s : S.best_s + wg * (size_t)S.ms_cap;
+  unsigned long long *best_v = sm_v ? sh.best_v : S.best_v + wg * (size_t)S.vs_cap;
+  // the event's seeds in canonical order (half 0 then half 1)
+  for (int i = tid; i < ns && pool_ok; i += kSeedWG) {
+    const sm_seed sd = i < n0 ? S.pool[b0 + i] : S.pool[b1 + i - n0];
+    if (plain && (long long)so + i < D->seed_cap) D->seeds[so + i] = sd;
+    if (fits) {
+      const MState m = seed_state(sd, P);
+      ms[i] = m;
+      xsf[i] = m.xsf; txsf[i] = m.txsf; ymf[i] = m.y_mf; tyf[i] = m.tyf;
+      best_s[i] = ~0ull;
+    }
+  }
+  __syncthreads();
+  // seeds sorted by t_y, so each VELO state visits only its |dty| window
+  if (fits) {
+    for (int i = tid; i < ns; i += kSeedWG) {
+      const float t = tyf[i];
+      int r = 0;
+      for (int j = 0; j < ns; ++j) {
+        const float u = tyf[j];
+        r += (u < t) || (u == t && j < i);
+      }
+      sty[r] = t;
+      sidx[r] = i;
+    }
+  }
+  __syncthreads();
+  Surv *surv = S.surv + wg * (size_t)(2 * S.surv_cap);
+  if (fits && ns > 0) {
+    for (int v = tid; v < nv; v += kSeedWG) {
+      const float xvf = D->b.velo_x[v0 + v], yvf = D->b.velo_y[v0 + v], zvf = D->b.velo_z[v0 + v];
+      const float txvf = D->b.velo_tx[v0 + v], tyvf = D->b.velo_ty[v0 + v];
+      const float yvm = yvf + tyvf * (P.z_ymatchf - zvf);
+      const float zmv = P.zmf[0] + P.zmf[4] * txvf * txvf;
+      unsigned long long bv = ~0ull;
+      const float thi = tyvf + P.pre_dty;
+      for (int k = lower_f(sty, 0, ns, tyvf - P.pre_dty); k < ns && sty[k] <= thi; ++k) {
+        const int s = sidx[k];
+        const float dtx = txsf[s] - txvf;
+        if (!(fabsf(dtx) < P.pre_dtx)) continue;
+        if (!(fabsf(ymf[s] - yvm) < P.pre_dy)) continue;
+        const float zm = zmv + P.zmf[1] * fabsf(dtx) + P.zmf[2] * dtx * dtx + P.zmf[3] * fabsf(xsf[s]);
+        const float dx = (xsf[s] + (zm - P.z_statef) * txsf[s]) - (xvf + (zm - zvf) * txvf);
+        if (!(fabsf(dx) < P.pre_dx)) continue;
+        const PairEval r = eval_pair(ms[s], xvf, yvf, zvf, txvf, tyvf, P);
+        if (!r.ok) continue;
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(r.chi2);
+        bv = bits < bv ? bits : bv;
+        atomicMin(&best_s[s], bits);
+        const unsigned slot = atomicAdd(&sh.nsurv, 1u);
+        if (slot < (unsigned)kSurvLds) sh.surv[slot] = Surv{v, s, r.chi2};
+        else if (slot < (unsigned)(kSurvLds + S.surv_cap)) surv[slot - kSurvLds] = Surv{v, s, r.chi2};
+      }
+      best_v[v] = bv;
+    }
+  }
+  __syncthreads();
+  unsigned nsv = sh.nsurv;
+  if (nsv > (unsigned)(kSurvLds + S.surv_cap)) {
+    if (tid == 0) { raise_flag(cnt, F_SURV); atomicMax(&cnt->need_surv, nsv - kSurvLds); }
+    nsv = kSurvLds + S.surv_cap;
+  }
+  // final selection: a pair survives if its chi2 is the best of its seed and
+  // of its VELO track
+  unsigned long long *kkey =
+      nsv <= (unsigned)kSurvLds ? sh.kkey : (unsigned long long *)(surv + S.surv_cap);
+  for (unsigned i = tid; i < nsv; i += kSeedWG) {
+    const Surv sv = i < (unsigned)kSurvLds ? sh.surv[i] : surv[i - kSurvLds];
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(sv.chi2);
+    if (best_v[sv.v] == bits && best_s[sv.s] == bits) {
+      const unsigned slot = atomicAdd(&sh.nkeep, 1u);
+      kkey[slot] = ((unsigned long long)sv.v << 32) | (unsigned)sv.s;
+    }
+  }
+  __syncthreads();
+  const unsigned nk = sh.nkeep;
+  if (tid == 0) {
+    if (plain) {
+      const long long lo = D->long_off[e];
+      sh.lbase = (unsigned long long)lo;
+      D->long_off[e + 1] = (int)(lo + nk);
+    } else {
+      const unsigned long long b = atomicAdd(&cnt->lpool_top, (unsigned long long)nk);
+      if (b + nk > (unsigned long long)S.lpool_cap) raise_flag(cnt, F_LPOOL);
+      sh.lbase = b;
+      S.ev_lcnt[e] = (int)nk;
+      S.ev_lbase[e] = (int)(b < (unsigned long long)S.lpool_cap ? b : 0);
+    }
+  }
+  __syncthreads();
+  const unsigned long long lb = sh.lbase;
+  const long long cap = plain ? D->long_cap : S.lpool_cap;
+  sm_long *dst = plain ? D->longs : S.lpool;
+  for (unsigned i = tid; i < nk; i += kSeedWG) {
+    const unsigned long long key = kkey[i];
+    unsigned r = 0;
+    for (unsigned j = 0; j < nk; ++j) r += kkey[j] < key;
+    if ((long long)(lb + r) >= cap) continue;
+    const int vi = (int)(key >> 32), si = (int)(key & 0xffffffffu);
+    const int v = v0 + vi;
+    const PairEval pe = eval_pair(ms[si], D->b.velo_x[v], D->b.velo_y[v], D->b.velo_z[v],
+                                  D->b.velo_tx[v], D->b.velo_ty[v], P);
+    sm_long L;
+    L.velo_idx = vi; L.seed_idx = si; L.velo_id = D->b.velo_id[v];
+    L.qop = (float)pe.qop; L.chi2 = (float)pe.chi2; L.z_match = (float)pe.zm;
+    L.dx = (float)pe.dx; L.dy = (float)pe.dy; L.dtx = (float)pe.dtx; L.dty = (float)pe.dty;
+    dst[lb + r] = L;
+  }
+  if (plain && tid == 0 && (long long)(lb + nk) > D->long_cap) raise_flag(cnt, F_OUT_LONG);
+}
+
+// ----------------------------------------------------- the fused kernel ----
+
+// Persistent Seeding + Matching: each workgroup pulls (event, half) items from
+// the queue (or takes item_begin + blockIdx in the plain form) and seeds
+// them; the workgroup that completes the second half of an event then matches
+// that event.  The seeding state and the matching state share the same LDS.
+__global__ __launch_bounds__(kSeedWG, 4) void k_seed(const Desc *__restrict__ D,
+                                                     const KCtx *__restrict__ K, int item_begin,
+                                                     int item_count, int use_queue, int lds_hits,
+                                                     int plain) {
+  const Scratch &S = K->S;
+  const DevParams &P = K->P;
+  extern __shared__ __align__(16) unsigned char smem[];
+  SeedShared &sh = *reinterpret_cast<SeedShared *>(smem);
+  MatchShared &mh = *reinterpret_cast<MatchShared *>(smem);
+  float *s_x = reinterpret_cast<float *>(smem + sizeof(SeedShared));
+  float *s_z = s_x + lds_hits;
+  __shared__ int s_last;
+
+  const int tid = threadIdx.x;
+  const size_t wg = blockIdx.x;
+  const int32_t *zone_off = D->b.zone_off;
+  const float *hx = D->b.hit_x, *hz = D->b.hit_z;
+  const int32_t *hid = D->b.hit_id;
+  const int n_items = item_count < 0 ? D->n_items : item_count;
   bool first = true;
   for (;;) {
     if (tid == 0) {
       int q;
-      if (plain) q = first ? 0 : n_ev;
-      else q = (int)atomicAdd(&cnt->match_queue, 1u);
-      sh.ev = q < n_ev ? ev_begin + q : -1;
-      sh.nsurv = 0;
-      sh.nkeep = 0;
+      if (use_queue) q = (int)atomicAdd(&S.cnt->seed_queue, 1u);
+      else q = first ? (int)blockIdx.x : n_items;
+      sh.item = q < n_items ? (use_queue ? S.item_order[q] : item_begin + q) : -1;
+      sh.ntrip = 0; sh.ncand = 0; sh.nseed = 0; sh.ncombo = 0;
     }
     first = false;
     __syncthreads();
-    const int e = sh.ev;
-    if (e < 0) break;
-    const int n0 = S.item_cnt[2 * e], n1 = S.item_cnt[2 * e + 1];
-    const int b0 = S.item_base[2 * e], b1 = S.item_base[2 * e + 1];
-    const int ns = n0 + n1;
-    const int so = D->seed_off[e];
-    const int v0 = D->b.velo_off[e], nv = D->b.velo_off[e + 1] - v0;
-    const bool pool_ok = !(cnt->flags & F_POOL);
-    if (tid == 0 && plain) D->seed_off[e + 1] = so + ns;
-    const bool fits = ns <= S.ms_cap && nv <= S.vs_cap && pool_ok;
-    if (tid == 0 && !fits && pool_ok) {
-      if (ns > S.ms_cap) { raise_flag(cnt, F_MS); atomicMax(&cnt->need_ms, (unsigned)ns); }
-      if (nv > S.vs_cap) { raise_flag(cnt, F_VS); atomicMax(&cnt->need_vs, (unsigned)nv); }
-    }
-    // per-seed arrays in LDS, or in this workgroup's global scratch for
-    // events with many seeds / VELO states
-    const bool sm_s = ns <= kMsLds, sm_v = nv <= kVsLds;
-    float *xsf = sm_s ? sh.xsf : mf, *txsf = sm_s ? sh.txsf : mf + S.ms_cap;
-    float *ymf = sm_s ? sh.ymf : mf + 2 * (size_t)S.ms_cap;
-    float *tyf = sm_s ? sh.tyf : mf + 3 * (size_t)S.ms_cap;
-    float *sty = sm_s ? sh.sty : mf + 4 * (size_t)S.ms_cap;
-    int *sidx = sm_s ? sh.sidx : (int *)(mf + 5 * (size_t)S.ms_cap);
-    unsigned long long *best_s = sm_s ? sh.best_s : S.best_s + wg * (size_t)S.ms_cap;
-    unsigned long long *best_v = sm_v ? sh.best_v : S.best_v + wg * (size_t)S.vs_cap;
-    // seeds to the output in canonical order (half 0 then half 1) and their
-    // matching state
-    for (int i = tid; i < ns && pool_ok; i += kMatchWG) {
-      const sm_seed sd = i < n0 ? S.pool[b0 + i] : S.pool[b1 + i - n0];
-      if ((long long)so + i < D->seed_cap) D->seeds[so + i] = sd;
-      if (fits) {
-        const MState m = seed_state(sd, P);
-        ms[i] = m;
-        xsf[i] = m.xsf; txsf[i] = m.txsf; ymf[i] = m.y_mf; tyf[i] = m.tyf;
-        best_s[i] = ~0ull;
-      }
-    }
-    __syncthreads();
-    // seeds sorted by t_y, so each VELO state visits only its |dty| window
-    if (fits) {
-      for (int i = tid; i < ns; i += kMatchWG) {
-        const float t = tyf[i];
-        int r = 0;
-        for (int j = 0; j < ns; ++j) {
-          const float u = tyf[j];
-          r += (u < t) || (u == t && j < i);
-        }
-        sty[r] = t;
-        sidx[r] = i;
-      }
-    }
-    __syncthreads();
-    Surv *surv = S.surv + wg * (size_t)(2 * S.surv_cap);
-    if (fits && ns > 0) {
-      for (int v = tid; v < nv; v += kMatchWG) {
-        const float xvf = D->b.velo_x[v0 + v], yvf = D->b.velo_y[v0 + v], zvf = D->b.velo_z[v0 + v];
-        const float txvf = D->b.velo_tx[v0 + v], tyvf = D->b.velo_ty[v0 + v];
-        const float yvm = yvf + tyvf * (P.z_ymatchf - zvf);
-        const float zmv = P.zmf[0] + P.zmf[4] * txvf * txvf;
-        unsigned long long bv = ~0ull;
-        const float thi = tyvf + P.pre_dty;
-        for (int k = lower_f(sty, 0, ns, tyvf - P.pre_dty); k < ns && sty[k] <= thi; ++k) {
-          const int s = sidx[k];
-          const float dtx = txsf[s] - txvf;
-          if (!(fabsf(dtx) < P.pre_dtx)) continue;
-          if (!(fabsf(ymf[s] - yvm) < P.pre_dy)) continue;
-          const float zm = zmv + P.zmf[1] * fabsf(dtx) + P.zmf[2] * dtx * dtx + P.zmf[3] * fabsf(xsf[s]);
-          const float dx = (xsf[s] + (zm - P.z_statef) * txsf[s]) - (xvf + (zm - zvf) * txvf);
-          if (!(fabsf(dx) < P.pre_dx)) continue;
-          const PairEval r = eval_pair(ms[s], xvf, yvf, zvf, txvf, tyvf, P);
-          if (!r.ok) continue;
-          const unsigned long long bits = (unsigned long long)__double_as_longlong(r.chi2);
-          bv = bits < bv ? bits : bv;
-          atomicMin(&best_s[s], bits);
-          const unsigned slot = atomicAdd(&sh.nsurv, 1u);
-          if (slot < (unsigned)kSurvLds) sh.surv[slot] = Surv{v, s, r.chi2};
-          else if (slot < (unsigned)(kSurvLds + S.surv_cap)) surv[slot - kSurvLds] = Surv{v, s, r.chi2};
-        }
-        best_v[v] = bv;
-      }
-    }
-    __syncthreads();
-    unsigned nsv = sh.nsurv;
-    if (nsv > (unsigned)(kSurvLds + S.surv_cap)) {
-      if (tid == 0) { raise_flag(cnt, F_SURV); atomicMax(&cnt->need_surv, nsv - kSurvLds); }
-      nsv = kSurvLds + S.surv_cap;
-    }
-    // final selection: a pair survives if its chi2 is the best of its seed and
-    // of its VELO track
-    unsigned long long *kkey = nsv <= (unsigned)kSurvLds ? sh.kkey : (unsigned long long *)(surv + S.surv_cap);
-    for (unsigned i = tid; i < nsv; i += kMatchWG) {
-      const Surv sv = i < (unsigned)kSurvLds ? sh.surv[i] : surv[i - kSurvLds];
-      const unsigned long long bits = (unsigned long long)__double_as_longlong(sv.chi2);
-      if (best_v[sv.v] == bits && best_s[sv.s] == bits) {
-        const unsigned slot = atomicAdd(&sh.nkeep, 1u);
-        kkey[slot] = ((unsigned long long)sv.v << 32) | (unsigned)sv.s;
-      }
-    }
-    __syncthreads();
-    const unsigned nk = sh.nkeep;
+    const int item = sh.item;
+    if (item < 0) break;
+    const int k0 = item * kNL;
+    const int base = zone_off[k0];
+    const int nh = zone_off[k0 + kNL] - base;
+    if (tid <= kNL) sh.zoff[tid] = zone_off[k0 + tid] - base;
     if (tid == 0) {
-      if (plain) {
-        const long long lo = D->long_off[e];
-        sh.lbase = (unsigned long long)lo;
-        D->long_off[e + 1] = (int)(lo + nk);
-      } else {
-        const unsigned long long b = atomicAdd(&cnt->lpool_top, (unsigned long long)nk);
-        if (b + nk > (unsigned long long)S.lpool_cap) raise_flag(cnt, F_LPOOL);
-        sh.lbase = b;
-        S.ev_lcnt[e] = (int)nk;
-        S.ev_lbase[e] = (int)(b < (unsigned long long)S.lpool_cap ? b : 0);
+      int acc = 0;
+      for (int k = 0; k < 6; ++k) {
+        sh.xb[k] = acc;
+        const int L = (k >> 1) * 4 + (k & 1) * 3;
+        acc += zone_off[k0 + L + 1] - zone_off[k0 + L];
       }
+      sh.xb[6] = acc;
+    }
+    if (nh >= kMaxItemHits || nh < 0) {
+      if (tid == 0) {
+        raise_flag(S.cnt, nh < 0 ? F_INVALID : F_LIMIT);
+        S.item_cnt[item] = 0;
+        S.item_base[item] = 0;
+      }
+      __syncthreads();
+    } else if (nh <= lds_hits) {
+      // stage the item's hits; every bin entry starts at its zone's size
+      for (int i = tid; i < kNL * kBins; i += kSeedWG) {
+        const int L = i / kBins;
+        sh.bins[L][i % kBins] = (unsigned short)(zone_off[k0 + L + 1] - zone_off[k0 + L]);
+      }
+      for (int i = tid; i < nh; i += kSeedWG) {
+        s_x[i] = hx[base + i];
+        s_z[i] = hz[base + i];
+      }
+      __syncthreads();
+      // hit i opens the bins in (kbin(previous hit), kbin(hit i)]
+      for (int i = tid; i < nh; i += kSeedWG) {
+        int L = 0;
+        while (sh.zoff[L + 1] <= i) ++L;
+        const int li = i - sh.zoff[L];
+        const int kc = kbin(s_x[i]);
+        const int kp = li > 0 ? kbin(s_x[i - 1]) : 0;
+        for (int b = kp; b < kc; ++b) sh.bins[L][b] = (unsigned short)li;
+      }
+      __syncthreads();
+      seed_item<true>(s_x, s_z, hid + base, item, nh, P, S, wg, sh);
+    } else {
+      __syncthreads();
+      seed_item<false>(hx + base, hz + base, hid + base, item, nh, P, S, wg, sh);
+    }
+    // hand-off: this item's pool entries are made visible device-wide before
+    // the per-event counter is bumped; the second half's workgroup matches
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(&S.ev_done[item >> 1], 1) == 1;
+    __syncthreads();
+    if (s_last) {
+      __threadfence();
+      match_event(D, S, P, item >> 1, plain, wg, mh);
     }
     __syncthreads();
-    const unsigned long long lb = sh.lbase;
-    const long long cap = plain ? D->long_cap : S.lpool_cap;
-    sm_long *dst = plain ? D->longs : S.lpool;
-    for (unsigned i = tid; i < nk; i += kMatchWG) {
-      const unsigned long long key = kkey[i];
-      unsigned r = 0;
-      for (unsigned j = 0; j < nk; ++j) r += kkey[j] < key;
-      if ((long long)(lb + r) >= cap) continue;
-      const int vi = (int)(key >> 32), si = (int)(key & 0xffffffffu);
-      const int v = v0 + vi;
-      const PairEval pe = eval_pair(ms[si], D->b.velo_x[v], D->b.velo_y[v], D->b.velo_z[v],
-                                    D->b.velo_tx[v], D->b.velo_ty[v], P);
-      sm_long L;
-      L.velo_idx = vi; L.seed_idx = si; L.velo_id = D->b.velo_id[v];
-      L.qop = (float)pe.qop; L.chi2 = (float)pe.chi2; L.z_match = (float)pe.zm;
-      L.dx = (float)pe.dx; L.dy = (float)pe.dy; L.dtx = (float)pe.dtx; L.dty = (float)pe.dty;
-      dst[lb + r] = L;
-    }
-    if (plain && tid == 0 && (long long)(lb + nk) > D->long_cap) raise_flag(cnt, F_OUT_LONG);
-    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------ batch plumbing ----
+
+// Clear counters and per-event hand-off counts; in the batched form also
+// order the (event, half) items by hit count, largest first (log2 buckets),
+// so the longest items start first and the persistent grid drains evenly.
+__global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
+                                                  const KCtx *__restrict__ K, int plain) {
+  const Scratch &S = K->S;
+  __shared__ int hist[32], base[32];
+  const int ne = D->n_events, n = D->n_items;
+  const int32_t *zo = D->b.zone_off;
+  if (threadIdx.x == 0) {
+    Counters *c = S.cnt;
+    c->seed_queue = 0; c->match_queue = 0; c->flags = 0;
+    c->pool_top = 0; c->lpool_top = 0;
+    c->need_trip = c->need_cand = c->need_tbl = c->need_sst = 0;
+    c->need_ms = c->need_vs = c->need_surv = c->need_combo = 0;
+    c->total_seeds = 0; c->total_longs = 0;
+    if (plain) { D->seed_off[0] = 0; D->long_off[0] = 0; }
+  }
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) S.ev_done[e] = 0;
+  if (plain) return;
+  if (threadIdx.x < 32) hist[threadIdx.x] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int sz = max(zo[(i + 1) * kNL] - zo[i * kNL], 0);
+    atomicAdd(&hist[31 - __clz(sz + 1)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = 31; b >= 0; --b) { base[b] = acc; acc += hist[b]; }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int sz = max(zo[(i + 1) * kNL] - zo[i * kNL], 0);
+    const int p = atomicAdd(&base[31 - __clz(sz + 1)], 1);
+    S.item_order[p] = i;
+  }
+}
+
+// exclusive scan of per-event counts into off[0..n] (one workgroup)
+__device__ __forceinline__ void scan_counts(const int *c0, const int *c1, int stride, int n,
+                                            int32_t *off, int *s_tmp, long long *total) {
+  int carry = 0;
+  for (int b0 = 0; b0 < n; b0 += 1024) {
+    const int e = b0 + (int)threadIdx.x;
+    const int v = e < n ? (c1 ? c0[e * stride] + c1[e * stride] : c0[e * stride]) : 0;
+    int tot;
+    const int ex = block_excl_scan<1024>(v, s_tmp, tot);
+    if (e < n) off[e] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    off[n] = carry;
+    *total = carry;
+  }
+}
+
+// Per-event seed and long-track offsets of the batched form, totals and the
+// caller-capacity checks.
+__global__ __launch_bounds__(1024) void k_offsets(const Desc *__restrict__ D,
+                                                  const KCtx *__restrict__ K) {
+  const Scratch &S = K->S;
+  __shared__ int s_tmp[16];
+  const int n = D->n_events;
+  scan_counts(S.item_cnt, S.item_cnt + 1, 2, n, D->seed_off, s_tmp, &S.cnt->total_seeds);
+  scan_counts(S.ev_lcnt, nullptr, 1, n, D->long_off, s_tmp, &S.cnt->total_longs);
+  if (threadIdx.x == 0) {
+    if (S.cnt->total_seeds > D->seed_cap) raise_flag(S.cnt, F_OUT_SEED);
+    if (S.cnt->total_longs > D->long_cap) raise_flag(S.cnt, F_OUT_LONG);
+  }
+}
+
+// Seeds and long tracks from the pools to the caller's CSR outputs.
+__global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
+                                              const KCtx *__restrict__ K) {
+  const Scratch &S = K->S;
+  const int n = D->n_events;
+  const unsigned f = S.cnt->flags;
+  if (f & (F_POOL | F_LPOOL | F_OUT_SEED | F_OUT_LONG)) return;
+  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+    const int n0 = S.item_cnt[2 * e], n1 = S.item_cnt[2 * e + 1];
+    const long long b0 = S.item_base[2 * e], b1 = S.item_base[2 * e + 1];
+    const long long so = D->seed_off[e];
+    for (int i = threadIdx.x; i < n0 + n1; i += blockDim.x)
+      D->seeds[so + i] = i < n0 ? S.pool[b0 + i] : S.pool[b1 + i - n0];
+    const int m = S.ev_lcnt[e];
+    const long long src = S.ev_lbase[e], dst = D->long_off[e];
+    for (int i = threadIdx.x; i < m; i += blockDim.x) D->longs[dst + i] = S.lpool[src + i];
   }
 }
 
@@ -1090,37 +1099,28 @@ __global__ void k_plain_totals(const Desc *__restrict__ D, const KCtx *__restric
 
 using namespace smk;
 
+size_t smk_seed_lds_bytes(int lds_hits) {
+  const size_t a = sizeof(SeedShared) + (size_t)lds_hits * 2 * sizeof(float);
+  return a > sizeof(MatchShared) ? a : sizeof(MatchShared);
+}
+
 extern "C" {
-int smk_launch_init(const Desc *d, const KCtx *k, int plain, hipStream_t st) {
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, d, k, plain);
+int smk_launch_prepare(const Desc *d, const KCtx *k, int plain, hipStream_t st) {
+  hipLaunchKernelGGL(k_prepare, dim3(1), dim3(1024), 0, st, d, k, plain);
   return (int)hipGetLastError();
 }
-int smk_launch_order(const Desc *d, const KCtx *k, hipStream_t st) {
-  hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, st, d, k);
+int smk_launch_seed(const Desc *d, const KCtx *k, int item_begin, int item_count, int use_queue,
+                    int grid, int lds_hits, int plain, hipStream_t st) {
+  hipLaunchKernelGGL(k_seed, dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits), st, d, k,
+                     item_begin, item_count, use_queue, lds_hits, plain);
   return (int)hipGetLastError();
 }
-int smk_launch_seed(const Desc *d, const KCtx *k, int item_begin, int item_count,
-                    int use_queue, int grid, int lds_hits, hipStream_t st) {
-  hipLaunchKernelGGL(k_seed, dim3(grid), dim3(kSeedWG), (size_t)lds_hits * 2 * sizeof(float), st,
-                     d, k, item_begin, item_count, use_queue, lds_hits);
+int smk_launch_offsets(const Desc *d, const KCtx *k, hipStream_t st) {
+  hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, st, d, k);
   return (int)hipGetLastError();
 }
-int smk_launch_seed_off(const Desc *d, const KCtx *k, hipStream_t st) {
-  hipLaunchKernelGGL(k_seed_off, dim3(1), dim3(1024), 0, st, d, k);
-  return (int)hipGetLastError();
-}
-int smk_launch_match(const Desc *d, const KCtx *k, int ev_begin, int ev_count,
-                     int plain, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_match, dim3(grid), dim3(kMatchWG), 0, st, d, k, ev_begin, ev_count,
-                     plain);
-  return (int)hipGetLastError();
-}
-int smk_launch_long_off(const Desc *d, const KCtx *k, hipStream_t st) {
-  hipLaunchKernelGGL(k_long_off, dim3(1), dim3(1024), 0, st, d, k);
-  return (int)hipGetLastError();
-}
-int smk_launch_long_copy(const Desc *d, const KCtx *k, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_long_copy, dim3(grid), dim3(256), 0, st, d, k);
+int smk_launch_copy(const Desc *d, const KCtx *k, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, st, d, k);
   return (int)hipGetLastError();
 }
 int smk_launch_validate(const Desc *d, const KCtx *k, int grid, hipStream_t st) {

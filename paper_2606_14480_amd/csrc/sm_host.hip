@@ -14,7 +14,6 @@
 #include "sm.h"
 #include "sm_device.h"
 
-extern "C" int smk_launch_plain_totals(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
 
 namespace {
 
@@ -163,7 +162,7 @@ sm_status dalloc(Slot &s, T **p, size_t n, int64_t &bytes) {
 sm_status alloc_slot(sm_ctx *c, Slot &s) {
   free_slot_scratch(s);
   int64_t bytes = 0;
-  const size_t G = (size_t)c->seed_wgs, M = (size_t)c->match_wgs;
+  const size_t G = (size_t)c->seed_wgs;
   const Caps &k = s.caps;
   Scratch &S = s.S;
   memset(&S, 0, sizeof(S));
@@ -186,13 +185,14 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
   A(S.item_base, k.items);
   A(S.ev_lcnt, k.events);
   A(S.ev_lbase, k.events);
+  A(S.ev_done, k.events);
   A(S.pool, (size_t)k.pool);
   A(S.lpool, (size_t)k.lpool);
-  A(S.ms, M * k.ms);
-  A(S.mf, M * 6 * (size_t)k.ms);
-  A(S.best_s, M * k.ms);
-  A(S.best_v, M * k.vs);
-  A(S.surv, M * 2 * (size_t)k.surv);
+  A(S.ms, G * k.ms);
+  A(S.mf, G * 6 * (size_t)k.ms);
+  A(S.best_s, G * k.ms);
+  A(S.best_v, G * k.vs);
+  A(S.surv, G * 2 * (size_t)k.surv);
   A(S.cnt, 1);
 #undef A
   S.trip_cap = k.trip; S.cand_cap = k.cand; S.tbl_cap = k.tbl; S.sst_cap = k.sst;
@@ -281,14 +281,11 @@ sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
   const smk::KCtx *S = s.d_kctx;
   const Desc *d = s.d_desc;
   auto seq = [&](hipStream_t q) -> hipError_t {
-    int e = smk_launch_init(d, S, 0, q);
+    int e = smk_launch_prepare(d, S, 0, q);
     if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
-    if (!e) e = smk_launch_order(d, S, q);
-    if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, q);
-    if (!e) e = smk_launch_seed_off(d, S, q);
-    if (!e) e = smk_launch_match(d, S, 0, -1, 0, c->match_wgs, q);
-    if (!e) e = smk_launch_long_off(d, S, q);
-    if (!e) e = smk_launch_long_copy(d, S, 1024, q);
+    if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, q);
+    if (!e) e = smk_launch_offsets(d, S, q);
+    if (!e) e = smk_launch_copy(d, S, 1024, q);
     return (hipError_t)e;
   };
   if (!s.graph_ok) {
@@ -311,12 +308,10 @@ sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
 sm_status enqueue_plain(sm_ctx *c, Slot &s, int n_events, hipStream_t st) {
   const smk::KCtx *S = s.d_kctx;
   const Desc *d = s.d_desc;
-  int e = smk_launch_init(d, S, 1, st);
+  int e = smk_launch_prepare(d, S, 1, st);
   if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, st);
-  for (int ev = 0; ev < n_events && !e; ++ev) {
-    e = smk_launch_seed(d, S, 2 * ev, 2, 0, 2, s.lds_hits, st);
-    if (!e) e = smk_launch_match(d, S, ev, 1, 1, 1, st);
-  }
+  for (int ev = 0; ev < n_events && !e; ++ev)
+    e = smk_launch_seed(d, S, 2 * ev, 2, 0, 2, s.lds_hits, 1, st);
   if (!e) e = smk_launch_plain_totals(d, S, st);
   return hip_status((hipError_t)e);
 }
@@ -326,21 +321,15 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   const smk::KCtx *S = s.d_kctx;
   const Desc *d = s.d_desc;
   int e = hipEventRecord(ev[0], q);
-  if (!e) e = smk_launch_init(d, S, 0, q);
+  if (!e) e = smk_launch_prepare(d, S, 0, q);
   if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
   if (!e) e = hipEventRecord(ev[1], q);
-  if (!e) e = smk_launch_order(d, S, q);
+  if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, q);
   if (!e) e = hipEventRecord(ev[2], q);
-  if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, q);
+  if (!e) e = smk_launch_offsets(d, S, q);
   if (!e) e = hipEventRecord(ev[3], q);
-  if (!e) e = smk_launch_seed_off(d, S, q);
+  if (!e) e = smk_launch_copy(d, S, 1024, q);
   if (!e) e = hipEventRecord(ev[4], q);
-  if (!e) e = smk_launch_match(d, S, 0, -1, 0, c->match_wgs, q);
-  if (!e) e = hipEventRecord(ev[5], q);
-  if (!e) e = smk_launch_long_off(d, S, q);
-  if (!e) e = hipEventRecord(ev[6], q);
-  if (!e) e = smk_launch_long_copy(d, S, 1024, q);
-  if (!e) e = hipEventRecord(ev[7], q);
   return hip_status((hipError_t)e);
 }
 
@@ -386,7 +375,7 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
     fill_desc(s, *b, *o);
     if (hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, q) != hipSuccess)
       return SM_ERR_DEVICE;
-    hipEvent_t ev[8] = {};
+    hipEvent_t ev[5] = {};
     if (times) {
       for (auto &x : ev)
         if (hipEventCreate(&x) != hipSuccess) return SM_ERR_DEVICE;
@@ -400,9 +389,9 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
     if (st == SM_OK && hipStreamSynchronize(q) != hipSuccess) st = SM_ERR_DEVICE;
     if (times) {
       if (st == SM_OK) {
-        float *f = &times->init;
-        for (int k = 0; k < 7; ++k) hipEventElapsedTime(&f[k], ev[k], ev[k + 1]);
-        hipEventElapsedTime(&times->total, ev[0], ev[7]);
+        float *f = &times->prepare;
+        for (int k = 0; k < 4; ++k) hipEventElapsedTime(&f[k], ev[k], ev[k + 1]);
+        hipEventElapsedTime(&times->total, ev[0], ev[4]);
       }
       for (auto &x : ev) hipEventDestroy(x);
     }

@@ -65,8 +65,7 @@ class Batch(C.Structure):
 
 
 class KernelTimes(C.Structure):
-    _fields_ = [(n, C.c_float) for n in ("init", "order", "seed", "seed_off", "match",
-                                         "long_off", "long_copy", "total")]
+    _fields_ = [(n, C.c_float) for n in ("prepare", "seed_match", "offsets", "copy", "total")]
 
     def as_dict(self):
         return {n: float(getattr(self, n)) for n, _ in self._fields_}
@@ -208,12 +207,12 @@ def _stream_ptr(stream):
 
 class Context:
     def __init__(self, geometry: Geometry | None = None, params: Params | None = None,
-                 device: int = 0, n_slots: int = 2, seed_wgs: int = 0, match_wgs: int = 0,
+                 device: int = 0, n_slots: int = 2, seed_wgs: int = 0, lds_hits: int = 0,
                  validate: bool = False, mem_budget: int = 0):
         self.geometry = geometry or default_geometry()
         self.params = params or default_params()
-        cfg = Config(device=device, n_slots=n_slots, seed_wgs=seed_wgs, match_wgs=match_wgs,
-                     lds_hits=0, validate=int(validate), mem_budget=mem_budget)
+        cfg = Config(device=device, n_slots=n_slots, seed_wgs=seed_wgs, match_wgs=0,
+                     lds_hits=lds_hits, validate=int(validate), mem_budget=mem_budget)
         h = C.c_void_p()
         st = _lib.sm_create(C.byref(self.geometry), C.byref(self.params), C.byref(cfg), C.byref(h))
         if st != OK:
@@ -245,9 +244,20 @@ class Context:
         return t.as_dict()
 
     def submit(self, batch: DeviceBatch, out: DeviceOut):
+        return self.submit_c(batch.c, out.c)
+
+    def submit_c(self, batch_c: Batch, out_c: Out):
+        """sm_submit on raw structs; both must stay alive until the ticket completes."""
         t = C.c_int64()
-        st = _lib.sm_submit(self.h, C.byref(batch.c), C.byref(out.c), C.byref(t))
+        st = _lib.sm_submit(self.h, C.byref(batch_c), C.byref(out_c), C.byref(t))
         return st, t.value
+
+    def run_c(self, batch_c: Batch, out_c: Out, stream=None, plain: bool = False) -> int:
+        fn = _lib.sm_run_plain if plain else _lib.sm_run
+        st = fn(self.h, C.byref(batch_c), C.byref(out_c), _stream_ptr(stream))
+        if st != OK:
+            raise SmError(st, "sm_run_plain" if plain else "sm_run")
+        return st
 
     def poll(self, ticket: int, wait: bool = False) -> int:
         return _lib.sm_poll(self.h, C.c_int64(ticket), int(wait))

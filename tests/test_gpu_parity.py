@@ -109,7 +109,7 @@ def test_grid_shape_and_batch_composition(sm, ctx):
     b = ev.generate(ev.config(3, n_events=50))
     say("[gpu] grid shapes, 50 events")
     g1 = gpu_run(sm, ctx, b)
-    c2 = sm.Context(seed_wgs=7, match_wgs=3)
+    c2 = sm.Context(seed_wgs=7, lds_hits=1024)
     try:
         g2 = gpu_run(sm, c2, b)
     finally:
@@ -180,7 +180,7 @@ def test_scratch_growth(orc, sm):
     """A context with tiny scratch grows it and re-runs; results unchanged."""
     b = ev.generate(ev.config(4, n_events=8))
     say("[gpu] scratch growth")
-    c = sm.Context(seed_wgs=16, match_wgs=8)
+    c = sm.Context(seed_wgs=16)
     try:
         g = gpu_run(sm, c, b)
     finally:
