@@ -25,6 +25,15 @@ sys.path.insert(0, os.path.join(ROOT, "tests"))
 METRIC = ("events/s seeding+matching on 1 MI355X (batched vs plain) at oracle-matched "
           "tracks; p99 latency")
 HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "minbias": "minbias-{n}: {n} min-bias-like events per batch, Poisson(120) tracks in "
+               "acceptance, p 1.5-100 GeV, 2% hit inefficiency, 10% noise hits, 5% ghost VELO "
+               "states",
+    "uneven": "uneven-{n}: {n} events per batch, negative-binomial(mean 120, k=1) tracks in "
+              "[10, 600], otherwise min-bias-like",
+    "stress": "stress-{n}: {n} events per batch, negative-binomial(mean 240, k=1) tracks in "
+              "[20, 3000], 5% inefficiency, 20% noise hits",
+}
 
 
 def log(*a):
@@ -111,7 +120,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--events", type=int, default=1000)
+    ap.add_argument("--events", type=int, default=0,
+                    help="events per batch (default: the workload's own size)")
+    ap.add_argument("--workload", default="minbias", choices=("minbias", "uneven", "stress"))
+    ap.add_argument("--parity-events", type=int, default=2000,
+                    help="events of the batch checked against the oracle")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=2.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -136,7 +149,8 @@ def main():
     from paper_2606_14480_amd import sm
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    cfg = ev.config(2, n_events=args.events)
+    wl = {"minbias": 2, "uneven": 3, "stress": 4}[args.workload]
+    cfg = ev.config(wl, n_events=args.events or None)
     t0 = time.perf_counter()
     host = ev.generate(cfg)
     log(f"[bench] generated {host.n_events} events, {host.n_hits} hits, {host.n_velo} VELO "
@@ -153,13 +167,16 @@ def main():
     if not args.no_parity:
         from oracle import oracle as O
         import parity as PT
-        o = O.run(host, threads=os.cpu_count())
-        st = PT.compare(o, gpu, host.n_events)
+        npar = min(host.n_events, args.parity_events)
+        sub = host if npar == host.n_events else host.subset(range(npar))
+        g_sub = (gpu[0][:npar + 1], gpu[1][:gpu[0][npar]], gpu[2][:npar + 1], gpu[3][:gpu[2][npar]])
+        o = O.run(sub, threads=os.cpu_count())
+        st = PT.compare(o, g_sub, npar)
         if st["mismatches"]:
-            st = PT.compare(o, gpu, host.n_events, band=(
-                O.run(host, PT.eps_params(O, 1e-4), threads=os.cpu_count()),
-                O.run(host, PT.eps_params(O, -1e-4), threads=os.cpu_count())))
-        parity = {"seed_jaccard": round(st["seed_jaccard"], 6),
+            st = PT.compare(o, g_sub, npar, band=(
+                O.run(sub, PT.eps_params(O, 1e-4), threads=os.cpu_count()),
+                O.run(sub, PT.eps_params(O, -1e-4), threads=os.cpu_count())))
+        parity = {"events_checked": npar, "seed_jaccard": round(st["seed_jaccard"], 6),
                   "long_jaccard": round(st["long_jaccard"], 6),
                   "mismatches": st["mismatches"], "unexplained": len(st["unexplained"]),
                   "param_failures": len(st["param_fail"])}
@@ -199,7 +216,7 @@ def main():
         log(f"[bench] plain: {plain:.0f} events/s")
 
     serve = None
-    if args.serve_requests > 0:
+    if args.serve_requests > 0 and args.workload == "minbias":
         serve = serve_stream(ctx, sm, host, value, args.serve_requests, args.serve_load)
         log(f"[bench] served: {serve}")
     if args.calib_copy_mb > 0:
@@ -225,9 +242,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"minbias-{host.n_events}: {host.n_events} min-bias-like events "
-                               "per batch, Poisson(120) tracks in acceptance, p 1.5-100 GeV, "
-                               "2% hit inefficiency, 10% noise hits, 5% ghost VELO states",
+        "config": {"workload": WORKLOADS[args.workload].format(n=host.n_events),
                    "events_per_batch": host.n_events, "hits": host.n_hits,
                    "velo_states": host.n_velo, "seeds": n_seeds, "long_tracks": n_longs,
                    "form": "batched: captured graph, persistent kernels, LPT work queue",

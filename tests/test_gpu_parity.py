@@ -189,3 +189,91 @@ def test_scratch_growth(orc, sm):
     PT.assert_parity(PT.compare(o, g, b.n_events, band=(
         orc.run(b, PT.eps_params(orc, 1e-4), threads=8),
         orc.run(b, PT.eps_params(orc, -1e-4), threads=8))))
+
+
+def test_uneven_full_size(orc, sm, ctx):
+    """The uneven workload at its own size: 10,000 events in one batch."""
+    b = ev.generate(ev.config(3))
+    say("[gpu] uneven hits/event range", int(b.event_hits().min()), int(b.event_hits().max()))
+    check(orc, sm, ctx, b, "uneven 10000")
+
+
+def test_stress_batch_with_oracle_subset(orc, sm, ctx):
+    """A 5000-event stress batch on the GPU; the oracle checks events 0..499
+    (events are independent, so a subset of the batch's outputs is the
+    subset's result)."""
+    b = ev.generate(ev.config(4, n_events=5000))
+    say("[gpu] stress 5000, hits/event max", int(b.event_hits().max()))
+    g = gpu_run(sm, ctx, b)
+    n = 500
+    sub = b.subset(range(n))
+    gs = (g[0][:n + 1], g[1][:g[0][n]], g[2][:n + 1], g[3][:g[2][n]])
+    o = orc.run(sub, threads=8)
+    st = PT.compare(o, gs, n)
+    if st["mismatches"]:
+        st = PT.compare(o, gs, n, band=(orc.run(sub, PT.eps_params(orc, 1e-4), threads=8),
+                                        orc.run(sub, PT.eps_params(orc, -1e-4), threads=8)))
+    say(f"[gpu] stress subset: seeds {st['seeds_o']}/{st['seeds_g']} mismatches {st['mismatches']}")
+    PT.assert_parity(st)
+
+
+def test_tied_hit_positions(orc, sm, ctx):
+    """Hits with identical x in a zone: window and closest-hit choices follow
+    the lower position, as in the oracle."""
+    base = ev.generate(ev.config(1, n_events=3))
+    evs = []
+    for e in range(3):
+        E = base.event(e)
+        x = E.hit_x.copy()
+        # duplicate every hit of every other zone (same x, new id), keep sorting
+        hx, hz, hid, off = [], [], [], [0]
+        nid = E.n_hits
+        for k in range(24):
+            lo, hi = E.zone_off[k], E.zone_off[k + 1]
+            for i in range(lo, hi):
+                hx.append(x[i]); hz.append(E.hit_z[i]); hid.append(E.hit_id[i])
+                if k % 2 == 0:
+                    hx.append(x[i]); hz.append(E.hit_z[i]); hid.append(nid); nid += 1
+            off.append(len(hx))
+        E.zone_off = np.array(off, np.int32)
+        E.hit_x = np.array(hx, np.float32)
+        E.hit_z = np.array(hz, np.float32)
+        E.hit_id = np.array(hid, np.int32)
+        evs.append(E)
+    b = ev.concat(evs)
+    say("[gpu] tied hits")
+    g = gpu_run(sm, ctx, b)
+    o = orc.run(b)
+    st = PT.compare(o, g, b.n_events)
+    PT.assert_parity(st)
+    assert st["mismatches"] == 0 and st["seeds_g"] > 0
+
+
+def test_noise_only_event(orc, sm, ctx):
+    cfg = ev.GenConfig(n_events=4, config_id=301, mult="fixed", mean_tracks=1, noise=400.0)
+    b = ev.generate(cfg)
+    say("[gpu] noise-dominated events", b.n_hits)
+    g = gpu_run(sm, ctx, b)
+    o = orc.run(b)
+    PT.assert_parity(PT.compare(o, g, b.n_events))
+
+
+def test_item_hit_limit(sm, ctx):
+    """An (event, half) with 2^21 hits is refused with SM_ERR_LIMIT."""
+    n = 1 << 21
+    off = np.zeros(25, np.int32)
+    off[1:] = n                      # every hit in zone 0 (half 0, layer 0)
+    b = ev.Batch(zone_off=off, hit_x=np.sort(np.random.default_rng(0).uniform(-3000, 3000, n)).astype(np.float32),
+                 hit_z=np.full(n, 7826.0, np.float32), hit_id=np.arange(n, dtype=np.int32),
+                 velo_off=np.array([0, 0], np.int32), velo_x=np.zeros(0, np.float32),
+                 velo_y=np.zeros(0, np.float32), velo_z=np.zeros(0, np.float32),
+                 velo_tx=np.zeros(0, np.float32), velo_ty=np.zeros(0, np.float32),
+                 velo_id=np.zeros(0, np.int32))
+    say("[gpu] hit limit")
+    db = sm.DeviceBatch(b)
+    out = sm.DeviceOut(1, 1024, 1024)
+    assert ctx.run(db, out, check=False) == sm.ERR_LIMIT
+    # the context still works afterwards
+    b2 = ev.generate(ev.config(1))
+    g = gpu_run(sm, ctx, b2)
+    assert g[0][-1] > 0
