@@ -82,6 +82,11 @@ void orc_default_params(orc_params *p) {
   p->tol_ty = 1.0 / 937.5;
   p->chi2m_max = 2.0;
   p->polarity = 1.0;
+  p->uv_mode = 0;             /* Sec. 3.4: the iterative search is the default */
+  p->hough_bins = 64;         /* READING: the Hough variant's binning is not printed */
+  p->hough_best = 8;          /* Sec. 3.4: up to eight best bins */
+  p->hough_fine = 4;          /* READING: "several finer bins" */
+  p->hough_min = 2;           /* READING */
 }
 
 /* ---------------------------------------------------------- helpers ----- */
@@ -350,8 +355,9 @@ void orc_clone_vote(const orc_cand *c, int n, int n_pos, int32_t *keep) {
  * ascending z, averaging t_y after each found hit.  Each combination gets a
  * weighted y-z line fit; the best has most hits, then lowest chi2_y, then the
  * earlier (pass, initial hit).  Returns 1 and fills `out` if a seed is made. */
-int orc_uv(const orc_geom *g, const orc_params *P, const int32_t *off, const float *X,
-           const float *Z, const int32_t *ID, const orc_cand *cd, orc_seed *out) {
+static int uv_iterative(const orc_geom *g, const orc_params *P, const int32_t *off,
+                        const float *X, const float *Z, const int32_t *ID, const orc_cand *cd,
+                        orc_seed *out) {
   const int half = cd->half;
   const double zr = g->z_ref, d = P->d_ratio;
   const double ylo = half == 0 ? 0.0 : -P->y_max, yhi = half == 0 ? P->y_max : 0.0;
@@ -416,6 +422,133 @@ int orc_uv(const orc_geom *g, const orc_params *P, const int32_t *off, const flo
     out->id[l] = h >= 0 ? ID[h] : -1;
   }
   return 1;
+}
+
+
+/* One stereo-hit combination for a given t_y hypothesis, as the Hough
+ * variant builds it: the closest hit within uv_tol in each stereo layer,
+ * then the weighted y-z line fit.  Returns the hit count (0 if rejected). */
+static int uv_attach(const orc_geom *g, const orc_params *P, const int32_t *off, const float *X,
+                     const float *Z, const orc_cand *cd, double ty, int pos[ORC_NL],
+                     double *chi2_out, double *y0_out, double *ty_out) {
+  const double zr = g->z_ref, d = P->d_ratio;
+  double zs[6], ys[6], ws[6];
+  int n = 0;
+  for (int l = 0; l < ORC_NL; ++l) pos[l] = -1;
+  for (int j = 0; j < 6; ++j) {
+    const int L = UV_LAYERS[j];
+    const double zl = g->z[L], tl = g->tan_a[L];
+    const double pred = xmodel(cd->a, cd->b, cd->c, zl, zr, d) - ty * zl * tl;
+    const int h = closest_in_window(X, off[cd->half * 12 + L], off[cd->half * 12 + L + 1], pred, P->uv_tol);
+    if (h < 0) continue;
+    pos[L] = h;
+    zs[n] = Z[h];
+    ys[n] = (xmodel(cd->a, cd->b, cd->c, Z[h], zr, d) - X[h]) / tl;
+    ws[n] = tl * tl / (P->sigma_x * P->sigma_x);
+    ++n;
+  }
+  if (n < P->min_uv_hits) return 0;
+  double fy0, fty;
+  fit_line(zs, ys, ws, n, zr, &fy0, &fty);
+  double chi2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = ys[i] - (fy0 + fty * (zs[i] - zr));
+    chi2 += ws[i] * r * r;
+  }
+  chi2 /= (double)(n - 2);
+  if (!(chi2 < P->chi2y_max)) return 0;
+  *chi2_out = chi2; *y0_out = fy0; *ty_out = fty;
+  return n;
+}
+
+/* Hough-cluster UV seeding (Sec. 3.4, second variant).  Every stereo hit
+ * whose y lies in the half gives t_y = y / z; the t_y values fill a coarse
+ * histogram over the half's range; the most populated bins (up to
+ * hough_best, ties to the lower bin) are each split into hough_fine finer
+ * bins, and the mean t_y of each non-empty fine bin is a hypothesis for which
+ * the closest hit within uv_tol is attached in every stereo layer.  The best
+ * combination is chosen as in the iterative variant: most hits, then lowest
+ * chi2_y, then the earlier hypothesis. */
+static int uv_hough(const orc_geom *g, const orc_params *P, const int32_t *off, const float *X,
+                    const float *Z, const int32_t *ID, const orc_cand *cd, orc_seed *out) {
+  const int half = cd->half, NB = P->hough_bins, NF = P->hough_fine;
+  const double zr = g->z_ref, d = P->d_ratio;
+  double zmin = 1e300;
+  for (int j = 0; j < 6; ++j) zmin = g->z[UV_LAYERS[j]] < zmin ? g->z[UV_LAYERS[j]] : zmin;
+  const double lo = half == 0 ? 0.0 : -P->y_max / zmin;
+  const double hi = half == 0 ? P->y_max / zmin : 0.0;
+  const double w = (hi - lo) / NB;
+  const double ylo = half == 0 ? 0.0 : -P->y_max, yhi = half == 0 ? P->y_max : 0.0;
+  /* entries: t_y of every stereo hit with y inside the half */
+  int cap = 64, n = 0;
+  double *tys = (double *)malloc(sizeof(double) * (size_t)cap);
+  for (int j = 0; j < 6; ++j) {
+    const int L = UV_LAYERS[j];
+    for (int h = off[half * 12 + L]; h < off[half * 12 + L + 1]; ++h) {
+      const double y = (xmodel(cd->a, cd->b, cd->c, Z[h], zr, d) - X[h]) / g->tan_a[L];
+      if (!(y >= ylo && y <= yhi)) continue;
+      if (n == cap) { cap *= 2; tys = (double *)realloc(tys, sizeof(double) * (size_t)cap); }
+      tys[n++] = y / Z[h];
+    }
+  }
+  int *cnt = (int *)calloc((size_t)NB, sizeof(int));
+  for (int i = 0; i < n; ++i) {
+    int b = (int)floor((tys[i] - lo) / w);
+    b = b < 0 ? 0 : (b >= NB ? NB - 1 : b);
+    cnt[b]++;
+  }
+  int best_n = 0, bpos[ORC_NL];
+  double best_chi2 = 0.0, best_y0 = 0.0, best_ty = 0.0;
+  int *used = (int *)calloc((size_t)NB, sizeof(int));
+  for (int r = 0; r < P->hough_best; ++r) {
+    int bb = -1;
+    for (int b = 0; b < NB; ++b)
+      if (!used[b] && cnt[b] >= P->hough_min && (bb < 0 || cnt[b] > cnt[bb])) bb = b;
+    if (bb < 0) break;
+    used[bb] = 1;
+    const double blo = lo + bb * w, fw = w / NF;
+    for (int f = 0; f < NF; ++f) {
+      double sum = 0.0;
+      int m = 0;
+      for (int i = 0; i < n; ++i) {
+        int b = (int)floor((tys[i] - lo) / w);
+        b = b < 0 ? 0 : (b >= NB ? NB - 1 : b);
+        if (b != bb) continue;
+        int fi = (int)floor((tys[i] - blo) / fw);
+        fi = fi < 0 ? 0 : (fi >= NF ? NF - 1 : fi);
+        if (fi != f) continue;
+        sum += tys[i];
+        ++m;
+      }
+      if (m == 0) continue;
+      int pos[ORC_NL];
+      double chi2, y0, ty;
+      const int k = uv_attach(g, P, off, X, Z, cd, sum / m, pos, &chi2, &y0, &ty);
+      if (k > best_n || (k > 0 && k == best_n && chi2 < best_chi2)) {
+        best_n = k; best_chi2 = chi2; best_y0 = y0; best_ty = ty;
+        memcpy(bpos, pos, sizeof(pos));
+      }
+    }
+  }
+  free(tys); free(cnt); free(used);
+  if (best_n == 0) return 0;
+  memset(out, 0, sizeof(*out));
+  out->a = cd->a; out->b = cd->b; out->c = cd->c;
+  out->y0 = best_y0; out->ty = best_ty;
+  out->chi2x = cd->chi2; out->chi2y = best_chi2; out->score = cd->score;
+  out->nx = cd->n; out->nuv = best_n; out->half = cd->half; out->it = cd->it;
+  for (int l = 0; l < ORC_NL; ++l) {
+    const int h = (g->tan_a[l] == 0.0) ? cd->pos[l] : bpos[l];
+    out->pos[l] = h;
+    out->id[l] = h >= 0 ? ID[h] : -1;
+  }
+  return 1;
+}
+
+int orc_uv(const orc_geom *g, const orc_params *P, const int32_t *off, const float *X,
+           const float *Z, const int32_t *ID, const orc_cand *cd, orc_seed *out) {
+  return P->uv_mode == 1 ? uv_hough(g, P, off, X, Z, ID, cd, out)
+                         : uv_iterative(g, P, off, X, Z, ID, cd, out);
 }
 
 /* ---------------------------------------------------------- Matching ---- */

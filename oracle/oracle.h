@@ -53,6 +53,13 @@ typedef struct {
   double tol_tx, tol_ty;
   double chi2m_max;
   double polarity;
+  /* UV variant (Sec. 3.4): 0 iterative (default), 1 Hough clusters */
+  int32_t uv_mode;
+  int32_t hough_bins;  /* coarse t_y bins over the half's range */
+  int32_t hough_best;  /* most populated coarse bins kept */
+  int32_t hough_fine;  /* fine bins per kept coarse bin */
+  int32_t hough_min;   /* entries a coarse bin needs to be kept */
+  int32_t pad2;
 } orc_params;
 
 /* One three-hit combination and what became of it. */

@@ -175,3 +175,64 @@ def uv_full_scan(ev, cand, P, G):
             if best is None or n > best[1] or (n == best[1] and chi2 < best[4]):
                 best = (pos, n, sol[0], sol[1], chi2)
     return best
+
+
+def uv_hough_full_scan(ev, cand, P, G):
+    """Hough-cluster UV search with full-zone scans: coarse t_y histogram over
+    the half's range, the most populated bins (ties to the lower bin), fine
+    bins inside each, the mean t_y of a fine bin as the hypothesis, the
+    closest hit within uv_tol per stereo layer, the weighted line fit.
+    Returns (pos[12], n, y0, ty, chi2) of the best combination or None."""
+    X, Z = ev.hit_x.astype(float), ev.hit_z.astype(float)
+    zr, d = G.z_ref, P.d_ratio
+    prm = (cand["a"], cand["b"], cand["c"])
+    half = int(cand["half"])
+    zmin = min(G.z[L] for L in UV_LAYERS)
+    lo, hi = (0.0, P.y_max / zmin) if half == 0 else (-P.y_max / zmin, 0.0)
+    ylo, yhi = (0.0, P.y_max) if half == 0 else (-P.y_max, 0.0)
+    NB, NF = P.hough_bins, P.hough_fine
+    w = (hi - lo) / NB
+    tys = []
+    for L in UV_LAYERS:
+        a, bz = zone(ev, half, L)
+        for h in range(a, bz):
+            y = (xmodel(prm, Z[h], zr, d) - X[h]) / G.tan_a[L]
+            if ylo <= y <= yhi:
+                tys.append(y / Z[h])
+    bins = [min(max(int(math.floor((t - lo) / w)), 0), NB - 1) for t in tys]
+    counts = np.bincount(bins, minlength=NB) if bins else np.zeros(NB, int)
+    order = sorted(range(NB), key=lambda b: (-counts[b], b))
+    kept = [b for b in order if counts[b] >= P.hough_min][:P.hough_best]
+    best = None
+    for bb in kept:
+        blo = lo + bb * w
+        fw = w / NF
+        for f in range(NF):
+            sel = [t for t, b in zip(tys, bins)
+                   if b == bb and min(max(int(math.floor((t - blo) / fw)), 0), NF - 1) == f]
+            if not sel:
+                continue
+            ty = sum(sel) / len(sel)
+            pos = [-1] * 12
+            pts = []
+            for L in UV_LAYERS:
+                a, bz = zone(ev, half, L)
+                pred = xmodel(prm, G.z[L], zr, d) - ty * G.z[L] * G.tan_a[L]
+                h = closest_full_scan(X, a, bz, pred, P.uv_tol)
+                if h >= 0:
+                    pos[L] = h
+                    pts.append((Z[h], (xmodel(prm, Z[h], zr, d) - X[h]) / G.tan_a[L], G.tan_a[L]))
+            n = len(pts)
+            if n < P.min_uv_hits:
+                continue
+            zz = np.array([p[0] for p in pts]) - zr
+            yy = np.array([p[1] for p in pts])
+            ww = np.array([(p[2] / P.sigma_x) ** 2 for p in pts])
+            A = np.stack([np.ones_like(zz), zz], 1) * np.sqrt(ww)[:, None]
+            sol, *_ = np.linalg.lstsq(A, yy * np.sqrt(ww), rcond=None)
+            chi2 = float(np.sum(ww * (yy - sol[0] - sol[1] * zz) ** 2) / (n - 2))
+            if not chi2 < P.chi2y_max:
+                continue
+            if best is None or n > best[1] or (n == best[1] and chi2 < best[4]):
+                best = (pos, n, sol[0], sol[1], chi2)
+    return best
