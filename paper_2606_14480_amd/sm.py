@@ -267,9 +267,16 @@ class Context:
 
 
 def reconstruct(ctx: Context, host_batch, plain: bool = False, seed_cap=None, long_cap=None):
-    """Convenience: copy a host batch to the device, run, return host arrays."""
+    """Convenience: copy a host batch to the device, run, return host arrays.
+    If the outputs do not fit the first guess, runs once more with the sizes
+    the library reported."""
     db = DeviceBatch(host_batch)
     out = DeviceOut(host_batch.n_events, seed_cap or max(host_batch.n_hits // 4, 16),
                     long_cap or max(host_batch.n_velo * 2, 16))
-    ctx.run(db, out, plain=plain)
+    st = ctx.run(db, out, plain=plain, check=False)
+    if st == ERR_CAPACITY:
+        out = DeviceOut(host_batch.n_events, max(out.n_seeds, 16), max(out.n_longs, 16))
+        st = ctx.run(db, out, plain=plain, check=False)
+    if st != OK:
+        raise SmError(st, "sm_run_plain" if plain else "sm_run")
     return out.to_host()
