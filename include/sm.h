@@ -87,6 +87,19 @@ typedef struct {
   double tol_tx, tol_ty;
   double chi2m_max;        /* chi2_match cut */
   double polarity;         /* +1 or -1, magnet polarity */
+  /* UV seeding variant, Sec. 3.4: 0 the iterative search, 1 the Hough-cluster
+   * search.  The Hough search histograms t_y = y/z of every stereo hit whose
+   * y lies in the half, over [0, y_max/z_min] (upper half) or
+   * [-y_max/z_min, 0] (lower half), z_min the lowest nominal stereo-layer z;
+   * keeps the hough_best most populated bins holding at least hough_min
+   * entries (ties to the lower bin), splits each into hough_fine bins and
+   * tries the mean t_y of every non-empty fine bin as a hypothesis. */
+  int32_t uv_mode;
+  int32_t hough_bins;      /* 1..128 */
+  int32_t hough_best;      /* >= 1, hough_best * hough_fine <= 64 */
+  int32_t hough_fine;      /* >= 1 */
+  int32_t hough_min;       /* >= 1 */
+  int32_t pad2;
 } sm_params;
 
 /* Library resources; zero fields take defaults. */

@@ -109,14 +109,19 @@ static int first_at_least(const float *x, int lo, int hi, double v) {
   return lo;
 }
 
-/* Closest hit to `pred` among hits of [lo, hi) inside [pred - tol, pred + tol];
- * ties go to the lower position (READING).  Returns -1 if none. */
+/* Closest hit to `pred` among hits of [lo, hi) inside [pred - tol, pred + tol].
+ * READING: distances closer than ORC_TIE_MM are a tie, won by the lower
+ * position (a prediction midway between two hits, as a mean t_y of two hits of
+ * one layer gives, is a tie that rounding alone would otherwise break); the
+ * hits are visited in ascending position and a later hit replaces the current
+ * one only if it is closer by more than ORC_TIE_MM.  Returns -1 if none. */
+#define ORC_TIE_MM 1e-6
 static int closest_in_window(const float *x, int lo, int hi, double pred, double tol) {
   int best = -1;
   double bestd = 0.0;
   for (int i = first_at_least(x, lo, hi, pred - tol); i < hi && (double)x[i] <= pred + tol; ++i) {
     double d = fabs((double)x[i] - pred);
-    if (best < 0 || d < bestd) { best = i; bestd = d; }
+    if (best < 0 || d < bestd - ORC_TIE_MM) { best = i; bestd = d; }
   }
   return best;
 }

@@ -28,6 +28,8 @@ constexpr int kVsLds = 512;         // VELO states per event with LDS best-chi2 
 constexpr int kSurvLds = 512;       // matching survivors kept in LDS
 constexpr int kPosBits = 21;        // item-relative hit positions < 2^21
 constexpr int kMaxItemHits = 1 << kPosBits;
+constexpr int kHoughBins = 128;     // largest coarse t_y histogram
+constexpr double kTieMm = 1e-6;     // closest-hit distances this close are a tie
 
 // status flags (Counters::flags)
 enum : unsigned {
@@ -90,6 +92,9 @@ struct DevParams {
   double chi2m_max, polarity, invp_a, invp_b;
   float pre_dx, pre_dy, pre_dtx, pre_dty;  // FP32 prefilter, slightly wider
   float zmf[5], z_ymatchf, z_statef;
+  // Hough-cluster UV variant
+  int uv_mode, hough_bins, hough_best, hough_fine, hough_min, pad_h;
+  double hough_lo[2], hough_hi[2];
 };
 
 // An x-z candidate (Sec. 3.2) in per-workgroup scratch.
@@ -164,7 +169,8 @@ extern "C" {
 // Launchers (sm_device.hip); each returns the hipError_t of its launch.
 int smk_launch_prepare(const smk::Desc *d, const smk::KCtx *k, int plain, hipStream_t st);
 int smk_launch_seed(const smk::Desc *d, const smk::KCtx *k, int item_begin, int item_count,
-                    int use_queue, int grid, int lds_hits, int plain, hipStream_t st);
+                    int use_queue, int grid, int lds_hits, int plain, int uv_mode,
+                    hipStream_t st);
 int smk_launch_offsets(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
 int smk_launch_copy(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 int smk_launch_validate(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);

@@ -71,33 +71,6 @@ __device__ __forceinline__ int lower_f(const float *X, int lo, int hi, float v) 
   }
   return lo;
 }
-// first i in [lo, hi) with X[i] > v
-__device__ __forceinline__ int upper_f(const float *X, int lo, int hi, float v) {
-  while (lo < hi) {
-    const int m = (lo + hi) >> 1;
-    if (X[m] <= v) lo = m + 1; else hi = m;
-  }
-  return lo;
-}
-__device__ __forceinline__ int lower_d(const float *X, int lo, int hi, double v) {
-  while (lo < hi) {
-    const int m = (lo + hi) >> 1;
-    if ((double)X[m] < v) lo = m + 1; else hi = m;
-  }
-  return lo;
-}
-// Closest hit to pred inside [pred - tol, pred + tol], lower position on ties.
-__device__ __forceinline__ int closest_d(const float *X, int lo, int hi, double pred, double tol) {
-  int best = -1;
-  double bd = 0.0;
-  for (int i = lower_d(X, lo, hi, pred - tol); i < hi; ++i) {
-    const double x = X[i];
-    if (x > pred + tol) break;
-    const double d = fabs(x - pred);
-    if (best < 0 || d < bd) { best = i; bd = d; }
-  }
-  return best;
-}
 
 __device__ __forceinline__ void raise_flag(Counters *c, unsigned f) { atomicOr(&c->flags, f); }
 
@@ -182,6 +155,7 @@ struct SeedShared {
   int scan[kSeedWG], a0[kSeedWG], a1[kSeedWG], a2[kSeedWG];
   int tmp[16];
   int zoff[kNL + 1];
+  int zlo[kNL], zhi[kNL];                // z span of each layer (Hough UV), as zkey
   int xb[7];                             // first compact x index of each x slot
   int item;
   unsigned ntrip, ncand, nseed, ncombo;
@@ -207,8 +181,11 @@ __device__ __forceinline__ int zlower(const float *X, const SeedShared &sh, int 
   }
 }
 
-// Closest hit to pred in zone L inside [pred - tol, pred + tol], lower
-// position on ties; -1 if none.
+// Closest hit to pred in zone L inside [pred - tol, pred + tol]; -1 if none.
+// Distances closer than kTieMm are a tie, won by the lower position: a later
+// hit replaces the current one only if it is closer by more than kTieMm, so a
+// prediction midway between two hits picks the same hit whatever the
+// rounding of the prediction.
 template <bool kLds>
 __device__ __forceinline__ int zclosest(const float *X, const SeedShared &sh, int L, double pred,
                                         double tol) {
@@ -219,7 +196,7 @@ __device__ __forceinline__ int zclosest(const float *X, const SeedShared &sh, in
     const double x = X[i];
     if (x > pred + tol) break;
     const double d = fabs(x - pred);
-    if (best < 0 || d < bd) { best = i; bd = d; }
+    if (best < 0 || d < bd - kTieMm) { best = i; bd = d; }
   }
   return best;
 }
@@ -418,12 +395,228 @@ __device__ __forceinline__ bool uv_combo(const float *X, const float *Z, const S
   return true;
 }
 
+// ------------------------------------------------ Hough-cluster UV ------
+
+// Per-wave LDS of the Hough-cluster UV search (one x-z track per wave).
+struct HoughWave {
+  int hist[kHoughBins];          // coarse t_y histogram
+  long long fsum[64];            // t_y sums of the fine bins, in units of 2^-40
+  int fcnt[64];                  // entries of the fine bins
+  signed char rank[kHoughBins];  // order of a kept coarse bin, -1 if not kept
+};
+static_assert((kSeedWG / 64) * sizeof(HoughWave) <= sizeof(double) * kCandLds * 3,
+              "Hough per-wave state must fit the UV parameter area");
+
+// float order as int order, and back
+__device__ __forceinline__ int zkey(float z) {
+  const int b = __float_as_int(z);
+  return b ^ ((b >> 31) & 0x7fffffff);
+}
+__device__ __forceinline__ float zunkey(int k) { return __int_as_float(k ^ ((k >> 31) & 0x7fffffff)); }
+
+// x range of stereo layer L holding every hit whose y = (x(z_hit) - x_hit) /
+// tan lies in [ylo, yhi] for a z_hit inside the layer's z span.  x(z) may
+// depart from its chord over the span by at most span^2/8 max|x''|.  The
+// range is a superset; the exact test is taken hit by hit.
+__device__ __forceinline__ void hough_xrange(const SeedShared &sh, const DevParams &P, int L,
+                                             double a, double b, double c, double ylo,
+                                             double yhi, double &lo, double &hi) {
+  const double za = zunkey(sh.zlo[L]), zb = zunkey(sh.zhi[L]);
+  const double xa = xm(a, b, c, za, P), xb = xm(a, b, c, zb, P);
+  const double dz = zb - za, um = fmax(fabs(za - P.zref), fabs(zb - P.zref));
+  const double e = 0.125 * dz * dz * fabs(c) * (2.0 + 6.0 * fabs(P.d) * um);
+  const double t = P.tand[L], s1 = yhi * t, s2 = ylo * t;
+  lo = fmin(xa, xb) - e - fmax(s1, s2);
+  hi = fmax(xa, xb) + e - fmin(s1, s2);
+  const double slack = 1e-9 * (fabs(lo) + fabs(hi)) + 1e-6;
+  lo -= slack;
+  hi += slack;
+}
+
+// Calls f(L, i) on the lanes of one wave for every hit i of the six stereo
+// layers inside the x range of hough_xrange.
+template <bool kLds, class F>
+__device__ __forceinline__ void hough_scan(const float *X, const SeedShared &sh, const DevParams &P,
+                                           double a, double b, double c, double ylo, double yhi,
+                                           F &&f) {
+  const int lane = threadIdx.x & 63;
+  for (int k = 0; k < 6; ++k) {
+    const int L = uvlayer(k);
+    const int e = sh.zoff[L + 1];
+    if (sh.zoff[L] == e) continue;
+    double lo, hi;
+    hough_xrange(sh, P, L, a, b, c, ylo, yhi, lo, hi);
+    const int s = zlower<kLds>(X, sh, L, lo);
+    for (int i0 = s; i0 < e; i0 += 64) {
+      const int i = i0 + lane;
+      const bool in = i < e && (double)X[i] <= hi;
+      if (in) f(L, i);
+      if (__ballot(in) != ~0ull) break;
+    }
+  }
+}
+
+// One t_y hypothesis: the closest hit within uv_tol in every stereo layer,
+// then the weighted line fit of uv_combo.
+template <bool kLds>
+__device__ __forceinline__ bool hough_attach(const float *X, const float *Z, const SeedShared &sh,
+                                             const DevParams &P, double a, double b, double c,
+                                             double ty, Combo &r) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0, yref = 0.0;
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int L = uvlayer(k);
+    const double zl = P.zd[L], tl = P.tand[L];
+    const double pred = xm(a, b, c, zl, P) - ty * zl * tl;
+    const int h = zclosest<kLds>(X, sh, L, pred, P.uv_tol);
+    r.pos[k] = h;
+    if (h < 0) continue;
+    const double zh = Z[h];
+    const double yl = (xm(a, b, c, zh, P) - (double)X[h]) * P.inv_tand[L];
+    if (n == 0) yref = yl;
+    const double w = tl * tl, u = zh - P.zref, yr = yl - yref;
+    s0 += w; s1 += w * u; s2 += w * u * u;
+    q0 += w * yr; q1 += w * u * yr; q2 += w * yr * yr;
+    ++n;
+  }
+  if (n < P.min_uv_hits) return false;
+  const double idet = 1.0 / (s0 * s2 - s1 * s1);
+  const double fy = (q0 * s2 - q1 * s1) * idet;
+  const double ft = (s0 * q1 - s1 * q0) * idet;
+  const double rss = fmax(q2 - fy * q0 - ft * q1, 0.0);
+  const double chi2 = rss * P.inv_sigma2 / (double)(n - 2);
+  if (!(chi2 < P.chi2y_max)) return false;
+  r.chi2 = chi2;
+  r.y0 = fy + yref;
+  r.ty = ft;
+  r.n = n;
+  return true;
+}
+
+// Hough-cluster UV seeding (Sec. 3.4, second variant) of the item's
+// surviving x-z tracks, one track per wave: coarse t_y histogram of the
+// stereo hits with y in the half, the hough_best most populated bins (ties
+// to the lower bin, at least hough_min entries), hough_fine fine bins in
+// each, the mean t_y of every non-empty fine bin tried by one lane.  The
+// best hypothesis (most hits, lowest chi2_y, earliest) is the track's only
+// combination.  Bins are decided in FP64; the fine-bin sums are exact
+// fixed-point sums, so the result does not depend on the order of the adds.
+template <bool kLds>
+__device__ void uv_hough(const float *X, const float *Z, SeedShared &sh, const DevParams &P,
+                         int half, unsigned nc, const int *cinfo, const Cand *cand, int *bestn,
+                         unsigned long long *bestchi, int *bestidx, Combo *combo, int combo_cap) {
+#pragma clang fp contract(off)
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  HoughWave &hw = reinterpret_cast<HoughWave *>(&sh.u.uv.cabc[0][0])[wv];
+  if (tid < kNL) {
+    sh.zlo[tid] = 0x7fffffff;
+    sh.zhi[tid] = -0x7fffffff - 1;
+  }
+  __syncthreads();
+  for (int k = 0; k < 6; ++k) {
+    const int L = uvlayer(k);
+    for (int i = sh.zoff[L] + tid; i < sh.zoff[L + 1]; i += kSeedWG) {
+      const int key = zkey(Z[i]);
+      atomicMin(&sh.zlo[L], key);
+      atomicMax(&sh.zhi[L], key);
+    }
+  }
+  __syncthreads();
+  const double ylo = half == 0 ? 0.0 : -P.y_max, yhi = half == 0 ? P.y_max : 0.0;
+  const double lo = P.hough_lo[half], hi = P.hough_hi[half];
+  const int NB = P.hough_bins, NF = P.hough_fine, NH = P.hough_best * P.hough_fine;
+  const double w = (hi - lo) / NB, fw = w / NF;
+  constexpr double kFix = 1099511627776.0;   // 2^40
+  auto coarse = [&](double t) {
+    const int k = (int)floor((t - lo) / w);
+    return k < 0 ? 0 : (k >= NB ? NB - 1 : k);
+  };
+  for (unsigned c0 = 0; c0 < nc; c0 += kSeedWG / 64) {
+    const unsigned ci = c0 + wv;
+    const bool act = ci < nc && !(cinfo[ci] & ((1 << 4) | (1 << 5)));
+    double a = 0.0, b = 0.0, c = 0.0;
+    if (act) {
+      a = cand[ci].a; b = cand[ci].b; c = cand[ci].c;
+    }
+    for (int i = lane; i < kHoughBins; i += 64) hw.hist[i] = 0;
+    hw.fsum[lane] = 0;
+    hw.fcnt[lane] = 0;
+    if (act && lane == 0) {
+      bestn[ci] = 0;
+      bestchi[ci] = ~0ull;
+      bestidx[ci] = 0x7fffffff;
+    }
+    __syncthreads();
+    if (act)
+      hough_scan<kLds>(X, sh, P, a, b, c, ylo, yhi, [&](int L, int i) {
+        const double zh = Z[i];
+        const double y = (xm(a, b, c, zh, P) - (double)X[i]) / P.tand[L];
+        if (y >= ylo && y <= yhi) atomicAdd(&hw.hist[coarse(y / zh)], 1);
+      });
+    __syncthreads();
+    if (act) {
+      for (int k = lane; k < NB; k += 64) {
+        const int h = hw.hist[k];
+        int r = 0;
+        for (int j = 0; j < NB; ++j) {
+          const int hj = hw.hist[j];
+          r += (hj > h) | (hj == h && j < k);
+        }
+        hw.rank[k] = (h >= P.hough_min && r < P.hough_best) ? (signed char)r : (signed char)-1;
+      }
+    }
+    __syncthreads();
+    if (act)
+      hough_scan<kLds>(X, sh, P, a, b, c, ylo, yhi, [&](int L, int i) {
+        const double zh = Z[i];
+        const double y = (xm(a, b, c, zh, P) - (double)X[i]) / P.tand[L];
+        if (!(y >= ylo && y <= yhi)) return;
+        const double t = y / zh;
+        const int k = coarse(t);
+        const int r = hw.rank[k];
+        if (r < 0) return;
+        int f = (int)floor((t - (lo + k * w)) / fw);
+        f = f < 0 ? 0 : (f >= NF ? NF - 1 : f);
+        atomicAdd(&hw.fcnt[r * NF + f], 1);
+        atomicAdd((unsigned long long *)&hw.fsum[r * NF + f],
+                  (unsigned long long)(long long)llrint(t * kFix));
+      });
+    __syncthreads();
+    if (act) {
+      Combo r;
+      bool ok = false;
+      if (lane < NH && hw.fcnt[lane] > 0) {
+        const double ty = (double)hw.fsum[lane] / kFix / (double)hw.fcnt[lane];
+        ok = hough_attach<kLds>(X, Z, sh, P, a, b, c, ty, r);
+      }
+      int kn = ok ? r.n : 0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) kn = max(kn, __shfl_xor(kn, o, 64));
+      double kc = (ok && r.n == kn) ? r.chi2 : __builtin_inf();
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) kc = fmin(kc, __shfl_xor(kc, o, 64));
+      int kh = (ok && r.n == kn && r.chi2 == kc) ? lane : 64;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) kh = min(kh, __shfl_xor(kh, o, 64));
+      if (kn > 0 && lane == kh) {
+        r.c = (int)ci;
+        r.tb = lane;
+        const unsigned slot = atomicAdd(&sh.ncombo, 1u);
+        if (slot < (unsigned)combo_cap) combo[slot] = r;
+        bestn[ci] = r.n;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // -------------------------------------------------------- seed kernel -----
 
 // Seeding of one (event, half) item.  kLds: the item's hits are in LDS (with
 // the x-bin index); the candidate-side arrays are in LDS whenever they fit,
 // else in this workgroup's global scratch.
-template <bool kLds>
+template <bool kLds, int kUv>
 __device__ __forceinline__ void seed_item(const float *X, const float *Z, const int32_t *hid,
                                           int item, int nh, const DevParams &P,
                                           const Scratch &S, size_t wg, SeedShared &sh) {
@@ -533,7 +726,10 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   unsigned long long *bestchi = small ? sh.u.uv.bestchi : S.bestchi + co;
   int *bestidx = small ? sh.u.uv.bestidx : S.bestidx + co;
   const double ylo = half == 0 ? 0.0 : -P.y_max, yhi = half == 0 ? P.y_max : 0.0;
-  for (unsigned c0 = 0; c0 < nc; c0 += kSeedWG) {
+  if constexpr (kUv == 1)
+    uv_hough<kLds>(X, Z, sh, P, half, nc, cinfo, cand, bestn, bestchi, bestidx, combo,
+                   S.combo_cap);
+  for (unsigned c0 = 0; c0 < nc && kUv == 0; c0 += kSeedWG) {
     const unsigned ci = c0 + tid;
     int cnt0 = 0, cnt1 = 0, st0 = 0, st1 = 0;
     if (ci < nc && !(cinfo[ci] & ((1 << 4) | (1 << 5)))) {
@@ -898,6 +1094,7 @@ __device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Sc
 // the queue (or takes item_begin + blockIdx in the plain form) and seeds
 // them; the workgroup that completes the second half of an event then matches
 // that event.  The seeding state and the matching state share the same LDS.
+template <int kUv>
 __global__ __launch_bounds__(kSeedWG, 4) void k_seed(const Desc *__restrict__ D,
                                                      const KCtx *__restrict__ K, int item_begin,
                                                      int item_count, int use_queue, int lds_hits,
@@ -971,10 +1168,10 @@ __global__ __launch_bounds__(kSeedWG, 4) void k_seed(const Desc *__restrict__ D,
         for (int b = kp; b < kc; ++b) sh.bins[L][b] = (unsigned short)li;
       }
       __syncthreads();
-      seed_item<true>(s_x, s_z, hid + base, item, nh, P, S, wg, sh);
+      seed_item<true, kUv>(s_x, s_z, hid + base, item, nh, P, S, wg, sh);
     } else {
       __syncthreads();
-      seed_item<false>(hx + base, hz + base, hid + base, item, nh, P, S, wg, sh);
+      seed_item<false, kUv>(hx + base, hz + base, hid + base, item, nh, P, S, wg, sh);
     }
     // hand-off: this item's pool entries are made visible device-wide before
     // the per-event counter is bumped; the second half's workgroup matches
@@ -1110,9 +1307,13 @@ int smk_launch_prepare(const Desc *d, const KCtx *k, int plain, hipStream_t st) 
   return (int)hipGetLastError();
 }
 int smk_launch_seed(const Desc *d, const KCtx *k, int item_begin, int item_count, int use_queue,
-                    int grid, int lds_hits, int plain, hipStream_t st) {
-  hipLaunchKernelGGL(k_seed, dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits), st, d, k,
-                     item_begin, item_count, use_queue, lds_hits, plain);
+                    int grid, int lds_hits, int plain, int uv_mode, hipStream_t st) {
+  if (uv_mode == 1)
+    hipLaunchKernelGGL(k_seed<1>, dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits), st, d,
+                       k, item_begin, item_count, use_queue, lds_hits, plain);
+  else
+    hipLaunchKernelGGL(k_seed<0>, dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits), st, d,
+                       k, item_begin, item_count, use_queue, lds_hits, plain);
   return (int)hipGetLastError();
 }
 int smk_launch_offsets(const Desc *d, const KCtx *k, hipStream_t st) {

@@ -121,6 +121,19 @@ DevParams make_params(const sm_geometry &g, const sm_params &p) {
   d.tol_tx = p.tol_tx; d.tol_ty = p.tol_ty;
   d.chi2m_max = p.chi2m_max;
   d.polarity = p.polarity;
+  // Hough-cluster UV: t_y range of each half from the lowest nominal stereo z
+  d.uv_mode = p.uv_mode;
+  d.hough_bins = p.hough_bins;
+  d.hough_best = p.hough_best;
+  d.hough_fine = p.hough_fine;
+  d.hough_min = p.hough_min;
+  double zmin = 1e300;
+  for (int l = 0; l < smk::kNL; ++l)
+    if (g.tan_stereo[l] != 0.0) zmin = std::min(zmin, g.z[l]);
+  d.hough_lo[0] = 0.0;
+  d.hough_hi[0] = p.y_max / zmin;
+  d.hough_lo[1] = -p.y_max / zmin;
+  d.hough_hi[1] = 0.0;
   d.invp_a = p.invp_a;
   d.invp_b = p.invp_b;
   // FP32 prefilter of the matching preselection: wider than the FP64 cut by
@@ -134,7 +147,7 @@ DevParams make_params(const sm_geometry &g, const sm_params &p) {
 }
 
 void free_slot_scratch(Slot &s) {
-  for (void *p : s.allocs) hipFree(p);
+  for (void *p : s.allocs) (void)hipFree(p);
   s.allocs.clear();
   if (s.graph_ok) {
     hipGraphExecDestroy(s.gexec);
@@ -283,7 +296,7 @@ sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
   auto seq = [&](hipStream_t q) -> hipError_t {
     int e = smk_launch_prepare(d, S, 0, q);
     if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
-    if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, q);
+    if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
     if (!e) e = smk_launch_offsets(d, S, q);
     if (!e) e = smk_launch_copy(d, S, 1024, q);
     return (hipError_t)e;
@@ -311,7 +324,7 @@ sm_status enqueue_plain(sm_ctx *c, Slot &s, int n_events, hipStream_t st) {
   int e = smk_launch_prepare(d, S, 1, st);
   if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, st);
   for (int ev = 0; ev < n_events && !e; ++ev)
-    e = smk_launch_seed(d, S, 2 * ev, 2, 0, 2, s.lds_hits, 1, st);
+    e = smk_launch_seed(d, S, 2 * ev, 2, 0, 2, s.lds_hits, 1, c->p.uv_mode, st);
   if (!e) e = smk_launch_plain_totals(d, S, st);
   return hip_status((hipError_t)e);
 }
@@ -324,7 +337,7 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   if (!e) e = smk_launch_prepare(d, S, 0, q);
   if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
   if (!e) e = hipEventRecord(ev[1], q);
-  if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, q);
+  if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
   if (!e) e = hipEventRecord(ev[2], q);
   if (!e) e = smk_launch_offsets(d, S, q);
   if (!e) e = hipEventRecord(ev[3], q);
@@ -456,6 +469,11 @@ void sm_default_params(sm_params *p) {
   p->tol_ty = 1.0 / 937.5;
   p->chi2m_max = 2.0;
   p->polarity = 1.0;
+  p->uv_mode = 0;
+  p->hough_bins = 64;
+  p->hough_best = 8;
+  p->hough_fine = 4;
+  p->hough_min = 2;
 }
 
 sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *cfg, sm_ctx **out) {
@@ -468,7 +486,11 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
   if (cfg) c->cfg = *cfg;
   if (c->p.p_min <= 0 || c->p.sigma_x <= 0 || c->p.min_x_hits < 4 || c->p.min_x_hits > 6 ||
       c->p.min_uv_hits < 3 || c->p.min_uv_hits > 6 ||
-      c->p.invp_a * c->p.invp_a + 4.0 * c->p.invp_b / c->p.p_min < 0) {
+      c->p.invp_a * c->p.invp_a + 4.0 * c->p.invp_b / c->p.p_min < 0 ||
+      (c->p.uv_mode != 0 && c->p.uv_mode != 1) ||
+      (c->p.uv_mode == 1 &&
+       (c->p.hough_bins < 1 || c->p.hough_bins > smk::kHoughBins || c->p.hough_best < 1 ||
+        c->p.hough_fine < 1 || c->p.hough_best * c->p.hough_fine > 64 || c->p.hough_min < 1))) {
     delete c;
     return SM_ERR_INVALID;
   }

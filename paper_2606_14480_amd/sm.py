@@ -47,7 +47,9 @@ class Params(C.Structure):
                 ("tolx_scale", C.c_double), ("tolx_a", C.c_double), ("tolx_b", C.c_double),
                 ("toly_scale", C.c_double), ("toly_a", C.c_double), ("toly_b", C.c_double),
                 ("tol_tx", C.c_double), ("tol_ty", C.c_double), ("chi2m_max", C.c_double),
-                ("polarity", C.c_double)]
+                ("polarity", C.c_double), ("uv_mode", C.c_int32), ("hough_bins", C.c_int32),
+                ("hough_best", C.c_int32), ("hough_fine", C.c_int32), ("hough_min", C.c_int32),
+                ("pad2", C.c_int32)]
 
 
 class Config(C.Structure):

@@ -43,7 +43,7 @@ def closest_full_scan(X, lo, hi, pred, tol):
         x = float(X[i])
         if pred - tol <= x <= pred + tol:
             dd = abs(x - pred)
-            if dd < bestd:          # strict: ties keep the lower position
+            if dd < bestd - 1e-6:   # closer by more than 1 nm, else the lower position stays
                 best, bestd = i, dd
     return best
 

@@ -277,3 +277,32 @@ def test_item_hit_limit(sm, ctx):
     b2 = ev.generate(ev.config(1))
     g = gpu_run(sm, ctx, b2)
     assert g[0][-1] > 0
+
+
+@pytest.mark.parametrize("cfgn,n", [(2, 300), (3, 200), (4, 40)])
+def test_hough_uv_parity(orc, sm, cfgn, n):
+    """The Hough-cluster UV variant (Sec. 3.4) against the oracle's."""
+    b = ev.generate(ev.config(cfgn, n_events=n))
+    c = sm.Context(params=sm.default_params(uv_mode=1))
+    try:
+        check(orc, sm, c, b, f"hough uv config {cfgn} x {n}", params_over=dict(uv_mode=1))
+    finally:
+        c.close()
+
+
+def test_hough_uv_deterministic(sm):
+    """Fixed-point fine-bin sums: the same bytes for any grid shape and in the
+    per-event (plain) form."""
+    b = ev.generate(ev.config(3, n_events=60))
+    say("[gpu] hough determinism")
+    p = sm.default_params(uv_mode=1)
+    c1, c2 = sm.Context(params=p), sm.Context(params=p, seed_wgs=5, lds_hits=1024)
+    try:
+        g1 = gpu_run(sm, c1, b)
+        g2 = gpu_run(sm, c2, b)
+        g3 = gpu_run(sm, c1, b, plain=True)
+    finally:
+        c1.close()
+        c2.close()
+    for x, y, z in zip(g1, g2, g3):
+        assert x.tobytes() == y.tobytes() == z.tobytes()

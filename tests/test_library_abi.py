@@ -68,3 +68,16 @@ def test_product_does_not_touch_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 for bad in ("import oracle", "from oracle", "liboracle", "orc_"):
                     assert bad not in txt, (f, bad)
+
+
+def test_create_rejects_bad_uv_settings():
+    """Parameter checks come before any device call, so they run here."""
+    from paper_2606_14480_amd import sm
+    lib = sm.lib()
+    for over in (dict(uv_mode=2), dict(uv_mode=1, hough_bins=0), dict(uv_mode=1, hough_bins=129),
+                 dict(uv_mode=1, hough_best=16, hough_fine=8), dict(uv_mode=1, hough_min=0),
+                 dict(uv_mode=1, hough_fine=0)):
+        p = sm.default_params(**over)
+        h = ctypes.c_void_p()
+        assert lib.sm_create(None, ctypes.byref(p), None, ctypes.byref(h)) == sm.ERR_INVALID, over
+        assert not h.value
