@@ -1173,16 +1173,20 @@ __global__ __launch_bounds__(kSeedWG, 4) void k_seed(const Desc *__restrict__ D,
       __syncthreads();
       seed_item<false, kUv>(hx + base, hz + base, hid + base, item, nh, P, S, wg, sh);
     }
-    // hand-off: this item's pool entries are made visible device-wide before
-    // the per-event counter is bumped; the second half's workgroup matches
-    __threadfence();
+    // hand-off: after the barrier, one release increment of the per-event
+    // count publishes the whole workgroup's writes (barrier synchronisation
+    // and the release compose); the workgroup that completes the event's
+    // second half acquires once and matches.  One L2 write-back per item and
+    // one invalidate per event, instead of a device-wide fence per wave.
     __syncthreads();
-    if (tid == 0) s_last = atomicAdd(&S.ev_done[item >> 1], 1) == 1;
-    __syncthreads();
-    if (s_last) {
-      __threadfence();
-      match_event(D, S, P, item >> 1, plain, wg, mh);
+    if (tid == 0) {
+      const int prev = __hip_atomic_fetch_add(&S.ev_done[item >> 1], 1, __ATOMIC_RELEASE,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+      s_last = prev == 1;
+      if (prev == 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
+    __syncthreads();
+    if (s_last) match_event(D, S, P, item >> 1, plain, wg, mh);
     __syncthreads();
   }
 }
