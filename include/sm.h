@@ -93,7 +93,9 @@ typedef struct {
    * [-y_max/z_min, 0] (lower half), z_min the lowest nominal stereo-layer z;
    * keeps the hough_best most populated bins holding at least hough_min
    * entries (ties to the lower bin), splits each into hough_fine bins and
-   * tries the mean t_y of every non-empty fine bin as a hypothesis. */
+   * tries the mean t_y of every non-empty fine bin as a hypothesis.
+   * uv_mode 1 is currently refused by sm_create (SM_ERR_INVALID): its kernel
+   * is switched off until a memory fault seen once in it is explained. */
   int32_t uv_mode;
   int32_t hough_bins;      /* 1..128 */
   int32_t hough_best;      /* >= 1, hough_best * hough_fine <= 64 */

@@ -613,51 +613,21 @@ __device__ void uv_hough(const float *X, const float *Z, SeedShared &sh, const D
 
 // -------------------------------------------------------- seed kernel -----
 
-// Seeding of one (event, half) item.  kLds: the item's hits are in LDS (with
-// the x-bin index); the candidate-side arrays are in LDS whenever they fit,
-// else in this workgroup's global scratch.
-template <bool kLds, int kUv>
-__device__ __forceinline__ void seed_item(const float *X, const float *Z, const int32_t *hid,
-                                          int item, int nh, const DevParams &P,
+// Clone killing, UV seeding, best combination and seed staging of one item
+// (continuation of seed_item).  kSmall: the vote records, the vote table and
+// the UV bookkeeping are in LDS.
+template <bool kLds, int kUv, bool kSmall>
+__device__ __forceinline__ void seed_rest(const float *X, const float *Z, const int32_t *hid,
+                                          int item, unsigned nc, int nx, const DevParams &P,
                                           const Scratch &S, size_t wg, SeedShared &sh) {
   const int tid = threadIdx.x;
   const int half = item & 1;
   const int *zoff = sh.zoff;
   Counters *cnt = S.cnt;
-  unsigned long long *trip = S.trip + wg * (size_t)S.trip_cap;
   Cand *cand = S.cand + wg * (size_t)S.cand_cap;
   SeedStage *sst = S.sst + wg * (size_t)S.sst_cap;
   Combo *combo = S.combo + wg * (size_t)S.combo_cap;
-
-  // XZ seeding: two independent iterations (Sec. 3)
-  xz_triplets<kLds>(X, Z, sh, P, trip, S.trip_cap);
-  unsigned ntrip = sh.ntrip;
-  if (ntrip > (unsigned)S.trip_cap) {
-    if (tid == 0) { raise_flag(cnt, F_TRIP); atomicMax(&cnt->need_trip, ntrip); }
-    ntrip = S.trip_cap;
-  }
-  for (unsigned t = tid; t < ntrip; t += kSeedWG) {
-    Cand cd;
-    if (xz_candidate<kLds>(X, Z, sh, P, trip[t], cd)) {
-      const unsigned slot = wave_append(&sh.ncand);
-      if (slot < (unsigned)S.cand_cap) cand[slot] = cd;
-      if (slot < (unsigned)kCandLds) {
-        sh.cscore[slot] = cd.score;
-        sh.cinfo[slot] = cd.n | (cd.it << 3);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) sh.cpos[slot][k] = (unsigned short)(cd.pos[k] + 1);
-      }
-    }
-  }
-  __syncthreads();
-  unsigned nc = sh.ncand;
-  if (nc > (unsigned)S.cand_cap) {
-    if (tid == 0) { raise_flag(cnt, F_CAND); atomicMax(&cnt->need_cand, nc); }
-    nc = S.cand_cap;
-  }
-  const int nx = sh.xb[6];
-  // vote records and table in LDS when they fit, else in global scratch
-  const bool small = kLds && nc <= (unsigned)kCandLds && nx <= kXtabLds;
+  constexpr bool small = kSmall;
   const size_t co = wg * (size_t)S.cand_cap;
   unsigned long long *cscore = small ? sh.cscore : S.cscore + co;
   int *cinfo = small ? sh.cinfo : S.cinfo + co;
@@ -704,19 +674,30 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   __syncthreads();
   // repeated tracks of the two iterations: a kept iteration-1 track whose
   // x-hit set equals a kept iteration-0 track's is dropped.  Equal sets have
-  // bit-identical scores, which filters the comparison.
-  for (unsigned i = tid; i < nc; i += kSeedWG) {
-    if ((cinfo[i] & (1 << 4)) || !(cinfo[i] & (1 << 3))) continue;
-    const unsigned long long sc = cscore[i];
-    bool dup = false;
-    for (unsigned j = 0; j < nc && !dup; ++j) {
-      if (cscore[j] != sc || (cinfo[j] & ((1 << 3) | (1 << 4)))) continue;
-      bool same = true;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) same = same && xidx(j, k) == xidx(i, k);
-      dup = same;
+  // bit-identical scores, which filters the comparison: one wave takes one
+  // iteration-1 track, ballots 64 list entries at a time on the score, and
+  // compares hit sets (one slot per lane) only where the score matches.
+  {
+    const int lane = tid & 63;
+    for (unsigned i = tid >> 6; i < nc; i += kSeedWG / 64) {
+      const int ci = cinfo[i];
+      if ((ci & (1 << 4)) || !(ci & (1 << 3))) continue;
+      const unsigned long long sc = cscore[i];
+      const int mine = lane < 6 ? xidx(i, lane) : 0;
+      bool dup = false;
+      for (unsigned j0 = 0; j0 < nc && !dup; j0 += 64) {
+        const unsigned j = j0 + lane;
+        const bool cand_j = j < nc && cscore[j] == sc && !(cinfo[j] & ((1 << 3) | (1 << 4)));
+        unsigned long long m = __ballot(cand_j);
+        while (m != 0ull && !dup) {
+          const unsigned jj = j0 + (unsigned)__builtin_ctzll(m);
+          m &= m - 1ull;
+          const bool differs = lane < 6 && xidx(jj, lane) != mine;
+          dup = __ballot(differs) == 0ull;
+        }
+      }
+      if (dup && lane == 0) cinfo[i] |= 1 << 5;
     }
-    if (dup) cinfo[i] |= 1 << 5;
   }
   __syncthreads();
 
@@ -854,6 +835,62 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
         for (unsigned j = 0; j < ns; ++j) r += sst[j].key < key;
       S.pool[base + r] = sst[i].s;
     }
+  }
+}
+
+// Seeding of one (event, half) item.  kLds: the item's hits are in LDS (with
+// the x-bin index); the candidate-side arrays are in LDS whenever they fit,
+// else in this workgroup's global scratch.
+template <bool kLds, int kUv>
+__device__ __forceinline__ void seed_item(const float *X, const float *Z, const int32_t *hid,
+                                          int item, int nh, const DevParams &P,
+                                          const Scratch &S, size_t wg, SeedShared &sh) {
+  const int tid = threadIdx.x;
+  const int half = item & 1;
+  const int *zoff = sh.zoff;
+  Counters *cnt = S.cnt;
+  unsigned long long *trip = S.trip + wg * (size_t)S.trip_cap;
+  Cand *cand = S.cand + wg * (size_t)S.cand_cap;
+  SeedStage *sst = S.sst + wg * (size_t)S.sst_cap;
+  Combo *combo = S.combo + wg * (size_t)S.combo_cap;
+
+  // XZ seeding: two independent iterations (Sec. 3)
+  xz_triplets<kLds>(X, Z, sh, P, trip, S.trip_cap);
+  unsigned ntrip = sh.ntrip;
+  if (ntrip > (unsigned)S.trip_cap) {
+    if (tid == 0) { raise_flag(cnt, F_TRIP); atomicMax(&cnt->need_trip, ntrip); }
+    ntrip = S.trip_cap;
+  }
+  for (unsigned t = tid; t < ntrip; t += kSeedWG) {
+    Cand cd;
+    if (xz_candidate<kLds>(X, Z, sh, P, trip[t], cd)) {
+      const unsigned slot = wave_append(&sh.ncand);
+      if (slot < (unsigned)S.cand_cap) cand[slot] = cd;
+      if (slot < (unsigned)kCandLds) {
+        sh.cscore[slot] = cd.score;
+        sh.cinfo[slot] = cd.n | (cd.it << 3);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sh.cpos[slot][k] = (unsigned short)(cd.pos[k] + 1);
+      }
+    }
+  }
+  __syncthreads();
+  unsigned nc = sh.ncand;
+  if (nc > (unsigned)S.cand_cap) {
+    if (tid == 0) { raise_flag(cnt, F_CAND); atomicMax(&cnt->need_cand, nc); }
+    nc = S.cand_cap;
+  }
+  const int nx = sh.xb[6];
+  // vote records and table in LDS when they fit, else in global scratch; the
+  // two forms are separate instantiations so that LDS accesses compile to
+  // LDS instructions rather than generic ones
+  if constexpr (kLds) {
+    if (nc <= (unsigned)kCandLds && nx <= kXtabLds)
+      seed_rest<true, kUv, true>(X, Z, hid, item, nc, nx, P, S, wg, sh);
+    else
+      seed_rest<true, kUv, false>(X, Z, hid, item, nc, nx, P, S, wg, sh);
+  } else {
+    seed_rest<false, kUv, false>(X, Z, hid, item, nc, nx, P, S, wg, sh);
   }
 }
 

@@ -279,6 +279,12 @@ def test_item_hit_limit(sm, ctx):
     assert g[0][-1] > 0
 
 
+HOUGH_OFF = ("the Hough-cluster UV kernel is switched off in sm_create: one run of "
+             "test_hough_uv_deterministic (5-workgroup context) ended in a GPU memory "
+             "aperture fault whose cause is not found yet")
+
+
+@pytest.mark.skip(reason=HOUGH_OFF)
 @pytest.mark.parametrize("cfgn,n", [(2, 300), (3, 200), (4, 40)])
 def test_hough_uv_parity(orc, sm, cfgn, n):
     """The Hough-cluster UV variant (Sec. 3.4) against the oracle's."""
@@ -290,6 +296,7 @@ def test_hough_uv_parity(orc, sm, cfgn, n):
         c.close()
 
 
+@pytest.mark.skip(reason=HOUGH_OFF)
 def test_hough_uv_deterministic(sm):
     """Fixed-point fine-bin sums: the same bytes for any grid shape and in the
     per-event (plain) form."""
@@ -306,3 +313,10 @@ def test_hough_uv_deterministic(sm):
         c2.close()
     for x, y, z in zip(g1, g2, g3):
         assert x.tobytes() == y.tobytes() == z.tobytes()
+
+
+def test_hough_uv_refused(sm):
+    """While its kernel is switched off, uv_mode 1 is refused up front."""
+    with pytest.raises(sm.SmError) as e:
+        sm.Context(params=sm.default_params(uv_mode=1))
+    assert e.value.status == sm.ERR_INVALID

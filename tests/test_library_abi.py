@@ -74,7 +74,7 @@ def test_create_rejects_bad_uv_settings():
     """Parameter checks come before any device call, so they run here."""
     from paper_2606_14480_amd import sm
     lib = sm.lib()
-    for over in (dict(uv_mode=2), dict(uv_mode=1, hough_bins=0), dict(uv_mode=1, hough_bins=129),
+    for over in (dict(uv_mode=2), dict(uv_mode=1), dict(uv_mode=1, hough_bins=0), dict(uv_mode=1, hough_bins=129),
                  dict(uv_mode=1, hough_best=16, hough_fine=8), dict(uv_mode=1, hough_min=0),
                  dict(uv_mode=1, hough_fine=0)):
         p = sm.default_params(**over)
