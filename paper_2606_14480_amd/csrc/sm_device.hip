@@ -72,6 +72,26 @@ __device__ __forceinline__ int lower_f(const float *X, int lo, int hi, float v) 
   return lo;
 }
 
+// Rank of value v among a[0..n): entries below v plus equal entries before
+// position self.  Loads are issued eight at a time so that their latencies
+// overlap (every lane reads the same a[j]: an LDS broadcast).
+template <class T>
+__device__ __forceinline__ unsigned rank_of(const T *a, unsigned n, T v, unsigned self) {
+  unsigned r = 0, j = 0;
+  for (; j + 8 <= n; j += 8) {
+    T u[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] = a[j + q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r += (u[q] < v) | ((u[q] == v) & (j + q < self));
+  }
+  for (; j < n; ++j) {
+    const T u = a[j];
+    r += (u < v) | ((u == v) & (j < self));
+  }
+  return r;
+}
+
 __device__ __forceinline__ void raise_flag(Counters *c, unsigned f) { atomicOr(&c->flags, f); }
 
 // Least-squares fit of eq. trackequation over the x-layer hits present in
@@ -395,6 +415,28 @@ __device__ __forceinline__ bool uv_combo(const float *X, const float *Z, const S
   return true;
 }
 
+
+// Selection keys of the first kComboLds combinations of an item, kept in LDS
+// regions the vote no longer needs: chi2 bits in cscore, (track, hits,
+// order) in cpos viewed as three int arrays.
+constexpr int kComboLds = kCandLds;
+__device__ __forceinline__ int *combo_keys(SeedShared &sh) {
+  return reinterpret_cast<int *>(&sh.cpos[0][0]);
+}
+__device__ __forceinline__ void push_combo(SeedShared &sh, Combo *combo, int cap, const Combo &r) {
+  const unsigned slot = wave_append(&sh.ncombo);
+  if (slot < (unsigned)cap) combo[slot] = r;
+  if (slot < (unsigned)kComboLds) {
+    int *ck = combo_keys(sh);
+    sh.cscore[slot] = (unsigned long long)__double_as_longlong(r.chi2);
+    ck[slot] = r.c;
+    ck[kComboLds + slot] = r.n;
+    ck[2 * kComboLds + slot] = r.tb;
+  }
+}
+static_assert(sizeof(unsigned short) * kCandLds * 6 >= sizeof(int) * 3 * kComboLds,
+              "combination keys must fit the candidate position area");
+
 // ------------------------------------------------ Hough-cluster UV ------
 
 // Per-wave LDS of the Hough-cluster UV search (one x-z track per wave).
@@ -602,8 +644,7 @@ __device__ void uv_hough(const float *X, const float *Z, SeedShared &sh, const D
       if (kn > 0 && lane == kh) {
         r.c = (int)ci;
         r.tb = lane;
-        const unsigned slot = atomicAdd(&sh.ncombo, 1u);
-        if (slot < (unsigned)combo_cap) combo[slot] = r;
+        push_combo(sh, combo, combo_cap, r);
         bestn[ci] = r.n;
       }
     }
@@ -760,8 +801,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
       if (!uv_combo<kLds>(X, Z, sh, P, a, b, cc, 1 + pass, h0, r)) continue;
       r.c = c;
       r.tb = (pass << 24) | (h0 - zoff[1 + pass]);
-      const unsigned slot = wave_append(&sh.ncombo);
-      if (slot < (unsigned)S.combo_cap) combo[slot] = r;
+      push_combo(sh, combo, S.combo_cap, r);
       atomicMax(&bestn[c], r.n);
     }
     __syncthreads();
@@ -773,24 +813,30 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   }
   // best combination per track: most hits, then lowest chi2_y, then the
   // earlier (pass, initial hit)
+  const int *ck = combo_keys(sh);
+  auto key_c = [&](unsigned i) { return i < (unsigned)kComboLds ? ck[i] : combo[i].c; };
+  auto key_n = [&](unsigned i) { return i < (unsigned)kComboLds ? ck[kComboLds + i] : combo[i].n; };
+  auto key_tb = [&](unsigned i) {
+    return i < (unsigned)kComboLds ? ck[2 * kComboLds + i] : combo[i].tb;
+  };
+  auto key_chi = [&](unsigned i) {
+    return i < (unsigned)kComboLds ? sh.cscore[i]
+                                   : (unsigned long long)__double_as_longlong(combo[i].chi2);
+  };
   for (unsigned i = tid; i < ncb; i += kSeedWG) {
-    const int c = combo[i].c;
-    if (combo[i].n == bestn[c])
-      atomicMin(&bestchi[c], (unsigned long long)__double_as_longlong(combo[i].chi2));
+    const int c = key_c(i);
+    if (key_n(i) == bestn[c]) atomicMin(&bestchi[c], key_chi(i));
   }
   __syncthreads();
   for (unsigned i = tid; i < ncb; i += kSeedWG) {
-    const int c = combo[i].c;
-    if (combo[i].n == bestn[c] &&
-        (unsigned long long)__double_as_longlong(combo[i].chi2) == bestchi[c])
-      atomicMin(&bestidx[c], combo[i].tb);
+    const int c = key_c(i);
+    if (key_n(i) == bestn[c] && key_chi(i) == bestchi[c]) atomicMin(&bestidx[c], key_tb(i));
   }
   __syncthreads();
   for (unsigned i = tid; i < ncb; i += kSeedWG) {
+    const int c = key_c(i);
+    if (key_n(i) != bestn[c] || key_tb(i) != bestidx[c] || key_chi(i) != bestchi[c]) continue;
     const Combo r = combo[i];
-    if (r.n != bestn[r.c] || r.tb != bestidx[r.c] ||
-        (unsigned long long)__double_as_longlong(r.chi2) != bestchi[r.c])
-      continue;
     const Cand &cd = cand[r.c];
     SeedStage st;
     st.key = cd.key;
@@ -830,7 +876,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
       const unsigned long long key = lds_keys ? sh.u.skey[i] : sst[i].key;
       unsigned r = 0;
       if (lds_keys)
-        for (unsigned j = 0; j < ns; ++j) r += sh.u.skey[j] < key;
+        r = rank_of(sh.u.skey, ns, key, i);
       else
         for (unsigned j = 0; j < ns; ++j) r += sst[j].key < key;
       S.pool[base + r] = sst[i].s;
@@ -982,9 +1028,12 @@ __global__ __launch_bounds__(256) void k_validate(const Desc *__restrict__ D, co
 // second half of the event.  plain: outputs go straight to the caller's
 // buffers at offsets chained from the previous event; batched: long tracks go
 // to the pool and the seeds stay in theirs until the offsets are known.
-__device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Scratch &S,
-                                            const DevParams &P, int e, int plain, size_t wg,
-                                            MatchShared &sh) {
+// kSmallM: the event's seeds and VELO states fit the LDS arrays, which the
+// instantiation then addresses as LDS (not through generic pointers).
+template <bool kSmallM>
+__device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, const Scratch &S,
+                                                 const DevParams &P, int e, int plain, size_t wg,
+                                                 MatchShared &sh) {
   const int tid = threadIdx.x;
   MState *ms = S.ms + wg * (size_t)S.ms_cap;
   float *mf = S.mf + wg * (size_t)S.ms_cap * 6;
@@ -1007,7 +1056,7 @@ __device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Sc
   }
   // per-seed arrays in LDS, or in this workgroup's global scratch for events
   // with many seeds / VELO states
-  const bool sm_s = ns <= kMsLds, sm_v = nv <= kVsLds;
+  const bool sm_s = kSmallM || ns <= kMsLds, sm_v = kSmallM || nv <= kVsLds;
   float *xsf = sm_s ? sh.xsf : mf, *txsf = sm_s ? sh.txsf : mf + S.ms_cap;
   float *ymf = sm_s ? sh.ymf : mf + 2 * (size_t)S.ms_cap;
   float *tyf = sm_s ? sh.tyf : mf + 3 * (size_t)S.ms_cap;
@@ -1031,11 +1080,7 @@ __device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Sc
   if (fits) {
     for (int i = tid; i < ns; i += kSeedWG) {
       const float t = tyf[i];
-      int r = 0;
-      for (int j = 0; j < ns; ++j) {
-        const float u = tyf[j];
-        r += (u < t) || (u == t && j < i);
-      }
+      const int r = (int)rank_of(tyf, (unsigned)ns, t, (unsigned)i);
       sty[r] = t;
       sidx[r] = i;
     }
@@ -1109,8 +1154,7 @@ __device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Sc
   sm_long *dst = plain ? D->longs : S.lpool;
   for (unsigned i = tid; i < nk; i += kSeedWG) {
     const unsigned long long key = kkey[i];
-    unsigned r = 0;
-    for (unsigned j = 0; j < nk; ++j) r += kkey[j] < key;
+    const unsigned r = rank_of(kkey, nk, key, i);
     if ((long long)(lb + r) >= cap) continue;
     const int vi = (int)(key >> 32), si = (int)(key & 0xffffffffu);
     const int v = v0 + vi;
@@ -1126,6 +1170,17 @@ __device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Sc
 }
 
 // ----------------------------------------------------- the fused kernel ----
+
+__device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Scratch &S,
+                                            const DevParams &P, int e, int plain, size_t wg,
+                                            MatchShared &sh) {
+  const int ns = S.item_cnt[2 * e] + S.item_cnt[2 * e + 1];
+  const int nv = D->b.velo_off[e + 1] - D->b.velo_off[e];
+  if (ns <= kMsLds && nv <= kVsLds)
+    match_event_impl<true>(D, S, P, e, plain, wg, sh);
+  else
+    match_event_impl<false>(D, S, P, e, plain, wg, sh);
+}
 
 // Persistent Seeding + Matching: each workgroup pulls (event, half) items from
 // the queue (or takes item_begin + blockIdx in the plain form) and seeds
@@ -1196,9 +1251,13 @@ __global__ __launch_bounds__(kSeedWG, 4) void k_seed(const Desc *__restrict__ D,
       }
       __syncthreads();
       // hit i opens the bins in (kbin(previous hit), kbin(hit i)]
+      int zb[kNL];
+#pragma unroll
+      for (int k = 0; k < kNL; ++k) zb[k] = sh.zoff[k + 1];
       for (int i = tid; i < nh; i += kSeedWG) {
         int L = 0;
-        while (sh.zoff[L + 1] <= i) ++L;
+#pragma unroll
+        for (int k = 0; k < kNL - 1; ++k) L += i >= zb[k];
         const int li = i - sh.zoff[L];
         const int kc = kbin(s_x[i]);
         const int kp = li > 0 ? kbin(s_x[i - 1]) : 0;
