@@ -259,12 +259,32 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_seed (seeding + matching)", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": None, "alg_bytes_per_launch": alg_bytes},
+                     "traffic": measured_traffic(), "alg_bytes_per_launch": alg_bytes},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(host, args.cpu_seconds)
     ctx.close()
     print(json.dumps(res), flush=True)
+
+
+def measured_traffic():
+    """HBM bytes of one k_seed launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None
+    when the kernel sources differ from the ones the counters were taken on."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_seed_minbias1000_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    for name in ("sm_device.hip", "sm_device.h"):
+        src = os.path.join(ROOT, "paper_2606_14480_amd", "csrc", name)
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if not re.search(re.escape(name) + r"` sha256\s*`" + digest + "`", text):
+            return None
+    f = re.search(r"^fetch_bytes_per_launch: (\d+)$", text, re.M)
+    w = re.search(r"^write_bytes_per_launch: (\d+)$", text, re.M)
+    return int(f.group(1)) + int(w.group(1)) if f and w else None
 
 
 if __name__ == "__main__":
