@@ -13,12 +13,14 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+SERVE_SLOTS = 4   # serving slots: uploads, kernels and result copies of different requests overlap
 sys.path.insert(0, ROOT)
 sys.path.insert(0, os.path.join(ROOT, "tests"))
 
@@ -92,10 +94,12 @@ def serve_stream(ctx, sm, host, capacity, n_req, load):
     me = max(r.batch.n_events for r in reqs)
     mh = max(r.batch.n_hits for r in reqs)
     mv = max(r.batch.n_velo for r in reqs)
-    srv = serving.Server(ctx, 2, me, mh, mv)
-    srv.serve(reqs[:3])                                     # warm the slots
+    srv = serving.Server(ctx, SERVE_SLOTS, me, mh, mv)
+    # warm the slots, scratch and captured graphs with the largest request first
+    big = max(reqs, key=lambda r: r.batch.n_hits)
+    srv.serve([dataclasses.replace(big, arrival=0.0)] + [dataclasses.replace(r, arrival=0.0) for r in reqs[:3]])
     t0 = time.perf_counter()
-    res = srv.serve(reqs)
+    res = srv.serve(reqs, keep=False)
     wall = time.perf_counter() - t0
     s = serving.summarize(res, wall)
     out = {"requests": n_req, "events_per_request": "uniform 1-%d" % host.n_events,
@@ -103,7 +107,7 @@ def serve_stream(ctx, sm, host, capacity, n_req, load):
            "events_per_s": round(s["events_per_s"], 1),
            "latency_ms_p50": round(s["latency_ms_p50"], 3),
            "latency_ms_p99": round(s["latency_ms_p99"], 3),
-           "what": "arrival to results on the host, incl. H2D of the request and D2H of results"}
+           "what": "arrival to results in pinned host memory, incl. H2D of the request and D2H of results"}
     n_plain = min(n_req, 12)
     t0 = time.perf_counter()
     pres = serving.serve_plain(ctx, reqs[:n_plain], me, mh, mv)
@@ -155,7 +159,7 @@ def main():
     host = ev.generate(cfg)
     log(f"[bench] generated {host.n_events} events, {host.n_hits} hits, {host.n_velo} VELO "
         f"states in {time.perf_counter() - t0:.1f} s")
-    ctx = sm.Context()
+    ctx = sm.Context(n_slots=SERVE_SLOTS)
     db = sm.DeviceBatch(host)
     out = sm.DeviceOut(host.n_events, host.n_hits // 4 + 1024, host.n_velo + 1024)
     stream = torch.cuda.current_stream()

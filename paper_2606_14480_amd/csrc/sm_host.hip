@@ -39,9 +39,15 @@ struct Slot {
   Counters *h_cnt = nullptr;  // pinned
   Scratch S{};
   Caps caps;
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
-  bool graph_ok = false;
+  // captured batched sequence, one per LDS hit capacity used so far; kernel
+  // arguments are the slot's fixed descriptor and context pointers, so a
+  // graph stays valid when scratch is reallocated
+  struct Captured {
+    int lds_hits;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<Captured> graphs;
   int lds_hits = 2048;  // LDS hit capacity of the seeding workgroup for this batch
   hipEvent_t done = nullptr;
   // serving state
@@ -149,11 +155,14 @@ DevParams make_params(const sm_geometry &g, const sm_params &p) {
 void free_slot_scratch(Slot &s) {
   for (void *p : s.allocs) (void)hipFree(p);
   s.allocs.clear();
-  if (s.graph_ok) {
-    hipGraphExecDestroy(s.gexec);
-    hipGraphDestroy(s.graph);
-    s.graph_ok = false;
+}
+
+void destroy_graphs(Slot &s) {
+  for (Slot::Captured &g : s.graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
   }
+  s.graphs.clear();
 }
 
 template <class T>
@@ -250,14 +259,7 @@ sm_status fit_batch(sm_ctx *c, Slot &s, const sm_batch &b) {
     h = 256 * (int)std::ceil(1.5 * mean / 256.0);
     h = std::max(1024, std::min(h, 4096));
   }
-  if (h != s.lds_hits) {
-    s.lds_hits = h;
-    if (s.graph_ok) {
-      hipGraphExecDestroy(s.gexec);
-      hipGraphDestroy(s.graph);
-      s.graph_ok = false;
-    }
-  }
+  s.lds_hits = h;
   if (!re && !s.allocs.empty()) return SM_OK;
   return alloc_slot(c, s);
 }
@@ -301,21 +303,25 @@ sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
     if (!e) e = smk_launch_copy(d, S, 1024, q);
     return (hipError_t)e;
   };
-  if (!s.graph_ok) {
-    hipStream_t cap;
-    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return SM_ERR_DEVICE;
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
-    if (e == hipSuccess) {
-      hipError_t e2 = seq(cap);
-      e = hipStreamEndCapture(cap, &s.graph);
-      if (e == hipSuccess && e2 != hipSuccess) e = e2;
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&s.gexec, s.graph, nullptr, nullptr, 0);
-    hipStreamDestroy(cap);
-    if (e != hipSuccess) return SM_ERR_DEVICE;
-    s.graph_ok = true;
+  for (const Slot::Captured &g : s.graphs)
+    if (g.lds_hits == s.lds_hits) return hip_status(hipGraphLaunch(g.exec, st));
+  hipStream_t cap;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return SM_ERR_DEVICE;
+  Slot::Captured g{s.lds_hits, nullptr, nullptr};
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    hipError_t e2 = seq(cap);
+    e = hipStreamEndCapture(cap, &g.graph);
+    if (e == hipSuccess && e2 != hipSuccess) e = e2;
   }
-  return hip_status(hipGraphLaunch(s.gexec, st));
+  if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) {
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    return SM_ERR_DEVICE;
+  }
+  s.graphs.push_back(g);
+  return hip_status(hipGraphLaunch(g.exec, st));
 }
 
 sm_status enqueue_plain(sm_ctx *c, Slot &s, int n_events, hipStream_t st) {
@@ -625,8 +631,9 @@ sm_status sm_destroy(sm_ctx *ctx) {
   if (!ctx) return SM_ERR_INVALID;
   hipSetDevice(ctx->device);
   for (Slot &s : ctx->slots) {
-    if (s.stream) hipStreamSynchronize(s.stream);
+    if (s.stream) (void)hipStreamSynchronize(s.stream);
     free_slot_scratch(s);
+    destroy_graphs(s);
     if (s.done) hipEventDestroy(s.done);
     if (s.stream) hipStreamDestroy(s.stream);
     if (s.d_desc) hipFree(s.d_desc);

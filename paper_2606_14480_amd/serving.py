@@ -20,20 +20,45 @@ import numpy as np
 
 _FIELDS = ("zone_off", "hit_x", "hit_z", "hit_id", "velo_off", "velo_id", "velo_x", "velo_y",
            "velo_z", "velo_tx", "velo_ty")
+_ALIGN = 256
 
 
-def pin(batch) -> dict:
-    """The batch's arrays in pinned host memory (where a trigger's network
-    receive would leave them), ready for an asynchronous DMA."""
-    import torch
-    out = {}
+def layout(n_events: int, n_hits: int, n_velo: int):
+    """Byte offsets of every input array of a batch packed into one buffer
+    (each array 256-byte aligned), and the total size."""
+    counts = {"zone_off": n_events * 24 + 1, "hit_x": n_hits, "hit_z": n_hits, "hit_id": n_hits,
+              "velo_off": n_events + 1, "velo_id": n_velo, "velo_x": n_velo, "velo_y": n_velo,
+              "velo_z": n_velo, "velo_tx": n_velo, "velo_ty": n_velo}
+    off, pos = {}, 0
+    for f in _FIELDS:
+        off[f] = (pos, counts[f])
+        pos += -(-counts[f] * 4 // _ALIGN) * _ALIGN
+    return off, max(pos, _ALIGN)
+
+
+@dataclasses.dataclass
+class Packed:
+    """A batch packed into one pinned host buffer (where a trigger's network
+    receive would leave it), ready for a single asynchronous DMA."""
+    buf: object            # torch uint8 tensor, pinned
+    offsets: dict
+    nbytes: int
+
+
+def _pack_into(batch, host_u8: np.ndarray, offsets: dict):
     for f in _FIELDS:
         a = np.ascontiguousarray(getattr(batch, f))
-        t = torch.empty(len(a), dtype=torch.from_numpy(a[:0]).dtype, pin_memory=True)
-        if len(a):
-            t.numpy()[:] = a
-        out[f] = t
-    return out
+        o, n = offsets[f]
+        if n:
+            host_u8[o:o + 4 * n] = a.view(np.uint8)
+
+
+def pin(batch) -> Packed:
+    import torch
+    offsets, nbytes = layout(batch.n_events, batch.n_hits, batch.n_velo)
+    t = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    _pack_into(batch, t.numpy(), offsets)
+    return Packed(t, offsets, nbytes)
 
 
 @dataclasses.dataclass
@@ -41,7 +66,7 @@ class Request:
     rid: int
     batch: object          # events.Batch (host)
     arrival: float         # seconds from the start of the run
-    pinned: dict | None = None
+    pinned: Packed | None = None
 
 
 @dataclasses.dataclass
@@ -67,66 +92,86 @@ def poisson_arrivals(rate_hz: float, n: int, seed: int = 7) -> np.ndarray:
 
 
 class SlotBuffers:
-    """Resident device buffers of one serving slot (torch tensors)."""
+    """Resident buffers of one serving slot: one device input arena, the
+    device outputs, and pinned host staging for inputs and results."""
 
     def __init__(self, max_events: int, max_hits: int, max_velo: int, device="cuda"):
         import torch
         from . import sm
-        f32, i32 = torch.float32, torch.int32
         self.cap = (max_events, max_hits, max_velo)
-        z = lambda n, dt: torch.zeros(max(n, 1), dtype=dt, device=device)
-        self.zone_off = z(max_events * 24 + 1, i32)
-        self.hit_x, self.hit_z, self.hit_id = z(max_hits, f32), z(max_hits, f32), z(max_hits, i32)
-        self.velo_off = z(max_events + 1, i32)
-        self.velo = {k: z(max_velo, f32) for k in ("x", "y", "z", "tx", "ty")}
-        self.velo_id = z(max_velo, i32)
-        self.out = sm.DeviceOut(max_events, max_hits // 4 + 1024, max_velo + 1024, device)
+        _, nbytes = layout(max_events, max_hits, max_velo)
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.staging = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        seed_cap, long_cap = max_hits // 4 + 1024, max_velo + 1024
+        self.out = sm.DeviceOut(max_events, seed_cap, long_cap, device)
+        self.h_seed_off = torch.empty(max_events + 1, dtype=torch.int32, pin_memory=True)
+        self.h_long_off = torch.empty(max_events + 1, dtype=torch.int32, pin_memory=True)
+        self.h_seeds = torch.empty(self.out.seeds.numel(), dtype=torch.uint8, pin_memory=True)
+        self.h_longs = torch.empty(self.out.longs.numel(), dtype=torch.uint8, pin_memory=True)
         self.c = sm.Batch()
-        # pinned host staging, one buffer per device array
-        self.pinned = {}
-        for name, t in self._arrays().items():
-            self.pinned[name] = torch.empty(t.numel(), dtype=t.dtype, pin_memory=True)
-
-    def _arrays(self):
-        d = {"zone_off": self.zone_off, "hit_x": self.hit_x, "hit_z": self.hit_z,
-             "hit_id": self.hit_id, "velo_off": self.velo_off, "velo_id": self.velo_id}
-        d.update({"velo_" + k: v for k, v in self.velo.items()})
-        return d
+        self.n_events = 0
+        self.fetched = None
 
     def bytes(self) -> int:
-        e, h, v = self.cap
-        return (e * 24 + 1) * 4 + h * 12 + (e + 1) * 4 + v * 24 + \
-            self.out.seeds.numel() + self.out.longs.numel() + 2 * (e + 1) * 4
+        return self.arena.numel() + self.out.seeds.numel() + self.out.longs.numel() + \
+            2 * 4 * (self.cap[0] + 1)
 
-    def load(self, b, stream, pinned: dict | None = None):
-        """Copy a host batch into the resident buffers on `stream` (straight
-        from `pinned` when the request arrived in pinned memory)."""
+    def load(self, b, stream, packed: Packed | None = None):
+        """Copy a host batch into the arena on `stream` with one DMA (straight
+        from `packed` when the request arrived packed in pinned memory)."""
         import torch
         from . import sm
         e, h, v = b.n_events, b.n_hits, b.n_velo
         if e > self.cap[0] or h > self.cap[1] or v > self.cap[2]:
             raise ValueError("request larger than the slot buffers")
-        dev = self._arrays()
+        if packed is None:
+            offsets, nbytes = layout(e, h, v)
+            _pack_into(b, self.staging.numpy(), offsets)
+            src = self.staging[:nbytes]
+        else:
+            offsets, nbytes, src = packed.offsets, packed.nbytes, packed.buf
         with torch.cuda.stream(stream):
-            for name in _FIELDS:
-                a = getattr(b, name)
-                n = len(a)
-                if not n:
-                    continue
-                if pinned is not None:
-                    src = pinned[name]
-                else:
-                    src = self.pinned[name][:n]
-                    src.numpy()[:] = a
-                dev[name][:n].copy_(src, non_blocking=True)
-        self.c = sm.Batch(n_events=e, pad=0, n_hits=h, n_velo=v,
-                          zone_off=self.zone_off.data_ptr(), hit_x=self.hit_x.data_ptr(),
-                          hit_z=self.hit_z.data_ptr(), hit_id=self.hit_id.data_ptr(),
-                          velo_off=self.velo_off.data_ptr(), velo_x=self.velo["x"].data_ptr(),
-                          velo_y=self.velo["y"].data_ptr(), velo_z=self.velo["z"].data_ptr(),
-                          velo_tx=self.velo["tx"].data_ptr(), velo_ty=self.velo["ty"].data_ptr(),
-                          velo_id=self.velo_id.data_ptr())
+            self.arena[:nbytes].copy_(src, non_blocking=True)
+        base = self.arena.data_ptr()
+        ptr = {f: base + offsets[f][0] for f in _FIELDS}
+        self.c = sm.Batch(n_events=e, pad=0, n_hits=h, n_velo=v, zone_off=ptr["zone_off"],
+                          hit_x=ptr["hit_x"], hit_z=ptr["hit_z"], hit_id=ptr["hit_id"],
+                          velo_off=ptr["velo_off"], velo_x=ptr["velo_x"], velo_y=ptr["velo_y"],
+                          velo_z=ptr["velo_z"], velo_tx=ptr["velo_tx"], velo_ty=ptr["velo_ty"],
+                          velo_id=ptr["velo_id"])
+        self.n_events = e
         self.out.n_events = e
+
+    def fetch(self, stream):
+        """Start the copy of this slot's results into pinned host memory on
+        `stream`; returns an event that completes with it."""
+        import torch
+        from . import sm
+        e = self.n_events
+        ns, nl = self.out.n_seeds, self.out.n_longs
+        with torch.cuda.stream(stream):
+            self.h_seed_off[:e + 1].copy_(self.out.seed_off[:e + 1], non_blocking=True)
+            self.h_long_off[:e + 1].copy_(self.out.long_off[:e + 1], non_blocking=True)
+            if ns:
+                nb = ns * sm.SEED_DTYPE.itemsize
+                self.h_seeds[:nb].copy_(self.out.seeds[:nb], non_blocking=True)
+            if nl:
+                nb = nl * sm.LONG_DTYPE.itemsize
+                self.h_longs[:nb].copy_(self.out.longs[:nb], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        self.fetched = (e, ns, nl)
+        return ev
+
+    def collect(self):
+        """Host copies of the fetched results (after the fetch event)."""
+        from . import sm
+        e, ns, nl = self.fetched
+        so = self.h_seed_off.numpy()[:e + 1].copy()
+        lo = self.h_long_off.numpy()[:e + 1].copy()
+        seeds = self.h_seeds.numpy()[:ns * sm.SEED_DTYPE.itemsize].copy().view(sm.SEED_DTYPE)
+        longs = self.h_longs.numpy()[:nl * sm.LONG_DTYPE.itemsize].copy().view(sm.LONG_DTYPE)
+        return so, seeds, lo, longs
 
 
 class Server:
@@ -139,6 +184,7 @@ class Server:
         self.slots = [SlotBuffers(max_events, max_hits, max_velo) for _ in range(n_slots)]
         self.free = collections.deque(range(n_slots))
         self.copy_stream = torch.cuda.Stream()
+        self.fetch_stream = torch.cuda.Stream()
         self.mem_budget = mem_budget
         self.in_use = 0
         self.peak_in_use = 0
@@ -146,41 +192,59 @@ class Server:
     def _needs(self, b) -> int:
         return self.ctx.batch_bytes(b.n_events, b.n_hits, b.n_velo)
 
-    def serve(self, requests: list, clock=time.perf_counter) -> list:
-        """Serve requests (sorted by arrival); returns Results in completion order."""
+    def serve(self, requests: list, clock=time.perf_counter, keep: bool = True) -> list:
+        """Serve requests (sorted by arrival); returns Results in completion
+        order.  A request's slot is busy from admission until its results are
+        in pinned host memory: upload, kernels, then the result copy, each
+        stream-ordered and each polled, so the loop never blocks on one
+        request while others can make progress.  keep=False leaves the
+        results in the slot's pinned buffers (a consumer would read them
+        there) and returns only their sizes."""
         import torch
         from . import sm
         pending = collections.deque(requests)
-        inflight = {}   # ticket -> (slot, request, admitted)
+        uploading = []  # (event, slot, request, admitted, need)
+        inflight = {}   # ticket -> (slot, request, admitted, need)
+        draining = []   # (event, slot, request, admitted, need)
         done = []
         t0 = clock()
-        while pending or inflight:
+        while pending or uploading or inflight or draining:
             now = clock() - t0
+            busy = uploading or inflight or draining
             # admit every arrived request that finds a free slot and memory
             while pending and pending[0].arrival <= now and self.free:
                 req = pending[0]
                 need = self._needs(req.batch)
-                if self.mem_budget is not None and self.in_use + need > self.mem_budget and inflight:
+                if self.mem_budget is not None and self.in_use + need > self.mem_budget and busy:
                     break
                 pending.popleft()
                 si = self.free.popleft()
-                slot = self.slots[si]
-                slot.load(req.batch, self.copy_stream, req.pinned)
-                self.copy_stream.synchronize()
-                out = slot.out
-                out.c.seed_off = out.seed_off.data_ptr()
-                out.c.long_off = out.long_off.data_ptr()
-                st, ticket = self.ctx.submit_c(slot.c, out.c)
-                if st == sm.ERR_BUSY:          # library slots all taken: retry later
-                    self.free.appendleft(si)
-                    pending.appendleft(req)
-                    break
-                if st != sm.OK:
-                    raise sm.SmError(st, "sm_submit")
+                self.slots[si].load(req.batch, self.copy_stream, req.pinned)
+                ev = torch.cuda.Event()
+                ev.record(self.copy_stream)
                 self.in_use += need
                 self.peak_in_use = max(self.peak_in_use, self.in_use)
-                inflight[ticket] = (si, req, clock() - t0, need)
-            # retire finished batches
+                uploading.append((ev, si, req, clock() - t0, need))
+                busy = True
+            # uploaded requests: submit to a library slot
+            still = []
+            for item in uploading:
+                ev, si, req, adm, need = item
+                if not ev.query():
+                    still.append(item)
+                    continue
+                out = self.slots[si].out
+                out.c.seed_off = out.seed_off.data_ptr()
+                out.c.long_off = out.long_off.data_ptr()
+                st, ticket = self.ctx.submit_c(self.slots[si].c, out.c)
+                if st == sm.ERR_BUSY:          # library slots all taken: retry later
+                    still.append(item)
+                    continue
+                if st != sm.OK:
+                    raise sm.SmError(st, "sm_submit")
+                inflight[ticket] = (si, req, adm, need)
+            uploading = still
+            # finished batches: start their result copies
             for ticket in list(inflight):
                 st = self.ctx.poll(ticket, wait=False)
                 if st == sm.ERR_NOT_READY:
@@ -188,14 +252,31 @@ class Server:
                 si, req, adm, need = inflight.pop(ticket)
                 if st != sm.OK:
                     raise sm.SmError(st, "sm_poll")
+                ev = self.slots[si].fetch(self.fetch_stream)
+                draining.append((ev, si, req, adm, need))
+            # results in host memory: hand them out and free the slot
+            still = []
+            for item in draining:
+                ev, si, req, adm, need = item
+                if not ev.query():
+                    still.append(item)
+                    continue
+                t_done = clock() - t0
                 slot = self.slots[si]
-                so, seeds, lo, longs = slot.out.to_host()
-                done.append(Result(req.rid, req.batch.n_events, req.arrival, adm, clock() - t0,
-                                   so[:req.batch.n_events + 1], seeds, lo[:req.batch.n_events + 1],
-                                   longs))
+                if keep:
+                    so, seeds, lo, longs = slot.collect()
+                else:
+                    e, ns, nl = slot.fetched
+                    so = lo = np.zeros(0, np.int32)
+                    seeds = np.zeros(0, sm.SEED_DTYPE)
+                    longs = np.zeros(0, sm.LONG_DTYPE)
+                done.append(Result(req.rid, req.batch.n_events, req.arrival, adm, t_done,
+                                   so, seeds, lo, longs))
                 self.free.append(si)
                 self.in_use -= need
-            if not inflight and pending and pending[0].arrival > clock() - t0:
+            draining = still
+            if not (uploading or inflight or draining) and pending and \
+                    pending[0].arrival > clock() - t0:
                 time.sleep(min(1e-4, max(0.0, pending[0].arrival - (clock() - t0))))
         return done
 
@@ -203,8 +284,8 @@ class Server:
 def serve_plain(ctx, requests: list, max_events: int, max_hits: int, max_velo: int,
                 clock=time.perf_counter) -> list:
     """The same arrival stream, one request at a time through the plain form."""
-    slot = SlotBuffers(max_events, max_hits, max_velo)
     import torch
+    slot = SlotBuffers(max_events, max_hits, max_velo)
     stream = torch.cuda.current_stream()
     out = []
     t0 = clock()
@@ -214,9 +295,10 @@ def serve_plain(ctx, requests: list, max_events: int, max_hits: int, max_velo: i
         adm = clock() - t0
         slot.load(req.batch, stream, req.pinned)
         ctx.run_c(slot.c, slot.out.c, plain=True)
-        so, seeds, lo, longs = slot.out.to_host()
+        slot.fetch(stream).synchronize()
+        so, seeds, lo, longs = slot.collect()
         out.append(Result(req.rid, req.batch.n_events, req.arrival, adm, clock() - t0,
-                          so[:req.batch.n_events + 1], seeds, lo[:req.batch.n_events + 1], longs))
+                          so, seeds, lo, longs))
     return out
 
 
