@@ -175,6 +175,7 @@ struct SeedShared {
   int scan[kSeedWG], a0[kSeedWG], a1[kSeedWG], a2[kSeedWG];
   int tmp[16];
   int zoff[kNL + 1];
+  int zabs[kNL + 1];                     // the item's zone offsets in the batch
   int zlo[kNL], zhi[kNL];                // z span of each layer (Hough UV), as zkey
   int xb[7];                             // first compact x index of each x slot
   int item;
@@ -833,9 +834,8 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     if (key_n(i) == bestn[c] && key_chi(i) == bestchi[c]) atomicMin(&bestidx[c], key_tb(i));
   }
   __syncthreads();
-  for (unsigned i = tid; i < ncb; i += kSeedWG) {
-    const int c = key_c(i);
-    if (key_n(i) != bestn[c] || key_tb(i) != bestidx[c] || key_chi(i) != bestchi[c]) continue;
+  // the seed record of winning combination i
+  auto make_seed = [&](unsigned i) {
     const Combo r = combo[i];
     const Cand &cd = cand[r.c];
     SeedStage st;
@@ -850,6 +850,45 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
       st.s.hits[xlayer(k)] = cd.pos[k] >= 0 ? hid[cd.pos[k]] : -1;
       st.s.hits[uvlayer(k)] = r.pos[k] >= 0 ? hid[r.pos[k]] : -1;
     }
+    return st;
+  };
+  auto is_winner = [&](unsigned i) {
+    const int c = key_c(i);
+    return key_n(i) == bestn[c] && key_tb(i) == bestidx[c] && key_chi(i) == bestchi[c];
+  };
+  auto claim_pool = [&](unsigned ns) {
+    if (tid == 0) {
+      unsigned long long b = atomicAdd(&cnt->pool_top, (unsigned long long)ns);
+      if (b + ns > (unsigned long long)S.pool_cap) raise_flag(cnt, F_POOL);
+      sh.pbase = b;
+      S.item_cnt[item] = (int)ns;
+      S.item_base[item] = (int)(b < (unsigned long long)S.pool_cap ? b : 0);
+    }
+  };
+  if (ncb <= (unsigned)kSeedWG) {
+    // one combination per thread: each winner publishes its key in LDS, and
+    // once the pool range is known writes its record straight to its
+    // canonical place (rank of its (iteration, T1, T3, T2) key)
+    const bool win = tid < ncb && is_winner(tid);
+    unsigned slot = 0;
+    unsigned long long key = 0;
+    if (win) {
+      key = cand[key_c(tid)].key;
+      slot = wave_append(&sh.nseed);
+      sh.u.skey[slot] = key;
+    }
+    __syncthreads();
+    const unsigned ns = sh.nseed;
+    claim_pool(ns);
+    __syncthreads();
+    const unsigned long long base = sh.pbase;
+    if (win && base + ns <= (unsigned long long)S.pool_cap)
+      S.pool[base + rank_of(sh.u.skey, ns, key, slot)] = make_seed(tid).s;
+    return;
+  }
+  for (unsigned i = tid; i < ncb; i += kSeedWG) {
+    if (!is_winner(i)) continue;
+    const SeedStage st = make_seed(i);
     const unsigned slot = wave_append(&sh.nseed);
     if (slot < (unsigned)S.sst_cap) sst[slot] = st;
   }
@@ -861,13 +900,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   }
   const bool lds_keys = ns <= (unsigned)kSeedLds;
   for (unsigned i = tid; i < ns && lds_keys; i += kSeedWG) sh.u.skey[i] = sst[i].key;
-  if (tid == 0) {
-    unsigned long long base = atomicAdd(&cnt->pool_top, (unsigned long long)ns);
-    if (base + ns > (unsigned long long)S.pool_cap) raise_flag(cnt, F_POOL);
-    sh.pbase = base;
-    S.item_cnt[item] = (int)ns;
-    S.item_base[item] = (int)(base < (unsigned long long)S.pool_cap ? base : 0);
-  }
+  claim_pool(ns);
   __syncthreads();
   const unsigned long long base = sh.pbase;
   if (base + ns <= (unsigned long long)S.pool_cap) {
@@ -1220,15 +1253,18 @@ __global__ __launch_bounds__(kSeedWG, 4) void k_seed(const Desc *__restrict__ D,
     const int item = sh.item;
     if (item < 0) break;
     const int k0 = item * kNL;
-    const int base = zone_off[k0];
-    const int nh = zone_off[k0 + kNL] - base;
-    if (tid <= kNL) sh.zoff[tid] = zone_off[k0 + tid] - base;
+    // the item's zone offsets once from global memory, then from LDS
+    if (tid <= kNL) sh.zabs[tid] = zone_off[k0 + tid];
+    __syncthreads();
+    const int base = sh.zabs[0];
+    const int nh = sh.zabs[kNL] - base;
+    if (tid <= kNL) sh.zoff[tid] = sh.zabs[tid] - base;
     if (tid == 0) {
       int acc = 0;
       for (int k = 0; k < 6; ++k) {
         sh.xb[k] = acc;
         const int L = (k >> 1) * 4 + (k & 1) * 3;
-        acc += zone_off[k0 + L + 1] - zone_off[k0 + L];
+        acc += sh.zabs[L + 1] - sh.zabs[L];
       }
       sh.xb[6] = acc;
     }
@@ -1241,13 +1277,13 @@ __global__ __launch_bounds__(kSeedWG, 4) void k_seed(const Desc *__restrict__ D,
       __syncthreads();
     } else if (nh <= lds_hits) {
       // stage the item's hits; every bin entry starts at its zone's size
-      for (int i = tid; i < kNL * kBins; i += kSeedWG) {
-        const int L = i / kBins;
-        sh.bins[L][i % kBins] = (unsigned short)(zone_off[k0 + L + 1] - zone_off[k0 + L]);
-      }
       for (int i = tid; i < nh; i += kSeedWG) {
         s_x[i] = hx[base + i];
         s_z[i] = hz[base + i];
+      }
+      for (int i = tid; i < kNL * kBins; i += kSeedWG) {
+        const int L = i / kBins;
+        sh.bins[L][i % kBins] = (unsigned short)(sh.zabs[L + 1] - sh.zabs[L]);
       }
       __syncthreads();
       // hit i opens the bins in (kbin(previous hit), kbin(hit i)]
