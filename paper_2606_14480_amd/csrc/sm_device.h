@@ -29,6 +29,8 @@ constexpr int kSurvLds = 512;       // matching survivors kept in LDS
 constexpr int kPosBits = 21;        // item-relative hit positions < 2^21
 constexpr int kMaxItemHits = 1 << kPosBits;
 constexpr int kHoughBins = 128;     // largest coarse t_y histogram
+constexpr int kBigWG = 1024;        // threads of the big-item workgroup (16 wave64)
+constexpr int kBigBucket = 12;      // items with >= 2^12 - 1 hits are big
 constexpr double kTieMm = 1e-6;     // closest-hit distances this close are a tie
 
 // status flags (Counters::flags)
@@ -57,6 +59,8 @@ struct Counters {
   unsigned need_trip, need_cand, need_tbl, need_sst;
   unsigned need_ms, need_vs, need_surv, need_combo;
   long long total_seeds, total_longs;
+  unsigned big_queue, n_big;     // big-item queue: order positions [0, n_big)
+  unsigned need_big[8];          // needs of the big-item scratch, same order as need_trip..
 };
 
 // Everything a batch needs that changes from call to call; lives in device
@@ -93,7 +97,10 @@ struct DevParams {
   float pre_dx, pre_dy, pre_dtx, pre_dty;  // FP32 prefilter, slightly wider
   float zmf[5], z_ymatchf, z_statef;
   // Hough-cluster UV variant
-  int uv_mode, hough_bins, hough_best, hough_fine, hough_min, pad_h;
+  int uv_mode, hough_bins, hough_best, hough_fine, hough_min;
+  // scheduling: main-form workgroups and the item latency model (us, n = hits)
+  int main_slots, big_slots;
+  float lat_a, lat_b, big_speedup;
   double hough_lo[2], hough_hi[2];
 };
 
@@ -151,12 +158,15 @@ struct Scratch {
   Surv *surv;                 // [seed_wgs][2 * surv_cap]
   int ms_cap, vs_cap, surv_cap, pad;
   Counters *cnt;
+  unsigned *need;             // 8 overflow needs of this scratch (trip, cand, tbl, sst,
+                              // ms, vs, surv, combo), inside *cnt
 };
 
 // Per-slot kernel context in device memory: kernels read scratch pointers and
 // parameters through one pointer, so no argument has to stay in registers.
 struct KCtx {
-  Scratch S;
+  Scratch S;   // main form: per-workgroup arrays for seed_wgs workgroups
+  Scratch SB;  // big-item form: own per-workgroup arrays, shared pools and counters
   DevParams P;
 };
 
@@ -164,6 +174,7 @@ struct KCtx {
 
 // Dynamic LDS bytes of k_seed for a given LDS hit capacity.
 size_t smk_seed_lds_bytes(int lds_hits);
+size_t smk_seed_big_lds_bytes(int lds_hits);
 
 extern "C" {
 // Launchers (sm_device.hip); each returns the hipError_t of its launch.
@@ -171,6 +182,9 @@ int smk_launch_prepare(const smk::Desc *d, const smk::KCtx *k, int plain, hipStr
 int smk_launch_seed(const smk::Desc *d, const smk::KCtx *k, int item_begin, int item_count,
                     int use_queue, int grid, int lds_hits, int plain, int uv_mode,
                     hipStream_t st);
+int smk_launch_seed_big(const smk::Desc *d, const smk::KCtx *k, int grid, int lds_hits,
+                        hipStream_t st);
+int smk_seed_big_lds_limit(int bytes);
 int smk_launch_offsets(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
 int smk_launch_copy(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 int smk_launch_validate(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);

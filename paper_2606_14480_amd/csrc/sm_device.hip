@@ -157,6 +157,7 @@ __device__ __forceinline__ int kbin(float x) {
 
 // Everything one seeding workgroup keeps in LDS besides the hits (whose
 // capacity is set per launch in dynamic LDS).
+template <int NT>
 struct SeedShared {
   unsigned short bins[kNL][kBins];
   unsigned long long cscore[kCandLds];   // candidate scores
@@ -172,7 +173,7 @@ struct SeedShared {
     } uv;
     unsigned long long skey[kSeedLds];   // seed keys for the canonical rank
   } u;
-  int scan[kSeedWG], a0[kSeedWG], a1[kSeedWG], a2[kSeedWG];
+  int scan[NT], a0[NT], a1[NT], a2[NT];
   int tmp[16];
   int zoff[kNL + 1];
   int zabs[kNL + 1];                     // the item's zone offsets in the batch
@@ -184,8 +185,8 @@ struct SeedShared {
 };
 
 // first i of zone L with X[i] >= v
-template <bool kLds, class T>
-__device__ __forceinline__ int zlower(const float *X, const SeedShared &sh, int L, T v) {
+template <bool kLds, class T, int NT>
+__device__ __forceinline__ int zlower(const float *X, const SeedShared<NT> &sh, int L, T v) {
   const int lo = sh.zoff[L], hi = sh.zoff[L + 1];
   if constexpr (kLds) {
     const int k = kbin((float)v);
@@ -207,8 +208,8 @@ __device__ __forceinline__ int zlower(const float *X, const SeedShared &sh, int 
 // hit replaces the current one only if it is closer by more than kTieMm, so a
 // prediction midway between two hits picks the same hit whatever the
 // rounding of the prediction.
-template <bool kLds>
-__device__ __forceinline__ int zclosest(const float *X, const SeedShared &sh, int L, double pred,
+template <bool kLds, int NT>
+__device__ __forceinline__ int zclosest(const float *X, const SeedShared<NT> &sh, int L, double pred,
                                         double tol) {
   const int hi = sh.zoff[L + 1];
   int best = -1;
@@ -227,15 +228,15 @@ __device__ __forceinline__ int zclosest(const float *X, const SeedShared &sh, in
 // each thread finds the T3 window of its T1 hit, a workgroup scan flattens
 // the doublets so every thread gets an equal share, and the T2 hits found
 // for a doublet are appended with one atomic per wave.
-template <bool kLds>
-__device__ __forceinline__ void xz_triplets(const float *X, const float *Z, SeedShared &sh,
+template <bool kLds, int NT>
+__device__ __forceinline__ void xz_triplets(const float *X, const float *Z, SeedShared<NT> &sh,
                                             const DevParams &P, unsigned long long *trip,
                                             int trip_cap) {
   const int *zoff = sh.zoff;
   const int n1a = zoff[1] - zoff[0], n1b = zoff[4] - zoff[3];
   const int N1 = n1a + n1b;
   const float zr = P.zreff, dd = P.df;
-  for (int c0 = 0; c0 < N1; c0 += kSeedWG) {
+  for (int c0 = 0; c0 < N1; c0 += NT) {
     const int j = c0 + (int)threadIdx.x;
     int st = 0, cnt_j = 0, i1 = 0, it = 0;
     if (j < N1) {
@@ -263,13 +264,13 @@ __device__ __forceinline__ void xz_triplets(const float *X, const float *Z, Seed
       cnt_j = en - st;
     }
     int total;
-    const int excl = block_excl_scan<kSeedWG>(cnt_j, sh.tmp, total);
+    const int excl = block_excl_scan<NT>(cnt_j, sh.tmp, total);
     sh.scan[threadIdx.x] = excl;
     sh.a0[threadIdx.x] = st;
     sh.a1[threadIdx.x] = i1 | (it << 30);
     __syncthreads();
-    const int nj = min(kSeedWG, N1 - c0);
-    for (int d0 = 0; d0 < total; d0 += kSeedWG) {
+    const int nj = min(NT, N1 - c0);
+    for (int d0 = 0; d0 < total; d0 += NT) {
       const int d = d0 + (int)threadIdx.x;
       if (d < total) {
         int lo = 0, hi = nj;
@@ -313,8 +314,8 @@ __device__ __forceinline__ void xz_triplets(const float *X, const float *Z, Seed
 }
 
 // Extension, fit and score of one triplet (Sec. 3.2, eq. seed_clone_score).
-template <bool kLds>
-__device__ __forceinline__ bool xz_candidate(const float *X, const float *Z, const SeedShared &sh,
+template <bool kLds, int NT>
+__device__ __forceinline__ bool xz_candidate(const float *X, const float *Z, const SeedShared<NT> &sh,
                                              const DevParams &P, unsigned long long key, Cand &cd) {
   const unsigned msk = (1u << kPosBits) - 1u;
   const int it = (int)(key >> 63);
@@ -369,8 +370,8 @@ __device__ __forceinline__ bool xz_candidate(const float *X, const float *Z, con
 // ascending z, averaging t_y after each, then fit y = y0 + t_y (z - z_ref)
 // with weights tan^2(alpha) / sigma^2.  Returns false if it has too few hits
 // or fails the chi2 cut.
-template <bool kLds>
-__device__ __forceinline__ bool uv_combo(const float *X, const float *Z, const SeedShared &sh,
+template <bool kLds, int NT>
+__device__ __forceinline__ bool uv_combo(const float *X, const float *Z, const SeedShared<NT> &sh,
                                          const DevParams &P, double a, double b, double c,
                                          int L0, int h0, Combo &r) {
   const double xh0 = X[h0], zh0 = Z[h0];
@@ -421,10 +422,12 @@ __device__ __forceinline__ bool uv_combo(const float *X, const float *Z, const S
 // regions the vote no longer needs: chi2 bits in cscore, (track, hits,
 // order) in cpos viewed as three int arrays.
 constexpr int kComboLds = kCandLds;
-__device__ __forceinline__ int *combo_keys(SeedShared &sh) {
+template <int NT>
+__device__ __forceinline__ int *combo_keys(SeedShared<NT> &sh) {
   return reinterpret_cast<int *>(&sh.cpos[0][0]);
 }
-__device__ __forceinline__ void push_combo(SeedShared &sh, Combo *combo, int cap, const Combo &r) {
+template <int NT>
+__device__ __forceinline__ void push_combo(SeedShared<NT> &sh, Combo *combo, int cap, const Combo &r) {
   const unsigned slot = wave_append(&sh.ncombo);
   if (slot < (unsigned)cap) combo[slot] = r;
   if (slot < (unsigned)kComboLds) {
@@ -461,7 +464,8 @@ __device__ __forceinline__ float zunkey(int k) { return __int_as_float(k ^ ((k >
 // tan lies in [ylo, yhi] for a z_hit inside the layer's z span.  x(z) may
 // depart from its chord over the span by at most span^2/8 max|x''|.  The
 // range is a superset; the exact test is taken hit by hit.
-__device__ __forceinline__ void hough_xrange(const SeedShared &sh, const DevParams &P, int L,
+template <int NT>
+__device__ __forceinline__ void hough_xrange(const SeedShared<NT> &sh, const DevParams &P, int L,
                                              double a, double b, double c, double ylo,
                                              double yhi, double &lo, double &hi) {
   const double za = zunkey(sh.zlo[L]), zb = zunkey(sh.zhi[L]);
@@ -478,8 +482,8 @@ __device__ __forceinline__ void hough_xrange(const SeedShared &sh, const DevPara
 
 // Calls f(L, i) on the lanes of one wave for every hit i of the six stereo
 // layers inside the x range of hough_xrange.
-template <bool kLds, class F>
-__device__ __forceinline__ void hough_scan(const float *X, const SeedShared &sh, const DevParams &P,
+template <bool kLds, class F, int NT>
+__device__ __forceinline__ void hough_scan(const float *X, const SeedShared<NT> &sh, const DevParams &P,
                                            double a, double b, double c, double ylo, double yhi,
                                            F &&f) {
   const int lane = threadIdx.x & 63;
@@ -501,8 +505,8 @@ __device__ __forceinline__ void hough_scan(const float *X, const SeedShared &sh,
 
 // One t_y hypothesis: the closest hit within uv_tol in every stereo layer,
 // then the weighted line fit of uv_combo.
-template <bool kLds>
-__device__ __forceinline__ bool hough_attach(const float *X, const float *Z, const SeedShared &sh,
+template <bool kLds, int NT>
+__device__ __forceinline__ bool hough_attach(const float *X, const float *Z, const SeedShared<NT> &sh,
                                              const DevParams &P, double a, double b, double c,
                                              double ty, Combo &r) {
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0, yref = 0.0;
@@ -545,11 +549,12 @@ __device__ __forceinline__ bool hough_attach(const float *X, const float *Z, con
 // best hypothesis (most hits, lowest chi2_y, earliest) is the track's only
 // combination.  Bins are decided in FP64; the fine-bin sums are exact
 // fixed-point sums, so the result does not depend on the order of the adds.
-template <bool kLds>
-__device__ void uv_hough(const float *X, const float *Z, SeedShared &sh, const DevParams &P,
+template <bool kLds, int NT>
+__device__ void uv_hough(const float *X, const float *Z, SeedShared<NT> &sh, const DevParams &P,
                          int half, unsigned nc, const int *cinfo, const Cand *cand, int *bestn,
                          unsigned long long *bestchi, int *bestidx, Combo *combo, int combo_cap) {
 #pragma clang fp contract(off)
+  static_assert(NT == kSeedWG, "the Hough search keeps one state per wave of a 256-thread workgroup");
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   HoughWave &hw = reinterpret_cast<HoughWave *>(&sh.u.uv.cabc[0][0])[wv];
   if (tid < kNL) {
@@ -559,7 +564,7 @@ __device__ void uv_hough(const float *X, const float *Z, SeedShared &sh, const D
   __syncthreads();
   for (int k = 0; k < 6; ++k) {
     const int L = uvlayer(k);
-    for (int i = sh.zoff[L] + tid; i < sh.zoff[L + 1]; i += kSeedWG) {
+    for (int i = sh.zoff[L] + tid; i < sh.zoff[L + 1]; i += NT) {
       const int key = zkey(Z[i]);
       atomicMin(&sh.zlo[L], key);
       atomicMax(&sh.zhi[L], key);
@@ -575,7 +580,7 @@ __device__ void uv_hough(const float *X, const float *Z, SeedShared &sh, const D
     const int k = (int)floor((t - lo) / w);
     return k < 0 ? 0 : (k >= NB ? NB - 1 : k);
   };
-  for (unsigned c0 = 0; c0 < nc; c0 += kSeedWG / 64) {
+  for (unsigned c0 = 0; c0 < nc; c0 += NT / 64) {
     const unsigned ci = c0 + wv;
     const bool act = ci < nc && !(cinfo[ci] & ((1 << 4) | (1 << 5)));
     double a = 0.0, b = 0.0, c = 0.0;
@@ -658,10 +663,10 @@ __device__ void uv_hough(const float *X, const float *Z, SeedShared &sh, const D
 // Clone killing, UV seeding, best combination and seed staging of one item
 // (continuation of seed_item).  kSmall: the vote records, the vote table and
 // the UV bookkeeping are in LDS.
-template <bool kLds, int kUv, bool kSmall>
+template <bool kLds, int kUv, bool kSmall, int NT>
 __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const int32_t *hid,
                                           int item, unsigned nc, int nx, const DevParams &P,
-                                          const Scratch &S, size_t wg, SeedShared &sh) {
+                                          const Scratch &S, size_t wg, SeedShared<NT> &sh) {
   const int tid = threadIdx.x;
   const int half = item & 1;
   const int *zoff = sh.zoff;
@@ -675,16 +680,16 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   int *cinfo = small ? sh.cinfo : S.cinfo + co;
   unsigned long long *xt = small ? sh.u.xtab : S.tbl + wg * (size_t)S.tbl_cap;
   if (!small && nx > S.tbl_cap) {
-    if (tid == 0) { raise_flag(cnt, F_TBL); atomicMax(&cnt->need_tbl, (unsigned)nx); }
+    if (tid == 0) { raise_flag(cnt, F_TBL); atomicMax(&S.need[2], (unsigned)nx); }
     nc = 0;
   }
   if (!small) {
-    for (unsigned i = tid; i < nc; i += kSeedWG) {
+    for (unsigned i = tid; i < nc; i += NT) {
       cscore[i] = cand[i].score;
       cinfo[i] = cand[i].n | (cand[i].it << 3);
     }
   }
-  for (int i = tid; i < nx && nc > 0; i += kSeedWG) xt[i] = ~0ull;
+  for (int i = tid; i < nx && nc > 0; i += NT) xt[i] = ~0ull;
   __syncthreads();
   // compact x index of the hit in slot k of candidate i, or -1
   auto xidx = [&](unsigned i, int k) -> int {
@@ -693,7 +698,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   };
 
   // O(n) clone killing (Sec. 3.3.4): per-hit minimum score, then own counts
-  for (unsigned i = tid; i < nc; i += kSeedWG) {
+  for (unsigned i = tid; i < nc; i += NT) {
     const unsigned long long sc = cscore[i];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -702,7 +707,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     }
   }
   __syncthreads();
-  for (unsigned i = tid; i < nc; i += kSeedWG) {
+  for (unsigned i = tid; i < nc; i += NT) {
     const unsigned long long sc = cscore[i];
     int own = 0;
 #pragma unroll
@@ -721,7 +726,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   // compares hit sets (one slot per lane) only where the score matches.
   {
     const int lane = tid & 63;
-    for (unsigned i = tid >> 6; i < nc; i += kSeedWG / 64) {
+    for (unsigned i = tid >> 6; i < nc; i += NT / 64) {
       const int ci = cinfo[i];
       if ((ci & (1 << 4)) || !(ci & (1 << 3))) continue;
       const unsigned long long sc = cscore[i];
@@ -752,7 +757,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   if constexpr (kUv == 1)
     uv_hough<kLds>(X, Z, sh, P, half, nc, cinfo, cand, bestn, bestchi, bestidx, combo,
                    S.combo_cap);
-  for (unsigned c0 = 0; c0 < nc && kUv == 0; c0 += kSeedWG) {
+  for (unsigned c0 = 0; c0 < nc && kUv == 0; c0 += NT) {
     const unsigned ci = c0 + tid;
     int cnt0 = 0, cnt1 = 0, st0 = 0, st1 = 0;
     if (ci < nc && !(cinfo[ci] & ((1 << 4) | (1 << 5)))) {
@@ -775,14 +780,14 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
       bestidx[ci] = 0x7fffffff;
     }
     int total;
-    const int excl = block_excl_scan<kSeedWG>(cnt0 + cnt1, sh.tmp, total);
+    const int excl = block_excl_scan<NT>(cnt0 + cnt1, sh.tmp, total);
     sh.scan[tid] = excl;
     sh.a0[tid] = st0;
     sh.a1[tid] = cnt0;
     sh.a2[tid] = st1;
     __syncthreads();
-    const int nj = min((int)kSeedWG, (int)(nc - c0));
-    for (int d0 = 0; d0 < total; d0 += kSeedWG) {
+    const int nj = min((int)NT, (int)(nc - c0));
+    for (int d0 = 0; d0 < total; d0 += NT) {
       const int d = d0 + tid;
       if (d >= total) continue;
       int lo = 0, hi = nj;
@@ -809,7 +814,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   }
   unsigned ncb = sh.ncombo;
   if (ncb > (unsigned)S.combo_cap) {
-    if (tid == 0) { raise_flag(cnt, F_COMBO); atomicMax(&cnt->need_combo, ncb); }
+    if (tid == 0) { raise_flag(cnt, F_COMBO); atomicMax(&S.need[7], ncb); }
     ncb = S.combo_cap;
   }
   // best combination per track: most hits, then lowest chi2_y, then the
@@ -824,12 +829,12 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     return i < (unsigned)kComboLds ? sh.cscore[i]
                                    : (unsigned long long)__double_as_longlong(combo[i].chi2);
   };
-  for (unsigned i = tid; i < ncb; i += kSeedWG) {
+  for (unsigned i = tid; i < ncb; i += NT) {
     const int c = key_c(i);
     if (key_n(i) == bestn[c]) atomicMin(&bestchi[c], key_chi(i));
   }
   __syncthreads();
-  for (unsigned i = tid; i < ncb; i += kSeedWG) {
+  for (unsigned i = tid; i < ncb; i += NT) {
     const int c = key_c(i);
     if (key_n(i) == bestn[c] && key_chi(i) == bestchi[c]) atomicMin(&bestidx[c], key_tb(i));
   }
@@ -865,8 +870,8 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
       S.item_base[item] = (int)(b < (unsigned long long)S.pool_cap ? b : 0);
     }
   };
-  if (ncb <= (unsigned)kSeedWG) {
-    // one combination per thread: each winner publishes its key in LDS, and
+  if (ncb <= (unsigned)(NT < kSeedLds ? NT : kSeedLds)) {
+    // one combination per thread (and every key fits the LDS key list): each winner publishes its key in LDS, and
     // once the pool range is known writes its record straight to its
     // canonical place (rank of its (iteration, T1, T3, T2) key)
     const bool win = tid < ncb && is_winner(tid);
@@ -886,7 +891,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
       S.pool[base + rank_of(sh.u.skey, ns, key, slot)] = make_seed(tid).s;
     return;
   }
-  for (unsigned i = tid; i < ncb; i += kSeedWG) {
+  for (unsigned i = tid; i < ncb; i += NT) {
     if (!is_winner(i)) continue;
     const SeedStage st = make_seed(i);
     const unsigned slot = wave_append(&sh.nseed);
@@ -895,17 +900,17 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   __syncthreads();
   unsigned ns = sh.nseed;
   if (ns > (unsigned)S.sst_cap) {
-    if (tid == 0) { raise_flag(cnt, F_SST); atomicMax(&cnt->need_sst, ns); }
+    if (tid == 0) { raise_flag(cnt, F_SST); atomicMax(&S.need[3], ns); }
     ns = S.sst_cap;
   }
   const bool lds_keys = ns <= (unsigned)kSeedLds;
-  for (unsigned i = tid; i < ns && lds_keys; i += kSeedWG) sh.u.skey[i] = sst[i].key;
+  for (unsigned i = tid; i < ns && lds_keys; i += NT) sh.u.skey[i] = sst[i].key;
   claim_pool(ns);
   __syncthreads();
   const unsigned long long base = sh.pbase;
   if (base + ns <= (unsigned long long)S.pool_cap) {
     // canonical order: rank of each seed's (iteration, T1, T3, T2) key
-    for (unsigned i = tid; i < ns; i += kSeedWG) {
+    for (unsigned i = tid; i < ns; i += NT) {
       const unsigned long long key = lds_keys ? sh.u.skey[i] : sst[i].key;
       unsigned r = 0;
       if (lds_keys)
@@ -920,10 +925,10 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
 // Seeding of one (event, half) item.  kLds: the item's hits are in LDS (with
 // the x-bin index); the candidate-side arrays are in LDS whenever they fit,
 // else in this workgroup's global scratch.
-template <bool kLds, int kUv>
+template <bool kLds, int kUv, int NT>
 __device__ __forceinline__ void seed_item(const float *X, const float *Z, const int32_t *hid,
                                           int item, int nh, const DevParams &P,
-                                          const Scratch &S, size_t wg, SeedShared &sh) {
+                                          const Scratch &S, size_t wg, SeedShared<NT> &sh) {
   const int tid = threadIdx.x;
   const int half = item & 1;
   const int *zoff = sh.zoff;
@@ -937,10 +942,10 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   xz_triplets<kLds>(X, Z, sh, P, trip, S.trip_cap);
   unsigned ntrip = sh.ntrip;
   if (ntrip > (unsigned)S.trip_cap) {
-    if (tid == 0) { raise_flag(cnt, F_TRIP); atomicMax(&cnt->need_trip, ntrip); }
+    if (tid == 0) { raise_flag(cnt, F_TRIP); atomicMax(&S.need[0], ntrip); }
     ntrip = S.trip_cap;
   }
-  for (unsigned t = tid; t < ntrip; t += kSeedWG) {
+  for (unsigned t = tid; t < ntrip; t += NT) {
     Cand cd;
     if (xz_candidate<kLds>(X, Z, sh, P, trip[t], cd)) {
       const unsigned slot = wave_append(&sh.ncand);
@@ -956,7 +961,7 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   __syncthreads();
   unsigned nc = sh.ncand;
   if (nc > (unsigned)S.cand_cap) {
-    if (tid == 0) { raise_flag(cnt, F_CAND); atomicMax(&cnt->need_cand, nc); }
+    if (tid == 0) { raise_flag(cnt, F_CAND); atomicMax(&S.need[1], nc); }
     nc = S.cand_cap;
   }
   const int nx = sh.xb[6];
@@ -1063,7 +1068,7 @@ __global__ __launch_bounds__(256) void k_validate(const Desc *__restrict__ D, co
 // to the pool and the seeds stay in theirs until the offsets are known.
 // kSmallM: the event's seeds and VELO states fit the LDS arrays, which the
 // instantiation then addresses as LDS (not through generic pointers).
-template <bool kSmallM>
+template <bool kSmallM, int NT>
 __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, const Scratch &S,
                                                  const DevParams &P, int e, int plain, size_t wg,
                                                  MatchShared &sh) {
@@ -1084,8 +1089,8 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   if (tid == 0 && plain) D->seed_off[e + 1] = so + ns;
   const bool fits = ns <= S.ms_cap && nv <= S.vs_cap && pool_ok;
   if (tid == 0 && !fits && pool_ok) {
-    if (ns > S.ms_cap) { raise_flag(cnt, F_MS); atomicMax(&cnt->need_ms, (unsigned)ns); }
-    if (nv > S.vs_cap) { raise_flag(cnt, F_VS); atomicMax(&cnt->need_vs, (unsigned)nv); }
+    if (ns > S.ms_cap) { raise_flag(cnt, F_MS); atomicMax(&S.need[4], (unsigned)ns); }
+    if (nv > S.vs_cap) { raise_flag(cnt, F_VS); atomicMax(&S.need[5], (unsigned)nv); }
   }
   // per-seed arrays in LDS, or in this workgroup's global scratch for events
   // with many seeds / VELO states
@@ -1098,7 +1103,7 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   unsigned long long *best_s = sm_s ? sh.best_s : S.best_s + wg * (size_t)S.ms_cap;
   unsigned long long *best_v = sm_v ? sh.best_v : S.best_v + wg * (size_t)S.vs_cap;
   // the event's seeds in canonical order (half 0 then half 1)
-  for (int i = tid; i < ns && pool_ok; i += kSeedWG) {
+  for (int i = tid; i < ns && pool_ok; i += NT) {
     const sm_seed sd = i < n0 ? S.pool[b0 + i] : S.pool[b1 + i - n0];
     if (plain && (long long)so + i < D->seed_cap) D->seeds[so + i] = sd;
     if (fits) {
@@ -1111,7 +1116,7 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   __syncthreads();
   // seeds sorted by t_y, so each VELO state visits only its |dty| window
   if (fits) {
-    for (int i = tid; i < ns; i += kSeedWG) {
+    for (int i = tid; i < ns; i += NT) {
       const float t = tyf[i];
       const int r = (int)rank_of(tyf, (unsigned)ns, t, (unsigned)i);
       sty[r] = t;
@@ -1121,7 +1126,7 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   __syncthreads();
   Surv *surv = S.surv + wg * (size_t)(2 * S.surv_cap);
   if (fits && ns > 0) {
-    for (int v = tid; v < nv; v += kSeedWG) {
+    for (int v = tid; v < nv; v += NT) {
       const float xvf = D->b.velo_x[v0 + v], yvf = D->b.velo_y[v0 + v], zvf = D->b.velo_z[v0 + v];
       const float txvf = D->b.velo_tx[v0 + v], tyvf = D->b.velo_ty[v0 + v];
       const float yvm = yvf + tyvf * (P.z_ymatchf - zvf);
@@ -1151,14 +1156,14 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   __syncthreads();
   unsigned nsv = sh.nsurv;
   if (nsv > (unsigned)(kSurvLds + S.surv_cap)) {
-    if (tid == 0) { raise_flag(cnt, F_SURV); atomicMax(&cnt->need_surv, nsv - kSurvLds); }
+    if (tid == 0) { raise_flag(cnt, F_SURV); atomicMax(&S.need[6], nsv - kSurvLds); }
     nsv = kSurvLds + S.surv_cap;
   }
   // final selection: a pair survives if its chi2 is the best of its seed and
   // of its VELO track
   unsigned long long *kkey =
       nsv <= (unsigned)kSurvLds ? sh.kkey : (unsigned long long *)(surv + S.surv_cap);
-  for (unsigned i = tid; i < nsv; i += kSeedWG) {
+  for (unsigned i = tid; i < nsv; i += NT) {
     const Surv sv = i < (unsigned)kSurvLds ? sh.surv[i] : surv[i - kSurvLds];
     const unsigned long long bits = (unsigned long long)__double_as_longlong(sv.chi2);
     if (best_v[sv.v] == bits && best_s[sv.s] == bits) {
@@ -1185,7 +1190,7 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   const unsigned long long lb = sh.lbase;
   const long long cap = plain ? D->long_cap : S.lpool_cap;
   sm_long *dst = plain ? D->longs : S.lpool;
-  for (unsigned i = tid; i < nk; i += kSeedWG) {
+  for (unsigned i = tid; i < nk; i += NT) {
     const unsigned long long key = kkey[i];
     const unsigned r = rank_of(kkey, nk, key, i);
     if ((long long)(lb + r) >= cap) continue;
@@ -1204,32 +1209,39 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
 
 // ----------------------------------------------------- the fused kernel ----
 
+template <int NT>
 __device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Scratch &S,
                                             const DevParams &P, int e, int plain, size_t wg,
                                             MatchShared &sh) {
   const int ns = S.item_cnt[2 * e] + S.item_cnt[2 * e + 1];
   const int nv = D->b.velo_off[e + 1] - D->b.velo_off[e];
   if (ns <= kMsLds && nv <= kVsLds)
-    match_event_impl<true>(D, S, P, e, plain, wg, sh);
+    match_event_impl<true, NT>(D, S, P, e, plain, wg, sh);
   else
-    match_event_impl<false>(D, S, P, e, plain, wg, sh);
+    match_event_impl<false, NT>(D, S, P, e, plain, wg, sh);
 }
 
 // Persistent Seeding + Matching: each workgroup pulls (event, half) items from
 // the queue (or takes item_begin + blockIdx in the plain form) and seeds
 // them; the workgroup that completes the second half of an event then matches
 // that event.  The seeding state and the matching state share the same LDS.
-template <int kUv>
-__global__ __launch_bounds__(kSeedWG, 4) void k_seed(const Desc *__restrict__ D,
+// NT = kSeedWG: the main form, 4 workgroups per CU, over the items after the
+// big ones in the longest-first order.  NT = kBigWG: one workgroup of 16
+// waves per CU with its own scratch, over the big items (at the head of the
+// order); it runs first, so a big item gets a whole CU instead of holding one
+// 256-thread workgroup for the whole batch.
+template <int kUv, int NT>
+__global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *__restrict__ D,
                                                      const KCtx *__restrict__ K, int item_begin,
                                                      int item_count, int use_queue, int lds_hits,
                                                      int plain) {
-  const Scratch &S = K->S;
+  constexpr bool kBig = NT == kBigWG;
+  const Scratch &S = kBig ? K->SB : K->S;
   const DevParams &P = K->P;
   extern __shared__ __align__(16) unsigned char smem[];
-  SeedShared &sh = *reinterpret_cast<SeedShared *>(smem);
+  SeedShared<NT> &sh = *reinterpret_cast<SeedShared<NT> *>(smem);
   MatchShared &mh = *reinterpret_cast<MatchShared *>(smem);
-  float *s_x = reinterpret_cast<float *>(smem + sizeof(SeedShared));
+  float *s_x = reinterpret_cast<float *>(smem + sizeof(SeedShared<NT>));
   float *s_z = s_x + lds_hits;
   __shared__ int s_last;
 
@@ -1238,14 +1250,17 @@ __global__ __launch_bounds__(kSeedWG, 4) void k_seed(const Desc *__restrict__ D,
   const int32_t *zone_off = D->b.zone_off;
   const float *hx = D->b.hit_x, *hz = D->b.hit_z;
   const int32_t *hid = D->b.hit_id;
-  const int n_items = item_count < 0 ? D->n_items : item_count;
+  const int n_big = use_queue ? (int)S.cnt->n_big : 0;
+  // queue of this form: the big items [0, n_big) or the rest of the order
+  const int n_items = item_count >= 0 ? item_count : (kBig ? n_big : D->n_items - n_big);
+  const int q0 = kBig ? 0 : n_big;
   bool first = true;
   for (;;) {
     if (tid == 0) {
       int q;
-      if (use_queue) q = (int)atomicAdd(&S.cnt->seed_queue, 1u);
+      if (use_queue) q = (int)atomicAdd(kBig ? &S.cnt->big_queue : &S.cnt->seed_queue, 1u);
       else q = first ? (int)blockIdx.x : n_items;
-      sh.item = q < n_items ? (use_queue ? S.item_order[q] : item_begin + q) : -1;
+      sh.item = q < n_items ? (use_queue ? S.item_order[q0 + q] : item_begin + q) : -1;
       sh.ntrip = 0; sh.ncand = 0; sh.nseed = 0; sh.ncombo = 0;
     }
     first = false;
@@ -1277,11 +1292,11 @@ __global__ __launch_bounds__(kSeedWG, 4) void k_seed(const Desc *__restrict__ D,
       __syncthreads();
     } else if (nh <= lds_hits) {
       // stage the item's hits; every bin entry starts at its zone's size
-      for (int i = tid; i < nh; i += kSeedWG) {
+      for (int i = tid; i < nh; i += NT) {
         s_x[i] = hx[base + i];
         s_z[i] = hz[base + i];
       }
-      for (int i = tid; i < kNL * kBins; i += kSeedWG) {
+      for (int i = tid; i < kNL * kBins; i += NT) {
         const int L = i / kBins;
         sh.bins[L][i % kBins] = (unsigned short)(sh.zabs[L + 1] - sh.zabs[L]);
       }
@@ -1290,7 +1305,7 @@ __global__ __launch_bounds__(kSeedWG, 4) void k_seed(const Desc *__restrict__ D,
       int zb[kNL];
 #pragma unroll
       for (int k = 0; k < kNL; ++k) zb[k] = sh.zoff[k + 1];
-      for (int i = tid; i < nh; i += kSeedWG) {
+      for (int i = tid; i < nh; i += NT) {
         int L = 0;
 #pragma unroll
         for (int k = 0; k < kNL - 1; ++k) L += i >= zb[k];
@@ -1318,7 +1333,7 @@ __global__ __launch_bounds__(kSeedWG, 4) void k_seed(const Desc *__restrict__ D,
       if (prev == 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    if (s_last) match_event(D, S, P, item >> 1, plain, wg, mh);
+    if (s_last) match_event<NT>(D, S, P, item >> 1, plain, wg, mh);
     __syncthreads();
   }
 }
@@ -1338,6 +1353,8 @@ __global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
     Counters *c = S.cnt;
     c->seed_queue = 0; c->match_queue = 0; c->flags = 0;
     c->pool_top = 0; c->lpool_top = 0;
+    c->big_queue = 0; c->n_big = 0;
+    for (int k = 0; k < 8; ++k) c->need_big[k] = 0;
     c->need_trip = c->need_cand = c->need_tbl = c->need_sst = 0;
     c->need_ms = c->need_vs = c->need_surv = c->need_combo = 0;
     c->total_seeds = 0; c->total_longs = 0;
@@ -1345,22 +1362,113 @@ __global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
   }
   for (int e = threadIdx.x; e < ne; e += blockDim.x) S.ev_done[e] = 0;
   if (plain) return;
-  if (threadIdx.x < 32) hist[threadIdx.x] = 0;
+  // Size classes are log2 buckets.  The big-item form takes every class from
+  // a cut B upwards; it runs before the main form.  B is chosen by a latency
+  // model of one item on a 256-thread workgroup, L(n) = a n + b n^2 (us):
+  // T(B) = max(L_max(>=B) / r, W(>=B) / (r S_big)) + max(L_max(<B), W(<B) / S_main),
+  // r the speed-up of the 16-wave form, S the workgroups of each form, W the
+  // summed latencies; "no big form" is B = 32.  The Hough variant keeps every
+  // item in the main form.  Order: big classes, then the rest, longest first.
+  __shared__ float wsum[32];
+  __shared__ int mx[32];
+  if (threadIdx.x < 32) { hist[threadIdx.x] = 0; wsum[threadIdx.x] = 0.0f; mx[threadIdx.x] = 0; }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int sz = max(zo[(i + 1) * kNL] - zo[i * kNL], 0);
-    atomicAdd(&hist[31 - __clz(sz + 1)], 1);
+  const DevParams &P = K->P;
+  auto latency = [&](float nh) { return P.lat_a * nh + P.lat_b * nh * nh; };
+  // per-class count, summed latency and largest size; a wave whose items
+  // share one class (the common case) adds them up first and updates once
+  for (int i0 = 0; i0 < n; i0 += blockDim.x) {
+    const int i = i0 + (int)threadIdx.x;
+    const bool in = i < n;
+    const int sz = in ? max(zo[(i + 1) * kNL] - zo[i * kNL], 0) : 0;
+    const int b = 31 - __clz(sz + 1);
+    const float w = in ? latency((float)sz) : 0.0f;
+    const unsigned long long act = __ballot(in);
+    if (act == 0ull) continue;
+    const int b0 = __shfl(b, __builtin_ctzll(act), 64);
+    if (__ballot(in && b != b0) == 0ull) {
+      float ws = w;
+      int c = in ? 1 : 0, m = sz;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        ws += __shfl_xor(ws, o, 64);
+        c += __shfl_xor(c, o, 64);
+        m = max(m, __shfl_xor(m, o, 64));
+      }
+      if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&hist[b0], c);
+        atomicAdd(&wsum[b0], ws);
+        atomicMax(&mx[b0], m);
+      }
+    } else if (in) {
+      atomicAdd(&hist[b], 1);
+      atomicAdd(&wsum[b], w);
+      atomicMax(&mx[b], sz);
+    }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int b = 31; b >= 0; --b) { base[b] = acc; acc += hist[b]; }
+  // the cut: wave 0, one lane per class; prefix maximum of the latencies
+  // below a class, suffix sum and maximum from it upwards, then the argmin
+  // of T over the lanes (ties to the higher cut)
+  if (threadIdx.x < 64) {
+    const int b = threadIdx.x;
+    const bool v = b < 32;
+    const float lm = v && hist[b] ? latency((float)mx[b]) : 0.0f;
+    const float ws = v ? wsum[b] : 0.0f;
+    float wtot = ws, lall = lm, pre = lm, wsuf = ws, lsuf = lm;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      wtot += __shfl_xor(wtot, o, 64);
+      lall = fmaxf(lall, __shfl_xor(lall, o, 64));
+    }
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+      const float t0 = __shfl_up(pre, o, 64);
+      const float t1 = __shfl_down(wsuf, o, 64), t2 = __shfl_down(lsuf, o, 64);
+      if (b >= o) pre = fmaxf(pre, t0);
+      if (b + o < 32) { wsuf += t1; lsuf = fmaxf(lsuf, t2); }
+    }
+    float l_lo = __shfl_up(pre, 1, 64);
+    if (b == 0) l_lo = 0.0f;
+    const float r = P.big_speedup, sb = (float)max(P.big_slots, 1), sm = (float)max(P.main_slots, 1);
+    const float t_none = fmaxf(lall, wtot / sm);
+    float t = __builtin_inff();
+    if (v && b >= kBigBucket && P.uv_mode == 0 && wsuf > 0.0f)
+      t = fmaxf(lsuf / r, wsuf / (r * sb)) + fmaxf(l_lo, (wtot - wsuf) / sm);
+    float tb = t;
+    int bb = t < t_none ? b : 32;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const float ot = __shfl_xor(tb, o, 64);
+      const int ob = __shfl_xor(bb, o, 64);
+      if (ot < tb || (ot == tb && ob > bb)) { tb = ot; bb = ob; }
+    }
+    if (b == 0) {
+      const int best = tb < t_none ? bb : 32;
+      int acc = 0;
+      for (int k = 31; k >= 0; --k) { base[k] = acc; acc += hist[k]; }
+      S.cnt->n_big = best < 32 ? (unsigned)base[best - 1] : 0u;   // classes >= best
+    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int sz = max(zo[(i + 1) * kNL] - zo[i * kNL], 0);
-    const int p = atomicAdd(&base[31 - __clz(sz + 1)], 1);
-    S.item_order[p] = i;
+  // positions in the order, one atomic per wave when its items share a class
+  for (int i0 = 0; i0 < n; i0 += blockDim.x) {
+    const int i = i0 + (int)threadIdx.x;
+    const bool in = i < n;
+    const int sz = in ? max(zo[(i + 1) * kNL] - zo[i * kNL], 0) : 0;
+    const int b = 31 - __clz(sz + 1);
+    const unsigned long long act = __ballot(in);
+    if (act == 0ull) continue;
+    const int b0 = __shfl(b, __builtin_ctzll(act), 64);
+    if (__ballot(in && b != b0) == 0ull) {
+      const unsigned r = lane_rank(act);
+      int p = 0;
+      if (r == 0 && in) p = atomicAdd(&base[b0], __popcll(act));
+      p = __shfl(p, __builtin_ctzll(act), 64);
+      if (in) S.item_order[p + (int)r] = i;
+    } else if (in) {
+      S.item_order[atomicAdd(&base[b], 1)] = i;
+    }
   }
 }
 
@@ -1433,7 +1541,11 @@ __global__ void k_plain_totals(const Desc *__restrict__ D, const KCtx *__restric
 using namespace smk;
 
 size_t smk_seed_lds_bytes(int lds_hits) {
-  const size_t a = sizeof(SeedShared) + (size_t)lds_hits * 2 * sizeof(float);
+  const size_t a = sizeof(SeedShared<kSeedWG>) + (size_t)lds_hits * 2 * sizeof(float);
+  return a > sizeof(MatchShared) ? a : sizeof(MatchShared);
+}
+size_t smk_seed_big_lds_bytes(int lds_hits) {
+  const size_t a = sizeof(SeedShared<kBigWG>) + (size_t)lds_hits * 2 * sizeof(float);
   return a > sizeof(MatchShared) ? a : sizeof(MatchShared);
 }
 
@@ -1445,12 +1557,21 @@ int smk_launch_prepare(const Desc *d, const KCtx *k, int plain, hipStream_t st) 
 int smk_launch_seed(const Desc *d, const KCtx *k, int item_begin, int item_count, int use_queue,
                     int grid, int lds_hits, int plain, int uv_mode, hipStream_t st) {
   if (uv_mode == 1)
-    hipLaunchKernelGGL(k_seed<1>, dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits), st, d,
-                       k, item_begin, item_count, use_queue, lds_hits, plain);
+    hipLaunchKernelGGL((k_seed<1, kSeedWG>), dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits),
+                       st, d, k, item_begin, item_count, use_queue, lds_hits, plain);
   else
-    hipLaunchKernelGGL(k_seed<0>, dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits), st, d,
-                       k, item_begin, item_count, use_queue, lds_hits, plain);
+    hipLaunchKernelGGL((k_seed<0, kSeedWG>), dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits),
+                       st, d, k, item_begin, item_count, use_queue, lds_hits, plain);
   return (int)hipGetLastError();
+}
+int smk_launch_seed_big(const Desc *d, const KCtx *k, int grid, int lds_hits, hipStream_t st) {
+  hipLaunchKernelGGL((k_seed<0, kBigWG>), dim3(grid), dim3(kBigWG),
+                     smk_seed_big_lds_bytes(lds_hits), st, d, k, 0, -1, 1, lds_hits, 0);
+  return (int)hipGetLastError();
+}
+int smk_seed_big_lds_limit(int bytes) {
+  return (int)hipFuncSetAttribute((const void *)k_seed<0, kBigWG>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 int smk_launch_offsets(const Desc *d, const KCtx *k, hipStream_t st) {
   hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, st, d, k);

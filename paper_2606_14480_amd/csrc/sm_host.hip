@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -38,7 +39,9 @@ struct Slot {
   smk::KCtx *d_kctx = nullptr;  // scratch pointers + parameters, device copy
   Counters *h_cnt = nullptr;  // pinned
   Scratch S{};
+  Scratch SB{};     // big-item form
   Caps caps;
+  Caps caps_big;
   // captured batched sequence, one per LDS hit capacity used so far; kernel
   // arguments are the slot's fixed descriptor and context pointers, so a
   // graph stays valid when scratch is reallocated
@@ -68,6 +71,7 @@ struct sm_ctx {
   sm_config cfg{};
   DevParams dp{};
   int seed_wgs = 0, match_wgs = 0;
+  int big_wgs = 0, lds_big = 0;  // big-item form: workgroups (one per CU) and LDS hits
   std::vector<Slot> slots;  // slots[0]: blocking calls; 1..: serving
   int64_t next_ticket = 1;
   std::mutex mu;
@@ -216,14 +220,45 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
   A(S.best_v, G * k.vs);
   A(S.surv, G * 2 * (size_t)k.surv);
   A(S.cnt, 1);
+  // big-item form: its own per-workgroup arrays, everything else shared
+  Scratch &B = s.SB;
+  B = S;
+  const size_t GB = (size_t)std::max(c->big_wgs, 1);
+  const Caps &kb = s.caps_big;
+  A(B.trip, GB * kb.trip);
+  A(B.cand, GB * kb.cand);
+  A(B.tbl, GB * kb.tbl);
+  A(B.sst, GB * kb.sst);
+  A(B.combo, GB * kb.combo);
+  A(B.cscore, GB * kb.cand);
+  A(B.cinfo, GB * kb.cand);
+  A(B.bestn, GB * kb.cand);
+  A(B.bestchi, GB * kb.cand);
+  A(B.bestidx, GB * kb.cand);
+  A(B.ms, GB * kb.ms);
+  A(B.mf, GB * 6 * (size_t)kb.ms);
+  A(B.best_s, GB * kb.ms);
+  A(B.best_v, GB * kb.vs);
+  A(B.surv, GB * 2 * (size_t)kb.surv);
 #undef A
   S.trip_cap = k.trip; S.cand_cap = k.cand; S.tbl_cap = k.tbl; S.sst_cap = k.sst;
   S.combo_cap = k.combo;
   S.pool_cap = k.pool; S.lpool_cap = k.lpool;
   S.ms_cap = k.ms; S.vs_cap = k.vs; S.surv_cap = k.surv;
+  B.trip_cap = kb.trip; B.cand_cap = kb.cand; B.tbl_cap = kb.tbl; B.sst_cap = kb.sst;
+  B.combo_cap = kb.combo;
+  B.ms_cap = kb.ms; B.vs_cap = kb.vs; B.surv_cap = kb.surv;
+  B.item_order = S.item_order; B.item_cnt = S.item_cnt; B.item_base = S.item_base;
+  B.ev_lcnt = S.ev_lcnt; B.ev_lbase = S.ev_lbase; B.ev_done = S.ev_done;
+  B.pool = S.pool; B.lpool = S.lpool; B.pool_cap = S.pool_cap; B.lpool_cap = S.lpool_cap;
+  B.cnt = S.cnt;
+  // device addresses inside the counters (address arithmetic only)
+  S.need = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(S.cnt) + offsetof(Counters, need_trip));
+  B.need = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(S.cnt) + offsetof(Counters, need_big));
   c->bytes += bytes;
   smk::KCtx kc;
   kc.S = S;
+  kc.SB = B;
   kc.P = c->dp;
   if (hipMemcpy(s.d_kctx, &kc, sizeof(kc), hipMemcpyHostToDevice) != hipSuccess) return SM_ERR_DEVICE;
   if (c->cfg.mem_budget > 0 && bytes > c->cfg.mem_budget) return SM_ERR_OOM;
@@ -298,6 +333,7 @@ sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
   auto seq = [&](hipStream_t q) -> hipError_t {
     int e = smk_launch_prepare(d, S, 0, q);
     if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
+    if (!e && c->p.uv_mode == 0) e = smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, q);
     if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
     if (!e) e = smk_launch_offsets(d, S, q);
     if (!e) e = smk_launch_copy(d, S, 1024, q);
@@ -343,6 +379,7 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   if (!e) e = smk_launch_prepare(d, S, 0, q);
   if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
   if (!e) e = hipEventRecord(ev[1], q);
+  if (!e && c->p.uv_mode == 0) e = smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, q);
   if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
   if (!e) e = hipEventRecord(ev[2], q);
   if (!e) e = smk_launch_offsets(d, S, q);
@@ -363,14 +400,21 @@ bool needs_rerun(sm_ctx *c, Slot &s, sm_status &st) {
   if (f & smk::F_LIMIT) { st = SM_ERR_LIMIT; return false; }
   bool re = false;
   Caps &cp = s.caps;
-  if (f & smk::F_TRIP) re |= grow(cp.trip, k.need_trip);
-  if (f & smk::F_CAND) re |= grow(cp.cand, k.need_cand);
-  if (f & smk::F_TBL) re |= grow(cp.tbl, k.need_tbl);
-  if (f & smk::F_SST) re |= grow(cp.sst, k.need_sst);
-  if (f & smk::F_COMBO) re |= grow(cp.combo, k.need_combo);
-  if (f & smk::F_MS) re |= grow(cp.ms, k.need_ms);
-  if (f & smk::F_VS) re |= grow(cp.vs, k.need_vs);
-  if (f & smk::F_SURV) re |= grow(cp.surv, k.need_surv);
+  // each form's scratch grows to what its own items needed
+  auto grow_caps = [&](Caps &q, const unsigned *n) {
+    bool r = false;
+    if ((f & smk::F_TRIP) && n[0] > (unsigned)q.trip) r |= grow(q.trip, n[0]);
+    if ((f & smk::F_CAND) && n[1] > (unsigned)q.cand) r |= grow(q.cand, n[1]);
+    if ((f & smk::F_TBL) && n[2] > (unsigned)q.tbl) r |= grow(q.tbl, n[2]);
+    if ((f & smk::F_SST) && n[3] > (unsigned)q.sst) r |= grow(q.sst, n[3]);
+    if ((f & smk::F_MS) && n[4] > (unsigned)q.ms) r |= grow(q.ms, n[4]);
+    if ((f & smk::F_VS) && n[5] > (unsigned)q.vs) r |= grow(q.vs, n[5]);
+    if ((f & smk::F_SURV) && n[6] > (unsigned)q.surv) r |= grow(q.surv, n[6]);
+    if ((f & smk::F_COMBO) && n[7] > (unsigned)q.combo) r |= grow(q.combo, n[7]);
+    return r;
+  };
+  re |= grow_caps(cp, &k.need_trip);
+  re |= grow_caps(s.caps_big, k.need_big);
   if (f & smk::F_POOL) { cp.pool = std::max<long long>(2 * cp.pool, (long long)k.pool_top + 1024); re = true; }
   if (f & smk::F_LPOOL) { cp.lpool = std::max<long long>(2 * cp.lpool, (long long)k.lpool_top + 1024); re = true; }
   if (re) {
@@ -515,8 +559,31 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
   hipGetDeviceProperties(&prop, c->device);
   const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   c->seed_wgs = c->cfg.seed_wgs > 0 ? c->cfg.seed_wgs : cus * 4;
+  // big-item form: one 1024-thread workgroup per CU, hits in LDS up to what
+  // the per-workgroup LDS limit leaves after its shared state
+  c->big_wgs = std::max(cus / 2, 1);
+  {
+    const size_t lim = prop.sharedMemPerBlock > 0 ? (size_t)prop.sharedMemPerBlock : 65536;
+    const size_t base = smk_seed_big_lds_bytes(0);
+    long long h = lim > base ? (long long)((lim - base) / 8) : 0;
+    h = std::min<long long>(h, 12288) / 256 * 256;
+    c->lds_big = (int)std::max<long long>(h, 256);
+    if (smk_seed_big_lds_bytes(c->lds_big) > 65536 &&
+        smk_seed_big_lds_limit((int)smk_seed_big_lds_bytes(c->lds_big)) != 0) {
+      (void)hipGetLastError();
+      const size_t b64 = 65536 > base ? (65536 - base) / 8 / 256 * 256 : 0;
+      c->lds_big = (int)std::max<size_t>(b64, 256);
+    }
+  }
   c->match_wgs = c->cfg.match_wgs > 0 ? c->cfg.match_wgs : cus * 2;
   c->dp = make_params(c->g, c->p);
+  // item latency on one 256-thread workgroup, fitted to phase timers on
+  // min-bias (778 hits: 93 us) and stress items (12,011 hits: 13.9 ms)
+  c->dp.main_slots = c->seed_wgs;
+  c->dp.big_slots = c->big_wgs;
+  c->dp.lat_a = 0.048f;
+  c->dp.lat_b = 9.2e-5f;
+  c->dp.big_speedup = 3.0f;   // 16 waves against 4 on the same item
   const int n_slots = 1 + (c->cfg.n_slots > 0 ? c->cfg.n_slots : 2);
   c->slots.resize(n_slots);
   for (Slot &s : c->slots) {

@@ -320,3 +320,33 @@ def test_hough_uv_refused(sm):
     with pytest.raises(sm.SmError) as e:
         sm.Context(params=sm.default_params(uv_mode=1))
     assert e.value.status == sm.ERR_INVALID
+
+
+def big_item_batch():
+    """40 min-bias events around the largest event of the first 200 stress
+    events, so that one item would outlast the rest of the batch."""
+    stress = ev.generate(ev.config(4, n_events=200))
+    sizes = np.diff(stress.zone_off[::12].astype(np.int64))
+    e = int(np.argmax(sizes)) // 2
+    mb = ev.generate(ev.config(2, n_events=40))
+    return ev.concat([mb.event(i) for i in range(20)] + [stress.event(e)] +
+                     [mb.event(i) for i in range(20, 40)])
+
+
+def test_big_items_batched_equals_plain(sm, ctx):
+    """A dominating item runs in the big-item form (1024-thread workgroup,
+    own scratch) in the batched call and in the 256-thread form in the
+    per-event call; both give the same bytes, and the oracle agrees."""
+    b = big_item_batch()
+    sizes = np.diff(b.zone_off[::12].astype(np.int64))
+    say("[gpu] big items: largest item", int(sizes.max()), "hits")
+    assert sizes.max() >= 8191
+    g1 = gpu_run(sm, ctx, b)
+    g2 = gpu_run(sm, ctx, b, plain=True)
+    for x, y in zip(g1, g2):
+        assert x.tobytes() == y.tobytes()
+
+
+def test_big_items_parity(orc, sm, ctx):
+    b = big_item_batch()
+    check(orc, sm, ctx, b, "batch with a dominating item")
