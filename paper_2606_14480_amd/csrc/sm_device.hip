@@ -724,7 +724,48 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   // bit-identical scores, which filters the comparison: one wave takes one
   // iteration-1 track, ballots 64 list entries at a time on the score, and
   // compares hit sets (one slot per lane) only where the score matches.
-  {
+  if constexpr (kSmall) {
+    // LDS records: a hash table keyed by score over the kept iteration-0
+    // tracks (in the vote table's LDS, free once own counts are taken), at
+    // most half full, so a probe always ends at an empty slot
+    constexpr int kHT = 2 * kCandLds;
+    static_assert(kHT * (sizeof(unsigned long long) + sizeof(int)) <=
+                      kXtabLds * sizeof(unsigned long long), "hash table must fit the vote table");
+    unsigned long long *hk = sh.u.xtab;
+    int *hv = reinterpret_cast<int *>(sh.u.xtab + kHT);
+    auto slot_of = [](unsigned long long k) {
+      const unsigned x = (unsigned)(k ^ (k >> 29) ^ (k >> 43)) * 0x9E3779B1u;
+      return (int)(x >> 23);   // 9 bits: kHT = 512
+    };
+    static_assert(kHT == 512, "slot_of takes 9 bits");
+    for (int i = tid; i < kHT; i += NT) hk[i] = ~0ull;
+    __syncthreads();
+    for (unsigned j = tid; j < nc; j += NT) {
+      if (cinfo[j] & ((1 << 3) | (1 << 4))) continue;   // kept iteration-0 only
+      const unsigned long long sc = cscore[j];
+      for (int h = slot_of(sc);; h = (h + 1) & (kHT - 1)) {
+        if (atomicCAS(&hk[h], ~0ull, sc) == ~0ull) { hv[h] = (int)j; break; }
+      }
+    }
+    __syncthreads();
+    for (unsigned i = tid; i < nc; i += NT) {
+      const int ci = cinfo[i];
+      if ((ci & (1 << 4)) || !(ci & (1 << 3))) continue;   // kept iteration-1 only
+      const unsigned long long sc = cscore[i];
+      bool dup = false;
+      for (int h = slot_of(sc); !dup; h = (h + 1) & (kHT - 1)) {
+        const unsigned long long k = hk[h];
+        if (k == ~0ull) break;
+        if (k != sc) continue;
+        const unsigned j = (unsigned)hv[h];
+        bool same = true;
+#pragma unroll
+        for (int k6 = 0; k6 < 6; ++k6) same = same && xidx(j, k6) == xidx(i, k6);
+        dup = same;
+      }
+      if (dup) cinfo[i] |= 1 << 5;
+    }
+  } else {
     const int lane = tid & 63;
     for (unsigned i = tid >> 6; i < nc; i += NT / 64) {
       const int ci = cinfo[i];
