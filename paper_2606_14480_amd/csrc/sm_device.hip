@@ -180,7 +180,7 @@ struct SeedShared {
   int zlo[kNL], zhi[kNL];                // z span of each layer (Hough UV), as zkey
   int xb[7];                             // first compact x index of each x slot
   int item;
-  unsigned ntrip, ncand, nseed, ncombo;
+  unsigned ntrip, ncand, nseed, ncombo, nkept;
   unsigned long long pbase;
 };
 
@@ -716,9 +716,17 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
       if (p >= 0 && xt[p] == sc) ++own;
     }
     const int n = cinfo[i] & 7;
-    if (!(own >= 3 || (own >= 2 && n == 6))) cinfo[i] |= 1 << 4;
+    const bool kept = own >= 3 || (own >= 2 && n == 6);
+    if (!kept) cinfo[i] |= 1 << 4;
+    const unsigned long long km = __ballot(kept);
+    if (kept && lane_rank(km) == 0) atomicAdd(&sh.nkept, (unsigned)__popcll(km));
   }
   __syncthreads();
+  // the item's pool range is claimed now, for the tracks that survived the
+  // vote (at least as many as its seeds); the atomic's latency overlaps the
+  // UV search and the range may keep unused slots
+  unsigned long long pool_claim = 0;
+  if (tid == 0) pool_claim = atomicAdd(&cnt->pool_top, (unsigned long long)sh.nkept);
   // repeated tracks of the two iterations: a kept iteration-1 track whose
   // x-hit set equals a kept iteration-0 track's is dropped.  Equal sets have
   // bit-identical scores, which filters the comparison: one wave takes one
@@ -904,7 +912,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   };
   auto claim_pool = [&](unsigned ns) {
     if (tid == 0) {
-      unsigned long long b = atomicAdd(&cnt->pool_top, (unsigned long long)ns);
+      const unsigned long long b = pool_claim;
       if (b + ns > (unsigned long long)S.pool_cap) raise_flag(cnt, F_POOL);
       sh.pbase = b;
       S.item_cnt[item] = (int)ns;
@@ -1284,6 +1292,7 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
   MatchShared &mh = *reinterpret_cast<MatchShared *>(smem);
   float *s_x = reinterpret_cast<float *>(smem + sizeof(SeedShared<NT>));
   float *s_z = s_x + lds_hits;
+  int32_t *s_id = reinterpret_cast<int32_t *>(s_z + lds_hits);
   __shared__ int s_last;
 
   const int tid = threadIdx.x;
@@ -1302,7 +1311,7 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
       if (use_queue) q = (int)atomicAdd(kBig ? &S.cnt->big_queue : &S.cnt->seed_queue, 1u);
       else q = first ? (int)blockIdx.x : n_items;
       sh.item = q < n_items ? (use_queue ? S.item_order[q0 + q] : item_begin + q) : -1;
-      sh.ntrip = 0; sh.ncand = 0; sh.nseed = 0; sh.ncombo = 0;
+      sh.ntrip = 0; sh.ncand = 0; sh.nseed = 0; sh.ncombo = 0; sh.nkept = 0;
     }
     first = false;
     __syncthreads();
@@ -1336,6 +1345,7 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
       for (int i = tid; i < nh; i += NT) {
         s_x[i] = hx[base + i];
         s_z[i] = hz[base + i];
+        s_id[i] = hid[base + i];
       }
       for (int i = tid; i < kNL * kBins; i += NT) {
         const int L = i / kBins;
@@ -1356,7 +1366,7 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
         for (int b = kp; b < kc; ++b) sh.bins[L][b] = (unsigned short)li;
       }
       __syncthreads();
-      seed_item<true, kUv>(s_x, s_z, hid + base, item, nh, P, S, wg, sh);
+      seed_item<true, kUv>(s_x, s_z, s_id, item, nh, P, S, wg, sh);
     } else {
       __syncthreads();
       seed_item<false, kUv>(hx + base, hz + base, hid + base, item, nh, P, S, wg, sh);
@@ -1582,11 +1592,11 @@ __global__ void k_plain_totals(const Desc *__restrict__ D, const KCtx *__restric
 using namespace smk;
 
 size_t smk_seed_lds_bytes(int lds_hits) {
-  const size_t a = sizeof(SeedShared<kSeedWG>) + (size_t)lds_hits * 2 * sizeof(float);
+  const size_t a = sizeof(SeedShared<kSeedWG>) + (size_t)lds_hits * 3 * sizeof(float);
   return a > sizeof(MatchShared) ? a : sizeof(MatchShared);
 }
 size_t smk_seed_big_lds_bytes(int lds_hits) {
-  const size_t a = sizeof(SeedShared<kBigWG>) + (size_t)lds_hits * 2 * sizeof(float);
+  const size_t a = sizeof(SeedShared<kBigWG>) + (size_t)lds_hits * 3 * sizeof(float);
   return a > sizeof(MatchShared) ? a : sizeof(MatchShared);
 }
 

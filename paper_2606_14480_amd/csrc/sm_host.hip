@@ -565,13 +565,13 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
   {
     const size_t lim = prop.sharedMemPerBlock > 0 ? (size_t)prop.sharedMemPerBlock : 65536;
     const size_t base = smk_seed_big_lds_bytes(0);
-    long long h = lim > base ? (long long)((lim - base) / 8) : 0;
+    long long h = lim > base ? (long long)((lim - base) / 12) : 0;   // x, z, id per hit
     h = std::min<long long>(h, 12288) / 256 * 256;
     c->lds_big = (int)std::max<long long>(h, 256);
     if (smk_seed_big_lds_bytes(c->lds_big) > 65536 &&
         smk_seed_big_lds_limit((int)smk_seed_big_lds_bytes(c->lds_big)) != 0) {
       (void)hipGetLastError();
-      const size_t b64 = 65536 > base ? (65536 - base) / 8 / 256 * 256 : 0;
+      const size_t b64 = 65536 > base ? (65536 - base) / 12 / 256 * 256 : 0;
       c->lds_big = (int)std::max<size_t>(b64, 256);
     }
   }
