@@ -23,7 +23,8 @@ constexpr int kSeedWG = 256;        // threads of the seeding workgroup (4 waves
 constexpr int kCandLds = 256;       // x-z candidates whose vote records live in LDS
 constexpr int kXtabLds = 1024;      // x hits of an item with an LDS clone-vote entry
 constexpr int kSeedLds = 256;       // seeds per item ranked from LDS keys
-constexpr int kMsLds = 512;         // seeds per event whose matching state lives in LDS
+constexpr int kMsLds = 384;         // seeds per event whose matching state lives in LDS
+constexpr int kVflat = 256;         // VELO states per event for the flattened pair search
 constexpr int kVsLds = 512;         // VELO states per event with LDS best-chi2 entries
 constexpr int kSurvLds = 512;       // matching survivors kept in LDS
 constexpr int kPosBits = 21;        // item-relative hit positions < 2^21

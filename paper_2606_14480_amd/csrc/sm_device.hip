@@ -64,6 +64,14 @@ __device__ __forceinline__ int block_excl_scan(int v, int *s_tmp, int &total) {
 }
 
 // first i in [lo, hi) with X[i] >= v
+// first i in [lo, hi) with X[i] > v
+__device__ __forceinline__ int upper_f(const float *X, int lo, int hi, float v) {
+  while (lo < hi) {
+    const int m = (lo + hi) >> 1;
+    if (X[m] <= v) lo = m + 1; else hi = m;
+  }
+  return lo;
+}
 __device__ __forceinline__ int lower_f(const float *X, int lo, int hi, float v) {
   while (lo < hi) {
     const int m = (lo + hi) >> 1;
@@ -1083,6 +1091,10 @@ struct MatchShared {
   unsigned long long best_v[kVsLds];
   Surv surv[kSurvLds];
   unsigned long long kkey[kSurvLds];
+  // flattened pair search: VELO states of the event, their window starts and
+  // the scan of the window sizes
+  float vx[kVflat], vy[kVflat], vz[kVflat], vtx[kVflat], vty[kVflat];
+  int vk0[kVflat], vscan[kVflat];
   int tmp[16];
   int ev;
   unsigned nsurv, nkeep;
@@ -1174,30 +1186,72 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   }
   __syncthreads();
   Surv *surv = S.surv + wg * (size_t)(2 * S.surv_cap);
-  if (fits && ns > 0) {
+  // one pair test: the FP32 prefilter, then the FP64 evaluation
+  auto test_pair = [&](int v, int s, float xvf, float yvf, float zvf, float txvf, float tyvf,
+                       unsigned long long &bits) {
+    const float yvm = yvf + tyvf * (P.z_ymatchf - zvf);
+    const float dtx = txsf[s] - txvf;
+    if (!(fabsf(dtx) < P.pre_dtx)) return false;
+    if (!(fabsf(ymf[s] - yvm) < P.pre_dy)) return false;
+    const float zm = P.zmf[0] + P.zmf[4] * txvf * txvf + P.zmf[1] * fabsf(dtx) +
+                     P.zmf[2] * dtx * dtx + P.zmf[3] * fabsf(xsf[s]);
+    const float dx = (xsf[s] + (zm - P.z_statef) * txsf[s]) - (xvf + (zm - zvf) * txvf);
+    if (!(fabsf(dx) < P.pre_dx)) return false;
+    const PairEval r = eval_pair(ms[s], xvf, yvf, zvf, txvf, tyvf, P);
+    if (!r.ok) return false;
+    bits = (unsigned long long)__double_as_longlong(r.chi2);
+    atomicMin(&best_s[s], bits);
+    const unsigned slot = atomicAdd(&sh.nsurv, 1u);
+    if (slot < (unsigned)kSurvLds) sh.surv[slot] = Surv{v, s, r.chi2};
+    else if (slot < (unsigned)(kSurvLds + S.surv_cap)) surv[slot - kSurvLds] = Surv{v, s, r.chi2};
+    return true;
+  };
+  if (fits && ns > 0 && kSmallM && nv <= kVflat && nv <= NT) {
+    // every (VELO state, seed in its t_y window) pair gets its own thread:
+    // window bounds per VELO state, a scan of the window sizes, then the
+    // pairs in rounds of NT
+    int cnt_v = 0;
+    if (tid < nv) {
+      const int v = tid;
+      const float tyvf = D->b.velo_ty[v0 + v];
+      sh.vx[v] = D->b.velo_x[v0 + v];
+      sh.vy[v] = D->b.velo_y[v0 + v];
+      sh.vz[v] = D->b.velo_z[v0 + v];
+      sh.vtx[v] = D->b.velo_tx[v0 + v];
+      sh.vty[v] = tyvf;
+      const int k0 = lower_f(sty, 0, ns, tyvf - P.pre_dty);
+      const int k1 = upper_f(sty, k0, ns, tyvf + P.pre_dty);
+      sh.vk0[v] = k0;
+      cnt_v = k1 - k0;
+      best_v[v] = ~0ull;
+    }
+    int total;
+    const int ex = block_excl_scan<NT>(cnt_v, sh.tmp, total);
+    if (tid < nv) sh.vscan[tid] = ex;
+    __syncthreads();
+    for (int d0 = 0; d0 < total; d0 += NT) {
+      const int d = d0 + tid;
+      if (d >= total) continue;
+      int lo = 0, hi = nv;
+      while (lo < hi) {
+        const int m = (lo + hi) >> 1;
+        if (sh.vscan[m] <= d) lo = m + 1; else hi = m;
+      }
+      const int v = lo - 1;
+      const int s = sidx[sh.vk0[v] + (d - sh.vscan[v])];
+      unsigned long long bits;
+      if (test_pair(v, s, sh.vx[v], sh.vy[v], sh.vz[v], sh.vtx[v], sh.vty[v], bits))
+        atomicMin(&best_v[v], bits);
+    }
+  } else if (fits && ns > 0) {
     for (int v = tid; v < nv; v += NT) {
       const float xvf = D->b.velo_x[v0 + v], yvf = D->b.velo_y[v0 + v], zvf = D->b.velo_z[v0 + v];
       const float txvf = D->b.velo_tx[v0 + v], tyvf = D->b.velo_ty[v0 + v];
-      const float yvm = yvf + tyvf * (P.z_ymatchf - zvf);
-      const float zmv = P.zmf[0] + P.zmf[4] * txvf * txvf;
       unsigned long long bv = ~0ull;
       const float thi = tyvf + P.pre_dty;
       for (int k = lower_f(sty, 0, ns, tyvf - P.pre_dty); k < ns && sty[k] <= thi; ++k) {
-        const int s = sidx[k];
-        const float dtx = txsf[s] - txvf;
-        if (!(fabsf(dtx) < P.pre_dtx)) continue;
-        if (!(fabsf(ymf[s] - yvm) < P.pre_dy)) continue;
-        const float zm = zmv + P.zmf[1] * fabsf(dtx) + P.zmf[2] * dtx * dtx + P.zmf[3] * fabsf(xsf[s]);
-        const float dx = (xsf[s] + (zm - P.z_statef) * txsf[s]) - (xvf + (zm - zvf) * txvf);
-        if (!(fabsf(dx) < P.pre_dx)) continue;
-        const PairEval r = eval_pair(ms[s], xvf, yvf, zvf, txvf, tyvf, P);
-        if (!r.ok) continue;
-        const unsigned long long bits = (unsigned long long)__double_as_longlong(r.chi2);
-        bv = bits < bv ? bits : bv;
-        atomicMin(&best_s[s], bits);
-        const unsigned slot = atomicAdd(&sh.nsurv, 1u);
-        if (slot < (unsigned)kSurvLds) sh.surv[slot] = Surv{v, s, r.chi2};
-        else if (slot < (unsigned)(kSurvLds + S.surv_cap)) surv[slot - kSurvLds] = Surv{v, s, r.chi2};
+        unsigned long long bits;
+        if (test_pair(v, sidx[k], xvf, yvf, zvf, txvf, tyvf, bits)) bv = bits < bv ? bits : bv;
       }
       best_v[v] = bv;
     }
