@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--events", type=int, default=0,
                     help="events per batch (default: the workload's own size)")
     ap.add_argument("--workload", default="minbias", choices=("minbias", "uneven", "stress"))
+    ap.add_argument("--p-min", type=float, default=0.0,
+                    help="minimum momentum the windows are opened for, MeV/c (0: the default 3 GeV)")
     ap.add_argument("--parity-events", type=int, default=2000,
                     help="events of the batch checked against the oracle")
     ap.add_argument("--plain-steps", type=int, default=3)
@@ -159,7 +161,8 @@ def main():
     host = ev.generate(cfg)
     log(f"[bench] generated {host.n_events} events, {host.n_hits} hits, {host.n_velo} VELO "
         f"states in {time.perf_counter() - t0:.1f} s")
-    ctx = sm.Context(n_slots=SERVE_SLOTS)
+    over = {"p_min": args.p_min} if args.p_min > 0 else {}
+    ctx = sm.Context(params=sm.default_params(**over), n_slots=SERVE_SLOTS)
     db = sm.DeviceBatch(host)
     out = sm.DeviceOut(host.n_events, host.n_hits // 4 + 1024, host.n_velo + 1024)
     stream = torch.cuda.current_stream()
@@ -174,12 +177,12 @@ def main():
         npar = min(host.n_events, args.parity_events)
         sub = host if npar == host.n_events else host.subset(range(npar))
         g_sub = (gpu[0][:npar + 1], gpu[1][:gpu[0][npar]], gpu[2][:npar + 1], gpu[3][:gpu[2][npar]])
-        o = O.run(sub, threads=os.cpu_count())
+        o = O.run(sub, O.default_params(**over), threads=os.cpu_count())
         st = PT.compare(o, g_sub, npar)
         if st["mismatches"]:
             st = PT.compare(o, g_sub, npar, band=(
-                O.run(sub, PT.eps_params(O, 1e-4), threads=os.cpu_count()),
-                O.run(sub, PT.eps_params(O, -1e-4), threads=os.cpu_count())))
+                O.run(sub, PT.eps_params(O, 1e-4, **over), threads=os.cpu_count()),
+                O.run(sub, PT.eps_params(O, -1e-4, **over), threads=os.cpu_count())))
         parity = {"events_checked": npar, "seed_jaccard": round(st["seed_jaccard"], 6),
                   "long_jaccard": round(st["long_jaccard"], 6),
                   "mismatches": st["mismatches"], "unexplained": len(st["unexplained"]),
@@ -250,7 +253,8 @@ def main():
                    "events_per_batch": host.n_events, "hits": host.n_hits,
                    "velo_states": host.n_velo, "seeds": n_seeds, "long_tracks": n_longs,
                    "form": "batched: captured graph, persistent kernels, LPT work queue",
-                   "search_dtype": "f32", "fit_dtype": "f64"},
+                   "search_dtype": "f32", "fit_dtype": "f64",
+                   "p_min_mev": float(args.p_min) if args.p_min > 0 else 3000.0},
         "plain_events_per_s": round(plain, 1) if plain else None,
         "batched_over_plain": round(value / plain, 2) if plain else None,
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),

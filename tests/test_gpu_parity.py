@@ -350,3 +350,21 @@ def test_big_items_batched_equals_plain(sm, ctx):
 def test_big_items_parity(orc, sm, ctx):
     b = big_item_batch()
     check(orc, sm, ctx, b, "batch with a dominating item")
+
+
+@pytest.mark.parametrize("p_min", [1500.0, 2000.0, 5000.0])
+def test_p_min_scan(orc, sm, p_min):
+    """The window constants follow the minimum momentum (eq. tolHp, eq.
+    alphacorr): parity at several p_min on min-bias events, and fewer seeds
+    as p_min rises."""
+    b = ev.generate(ev.config(2, n_events=100))
+    c = sm.Context(params=sm.default_params(p_min=p_min))
+    try:
+        g, o, st = check(orc, sm, c, b, f"p_min {p_min / 1000:.1f} GeV", params_over=dict(p_min=p_min))
+    finally:
+        c.close()
+    ref = orc.run(b, orc.default_params(), threads=8)
+    if p_min < 3000.0:
+        assert st["seeds_g"] >= len(ref.seeds)
+    else:
+        assert st["seeds_g"] <= len(ref.seeds)
