@@ -220,13 +220,36 @@ template <bool kLds, int NT>
 __device__ __forceinline__ int zclosest(const float *X, const SeedShared<NT> &sh, int L, double pred,
                                         double tol) {
   const int hi = sh.zoff[L + 1];
+  const double lo_v = pred - tol, hi_v = pred + tol;
   int best = -1;
   double bd = 0.0;
-  for (int i = zlower<kLds>(X, sh, L, pred - tol); i < hi; ++i) {
-    const double x = X[i];
-    if (x > pred + tol) break;
-    const double d = fabs(x - pred);
-    if (best < 0 || d < bd - kTieMm) { best = i; bd = d; }
+  if constexpr (kLds) {
+    // from the bin of pred - tol, four hits per LDS round trip; the same
+    // comparisons in the same order as the one-hit walk
+    const int k = kbin((float)lo_v);
+    int i = sh.zoff[L] + (k > 0 ? (int)sh.bins[L][k - 1] : 0);
+    for (; i < hi; i += 4) {
+      float x4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x4[q] = i + q < hi ? X[i + q] : __builtin_inff();
+      bool done = false;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double x = x4[q];
+        if (done || x < lo_v) continue;
+        if (x > hi_v) { done = true; continue; }
+        const double d = fabs(x - pred);
+        if (best < 0 || d < bd - kTieMm) { best = i + q; bd = d; }
+      }
+      if (done) break;
+    }
+  } else {
+    for (int i = zlower<kLds>(X, sh, L, lo_v); i < hi; ++i) {
+      const double x = X[i];
+      if (x > hi_v) break;
+      const double d = fabs(x - pred);
+      if (best < 0 || d < bd - kTieMm) { best = i; bd = d; }
+    }
   }
   return best;
 }
