@@ -109,7 +109,14 @@ typedef struct {
   int32_t device;          /* HIP device ordinal */
   int32_t n_slots;         /* concurrent serving slots (sm_submit), default 2 */
   int32_t seed_wgs;        /* persistent workgroups of the seeding kernel (0: auto) */
-  int32_t match_wgs;       /* reserved (matching runs inside the seeding kernel) */
+  int32_t match_wgs;       /* where batched Matching runs.  0: chosen per batch: a
+                              matching kernel of seed_wgs workgroups after the
+                              seeding kernels, or, when the batch has items for
+                              the big-item form, inside the seeding kernel (the
+                              workgroup completing an event matches it); > 0:
+                              always the matching kernel, with this many
+                              workgroups (at most seed_wgs); < 0: always inside
+                              the seeding kernel.  Outputs are identical. */
   int32_t lds_hits;        /* per-workgroup LDS hit budget (0: auto) */
   int32_t validate;        /* 1: check offsets and x-sorting before each batch */
   int64_t mem_budget;      /* bytes of device memory the context may hold (0: no cap) */
@@ -202,9 +209,11 @@ sm_status sm_submit(sm_ctx *ctx, const sm_batch *batch, sm_out *out, int64_t *ti
 sm_status sm_poll(sm_ctx *ctx, int64_t ticket, int wait);
 
 /* Per-kernel device time of one batched run, from HIP events recorded on
- * `stream` between the kernels (milliseconds): counters and item order,
- * the persistent Seeding + Matching kernel, the offset scans, the copy to
- * the caller's buffers, and the whole sequence. */
+ * `stream` between the kernels (milliseconds): counters and item order;
+ * Seeding and Matching (the seeding kernels and, when the batch uses it, the
+ * matching kernel); offsets, now always 0 (the offset scans run inside the
+ * copy kernel); the offsets and copy to the caller's buffers; and the whole
+ * sequence. */
 typedef struct {
   float prepare, seed_match, offsets, copy, total;
 } sm_kernel_times;

@@ -8,8 +8,10 @@
 //              XZ seeding (both iterations), the clone vote and UV seeding of
 //              one detector half of one event, hits staged in LDS; the
 //              workgroup that completes an event's second half matches it
-//   k_offsets  per-event seed and long-track offsets (exclusive scans)
-//   k_copy     seeds and long tracks from the pools to the caller's CSR
+//   k_match    (when chosen for the batch) Matching of every event, after
+//              all seeding, instead of the hand-off inside k_seed
+//   k_copy     per-event offsets (scans) and the seeds and long tracks from
+//              the pools to the caller's CSR
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -55,7 +57,7 @@ enum : unsigned {
 
 struct Counters {
   unsigned seed_queue, match_queue;
-  unsigned flags, pad0;
+  unsigned flags, fuse;           // fuse: matching inside the seeding kernel (else k_match)
   unsigned long long pool_top, lpool_top;
   unsigned need_trip, need_cand, need_tbl, need_sst;
   unsigned need_ms, need_vs, need_surv, need_combo;
@@ -101,6 +103,7 @@ struct DevParams {
   int uv_mode, hough_bins, hough_best, hough_fine, hough_min;
   // scheduling: main-form workgroups and the item latency model (us, n = hits)
   int main_slots, big_slots;
+  int match_mode;   // 0: automatic, 1: matching kernel, -1: matching inside the seeding kernel
   float lat_a, lat_b, big_speedup;
   double hough_lo[2], hough_hi[2];
 };
@@ -137,6 +140,15 @@ struct Combo {
   int pos[6];
 };
 
+// One position of the longest-first item order: the item and its zone
+// offsets in the batch, read by the workgroup that takes the position in one
+// round trip.
+struct ItemRec {
+  int item;
+  int zabs[kNL + 1];
+  int pad[2];
+};
+
 // Library-owned scratch of one slot.
 struct Scratch {
   unsigned long long *trip;  // [seed_wgs][trip_cap]
@@ -147,7 +159,8 @@ struct Scratch {
   unsigned long long *cscore, *bestchi;  // [seed_wgs][cand_cap], items with many candidates
   int *cinfo, *bestn, *bestidx;          // [seed_wgs][cand_cap]
   int trip_cap, cand_cap, tbl_cap, sst_cap, combo_cap, pad2;
-  int *item_order, *item_cnt, *item_base;  // [items_cap]
+  ItemRec *item_rec;                       // [items_cap]
+  int *item_cnt, *item_base;               // [items_cap]
   int *ev_lcnt, *ev_lbase, *ev_done;       // [events_cap]
   sm_seed *pool;
   sm_long *lpool;
@@ -185,8 +198,8 @@ int smk_launch_seed(const smk::Desc *d, const smk::KCtx *k, int item_begin, int 
                     hipStream_t st);
 int smk_launch_seed_big(const smk::Desc *d, const smk::KCtx *k, int grid, int lds_hits,
                         hipStream_t st);
+int smk_launch_match(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 int smk_seed_big_lds_limit(int bytes);
-int smk_launch_offsets(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
 int smk_launch_copy(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 int smk_launch_validate(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 int smk_launch_plain_totals(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);

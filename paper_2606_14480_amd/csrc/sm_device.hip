@@ -172,7 +172,8 @@ struct SeedShared {
   int cinfo[kCandLds];                   // n | it << 3 | lost << 4 | repeat << 5
   unsigned short cpos[kCandLds][6];      // x-hit positions + 1 (0: none)
   union {
-    unsigned long long xtab[kXtabLds];   // clone-vote table over the item's x hits
+    unsigned long long xtab[kXtabLds];   // clone-vote table over the item's x hits; before
+                                         // the vote, the first kTripLds triplets
     struct {
       double cabc[kCandLds][3];          // x-z parameters for UV
       unsigned long long bestchi[kCandLds];
@@ -191,6 +192,9 @@ struct SeedShared {
   unsigned ntrip, ncand, nseed, ncombo, nkept;
   unsigned long long pbase;
 };
+
+// triplets kept in LDS (the vote table's space, unused until the vote)
+constexpr int kTripLds = kXtabLds;
 
 // first i of zone L with X[i] >= v
 template <bool kLds, class T, int NT>
@@ -258,7 +262,8 @@ __device__ __forceinline__ int zclosest(const float *X, const SeedShared<NT> &sh
 // FP32.  The T1 hits of both iterations form one list taken 256 at a time;
 // each thread finds the T3 window of its T1 hit, a workgroup scan flattens
 // the doublets so every thread gets an equal share, and the T2 hits found
-// for a doublet are appended with one atomic per wave.
+// for a doublet are appended with one atomic per wave, the first kTripLds
+// triplets to LDS and the rest to the workgroup's global scratch.
 template <bool kLds, int NT>
 __device__ __forceinline__ void xz_triplets(const float *X, const float *Z, SeedShared<NT> &sh,
                                             const DevParams &P, unsigned long long *trip,
@@ -334,7 +339,9 @@ __device__ __forceinline__ void xz_triplets(const float *X, const float *Z, Seed
                                         ((unsigned long long)d3 << 21);
         while (more) {
           const unsigned slot = wave_append(&sh.ntrip);
-          if (slot < (unsigned)trip_cap) trip[slot] = head | (unsigned long long)k;
+          const unsigned long long v = head | (unsigned long long)k;
+          if (slot < (unsigned)kTripLds) sh.u.xtab[slot] = v;
+          else if (slot < (unsigned)trip_cap) trip[slot] = v;
           ++k;
           more = k < e2 && X[k] <= hi2;
         }
@@ -921,8 +928,10 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   __syncthreads();
   // the seed record of winning combination i
   auto make_seed = [&](unsigned i) {
+    // the track index from the key list, so that the candidate and the
+    // combination are read together
+    const Cand &cd = cand[key_c(i)];
     const Combo r = combo[i];
-    const Cand &cd = cand[r.c];
     SeedStage st;
     st.key = cd.key;
     st.s.ax = (float)cd.a; st.s.bx = (float)cd.b; st.s.cx = (float)cd.c;
@@ -1027,7 +1036,7 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
   }
   for (unsigned t = tid; t < ntrip; t += NT) {
     Cand cd;
-    if (xz_candidate<kLds>(X, Z, sh, P, trip[t], cd)) {
+    if (xz_candidate<kLds>(X, Z, sh, P, t < (unsigned)kTripLds ? sh.u.xtab[t] : trip[t], cd)) {
       const unsigned slot = wave_append(&sh.ncand);
       if (slot < (unsigned)S.cand_cap) cand[slot] = cd;
       if (slot < (unsigned)kCandLds) {
@@ -1094,14 +1103,15 @@ __device__ __forceinline__ PairEval eval_pair(const MState &m, double xv, double
   return r;
 }
 
-__device__ __forceinline__ MState seed_state(const sm_seed &s, const DevParams &P) {
+// from the seed's x-z parameters and its y line (the only fields read)
+__device__ __forceinline__ MState seed_state(const sm_seed *s, const DevParams &P) {
   MState m;
-  const double a = s.ax, b = s.bx, c = s.cx;
+  const double a = s->ax, b = s->bx, c = s->cx, y0 = s->y0, ty = s->ty;
   const double us = P.z_state - P.zref;
   m.xs = a + b * us + c * gd(us, P.d);
   m.txs = b + c * (2.0 * us + 3.0 * P.d * us * us);
-  m.y_m = (double)s.y0 + (double)s.ty * (P.z_ymatch - P.zref);
-  m.ty = s.ty;
+  m.y_m = y0 + ty * (P.z_ymatch - P.zref);
+  m.ty = ty;
   m.x0s = m.xs - P.z_state * m.txs;
   m.xsf = (float)m.xs; m.txsf = (float)m.txs; m.y_mf = (float)m.y_m; m.tyf = (float)m.ty;
   return m;
@@ -1186,16 +1196,16 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   int *sidx = sm_s ? sh.sidx : (int *)(mf + 5 * (size_t)S.ms_cap);
   unsigned long long *best_s = sm_s ? sh.best_s : S.best_s + wg * (size_t)S.ms_cap;
   unsigned long long *best_v = sm_v ? sh.best_v : S.best_v + wg * (size_t)S.vs_cap;
-  // the event's seeds in canonical order (half 0 then half 1)
-  for (int i = tid; i < ns && pool_ok; i += NT) {
-    const sm_seed sd = i < n0 ? S.pool[b0 + i] : S.pool[b1 + i - n0];
-    if (plain && (long long)so + i < D->seed_cap) D->seeds[so + i] = sd;
-    if (fits) {
-      const MState m = seed_state(sd, P);
-      ms[i] = m;
-      xsf[i] = m.xsf; txsf[i] = m.txsf; ymf[i] = m.y_mf; tyf[i] = m.tyf;
-      best_s[i] = ~0ull;
-    }
+  // the event's seeds in canonical order (half 0 then half 1); the plain form
+  // copies whole records to the caller, matching reads five fields of each
+  if (plain)
+    for (int i = tid; i < ns && pool_ok; i += NT)
+      if ((long long)so + i < D->seed_cap) D->seeds[so + i] = i < n0 ? S.pool[b0 + i] : S.pool[b1 + i - n0];
+  for (int i = tid; i < ns && pool_ok && fits; i += NT) {
+    const MState m = seed_state(i < n0 ? &S.pool[b0 + i] : &S.pool[b1 + i - n0], P);
+    ms[i] = m;
+    xsf[i] = m.xsf; txsf[i] = m.txsf; ymf[i] = m.y_mf; tyf[i] = m.tyf;
+    best_s[i] = ~0ull;
   }
   __syncthreads();
   // seeds sorted by t_y, so each VELO state visits only its |dty| window
@@ -1229,7 +1239,9 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     else if (slot < (unsigned)(kSurvLds + S.surv_cap)) surv[slot - kSurvLds] = Surv{v, s, r.chi2};
     return true;
   };
-  if (fits && ns > 0 && kSmallM && nv <= kVflat && nv <= NT) {
+  // VELO states of the event in LDS (flattened pair search)
+  const bool vlds = fits && ns > 0 && kSmallM && nv <= kVflat && nv <= NT;
+  if (vlds) {
     // every (VELO state, seed in its t_y window) pair gets its own thread:
     // window bounds per VELO state, a scan of the window sizes, then the
     // pairs in rounds of NT
@@ -1305,7 +1317,13 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
       sh.lbase = (unsigned long long)lo;
       D->long_off[e + 1] = (int)(lo + nk);
     } else {
-      const unsigned long long b = atomicAdd(&cnt->lpool_top, (unsigned long long)nk);
+      // a VELO state is in at most one long track unless chi2 values tie
+      // exactly, so the event's long tracks go to its VELO range of the pool;
+      // an event with more goes to the overflow area after all VELO states
+      const unsigned long long b =
+          nk <= (unsigned)nv ? (unsigned long long)v0
+                             : (unsigned long long)D->b.n_velo +
+                                   atomicAdd(&cnt->lpool_top, (unsigned long long)nk);
       if (b + nk > (unsigned long long)S.lpool_cap) raise_flag(cnt, F_LPOOL);
       sh.lbase = b;
       S.ev_lcnt[e] = (int)nk;
@@ -1322,8 +1340,10 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     if ((long long)(lb + r) >= cap) continue;
     const int vi = (int)(key >> 32), si = (int)(key & 0xffffffffu);
     const int v = v0 + vi;
-    const PairEval pe = eval_pair(ms[si], D->b.velo_x[v], D->b.velo_y[v], D->b.velo_z[v],
-                                  D->b.velo_tx[v], D->b.velo_ty[v], P);
+    const PairEval pe =
+        vlds ? eval_pair(ms[si], sh.vx[vi], sh.vy[vi], sh.vz[vi], sh.vtx[vi], sh.vty[vi], P)
+             : eval_pair(ms[si], D->b.velo_x[v], D->b.velo_y[v], D->b.velo_z[v],
+                         D->b.velo_tx[v], D->b.velo_ty[v], P);
     sm_long L;
     L.velo_idx = vi; L.seed_idx = si; L.velo_id = D->b.velo_id[v];
     L.qop = (float)pe.qop; L.chi2 = (float)pe.chi2; L.z_match = (float)pe.zm;
@@ -1378,26 +1398,46 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
   const float *hx = D->b.hit_x, *hz = D->b.hit_z;
   const int32_t *hid = D->b.hit_id;
   const int n_big = use_queue ? (int)S.cnt->n_big : 0;
+  // matching here (hand-off to the workgroup completing an event) or in k_match
+  const bool fuse = use_queue ? S.cnt->fuse != 0u : true;
   // queue of this form: the big items [0, n_big) or the rest of the order
   const int n_items = item_count >= 0 ? item_count : (kBig ? n_big : D->n_items - n_big);
   const int q0 = kBig ? 0 : n_big;
   bool first = true;
   for (;;) {
+    // the next item and its zone offsets (once from global memory, then from
+    // LDS): from its record in the order, or from the zone offsets
     if (tid == 0) {
       int q;
-      if (use_queue) q = (int)atomicAdd(kBig ? &S.cnt->big_queue : &S.cnt->seed_queue, 1u);
-      else q = first ? (int)blockIdx.x : n_items;
-      sh.item = q < n_items ? (use_queue ? S.item_order[q0 + q] : item_begin + q) : -1;
+      // the first item of each workgroup is its own index; later ones come
+      // from the queue, which counts from the grid size
+      if (first) q = (int)blockIdx.x;
+      else if (use_queue)
+        q = (int)gridDim.x + (int)atomicAdd(kBig ? &S.cnt->big_queue : &S.cnt->seed_queue, 1u);
+      else q = n_items;
+      int it = -1, z[kNL + 1];
+      if (q < n_items) {
+        // every load issued before the first LDS store
+        if (use_queue) {
+          const ItemRec *r = &S.item_rec[q0 + q];
+          it = r->item;
+#pragma unroll
+          for (int k = 0; k <= kNL; ++k) z[k] = r->zabs[k];
+        } else {
+          it = item_begin + q;
+#pragma unroll
+          for (int k = 0; k <= kNL; ++k) z[k] = zone_off[it * kNL + k];
+        }
+#pragma unroll
+        for (int k = 0; k <= kNL; ++k) sh.zabs[k] = z[k];
+      }
+      sh.item = it;
       sh.ntrip = 0; sh.ncand = 0; sh.nseed = 0; sh.ncombo = 0; sh.nkept = 0;
     }
     first = false;
     __syncthreads();
     const int item = sh.item;
     if (item < 0) break;
-    const int k0 = item * kNL;
-    // the item's zone offsets once from global memory, then from LDS
-    if (tid <= kNL) sh.zabs[tid] = zone_off[k0 + tid];
-    __syncthreads();
     const int base = sh.zabs[0];
     const int nh = sh.zabs[kNL] - base;
     if (tid <= kNL) sh.zoff[tid] = sh.zabs[tid] - base;
@@ -1454,6 +1494,7 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
     // second half acquires once and matches.  One L2 write-back per item and
     // one invalidate per event, instead of a device-wide fence per wave.
     __syncthreads();
+    if (!fuse) continue;
     if (tid == 0) {
       const int prev = __hip_atomic_fetch_add(&S.ev_done[item >> 1], 1, __ATOMIC_RELEASE,
                                               __HIP_MEMORY_SCOPE_AGENT);
@@ -1462,6 +1503,30 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
     }
     __syncthreads();
     if (s_last) match_event<NT>(D, S, P, item >> 1, plain, wg, mh);
+    __syncthreads();
+  }
+}
+
+// Matching (Sec. 4) as a kernel of its own, after the seeding kernels, when
+// k_prepare chose it for the batch: a persistent grid pulls events from a
+// queue.  The kernel boundary orders every seed before every match, so the
+// seeding kernel needs no per-event hand-off (one agent-scope release per
+// item and one acquire per event, each an L2 write-back or invalidate on a
+// chip with one L2 per XCD).
+__global__ __launch_bounds__(kSeedWG, 4) void k_match(const Desc *__restrict__ D,
+                                                      const KCtx *__restrict__ K) {
+  const Scratch &S = K->S;
+  const DevParams &P = K->P;
+  extern __shared__ __align__(16) unsigned char smem[];
+  MatchShared &mh = *reinterpret_cast<MatchShared *>(smem);
+  __shared__ int s_e;
+  if (S.cnt->fuse) return;
+  for (;;) {
+    if (threadIdx.x == 0) s_e = (int)atomicAdd(&S.cnt->match_queue, 1u);
+    __syncthreads();
+    const int e = s_e;
+    if (e >= D->n_events) break;
+    match_event<kSeedWG>(D, S, P, e, 0, blockIdx.x, mh);
     __syncthreads();
   }
 }
@@ -1486,6 +1551,7 @@ __global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
     c->need_trip = c->need_cand = c->need_tbl = c->need_sst = 0;
     c->need_ms = c->need_vs = c->need_surv = c->need_combo = 0;
     c->total_seeds = 0; c->total_longs = 0;
+    c->fuse = 1;
     if (plain) { D->seed_off[0] = 0; D->long_off[0] = 0; }
   }
   for (int e = threadIdx.x; e < ne; e += blockDim.x) S.ev_done[e] = 0;
@@ -1576,14 +1642,27 @@ __global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
       int acc = 0;
       for (int k = 31; k >= 0; --k) { base[k] = acc; acc += hist[k]; }
       S.cnt->n_big = best < 32 ? (unsigned)base[best - 1] : 0u;   // classes >= best
+      // matching: in k_match after all seeding, unless big items are in the
+      // batch; then inside the seeding kernel, where it overlaps their tail
+      S.cnt->fuse = P.match_mode < 0 ? 1u : P.match_mode > 0 ? 0u : (best < 32 ? 1u : 0u);
     }
   }
   __syncthreads();
-  // positions in the order, one atomic per wave when its items share a class
+  // positions in the order, one atomic per wave when its items share a class;
+  // each position's record holds the item and its zone offsets
   for (int i0 = 0; i0 < n; i0 += blockDim.x) {
     const int i = i0 + (int)threadIdx.x;
     const bool in = i < n;
-    const int sz = in ? max(zo[(i + 1) * kNL] - zo[i * kNL], 0) : 0;
+    int z[kNL + 1];   // all loads before the record stores (which may alias them)
+#pragma unroll
+    for (int k = 0; k <= kNL; ++k) z[k] = in ? zo[i * kNL + k] : 0;
+    auto put = [&](int p) {
+      ItemRec &r = S.item_rec[p];
+      r.item = i;
+#pragma unroll
+      for (int k = 0; k <= kNL; ++k) r.zabs[k] = z[k];
+    };
+    const int sz = in ? max(z[kNL] - z[0], 0) : 0;
     const int b = 31 - __clz(sz + 1);
     const unsigned long long act = __ballot(in);
     if (act == 0ull) continue;
@@ -1593,62 +1672,81 @@ __global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
       int p = 0;
       if (r == 0 && in) p = atomicAdd(&base[b0], __popcll(act));
       p = __shfl(p, __builtin_ctzll(act), 64);
-      if (in) S.item_order[p + (int)r] = i;
+      if (in) put(p + (int)r);
     } else if (in) {
-      S.item_order[atomicAdd(&base[b], 1)] = i;
+      put(atomicAdd(&base[b], 1));
     }
   }
 }
 
-// exclusive scan of per-event counts into off[0..n] (one workgroup)
-__device__ __forceinline__ void scan_counts(const int *c0, const int *c1, int stride, int n,
-                                            int32_t *off, int *s_tmp, long long *total) {
-  int carry = 0;
-  for (int b0 = 0; b0 < n; b0 += 1024) {
-    const int e = b0 + (int)threadIdx.x;
-    const int v = e < n ? (c1 ? c0[e * stride] + c1[e * stride] : c0[e * stride]) : 0;
-    int tot;
-    const int ex = block_excl_scan<1024>(v, s_tmp, tot);
-    if (e < n) off[e] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) {
-    off[n] = carry;
-    *total = carry;
-  }
-}
-
-// Per-event seed and long-track offsets of the batched form, totals and the
-// caller-capacity checks.
-__global__ __launch_bounds__(1024) void k_offsets(const Desc *__restrict__ D,
-                                                  const KCtx *__restrict__ K) {
-  const Scratch &S = K->S;
-  __shared__ int s_tmp[16];
-  const int n = D->n_events;
-  scan_counts(S.item_cnt, S.item_cnt + 1, 2, n, D->seed_off, s_tmp, &S.cnt->total_seeds);
-  scan_counts(S.ev_lcnt, nullptr, 1, n, D->long_off, s_tmp, &S.cnt->total_longs);
-  if (threadIdx.x == 0) {
-    if (S.cnt->total_seeds > D->seed_cap) raise_flag(S.cnt, F_OUT_SEED);
-    if (S.cnt->total_longs > D->long_cap) raise_flag(S.cnt, F_OUT_LONG);
-  }
-}
-
-// Seeds and long tracks from the pools to the caller's CSR outputs.
+// Per-event seed and long-track offsets and the copy from the pools to the
+// caller's CSR outputs, in one kernel.  Workgroup b takes a contiguous range
+// of events: it sums the counts of every earlier event (a reduction over the
+// prefix, read from L2), scans its own range, writes those offsets and copies
+// the range's records.  The workgroup holding the last event writes the
+// totals and the capacity checks; an event whose records would pass the
+// caller's capacity is not copied (the call then reports the capacity).
 __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
                                               const KCtx *__restrict__ K) {
   const Scratch &S = K->S;
-  const int n = D->n_events;
-  const unsigned f = S.cnt->flags;
-  if (f & (F_POOL | F_LPOOL | F_OUT_SEED | F_OUT_LONG)) return;
-  for (int e = blockIdx.x; e < n; e += gridDim.x) {
+  const int n = D->n_events, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int e_lo = min(n, (int)blockIdx.x * per), e_hi = min(n, e_lo + per);
+  const bool last = (e_lo < e_hi && e_hi == n) || (n == 0 && blockIdx.x == 0);
+  if (e_lo >= e_hi && !last) return;
+  __shared__ long long s_part[2][4];
+  __shared__ int s_tmp[16];
+  long long ps = 0, pl = 0;
+  for (int e = tid; e < e_lo; e += 256) {
+    ps += S.item_cnt[2 * e] + S.item_cnt[2 * e + 1];
+    pl += S.ev_lcnt[e];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    ps += __shfl_xor(ps, o, 64);
+    pl += __shfl_xor(pl, o, 64);
+  }
+  if (lane == 0) { s_part[0][w] = ps; s_part[1][w] = pl; }
+  __syncthreads();
+  long long cs = s_part[0][0] + s_part[0][1] + s_part[0][2] + s_part[0][3];
+  long long cl = s_part[1][0] + s_part[1][1] + s_part[1][2] + s_part[1][3];
+  for (int c0 = e_lo; c0 < e_hi; c0 += 256) {
+    const int e = c0 + tid;
+    const int vs = e < e_hi ? S.item_cnt[2 * e] + S.item_cnt[2 * e + 1] : 0;
+    const int vl = e < e_hi ? S.ev_lcnt[e] : 0;
+    int ts, tl;
+    const int xs = block_excl_scan<256>(vs, s_tmp, ts);
+    __syncthreads();
+    const int xl = block_excl_scan<256>(vl, s_tmp, tl);
+    if (e < e_hi) {
+      D->seed_off[e] = (int32_t)(cs + xs);
+      D->long_off[e] = (int32_t)(cl + xl);
+    }
+    cs += ts;
+    cl += tl;
+    __syncthreads();
+  }
+  if (last && tid == 0) {
+    D->seed_off[n] = (int32_t)cs;
+    D->long_off[n] = (int32_t)cl;
+    S.cnt->total_seeds = cs;
+    S.cnt->total_longs = cl;
+    if (cs > D->seed_cap) raise_flag(S.cnt, F_OUT_SEED);
+    if (cl > D->long_cap) raise_flag(S.cnt, F_OUT_LONG);
+  }
+  if (S.cnt->flags & (F_POOL | F_LPOOL)) return;
+  __syncthreads();   // this workgroup's offsets are written
+  for (int e = e_lo; e < e_hi; ++e) {
     const int n0 = S.item_cnt[2 * e], n1 = S.item_cnt[2 * e + 1];
     const long long b0 = S.item_base[2 * e], b1 = S.item_base[2 * e + 1];
     const long long so = D->seed_off[e];
-    for (int i = threadIdx.x; i < n0 + n1; i += blockDim.x)
-      D->seeds[so + i] = i < n0 ? S.pool[b0 + i] : S.pool[b1 + i - n0];
+    if (so + n0 + n1 <= D->seed_cap)
+      for (int i = tid; i < n0 + n1; i += 256)
+        D->seeds[so + i] = i < n0 ? S.pool[b0 + i] : S.pool[b1 + i - n0];
     const int m = S.ev_lcnt[e];
     const long long src = S.ev_lbase[e], dst = D->long_off[e];
-    for (int i = threadIdx.x; i < m; i += blockDim.x) D->longs[dst + i] = S.lpool[src + i];
+    if (dst + m <= D->long_cap)
+      for (int i = tid; i < m; i += 256) D->longs[dst + i] = S.lpool[src + i];
   }
 }
 
@@ -1697,13 +1795,13 @@ int smk_launch_seed_big(const Desc *d, const KCtx *k, int grid, int lds_hits, hi
                      smk_seed_big_lds_bytes(lds_hits), st, d, k, 0, -1, 1, lds_hits, 0);
   return (int)hipGetLastError();
 }
+int smk_launch_match(const Desc *d, const KCtx *k, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_match, dim3(grid), dim3(kSeedWG), sizeof(MatchShared), st, d, k);
+  return (int)hipGetLastError();
+}
 int smk_seed_big_lds_limit(int bytes) {
   return (int)hipFuncSetAttribute((const void *)k_seed<0, kBigWG>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-}
-int smk_launch_offsets(const Desc *d, const KCtx *k, hipStream_t st) {
-  hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, st, d, k);
-  return (int)hipGetLastError();
 }
 int smk_launch_copy(const Desc *d, const KCtx *k, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, st, d, k);

@@ -206,7 +206,7 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
   A(S.bestn, G * k.cand);
   A(S.bestchi, G * k.cand);
   A(S.bestidx, G * k.cand);
-  A(S.item_order, k.items);
+  A(S.item_rec, k.items);
   A(S.item_cnt, k.items);
   A(S.item_base, k.items);
   A(S.ev_lcnt, k.events);
@@ -248,7 +248,7 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
   B.trip_cap = kb.trip; B.cand_cap = kb.cand; B.tbl_cap = kb.tbl; B.sst_cap = kb.sst;
   B.combo_cap = kb.combo;
   B.ms_cap = kb.ms; B.vs_cap = kb.vs; B.surv_cap = kb.surv;
-  B.item_order = S.item_order; B.item_cnt = S.item_cnt; B.item_base = S.item_base;
+  B.item_rec = S.item_rec; B.item_cnt = S.item_cnt; B.item_base = S.item_base;
   B.ev_lcnt = S.ev_lcnt; B.ev_lbase = S.ev_lbase; B.ev_done = S.ev_done;
   B.pool = S.pool; B.lpool = S.lpool; B.pool_cap = S.pool_cap; B.lpool_cap = S.lpool_cap;
   B.cnt = S.cnt;
@@ -335,7 +335,7 @@ sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
     if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
     if (!e && c->p.uv_mode == 0) e = smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, q);
     if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
-    if (!e) e = smk_launch_offsets(d, S, q);
+    if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, c->match_wgs, q);
     if (!e) e = smk_launch_copy(d, S, 1024, q);
     return (hipError_t)e;
   };
@@ -381,11 +381,10 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   if (!e) e = hipEventRecord(ev[1], q);
   if (!e && c->p.uv_mode == 0) e = smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, q);
   if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
+  if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, c->match_wgs, q);
   if (!e) e = hipEventRecord(ev[2], q);
-  if (!e) e = smk_launch_offsets(d, S, q);
+  if (!e) e = smk_launch_copy(d, S, 1024, q);   // offset scans and copy
   if (!e) e = hipEventRecord(ev[3], q);
-  if (!e) e = smk_launch_copy(d, S, 1024, q);
-  if (!e) e = hipEventRecord(ev[4], q);
   return hip_status((hipError_t)e);
 }
 
@@ -416,7 +415,8 @@ bool needs_rerun(sm_ctx *c, Slot &s, sm_status &st) {
   re |= grow_caps(cp, &k.need_trip);
   re |= grow_caps(s.caps_big, k.need_big);
   if (f & smk::F_POOL) { cp.pool = std::max<long long>(2 * cp.pool, (long long)k.pool_top + 1024); re = true; }
-  if (f & smk::F_LPOOL) { cp.lpool = std::max<long long>(2 * cp.lpool, (long long)k.lpool_top + 1024); re = true; }
+  // long-track pool: every VELO state's slot, then the overflow area
+  if (f & smk::F_LPOOL) { cp.lpool = std::max<long long>(2 * cp.lpool, cp.lpool + (long long)k.lpool_top + 1024); re = true; }
   if (re) {
     if (alloc_slot(c, s) != SM_OK) { st = SM_ERR_OOM; return false; }
     return true;
@@ -438,7 +438,7 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
     fill_desc(s, *b, *o);
     if (hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, q) != hipSuccess)
       return SM_ERR_DEVICE;
-    hipEvent_t ev[5] = {};
+    hipEvent_t ev[4] = {};
     if (times) {
       for (auto &x : ev)
         if (hipEventCreate(&x) != hipSuccess) return SM_ERR_DEVICE;
@@ -452,9 +452,11 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
     if (st == SM_OK && hipStreamSynchronize(q) != hipSuccess) st = SM_ERR_DEVICE;
     if (times) {
       if (st == SM_OK) {
-        float *f = &times->prepare;
-        for (int k = 0; k < 4; ++k) hipEventElapsedTime(&f[k], ev[k], ev[k + 1]);
-        hipEventElapsedTime(&times->total, ev[0], ev[4]);
+        hipEventElapsedTime(&times->prepare, ev[0], ev[1]);
+        hipEventElapsedTime(&times->seed_match, ev[1], ev[2]);
+        times->offsets = 0.0f;
+        hipEventElapsedTime(&times->copy, ev[2], ev[3]);
+        hipEventElapsedTime(&times->total, ev[0], ev[3]);
       }
       for (auto &x : ev) hipEventDestroy(x);
     }
@@ -575,8 +577,13 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
       c->lds_big = (int)std::max<size_t>(b64, 256);
     }
   }
-  c->match_wgs = c->cfg.match_wgs > 0 ? c->cfg.match_wgs : cus * 2;
+  // matching kernel: its workgroups (at most seed_wgs: it uses their
+  // per-workgroup matching scratch); whether it or the seeding kernel
+  // matches is chosen per batch (match_wgs 0), or fixed (> 0: the matching
+  // kernel, < 0: the seeding kernel)
+  c->match_wgs = c->cfg.match_wgs > 0 ? std::min(c->cfg.match_wgs, c->seed_wgs) : c->seed_wgs;
   c->dp = make_params(c->g, c->p);
+  c->dp.match_mode = c->cfg.match_wgs > 0 ? 1 : (c->cfg.match_wgs < 0 ? -1 : 0);
   // item latency on one 256-thread workgroup, fitted to phase timers on
   // min-bias (778 hits: 93 us) and stress items (12,011 hits: 13.9 ms)
   c->dp.main_slots = c->seed_wgs;

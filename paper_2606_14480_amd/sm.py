@@ -210,10 +210,10 @@ def _stream_ptr(stream):
 class Context:
     def __init__(self, geometry: Geometry | None = None, params: Params | None = None,
                  device: int = 0, n_slots: int = 2, seed_wgs: int = 0, lds_hits: int = 0,
-                 validate: bool = False, mem_budget: int = 0):
+                 validate: bool = False, mem_budget: int = 0, match_wgs: int = 0):
         self.geometry = geometry or default_geometry()
         self.params = params or default_params()
-        cfg = Config(device=device, n_slots=n_slots, seed_wgs=seed_wgs, match_wgs=0,
+        cfg = Config(device=device, n_slots=n_slots, seed_wgs=seed_wgs, match_wgs=match_wgs,
                      lds_hits=lds_hits, validate=int(validate), mem_budget=mem_budget)
         h = C.c_void_p()
         st = _lib.sm_create(C.byref(self.geometry), C.byref(self.params), C.byref(cfg), C.byref(h))

@@ -352,6 +352,26 @@ def test_big_items_parity(orc, sm, ctx):
     check(orc, sm, ctx, b, "batch with a dominating item")
 
 
+@pytest.mark.parametrize("batch", ["minbias", "big"])
+def test_matching_kernel_equals_fused(sm, ctx, batch):
+    """Matching in a kernel of its own after all seeding, and matching inside
+    the seeding kernel by the workgroup that completes an event, give the
+    same bytes: on min-bias (automatic choice: the matching kernel) and on a
+    batch with a big item (automatic choice: inside), each forced both ways,
+    also with one matching workgroup and with fewer workgroups than events."""
+    b = ev.generate(ev.config(2, n_events=300)) if batch == "minbias" else big_item_batch()
+    say(f"[gpu] matching kernel vs fused, {batch}: {b.n_events} events")
+    g0 = gpu_run(sm, ctx, b)
+    for mw in (-1, 1, 37, 4096):
+        c = sm.Context(match_wgs=mw)
+        try:
+            g = gpu_run(sm, c, b)
+        finally:
+            c.close()
+        for x, y in zip(g0, g):
+            assert x.tobytes() == y.tobytes(), mw
+
+
 @pytest.mark.parametrize("p_min", [1500.0, 2000.0, 5000.0])
 def test_p_min_scan(orc, sm, p_min):
     """The window constants follow the minimum momentum (eq. tolHp, eq.
