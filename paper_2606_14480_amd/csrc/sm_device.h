@@ -27,6 +27,7 @@ constexpr int kXtabLds = 1024;      // x hits of an item with an LDS clone-vote 
 constexpr int kSeedLds = 256;       // seeds per item ranked from LDS keys
 constexpr int kMsLds = 384;         // seeds per event whose matching state lives in LDS
 constexpr int kVflat = 256;         // VELO states per event for the flattened pair search
+constexpr int kPvLds = 2048;        // flattened pairs whose VELO state is looked up in LDS
 constexpr int kVsLds = 512;         // VELO states per event with LDS best-chi2 entries
 constexpr int kSurvLds = 512;       // matching survivors kept in LDS
 constexpr int kPosBits = 21;        // item-relative hit positions < 2^21

@@ -219,23 +219,29 @@ __device__ __forceinline__ int zlower(const float *X, const SeedShared<NT> &sh, 
 // Distances closer than kTieMm are a tie, won by the lower position: a later
 // hit replaces the current one only if it is closer by more than kTieMm, so a
 // prediction midway between two hits picks the same hit whatever the
-// rounding of the prediction.
+// rounding of the prediction.  The x and z of the chosen hit come back in
+// xb, zb (read with the walk).
 template <bool kLds, int NT>
-__device__ __forceinline__ int zclosest(const float *X, const SeedShared<NT> &sh, int L, double pred,
-                                        double tol) {
+__device__ __forceinline__ int zclosest(const float *X, const float *Z, const SeedShared<NT> &sh,
+                                        int L, double pred, double tol, float &xb, float &zb) {
   const int hi = sh.zoff[L + 1];
   const double lo_v = pred - tol, hi_v = pred + tol;
   int best = -1;
   double bd = 0.0;
+  xb = 0.0f;
+  zb = 0.0f;
   if constexpr (kLds) {
     // from the bin of pred - tol, four hits per LDS round trip; the same
     // comparisons in the same order as the one-hit walk
     const int k = kbin((float)lo_v);
     int i = sh.zoff[L] + (k > 0 ? (int)sh.bins[L][k - 1] : 0);
     for (; i < hi; i += 4) {
-      float x4[4];
+      float x4[4], z4[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) x4[q] = i + q < hi ? X[i + q] : __builtin_inff();
+      for (int q = 0; q < 4; ++q) {
+        x4[q] = i + q < hi ? X[i + q] : __builtin_inff();
+        z4[q] = i + q < hi ? Z[i + q] : 0.0f;
+      }
       bool done = false;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -243,7 +249,7 @@ __device__ __forceinline__ int zclosest(const float *X, const SeedShared<NT> &sh
         if (done || x < lo_v) continue;
         if (x > hi_v) { done = true; continue; }
         const double d = fabs(x - pred);
-        if (best < 0 || d < bd - kTieMm) { best = i + q; bd = d; }
+        if (best < 0 || d < bd - kTieMm) { best = i + q; bd = d; xb = x4[q]; zb = z4[q]; }
       }
       if (done) break;
     }
@@ -254,8 +260,15 @@ __device__ __forceinline__ int zclosest(const float *X, const SeedShared<NT> &sh
       const double d = fabs(x - pred);
       if (best < 0 || d < bd - kTieMm) { best = i; bd = d; }
     }
+    if (best >= 0) { xb = X[best]; zb = Z[best]; }
   }
   return best;
+}
+template <bool kLds, int NT>
+__device__ __forceinline__ int zclosest(const float *X, const float *Z, const SeedShared<NT> &sh,
+                                        int L, double pred, double tol) {
+  float xb, zb;
+  return zclosest<kLds>(X, Z, sh, L, pred, tol, xb, zb);
 }
 
 // T1 x T3 doublets and T2 third hits of both iterations (Sec. 3.3.2-3.3.3),
@@ -380,7 +393,7 @@ __device__ __forceinline__ bool xz_candidate(const float *X, const float *Z, con
     else if (k == s3) pos[k] = i3;
     else if ((k & 1) != it) {
       const int L = xlayer(k);
-      const int h = zclosest<kLds>(X, sh, L, xm(a, b, c, P.zd[L], P), P.ext_tol);
+      const int h = zclosest<kLds>(X, Z, sh, L, xm(a, b, c, P.zd[L], P), P.ext_tol);
       if (h >= 0) { pos[k] = h; ++n; }
     }
   }
@@ -428,10 +441,11 @@ __device__ __forceinline__ bool uv_combo(const float *X, const float *Z, const S
     if (L == L0) continue;
     const double zl = P.zd[L], tl = P.tand[L];
     const double pred = xm(a, b, c, zl, P) - ty * zl * tl;
-    const int h = zclosest<kLds>(X, sh, L, pred, P.uv_tol);
+    float xhf, zhf;
+    const int h = zclosest<kLds>(X, Z, sh, L, pred, P.uv_tol, xhf, zhf);
     if (h < 0) continue;
-    const double zh = Z[h];
-    const double yl = (xm(a, b, c, zh, P) - (double)X[h]) * P.inv_tand[L];
+    const double zh = zhf;
+    const double yl = (xm(a, b, c, zh, P) - (double)xhf) * P.inv_tand[L];
     ty = 0.5 * (ty + yl / zh);
     r.pos[k] = h;
     const double w = tl * tl, u = zh - P.zref, yr = yl - y0h;
@@ -554,11 +568,12 @@ __device__ __forceinline__ bool hough_attach(const float *X, const float *Z, con
     const int L = uvlayer(k);
     const double zl = P.zd[L], tl = P.tand[L];
     const double pred = xm(a, b, c, zl, P) - ty * zl * tl;
-    const int h = zclosest<kLds>(X, sh, L, pred, P.uv_tol);
+    float xhf, zhf;
+    const int h = zclosest<kLds>(X, Z, sh, L, pred, P.uv_tol, xhf, zhf);
     r.pos[k] = h;
     if (h < 0) continue;
-    const double zh = Z[h];
-    const double yl = (xm(a, b, c, zh, P) - (double)X[h]) * P.inv_tand[L];
+    const double zh = zhf;
+    const double yl = (xm(a, b, c, zh, P) - (double)xhf) * P.inv_tand[L];
     if (n == 0) yref = yl;
     const double w = tl * tl, u = zh - P.zref, yr = yl - yref;
     s0 += w; s1 += w * u; s2 += w * u * u;
@@ -1128,9 +1143,10 @@ struct MatchShared {
   // the scan of the window sizes
   float vx[kVflat], vy[kVflat], vz[kVflat], vtx[kVflat], vty[kVflat];
   int vk0[kVflat], vscan[kVflat];
+  unsigned char pv[kPvLds];   // VELO state of each flattened pair
   int tmp[16];
   int ev;
-  unsigned nsurv, nkeep;
+  unsigned nsurv, nkeep, nplist;
   unsigned long long lbase;
 };
 
@@ -1173,6 +1189,7 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   if (tid == 0) {
     sh.nsurv = 0;
     sh.nkeep = 0;
+    sh.nplist = 0;
   }
   const int n0 = S.item_cnt[2 * e], n1 = S.item_cnt[2 * e + 1];
   const int b0 = S.item_base[2 * e], b1 = S.item_base[2 * e + 1];
@@ -1196,6 +1213,17 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   int *sidx = sm_s ? sh.sidx : (int *)(mf + 5 * (size_t)S.ms_cap);
   unsigned long long *best_s = sm_s ? sh.best_s : S.best_s + wg * (size_t)S.ms_cap;
   unsigned long long *best_v = sm_v ? sh.best_v : S.best_v + wg * (size_t)S.vs_cap;
+  // VELO states of the event for the flattened pair search, loaded here so
+  // that the loads overlap the seed loads below
+  const bool vlds = fits && ns > 0 && kSmallM && nv <= kVflat && nv <= NT;
+  float vxr = 0.0f, vyr = 0.0f, vzr = 0.0f, vtxr = 0.0f, vtyr = 0.0f;
+  if (vlds && tid < nv) {
+    vxr = D->b.velo_x[v0 + tid];
+    vyr = D->b.velo_y[v0 + tid];
+    vzr = D->b.velo_z[v0 + tid];
+    vtxr = D->b.velo_tx[v0 + tid];
+    vtyr = D->b.velo_ty[v0 + tid];
+  }
   // the event's seeds in canonical order (half 0 then half 1); the plain form
   // copies whole records to the caller, matching reads five fields of each
   if (plain)
@@ -1220,8 +1248,7 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   __syncthreads();
   Surv *surv = S.surv + wg * (size_t)(2 * S.surv_cap);
   // one pair test: the FP32 prefilter, then the FP64 evaluation
-  auto test_pair = [&](int v, int s, float xvf, float yvf, float zvf, float txvf, float tyvf,
-                       unsigned long long &bits) {
+  auto prefilter = [&](int s, float xvf, float yvf, float zvf, float txvf, float tyvf) {
     const float yvm = yvf + tyvf * (P.z_ymatchf - zvf);
     const float dtx = txsf[s] - txvf;
     if (!(fabsf(dtx) < P.pre_dtx)) return false;
@@ -1229,7 +1256,10 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     const float zm = P.zmf[0] + P.zmf[4] * txvf * txvf + P.zmf[1] * fabsf(dtx) +
                      P.zmf[2] * dtx * dtx + P.zmf[3] * fabsf(xsf[s]);
     const float dx = (xsf[s] + (zm - P.z_statef) * txsf[s]) - (xvf + (zm - zvf) * txvf);
-    if (!(fabsf(dx) < P.pre_dx)) return false;
+    return fabsf(dx) < P.pre_dx;
+  };
+  auto evaluate = [&](int v, int s, float xvf, float yvf, float zvf, float txvf, float tyvf,
+                      unsigned long long &bits) {
     const PairEval r = eval_pair(ms[s], xvf, yvf, zvf, txvf, tyvf, P);
     if (!r.ok) return false;
     bits = (unsigned long long)__double_as_longlong(r.chi2);
@@ -1239,8 +1269,11 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     else if (slot < (unsigned)(kSurvLds + S.surv_cap)) surv[slot - kSurvLds] = Surv{v, s, r.chi2};
     return true;
   };
-  // VELO states of the event in LDS (flattened pair search)
-  const bool vlds = fits && ns > 0 && kSmallM && nv <= kVflat && nv <= NT;
+  auto test_pair = [&](int v, int s, float xvf, float yvf, float zvf, float txvf, float tyvf,
+                       unsigned long long &bits) {
+    return prefilter(s, xvf, yvf, zvf, txvf, tyvf) &&
+           evaluate(v, s, xvf, yvf, zvf, txvf, tyvf, bits);
+  };
   if (vlds) {
     // every (VELO state, seed in its t_y window) pair gets its own thread:
     // window bounds per VELO state, a scan of the window sizes, then the
@@ -1248,11 +1281,11 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     int cnt_v = 0;
     if (tid < nv) {
       const int v = tid;
-      const float tyvf = D->b.velo_ty[v0 + v];
-      sh.vx[v] = D->b.velo_x[v0 + v];
-      sh.vy[v] = D->b.velo_y[v0 + v];
-      sh.vz[v] = D->b.velo_z[v0 + v];
-      sh.vtx[v] = D->b.velo_tx[v0 + v];
+      const float tyvf = vtyr;
+      sh.vx[v] = vxr;
+      sh.vy[v] = vyr;
+      sh.vz[v] = vzr;
+      sh.vtx[v] = vtxr;
       sh.vty[v] = tyvf;
       const int k0 = lower_f(sty, 0, ns, tyvf - P.pre_dty);
       const int k1 = upper_f(sty, k0, ns, tyvf + P.pre_dty);
@@ -1262,20 +1295,47 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     }
     int total;
     const int ex = block_excl_scan<NT>(cnt_v, sh.tmp, total);
-    if (tid < nv) sh.vscan[tid] = ex;
+    if (tid < nv) {
+      sh.vscan[tid] = ex;
+      // the VELO state of each of its pairs (the first kPvLds pairs)
+      for (int d = ex; d < ex + cnt_v && d < kPvLds; ++d) sh.pv[d] = (unsigned char)tid;
+    }
     __syncthreads();
+    // pass 1, LDS only: the FP32 prefilter; passing pairs are listed (in the
+    // final-selection keys' space, free until then) for pass 2, or evaluated
+    // at once if the list is full
+    unsigned *plist = reinterpret_cast<unsigned *>(sh.kkey);
+    constexpr unsigned kPlist = sizeof(sh.kkey) / sizeof(unsigned);
     for (int d0 = 0; d0 < total; d0 += NT) {
       const int d = d0 + tid;
       if (d >= total) continue;
-      int lo = 0, hi = nv;
-      while (lo < hi) {
-        const int m = (lo + hi) >> 1;
-        if (sh.vscan[m] <= d) lo = m + 1; else hi = m;
+      int v;
+      if (d < kPvLds) {
+        v = sh.pv[d];
+      } else {
+        int lo = 0, hi = nv;
+        while (lo < hi) {
+          const int m = (lo + hi) >> 1;
+          if (sh.vscan[m] <= d) lo = m + 1; else hi = m;
+        }
+        v = lo - 1;
       }
-      const int v = lo - 1;
       const int s = sidx[sh.vk0[v] + (d - sh.vscan[v])];
+      if (!prefilter(s, sh.vx[v], sh.vy[v], sh.vz[v], sh.vtx[v], sh.vty[v])) continue;
+      const unsigned slot = wave_append(&sh.nplist);
       unsigned long long bits;
-      if (test_pair(v, s, sh.vx[v], sh.vy[v], sh.vz[v], sh.vtx[v], sh.vty[v], bits))
+      if (slot < kPlist) plist[slot] = ((unsigned)v << 16) | (unsigned)s;
+      else if (evaluate(v, s, sh.vx[v], sh.vy[v], sh.vz[v], sh.vtx[v], sh.vty[v], bits))
+        atomicMin(&best_v[v], bits);
+    }
+    __syncthreads();
+    // pass 2: the FP64 evaluation of the listed pairs
+    const unsigned np = sh.nplist < kPlist ? sh.nplist : kPlist;
+    for (unsigned i = tid; i < np; i += NT) {
+      const unsigned w = plist[i];
+      const int v = (int)(w >> 16), s = (int)(w & 0xffffu);
+      unsigned long long bits;
+      if (evaluate(v, s, sh.vx[v], sh.vy[v], sh.vz[v], sh.vtx[v], sh.vty[v], bits))
         atomicMin(&best_v[v], bits);
     }
   } else if (fits && ns > 0) {
@@ -1521,8 +1581,12 @@ __global__ __launch_bounds__(kSeedWG, 4) void k_match(const Desc *__restrict__ D
   MatchShared &mh = *reinterpret_cast<MatchShared *>(smem);
   __shared__ int s_e;
   if (S.cnt->fuse) return;
-  for (;;) {
-    if (threadIdx.x == 0) s_e = (int)atomicAdd(&S.cnt->match_queue, 1u);
+  // the first event of each workgroup is its own index (1024 workgroups on
+  // one queue counter would queue behind each other at launch); later ones
+  // come from the queue, which counts from the grid size
+  for (bool first = true;; first = false) {
+    if (threadIdx.x == 0)
+      s_e = first ? (int)blockIdx.x : (int)gridDim.x + (int)atomicAdd(&S.cnt->match_queue, 1u);
     __syncthreads();
     const int e = s_e;
     if (e >= D->n_events) break;
@@ -1569,16 +1633,25 @@ __global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
   __syncthreads();
   const DevParams &P = K->P;
   auto latency = [&](float nh) { return P.lat_a * nh + P.lat_b * nh * nh; };
+  // the zone offsets of the first kPrepCache * blockDim items stay in
+  // registers from one load for both passes below; later items are reloaded
+  constexpr int kPrepCache = 2;
+  int zc[kPrepCache][kNL + 1];
+#pragma unroll
+  for (int c = 0; c < kPrepCache; ++c) {
+    const int i = c * (int)blockDim.x + (int)threadIdx.x;
+#pragma unroll
+    for (int k = 0; k <= kNL; ++k) zc[c][k] = i < n ? zo[i * kNL + k] : 0;
+  }
   // per-class count, summed latency and largest size; a wave whose items
   // share one class (the common case) adds them up first and updates once
-  for (int i0 = 0; i0 < n; i0 += blockDim.x) {
-    const int i = i0 + (int)threadIdx.x;
+  auto stat = [&](int i, const int (&z)[kNL + 1]) {
     const bool in = i < n;
-    const int sz = in ? max(zo[(i + 1) * kNL] - zo[i * kNL], 0) : 0;
+    const int sz = in ? max(z[kNL] - z[0], 0) : 0;
     const int b = 31 - __clz(sz + 1);
     const float w = in ? latency((float)sz) : 0.0f;
     const unsigned long long act = __ballot(in);
-    if (act == 0ull) continue;
+    if (act == 0ull) return;
     const int b0 = __shfl(b, __builtin_ctzll(act), 64);
     if (__ballot(in && b != b0) == 0ull) {
       float ws = w;
@@ -1599,6 +1672,17 @@ __global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
       atomicAdd(&wsum[b], w);
       atomicMax(&mx[b], sz);
     }
+  };
+  auto reload = [&](int i, int (&z)[kNL + 1]) {
+#pragma unroll
+    for (int k = 0; k <= kNL; ++k) z[k] = i < n ? zo[i * kNL + k] : 0;
+  };
+#pragma unroll
+  for (int c = 0; c < kPrepCache; ++c) stat(c * (int)blockDim.x + (int)threadIdx.x, zc[c]);
+  for (int i0 = kPrepCache * (int)blockDim.x; i0 < n; i0 += blockDim.x) {
+    int z[kNL + 1];
+    reload(i0 + (int)threadIdx.x, z);
+    stat(i0 + (int)threadIdx.x, z);
   }
   __syncthreads();
   // the cut: wave 0, one lane per class; prefix maximum of the latencies
@@ -1650,12 +1734,8 @@ __global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
   __syncthreads();
   // positions in the order, one atomic per wave when its items share a class;
   // each position's record holds the item and its zone offsets
-  for (int i0 = 0; i0 < n; i0 += blockDim.x) {
-    const int i = i0 + (int)threadIdx.x;
+  auto place = [&](int i, const int (&z)[kNL + 1]) {
     const bool in = i < n;
-    int z[kNL + 1];   // all loads before the record stores (which may alias them)
-#pragma unroll
-    for (int k = 0; k <= kNL; ++k) z[k] = in ? zo[i * kNL + k] : 0;
     auto put = [&](int p) {
       ItemRec &r = S.item_rec[p];
       r.item = i;
@@ -1665,7 +1745,7 @@ __global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
     const int sz = in ? max(z[kNL] - z[0], 0) : 0;
     const int b = 31 - __clz(sz + 1);
     const unsigned long long act = __ballot(in);
-    if (act == 0ull) continue;
+    if (act == 0ull) return;
     const int b0 = __shfl(b, __builtin_ctzll(act), 64);
     if (__ballot(in && b != b0) == 0ull) {
       const unsigned r = lane_rank(act);
@@ -1676,6 +1756,13 @@ __global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
     } else if (in) {
       put(atomicAdd(&base[b], 1));
     }
+  };
+#pragma unroll
+  for (int c = 0; c < kPrepCache; ++c) place(c * (int)blockDim.x + (int)threadIdx.x, zc[c]);
+  for (int i0 = kPrepCache * (int)blockDim.x; i0 < n; i0 += blockDim.x) {
+    int z[kNL + 1];   // loads before the record stores (which may alias them)
+    reload(i0 + (int)threadIdx.x, z);
+    place(i0 + (int)threadIdx.x, z);
   }
 }
 
