@@ -31,6 +31,8 @@ constexpr int kPvLds = 2048;        // flattened pairs whose VELO state is looke
 constexpr int kVsLds = 512;         // VELO states per event with LDS best-chi2 entries
 constexpr int kSurvLds = 512;       // matching survivors kept in LDS
 constexpr int kPosBits = 21;        // item-relative hit positions < 2^21
+constexpr int kPoolRegions = 8;     // seed-pool regions, each with its own counter
+constexpr int kRtopStride = 16;     // counters 128 bytes apart
 constexpr int kMaxItemHits = 1 << kPosBits;
 constexpr int kHoughBins = 128;     // largest coarse t_y histogram
 constexpr int kBigWG = 1024;        // threads of the big-item workgroup (16 wave64)
@@ -163,7 +165,8 @@ struct Scratch {
   ItemRec *item_rec;                       // [items_cap]
   int *item_cnt, *item_base;               // [items_cap]
   int *ev_lcnt, *ev_lbase, *ev_done;       // [events_cap]
-  sm_seed *pool;
+  sm_seed *pool;              // kPoolRegions regions of pool_cap / kPoolRegions seeds
+  unsigned long long *pool_rtop;  // fill level of each pool region, one per 128-byte line
   sm_long *lpool;
   long long pool_cap, lpool_cap;
   MState *ms;                 // [seed_wgs][ms_cap]

@@ -8,6 +8,8 @@
 // clone-vote scores keep the digits the vote compares.
 #include "sm_device.h"
 
+#include <type_traits>
+
 namespace smk {
 
 // x-layer slots 0..5 <-> layers 0, 3, 4, 7, 8, 11; stereo slots 0..5 <->
@@ -163,6 +165,19 @@ __device__ __forceinline__ int kbin(float x) {
   return f < 0.0f ? 0 : (f >= (float)kBins ? kBins : (int)f + 1);
 }
 
+// Before the vote, the vote table's LDS holds the first kTripLds triplets
+// and, after them, the doublet map of the triplet search: the workgroup
+// slot of the T1 hit of each of the first doublets of a round (one byte,
+// two with 1024-thread workgroups).
+constexpr int kTripLds = kXtabLds / 2;
+template <int NT>
+using SlotMap = typename std::conditional<(NT <= 256), unsigned char, unsigned short>::type;
+template <int NT>
+constexpr int kDmap = (kXtabLds - kTripLds) * (int)sizeof(unsigned long long) / (int)sizeof(SlotMap<NT>);
+// the track slot of each combination of a UV round (the first kCmap)
+template <int NT>
+constexpr int kCmap = 1024 / (int)sizeof(SlotMap<NT>);
+
 // Everything one seeding workgroup keeps in LDS besides the hits (whose
 // capacity is set per launch in dynamic LDS).
 template <int NT>
@@ -173,7 +188,7 @@ struct SeedShared {
   unsigned short cpos[kCandLds][6];      // x-hit positions + 1 (0: none)
   union {
     unsigned long long xtab[kXtabLds];   // clone-vote table over the item's x hits; before
-                                         // the vote, the first kTripLds triplets
+                                         // the vote, triplets and the doublet map
     struct {
       double cabc[kCandLds][3];          // x-z parameters for UV
       unsigned long long bestchi[kCandLds];
@@ -183,6 +198,7 @@ struct SeedShared {
     unsigned long long skey[kSeedLds];   // seed keys for the canonical rank
   } u;
   int scan[NT], a0[NT], a1[NT], a2[NT];
+  SlotMap<NT> cmap[kCmap<NT>];           // track slot of each combination of a UV round
   int tmp[16];
   int zoff[kNL + 1];
   int zabs[kNL + 1];                     // the item's zone offsets in the batch
@@ -193,8 +209,6 @@ struct SeedShared {
   unsigned long long pbase;
 };
 
-// triplets kept in LDS (the vote table's space, unused until the vote)
-constexpr int kTripLds = kXtabLds;
 
 // first i of zone L with X[i] >= v
 template <bool kLds, class T, int NT>
@@ -317,17 +331,25 @@ __device__ __forceinline__ void xz_triplets(const float *X, const float *Z, Seed
     sh.scan[threadIdx.x] = excl;
     sh.a0[threadIdx.x] = st;
     sh.a1[threadIdx.x] = i1 | (it << 30);
+    SlotMap<NT> *dmap = reinterpret_cast<SlotMap<NT> *>(sh.u.xtab + kTripLds);
+    for (int d = excl; d < excl + cnt_j && d < kDmap<NT>; ++d) dmap[d] = (SlotMap<NT>)threadIdx.x;
     __syncthreads();
     const int nj = min(NT, N1 - c0);
     for (int d0 = 0; d0 < total; d0 += NT) {
       const int d = d0 + (int)threadIdx.x;
       if (d < total) {
-        int lo = 0, hi = nj;
-        while (lo < hi) {
-          const int m = (lo + hi) >> 1;
-          if (sh.scan[m] <= d) lo = m + 1; else hi = m;
+        // the doublet's T1 slot: from the map, else a search of the scan
+        int jj;
+        if (d < kDmap<NT>) {
+          jj = dmap[d];
+        } else {
+          int lo = 0, hi = nj;
+          while (lo < hi) {
+            const int m = (lo + hi) >> 1;
+            if (sh.scan[m] <= d) lo = m + 1; else hi = m;
+          }
+          jj = lo - 1;
         }
-        const int jj = lo - 1;
         const int w = sh.a1[jj];
         const int di = w >> 30, d1 = w & 0x3fffffff;
         const int d3 = sh.a0[jj] + (d - sh.scan[jj]);
@@ -779,7 +801,12 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   // vote (at least as many as its seeds); the atomic's latency overlaps the
   // UV search and the range may keep unused slots
   unsigned long long pool_claim = 0;
-  if (tid == 0) pool_claim = atomicAdd(&cnt->pool_top, (unsigned long long)sh.nkept);
+  // in the item's region of the pool: eight counters, so that the items of a
+  // round (which reach this point together) do not all queue on one
+  const int region = item & (kPoolRegions - 1);
+  const unsigned long long rcap = (unsigned long long)S.pool_cap / kPoolRegions;
+  if (tid == 0)
+    pool_claim = atomicAdd(&S.pool_rtop[region * kRtopStride], (unsigned long long)sh.nkept);
   // repeated tracks of the two iterations: a kept iteration-1 track whose
   // x-hit set equals a kept iteration-0 track's is dropped.  Equal sets have
   // bit-identical scores, which filters the comparison: one wave takes one
@@ -887,17 +914,24 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     sh.a0[tid] = st0;
     sh.a1[tid] = cnt0;
     sh.a2[tid] = st1;
+    for (int d = excl; d < excl + cnt0 + cnt1 && d < kCmap<NT>; ++d) sh.cmap[d] = (SlotMap<NT>)tid;
     __syncthreads();
     const int nj = min((int)NT, (int)(nc - c0));
     for (int d0 = 0; d0 < total; d0 += NT) {
       const int d = d0 + tid;
       if (d >= total) continue;
-      int lo = 0, hi = nj;
-      while (lo < hi) {
-        const int m = (lo + hi) >> 1;
-        if (sh.scan[m] <= d) lo = m + 1; else hi = m;
+      // the combination's track slot: from the map, else a search of the scan
+      int jj;
+      if (d < kCmap<NT>) {
+        jj = sh.cmap[d];
+      } else {
+        int lo = 0, hi = nj;
+        while (lo < hi) {
+          const int m = (lo + hi) >> 1;
+          if (sh.scan[m] <= d) lo = m + 1; else hi = m;
+        }
+        jj = lo - 1;
       }
-      const int jj = lo - 1;
       const int k = d - sh.scan[jj];
       const int pass = k >= sh.a1[jj];
       const int h0 = pass ? sh.a2[jj] + (k - sh.a1[jj]) : sh.a0[jj] + k;
@@ -968,10 +1002,15 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   auto claim_pool = [&](unsigned ns) {
     if (tid == 0) {
       const unsigned long long b = pool_claim;
-      if (b + ns > (unsigned long long)S.pool_cap) raise_flag(cnt, F_POOL);
-      sh.pbase = b;
+      const bool ok = b + ns <= rcap;
+      if (!ok) {
+        raise_flag(cnt, F_POOL);
+        atomicMax(&cnt->pool_top, (b + ns) * kPoolRegions);
+      }
+      const unsigned long long g = region * rcap + b;
+      sh.pbase = ok ? g : (unsigned long long)S.pool_cap;   // no writes when full
       S.item_cnt[item] = (int)ns;
-      S.item_base[item] = (int)(b < (unsigned long long)S.pool_cap ? b : 0);
+      S.item_base[item] = ok ? (int)g : 0;
     }
   };
   if (ncb <= (unsigned)(NT < kSeedLds ? NT : kSeedLds)) {
@@ -1610,6 +1649,7 @@ __global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
     Counters *c = S.cnt;
     c->seed_queue = 0; c->match_queue = 0; c->flags = 0;
     c->pool_top = 0; c->lpool_top = 0;
+    for (int k = 0; k < kPoolRegions; ++k) S.pool_rtop[k * kRtopStride] = 0;
     c->big_queue = 0; c->n_big = 0;
     for (int k = 0; k < 8; ++k) c->need_big[k] = 0;
     c->need_trip = c->need_cand = c->need_tbl = c->need_sst = 0;

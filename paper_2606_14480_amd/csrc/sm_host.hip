@@ -213,6 +213,7 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
   A(S.ev_lbase, k.events);
   A(S.ev_done, k.events);
   A(S.pool, (size_t)k.pool);
+  A(S.pool_rtop, (size_t)smk::kPoolRegions * smk::kRtopStride);
   A(S.lpool, (size_t)k.lpool);
   A(S.ms, G * k.ms);
   A(S.mf, G * 6 * (size_t)k.ms);
@@ -250,7 +251,7 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
   B.ms_cap = kb.ms; B.vs_cap = kb.vs; B.surv_cap = kb.surv;
   B.item_rec = S.item_rec; B.item_cnt = S.item_cnt; B.item_base = S.item_base;
   B.ev_lcnt = S.ev_lcnt; B.ev_lbase = S.ev_lbase; B.ev_done = S.ev_done;
-  B.pool = S.pool; B.lpool = S.lpool; B.pool_cap = S.pool_cap; B.lpool_cap = S.lpool_cap;
+  B.pool = S.pool; B.pool_rtop = S.pool_rtop; B.lpool = S.lpool; B.pool_cap = S.pool_cap; B.lpool_cap = S.lpool_cap;
   B.cnt = S.cnt;
   // device addresses inside the counters (address arithmetic only)
   S.need = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(S.cnt) + offsetof(Counters, need_trip));
@@ -282,7 +283,7 @@ sm_status fit_batch(sm_ctx *c, Slot &s, const sm_batch &b) {
   const int items = 2 * b.n_events;
   if (items > k.items) { k.items = std::max(items, 2 * k.items); re = true; }
   if (b.n_events > k.events) { k.events = std::max(b.n_events, 2 * k.events); re = true; }
-  const long long pool = b.n_hits / 4 + 1024;
+  const long long pool = b.n_hits / 4 + 1024 * smk::kPoolRegions;   // regions of the seed pool
   if (pool > k.pool) { k.pool = std::max(pool, 2 * k.pool); re = true; }
   const long long lpool = b.n_velo + 1024;
   if (lpool > k.lpool) { k.lpool = std::max(lpool, 2 * k.lpool); re = true; }
@@ -414,7 +415,8 @@ bool needs_rerun(sm_ctx *c, Slot &s, sm_status &st) {
   };
   re |= grow_caps(cp, &k.need_trip);
   re |= grow_caps(s.caps_big, k.need_big);
-  if (f & smk::F_POOL) { cp.pool = std::max<long long>(2 * cp.pool, (long long)k.pool_top + 1024); re = true; }
+  // seed pool: pool_top is what the fullest region needed, times the regions
+  if (f & smk::F_POOL) { cp.pool = std::max<long long>(2 * cp.pool, (long long)k.pool_top + 1024 * smk::kPoolRegions); re = true; }
   // long-track pool: every VELO state's slot, then the overflow area
   if (f & smk::F_LPOOL) { cp.lpool = std::max<long long>(2 * cp.lpool, cp.lpool + (long long)k.lpool_top + 1024); re = true; }
   if (re) {
@@ -697,7 +699,8 @@ sm_status sm_poll(sm_ctx *ctx, int64_t ticket, int wait) {
 int64_t sm_batch_bytes(const sm_ctx *ctx, int32_t n_events, int64_t n_hits, int64_t n_velo) {
   (void)ctx;
   const int64_t items = 2 * (int64_t)n_events;
-  return items * 3 * 4 + (int64_t)n_events * 2 * 4 + (n_hits / 4 + 1024) * (int64_t)sizeof(sm_seed) +
+  return items * ((int64_t)sizeof(smk::ItemRec) + 2 * 4) + (int64_t)n_events * 3 * 4 +
+         (n_hits / 4 + 1024 * smk::kPoolRegions) * (int64_t)sizeof(sm_seed) +
          (n_velo + 1024) * (int64_t)sizeof(sm_long);
 }
 
