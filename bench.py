@@ -42,13 +42,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def seed_kernel_bytes(b, n_seeds: int, n_longs: int) -> int:
-    """Algorithmic HBM bytes of one launch of the fused Seeding + Matching
-    kernel: hit x and z (8 B/hit), the zone and VELO offsets, the VELO states
-    (24 B each), per item one count and one pool offset, per seed its 96 B
-    record plus the 12 hit ids it reports, and per long track its 40 B record."""
-    return (8 * b.n_hits + 4 * (24 * b.n_events + 1) + 4 * (b.n_events + 1) + 24 * b.n_velo
-            + 2 * 4 * 2 * b.n_events + n_seeds * (96 + 48) + 40 * n_longs)
+def seed_kernel_bytes(b, n_seeds: int) -> int:
+    """Algorithmic HBM bytes of one launch of the seeding kernel (main form):
+    hit x, z and id (12 B/hit), per item its order record (64 B: the item and
+    its 13 zone offsets) and its seed count and pool offset (8 B), per seed
+    its 96 B record written to the pool."""
+    return 12 * b.n_hits + (64 + 8) * 2 * b.n_events + 96 * n_seeds
+
+
+def match_kernel_bytes(b, n_seeds: int, n_longs: int) -> int:
+    """Algorithmic HBM bytes of one launch of the matching kernel: per event
+    the two items' seed counts and pool offsets, two VELO offsets and its
+    long-track count and pool offset (32 B), the VELO states (x, y, z, tx, ty,
+    id: 24 B each), five fields of each seed (20 B), and per long track its
+    40 B record."""
+    return 32 * b.n_events + 24 * b.n_velo + 20 * n_seeds + 40 * n_longs
 
 
 def cpu_baseline(batch, seconds: float):
@@ -234,8 +242,10 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {n * 4} bytes read, {n * 4} bytes written")
 
-    alg_bytes = seed_kernel_bytes(host, n_seeds, n_longs)
-    achieved = alg_bytes / (kern["seed_match"] * 1e-3) / 1e9
+    alg_bytes = seed_kernel_bytes(host, n_seeds)
+    achieved = alg_bytes / (kern["seed"] * 1e-3) / 1e9
+    m_bytes = match_kernel_bytes(host, n_seeds, n_longs)
+    m_achieved = m_bytes / (kern["match"] * 1e-3) / 1e9 if kern["match"] > 0 else None
     res = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -264,10 +274,15 @@ def main():
         "served": serve,
         "gpu_events_per_s": round(host.n_events / (kern["total"] * 1e-3), 1),
         "parity": parity,
-        "roofline": {"bound": "hbm", "kernel": "k_seed (seeding + matching)", "achieved": round(achieved, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "roofline": {"bound": "hbm", "kernel": "k_seed<0, 256> (seeding, main form)",
+                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": measured_traffic(), "alg_bytes_per_launch": alg_bytes},
+        "roofline_match": {"bound": "hbm", "kernel": "k_match",
+                           "achieved": round(m_achieved, 2) if m_achieved else None,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(m_achieved / HBM_PEAK_GBS, 5) if m_achieved else None,
+                           "alg_bytes_per_launch": m_bytes},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(host, args.cpu_seconds)

@@ -209,13 +209,14 @@ sm_status sm_submit(sm_ctx *ctx, const sm_batch *batch, sm_out *out, int64_t *ti
 sm_status sm_poll(sm_ctx *ctx, int64_t ticket, int wait);
 
 /* Per-kernel device time of one batched run, from HIP events recorded on
- * `stream` between the kernels (milliseconds): counters and item order;
- * Seeding and Matching (the seeding kernels and, when the batch uses it, the
- * matching kernel); offsets, now always 0 (the offset scans run inside the
- * copy kernel); the offsets and copy to the caller's buffers; and the whole
- * sequence. */
+ * `stream` between the kernels (milliseconds): counters and item order,
+ * with the big-item form when one launch does both (then seed_big is 0);
+ * the big-item seeding form; the main seeding form (with
+ * Matching inside it when the batch uses that form); the matching kernel
+ * (which exits at once when Matching ran inside seeding); the offset scans
+ * and copy to the caller's buffers; and the whole sequence. */
 typedef struct {
-  float prepare, seed_match, offsets, copy, total;
+  float prepare, seed_big, seed, match, copy, total;
 } sm_kernel_times;
 
 /* Tracing: runs the batched form once as plain stream launches (no graph)

@@ -31,12 +31,12 @@ constexpr int kPvLds = 2048;        // flattened pairs whose VELO state is looke
 constexpr int kVsLds = 512;         // VELO states per event with LDS best-chi2 entries
 constexpr int kSurvLds = 512;       // matching survivors kept in LDS
 constexpr int kPosBits = 21;        // item-relative hit positions < 2^21
-constexpr int kPoolRegions = 8;     // seed-pool regions, each with its own counter
-constexpr int kRtopStride = 16;     // counters 128 bytes apart
+constexpr int kPoolPerItem = 128;   // seed-pool slots of each item (more: the overflow area)
 constexpr int kMaxItemHits = 1 << kPosBits;
 constexpr int kHoughBins = 128;     // largest coarse t_y histogram
 constexpr int kBigWG = 1024;        // threads of the big-item workgroup (16 wave64)
 constexpr int kBigBucket = 12;      // items with >= 2^12 - 1 hits are big
+constexpr unsigned kPrepSpin = 1u << 22;  // polls of the preparation flag before giving up
 constexpr double kTieMm = 1e-6;     // closest-hit distances this close are a tie
 
 // status flags (Counters::flags)
@@ -66,6 +66,10 @@ struct Counters {
   unsigned need_ms, need_vs, need_surv, need_combo;
   long long total_seeds, total_longs;
   unsigned big_queue, n_big;     // big-item queue: order positions [0, n_big)
+  unsigned prep_ready;           // the batch is prepared (big form with preparation); 0
+                                 // again after the copy kernel
+  unsigned stall;                // a wait for the preparation gave up (sticky until the
+                                 // host clears the counters)
   unsigned need_big[8];          // needs of the big-item scratch, same order as need_trip..
 };
 
@@ -165,8 +169,9 @@ struct Scratch {
   ItemRec *item_rec;                       // [items_cap]
   int *item_cnt, *item_base;               // [items_cap]
   int *ev_lcnt, *ev_lbase, *ev_done;       // [events_cap]
-  sm_seed *pool;              // kPoolRegions regions of pool_cap / kPoolRegions seeds
-  unsigned long long *pool_rtop;  // fill level of each pool region, one per 128-byte line
+  sm_seed *pool;              // kPoolPerItem slots per item of the batch, then the
+                              // overflow area from pool_static (filled by pool_top)
+  long long pool_static;
   sm_long *lpool;
   long long pool_cap, lpool_cap;
   MState *ms;                 // [seed_wgs][ms_cap]
@@ -200,10 +205,11 @@ int smk_launch_prepare(const smk::Desc *d, const smk::KCtx *k, int plain, hipStr
 int smk_launch_seed(const smk::Desc *d, const smk::KCtx *k, int item_begin, int item_count,
                     int use_queue, int grid, int lds_hits, int plain, int uv_mode,
                     hipStream_t st);
-int smk_launch_seed_big(const smk::Desc *d, const smk::KCtx *k, int grid, int lds_hits,
+int smk_launch_seed_big(const smk::Desc *d, const smk::KCtx *k, int grid, int lds_hits, int prep,
                         hipStream_t st);
 int smk_launch_match(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 int smk_seed_big_lds_limit(int bytes);
+int smk_seed_big_static_lds();   // static LDS of the big form (its dynamic LDS comes on top)
 int smk_launch_copy(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 int smk_launch_validate(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 int smk_launch_plain_totals(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);

@@ -324,7 +324,7 @@ __device__ __forceinline__ void xz_triplets(const float *X, const float *Z, Seed
           if (X[m] <= hi3) en = m + 1; else b = m;
         }
       }
-      cnt_j = en - st;
+      cnt_j = en > st ? en - st : 0;
     }
     int total;
     const int excl = block_excl_scan<NT>(cnt_j, sh.tmp, total);
@@ -797,16 +797,16 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     if (kept && lane_rank(km) == 0) atomicAdd(&sh.nkept, (unsigned)__popcll(km));
   }
   __syncthreads();
-  // the item's pool range is claimed now, for the tracks that survived the
-  // vote (at least as many as its seeds); the atomic's latency overlaps the
-  // UV search and the range may keep unused slots
+  // the item's pool range, for the tracks that survived the vote (at least
+  // as many as its seeds): its own kPoolPerItem slots, or, for an item with
+  // more, a range of the overflow area claimed now (the atomic's latency
+  // overlaps the UV search); the range may keep unused slots
   unsigned long long pool_claim = 0;
-  // in the item's region of the pool: eight counters, so that the items of a
-  // round (which reach this point together) do not all queue on one
-  const int region = item & (kPoolRegions - 1);
-  const unsigned long long rcap = (unsigned long long)S.pool_cap / kPoolRegions;
   if (tid == 0)
-    pool_claim = atomicAdd(&S.pool_rtop[region * kRtopStride], (unsigned long long)sh.nkept);
+    pool_claim = sh.nkept <= (unsigned)kPoolPerItem
+                     ? (unsigned long long)item * kPoolPerItem
+                     : (unsigned long long)S.pool_static +
+                           atomicAdd(&cnt->pool_top, (unsigned long long)sh.nkept);
   // repeated tracks of the two iterations: a kept iteration-1 track whose
   // x-hit set equals a kept iteration-0 track's is dropped.  Equal sets have
   // bit-identical scores, which filters the comparison: one wave takes one
@@ -1002,15 +1002,11 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   auto claim_pool = [&](unsigned ns) {
     if (tid == 0) {
       const unsigned long long b = pool_claim;
-      const bool ok = b + ns <= rcap;
-      if (!ok) {
-        raise_flag(cnt, F_POOL);
-        atomicMax(&cnt->pool_top, (b + ns) * kPoolRegions);
-      }
-      const unsigned long long g = region * rcap + b;
-      sh.pbase = ok ? g : (unsigned long long)S.pool_cap;   // no writes when full
+      const bool ok = b + ns <= (unsigned long long)S.pool_cap;
+      if (!ok) raise_flag(cnt, F_POOL);
+      sh.pbase = ok ? b : (unsigned long long)S.pool_cap;   // no writes when full
       S.item_cnt[item] = (int)ns;
-      S.item_base[item] = ok ? (int)g : 0;
+      S.item_base[item] = ok ? (int)b : 0;
     }
   };
   if (ncb <= (unsigned)(NT < kSeedLds ? NT : kSeedLds)) {
@@ -1466,181 +1462,10 @@ __device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Sc
     match_event_impl<false, NT>(D, S, P, e, plain, wg, sh);
 }
 
-// Persistent Seeding + Matching: each workgroup pulls (event, half) items from
-// the queue (or takes item_begin + blockIdx in the plain form) and seeds
-// them; the workgroup that completes the second half of an event then matches
-// that event.  The seeding state and the matching state share the same LDS.
-// NT = kSeedWG: the main form, 4 workgroups per CU, over the items after the
-// big ones in the longest-first order.  NT = kBigWG: one workgroup of 16
-// waves per CU with its own scratch, over the big items (at the head of the
-// order); it runs first, so a big item gets a whole CU instead of holding one
-// 256-thread workgroup for the whole batch.
-template <int kUv, int NT>
-__global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *__restrict__ D,
-                                                     const KCtx *__restrict__ K, int item_begin,
-                                                     int item_count, int use_queue, int lds_hits,
-                                                     int plain) {
-  constexpr bool kBig = NT == kBigWG;
-  const Scratch &S = kBig ? K->SB : K->S;
-  const DevParams &P = K->P;
-  extern __shared__ __align__(16) unsigned char smem[];
-  SeedShared<NT> &sh = *reinterpret_cast<SeedShared<NT> *>(smem);
-  MatchShared &mh = *reinterpret_cast<MatchShared *>(smem);
-  float *s_x = reinterpret_cast<float *>(smem + sizeof(SeedShared<NT>));
-  float *s_z = s_x + lds_hits;
-  int32_t *s_id = reinterpret_cast<int32_t *>(s_z + lds_hits);
-  __shared__ int s_last;
-
-  const int tid = threadIdx.x;
-  const size_t wg = blockIdx.x;
-  const int32_t *zone_off = D->b.zone_off;
-  const float *hx = D->b.hit_x, *hz = D->b.hit_z;
-  const int32_t *hid = D->b.hit_id;
-  const int n_big = use_queue ? (int)S.cnt->n_big : 0;
-  // matching here (hand-off to the workgroup completing an event) or in k_match
-  const bool fuse = use_queue ? S.cnt->fuse != 0u : true;
-  // queue of this form: the big items [0, n_big) or the rest of the order
-  const int n_items = item_count >= 0 ? item_count : (kBig ? n_big : D->n_items - n_big);
-  const int q0 = kBig ? 0 : n_big;
-  bool first = true;
-  for (;;) {
-    // the next item and its zone offsets (once from global memory, then from
-    // LDS): from its record in the order, or from the zone offsets
-    if (tid == 0) {
-      int q;
-      // the first item of each workgroup is its own index; later ones come
-      // from the queue, which counts from the grid size
-      if (first) q = (int)blockIdx.x;
-      else if (use_queue)
-        q = (int)gridDim.x + (int)atomicAdd(kBig ? &S.cnt->big_queue : &S.cnt->seed_queue, 1u);
-      else q = n_items;
-      int it = -1, z[kNL + 1];
-      if (q < n_items) {
-        // every load issued before the first LDS store
-        if (use_queue) {
-          const ItemRec *r = &S.item_rec[q0 + q];
-          it = r->item;
-#pragma unroll
-          for (int k = 0; k <= kNL; ++k) z[k] = r->zabs[k];
-        } else {
-          it = item_begin + q;
-#pragma unroll
-          for (int k = 0; k <= kNL; ++k) z[k] = zone_off[it * kNL + k];
-        }
-#pragma unroll
-        for (int k = 0; k <= kNL; ++k) sh.zabs[k] = z[k];
-      }
-      sh.item = it;
-      sh.ntrip = 0; sh.ncand = 0; sh.nseed = 0; sh.ncombo = 0; sh.nkept = 0;
-    }
-    first = false;
-    __syncthreads();
-    const int item = sh.item;
-    if (item < 0) break;
-    const int base = sh.zabs[0];
-    const int nh = sh.zabs[kNL] - base;
-    if (tid <= kNL) sh.zoff[tid] = sh.zabs[tid] - base;
-    if (tid == 0) {
-      int acc = 0;
-      for (int k = 0; k < 6; ++k) {
-        sh.xb[k] = acc;
-        const int L = (k >> 1) * 4 + (k & 1) * 3;
-        acc += sh.zabs[L + 1] - sh.zabs[L];
-      }
-      sh.xb[6] = acc;
-    }
-    if (nh >= kMaxItemHits || nh < 0) {
-      if (tid == 0) {
-        raise_flag(S.cnt, nh < 0 ? F_INVALID : F_LIMIT);
-        S.item_cnt[item] = 0;
-        S.item_base[item] = 0;
-      }
-      __syncthreads();
-    } else if (nh <= lds_hits) {
-      // stage the item's hits; every bin entry starts at its zone's size
-      for (int i = tid; i < nh; i += NT) {
-        s_x[i] = hx[base + i];
-        s_z[i] = hz[base + i];
-        s_id[i] = hid[base + i];
-      }
-      for (int i = tid; i < kNL * kBins; i += NT) {
-        const int L = i / kBins;
-        sh.bins[L][i % kBins] = (unsigned short)(sh.zabs[L + 1] - sh.zabs[L]);
-      }
-      __syncthreads();
-      // hit i opens the bins in (kbin(previous hit), kbin(hit i)]
-      int zb[kNL];
-#pragma unroll
-      for (int k = 0; k < kNL; ++k) zb[k] = sh.zoff[k + 1];
-      for (int i = tid; i < nh; i += NT) {
-        int L = 0;
-#pragma unroll
-        for (int k = 0; k < kNL - 1; ++k) L += i >= zb[k];
-        const int li = i - sh.zoff[L];
-        const int kc = kbin(s_x[i]);
-        const int kp = li > 0 ? kbin(s_x[i - 1]) : 0;
-        for (int b = kp; b < kc; ++b) sh.bins[L][b] = (unsigned short)li;
-      }
-      __syncthreads();
-      seed_item<true, kUv>(s_x, s_z, s_id, item, nh, P, S, wg, sh);
-    } else {
-      __syncthreads();
-      seed_item<false, kUv>(hx + base, hz + base, hid + base, item, nh, P, S, wg, sh);
-    }
-    // hand-off: after the barrier, one release increment of the per-event
-    // count publishes the whole workgroup's writes (barrier synchronisation
-    // and the release compose); the workgroup that completes the event's
-    // second half acquires once and matches.  One L2 write-back per item and
-    // one invalidate per event, instead of a device-wide fence per wave.
-    __syncthreads();
-    if (!fuse) continue;
-    if (tid == 0) {
-      const int prev = __hip_atomic_fetch_add(&S.ev_done[item >> 1], 1, __ATOMIC_RELEASE,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-      s_last = prev == 1;
-      if (prev == 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
-    if (s_last) match_event<NT>(D, S, P, item >> 1, plain, wg, mh);
-    __syncthreads();
-  }
-}
-
-// Matching (Sec. 4) as a kernel of its own, after the seeding kernels, when
-// k_prepare chose it for the batch: a persistent grid pulls events from a
-// queue.  The kernel boundary orders every seed before every match, so the
-// seeding kernel needs no per-event hand-off (one agent-scope release per
-// item and one acquire per event, each an L2 write-back or invalidate on a
-// chip with one L2 per XCD).
-__global__ __launch_bounds__(kSeedWG, 4) void k_match(const Desc *__restrict__ D,
-                                                      const KCtx *__restrict__ K) {
-  const Scratch &S = K->S;
-  const DevParams &P = K->P;
-  extern __shared__ __align__(16) unsigned char smem[];
-  MatchShared &mh = *reinterpret_cast<MatchShared *>(smem);
-  __shared__ int s_e;
-  if (S.cnt->fuse) return;
-  // the first event of each workgroup is its own index (1024 workgroups on
-  // one queue counter would queue behind each other at launch); later ones
-  // come from the queue, which counts from the grid size
-  for (bool first = true;; first = false) {
-    if (threadIdx.x == 0)
-      s_e = first ? (int)blockIdx.x : (int)gridDim.x + (int)atomicAdd(&S.cnt->match_queue, 1u);
-    __syncthreads();
-    const int e = s_e;
-    if (e >= D->n_events) break;
-    match_event<kSeedWG>(D, S, P, e, 0, blockIdx.x, mh);
-    __syncthreads();
-  }
-}
-
-// ------------------------------------------------------ batch plumbing ----
-
-// Clear counters and per-event hand-off counts; in the batched form also
-// order the (event, half) items by hit count, largest first (log2 buckets),
-// so the longest items start first and the persistent grid drains evenly.
-__global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
-                                                  const KCtx *__restrict__ K, int plain) {
+// Counters, per-event hand-off counts and (batched) the longest-first item
+// order with the big-form cut: one workgroup of 1024 threads.
+__device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
+                                              const KCtx *__restrict__ K, int plain) {
   const Scratch &S = K->S;
   __shared__ int hist[32], base[32];
   const int ne = D->n_events, n = D->n_items;
@@ -1649,7 +1474,6 @@ __global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
     Counters *c = S.cnt;
     c->seed_queue = 0; c->match_queue = 0; c->flags = 0;
     c->pool_top = 0; c->lpool_top = 0;
-    for (int k = 0; k < kPoolRegions; ++k) S.pool_rtop[k * kRtopStride] = 0;
     c->big_queue = 0; c->n_big = 0;
     for (int k = 0; k < 8; ++k) c->need_big[k] = 0;
     c->need_trip = c->need_cand = c->need_tbl = c->need_sst = 0;
@@ -1806,6 +1630,219 @@ __global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
   }
 }
 
+// Persistent Seeding + Matching: each workgroup pulls (event, half) items from
+// the queue (or takes item_begin + blockIdx in the plain form) and seeds
+// them; the workgroup that completes the second half of an event then matches
+// that event.  The seeding state and the matching state share the same LDS.
+// NT = kSeedWG: the main form, 4 workgroups per CU, over the items after the
+// big ones in the longest-first order.  NT = kBigWG: one workgroup of 16
+// waves per CU with its own scratch, over the big items (at the head of the
+// order); it runs first, so a big item gets a whole CU instead of holding one
+// 256-thread workgroup for the whole batch.
+template <int kUv, int NT>
+__global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *__restrict__ D,
+                                                     const KCtx *__restrict__ K, int item_begin,
+                                                     int item_count, int use_queue, int lds_hits,
+                                                     int plain, int prep) {
+  constexpr bool kBig = NT == kBigWG;
+  const Scratch &S = kBig ? K->SB : K->S;
+  const DevParams &P = K->P;
+  extern __shared__ __align__(16) unsigned char smem[];
+  SeedShared<NT> &sh = *reinterpret_cast<SeedShared<NT> *>(smem);
+  MatchShared &mh = *reinterpret_cast<MatchShared *>(smem);
+  float *s_x = reinterpret_cast<float *>(smem + sizeof(SeedShared<NT>));
+  float *s_z = s_x + lds_hits;
+  int32_t *s_id = reinterpret_cast<int32_t *>(s_z + lds_hits);
+  __shared__ int s_last;
+
+  const int tid = threadIdx.x;
+  const size_t wg = blockIdx.x;
+  const int32_t *zone_off = D->b.zone_off;
+  const float *hx = D->b.hit_x, *hz = D->b.hit_z;
+  const int32_t *hid = D->b.hit_id;
+  if constexpr (kBig) {
+    if (prep) {
+      // this launch also prepares the batch: workgroup 0 does k_prepare's
+      // work and then releases the others, which poll for it (bounded: on
+      // giving up they flag the batch and leave, and the call fails)
+      __shared__ int s_stall;
+      if (blockIdx.x == 0) {
+        prepare_batch(D, K, 0);
+        __syncthreads();
+        if (tid == 0)
+          __hip_atomic_store(&S.cnt->prep_ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        if (tid == 0) {
+          s_stall = 0;
+          unsigned n = 0;
+          // relaxed polls (an acquire per poll would invalidate caches that
+          // workgroup 0 is reading through), one acquire after the flag
+          while (__hip_atomic_load(&S.cnt->prep_ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                 0u) {
+            __builtin_amdgcn_s_sleep(16);
+            if (++n == kPrepSpin) {
+              atomicExch(&S.cnt->stall, 1u);
+              s_stall = 1;
+              break;
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        if (s_stall) return;
+      }
+    }
+  }
+  // input that the validation kernel rejected is not processed
+  if (S.cnt->flags & (F_INVALID | F_UNSORTED)) return;
+  const int n_big = use_queue ? (int)S.cnt->n_big : 0;
+  // matching here (hand-off to the workgroup completing an event) or in k_match
+  const bool fuse = use_queue ? S.cnt->fuse != 0u : true;
+  // queue of this form: the big items [0, n_big) or the rest of the order
+  const int n_items = item_count >= 0 ? item_count : (kBig ? n_big : D->n_items - n_big);
+  const int q0 = kBig ? 0 : n_big;
+  bool first = true;
+  for (;;) {
+    // the next item and its zone offsets (once from global memory, then from
+    // LDS): from its record in the order, or from the zone offsets
+    if (tid == 0) {
+      int q;
+      // the first item of each workgroup is its own index; later ones come
+      // from the queue, which counts from the grid size
+      if (first) q = (int)blockIdx.x;
+      else if (use_queue)
+        q = (int)gridDim.x + (int)atomicAdd(kBig ? &S.cnt->big_queue : &S.cnt->seed_queue, 1u);
+      else q = n_items;
+      int it = -1, z[kNL + 1];
+      if (q < n_items) {
+        // every load issued before the first LDS store
+        if (use_queue) {
+          const ItemRec *r = &S.item_rec[q0 + q];
+          it = r->item;
+#pragma unroll
+          for (int k = 0; k <= kNL; ++k) z[k] = r->zabs[k];
+        } else {
+          it = item_begin + q;
+#pragma unroll
+          for (int k = 0; k <= kNL; ++k) z[k] = zone_off[it * kNL + k];
+        }
+#pragma unroll
+        for (int k = 0; k <= kNL; ++k) sh.zabs[k] = z[k];
+      }
+      sh.item = it;
+      sh.ntrip = 0; sh.ncand = 0; sh.nseed = 0; sh.ncombo = 0; sh.nkept = 0;
+    }
+    first = false;
+    __syncthreads();
+    const int item = sh.item;
+    if (item < 0) break;
+    const int base = sh.zabs[0];
+    const int nh = sh.zabs[kNL] - base;
+    if (tid <= kNL) sh.zoff[tid] = sh.zabs[tid] - base;
+    if (tid == 0) {
+      int acc = 0;
+      for (int k = 0; k < 6; ++k) {
+        sh.xb[k] = acc;
+        const int L = (k >> 1) * 4 + (k & 1) * 3;
+        acc += sh.zabs[L + 1] - sh.zabs[L];
+      }
+      sh.xb[6] = acc;
+    }
+    if (nh >= kMaxItemHits || nh < 0) {
+      if (tid == 0) {
+        raise_flag(S.cnt, nh < 0 ? F_INVALID : F_LIMIT);
+        S.item_cnt[item] = 0;
+        S.item_base[item] = 0;
+      }
+      __syncthreads();
+    } else if (nh <= lds_hits) {
+      // stage the item's hits; every bin entry starts at its zone's size
+      for (int i = tid; i < nh; i += NT) {
+        s_x[i] = hx[base + i];
+        s_z[i] = hz[base + i];
+        s_id[i] = hid[base + i];
+      }
+      for (int i = tid; i < kNL * kBins; i += NT) {
+        const int L = i / kBins;
+        sh.bins[L][i % kBins] = (unsigned short)(sh.zabs[L + 1] - sh.zabs[L]);
+      }
+      __syncthreads();
+      // hit i opens the bins in (kbin(previous hit), kbin(hit i)]
+      int zb[kNL];
+#pragma unroll
+      for (int k = 0; k < kNL; ++k) zb[k] = sh.zoff[k + 1];
+      for (int i = tid; i < nh; i += NT) {
+        int L = 0;
+#pragma unroll
+        for (int k = 0; k < kNL - 1; ++k) L += i >= zb[k];
+        const int li = i - sh.zoff[L];
+        const int kc = kbin(s_x[i]);
+        const int kp = li > 0 ? kbin(s_x[i - 1]) : 0;
+        for (int b = kp; b < kc; ++b) sh.bins[L][b] = (unsigned short)li;
+      }
+      __syncthreads();
+      seed_item<true, kUv>(s_x, s_z, s_id, item, nh, P, S, wg, sh);
+    } else {
+      __syncthreads();
+      seed_item<false, kUv>(hx + base, hz + base, hid + base, item, nh, P, S, wg, sh);
+    }
+    // hand-off: after the barrier, one release increment of the per-event
+    // count publishes the whole workgroup's writes (barrier synchronisation
+    // and the release compose); the workgroup that completes the event's
+    // second half acquires once and matches.  One L2 write-back per item and
+    // one invalidate per event, instead of a device-wide fence per wave.
+    __syncthreads();
+    if (!fuse) continue;
+    if (tid == 0) {
+      const int prev = __hip_atomic_fetch_add(&S.ev_done[item >> 1], 1, __ATOMIC_RELEASE,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+      s_last = prev == 1;
+      if (prev == 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    if (s_last) match_event<NT>(D, S, P, item >> 1, plain, wg, mh);
+    __syncthreads();
+  }
+}
+
+// Matching (Sec. 4) as a kernel of its own, after the seeding kernels, when
+// k_prepare chose it for the batch: a persistent grid pulls events from a
+// queue.  The kernel boundary orders every seed before every match, so the
+// seeding kernel needs no per-event hand-off (one agent-scope release per
+// item and one acquire per event, each an L2 write-back or invalidate on a
+// chip with one L2 per XCD).
+__global__ __launch_bounds__(kSeedWG, 4) void k_match(const Desc *__restrict__ D,
+                                                      const KCtx *__restrict__ K) {
+  const Scratch &S = K->S;
+  const DevParams &P = K->P;
+  extern __shared__ __align__(16) unsigned char smem[];
+  MatchShared &mh = *reinterpret_cast<MatchShared *>(smem);
+  __shared__ int s_e;
+  if (S.cnt->fuse || (S.cnt->flags & (F_INVALID | F_UNSORTED))) return;
+  // the first event of each workgroup is its own index (1024 workgroups on
+  // one queue counter would queue behind each other at launch); later ones
+  // come from the queue, which counts from the grid size
+  for (bool first = true;; first = false) {
+    if (threadIdx.x == 0)
+      s_e = first ? (int)blockIdx.x : (int)gridDim.x + (int)atomicAdd(&S.cnt->match_queue, 1u);
+    __syncthreads();
+    const int e = s_e;
+    if (e >= D->n_events) break;
+    match_event<kSeedWG>(D, S, P, e, 0, blockIdx.x, mh);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------ batch plumbing ----
+
+// Clear counters and per-event hand-off counts; in the batched form also
+// order the (event, half) items by hit count, largest first (log2 buckets),
+// so the longest items start first and the persistent grid drains evenly.
+__global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
+                                                  const KCtx *__restrict__ K, int plain) {
+  prepare_batch(D, K, plain);
+}
+
 // Per-event seed and long-track offsets and the copy from the pools to the
 // caller's CSR outputs, in one kernel.  Workgroup b takes a contiguous range
 // of events: it sums the counts of every earlier event (a reduction over the
@@ -1854,6 +1891,7 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
     __syncthreads();
   }
   if (last && tid == 0) {
+    S.cnt->prep_ready = 0u;   // for the next batch's preparing launch
     D->seed_off[n] = (int32_t)cs;
     D->long_off[n] = (int32_t)cl;
     S.cnt->total_seeds = cs;
@@ -1861,7 +1899,7 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
     if (cs > D->seed_cap) raise_flag(S.cnt, F_OUT_SEED);
     if (cl > D->long_cap) raise_flag(S.cnt, F_OUT_LONG);
   }
-  if (S.cnt->flags & (F_POOL | F_LPOOL)) return;
+  if (S.cnt->flags & (F_POOL | F_LPOOL | F_INVALID | F_UNSORTED)) return;
   __syncthreads();   // this workgroup's offsets are written
   for (int e = e_lo; e < e_hi; ++e) {
     const int n0 = S.item_cnt[2 * e], n1 = S.item_cnt[2 * e + 1];
@@ -1911,20 +1949,29 @@ int smk_launch_seed(const Desc *d, const KCtx *k, int item_begin, int item_count
                     int grid, int lds_hits, int plain, int uv_mode, hipStream_t st) {
   if (uv_mode == 1)
     hipLaunchKernelGGL((k_seed<1, kSeedWG>), dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits),
-                       st, d, k, item_begin, item_count, use_queue, lds_hits, plain);
+                       st, d, k, item_begin, item_count, use_queue, lds_hits, plain, 0);
   else
     hipLaunchKernelGGL((k_seed<0, kSeedWG>), dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits),
-                       st, d, k, item_begin, item_count, use_queue, lds_hits, plain);
+                       st, d, k, item_begin, item_count, use_queue, lds_hits, plain, 0);
   return (int)hipGetLastError();
 }
-int smk_launch_seed_big(const Desc *d, const KCtx *k, int grid, int lds_hits, hipStream_t st) {
+int smk_launch_seed_big(const Desc *d, const KCtx *k, int grid, int lds_hits, int prep,
+                        hipStream_t st) {
   hipLaunchKernelGGL((k_seed<0, kBigWG>), dim3(grid), dim3(kBigWG),
-                     smk_seed_big_lds_bytes(lds_hits), st, d, k, 0, -1, 1, lds_hits, 0);
+                     smk_seed_big_lds_bytes(lds_hits), st, d, k, 0, -1, 1, lds_hits, 0, prep);
   return (int)hipGetLastError();
 }
 int smk_launch_match(const Desc *d, const KCtx *k, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_match, dim3(grid), dim3(kSeedWG), sizeof(MatchShared), st, d, k);
   return (int)hipGetLastError();
+}
+int smk_seed_big_static_lds() {
+  hipFuncAttributes a;
+  if (hipFuncGetAttributes(&a, (const void *)k_seed<0, kBigWG>) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1024;   // a margin above what the kernel declares
+  }
+  return (int)a.sharedSizeBytes;
 }
 int smk_seed_big_lds_limit(int bytes) {
   return (int)hipFuncSetAttribute((const void *)k_seed<0, kBigWG>,

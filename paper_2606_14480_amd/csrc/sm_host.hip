@@ -186,6 +186,7 @@ sm_status dalloc(Slot &s, T **p, size_t n, int64_t &bytes) {
 
 // (Re)allocate all scratch of a slot for its current caps.
 sm_status alloc_slot(sm_ctx *c, Slot &s) {
+  destroy_graphs(s);   // their counter copy-back names the old counters
   free_slot_scratch(s);
   int64_t bytes = 0;
   const size_t G = (size_t)c->seed_wgs;
@@ -212,8 +213,8 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
   A(S.ev_lcnt, k.events);
   A(S.ev_lbase, k.events);
   A(S.ev_done, k.events);
-  A(S.pool, (size_t)k.pool);
-  A(S.pool_rtop, (size_t)smk::kPoolRegions * smk::kRtopStride);
+  S.pool_static = (long long)k.items * smk::kPoolPerItem;
+  A(S.pool, (size_t)(S.pool_static + k.pool));
   A(S.lpool, (size_t)k.lpool);
   A(S.ms, G * k.ms);
   A(S.mf, G * 6 * (size_t)k.ms);
@@ -221,6 +222,9 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
   A(S.best_v, G * k.vs);
   A(S.surv, G * 2 * (size_t)k.surv);
   A(S.cnt, 1);
+  // the preparation flag and the stall flag start clear (the kernels keep
+  // the first at 0 between batches)
+  if (hipMemset(S.cnt, 0, sizeof(Counters)) != hipSuccess) return SM_ERR_DEVICE;
   // big-item form: its own per-workgroup arrays, everything else shared
   Scratch &B = s.SB;
   B = S;
@@ -244,14 +248,14 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
 #undef A
   S.trip_cap = k.trip; S.cand_cap = k.cand; S.tbl_cap = k.tbl; S.sst_cap = k.sst;
   S.combo_cap = k.combo;
-  S.pool_cap = k.pool; S.lpool_cap = k.lpool;
+  S.pool_cap = S.pool_static + k.pool; S.lpool_cap = k.lpool;
   S.ms_cap = k.ms; S.vs_cap = k.vs; S.surv_cap = k.surv;
   B.trip_cap = kb.trip; B.cand_cap = kb.cand; B.tbl_cap = kb.tbl; B.sst_cap = kb.sst;
   B.combo_cap = kb.combo;
   B.ms_cap = kb.ms; B.vs_cap = kb.vs; B.surv_cap = kb.surv;
   B.item_rec = S.item_rec; B.item_cnt = S.item_cnt; B.item_base = S.item_base;
   B.ev_lcnt = S.ev_lcnt; B.ev_lbase = S.ev_lbase; B.ev_done = S.ev_done;
-  B.pool = S.pool; B.pool_rtop = S.pool_rtop; B.lpool = S.lpool; B.pool_cap = S.pool_cap; B.lpool_cap = S.lpool_cap;
+  B.pool = S.pool; B.pool_static = S.pool_static; B.lpool = S.lpool; B.pool_cap = S.pool_cap; B.lpool_cap = S.lpool_cap;
   B.cnt = S.cnt;
   // device addresses inside the counters (address arithmetic only)
   S.need = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(S.cnt) + offsetof(Counters, need_trip));
@@ -283,7 +287,7 @@ sm_status fit_batch(sm_ctx *c, Slot &s, const sm_batch &b) {
   const int items = 2 * b.n_events;
   if (items > k.items) { k.items = std::max(items, 2 * k.items); re = true; }
   if (b.n_events > k.events) { k.events = std::max(b.n_events, 2 * k.events); re = true; }
-  const long long pool = b.n_hits / 4 + 1024 * smk::kPoolRegions;   // regions of the seed pool
+  const long long pool = b.n_hits / 8 + 1024;   // overflow area of the seed pool
   if (pool > k.pool) { k.pool = std::max(pool, 2 * k.pool); re = true; }
   const long long lpool = b.n_velo + 1024;
   if (lpool > k.lpool) { k.lpool = std::max(lpool, 2 * k.lpool); re = true; }
@@ -328,16 +332,34 @@ void fill_desc(Slot &s, const sm_batch &b, const sm_out &o) {
   d.n_items = 2 * b.n_events;
 }
 
+// The head of the batched sequence: the batch's preparation and the
+// big-item form in one launch (its workgroup 0 prepares), or, with input
+// validation or the Hough variant, k_prepare, k_validate and the big form.
+int enqueue_prepare_big(sm_ctx *c, Slot &s, hipStream_t q) {
+  const smk::KCtx *S = s.d_kctx;
+  const Desc *d = s.d_desc;
+  if (c->p.uv_mode == 0 && !c->cfg.validate)
+    return smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, 1, q);
+  int e = smk_launch_prepare(d, S, 0, q);
+  if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
+  if (!e && c->p.uv_mode == 0) e = smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, 0, q);
+  return e;
+}
+
+// The batched sequence, replayed from a captured graph: the batch
+// descriptor's upload from the slot's pinned copy, the kernels, and the
+// counters' copy back to pinned memory (read when the graph runs, so one
+// graph serves every batch of the slot).
 sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
   const smk::KCtx *S = s.d_kctx;
   const Desc *d = s.d_desc;
   auto seq = [&](hipStream_t q) -> hipError_t {
-    int e = smk_launch_prepare(d, S, 0, q);
-    if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
-    if (!e && c->p.uv_mode == 0) e = smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, q);
+    int e = hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, q);
+    if (!e) e = enqueue_prepare_big(c, s, q);
     if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
     if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, c->match_wgs, q);
     if (!e) e = smk_launch_copy(d, S, 1024, q);
+    if (!e) e = hipMemcpyAsync(s.h_cnt, s.S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q);
     return (hipError_t)e;
   };
   for (const Slot::Captured &g : s.graphs)
@@ -377,15 +399,15 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   const smk::KCtx *S = s.d_kctx;
   const Desc *d = s.d_desc;
   int e = hipEventRecord(ev[0], q);
-  if (!e) e = smk_launch_prepare(d, S, 0, q);
-  if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
+  if (!e) e = enqueue_prepare_big(c, s, q);   // preparation and big form
   if (!e) e = hipEventRecord(ev[1], q);
-  if (!e && c->p.uv_mode == 0) e = smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, q);
-  if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
-  if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, c->match_wgs, q);
   if (!e) e = hipEventRecord(ev[2], q);
-  if (!e) e = smk_launch_copy(d, S, 1024, q);   // offset scans and copy
+  if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
   if (!e) e = hipEventRecord(ev[3], q);
+  if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, c->match_wgs, q);
+  if (!e) e = hipEventRecord(ev[4], q);
+  if (!e) e = smk_launch_copy(d, S, 1024, q);   // offset scans and copy
+  if (!e) e = hipEventRecord(ev[5], q);
   return hip_status((hipError_t)e);
 }
 
@@ -395,6 +417,12 @@ bool needs_rerun(sm_ctx *c, Slot &s, sm_status &st) {
   const Counters &k = *s.h_cnt;
   st = SM_OK;
   const unsigned f = k.flags;
+  if (k.stall) {
+    // a wait for the batch's preparation gave up: clear the counters
+    (void)hipMemset(s.S.cnt, 0, sizeof(Counters));
+    st = SM_ERR_DEVICE;
+    return false;
+  }
   if (f & smk::F_INVALID) { st = SM_ERR_INVALID; return false; }
   if (f & smk::F_UNSORTED) { st = SM_ERR_UNSORTED; return false; }
   if (f & smk::F_LIMIT) { st = SM_ERR_LIMIT; return false; }
@@ -415,8 +443,8 @@ bool needs_rerun(sm_ctx *c, Slot &s, sm_status &st) {
   };
   re |= grow_caps(cp, &k.need_trip);
   re |= grow_caps(s.caps_big, k.need_big);
-  // seed pool: pool_top is what the fullest region needed, times the regions
-  if (f & smk::F_POOL) { cp.pool = std::max<long long>(2 * cp.pool, (long long)k.pool_top + 1024 * smk::kPoolRegions); re = true; }
+  // seed pool: pool_top is what the overflow area needed
+  if (f & smk::F_POOL) { cp.pool = std::max<long long>(2 * cp.pool, (long long)k.pool_top + 1024); re = true; }
   // long-track pool: every VELO state's slot, then the overflow area
   if (f & smk::F_LPOOL) { cp.lpool = std::max<long long>(2 * cp.lpool, cp.lpool + (long long)k.lpool_top + 1024); re = true; }
   if (re) {
@@ -438,9 +466,13 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
   for (int tries = 0; tries < 8; ++tries) {
     if ((st = fit_batch(c, s, *b)) != SM_OK) return st;
     fill_desc(s, *b, *o);
-    if (hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, q) != hipSuccess)
+    // the batched graph uploads the descriptor and copies the counters back
+    // itself; the plain and timed sequences do it here
+    const bool graph = !times && !plain;
+    if (!graph &&
+        hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, q) != hipSuccess)
       return SM_ERR_DEVICE;
-    hipEvent_t ev[4] = {};
+    hipEvent_t ev[6] = {};
     if (times) {
       for (auto &x : ev)
         if (hipEventCreate(&x) != hipSuccess) return SM_ERR_DEVICE;
@@ -448,17 +480,15 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
     } else {
       st = plain ? enqueue_plain(c, s, b->n_events, q) : enqueue_batched(c, s, q);
     }
-    if (st == SM_OK &&
+    if (st == SM_OK && !graph &&
         hipMemcpyAsync(s.h_cnt, s.S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q) != hipSuccess)
       st = SM_ERR_DEVICE;
     if (st == SM_OK && hipStreamSynchronize(q) != hipSuccess) st = SM_ERR_DEVICE;
     if (times) {
       if (st == SM_OK) {
-        hipEventElapsedTime(&times->prepare, ev[0], ev[1]);
-        hipEventElapsedTime(&times->seed_match, ev[1], ev[2]);
-        times->offsets = 0.0f;
-        hipEventElapsedTime(&times->copy, ev[2], ev[3]);
-        hipEventElapsedTime(&times->total, ev[0], ev[3]);
+        float *f = &times->prepare;   // prepare, seed_big, seed, match, copy
+        for (int k = 0; k < 5; ++k) hipEventElapsedTime(&f[k], ev[k], ev[k + 1]);
+        hipEventElapsedTime(&times->total, ev[0], ev[5]);
       }
       for (auto &x : ev) hipEventDestroy(x);
     }
@@ -567,7 +597,9 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
   // the per-workgroup LDS limit leaves after its shared state
   c->big_wgs = std::max(cus / 2, 1);
   {
-    const size_t lim = prop.sharedMemPerBlock > 0 ? (size_t)prop.sharedMemPerBlock : 65536;
+    const size_t lim0 = prop.sharedMemPerBlock > 0 ? (size_t)prop.sharedMemPerBlock : 65536;
+    const size_t stat = (size_t)std::max(smk_seed_big_static_lds(), 0);
+    const size_t lim = lim0 > stat ? lim0 - stat : 0;
     const size_t base = smk_seed_big_lds_bytes(0);
     long long h = lim > base ? (long long)((lim - base) / 12) : 0;   // x, z, id per hit
     h = std::min<long long>(h, 12288) / 256 * 256;
@@ -575,7 +607,7 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
     if (smk_seed_big_lds_bytes(c->lds_big) > 65536 &&
         smk_seed_big_lds_limit((int)smk_seed_big_lds_bytes(c->lds_big)) != 0) {
       (void)hipGetLastError();
-      const size_t b64 = 65536 > base ? (65536 - base) / 12 / 256 * 256 : 0;
+      const size_t b64 = 65536 > base + stat ? (65536 - base - stat) / 12 / 256 * 256 : 0;
       c->lds_big = (int)std::max<size_t>(b64, 256);
     }
   }
@@ -641,11 +673,8 @@ static sm_status start_slot(sm_ctx *c, Slot &s) {
   sm_status st = fit_batch(c, s, s.batch);
   if (st != SM_OK) return st;
   fill_desc(s, s.batch, *s.out);
-  if (hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, s.stream) != hipSuccess)
-    return SM_ERR_DEVICE;
+  // the graph uploads the descriptor and copies the counters back
   if ((st = enqueue_batched(c, s, s.stream)) != SM_OK) return st;
-  if (hipMemcpyAsync(s.h_cnt, s.S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s.stream) != hipSuccess)
-    return SM_ERR_DEVICE;
   return hip_status(hipEventRecord(s.done, s.stream));
 }
 
@@ -700,7 +729,7 @@ int64_t sm_batch_bytes(const sm_ctx *ctx, int32_t n_events, int64_t n_hits, int6
   (void)ctx;
   const int64_t items = 2 * (int64_t)n_events;
   return items * ((int64_t)sizeof(smk::ItemRec) + 2 * 4) + (int64_t)n_events * 3 * 4 +
-         (n_hits / 4 + 1024 * smk::kPoolRegions) * (int64_t)sizeof(sm_seed) +
+         (items * smk::kPoolPerItem + n_hits / 8 + 1024) * (int64_t)sizeof(sm_seed) +
          (n_velo + 1024) * (int64_t)sizeof(sm_long);
 }
 

@@ -388,3 +388,31 @@ def test_p_min_scan(orc, sm, p_min):
         assert st["seeds_g"] >= len(ref.seeds)
     else:
         assert st["seeds_g"] <= len(ref.seeds)
+
+
+def test_validating_sequence_equals_default(sm, ctx):
+    """With input validation on, the batch runs k_prepare, k_validate and the
+    big form as separate launches (the default prepares inside the big-form
+    launch); both give the same bytes, and validation rejects an unsorted
+    zone."""
+    b = ev.generate(ev.config(2, n_events=60))
+    say("[gpu] validating sequence vs default, 60 events")
+    g0 = gpu_run(sm, ctx, b)
+    c = sm.Context(validate=True)
+    try:
+        g1 = gpu_run(sm, c, b)
+        for x, y in zip(g0, g1):
+            assert x.tobytes() == y.tobytes()
+        bad = b.subset(range(3))
+        zo = bad.zone_off
+        L = next(k for k in range(12) if zo[k + 1] - zo[k] >= 2)
+        i = int(zo[L])
+        bad.hit_x[i], bad.hit_x[i + 1] = bad.hit_x[i + 1] + 1.0, bad.hit_x[i]
+        with pytest.raises(sm.SmError) as e:
+            gpu_run(sm, c, bad)
+        assert e.value.status == sm.ERR_UNSORTED
+        g2 = gpu_run(sm, c, b)   # the context stays usable
+        for x, y in zip(g0, g2):
+            assert x.tobytes() == y.tobytes()
+    finally:
+        c.close()
