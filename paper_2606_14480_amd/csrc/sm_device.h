@@ -205,6 +205,10 @@ int smk_launch_prepare(const smk::Desc *d, const smk::KCtx *k, int plain, hipStr
 int smk_launch_seed(const smk::Desc *d, const smk::KCtx *k, int item_begin, int item_count,
                     int use_queue, int grid, int lds_hits, int plain, int uv_mode,
                     hipStream_t st);
+// the main form without the matching code, for batches matched by k_match
+// (returns at once otherwise); launched together with smk_launch_seed
+int smk_launch_seed_nomatch(const smk::Desc *d, const smk::KCtx *k, int grid, int lds_hits,
+                            hipStream_t st);
 int smk_launch_seed_big(const smk::Desc *d, const smk::KCtx *k, int grid, int lds_hits, int prep,
                         hipStream_t st);
 int smk_launch_match(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);

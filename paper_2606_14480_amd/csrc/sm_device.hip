@@ -1639,7 +1639,7 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
 // waves per CU with its own scratch, over the big items (at the head of the
 // order); it runs first, so a big item gets a whole CU instead of holding one
 // 256-thread workgroup for the whole batch.
-template <int kUv, int NT>
+template <int kUv, int NT, bool kFuse = true>
 __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *__restrict__ D,
                                                      const KCtx *__restrict__ K, int item_begin,
                                                      int item_count, int use_queue, int lds_hits,
@@ -1696,8 +1696,12 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
   // input that the validation kernel rejected is not processed
   if (S.cnt->flags & (F_INVALID | F_UNSORTED)) return;
   const int n_big = use_queue ? (int)S.cnt->n_big : 0;
-  // matching here (hand-off to the workgroup completing an event) or in k_match
+  // matching here (hand-off to the workgroup completing an event) or in
+  // k_match; the main form has one instantiation with the matching code and
+  // one without (which keeps the seeding phases' registers free of it), and
+  // the one that does not fit the batch returns at once
   const bool fuse = use_queue ? S.cnt->fuse != 0u : true;
+  if (!kBig && fuse != kFuse) return;
   // queue of this form: the big items [0, n_big) or the rest of the order
   const int n_items = item_count >= 0 ? item_count : (kBig ? n_big : D->n_items - n_big);
   const int q0 = kBig ? 0 : n_big;
@@ -1792,7 +1796,7 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
     // second half acquires once and matches.  One L2 write-back per item and
     // one invalidate per event, instead of a device-wide fence per wave.
     __syncthreads();
-    if (!fuse) continue;
+    if (!kFuse || !fuse) continue;
     if (tid == 0) {
       const int prev = __hip_atomic_fetch_add(&S.ev_done[item >> 1], 1, __ATOMIC_RELEASE,
                                               __HIP_MEMORY_SCOPE_AGENT);
@@ -1800,7 +1804,9 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
       if (prev == 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    if (s_last) match_event<NT>(D, S, P, item >> 1, plain, wg, mh);
+    if constexpr (kFuse) {
+      if (s_last) match_event<NT>(D, S, P, item >> 1, plain, wg, mh);
+    }
     __syncthreads();
   }
 }
@@ -1953,6 +1959,11 @@ int smk_launch_seed(const Desc *d, const KCtx *k, int item_begin, int item_count
   else
     hipLaunchKernelGGL((k_seed<0, kSeedWG>), dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits),
                        st, d, k, item_begin, item_count, use_queue, lds_hits, plain, 0);
+  return (int)hipGetLastError();
+}
+int smk_launch_seed_nomatch(const Desc *d, const KCtx *k, int grid, int lds_hits, hipStream_t st) {
+  hipLaunchKernelGGL((k_seed<0, kSeedWG, false>), dim3(grid), dim3(kSeedWG),
+                     smk_seed_lds_bytes(lds_hits), st, d, k, 0, -1, 1, lds_hits, 0, 0);
   return (int)hipGetLastError();
 }
 int smk_launch_seed_big(const Desc *d, const KCtx *k, int grid, int lds_hits, int prep,

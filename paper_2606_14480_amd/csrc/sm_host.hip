@@ -356,6 +356,8 @@ sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
   auto seq = [&](hipStream_t q) -> hipError_t {
     int e = hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, q);
     if (!e) e = enqueue_prepare_big(c, s, q);
+    if (!e && c->dp.match_mode >= 0 && c->p.uv_mode == 0)
+      e = smk_launch_seed_nomatch(d, S, c->seed_wgs, s.lds_hits, q);
     if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
     if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, c->match_wgs, q);
     if (!e) e = smk_launch_copy(d, S, 1024, q);
@@ -402,6 +404,8 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   if (!e) e = enqueue_prepare_big(c, s, q);   // preparation and big form
   if (!e) e = hipEventRecord(ev[1], q);
   if (!e) e = hipEventRecord(ev[2], q);
+  if (!e && c->dp.match_mode >= 0 && c->p.uv_mode == 0)
+    e = smk_launch_seed_nomatch(d, S, c->seed_wgs, s.lds_hits, q);
   if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
   if (!e) e = hipEventRecord(ev[3], q);
   if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, c->match_wgs, q);
