@@ -12,6 +12,16 @@
 
 namespace smk {
 
+// The thread's index in its workgroup, as a value the compiler must treat as
+// new at every call: addresses derived from it are then formed where they are
+// used, instead of being hoisted out of the item loop and kept live (which
+// spilled them to scratch memory, a global round trip per reload).
+__device__ __forceinline__ int tidx() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // x-layer slots 0..5 <-> layers 0, 3, 4, 7, 8, 11; stereo slots 0..5 <->
 // layers 1, 2, 5, 6, 9, 10 (Sec. 1: x-u-v-x in each station).
 __device__ __forceinline__ int xlayer(int slot) { return (slot >> 1) * 4 + (slot & 1) * 3; }
@@ -742,7 +752,7 @@ template <bool kLds, int kUv, bool kSmall, int NT>
 __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const int32_t *hid,
                                           int item, unsigned nc, int nx, const DevParams &P,
                                           const Scratch &S, size_t wg, SeedShared<NT> &sh) {
-  const int tid = threadIdx.x;
+  const int tid = tidx();
   const int half = item & 1;
   const int *zoff = sh.zoff;
   Counters *cnt = S.cnt;
@@ -1068,7 +1078,7 @@ template <bool kLds, int kUv, int NT>
 __device__ __forceinline__ void seed_item(const float *X, const float *Z, const int32_t *hid,
                                           int item, int nh, const DevParams &P,
                                           const Scratch &S, size_t wg, SeedShared<NT> &sh) {
-  const int tid = threadIdx.x;
+  const int tid = tidx();
   const int half = item & 1;
   const int *zoff = sh.zoff;
   Counters *cnt = S.cnt;
@@ -1217,7 +1227,7 @@ template <bool kSmallM, int NT>
 __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, const Scratch &S,
                                                  const DevParams &P, int e, int plain, size_t wg,
                                                  MatchShared &sh) {
-  const int tid = threadIdx.x;
+  const int tid = tidx();
   MState *ms = S.ms + wg * (size_t)S.ms_cap;
   float *mf = S.mf + wg * (size_t)S.ms_cap * 6;
   Counters *cnt = S.cnt;
@@ -1655,7 +1665,7 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
   int32_t *s_id = reinterpret_cast<int32_t *>(s_z + lds_hits);
   __shared__ int s_last;
 
-  const int tid = threadIdx.x;
+  const int tid = tidx();
   const size_t wg = blockIdx.x;
   const int32_t *zone_off = D->b.zone_off;
   const float *hx = D->b.hit_x, *hz = D->b.hit_z;
