@@ -1472,12 +1472,26 @@ __device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Sc
     match_event_impl<false, NT>(D, S, P, e, plain, wg, sh);
 }
 
+// Size class of an item for the longest-first order: kFineSub classes per
+// octave of (hits + 1), from its leading four bits; monotone in the size.
+constexpr int kFineSub = 16;
+constexpr int kFineCls = 32 * kFineSub;
+__device__ __forceinline__ int fine_class(int sz) {
+  const unsigned v = (unsigned)sz + 1u;
+  const int b = 31 - __clz(v);
+  const unsigned sub = b >= 4 ? (v >> (b - 4)) & 15u : (v << (4 - b)) & 15u;
+  return b * kFineSub + (int)sub;
+}
+
 // Counters, per-event hand-off counts and (batched) the longest-first item
 // order with the big-form cut: one workgroup of 1024 threads.
 __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
                                               const KCtx *__restrict__ K, int plain) {
   const Scratch &S = K->S;
-  __shared__ int hist[32], base[32];
+  __shared__ int hist[32];
+  __shared__ int fb[kFineCls];
+  __shared__ int s_scan[16];
+  __shared__ int s_best;
   const int ne = D->n_events, n = D->n_items;
   const int32_t *zo = D->b.zone_off;
   if (threadIdx.x == 0) {
@@ -1503,7 +1517,11 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
   // item in the main form.  Order: big classes, then the rest, longest first.
   __shared__ float wsum[32];
   __shared__ int mx[32];
+  // the order itself uses finer classes: kFineSub per octave, so that items
+  // of one octave (most of a min-bias batch) are still taken longest first
+  __shared__ int fh[kFineCls];
   if (threadIdx.x < 32) { hist[threadIdx.x] = 0; wsum[threadIdx.x] = 0.0f; mx[threadIdx.x] = 0; }
+  for (int f = threadIdx.x; f < kFineCls; f += blockDim.x) fh[f] = 0;
   __syncthreads();
   const DevParams &P = K->P;
   auto latency = [&](float nh) { return P.lat_a * nh + P.lat_b * nh * nh; };
@@ -1526,6 +1544,7 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
     const float w = in ? latency((float)sz) : 0.0f;
     const unsigned long long act = __ballot(in);
     if (act == 0ull) return;
+    if (in) atomicAdd(&fh[fine_class(sz)], 1);
     const int b0 = __shfl(b, __builtin_ctzll(act), 64);
     if (__ballot(in && b != b0) == 0ull) {
       float ws = w;
@@ -1595,19 +1614,29 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
       const int ob = __shfl_xor(bb, o, 64);
       if (ot < tb || (ot == tb && ob > bb)) { tb = ot; bb = ob; }
     }
-    if (b == 0) {
-      const int best = tb < t_none ? bb : 32;
-      int acc = 0;
-      for (int k = 31; k >= 0; --k) { base[k] = acc; acc += hist[k]; }
-      S.cnt->n_big = best < 32 ? (unsigned)base[best - 1] : 0u;   // classes >= best
-      // matching: in k_match after all seeding, unless big items are in the
-      // batch; then inside the seeding kernel, where it overlaps their tail
-      S.cnt->fuse = P.match_mode < 0 ? 1u : P.match_mode > 0 ? 0u : (best < 32 ? 1u : 0u);
-    }
+    if (b == 0) s_best = tb < t_none ? bb : 32;
+  }
+  // first position of each fine class: the items of all larger classes
+  {
+    const int f = kFineCls - 1 - (int)threadIdx.x;   // descending
+    const int v = f >= 0 ? fh[f] : 0;
+    int total;
+    const int ex = block_excl_scan<1024>(v, s_scan, total);
+    if (f >= 0) fb[f] = ex;
   }
   __syncthreads();
-  // positions in the order, one atomic per wave when its items share a class;
-  // each position's record holds the item and its zone offsets
+  if (threadIdx.x == 0) {
+    const int best = s_best;
+    // the big form takes the classes >= best: the positions before the
+    // first fine class of octave best
+    S.cnt->n_big = best < 32 ? (unsigned)fb[kFineSub * best - 1] : 0u;
+    // matching: in k_match after all seeding, unless big items are in the
+    // batch; then inside the seeding kernel, where it overlaps their tail
+    S.cnt->fuse = P.match_mode < 0 ? 1u : P.match_mode > 0 ? 0u : (best < 32 ? 1u : 0u);
+  }
+  __syncthreads();
+  // positions in the order, one LDS atomic per item on its fine class; each
+  // position's record holds the item and its zone offsets
   auto place = [&](int i, const int (&z)[kNL + 1]) {
     const bool in = i < n;
     auto put = [&](int p) {
@@ -1616,20 +1645,7 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
 #pragma unroll
       for (int k = 0; k <= kNL; ++k) r.zabs[k] = z[k];
     };
-    const int sz = in ? max(z[kNL] - z[0], 0) : 0;
-    const int b = 31 - __clz(sz + 1);
-    const unsigned long long act = __ballot(in);
-    if (act == 0ull) return;
-    const int b0 = __shfl(b, __builtin_ctzll(act), 64);
-    if (__ballot(in && b != b0) == 0ull) {
-      const unsigned r = lane_rank(act);
-      int p = 0;
-      if (r == 0 && in) p = atomicAdd(&base[b0], __popcll(act));
-      p = __shfl(p, __builtin_ctzll(act), 64);
-      if (in) put(p + (int)r);
-    } else if (in) {
-      put(atomicAdd(&base[b], 1));
-    }
+    if (in) put(atomicAdd(&fb[fine_class(max(z[kNL] - z[0], 0))], 1));
   };
 #pragma unroll
   for (int c = 0; c < kPrepCache; ++c) place(c * (int)blockDim.x + (int)threadIdx.x, zc[c]);
