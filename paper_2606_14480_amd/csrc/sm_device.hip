@@ -1631,8 +1631,10 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
     // first fine class of octave best
     S.cnt->n_big = best < 32 ? (unsigned)fb[kFineSub * best - 1] : 0u;
     // matching: in k_match after all seeding, unless big items are in the
-    // batch; then inside the seeding kernel, where it overlaps their tail
-    S.cnt->fuse = P.match_mode < 0 ? 1u : P.match_mode > 0 ? 0u : (best < 32 ? 1u : 0u);
+    // batch or the main form takes more than four rounds of items; then
+    // inside the seeding kernel, where it overlaps the seeding tail
+    const bool many = n > 4 * max(P.main_slots, 1);
+    S.cnt->fuse = P.match_mode < 0 ? 1u : P.match_mode > 0 ? 0u : ((best < 32 || many) ? 1u : 0u);
   }
   __syncthreads();
   // positions in the order, one LDS atomic per item on its fine class; each
