@@ -910,7 +910,9 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
         const double e1 = xp - yhi * t0, e2 = xp - ylo * t0;
         const double lo = fmin(e1, e2), hi = fmax(e1, e2);
         const int s = zlower<kLds>(X, sh, L0, lo);
-        int e = s;
+        // window end: from the lower bound of hi (bin lookup), past hits equal to hi
+        int e = kLds ? zlower<kLds>(X, sh, L0, hi) : s;
+        if (e < s) e = s;
         while (e < zoff[L0 + 1] && (double)X[e] <= hi) ++e;
         if (pass == 0) { st0 = s; cnt0 = e - s; } else { st1 = s; cnt1 = e - s; }
       }
