@@ -211,12 +211,13 @@ sm_status sm_poll(sm_ctx *ctx, int64_t ticket, int wait);
 /* Per-kernel device time of one batched run, from HIP events recorded on
  * `stream` between the kernels (milliseconds): counters and item order,
  * with the big-item form when one launch does both (then seed_big is 0);
- * the big-item seeding form; the main seeding form (with
- * Matching inside it when the batch uses that form); the matching kernel
- * (which exits at once when Matching ran inside seeding); the offset scans
- * and copy to the caller's buffers; and the whole sequence. */
+ * the big-item seeding form; the main seeding form built without the
+ * matching code (seed) and the one with it (seed_fused), of which the one
+ * that does not fit the batch returns at once; the matching kernel (which
+ * returns at once when Matching ran inside seeding); the offset scans and
+ * copy to the caller's buffers; and the whole sequence. */
 typedef struct {
-  float prepare, seed_big, seed, match, copy, total;
+  float prepare, seed_big, seed, seed_fused, match, copy, total;
 } sm_kernel_times;
 
 /* Tracing: runs the batched form once as plain stream launches (no graph)

@@ -406,12 +406,13 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   if (!e) e = hipEventRecord(ev[2], q);
   if (!e && c->dp.match_mode >= 0 && c->p.uv_mode == 0)
     e = smk_launch_seed_nomatch(d, S, c->seed_wgs, s.lds_hits, q);
-  if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
   if (!e) e = hipEventRecord(ev[3], q);
-  if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, c->match_wgs, q);
+  if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
   if (!e) e = hipEventRecord(ev[4], q);
-  if (!e) e = smk_launch_copy(d, S, 1024, q);   // offset scans and copy
+  if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, c->match_wgs, q);
   if (!e) e = hipEventRecord(ev[5], q);
+  if (!e) e = smk_launch_copy(d, S, 1024, q);   // offset scans and copy
+  if (!e) e = hipEventRecord(ev[6], q);
   return hip_status((hipError_t)e);
 }
 
@@ -476,7 +477,7 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
     if (!graph &&
         hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, q) != hipSuccess)
       return SM_ERR_DEVICE;
-    hipEvent_t ev[6] = {};
+    hipEvent_t ev[7] = {};
     if (times) {
       for (auto &x : ev)
         if (hipEventCreate(&x) != hipSuccess) return SM_ERR_DEVICE;
@@ -490,9 +491,9 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
     if (st == SM_OK && hipStreamSynchronize(q) != hipSuccess) st = SM_ERR_DEVICE;
     if (times) {
       if (st == SM_OK) {
-        float *f = &times->prepare;   // prepare, seed_big, seed, match, copy
-        for (int k = 0; k < 5; ++k) hipEventElapsedTime(&f[k], ev[k], ev[k + 1]);
-        hipEventElapsedTime(&times->total, ev[0], ev[5]);
+        float *f = &times->prepare;   // prepare, seed_big, seed, seed_fused, match, copy
+        for (int k = 0; k < 6; ++k) hipEventElapsedTime(&f[k], ev[k], ev[k + 1]);
+        hipEventElapsedTime(&times->total, ev[0], ev[6]);
       }
       for (auto &x : ev) hipEventDestroy(x);
     }

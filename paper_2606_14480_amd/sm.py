@@ -67,7 +67,8 @@ class Batch(C.Structure):
 
 
 class KernelTimes(C.Structure):
-    _fields_ = [(n, C.c_float) for n in ("prepare", "seed_big", "seed", "match", "copy", "total")]
+    _fields_ = [(n, C.c_float) for n in ("prepare", "seed_big", "seed", "seed_fused", "match", "copy",
+                                         "total")]
 
     def as_dict(self):
         return {n: float(getattr(self, n)) for n, _ in self._fields_}
