@@ -1894,12 +1894,26 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
   const int e_lo = min(n, (int)blockIdx.x * per), e_hi = min(n, e_lo + per);
   const bool last = (e_lo < e_hi && e_hi == n) || (n == 0 && blockIdx.x == 0);
   if (e_lo >= e_hi && !last) return;
+  // pool or input errors of the earlier kernels: no copy (read first, so
+  // that the load overlaps the others)
+  const bool bad = (S.cnt->flags & (F_POOL | F_LPOOL | F_INVALID | F_UNSORTED)) != 0u;
   __shared__ long long s_part[2][4];
   __shared__ int s_tmp[16];
+  // the counts of the events before this range, four loads in flight per
+  // thread at a time (independent accumulators, clamped addresses)
   long long ps = 0, pl = 0;
-  for (int e = tid; e < e_lo; e += 256) {
-    ps += S.item_cnt[2 * e] + S.item_cnt[2 * e + 1];
-    pl += S.ev_lcnt[e];
+  for (int e0 = tid; e0 < e_lo; e0 += 1024) {
+    int a[4], b[4], c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = min(e0 + 256 * u, e_lo - 1);
+      a[u] = S.item_cnt[2 * e];
+      b[u] = S.item_cnt[2 * e + 1];
+      c[u] = S.ev_lcnt[e];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (e0 + 256 * u < e_lo) { ps += a[u] + b[u]; pl += c[u]; }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -1910,17 +1924,31 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
   __syncthreads();
   long long cs = s_part[0][0] + s_part[0][1] + s_part[0][2] + s_part[0][3];
   long long cl = s_part[1][0] + s_part[1][1] + s_part[1][2] + s_part[1][3];
+  // the range: offsets by block scans; each event's counts, pool bases and
+  // offsets stay in LDS for the copy when the range fits one pass
+  __shared__ int s_n0[256], s_n1[256], s_m[256];
+  __shared__ long long s_b0[256], s_b1[256], s_src[256], s_so[256], s_lo[256];
+  const bool one = e_hi - e_lo <= 256;
   for (int c0 = e_lo; c0 < e_hi; c0 += 256) {
     const int e = c0 + tid;
-    const int vs = e < e_hi ? S.item_cnt[2 * e] + S.item_cnt[2 * e + 1] : 0;
-    const int vl = e < e_hi ? S.ev_lcnt[e] : 0;
+    int n0 = 0, n1 = 0, m = 0;
+    long long b0 = 0, b1 = 0, src = 0;
+    if (e < e_hi) {
+      n0 = S.item_cnt[2 * e]; n1 = S.item_cnt[2 * e + 1]; m = S.ev_lcnt[e];
+      b0 = S.item_base[2 * e]; b1 = S.item_base[2 * e + 1]; src = S.ev_lbase[e];
+    }
     int ts, tl;
-    const int xs = block_excl_scan<256>(vs, s_tmp, ts);
+    const int xs = block_excl_scan<256>(n0 + n1, s_tmp, ts);
     __syncthreads();
-    const int xl = block_excl_scan<256>(vl, s_tmp, tl);
+    const int xl = block_excl_scan<256>(m, s_tmp, tl);
     if (e < e_hi) {
       D->seed_off[e] = (int32_t)(cs + xs);
       D->long_off[e] = (int32_t)(cl + xl);
+      if (one) {
+        s_n0[tid] = n0; s_n1[tid] = n1; s_m[tid] = m;
+        s_b0[tid] = b0; s_b1[tid] = b1; s_src[tid] = src;
+        s_so[tid] = cs + xs; s_lo[tid] = cl + xl;
+      }
     }
     cs += ts;
     cl += tl;
@@ -1935,17 +1963,22 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
     if (cs > D->seed_cap) raise_flag(S.cnt, F_OUT_SEED);
     if (cl > D->long_cap) raise_flag(S.cnt, F_OUT_LONG);
   }
-  if (S.cnt->flags & (F_POOL | F_LPOOL | F_INVALID | F_UNSORTED)) return;
-  __syncthreads();   // this workgroup's offsets are written
+  if (bad) return;
   for (int e = e_lo; e < e_hi; ++e) {
-    const int n0 = S.item_cnt[2 * e], n1 = S.item_cnt[2 * e + 1];
-    const long long b0 = S.item_base[2 * e], b1 = S.item_base[2 * e + 1];
-    const long long so = D->seed_off[e];
+    const int k = e - e_lo;
+    int n0, n1, m;
+    long long b0, b1, src, so, dst;
+    if (one) {
+      n0 = s_n0[k]; n1 = s_n1[k]; m = s_m[k];
+      b0 = s_b0[k]; b1 = s_b1[k]; src = s_src[k]; so = s_so[k]; dst = s_lo[k];
+    } else {
+      n0 = S.item_cnt[2 * e]; n1 = S.item_cnt[2 * e + 1]; m = S.ev_lcnt[e];
+      b0 = S.item_base[2 * e]; b1 = S.item_base[2 * e + 1]; src = S.ev_lbase[e];
+      so = D->seed_off[e]; dst = D->long_off[e];
+    }
     if (so + n0 + n1 <= D->seed_cap)
       for (int i = tid; i < n0 + n1; i += 256)
         D->seeds[so + i] = i < n0 ? S.pool[b0 + i] : S.pool[b1 + i - n0];
-    const int m = S.ev_lcnt[e];
-    const long long src = S.ev_lbase[e], dst = D->long_off[e];
     if (dst + m <= D->long_cap)
       for (int i = tid; i < m; i += 256) D->longs[dst + i] = S.lpool[src + i];
   }
