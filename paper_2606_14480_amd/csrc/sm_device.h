@@ -1,15 +1,20 @@
 // Device side of the Seeding + Matching library (gfx950, wave64).
 //
 // Kernels, in launch order for one batch:
-//   k_prepare  clear counters and per-event hand-off counts (a fill kernel, so
-//              the sequence can live in a captured graph) and order the
-//              (event, half) items by hit count, largest first
-//   k_seed     persistent: each workgroup pulls items from the queue and runs
-//              XZ seeding (both iterations), the clone vote and UV seeding of
-//              one detector half of one event, hits staged in LDS; the
-//              workgroup that completes an event's second half matches it
-//   k_match    (when chosen for the batch) Matching of every event, after
-//              all seeding, instead of the hand-off inside k_seed
+//   k_seed<0, 1024>  workgroup 0 prepares the batch (counters, per-event
+//              hand-off counts, the longest-first order of the (event, half)
+//              items, the big-form cut) and releases the other workgroups;
+//              then the big-item form: 1024-thread workgroups over the
+//              largest items (separate k_prepare with input validation)
+//   k_seed<0, 256, false> / <0, 256, true>  the main form, persistent: each
+//              workgroup pulls items from the queue and runs XZ seeding (both
+//              iterations), the clone vote and UV seeding of one detector
+//              half of one event, hits staged in LDS; built without and with
+//              the matching code, the one that does not fit the batch returns
+//              at once; with it, the workgroup that completes an event's
+//              second half matches it
+//   k_match    Matching of every event after all seeding (when the batch is
+//              matched outside seeding)
 //   k_copy     per-event offsets (scans) and the seeds and long tracks from
 //              the pools to the caller's CSR
 #pragma once

@@ -1508,8 +1508,10 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
     c->fuse = 1;
     if (plain) { D->seed_off[0] = 0; D->long_off[0] = 0; }
   }
-  for (int e = threadIdx.x; e < ne; e += blockDim.x) S.ev_done[e] = 0;
-  if (plain) return;
+  if (plain) {
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) S.ev_done[e] = 0;
+    return;
+  }
   // Size classes are log2 buckets.  The big-item form takes every class from
   // a cut B upwards; it runs before the main form.  B is chosen by a latency
   // model of one item on a 256-thread workgroup, L(n) = a n + b n^2 (us):
@@ -1658,6 +1660,8 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
     reload(i0 + (int)threadIdx.x, z);
     place(i0 + (int)threadIdx.x, z);
   }
+  // per-event hand-off counts, last: no barrier above waits for these stores
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) S.ev_done[e] = 0;
 }
 
 // Persistent Seeding + Matching: each workgroup pulls (event, half) items from
