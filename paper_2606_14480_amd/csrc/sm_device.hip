@@ -1664,10 +1664,11 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
   for (int e = threadIdx.x; e < ne; e += blockDim.x) S.ev_done[e] = 0;
 }
 
-// Persistent Seeding + Matching: each workgroup pulls (event, half) items from
-// the queue (or takes item_begin + blockIdx in the plain form) and seeds
-// them; the workgroup that completes the second half of an event then matches
-// that event.  The seeding state and the matching state share the same LDS.
+// Persistent Seeding (+ Matching): each workgroup pulls (event, half) items
+// from the queue (or takes item_begin + blockIdx in the plain form) and seeds
+// them; when the batch is matched inside seeding (kFuse instantiation), the
+// workgroup that completes the second half of an event then matches that
+// event.  The seeding state and the matching state share the same LDS.
 // NT = kSeedWG: the main form, 4 workgroups per CU, over the items after the
 // big ones in the longest-first order.  NT = kBigWG: one workgroup of 16
 // waves per CU with its own scratch, over the big items (at the head of the
@@ -1696,8 +1697,8 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
   const int32_t *hid = D->b.hit_id;
   if constexpr (kBig) {
     if (prep) {
-      // this launch also prepares the batch: workgroup 0 does k_prepare's
-      // work and then releases the others, which poll for it (bounded: on
+      // this launch also prepares the batch: workgroup 0 does what k_prepare
+      // does and then releases the others, which poll for it (bounded: on
       // giving up they flag the batch and leave, and the call fails)
       __shared__ int s_stall;
       if (blockIdx.x == 0) {
@@ -1846,7 +1847,7 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
 }
 
 // Matching (Sec. 4) as a kernel of its own, after the seeding kernels, when
-// k_prepare chose it for the batch: a persistent grid pulls events from a
+// the preparation chose it for the batch: a persistent grid pulls events from a
 // queue.  The kernel boundary orders every seed before every match, so the
 // seeding kernel needs no per-event hand-off (one agent-scope release per
 // item and one acquire per event, each an L2 write-back or invalidate on a
