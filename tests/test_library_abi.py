@@ -81,3 +81,37 @@ def test_create_rejects_bad_uv_settings():
         h = ctypes.c_void_p()
         assert lib.sm_create(None, ctypes.byref(p), None, ctypes.byref(h)) == sm.ERR_INVALID, over
         assert not h.value
+
+
+def test_binding_structs_match_header(tmp_path):
+    """Every ctypes mirror in the binding has the size and field offsets of
+    its C struct in include/sm.h (compiled here with the host compiler)."""
+    import os
+    import subprocess
+
+    from paper_2606_14480_amd import sm
+    pairs = {"sm_geometry": sm.Geometry, "sm_params": sm.Params, "sm_config": sm.Config,
+             "sm_batch": sm.Batch, "sm_kernel_times": sm.KernelTimes, "sm_out": sm.Out}
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "sm.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    # the header is plain C: build it with gcc
+    r = subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = {}
+    for line in out.splitlines():
+        cname, what, v = line.split()
+        got[(cname, what)] = int(v)
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
