@@ -1771,6 +1771,13 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
       sh.item = it;
       sh.ntrip = 0; sh.ncand = 0; sh.nseed = 0; sh.ncombo = 0; sh.nkept = 0;
     }
+    // the last quarter of the workgroups is the youngest on its CU, whose
+    // waves the issue order serves last: its first item runs at a raised wave
+    // priority so that the first round of items ends more evenly
+    if (!kBig && use_queue) {
+      if (first && blockIdx.x >= 3 * gridDim.x / 4) __builtin_amdgcn_s_setprio(2);
+      if (!first) __builtin_amdgcn_s_setprio(0);
+    }
     first = false;
     __syncthreads();
     const int item = sh.item;
