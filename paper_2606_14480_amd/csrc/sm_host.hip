@@ -623,6 +623,10 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
   c->match_wgs = c->cfg.match_wgs > 0 ? std::min(c->cfg.match_wgs, c->seed_wgs) : c->seed_wgs;
   c->dp = make_params(c->g, c->p);
   c->dp.match_mode = c->cfg.match_wgs > 0 ? 1 : (c->cfg.match_wgs < 0 ? -1 : 0);
+  // the Hough-cluster form is built only with the matching code: its batches
+  // are always matched inside the seeding kernel (with k_match chosen, that
+  // instantiation would return at once and leave the batch unseeded)
+  if (c->p.uv_mode != 0) c->dp.match_mode = -1;
   // item latency on one 256-thread workgroup, fitted to phase timers on
   // min-bias (778 hits: 93 us) and stress items (12,011 hits: 13.9 ms)
   c->dp.main_slots = c->seed_wgs;
