@@ -12,6 +12,41 @@
 
 namespace smk {
 
+// Global-memory access through an address-space-1 pointer compiles to a
+// global (not flat) instruction: a 32-bit offset from a scalar base, and not
+// counted by the LDS wait counter, so a wait for an LDS result does not also
+// wait for these loads and stores.  Pointers read from the descriptor structs
+// are generic, so the hot accesses go through these helpers.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+// whole records of library scratch, in 16-byte pieces (records a multiple
+// of 16 B, 16 B aligned) or else 8-byte pieces (a multiple of 8 B, 8 B aligned)
+typedef int gvec4 __attribute__((ext_vector_type(4)));
+typedef int gvec2 __attribute__((ext_vector_type(2)));
+template <class T>
+using gpiece = typename std::conditional<sizeof(T) % 16 == 0, gvec4, gvec2>::type;
+template <class T> __device__ __forceinline__ void gstore(T *p, const T &v) {
+  static_assert(sizeof(T) % 8 == 0, "records are stored in 8- or 16-byte pieces");
+  using V = gpiece<T>;
+  const V *s = reinterpret_cast<const V *>(&v);
+  __attribute__((address_space(1))) V *d = (__attribute__((address_space(1))) V *)p;
+#pragma unroll
+  for (unsigned k = 0; k < sizeof(T) / sizeof(V); ++k) d[k] = s[k];
+}
+template <class T> __device__ __forceinline__ T gload(const T *p) {
+  static_assert(sizeof(T) % 8 == 0, "records are loaded in 8- or 16-byte pieces");
+  using V = gpiece<T>;
+  T v;
+  V *d = reinterpret_cast<V *>(&v);
+  const __attribute__((address_space(1))) V *s = (const __attribute__((address_space(1))) V *)p;
+#pragma unroll
+  for (unsigned k = 0; k < sizeof(T) / sizeof(V); ++k) d[k] = s[k];
+  return v;
+}
+
+
 // The thread's index in its workgroup, as a value the compiler must treat as
 // new at every call: addresses derived from it are then formed where they are
 // used, instead of being hoisted out of the item loop and kept live (which
@@ -513,7 +548,7 @@ __device__ __forceinline__ int *combo_keys(SeedShared<NT> &sh) {
 template <int NT>
 __device__ __forceinline__ void push_combo(SeedShared<NT> &sh, Combo *combo, int cap, const Combo &r) {
   const unsigned slot = wave_append(&sh.ncombo);
-  if (slot < (unsigned)cap) combo[slot] = r;
+  if (slot < (unsigned)cap) gstore(&combo[slot], r);
   if (slot < (unsigned)kComboLds) {
     int *ck = combo_keys(sh);
     sh.cscore[slot] = (unsigned long long)__double_as_longlong(r.chi2);
@@ -670,7 +705,7 @@ __device__ void uv_hough(const float *X, const float *Z, SeedShared<NT> &sh, con
     const bool act = ci < nc && !(cinfo[ci] & ((1 << 4) | (1 << 5)));
     double a = 0.0, b = 0.0, c = 0.0;
     if (act) {
-      a = cand[ci].a; b = cand[ci].b; c = cand[ci].c;
+      a = gmem(cand)[ci].a; b = gmem(cand)[ci].b; c = gmem(cand)[ci].c;
     }
     for (int i = lane; i < kHoughBins; i += 64) hw.hist[i] = 0;
     hw.fsum[lane] = 0;
@@ -770,15 +805,15 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   }
   if (!small) {
     for (unsigned i = tid; i < nc; i += NT) {
-      cscore[i] = cand[i].score;
-      cinfo[i] = cand[i].n | (cand[i].it << 3);
+      cscore[i] = gmem(cand)[i].score;
+      cinfo[i] = gmem(cand)[i].n | (gmem(cand)[i].it << 3);
     }
   }
   for (int i = tid; i < nx && nc > 0; i += NT) xt[i] = ~0ull;
   __syncthreads();
   // compact x index of the hit in slot k of candidate i, or -1
   auto xidx = [&](unsigned i, int k) -> int {
-    const int p = small ? (int)sh.cpos[i][k] - 1 : cand[i].pos[k];
+    const int p = small ? (int)sh.cpos[i][k] - 1 : gmem(cand)[i].pos[k];
     return p < 0 ? -1 : p - zoff[xlayer(k)] + sh.xb[k];
   };
 
@@ -900,7 +935,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     const unsigned ci = c0 + tid;
     int cnt0 = 0, cnt1 = 0, st0 = 0, st1 = 0;
     if (ci < nc && !(cinfo[ci] & ((1 << 4) | (1 << 5)))) {
-      const double a = cand[ci].a, b = cand[ci].b, c = cand[ci].c;
+      const double a = gmem(cand)[ci].a, b = gmem(cand)[ci].b, c = gmem(cand)[ci].c;
       if (small) { cabc[3 * ci] = a; cabc[3 * ci + 1] = b; cabc[3 * ci + 2] = c; }
 #pragma unroll
       for (int pass = 0; pass < 2; ++pass) {
@@ -950,7 +985,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
       const int c = c0 + jj;
       double a, b, cc;
       if (small) { a = cabc[3 * c]; b = cabc[3 * c + 1]; cc = cabc[3 * c + 2]; }
-      else { a = cand[c].a; b = cand[c].b; cc = cand[c].c; }
+      else { a = gmem(cand)[c].a; b = gmem(cand)[c].b; cc = gmem(cand)[c].c; }
       Combo r;
       if (!uv_combo<kLds>(X, Z, sh, P, a, b, cc, 1 + pass, h0, r)) continue;
       r.c = c;
@@ -968,14 +1003,14 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   // best combination per track: most hits, then lowest chi2_y, then the
   // earlier (pass, initial hit)
   const int *ck = combo_keys(sh);
-  auto key_c = [&](unsigned i) { return i < (unsigned)kComboLds ? ck[i] : combo[i].c; };
-  auto key_n = [&](unsigned i) { return i < (unsigned)kComboLds ? ck[kComboLds + i] : combo[i].n; };
+  auto key_c = [&](unsigned i) { return i < (unsigned)kComboLds ? ck[i] : gmem(combo)[i].c; };
+  auto key_n = [&](unsigned i) { return i < (unsigned)kComboLds ? ck[kComboLds + i] : gmem(combo)[i].n; };
   auto key_tb = [&](unsigned i) {
-    return i < (unsigned)kComboLds ? ck[2 * kComboLds + i] : combo[i].tb;
+    return i < (unsigned)kComboLds ? ck[2 * kComboLds + i] : gmem(combo)[i].tb;
   };
   auto key_chi = [&](unsigned i) {
     return i < (unsigned)kComboLds ? sh.cscore[i]
-                                   : (unsigned long long)__double_as_longlong(combo[i].chi2);
+                                   : (unsigned long long)__double_as_longlong(gmem(combo)[i].chi2);
   };
   for (unsigned i = tid; i < ncb; i += NT) {
     const int c = key_c(i);
@@ -991,8 +1026,8 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   auto make_seed = [&](unsigned i) {
     // the track index from the key list, so that the candidate and the
     // combination are read together
-    const Cand &cd = cand[key_c(i)];
-    const Combo r = combo[i];
+    const Cand cd = gload(&cand[key_c(i)]);
+    const Combo r = gload(&combo[i]);
     SeedStage st;
     st.key = cd.key;
     st.s.ax = (float)cd.a; st.s.bx = (float)cd.b; st.s.cx = (float)cd.c;
@@ -1029,7 +1064,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     unsigned slot = 0;
     unsigned long long key = 0;
     if (win) {
-      key = cand[key_c(tid)].key;
+      key = gmem(cand)[key_c(tid)].key;
       slot = wave_append(&sh.nseed);
       sh.u.skey[slot] = key;
     }
@@ -1039,7 +1074,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     __syncthreads();
     const unsigned long long base = sh.pbase;
     if (win && base + ns <= (unsigned long long)S.pool_cap)
-      S.pool[base + rank_of(sh.u.skey, ns, key, slot)] = make_seed(tid).s;
+      gstore(&S.pool[base + rank_of(sh.u.skey, ns, key, slot)], make_seed(tid).s);
     return;
   }
   for (unsigned i = tid; i < ncb; i += NT) {
@@ -1068,7 +1103,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
         r = rank_of(sh.u.skey, ns, key, i);
       else
         for (unsigned j = 0; j < ns; ++j) r += sst[j].key < key;
-      S.pool[base + r] = sst[i].s;
+      gstore(&S.pool[base + r], sst[i].s);
     }
   }
 }
@@ -1100,7 +1135,7 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
     Cand cd;
     if (xz_candidate<kLds>(X, Z, sh, P, t < (unsigned)kTripLds ? sh.u.xtab[t] : trip[t], cd)) {
       const unsigned slot = wave_append(&sh.ncand);
-      if (slot < (unsigned)S.cand_cap) cand[slot] = cd;
+      if (slot < (unsigned)S.cand_cap) gstore(&cand[slot], cd);
       if (slot < (unsigned)kCandLds) {
         sh.cscore[slot] = cd.score;
         sh.cinfo[slot] = cd.n | (cd.it << 3);
@@ -1168,7 +1203,8 @@ __device__ __forceinline__ PairEval eval_pair(const MState &m, double xv, double
 // from the seed's x-z parameters and its y line (the only fields read)
 __device__ __forceinline__ MState seed_state(const sm_seed *s, const DevParams &P) {
   MState m;
-  const double a = s->ax, b = s->bx, c = s->cx, y0 = s->y0, ty = s->ty;
+  const auto *g = gmem(s);
+  const double a = g->ax, b = g->bx, c = g->cx, y0 = g->y0, ty = g->ty;
   const double us = P.z_state - P.zref;
   m.xs = a + b * us + c * gd(us, P.d);
   m.txs = b + c * (2.0 * us + 3.0 * P.d * us * us);
@@ -1238,10 +1274,10 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     sh.nkeep = 0;
     sh.nplist = 0;
   }
-  const int n0 = S.item_cnt[2 * e], n1 = S.item_cnt[2 * e + 1];
-  const int b0 = S.item_base[2 * e], b1 = S.item_base[2 * e + 1];
+  const int n0 = gmem(S.item_cnt)[2 * e], n1 = gmem(S.item_cnt)[2 * e + 1];
+  const int b0 = gmem(S.item_base)[2 * e], b1 = gmem(S.item_base)[2 * e + 1];
   const int ns = n0 + n1;
-  const int v0 = D->b.velo_off[e], nv = D->b.velo_off[e + 1] - v0;
+  const int v0 = gmem(D->b.velo_off)[e], nv = gmem(D->b.velo_off)[e + 1] - v0;
   const bool pool_ok = !(cnt->flags & F_POOL);
   const int so = plain ? D->seed_off[e] : 0;
   if (tid == 0 && plain) D->seed_off[e + 1] = so + ns;
@@ -1265,11 +1301,11 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   const bool vlds = fits && ns > 0 && kSmallM && nv <= kVflat && nv <= NT;
   float vxr = 0.0f, vyr = 0.0f, vzr = 0.0f, vtxr = 0.0f, vtyr = 0.0f;
   if (vlds && tid < nv) {
-    vxr = D->b.velo_x[v0 + tid];
-    vyr = D->b.velo_y[v0 + tid];
-    vzr = D->b.velo_z[v0 + tid];
-    vtxr = D->b.velo_tx[v0 + tid];
-    vtyr = D->b.velo_ty[v0 + tid];
+    vxr = gmem(D->b.velo_x)[v0 + tid];
+    vyr = gmem(D->b.velo_y)[v0 + tid];
+    vzr = gmem(D->b.velo_z)[v0 + tid];
+    vtxr = gmem(D->b.velo_tx)[v0 + tid];
+    vtyr = gmem(D->b.velo_ty)[v0 + tid];
   }
   // the event's seeds in canonical order (half 0 then half 1); the plain form
   // copies whole records to the caller, matching reads five fields of each
@@ -1278,7 +1314,7 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
       if ((long long)so + i < D->seed_cap) D->seeds[so + i] = i < n0 ? S.pool[b0 + i] : S.pool[b1 + i - n0];
   for (int i = tid; i < ns && pool_ok && fits; i += NT) {
     const MState m = seed_state(i < n0 ? &S.pool[b0 + i] : &S.pool[b1 + i - n0], P);
-    ms[i] = m;
+    gstore(&ms[i], m);
     xsf[i] = m.xsf; txsf[i] = m.txsf; ymf[i] = m.y_mf; tyf[i] = m.tyf;
     best_s[i] = ~0ull;
   }
@@ -1307,13 +1343,13 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   };
   auto evaluate = [&](int v, int s, float xvf, float yvf, float zvf, float txvf, float tyvf,
                       unsigned long long &bits) {
-    const PairEval r = eval_pair(ms[s], xvf, yvf, zvf, txvf, tyvf, P);
+    const PairEval r = eval_pair(gload(&ms[s]), xvf, yvf, zvf, txvf, tyvf, P);
     if (!r.ok) return false;
     bits = (unsigned long long)__double_as_longlong(r.chi2);
     atomicMin(&best_s[s], bits);
     const unsigned slot = atomicAdd(&sh.nsurv, 1u);
     if (slot < (unsigned)kSurvLds) sh.surv[slot] = Surv{v, s, r.chi2};
-    else if (slot < (unsigned)(kSurvLds + S.surv_cap)) surv[slot - kSurvLds] = Surv{v, s, r.chi2};
+    else if (slot < (unsigned)(kSurvLds + S.surv_cap)) gstore(&surv[slot - kSurvLds], Surv{v, s, r.chi2});
     return true;
   };
   auto test_pair = [&](int v, int s, float xvf, float yvf, float zvf, float txvf, float tyvf,
@@ -1387,8 +1423,9 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     }
   } else if (fits && ns > 0) {
     for (int v = tid; v < nv; v += NT) {
-      const float xvf = D->b.velo_x[v0 + v], yvf = D->b.velo_y[v0 + v], zvf = D->b.velo_z[v0 + v];
-      const float txvf = D->b.velo_tx[v0 + v], tyvf = D->b.velo_ty[v0 + v];
+      const float xvf = gmem(D->b.velo_x)[v0 + v], yvf = gmem(D->b.velo_y)[v0 + v],
+                  zvf = gmem(D->b.velo_z)[v0 + v];
+      const float txvf = gmem(D->b.velo_tx)[v0 + v], tyvf = gmem(D->b.velo_ty)[v0 + v];
       unsigned long long bv = ~0ull;
       const float thi = tyvf + P.pre_dty;
       for (int k = lower_f(sty, 0, ns, tyvf - P.pre_dty); k < ns && sty[k] <= thi; ++k) {
@@ -1409,7 +1446,7 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   unsigned long long *kkey =
       nsv <= (unsigned)kSurvLds ? sh.kkey : (unsigned long long *)(surv + S.surv_cap);
   for (unsigned i = tid; i < nsv; i += NT) {
-    const Surv sv = i < (unsigned)kSurvLds ? sh.surv[i] : surv[i - kSurvLds];
+    const Surv sv = i < (unsigned)kSurvLds ? sh.surv[i] : gload(&surv[i - kSurvLds]);
     const unsigned long long bits = (unsigned long long)__double_as_longlong(sv.chi2);
     if (best_v[sv.v] == bits && best_s[sv.s] == bits) {
       const unsigned slot = atomicAdd(&sh.nkeep, 1u);
@@ -1448,14 +1485,15 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     const int vi = (int)(key >> 32), si = (int)(key & 0xffffffffu);
     const int v = v0 + vi;
     const PairEval pe =
-        vlds ? eval_pair(ms[si], sh.vx[vi], sh.vy[vi], sh.vz[vi], sh.vtx[vi], sh.vty[vi], P)
-             : eval_pair(ms[si], D->b.velo_x[v], D->b.velo_y[v], D->b.velo_z[v],
-                         D->b.velo_tx[v], D->b.velo_ty[v], P);
+        vlds ? eval_pair(gload(&ms[si]), sh.vx[vi], sh.vy[vi], sh.vz[vi], sh.vtx[vi], sh.vty[vi], P)
+             : eval_pair(gload(&ms[si]), gmem(D->b.velo_x)[v], gmem(D->b.velo_y)[v],
+                         gmem(D->b.velo_z)[v], gmem(D->b.velo_tx)[v], gmem(D->b.velo_ty)[v], P);
     sm_long L;
-    L.velo_idx = vi; L.seed_idx = si; L.velo_id = D->b.velo_id[v];
+    L.velo_idx = vi; L.seed_idx = si; L.velo_id = gmem(D->b.velo_id)[v];
     L.qop = (float)pe.qop; L.chi2 = (float)pe.chi2; L.z_match = (float)pe.zm;
     L.dx = (float)pe.dx; L.dy = (float)pe.dy; L.dtx = (float)pe.dtx; L.dty = (float)pe.dty;
-    dst[lb + r] = L;
+    if (plain) dst[lb + r] = L;
+    else gstore(&dst[lb + r], L);
   }
   if (plain && tid == 0 && (long long)(lb + nk) > D->long_cap) raise_flag(cnt, F_OUT_LONG);
 }
@@ -1756,10 +1794,10 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
       if (q < n_items) {
         // every load issued before the first LDS store
         if (use_queue) {
-          const ItemRec *r = &S.item_rec[q0 + q];
-          it = r->item;
+          const ItemRec r = gload(&S.item_rec[q0 + q]);
+          it = r.item;
 #pragma unroll
-          for (int k = 0; k <= kNL; ++k) z[k] = r->zabs[k];
+          for (int k = 0; k <= kNL; ++k) z[k] = r.zabs[k];
         } else {
           it = item_begin + q;
 #pragma unroll
@@ -1804,9 +1842,9 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
     } else if (nh <= lds_hits) {
       // stage the item's hits; every bin entry starts at its zone's size
       for (int i = tid; i < nh; i += NT) {
-        s_x[i] = hx[base + i];
-        s_z[i] = hz[base + i];
-        s_id[i] = hid[base + i];
+        s_x[i] = gmem(hx)[base + i];
+        s_z[i] = gmem(hz)[base + i];
+        s_id[i] = gmem(hid)[base + i];
       }
       for (int i = tid; i < kNL * kBins; i += NT) {
         const int L = i / kBins;
@@ -1990,9 +2028,9 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
     }
     if (so + n0 + n1 <= D->seed_cap)
       for (int i = tid; i < n0 + n1; i += 256)
-        D->seeds[so + i] = i < n0 ? S.pool[b0 + i] : S.pool[b1 + i - n0];
+        D->seeds[so + i] = gload(i < n0 ? &S.pool[b0 + i] : &S.pool[b1 + i - n0]);
     if (dst + m <= D->long_cap)
-      for (int i = tid; i < m; i += 256) D->longs[dst + i] = S.lpool[src + i];
+      for (int i = tid; i < m; i += 256) D->longs[dst + i] = gload(&S.lpool[src + i]);
   }
 }
 
