@@ -1533,7 +1533,7 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
   __shared__ int s_scan[16];
   __shared__ int s_best;
   const int ne = D->n_events, n = D->n_items;
-  const int32_t *zo = D->b.zone_off;
+  const auto *zo = gmem(D->b.zone_off);
   if (threadIdx.x == 0) {
     Counters *c = S.cnt;
     c->seed_queue = 0; c->match_queue = 0; c->flags = 0;
@@ -1547,7 +1547,7 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
     if (plain) { D->seed_off[0] = 0; D->long_off[0] = 0; }
   }
   if (plain) {
-    for (int e = threadIdx.x; e < ne; e += blockDim.x) S.ev_done[e] = 0;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) gmem(S.ev_done)[e] = 0;
     return;
   }
   // Size classes are log2 buckets.  The big-item form takes every class from
@@ -1684,10 +1684,12 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
   auto place = [&](int i, const int (&z)[kNL + 1]) {
     const bool in = i < n;
     auto put = [&](int p) {
-      ItemRec &r = S.item_rec[p];
+      ItemRec r;
       r.item = i;
 #pragma unroll
       for (int k = 0; k <= kNL; ++k) r.zabs[k] = z[k];
+      r.pad[0] = r.pad[1] = 0;
+      gstore(&S.item_rec[p], r);
     };
     if (in) put(atomicAdd(&fb[fine_class(max(z[kNL] - z[0], 0))], 1));
   };
@@ -1699,7 +1701,7 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
     place(i0 + (int)threadIdx.x, z);
   }
   // per-event hand-off counts, last: no barrier above waits for these stores
-  for (int e = threadIdx.x; e < ne; e += blockDim.x) S.ev_done[e] = 0;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) gmem(S.ev_done)[e] = 0;
 }
 
 // Persistent Seeding (+ Matching): each workgroup pulls (event, half) items
@@ -1957,9 +1959,9 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = min(e0 + 256 * u, e_lo - 1);
-      a[u] = S.item_cnt[2 * e];
-      b[u] = S.item_cnt[2 * e + 1];
-      c[u] = S.ev_lcnt[e];
+      a[u] = gmem(S.item_cnt)[2 * e];
+      b[u] = gmem(S.item_cnt)[2 * e + 1];
+      c[u] = gmem(S.ev_lcnt)[e];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -1984,8 +1986,8 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
     int n0 = 0, n1 = 0, m = 0;
     long long b0 = 0, b1 = 0, src = 0;
     if (e < e_hi) {
-      n0 = S.item_cnt[2 * e]; n1 = S.item_cnt[2 * e + 1]; m = S.ev_lcnt[e];
-      b0 = S.item_base[2 * e]; b1 = S.item_base[2 * e + 1]; src = S.ev_lbase[e];
+      n0 = gmem(S.item_cnt)[2 * e]; n1 = gmem(S.item_cnt)[2 * e + 1]; m = gmem(S.ev_lcnt)[e];
+      b0 = gmem(S.item_base)[2 * e]; b1 = gmem(S.item_base)[2 * e + 1]; src = gmem(S.ev_lbase)[e];
     }
     int ts, tl;
     const int xs = block_excl_scan<256>(n0 + n1, s_tmp, ts);
@@ -2022,8 +2024,8 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
       n0 = s_n0[k]; n1 = s_n1[k]; m = s_m[k];
       b0 = s_b0[k]; b1 = s_b1[k]; src = s_src[k]; so = s_so[k]; dst = s_lo[k];
     } else {
-      n0 = S.item_cnt[2 * e]; n1 = S.item_cnt[2 * e + 1]; m = S.ev_lcnt[e];
-      b0 = S.item_base[2 * e]; b1 = S.item_base[2 * e + 1]; src = S.ev_lbase[e];
+      n0 = gmem(S.item_cnt)[2 * e]; n1 = gmem(S.item_cnt)[2 * e + 1]; m = gmem(S.ev_lcnt)[e];
+      b0 = gmem(S.item_base)[2 * e]; b1 = gmem(S.item_base)[2 * e + 1]; src = gmem(S.ev_lbase)[e];
       so = D->seed_off[e]; dst = D->long_off[e];
     }
     if (so + n0 + n1 <= D->seed_cap)
