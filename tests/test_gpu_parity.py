@@ -83,6 +83,20 @@ def test_minbias_full_size(orc, sm, ctx):
     check(orc, sm, ctx, b, "minbias 1000")
 
 
+def test_global_hit_path_parity(orc, sm):
+    """An LDS hit capacity of 256, below every min-bias item: each item reads
+    its hits from global memory (and its candidate-side arrays from global
+    scratch where they outgrow LDS), against the oracle."""
+    b = ev.generate(ev.config(2, n_events=100))
+    say("[gpu] global hit path, minbias 100, lds_hits 256, smallest item",
+        int(np.diff(b.zone_off[::12].astype(np.int64)).min()))
+    c = sm.Context(lds_hits=256)
+    try:
+        check(orc, sm, c, b, "minbias 100, lds_hits 256")
+    finally:
+        c.close()
+
+
 def test_uneven_subset(orc, sm, ctx):
     b = ev.generate(ev.config(3, n_events=300))
     check(orc, sm, ctx, b, "uneven 300")
