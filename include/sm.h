@@ -108,7 +108,10 @@ typedef struct {
 typedef struct {
   int32_t device;          /* HIP device ordinal */
   int32_t n_slots;         /* concurrent serving slots (sm_submit), default 2 */
-  int32_t seed_wgs;        /* persistent workgroups of the seeding kernel (0: auto) */
+  int32_t seed_wgs;        /* persistent workgroups of the seeding kernel (0: auto);
+                              otherwise at least 2 (the per-event form runs one
+                              workgroup per detector half), else sm_create
+                              returns SM_ERR_INVALID */
   int32_t match_wgs;       /* where batched Matching runs.  0: chosen per batch: a
                               matching kernel of seed_wgs workgroups after the
                               seeding kernels, or, when the batch has items for

@@ -270,6 +270,10 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
   return SM_OK;
 }
 
+// Runs of one batch (the first and the re-runs after scratch growth) before
+// a call gives up with SM_ERR_CAPACITY.
+constexpr int kMaxTries = 8;
+
 bool grow(int &cap, unsigned need) {
   if (need == 0) need = (unsigned)cap + 1;
   long long n = cap;
@@ -468,7 +472,7 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
   if (hipSetDevice(c->device) != hipSuccess) return SM_ERR_DEVICE;
   Slot &s = c->slots[0];
   hipStream_t q = (hipStream_t)stream;
-  for (int tries = 0; tries < 8; ++tries) {
+  for (int tries = 0; tries < kMaxTries; ++tries) {
     if ((st = fit_batch(c, s, *b)) != SM_OK) return st;
     fill_desc(s, *b, *o);
     // the batched graph uploads the descriptor and copies the counters back
@@ -573,7 +577,10 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
   if (g) c->g = *g; else sm_default_geometry(&c->g);
   if (p) c->p = *p; else sm_default_params(&c->p);
   if (cfg) c->cfg = *cfg;
-  if (c->p.p_min <= 0 || c->p.sigma_x <= 0 || c->p.min_x_hits < 4 || c->p.min_x_hits > 6 ||
+  // the per-event form launches two workgroups (one per detector half) on the
+  // per-workgroup scratch, so a context needs scratch for at least two
+  if ((c->cfg.seed_wgs != 0 && c->cfg.seed_wgs < 2) ||
+      c->p.p_min <= 0 || c->p.sigma_x <= 0 || c->p.min_x_hits < 4 || c->p.min_x_hits > 6 ||
       c->p.min_uv_hits < 3 || c->p.min_uv_hits > 6 ||
       c->p.invp_a * c->p.invp_a + 4.0 * c->p.invp_b / c->p.p_min < 0 ||
       // the Hough-cluster UV kernel (uv_mode 1) is switched off: one run of
@@ -722,7 +729,13 @@ sm_status sm_poll(sm_ctx *ctx, int64_t ticket, int wait) {
       sm_status st;
       s.out->n_seeds = s.h_cnt->total_seeds;
       s.out->n_longs = s.h_cnt->total_longs;
-      if (needs_rerun(ctx, s, st) && ++s.tries < 8) {
+      if (needs_rerun(ctx, s, st)) {
+        if (++s.tries >= kMaxTries) {
+          // scratch grown kMaxTries times and still too small: the last run
+          // dropped work, so its outputs are not reported as complete
+          s.busy = false;
+          return SM_ERR_CAPACITY;
+        }
         if ((st = start_slot(ctx, s)) != SM_OK) { s.busy = false; return st; }
         if (!wait) return SM_ERR_NOT_READY;
         continue;

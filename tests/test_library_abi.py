@@ -115,3 +115,15 @@ def test_binding_structs_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_context_refuses_single_workgroup():
+    """A seeding grid below two workgroups is refused before any device call:
+    the per-event form runs one workgroup per detector half on the
+    per-workgroup scratch, which is sized by the grid."""
+    import pytest
+    from paper_2606_14480_amd import sm
+    for w in (1, -3):
+        with pytest.raises(sm.SmError) as e:
+            sm.Context(seed_wgs=w)
+        assert e.value.status == sm.ERR_INVALID
