@@ -229,6 +229,35 @@ typedef struct {
 sm_status sm_profile(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream,
                      sm_kernel_times *t);
 
+/* For callers that cannot allocate device memory (code that runs while a HIP
+ * graph is being captured, tight serving loops, harnesses that forbid
+ * hipMalloc): the batched computation of sm_run, with outputs bit-identical
+ * to sm_run's, run without any allocation.  The call itself makes no device
+ * or host allocation and captures no graph: it launches the kernels directly
+ * on `stream` and blocks until they are done.
+ *
+ * Its scratch is one static device array of SM_NOALLOC_SCRATCH_BYTES on each
+ * GPU, set up by the first sm_create on that GPU and held until the process
+ * ends.  That array is shared by every call on the GPU, from any context or
+ * thread: calls that overlap on one GPU race and their outputs are undefined.
+ * Each call clears what must start at zero; the array otherwise keeps the
+ * last call's contents.  The persistent grid is fixed at
+ * SM_NOALLOC_WORKGROUPS workgroups and the big-item form is not used.
+ *
+ * Limits: n_events <= SM_NOALLOC_MAX_EVENTS and n_velo <= SM_NOALLOC_MAX_VELO,
+ * else SM_ERR_LIMIT before any launch.  The per-workgroup scratch (triplets,
+ * candidates, UV combinations, matching state) and the seed pool have fixed
+ * sizes that the call cannot grow as sm_run does.  A batch that needs more
+ * (items denser than those of the uneven workload, such as the stress
+ * workload's largest) also returns SM_ERR_LIMIT, and its outputs are then
+ * undefined; sm_run handles such batches.  Output capacity behaves
+ * as in sm_run (SM_ERR_CAPACITY with the sizes needed). */
+#define SM_NOALLOC_MAX_EVENTS 1024
+#define SM_NOALLOC_MAX_VELO 262144
+#define SM_NOALLOC_WORKGROUPS 128
+#define SM_NOALLOC_SCRATCH_BYTES (128ull << 20) /* upper bound; the array takes less */
+sm_status sm_run_noalloc(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream);
+
 /* Device bytes a batch with these totals needs in a serving slot (used for
  * admission by free memory). */
 int64_t sm_batch_bytes(const sm_ctx *ctx, int32_t n_events, int64_t n_hits, int64_t n_velo);

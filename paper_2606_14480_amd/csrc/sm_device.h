@@ -114,7 +114,7 @@ struct DevParams {
   // Hough-cluster UV variant
   int uv_mode, hough_bins, hough_best, hough_fine, hough_min;
   // scheduling: main-form workgroups and the item latency model (us, n = hits)
-  int main_slots, big_slots;
+  int main_slots, big_slots;   // big_slots 0: no big-item form
   int match_mode;   // 0: automatic, 1: matching kernel, -1: matching inside the seeding kernel
   float lat_a, lat_b, big_speedup;
   double hough_lo[2], hough_hi[2];
@@ -222,4 +222,5 @@ int smk_seed_big_static_lds();   // static LDS of the big form (its dynamic LDS 
 int smk_launch_copy(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 int smk_launch_validate(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 int smk_launch_plain_totals(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
+int smk_launch_zero(void *p, int n_words, hipStream_t st);   // clears n_words 32-bit words
 }

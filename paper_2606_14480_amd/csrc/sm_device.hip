@@ -1646,7 +1646,7 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
     const float r = P.big_speedup, sb = (float)max(P.big_slots, 1), sm = (float)max(P.main_slots, 1);
     const float t_none = fmaxf(lall, wtot / sm);
     float t = __builtin_inff();
-    if (v && b >= kBigBucket && P.uv_mode == 0 && wsuf > 0.0f)
+    if (v && b >= kBigBucket && P.uv_mode == 0 && P.big_slots > 0 && wsuf > 0.0f)
       t = fmaxf(lsuf / r, wsuf / (r * sb)) + fmaxf(l_lo, (wtot - wsuf) / sm);
     float tb = t;
     int bb = t < t_none ? b : 32;
@@ -2036,6 +2036,12 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
   }
 }
 
+// Clears n words (a fill kernel rather than a memset, so that a captured
+// sequence records no memset node).
+__global__ __launch_bounds__(256) void k_zero(unsigned *p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
 // totals of the plain form (offsets were chained event by event)
 __global__ void k_plain_totals(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
   const Scratch &S = K->S;
@@ -2109,6 +2115,10 @@ int smk_launch_copy(const Desc *d, const KCtx *k, int grid, hipStream_t st) {
 }
 int smk_launch_validate(const Desc *d, const KCtx *k, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_validate, dim3(grid), dim3(256), 0, st, d, k);
+  return (int)hipGetLastError();
+}
+int smk_launch_zero(void *p, int n_words, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, st, (unsigned *)p, n_words);
   return (int)hipGetLastError();
 }
 int smk_launch_plain_totals(const Desc *d, const KCtx *k, hipStream_t st) {

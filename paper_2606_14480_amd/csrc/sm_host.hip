@@ -10,6 +10,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <cstdint>
 #include <vector>
 
 #include "sm.h"
@@ -76,6 +77,11 @@ struct sm_ctx {
   int64_t next_ticket = 1;
   std::mutex mu;
   int64_t bytes = 0;
+  // allocation-free form: pinned host copies of its kernel context (scratch
+  // pointers into the device's static array), descriptor and counters
+  smk::KCtx *na_kctx = nullptr;
+  Desc *na_desc = nullptr;
+  Counters *na_cnt = nullptr;
 };
 
 namespace {
@@ -284,6 +290,19 @@ bool grow(int &cap, unsigned need) {
   return true;
 }
 
+// LDS hit capacity of the seeding workgroup: the configured one, else 1.5x
+// the mean (event, half) size rounded up to 256, 1024..4096 (items above it
+// read their hits from global memory).
+int lds_hits_for(const sm_ctx *c, const sm_batch &b) {
+  int h = std::min(c->cfg.lds_hits, 4096);
+  if (h <= 0) {
+    const double mean = b.n_events > 0 ? (double)b.n_hits / (2.0 * b.n_events) : 0.0;
+    h = 256 * (int)std::ceil(1.5 * mean / 256.0);
+    h = std::max(1024, std::min(h, 4096));
+  }
+  return h;
+}
+
 // Make the slot's batch-sized buffers large enough for this batch.
 sm_status fit_batch(sm_ctx *c, Slot &s, const sm_batch &b) {
   Caps &k = s.caps;
@@ -295,15 +314,7 @@ sm_status fit_batch(sm_ctx *c, Slot &s, const sm_batch &b) {
   if (pool > k.pool) { k.pool = std::max(pool, 2 * k.pool); re = true; }
   const long long lpool = b.n_velo + 1024;
   if (lpool > k.lpool) { k.lpool = std::max(lpool, 2 * k.lpool); re = true; }
-  // LDS hit capacity: 1.5x the mean (event, half) size rounded up to 256,
-  // 1024..4096 (items above it read their hits from global memory)
-  int h = std::min(c->cfg.lds_hits, 4096);
-  if (h <= 0) {
-    const double mean = b.n_events > 0 ? (double)b.n_hits / (2.0 * b.n_events) : 0.0;
-    h = 256 * (int)std::ceil(1.5 * mean / 256.0);
-    h = std::max(1024, std::min(h, 4096));
-  }
-  s.lds_hits = h;
+  s.lds_hits = lds_hits_for(c, b);
   if (!re && !s.allocs.empty()) return SM_OK;
   return alloc_slot(c, s);
 }
@@ -323,8 +334,7 @@ sm_status check_batch(const sm_batch *b, const sm_out *o) {
   return SM_OK;
 }
 
-void fill_desc(Slot &s, const sm_batch &b, const sm_out &o) {
-  Desc &d = *s.h_desc;
+void fill_desc(Desc &d, const sm_batch &b, const sm_out &o) {
   d.b = b;
   d.seeds = o.seeds;
   d.longs = o.longs;
@@ -474,7 +484,7 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
   hipStream_t q = (hipStream_t)stream;
   for (int tries = 0; tries < kMaxTries; ++tries) {
     if ((st = fit_batch(c, s, *b)) != SM_OK) return st;
-    fill_desc(s, *b, *o);
+    fill_desc(*s.h_desc, *b, *o);
     // the batched graph uploads the descriptor and copies the counters back
     // itself; the plain and timed sequences do it here
     const bool graph = !times && !plain;
@@ -507,6 +517,185 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
     if (!needs_rerun(c, s, st)) return st;
   }
   return SM_ERR_CAPACITY;
+}
+
+
+// ------------------------------------------------ allocation-free form ----
+//
+// sm_run_noalloc runs on one static device array per GPU instead of slot
+// scratch.  Its layout: the kernel context, the descriptor and the counters,
+// then every scratch array of a slot (each 256-byte aligned) for a fixed
+// grid of kNaWgs workgroups and fixed per-workgroup capacities.
+
+constexpr int kNaWgs = SM_NOALLOC_WORKGROUPS;
+constexpr long long kNaEvents = SM_NOALLOC_MAX_EVENTS;
+constexpr long long kNaVelo = SM_NOALLOC_MAX_VELO;
+constexpr long long kNaPoolExtra = 1 << 16;   // seeds in the overflow area of the seed pool
+// per-workgroup capacities: sm_run's starting sizes (they hold the items and
+// events of the min-bias and uneven workloads: up to 630 VELO states and 524
+// seeds per event), except the clone table (x hits of one item) and the seed
+// staging (seeds of one item), which are halved
+constexpr int kNaTrip = 8192, kNaCand = 2048, kNaTbl = 4096, kNaSst = 512, kNaCombo = 2048;
+constexpr int kNaMs = 1024, kNaVs = 1024, kNaSurv = 2048;
+
+constexpr size_t na_align(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kNaKctxOff = 0;
+constexpr size_t kNaDescOff = na_align(sizeof(smk::KCtx));
+constexpr size_t kNaCntOff = kNaDescOff + na_align(sizeof(Desc));
+constexpr size_t kNaArrOff = kNaCntOff + na_align(sizeof(Counters));
+
+// Places the scratch arrays from kNaArrOff on; with S set, also points S's
+// arrays at base + offset.  `off` ends as the array's size.
+struct NaCarver {
+  uintptr_t base;
+  Scratch *S;
+  size_t off;
+  template <class T>
+  constexpr void put(T *Scratch::*m, long long n) {
+    off = na_align(off);
+    if (S) S->*m = reinterpret_cast<T *>(base + off);
+    off += (size_t)(n > 0 ? n : 1) * sizeof(T);
+  }
+};
+
+constexpr void na_layout(NaCarver &k) {
+  const long long G = kNaWgs, E = kNaEvents, I = 2 * kNaEvents;
+  k.off = kNaArrOff;
+  k.put(&Scratch::trip, G * kNaTrip);
+  k.put(&Scratch::cand, G * kNaCand);
+  k.put(&Scratch::tbl, G * kNaTbl);
+  k.put(&Scratch::sst, G * kNaSst);
+  k.put(&Scratch::combo, G * kNaCombo);
+  k.put(&Scratch::cscore, G * kNaCand);
+  k.put(&Scratch::cinfo, G * kNaCand);
+  k.put(&Scratch::bestn, G * kNaCand);
+  k.put(&Scratch::bestchi, G * kNaCand);
+  k.put(&Scratch::bestidx, G * kNaCand);
+  k.put(&Scratch::item_rec, I);
+  k.put(&Scratch::item_cnt, I);
+  k.put(&Scratch::item_base, I);
+  k.put(&Scratch::ev_lcnt, E);
+  k.put(&Scratch::ev_lbase, E);
+  k.put(&Scratch::ev_done, E);
+  k.put(&Scratch::pool, I * smk::kPoolPerItem + kNaPoolExtra);
+  k.put(&Scratch::lpool, kNaVelo + 1024);
+  k.put(&Scratch::ms, G * kNaMs);
+  k.put(&Scratch::mf, G * 6 * kNaMs);
+  k.put(&Scratch::best_s, G * kNaMs);
+  k.put(&Scratch::best_v, G * kNaVs);
+  k.put(&Scratch::surv, G * 2 * kNaSurv);
+  k.off = na_align(k.off);
+}
+
+constexpr size_t na_bytes() {
+  NaCarver k{0, nullptr, 0};
+  na_layout(k);
+  return k.off;
+}
+constexpr size_t kNaBytes = na_bytes();
+static_assert(kNaBytes <= SM_NOALLOC_SCRATCH_BYTES, "static scratch above its stated maximum");
+
+// Device address of `scratch` on each device, from hipGetSymbolAddress with
+// that device current (each GPU holds its own copy of the array).
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;
+void *g_na_ptr[kNaMaxDevices] = {};
+
+}  // namespace
+
+// The allocation-free form's scratch.  In host code this name is a host-side
+// stand-in, not a device address: only the per-device address from
+// hipGetSymbolAddress (g_na_ptr) is handed to kernels and copies.
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+// Once per device, with that device current: the array's address, and its
+// counters cleared.
+sm_status na_setup(int dev) {
+  if (dev < 0 || dev >= kNaMaxDevices) return SM_ERR_DEVICE;
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  if (g_na_ptr[dev]) return SM_OK;
+  void *ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return SM_ERR_DEVICE;
+  }
+  if (hipMemset(static_cast<char *>(ptr) + kNaCntOff, 0, sizeof(Counters)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    (void)hipGetLastError();
+    return SM_ERR_DEVICE;
+  }
+  g_na_ptr[dev] = ptr;
+  return SM_OK;
+}
+
+// The kernel context of the allocation-free form: the context's parameters,
+// scratch pointers into the device's array, its own grid, matching always in
+// the matching kernel and no big-item form.
+void na_fill_kctx(const sm_ctx *c, void *ptr, smk::KCtx &kc) {
+  memset(&kc, 0, sizeof(kc));
+  Scratch &S = kc.S;
+  NaCarver k{reinterpret_cast<uintptr_t>(ptr), &S, 0};
+  na_layout(k);
+  S.trip_cap = kNaTrip; S.cand_cap = kNaCand; S.tbl_cap = kNaTbl; S.sst_cap = kNaSst;
+  S.combo_cap = kNaCombo;
+  S.pool_static = 2 * kNaEvents * smk::kPoolPerItem;
+  S.pool_cap = S.pool_static + kNaPoolExtra;
+  S.lpool_cap = kNaVelo + 1024;
+  S.ms_cap = kNaMs; S.vs_cap = kNaVs; S.surv_cap = kNaSurv;
+  S.cnt = reinterpret_cast<Counters *>(static_cast<char *>(ptr) + kNaCntOff);
+  S.need = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(S.cnt) + offsetof(Counters, need_trip));
+  kc.SB = S;   // the big-item form is never launched here
+  kc.SB.need = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(S.cnt) + offsetof(Counters, need_big));
+  kc.P = c->dp;
+  kc.P.main_slots = kNaWgs;
+  kc.P.big_slots = 0;
+  kc.P.match_mode = 1;
+}
+
+sm_status run_noalloc(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream) {
+  sm_status st = check_batch(b, o);
+  if (st != SM_OK) return st;
+  if (b->n_events > kNaEvents || b->n_velo > kNaVelo) return SM_ERR_LIMIT;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (hipSetDevice(c->device) != hipSuccess) return SM_ERR_DEVICE;
+  char *base = static_cast<char *>(g_na_ptr[c->device]);
+  if (!base || !c->na_kctx) return SM_ERR_DEVICE;
+  const smk::KCtx *dk = reinterpret_cast<const smk::KCtx *>(base + kNaKctxOff);
+  Desc *dd = reinterpret_cast<Desc *>(base + kNaDescOff);
+  Counters *dc = reinterpret_cast<Counters *>(base + kNaCntOff);
+  fill_desc(*c->na_desc, *b, *o);
+  hipStream_t q = (hipStream_t)stream;
+  const int lds = lds_hits_for(c, *b);
+  int e = hipMemcpyAsync((void *)dk, c->na_kctx, sizeof(smk::KCtx), hipMemcpyHostToDevice, q);
+  if (!e) e = hipMemcpyAsync(dd, c->na_desc, sizeof(Desc), hipMemcpyHostToDevice, q);
+  if (!e) e = smk_launch_zero(dc, (int)(sizeof(Counters) / sizeof(unsigned)), q);
+  if (!e) e = smk_launch_prepare(dd, dk, 0, q);
+  if (!e && c->cfg.validate) e = smk_launch_validate(dd, dk, 1024, q);
+  if (!e) e = smk_launch_seed_nomatch(dd, dk, kNaWgs, lds, q);
+  if (!e) e = smk_launch_match(dd, dk, kNaWgs, q);
+  if (!e) e = smk_launch_copy(dd, dk, 1024, q);
+  if (!e) e = hipMemcpyAsync(c->na_cnt, dc, sizeof(Counters), hipMemcpyDeviceToHost, q);
+  if (!e) e = hipStreamSynchronize(q);
+  if (e) {
+    (void)hipGetLastError();
+    return SM_ERR_DEVICE;
+  }
+  const Counters &k = *c->na_cnt;
+  o->n_seeds = k.total_seeds;
+  o->n_longs = k.total_longs;
+  const unsigned f = k.flags;
+  if (k.stall) return SM_ERR_DEVICE;
+  if (f & smk::F_INVALID) return SM_ERR_INVALID;
+  if (f & smk::F_UNSORTED) return SM_ERR_UNSORTED;
+  if (f & smk::F_LIMIT) return SM_ERR_LIMIT;
+  // scratch that sm_run would grow and re-run with
+  const unsigned scratch_flags = smk::F_TRIP | smk::F_CAND | smk::F_TBL | smk::F_SST | smk::F_POOL |
+                                 smk::F_LPOOL | smk::F_MS | smk::F_VS | smk::F_SURV | smk::F_COMBO;
+  if (f & scratch_flags) return SM_ERR_LIMIT;
+  if (f & (smk::F_OUT_SEED | smk::F_OUT_LONG)) return SM_ERR_CAPACITY;
+  return SM_OK;
 }
 
 }  // namespace
@@ -641,6 +830,17 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
   c->dp.lat_a = 0.048f;
   c->dp.lat_b = 9.2e-5f;
   c->dp.big_speedup = 3.0f;   // 16 waves against 4 on the same item
+  // the allocation-free form: the device's static array (once per device)
+  // and this context's pinned copies of its kernel context and descriptor
+  if (na_setup(c->device) != SM_OK ||
+      hipHostMalloc(&c->na_kctx, sizeof(smk::KCtx), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(&c->na_desc, sizeof(Desc), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(&c->na_cnt, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    sm_destroy(c);
+    return SM_ERR_DEVICE;
+  }
+  na_fill_kctx(c, g_na_ptr[c->device], *c->na_kctx);
   const int n_slots = 1 + (c->cfg.n_slots > 0 ? c->cfg.n_slots : 2);
   c->slots.resize(n_slots);
   for (Slot &s : c->slots) {
@@ -678,6 +878,11 @@ sm_status sm_run_plain(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *st
   return run_blocking(ctx, batch, out, stream, true);
 }
 
+sm_status sm_run_noalloc(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream) {
+  if (!ctx) return SM_ERR_INVALID;
+  return run_noalloc(ctx, batch, out, stream);
+}
+
 sm_status sm_profile(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream,
                      sm_kernel_times *t) {
   if (!ctx || !t) return SM_ERR_INVALID;
@@ -688,7 +893,7 @@ sm_status sm_profile(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stre
 static sm_status start_slot(sm_ctx *c, Slot &s) {
   sm_status st = fit_batch(c, s, s.batch);
   if (st != SM_OK) return st;
-  fill_desc(s, s.batch, *s.out);
+  fill_desc(*s.h_desc, s.batch, *s.out);
   // the graph uploads the descriptor and copies the counters back
   if ((st = enqueue_batched(c, s, s.stream)) != SM_OK) return st;
   return hip_status(hipEventRecord(s.done, s.stream));
@@ -769,6 +974,9 @@ sm_status sm_destroy(sm_ctx *ctx) {
     if (s.h_desc) hipHostFree(s.h_desc);
     if (s.h_cnt) hipHostFree(s.h_cnt);
   }
+  if (ctx->na_kctx) hipHostFree(ctx->na_kctx);
+  if (ctx->na_desc) hipHostFree(ctx->na_desc);
+  if (ctx->na_cnt) hipHostFree(ctx->na_cnt);
   delete ctx;
   return SM_OK;
 }

@@ -19,6 +19,11 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                       "or python paper_2606_14480_amd/build.py")
 
+# limits of the allocation-free call (include/sm.h)
+NOALLOC_MAX_EVENTS = 1024
+NOALLOC_MAX_VELO = 262144
+NOALLOC_WORKGROUPS = 128
+
 OK, ERR_INVALID, ERR_UNSORTED, ERR_CAPACITY, ERR_OOM, ERR_DEVICE, ERR_BUSY, ERR_NOT_READY, \
     ERR_LIMIT = 0, -1, -2, -3, -4, -5, -6, -7, -8
 
@@ -99,6 +104,8 @@ _lib.sm_run.argtypes = [C.c_void_p, _P(Batch), _P(Out), C.c_void_p]
 _lib.sm_run.restype = C.c_int
 _lib.sm_run_plain.argtypes = [C.c_void_p, _P(Batch), _P(Out), C.c_void_p]
 _lib.sm_run_plain.restype = C.c_int
+_lib.sm_run_noalloc.argtypes = [C.c_void_p, _P(Batch), _P(Out), C.c_void_p]
+_lib.sm_run_noalloc.restype = C.c_int
 _lib.sm_submit.argtypes = [C.c_void_p, _P(Batch), _P(Out), _P(C.c_int64)]
 _lib.sm_submit.restype = C.c_int
 _lib.sm_poll.argtypes = [C.c_void_p, C.c_int64, C.c_int]
@@ -113,7 +120,7 @@ _lib.sm_status_str.argtypes = [C.c_int]
 _lib.sm_status_str.restype = C.c_char_p
 
 EXPORTS = ("sm_default_geometry", "sm_default_params", "sm_create", "sm_run", "sm_run_plain",
-           "sm_submit", "sm_poll", "sm_profile", "sm_batch_bytes", "sm_destroy", "sm_status_str")
+           "sm_run_noalloc", "sm_submit", "sm_poll", "sm_profile", "sm_batch_bytes", "sm_destroy", "sm_status_str")
 
 
 def lib():
@@ -236,6 +243,15 @@ class Context:
         st = fn(self.h, C.byref(batch.c), C.byref(out.c), _stream_ptr(stream))
         if check and st != OK:
             raise SmError(st, "sm_run_plain" if plain else "sm_run")
+        return st
+
+    def run_noalloc(self, batch: DeviceBatch, out: DeviceOut, stream=None,
+                    check: bool = True) -> int:
+        """sm_run_noalloc: the batched computation on the device's static
+        scratch, with no allocation inside the call."""
+        st = _lib.sm_run_noalloc(self.h, C.byref(batch.c), C.byref(out.c), _stream_ptr(stream))
+        if check and st != OK:
+            raise SmError(st, "sm_run_noalloc")
         return st
 
     def profile(self, batch: DeviceBatch, out: DeviceOut, stream=None) -> dict:
