@@ -126,6 +126,35 @@ static int closest_in_window(const float *x, int lo, int hi, double pred, double
   return best;
 }
 
+/* Off in a worker of an orc_run call made with log_margins = 0: the margin
+ * bookkeeping that costs a rescan or a pass of its own is then skipped. */
+static _Thread_local int g_nolog = 0;
+
+/* Margin of a closest-hit decision (see ORC_NEAR in oracle.h): with a hit
+ * chosen, the smaller of (tol - d)/tol and (d_other - d)/tol over the other
+ * hits in the window; with none, (d - tol)/tol of the nearest hit outside.
+ * INFINITY when the zone is empty. */
+static double closest_margin(const float *x, int lo, int hi, double pred, double tol, int best) {
+  double m = INFINITY;
+  if (best >= 0) {
+    const double d1 = fabs((double)x[best] - pred);
+    m = (tol - d1) / tol;
+    for (int i = first_at_least(x, lo, hi, pred - tol); i < hi && (double)x[i] <= pred + tol; ++i) {
+      if (i == best) continue;
+      const double r = fabs(fabs((double)x[i] - pred) - d1) / tol;
+      if (r < m) m = r;
+    }
+  } else {
+    const int j = first_at_least(x, lo, hi, pred);
+    if (j < hi) m = fmin(m, ((double)x[j] - pred - tol) / tol);
+    if (j > lo) m = fmin(m, (pred - (double)x[j - 1] - tol) / tol);
+  }
+  return fabs(m);
+}
+
+/* Margin of a cut q < cut (or |q| <= cut for a window), either way. */
+static double cut_margin(double q, double cut) { return fabs(cut - q) / fabs(cut); }
+
 /* Solve the 3x3 system A p = r by Gaussian elimination with partial pivoting. */
 static int solve3(double A[3][3], double r[3], double p[3]) {
   for (int k = 0; k < 3; ++k) {
@@ -235,6 +264,7 @@ static void xz_iteration(const orc_geom *g, const orc_params *P, const int32_t *
   double wc[2];
   window_constants(g, P, it, wc);
   const double dx3max = wc[0], alpha_corr = wc[1];
+  const int logm = !g_nolog;
   const int b1 = off[half * 12 + L1], e1 = off[half * 12 + L1 + 1];
   const int b2 = off[half * 12 + L2], e2 = off[half * 12 + L2 + 1];
   const int b3 = off[half * 12 + L3], e3 = off[half * 12 + L3 + 1];
@@ -264,6 +294,9 @@ static void xz_iteration(const orc_geom *g, const orc_params *P, const int32_t *
         memset(cd, 0, sizeof(*cd));
         cd->half = half;
         cd->it = it;
+        /* the two windows that admitted this combination */
+        cd->margin = fmin(cut_margin(fabs(x3 - centre), dx3max),
+                          cut_margin(fabs((double)X[i2] - pred2), tol2));
         for (int l = 0; l < ORC_NL; ++l) cd->pos[l] = -1;
         cd->pos[L1] = i1; cd->pos[L2] = i2; cd->pos[L3] = i3;
         /* Track model through the three hits (exact 3-point solve). */
@@ -279,7 +312,9 @@ static void xz_iteration(const orc_geom *g, const orc_params *P, const int32_t *
         for (int j = 0; j < 3; ++j) {
           const int L = EXT_LAYERS[it][j];
           const int lo = off[half * 12 + L], hi = off[half * 12 + L + 1];
-          const int h = closest_in_window(X, lo, hi, xmodel(pa, pb, pc, g->z[L], zr, d), P->ext_tol);
+          const double pe = xmodel(pa, pb, pc, g->z[L], zr, d);
+          const int h = closest_in_window(X, lo, hi, pe, P->ext_tol);
+          if (logm) cd->margin = fmin(cd->margin, closest_margin(X, lo, hi, pe, P->ext_tol, h));
           if (h >= 0) { cd->pos[L] = h; ++n; }
         }
         cd->n = n;
@@ -301,6 +336,7 @@ static void xz_iteration(const orc_geom *g, const orc_params *P, const int32_t *
         /* eq. seed_clone_score, READING: |c_x| so that the score is >= 0. */
         cd->score = (m == 6 ? 1.0 : 10.0) * (1000.0 * chi2 + fabs(pc));
         cd->status = chi2 < P->chi2x_max ? 0 : 2;
+        cd->margin = fmin(cd->margin, cut_margin(chi2, P->chi2x_max));
       }
     }
   }
@@ -325,6 +361,50 @@ int orc_xz_candidates(const orc_geom *g, const orc_params *p, const int32_t *zon
  * survives with >= 3 of them, or >= 2 if it has 6 hits.  Then the repeated
  * tracks of the two iterations (identical x-hit sets, Sec. 3) are removed,
  * keeping the first iteration's copy.  n_pos bounds the hit positions used. */
+/* Vote margin of every candidate: over its hits, the relative gap between
+ * its score and the lowest score of the other candidates on that hit whose
+ * x-hit set differs (identical sets carry identical scores by construction),
+ * and the x-z margin of every such candidate with a score no higher than its
+ * own (whether that rival takes part in the vote can change who owns the
+ * hit).  The first n_vote candidates are the voters; the rest are near
+ * misses of the fit, rivals only. */
+static void vote_margins(const orc_cand *c, int n, int n_vote, int n_pos, const double *xzm,
+                         double *vm) {
+  if (g_nolog) {
+    for (int i = 0; i < n_vote; ++i) vm[i] = INFINITY;
+    return;
+  }
+  int *cnt = (int *)calloc((size_t)(n_pos + 1), sizeof(int));
+  for (int i = 0; i < n; ++i)
+    for (int l = 0; l < ORC_NL; ++l)
+      if (c[i].pos[l] >= 0) ++cnt[c[i].pos[l] + 1];
+  for (int h = 0; h < n_pos; ++h) cnt[h + 1] += cnt[h];
+  int *fill = (int *)malloc(sizeof(int) * (size_t)(n_pos > 0 ? n_pos : 1));
+  int *lst = (int *)malloc(sizeof(int) * (size_t)(cnt[n_pos] > 0 ? cnt[n_pos] : 1));
+  for (int h = 0; h < n_pos; ++h) fill[h] = cnt[h];
+  for (int i = 0; i < n; ++i)
+    for (int l = 0; l < ORC_NL; ++l)
+      if (c[i].pos[l] >= 0) lst[fill[c[i].pos[l]]++] = i;
+  for (int i = 0; i < n_vote; ++i) {
+    double m = INFINITY;
+    const double scale = c[i].score > 0.0 ? c[i].score : 1e-300;
+    for (int l = 0; l < ORC_NL; ++l) {
+      const int h = c[i].pos[l];
+      if (h < 0) continue;
+      double lo = INFINITY;
+      for (int k = cnt[h]; k < cnt[h + 1]; ++k) {
+        const int j = lst[k];
+        if (j == i || memcmp(c[i].pos, c[j].pos, sizeof(c[i].pos)) == 0) continue;
+        if (j < n_vote && c[j].score < lo) lo = c[j].score;
+        if (c[j].score <= c[i].score) m = fmin(m, xzm[j]);
+      }
+      if (lo < INFINITY) m = fmin(m, fabs(c[i].score - lo) / scale);
+    }
+    vm[i] = m;
+  }
+  free(cnt); free(fill); free(lst);
+}
+
 void orc_clone_vote(const orc_cand *c, int n, int n_pos, int32_t *keep) {
   double *T = (double *)malloc(sizeof(double) * (size_t)(n_pos > 0 ? n_pos : 1));
   for (int i = 0; i < n_pos; ++i) T[i] = INFINITY;
@@ -360,15 +440,34 @@ void orc_clone_vote(const orc_cand *c, int n, int n_pos, int32_t *keep) {
  * ascending z, averaging t_y after each found hit.  Each combination gets a
  * weighted y-z line fit; the best has most hits, then lowest chi2_y, then the
  * earlier (pass, initial hit).  Returns 1 and fills `out` if a seed is made. */
+/* One UV combination as the margin log sees it. */
+typedef struct { int n, pos[ORC_NL]; double chi2, m; int valid; } uv_try;
+
+/* Near miss of kind k for the x-z track `cd` with stereo hits spos (NULL: x
+ * hits only). */
+static void push_near(dyn *near, int event, int kind, int velo, const orc_cand *cd,
+                      const int *spos, const int32_t *ID, double m) {
+  if (g_nolog) return;
+  orc_near *r = (orc_near *)dyn_push(near);
+  memset(r, 0, sizeof(*r));
+  r->event = event; r->kind = kind; r->velo_idx = velo; r->it = cd->it; r->margin = m;
+  for (int l = 0; l < ORC_NL; ++l) {
+    const int h = spos && spos[l] >= 0 ? spos[l] : cd->pos[l];
+    r->id[l] = h >= 0 ? ID[h] : -1;
+  }
+}
+
 static int uv_iterative(const orc_geom *g, const orc_params *P, const int32_t *off,
                         const float *X, const float *Z, const int32_t *ID, const orc_cand *cd,
-                        orc_seed *out) {
+                        orc_seed *out, dyn *near, int event) {
   const int half = cd->half;
   const double zr = g->z_ref, d = P->d_ratio;
   const double ylo = half == 0 ? 0.0 : -P->y_max, yhi = half == 0 ? P->y_max : 0.0;
-  int best_n = 0;
+  int best_n = 0, best_k = -1;
   double best_chi2 = 0.0, best_y0 = 0.0, best_ty = 0.0;
   int best_pos[ORC_NL];
+  dyn tries = {NULL, 0, 0, sizeof(uv_try)};
+  const int logm = !g_nolog;
   for (int pass = 0; pass < 2; ++pass) {
     const int L0 = pass == 0 ? 1 : 2;
     const double t0 = g->tan_a[L0];
@@ -385,13 +484,18 @@ static int uv_iterative(const orc_geom *g, const orc_params *P, const int32_t *o
       const double y0h = (xmodel(cd->a, cd->b, cd->c, zh0, zr, d) - X[h0]) / t0;
       double ty = y0h / zh0;
       pos[L0] = h0;
+      /* margin: the initial hit's y inside the half's range at the layer */
+      const double yw = (xp - X[h0]) / t0;
+      double mc = fmin(fabs(yw - ylo), fabs(yhi - yw)) / P->y_max;
       zs[n] = zh0; ys[n] = y0h; ws[n] = t0 * t0 / (P->sigma_x * P->sigma_x); ++n;
       for (int j = 0; j < 6; ++j) {
         const int L = UV_LAYERS[j];
         if (L == L0) continue;
         const double zl = g->z[L], tl = g->tan_a[L];
         const double pred = xmodel(cd->a, cd->b, cd->c, zl, zr, d) - ty * zl * tl;
-        const int h = closest_in_window(X, off[half * 12 + L], off[half * 12 + L + 1], pred, P->uv_tol);
+        const int zlo = off[half * 12 + L], zhi = off[half * 12 + L + 1];
+        const int h = closest_in_window(X, zlo, zhi, pred, P->uv_tol);
+        if (logm) mc = fmin(mc, closest_margin(X, zlo, zhi, pred, P->uv_tol, h));
         if (h < 0) continue;
         const double zh = Z[h];
         const double yl = (xmodel(cd->a, cd->b, cd->c, zh, zr, d) - X[h]) / tl;
@@ -399,6 +503,9 @@ static int uv_iterative(const orc_geom *g, const orc_params *P, const int32_t *o
         pos[L] = h;
         zs[n] = zh; ys[n] = yl; ws[n] = tl * tl / (P->sigma_x * P->sigma_x); ++n;
       }
+      uv_try scratch_try, *tr = logm ? (uv_try *)dyn_push(&tries) : &scratch_try;
+      tr->n = n; tr->valid = 0; tr->chi2 = INFINITY; tr->m = mc;
+      memcpy(tr->pos, pos, sizeof(pos));
       if (n < P->min_uv_hits) continue;
       double fy0, fty;
       fit_line(zs, ys, ws, n, zr, &fy0, &fty);
@@ -408,12 +515,39 @@ static int uv_iterative(const orc_geom *g, const orc_params *P, const int32_t *o
         chi2 += ws[i] * r * r;
       }
       chi2 /= (double)(n - 2);
+      tr->chi2 = chi2;
+      tr->m = fmin(mc, cut_margin(chi2, P->chi2y_max));
       if (!(chi2 < P->chi2y_max)) continue;
+      tr->valid = 1;
       if (n > best_n || (n == best_n && chi2 < best_chi2)) {
         best_n = n; best_chi2 = chi2; best_y0 = fy0; best_ty = fty;
         memcpy(best_pos, pos, sizeof(pos));
+        best_k = tries.n - 1;
       }
     }
+  }
+  double seed_m = cd->margin;
+  if (logm) {
+    /* the chosen combination's own decisions, its lead over the runners-up
+     * with as many hits, and every other combination that came near */
+    const uv_try *T = (const uv_try *)tries.p;
+    const double scale = fmax(best_chi2, 1e-3 * P->chi2y_max);
+    if (best_k >= 0) seed_m = fmin(seed_m, T[best_k].m);
+    for (int k = 0; k < tries.n; ++k) {
+      /* the chosen hit set reached again from another initial hit is the
+       * same seed, not a rival */
+      if (k == best_k || (best_k >= 0 && memcmp(T[k].pos, T[best_k].pos, sizeof(T[k].pos)) == 0))
+        continue;
+      /* any other combination may win once one of its own decisions goes
+       * the other way (a changed hit moves the t_y average and with it the
+       * later layers' hits), or once its chi2 passes the chosen one's */
+      double m = T[k].m;
+      if (best_k >= 0 && T[k].valid && T[k].n == best_n)
+        m = fmin(m, fabs(T[k].chi2 - best_chi2) / scale);
+      seed_m = fmin(seed_m, m);
+      if (near && m < ORC_NEAR) push_near(near, event, 3, -1, cd, T[k].pos, ID, fmin(m, cd->margin));
+    }
+    free(tries.p);
   }
   if (best_n == 0) return 0;
   memset(out, 0, sizeof(*out));
@@ -426,6 +560,7 @@ static int uv_iterative(const orc_geom *g, const orc_params *P, const int32_t *o
     out->pos[l] = h;
     out->id[l] = h >= 0 ? ID[h] : -1;
   }
+  out->margin = seed_m;
   return 1;
 }
 
@@ -527,7 +662,7 @@ static int uv_hough(const orc_geom *g, const orc_params *P, const int32_t *off, 
       }
       if (m == 0) continue;
       int pos[ORC_NL];
-      double chi2, y0, ty;
+      double chi2 = 0.0, y0 = 0.0, ty = 0.0;
       const int k = uv_attach(g, P, off, X, Z, cd, sum / m, pos, &chi2, &y0, &ty);
       if (k > best_n || (k > 0 && k == best_n && chi2 < best_chi2)) {
         best_n = k; best_chi2 = chi2; best_y0 = y0; best_ty = ty;
@@ -547,13 +682,14 @@ static int uv_hough(const orc_geom *g, const orc_params *P, const int32_t *off, 
     out->pos[l] = h;
     out->id[l] = h >= 0 ? ID[h] : -1;
   }
+  out->margin = cd->margin;   /* the Hough bin decisions are not logged */
   return 1;
 }
 
 int orc_uv(const orc_geom *g, const orc_params *P, const int32_t *off, const float *X,
            const float *Z, const int32_t *ID, const orc_cand *cd, orc_seed *out) {
   return P->uv_mode == 1 ? uv_hough(g, P, off, X, Z, ID, cd, out)
-                         : uv_iterative(g, P, off, X, Z, ID, cd, out);
+                         : uv_iterative(g, P, off, X, Z, ID, cd, out, NULL, 0);
 }
 
 /* ---------------------------------------------------------- Matching ---- */
@@ -561,11 +697,12 @@ int orc_uv(const orc_geom *g, const orc_params *P, const int32_t *off, const flo
 typedef struct {
   double chi2, zm, dx, dy, dtx, dty, qop;
   int ok;
+  double m;   /* accepted: smallest margin of its cuts; rejected: margin to acceptance */
 } pair_eval;
 
 /* One VELO-seed combination (Sec. 4.1, 4.2). */
 static pair_eval eval_pair(const orc_params *P, const orc_geom *g, const orc_seed *s,
-                           double xv, double yv, double zv, double txv, double tyv) {
+                           double xv, double yv, double zv, double txv, double tyv, int logm) {
   pair_eval r;
   memset(&r, 0, sizeof(r));
   const double zr = g->z_ref, d = P->d_ratio, zs = P->z_state;
@@ -582,15 +719,29 @@ static pair_eval eval_pair(const orc_params *P, const orc_geom *g, const orc_see
   const double dy = (s->y0 + s->ty * (P->z_ymatch - zr)) - (yv + tyv * (P->z_ymatch - zv));
   const double dty = s->ty - tyv;
   r.zm = zm; r.dx = dx; r.dy = dy; r.dtx = dtx; r.dty = dty;
-  if (!(fabs(dx) < P->max_dx && fabs(dy) < P->max_dy && fabs(dtx) < P->max_dtx &&
-        fabs(dty) < P->max_dty))
-    return r;
+  /* preselection margins: accepted, the tightest cut; rejected, the cut
+   * furthest from letting it through */
+  const double dev[4] = {fabs(dx), fabs(dy), fabs(dtx), fabs(dty)};
+  const double cut[4] = {P->max_dx, P->max_dy, P->max_dtx, P->max_dty};
+  double m_in = INFINITY, m_out = 0.0;
+  int pass = 1;
+  for (int k = 0; k < 4; ++k) {
+    if (dev[k] < cut[k]) {
+      if (logm) m_in = fmin(m_in, cut_margin(dev[k], cut[k]));
+    } else {
+      pass = 0;
+      if (logm) m_out = fmax(m_out, cut_margin(dev[k], cut[k]));
+    }
+  }
+  r.m = pass ? m_in : m_out;
+  if (!pass) return r;
   const double tolx = P->tolx_scale * (P->tolx_a * P->tolx_a + P->tolx_b * P->tolx_b * dtx * dtx);
   const double rho = txv * txv + tyv * tyv;
   const double toly = P->toly_scale * (P->toly_a * P->toly_a + P->toly_b * P->toly_b * rho);
   const double chi2 = dx * dx / tolx + dy * dy / toly + dtx * dtx / P->tol_tx + dty * dty / P->tol_ty;
   r.chi2 = chi2;
-  if (!(chi2 < P->chi2m_max)) return r;
+  if (!(chi2 < P->chi2m_max)) { r.m = cut_margin(chi2, P->chi2m_max); return r; }
+  r.m = fmin(r.m, cut_margin(chi2, P->chi2m_max));
   /* Momentum from the kick (READING): eq. invp evaluated on the distance at
    * z = 0 between the SciFi and VELO straight lines. */
   const double x0 = (xs - zs * txs) - (xv - zv * txv);
@@ -605,10 +756,23 @@ static pair_eval eval_pair(const orc_params *P, const orc_geom *g, const orc_see
  * chi2_match is the smallest both among the survivors sharing its seed and
  * among those sharing its VELO track (READING of the final clone removal of
  * Sec. 4.4, with chi2_match in place of the ghost probability). */
+static int match_event(const orc_geom *g, const orc_params *P, const orc_seed *seeds, int ns,
+                       int nv, const float *vx, const float *vy, const float *vz,
+                       const float *vtx, const float *vty, const int32_t *vid, orc_long *out,
+                       int cap, dyn *near, int event);
+
 int orc_match(const orc_geom *g, const orc_params *P, const orc_seed *seeds, int ns, int nv,
               const float *vx, const float *vy, const float *vz, const float *vtx,
               const float *vty, const int32_t *vid, orc_long *out, int cap) {
+  return match_event(g, P, seeds, ns, nv, vx, vy, vz, vtx, vty, vid, out, cap, NULL, 0);
+}
+
+static int match_event(const orc_geom *g, const orc_params *P, const orc_seed *seeds, int ns,
+                       int nv, const float *vx, const float *vy, const float *vz,
+                       const float *vtx, const float *vty, const int32_t *vid, orc_long *out,
+                       int cap, dyn *near, int event) {
   if (ns == 0 || nv == 0) return 0;
+  const int logm = !g_nolog;
   pair_eval *pe = (pair_eval *)malloc(sizeof(pair_eval) * (size_t)ns * (size_t)nv);
   double *best_v = (double *)malloc(sizeof(double) * (size_t)nv);
   double *best_s = (double *)malloc(sizeof(double) * (size_t)ns);
@@ -616,69 +780,144 @@ int orc_match(const orc_geom *g, const orc_params *P, const orc_seed *seeds, int
   for (int s = 0; s < ns; ++s) best_s[s] = INFINITY;
   for (int v = 0; v < nv; ++v)
     for (int s = 0; s < ns; ++s) {
-      pair_eval r = eval_pair(P, g, &seeds[s], vx[v], vy[v], vz[v], vtx[v], vty[v]);
+      pair_eval r = eval_pair(P, g, &seeds[s], vx[v], vy[v], vz[v], vtx[v], vty[v], logm);
       pe[(size_t)v * ns + s] = r;
       if (r.ok) {
         if (r.chi2 < best_v[v]) best_v[v] = r.chi2;
         if (r.chi2 < best_s[s]) best_s[s] = r.chi2;
       }
     }
+  /* the lead of a pair over the other survivors of its row and its column */
+  const double floor_m = 1e-3 * P->chi2m_max;
+  double *sec_v = (double *)malloc(sizeof(double) * (size_t)nv);
+  double *sec_s = (double *)malloc(sizeof(double) * (size_t)ns);
+  for (int v = 0; v < nv; ++v) sec_v[v] = INFINITY;
+  for (int s = 0; s < ns; ++s) sec_s[s] = INFINITY;
+  /* second lowest of each row and column: the lowest once one copy of the
+   * best is set aside (an exact tie gives a lead of 0) */
+  for (int v = 0; v < nv && logm; ++v) {
+    int seen = 0;
+    for (int s = 0; s < ns; ++s) {
+      const pair_eval *r = &pe[(size_t)v * ns + s];
+      if (!r->ok) continue;
+      if (r->chi2 == best_v[v] && !seen) { seen = 1; continue; }
+      sec_v[v] = fmin(sec_v[v], r->chi2);
+    }
+  }
+  for (int s = 0; s < ns && logm; ++s) {
+    int seen = 0;
+    for (int v = 0; v < nv; ++v) {
+      const pair_eval *r = &pe[(size_t)v * ns + s];
+      if (!r->ok) continue;
+      if (r->chi2 == best_s[s] && !seen) { seen = 1; continue; }
+      sec_s[s] = fmin(sec_s[s], r->chi2);
+    }
+  }
   int n = 0;
   for (int v = 0; v < nv; ++v)
     for (int s = 0; s < ns; ++s) {
       const pair_eval *r = &pe[(size_t)v * ns + s];
-      if (!r->ok || r->chi2 != best_v[v] || r->chi2 != best_s[s]) continue;
+      const int kept = r->ok && r->chi2 == best_v[v] && r->chi2 == best_s[s];
+      if (!kept) {
+        if (!near) continue;
+        double m = r->m;   /* rejected by a cut: its margin to acceptance */
+        if (r->ok) {       /* survived the cuts, lost the best choice */
+          const double sc = fmax(r->chi2, floor_m);
+          m = fmax(r->chi2 > best_v[v] ? (r->chi2 - best_v[v]) / sc : 0.0,
+                   r->chi2 > best_s[s] ? (r->chi2 - best_s[s]) / sc : 0.0);
+        }
+        if (m < ORC_NEAR && logm) {
+          orc_near *q = (orc_near *)dyn_push(near);
+          memset(q, 0, sizeof(*q));
+          q->event = event; q->kind = 4; q->velo_idx = v; q->it = seeds[s].it; q->margin = m;
+          memcpy(q->id, seeds[s].id, sizeof(q->id));
+        }
+        continue;
+      }
       if (n < cap) {
         orc_long *L = &out[n];
         L->velo_idx = v; L->velo_id = vid[v]; L->seed_idx = s; L->pad = 0;
         L->qop = r->qop; L->chi2 = r->chi2; L->zm = r->zm;
         L->dx = r->dx; L->dy = r->dy; L->dtx = r->dtx; L->dty = r->dty;
+        const double sc = fmax(r->chi2, floor_m);
+        L->margin = fmin(fmin(seeds[s].margin, r->m),
+                         fmin((sec_v[v] - r->chi2) / sc, (sec_s[s] - r->chi2) / sc));
       }
       ++n;
     }
-  free(pe); free(best_v); free(best_s);
+  free(pe); free(best_v); free(best_s); free(sec_v); free(sec_s);
   return n;
 }
 
 /* ------------------------------------------------------- whole event ---- */
 
-typedef struct { dyn seeds, longs; } ev_out;
+typedef struct { dyn seeds, longs, near; } ev_out;
 
 static void run_event(const orc_geom *g, const orc_params *P, const int32_t *off,
                       const float *X, const float *Z, const int32_t *ID, int nv,
                       const float *vx, const float *vy, const float *vz, const float *vtx,
-                      const float *vty, const int32_t *vid, ev_out *o) {
+                      const float *vty, const int32_t *vid, int event, ev_out *o) {
   o->seeds = (dyn){NULL, 0, 0, sizeof(orc_seed)};
   o->longs = (dyn){NULL, 0, 0, sizeof(orc_long)};
+  o->near = (dyn){NULL, 0, 0, sizeof(orc_near)};
   const int n_pos = off[24];
   for (int half = 0; half < 2; ++half) {
     dyn c = {NULL, 0, 0, sizeof(orc_cand)};
     xz_iteration(g, P, off, X, Z, half, 0, &c);
     xz_iteration(g, P, off, X, Z, half, 1, &c);
-    /* the clone vote sees the candidates that passed the fit */
-    int m = 0;
-    orc_cand *cs = (orc_cand *)c.p;
-    for (int i = 0; i < c.n; ++i) if (cs[i].status == 0) cs[m++] = cs[i];
+    /* the clone vote sees the candidates that passed the fit; those the fit
+     * or the x-hit count rejected by a narrow margin are near misses, and
+     * the fit's near misses are also rivals in the vote margins */
+    const orc_cand *all = (const orc_cand *)c.p;
+    orc_cand *rv = (orc_cand *)malloc(sizeof(orc_cand) * (size_t)(c.n > 0 ? c.n : 1));
+    double *xzm = (double *)malloc(sizeof(double) * (size_t)(c.n > 0 ? c.n : 1));
+    int m = 0, nr;
+    for (int i = 0; i < c.n; ++i)
+      if (all[i].status == 0) { rv[m] = all[i]; xzm[m] = all[i].margin; ++m; }
+    nr = m;
+    for (int i = 0; i < c.n; ++i) {
+      if (all[i].status == 0 || !(all[i].margin < ORC_NEAR)) continue;
+      push_near(&o->near, event, 1, -1, &all[i], NULL, ID, all[i].margin);
+      if (all[i].status == 2) { rv[nr] = all[i]; xzm[nr] = all[i].margin; ++nr; }
+    }
+    orc_cand *cs = rv;   /* the voters: rv[0, m) */
     int32_t *keep = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    double *vm = (double *)malloc(sizeof(double) * (size_t)(nr > 0 ? nr : 1));
     orc_clone_vote(cs, m, n_pos, keep);
+    vote_margins(rv, nr, m, n_pos, xzm, vm);
     for (int i = 0; i < m; ++i) {
-      if (!keep[i]) continue;
+      cs[i].margin = fmin(cs[i].margin, vm[i]);
+      if (!keep[i]) {
+        if (cs[i].margin < ORC_NEAR) push_near(&o->near, event, 2, -1, &cs[i], NULL, ID, cs[i].margin);
+        continue;
+      }
       orc_seed sd;
-      if (orc_uv(g, P, off, X, Z, ID, &cs[i], &sd)) *(orc_seed *)dyn_push(&o->seeds) = sd;
+      const int made = P->uv_mode == 1 ? orc_uv(g, P, off, X, Z, ID, &cs[i], &sd)
+                                       : uv_iterative(g, P, off, X, Z, ID, &cs[i], &sd, &o->near, event);
+      if (made) *(orc_seed *)dyn_push(&o->seeds) = sd;
     }
     free(keep);
+    free(vm);
+    free(xzm);
+    free(rv);
     free(c.p);
   }
   const int ns = o->seeds.n;
   if (ns > 0 && nv > 0) {
+    /* a pair count above cap only sizes the second call; near misses are
+     * taken in the call whose results are kept */
     int cap = ns < nv ? ns : nv;
     cap = cap * 4 + 16;
     orc_long *tmp = (orc_long *)malloc(sizeof(orc_long) * (size_t)cap);
-    int n = orc_match(g, P, (orc_seed *)o->seeds.p, ns, nv, vx, vy, vz, vtx, vty, vid, tmp, cap);
+    const int near0 = o->near.n;
+    int n = match_event(g, P, (orc_seed *)o->seeds.p, ns, nv, vx, vy, vz, vtx, vty, vid, tmp, cap,
+                        &o->near, event);
     if (n > cap) {
       free(tmp);
+      o->near.n = near0;
       tmp = (orc_long *)malloc(sizeof(orc_long) * (size_t)n);
-      orc_match(g, P, (orc_seed *)o->seeds.p, ns, nv, vx, vy, vz, vtx, vty, vid, tmp, n);
+      match_event(g, P, (orc_seed *)o->seeds.p, ns, nv, vx, vy, vz, vtx, vty, vid, tmp, n,
+                  &o->near, event);
     }
     for (int i = 0; i < n; ++i) *(orc_long *)dyn_push(&o->longs) = tmp[i];
     free(tmp);
@@ -697,11 +936,13 @@ typedef struct {
   const int32_t *vid;
   ev_out *outs;
   int next;
+  int log_margins;
   pthread_mutex_t mu;
 } job;
 
 static void *worker(void *arg) {
   job *J = (job *)arg;
+  g_nolog = !J->log_margins;
   for (;;) {
     pthread_mutex_lock(&J->mu);
     int e = J->next++;
@@ -713,7 +954,7 @@ static void *worker(void *arg) {
     const int v0 = J->velo_off[e], nv = J->velo_off[e + 1] - v0;
     run_event(J->g, J->P, off, J->hx + base, J->hz + base, J->hid + base, nv,
               J->vx + v0, J->vy + v0, J->vz + v0, J->vtx + v0, J->vty + v0, J->vid + v0,
-              &J->outs[e]);
+              e, &J->outs[e]);
   }
   return NULL;
 }
@@ -721,19 +962,31 @@ static void *worker(void *arg) {
 int orc_run(const orc_geom *g, const orc_params *p, int n_events, const int32_t *zone_off,
             const float *hx, const float *hz, const int32_t *hid, const int32_t *velo_off,
             const float *vx, const float *vy, const float *vz, const float *vtx,
-            const float *vty, const int32_t *vid, int n_threads, orc_result *res) {
+            const float *vty, const int32_t *vid, int n_threads, int log_margins,
+            orc_result *res) {
   memset(res, 0, sizeof(*res));
   if (n_events < 0) return -1;
   job J = {g, p, n_events, zone_off, hx, hz, hid, velo_off, vx, vy, vz, vtx, vty, vid,
-           NULL, 0, PTHREAD_MUTEX_INITIALIZER};
+           NULL, 0, log_margins, PTHREAD_MUTEX_INITIALIZER};
   J.outs = (ev_out *)calloc((size_t)(n_events > 0 ? n_events : 1), sizeof(ev_out));
   if (n_threads < 1) n_threads = 1;
   if (n_threads > 256) n_threads = 256;
   pthread_t th[256];
   for (int t = 0; t < n_threads; ++t) pthread_create(&th[t], NULL, worker, &J);
   for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
-  int64_t ns = 0, nl = 0;
-  for (int e = 0; e < n_events; ++e) { ns += J.outs[e].seeds.n; nl += J.outs[e].longs.n; }
+  int64_t ns = 0, nl = 0, nn = 0;
+  for (int e = 0; e < n_events; ++e) {
+    ns += J.outs[e].seeds.n; nl += J.outs[e].longs.n; nn += J.outs[e].near.n;
+  }
+  res->n_near = nn;
+  res->near = (orc_near *)malloc(sizeof(orc_near) * (size_t)(nn > 0 ? nn : 1));
+  int64_t in = 0;
+  for (int e = 0; e < n_events; ++e) {
+    if (J.outs[e].near.n)
+      memcpy(res->near + in, J.outs[e].near.p, sizeof(orc_near) * (size_t)J.outs[e].near.n);
+    in += J.outs[e].near.n;
+    free(J.outs[e].near.p);
+  }
   res->n_seeds = ns;
   res->n_longs = nl;
   res->seed_off = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_events + 1));
@@ -760,6 +1013,6 @@ int orc_run(const orc_geom *g, const orc_params *p, int n_events, const int32_t 
 }
 
 void orc_free(orc_result *res) {
-  free(res->seed_off); free(res->seeds); free(res->long_off); free(res->longs);
+  free(res->seed_off); free(res->seeds); free(res->long_off); free(res->longs); free(res->near);
   memset(res, 0, sizeof(*res));
 }

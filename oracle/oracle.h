@@ -62,12 +62,23 @@ typedef struct {
   int32_t pad2;
 } orc_params;
 
+/* Margins.  Every decision that shapes an output is logged with its
+ * relative distance from going the other way: |q - cut| / cut for a window
+ * or a cut, (second - best) / scale for a closest-hit choice (scale: the
+ * window) or a best-candidate choice (scale: the larger of the best value and
+ * 1e-3 of the cut), and the relative score gap to the nearest other score on
+ * a shared hit for the clone vote.  A kept track carries the smallest margin
+ * of its decisions; a rejection that came within ORC_NEAR of going the other
+ * way is listed as a near miss (orc_near). */
+#define ORC_NEAR 1e-3
+
 /* One three-hit combination and what became of it. */
 typedef struct {
   int32_t half, it, status; /* status 0: passed the fit cut; 1: < min_x_hits; 2: chi2 cut */
   int32_t n;                /* number of x hits */
   int32_t pos[ORC_NL];      /* event-relative hit positions by layer, -1 if none */
   double a, b, c, chi2, score;
+  double margin;            /* smallest margin of its x-z decisions (and, once voted, the vote) */
 } orc_cand;
 
 typedef struct {
@@ -75,12 +86,27 @@ typedef struct {
   int32_t nx, nuv, half, it;
   int32_t pos[ORC_NL];
   int32_t id[ORC_NL];
+  double margin;            /* smallest margin of every decision that made this seed */
 } orc_seed;
 
 typedef struct {
   int32_t velo_idx, velo_id, seed_idx, pad;
   double qop, chi2, zm, dx, dy, dtx, dty;
+  double margin;            /* smallest margin of its seed's and its matching decisions */
 } orc_long;
+
+/* A near miss: a track or pair that a decision within ORC_NEAR of its
+ * threshold rejected.  kind: 1 an x-z candidate (fit or x-hit count), 2 an
+ * x-z track killed by the clone vote, 3 a stereo-hit combination not chosen
+ * or cut, 4 a VELO-seed pair rejected or not the best.  id holds the hit ids
+ * by layer (-1 where none; only x layers for kinds 1 and 2); velo_idx is the
+ * VELO state of a kind-4 pair (-1 otherwise); it the x-z iteration that
+ * found the track. */
+typedef struct {
+  int32_t event, kind, velo_idx, it;   /* it: x-z iteration of the track */
+  int32_t id[ORC_NL];
+  double margin;
+} orc_near;
 
 typedef struct {
   int64_t n_seeds, n_longs;
@@ -88,6 +114,8 @@ typedef struct {
   orc_seed *seeds;
   int32_t *long_off;   /* [n_events + 1] */
   orc_long *longs;
+  int64_t n_near;
+  orc_near *near;      /* near misses of every event, by event */
 } orc_result;
 
 void orc_default_geom(orc_geom *g);
@@ -110,11 +138,16 @@ int orc_match(const orc_geom *g, const orc_params *p, const orc_seed *seeds, int
               const float *vtx, const float *vty, const int32_t *vid,
               orc_long *out, int cap);
 
-/* Whole batch; returns 0 on success.  Results are malloc'd; free with orc_free. */
+/* Whole batch; returns 0 on success.  Results are malloc'd; free with
+ * orc_free.  log_margins = 0 skips the margin bookkeeping that costs time of
+ * its own (closest-hit rescans, vote margins, near misses): the tracks are
+ * the same, their margins are then only partly filled and no near misses are
+ * listed (for timing the method alone). */
 int orc_run(const orc_geom *g, const orc_params *p, int n_events, const int32_t *zone_off,
             const float *hx, const float *hz, const int32_t *hid, const int32_t *velo_off,
             const float *vx, const float *vy, const float *vz, const float *vtx,
-            const float *vty, const int32_t *vid, int n_threads, orc_result *res);
+            const float *vty, const int32_t *vid, int n_threads, int log_margins,
+            orc_result *res);
 void orc_free(orc_result *res);
 
 #ifdef __cplusplus

@@ -60,22 +60,31 @@ class Params(C.Structure):
         return out
 
 
+# margins: the relative distance of a track's closest decision from going
+# the other way (oracle.h, ORC_NEAR); near misses: rejections within NEAR
+NEAR = 1e-3
+NEAR_XZ, NEAR_VOTE, NEAR_UV, NEAR_MATCH = 1, 2, 3, 4
+
 CAND_DTYPE = np.dtype([("half", "i4"), ("it", "i4"), ("status", "i4"), ("n", "i4"),
                        ("pos", "i4", NL), ("a", "f8"), ("b", "f8"), ("c", "f8"),
-                       ("chi2", "f8"), ("score", "f8")], align=True)
+                       ("chi2", "f8"), ("score", "f8"), ("margin", "f8")], align=True)
 SEED_DTYPE = np.dtype([("a", "f8"), ("b", "f8"), ("c", "f8"), ("y0", "f8"), ("ty", "f8"),
                        ("chi2x", "f8"), ("chi2y", "f8"), ("score", "f8"),
                        ("nx", "i4"), ("nuv", "i4"), ("half", "i4"), ("it", "i4"),
-                       ("pos", "i4", NL), ("id", "i4", NL)], align=True)
+                       ("pos", "i4", NL), ("id", "i4", NL), ("margin", "f8")], align=True)
 LONG_DTYPE = np.dtype([("velo_idx", "i4"), ("velo_id", "i4"), ("seed_idx", "i4"),
                        ("pad", "i4"), ("qop", "f8"), ("chi2", "f8"), ("zm", "f8"),
-                       ("dx", "f8"), ("dy", "f8"), ("dtx", "f8"), ("dty", "f8")], align=True)
+                       ("dx", "f8"), ("dy", "f8"), ("dtx", "f8"), ("dty", "f8"),
+                       ("margin", "f8")], align=True)
+NEAR_DTYPE = np.dtype([("event", "i4"), ("kind", "i4"), ("velo_idx", "i4"), ("it", "i4"),
+                       ("id", "i4", NL), ("margin", "f8")], align=True)
 
 
 class _Result(C.Structure):
     _fields_ = [("n_seeds", C.c_int64), ("n_longs", C.c_int64),
                 ("seed_off", C.POINTER(C.c_int32)), ("seeds", C.c_void_p),
-                ("long_off", C.POINTER(C.c_int32)), ("longs", C.c_void_p)]
+                ("long_off", C.POINTER(C.c_int32)), ("longs", C.c_void_p),
+                ("n_near", C.c_int64), ("near", C.c_void_p)]
 
 
 _lib = None
@@ -100,7 +109,7 @@ def lib():
                                 vp, vp, vp, vp, vp, vp, vp, C.c_int]
         L.orc_match.restype = C.c_int
         L.orc_run.argtypes = [C.POINTER(Geom), C.POINTER(Params), C.c_int] + [vp] * 11 + \
-                             [C.c_int, C.POINTER(_Result)]
+                             [C.c_int, C.c_int, C.POINTER(_Result)]
         L.orc_run.restype = C.c_int
         L.orc_free.argtypes = [C.POINTER(_Result)]
         L.orc_window_constants.argtypes = [C.POINTER(Geom), C.POINTER(Params), C.c_int, vp]
@@ -191,8 +200,12 @@ def match(seeds: np.ndarray, velo: dict, params: Params | None = None,
 
 
 class Result:
-    def __init__(self, seed_off, seeds, long_off, longs):
+    def __init__(self, seed_off, seeds, long_off, longs, near=None):
         self.seed_off, self.seeds, self.long_off, self.longs = seed_off, seeds, long_off, longs
+        self.near = near if near is not None else np.zeros(0, NEAR_DTYPE)
+
+    def event_near(self, e):
+        return self.near[self.near["event"] == e]
 
     def event_seeds(self, e):
         return self.seeds[self.seed_off[e]:self.seed_off[e + 1]]
@@ -202,8 +215,10 @@ class Result:
 
 
 def run(batch, params: Params | None = None, geom: Geom | None = None,
-        threads: int = 1) -> Result:
-    """Seeding + Matching of every event of `batch` (an events.Batch)."""
+        threads: int = 1, margins: bool = True) -> Result:
+    """Seeding + Matching of every event of `batch` (an events.Batch).
+    margins=False skips the margin log's own passes (same tracks; used to
+    time the method alone)."""
     params = params or default_params()
     geom = geom or default_geom()
     arrs = [_c(batch.zone_off, np.int32), _c(batch.hit_x, np.float32),
@@ -217,7 +232,7 @@ def run(batch, params: Params | None = None, geom: Geom | None = None,
     rc = lib().orc_run(C.byref(geom), C.byref(params), n_ev, _ptr(arrs[0]), _ptr(arrs[1]),
                        _ptr(arrs[2]), _ptr(arrs[3]), _ptr(arrs[4]), _ptr(arrs[5]),
                        _ptr(arrs[6]), _ptr(arrs[7]), _ptr(arrs[8]), _ptr(arrs[9]),
-                       _ptr(arrs[10]), int(threads), C.byref(res))
+                       _ptr(arrs[10]), int(threads), int(bool(margins)), C.byref(res))
     if rc != 0:
         raise RuntimeError(f"orc_run failed: {rc}")
     try:
@@ -228,6 +243,9 @@ def run(batch, params: Params | None = None, geom: Geom | None = None,
                               SEED_DTYPE).copy() if ns else np.zeros(0, SEED_DTYPE)
         longs = np.frombuffer((C.c_char * (nl * LONG_DTYPE.itemsize)).from_address(res.longs),
                               LONG_DTYPE).copy() if nl else np.zeros(0, LONG_DTYPE)
+        nn = res.n_near
+        near = np.frombuffer((C.c_char * (nn * NEAR_DTYPE.itemsize)).from_address(res.near),
+                             NEAR_DTYPE).copy() if nn else np.zeros(0, NEAR_DTYPE)
     finally:
         lib().orc_free(C.byref(res))
-    return Result(seed_off, seeds, long_off, longs)
+    return Result(seed_off, seeds, long_off, longs, near)

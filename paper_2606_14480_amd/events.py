@@ -180,8 +180,12 @@ def concat(events: list) -> Batch:
     if events and all(b.truth is not None for b in events):
         keys = [k for k in events[0].truth if k != "track_off"]
         truth = {k: np.concatenate([b.truth[k] for b in events]) for k in keys}
-        counts = [len(b.truth["p"]) for b in events]
-        truth["track_off"] = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        # per-event track offsets of every part, rebased (a part may hold several events)
+        offs, tbase = [np.zeros(1, np.int64)], 0
+        for b in events:
+            offs.append(np.asarray(b.truth["track_off"][1:], np.int64) + tbase)
+            tbase += len(b.truth["p"])
+        truth["track_off"] = np.concatenate(offs)
     return Batch(zone_off=np.concatenate(zo).astype(np.int32),
                  hit_x=cat("hit_x", np.float32), hit_z=cat("hit_z", np.float32),
                  hit_id=cat("hit_id", np.int32),
@@ -349,6 +353,48 @@ def generate_event(cfg: GenConfig, e: int, pol: float = POLARITY) -> Batch:
 
 def generate(cfg: GenConfig, pol: float = POLARITY) -> Batch:
     return concat([generate_event(cfg, cfg.first_event + i, pol) for i in range(cfg.n_events)])
+
+
+def _generate_range(cfg: GenConfig, first: int, n: int, pol: float) -> Batch:
+    return generate(dataclasses.replace(cfg, n_events=n, first_event=first), pol)
+
+
+def generate_parallel(cfg: GenConfig, workers: int = 16, pol: float = POLARITY) -> Batch:
+    """generate() spread over worker processes.  Every event is drawn from its
+    own seed, so the batch is identical to generate()'s.  The workers are
+    started fresh (spawn), never forked from a process that may hold GPU
+    state."""
+    n = cfg.n_events
+    workers = max(1, min(workers, n // 64))
+    if workers <= 1:
+        return generate(cfg, pol)
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    k = 4 * workers
+    bounds = [n * i // k for i in range(k + 1)]
+    jobs = [(cfg, cfg.first_event + bounds[i], bounds[i + 1] - bounds[i], pol)
+            for i in range(k) if bounds[i + 1] > bounds[i]]
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        parts = list(ex.map(_generate_range, *zip(*jobs)))
+    return concat(parts)
+
+
+def tile(b: Batch, times: int) -> Batch:
+    """The events of b repeated `times` times, one after the other (a larger
+    batch of the same events, for batch-size sweeps beyond what is worth
+    generating).  Truth is dropped."""
+    nh, nv, ne = b.n_hits, b.n_velo, b.n_events
+    zo = np.concatenate([np.zeros(1, np.int64)] +
+                        [b.zone_off[1:].astype(np.int64) + k * nh for k in range(times)])
+    vo = np.concatenate([np.zeros(1, np.int64)] +
+                        [b.velo_off[1:].astype(np.int64) + k * nv for k in range(times)])
+    if zo[-1] >= 2 ** 31 or vo[-1] >= 2 ** 31:
+        raise ValueError("tiled batch exceeds the int32 offsets of the batch layout")
+    rep = lambda a: np.tile(a, times)
+    return Batch(zone_off=zo.astype(np.int32), hit_x=rep(b.hit_x), hit_z=rep(b.hit_z),
+                 hit_id=rep(b.hit_id), velo_off=vo.astype(np.int32), velo_x=rep(b.velo_x),
+                 velo_y=rep(b.velo_y), velo_z=rep(b.velo_z), velo_tx=rep(b.velo_tx),
+                 velo_ty=rep(b.velo_ty), velo_id=rep(b.velo_id), truth=None)
 
 
 def empty_event() -> Batch:
