@@ -59,72 +59,185 @@ def match_kernel_bytes(b, n_seeds: int, n_longs: int) -> int:
     return 32 * b.n_events + 24 * b.n_velo + 20 * n_seeds + 40 * n_longs
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(batch, seconds: float):
     from oracle import oracle as O
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    O.run(batch.subset(range(min(10, batch.n_events))), threads=cores)   # warm
+    cores = min(cores, 16)   # the host share of one GPU
+    O.run(batch.subset(range(min(10, batch.n_events))), threads=cores, margins=False)   # warm
     t0 = time.perf_counter()
     reps = 0
     while True:
-        O.run(batch, threads=cores)
+        O.run(batch, threads=cores, margins=False)
         reps += 1
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
     n1 = min(200, batch.n_events)
     t1 = time.perf_counter()
-    O.run(batch.subset(range(n1)), threads=1)
+    O.run(batch.subset(range(n1)), threads=1, margins=False)
     d1 = time.perf_counter() - t1
     return {"value": round(reps * batch.n_events / dt, 1), "unit": "events/s", "cores": cores,
-            "kind": "oracle",
+            "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"the benchmark batch ({batch.n_events} events) run {reps}x on {cores} "
-                      f"threads ({dt:.1f} s wall); single thread on {n1} events: "
-                      f"{n1 / d1:.1f} events/s"}
+                      f"threads ({dt:.1f} s wall), the oracle's margin log off; single "
+                      f"thread on {n1} events: {n1 / d1:.1f} events/s"}
 
 
-def serve_stream(ctx, sm, host, capacity, n_req, load):
-    """Requests of 1..N events (N = the batch size) drawn from the benchmark
-    batch, Poisson arrivals at `load` x the batched capacity in events/s,
-    continuous batching over the library's serving slots; then the same
-    stream one request at a time through the plain form."""
+def copy_bandwidth(mib: int = 256):
+    """Host<->device copy rate of pinned memory (GB/s), timed with events on
+    one stream: the link the serving leg moves requests and results over."""
+    import torch
+    n = mib << 20
+    h = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    d = torch.empty(n, dtype=torch.uint8, device="cuda")
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    for _ in range(2):
+        e0.record(); d.copy_(h, non_blocking=True); e1.record(); h.copy_(d, non_blocking=True)
+        e2.record(); torch.cuda.synchronize()
+    return {"h2d_GBps": round(n / (e0.elapsed_time(e1) * 1e-3) / 1e9, 2),
+            "d2h_GBps": round(n / (e1.elapsed_time(e2) * 1e-3) / 1e9, 2),
+            "bytes": n}
+
+
+def serve_stream(ctx, sm, pool_batch, n_req, loads, n_plain):
+    """Serving leg: requests of 1..N consecutive events of a pinned pool of
+    N min-bias events, continuous batching over the library's serving slots.
+    The served capacity (every request queued at t = 0, copies included) is
+    measured first; then Poisson arrivals at each offered load (a fraction of
+    that capacity), and the first requests of the 0.8 stream one at a time
+    through the plain form."""
     import numpy as np
+    import torch
     from paper_2606_14480_amd import serving
+    pool = serving.EventPool(pool_batch)
+    N = pool.n_events
     rng = np.random.default_rng(11)
-    sizes = rng.integers(1, host.n_events + 1, n_req)
-    starts = [int(rng.integers(0, host.n_events - k + 1)) for k in sizes]
+    sizes = rng.integers(1, N + 1, n_req)
+    firsts = [int(rng.integers(0, N - int(k) + 1)) for k in sizes]
     mean_ev = float(np.mean(sizes))
-    rate = load * capacity / mean_ev
-    arr = serving.poisson_arrivals(rate, n_req, seed=12)
-    reqs = []
-    for i, (s, k) in enumerate(zip(starts, sizes)):
-        sub = host.subset(range(s, s + int(k)))
-        reqs.append(serving.Request(i, sub, float(arr[i]), serving.pin(sub)))
-    me = max(r.batch.n_events for r in reqs)
-    mh = max(r.batch.n_hits for r in reqs)
-    mv = max(r.batch.n_velo for r in reqs)
-    srv = serving.Server(ctx, SERVE_SLOTS, me, mh, mv)
-    # warm the slots, scratch and captured graphs with the largest request first
-    big = max(reqs, key=lambda r: r.batch.n_hits)
-    srv.serve([dataclasses.replace(big, arrival=0.0)] + [dataclasses.replace(r, arrival=0.0) for r in reqs[:3]])
+
+    def stream(arr):
+        return [serving.Request(i, None, float(arr[i]), pool=pool, first=firsts[i],
+                                count=int(sizes[i])) for i in range(n_req)]
+
+    free, _ = torch.cuda.mem_get_info()
+    srv = serving.Server(ctx, SERVE_SLOTS, N, pool_batch.n_hits, pool_batch.n_velo,
+                         mem_budget=int(free * 0.8))
+    srv.serve(stream(np.zeros(n_req))[:2 * SERVE_SLOTS], keep=False)   # warm slots and graphs
     t0 = time.perf_counter()
-    res = srv.serve(reqs, keep=False)
+    res = srv.serve(stream(np.zeros(n_req)), keep=False)
     wall = time.perf_counter() - t0
-    s = serving.summarize(res, wall)
-    out = {"requests": n_req, "events_per_request": "uniform 1-%d" % host.n_events,
-           "offered_events_per_s": round(rate * mean_ev, 1),
-           "events_per_s": round(s["events_per_s"], 1),
-           "latency_ms_p50": round(s["latency_ms_p50"], 3),
-           "latency_ms_p99": round(s["latency_ms_p99"], 3),
-           "what": "arrival to results in pinned host memory, incl. H2D of the request and D2H of results"}
-    n_plain = min(n_req, 12)
-    t0 = time.perf_counter()
-    pres = serving.serve_plain(ctx, reqs[:n_plain], me, mh, mv)
-    wall_p = time.perf_counter() - t0
-    p = serving.summarize(pres, wall_p)
-    out["plain_stream"] = {"requests": n_plain, "events_per_s": round(p["events_per_s"], 1),
-                           "latency_ms_p50": round(p["latency_ms_p50"], 3),
-                           "latency_ms_p99": round(p["latency_ms_p99"], 3)}
+    cap = sum(r.n_events for r in res) / wall
+    out = {"requests_per_load": n_req, "events_per_request": "uniform 1-%d" % N,
+           "pool": "%d min-bias events packed once in pinned memory; a request is a run of "
+                   "consecutive pool events" % N,
+           "capacity_events_per_s": round(cap, 1),
+           "capacity_what": "every request queued at t=0; H2D of each request and D2H of its "
+                            "results included",
+           "what": "latency = arrival to results in pinned host memory", "loads": {}}
+    for k, load in enumerate(loads):
+        rate = load * cap / mean_ev
+        arr = serving.poisson_arrivals(rate, n_req, seed=12 + k)
+        t0 = time.perf_counter()
+        res = srv.serve(stream(arr), keep=False)
+        wall = time.perf_counter() - t0
+        st = serving.summarize(res, wall)
+        out["loads"][str(load)] = {"offered_events_per_s": round(rate * mean_ev, 1),
+                                   "events_per_s": round(st["events_per_s"], 1),
+                                   "latency_ms_p50": round(st["latency_ms_p50"], 3),
+                                   "latency_ms_p99": round(st["latency_ms_p99"], 3)}
+        log(f"[bench] served at {load}: {out['loads'][str(load)]}")
+    if n_plain > 0:
+        rate = 0.8 * cap / mean_ev
+        arr = serving.poisson_arrivals(rate, n_req, seed=13)
+        reqs = stream(arr)[:n_plain]
+        t0 = time.perf_counter()
+        pres = serving.serve_plain(ctx, reqs, N, pool_batch.n_hits, pool_batch.n_velo)
+        p = serving.summarize(pres, time.perf_counter() - t0)
+        out["plain_stream"] = {"requests": n_plain, "what": "the first requests of the 0.8 "
+                               "stream, one kernel sequence per event",
+                               "events_per_s": round(p["events_per_s"], 1),
+                               "latency_ms_p50": round(p["latency_ms_p50"], 3),
+                               "latency_ms_p99": round(p["latency_ms_p99"], 3)}
+    out["copy_bandwidth"] = copy_bandwidth()
     return out
+
+
+def run_sized(ctx, sm, db, host, stream):
+    """One run with outputs sized from the first guess, or from the sizes the
+    library reports if they do not fit."""
+    out = sm.DeviceOut(host.n_events, host.n_hits // 8 + 1024, host.n_velo + 1024)
+    if ctx.run(db, out, stream, check=False) == sm.ERR_CAPACITY:
+        out = sm.DeviceOut(host.n_events, out.n_seeds + 1024, out.n_longs + 1024)
+        ctx.run(db, out, stream)
+    return out
+
+
+def oracle_parity(host, gpu, n_events, over):
+    """Seeds and long tracks of the first n_events events against the oracle."""
+    from oracle import oracle as O
+    import parity as PT
+    npar = min(host.n_events, n_events)
+    sub = host if npar == host.n_events else host.subset(range(npar))
+    g_sub = (gpu[0][:npar + 1], gpu[1][:gpu[0][npar]], gpu[2][:npar + 1], gpu[3][:gpu[2][npar]])
+    th = min(os.cpu_count() or 1, 16)
+    o = O.run(sub, O.default_params(**over), threads=th)
+    st = PT.compare(o, g_sub, npar)
+    if st["mismatches"]:
+        st = PT.compare(o, g_sub, npar, band=(
+            O.run(sub, PT.eps_params(O, 1e-4, **over), threads=th),
+            O.run(sub, PT.eps_params(O, -1e-4, **over), threads=th)))
+    return {"events_checked": npar, "seed_jaccard": round(st["seed_jaccard"], 6),
+            "long_jaccard": round(st["long_jaccard"], 6),
+            "mismatches": st["mismatches"], "unexplained": len(st["unexplained"]),
+            "param_failures": len(st["param_fail"])}
+
+
+def extra_leg(ctx, sm, name, host, steps, warmup, parity_events, over):
+    """Batched events/s of one more workload at its stated size (same
+    context, same captured-graph form), with oracle parity on its first
+    events."""
+    import numpy as np
+    import torch
+    stream = torch.cuda.current_stream()
+    db = sm.DeviceBatch(host)
+    out = run_sized(ctx, sm, db, host, stream)
+    gpu = out.to_host()
+    par = oracle_parity(host, gpu, parity_events, over) if parity_events > 0 else None
+    for _ in range(warmup):
+        ctx.run(db, out, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.run(db, out, stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    kern = ctx.profile(db, out, stream)
+    ev_hits = host.event_hits()
+    res = {"workload": WORKLOADS[name].format(n=host.n_events), "events": host.n_events,
+           "hits": host.n_hits, "hits_per_event": {"min": int(ev_hits.min()),
+                                                   "mean": round(float(ev_hits.mean()), 1),
+                                                   "max": int(ev_hits.max())},
+           "events_per_s": round(host.n_events / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
+           "steps": steps, "seeds": out.n_seeds, "long_tracks": out.n_longs,
+           "launch": dict(ctx.launch_shape(host), source=ctx.shape_source),
+           "kernel_ms": {k: round(v, 4) for k, v in kern.items()}, "parity": par}
+    log(f"[bench] {name}: {res['events_per_s']:.0f} events/s, {res['ms_per_batch']} ms/batch, "
+        f"parity {par}")
+    del db, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -143,10 +256,20 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=2.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=60,
-                    help="requests in the served-stream measurement (0: skip)")
-    ap.add_argument("--serve-load", type=float, default=0.8,
-                    help="offered load as a fraction of the measured batched capacity")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests per offered load in the serving leg (0: skip)")
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95",
+                    help="offered loads, as fractions of the measured served capacity")
+    ap.add_argument("--serve-pool", type=int, default=4000,
+                    help="min-bias events in the serving pool (requests are 1..this many)")
+    ap.add_argument("--serve-plain", type=int, default=20,
+                    help="requests of the 0.8 stream also run through the plain form")
+    ap.add_argument("--legs", default="uneven,stress",
+                    help="further workloads at their stated sizes, timed beside the headline "
+                         "(comma list of uneven, stress; empty: none)")
+    ap.add_argument("--leg-steps", type=int, default=5)
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="processes generating the synthetic events")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain copy of this many MiB (rocprof counter calibration)")
     args = ap.parse_args()
@@ -157,18 +280,27 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     from paper_2606_14480_amd import events as ev
-    from paper_2606_14480_amd import sm
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    # every synthetic input first, in worker processes started before this
+    # process touches the GPU
     wl = {"minbias": 2, "uneven": 3, "stress": 4}[args.workload]
-    cfg = ev.config(wl, n_events=args.events or None)
+    gen = lambda cfg: ev.generate_parallel(cfg, args.gen_workers)
     t0 = time.perf_counter()
-    host = ev.generate(cfg)
+    host = gen(ev.config(wl, n_events=args.events or None))
+    legs = [x for x in args.legs.split(",") if x and x != args.workload]
+    leg_hosts = {x: gen(ev.config({"uneven": 3, "stress": 4}[x])) for x in legs}
+    pool = gen(ev.config(5, n_events=args.serve_pool)) \
+        if args.serve_requests > 0 and args.workload == "minbias" else None
     log(f"[bench] generated {host.n_events} events, {host.n_hits} hits, {host.n_velo} VELO "
-        f"states in {time.perf_counter() - t0:.1f} s")
+        f"states (+ {', '.join(f'{k} {v.n_events}' for k, v in leg_hosts.items()) or 'no legs'}"
+        f"{', serving pool %d' % pool.n_events if pool is not None else ''}) in "
+        f"{time.perf_counter() - t0:.1f} s")
+
+    import torch
+    from paper_2606_14480_amd import sm
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
     over = {"p_min": args.p_min} if args.p_min > 0 else {}
     ctx = sm.Context(params=sm.default_params(**over), n_slots=SERVE_SLOTS)
     db = sm.DeviceBatch(host)
@@ -180,21 +312,7 @@ def main():
     n_seeds, n_longs = out.n_seeds, out.n_longs
     parity = None
     if not args.no_parity:
-        from oracle import oracle as O
-        import parity as PT
-        npar = min(host.n_events, args.parity_events)
-        sub = host if npar == host.n_events else host.subset(range(npar))
-        g_sub = (gpu[0][:npar + 1], gpu[1][:gpu[0][npar]], gpu[2][:npar + 1], gpu[3][:gpu[2][npar]])
-        o = O.run(sub, O.default_params(**over), threads=os.cpu_count())
-        st = PT.compare(o, g_sub, npar)
-        if st["mismatches"]:
-            st = PT.compare(o, g_sub, npar, band=(
-                O.run(sub, PT.eps_params(O, 1e-4, **over), threads=os.cpu_count()),
-                O.run(sub, PT.eps_params(O, -1e-4, **over), threads=os.cpu_count())))
-        parity = {"events_checked": npar, "seed_jaccard": round(st["seed_jaccard"], 6),
-                  "long_jaccard": round(st["long_jaccard"], 6),
-                  "mismatches": st["mismatches"], "unexplained": len(st["unexplained"]),
-                  "param_failures": len(st["param_fail"])}
+        parity = oracle_parity(host, gpu, args.parity_events, over)
         log(f"[bench] parity vs oracle: {parity}")
 
     # ---- batched form: the timed region
@@ -230,10 +348,22 @@ def main():
         plain = args.plain_steps * host.n_events / (time.perf_counter() - tp)
         log(f"[bench] plain: {plain:.0f} events/s")
 
+    # further workloads at their stated sizes (uneven: all events against the
+    # oracle; stress: events 0-499)
+    leg_res = {}
+    for name, lh in leg_hosts.items():
+        leg_res[name] = extra_leg(ctx, sm, name, lh, args.leg_steps, 1,
+                                  0 if args.no_parity else (lh.n_events if name == "uneven" else 500),
+                                  over)
+        del lh
+    leg_hosts.clear()
+
     serve = None
-    if args.serve_requests > 0 and args.workload == "minbias":
-        serve = serve_stream(ctx, sm, host, value, args.serve_requests, args.serve_load)
-        log(f"[bench] served: {serve}")
+    if pool is not None:
+        loads = [float(x) for x in args.serve_loads.split(",") if x]
+        serve = serve_stream(ctx, sm, pool, args.serve_requests, loads, args.serve_plain)
+        log(f"[bench] served: capacity {serve['capacity_events_per_s']:.0f} events/s, "
+            f"copies {serve['copy_bandwidth']}")
     if args.calib_copy_mb > 0:
         n = args.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -274,7 +404,9 @@ def main():
                        "p99": round(float(np.percentile(lat_ms, 99)), 4),
                        "what": "per-batch latency of the batched form, call to results"},
         "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
+        "launch": dict(ctx.launch_shape(host), source=ctx.shape_source),
         "served": serve,
+        "workloads": leg_res,
         "gpu_events_per_s": round(host.n_events / (kern["total"] * 1e-3), 1),
         "parity": parity,
         "roofline": {"bound": "hbm",

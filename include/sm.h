@@ -258,6 +258,35 @@ sm_status sm_profile(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stre
 #define SM_NOALLOC_SCRATCH_BYTES (128ull << 20) /* upper bound; the array takes less */
 sm_status sm_run_noalloc(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream);
 
+/* A launch shape of the batched form for one class of batches: the
+ * persistent grid of the main seeding form and the hits per workgroup that
+ * are staged in LDS (larger items read their hits from global memory).  The
+ * paper sizes its blocks from measured occupancy (Sec. 5.3); here an
+ * autotuner measures the shapes on the device and hands the best one per
+ * batch class to sm_set_shapes. */
+typedef struct {
+  int32_t max_mean_item_hits; /* the class: batches whose mean (event, half) hit count */
+  int32_t max_events;         /*   is at most this, with at most this many events */
+  int32_t seed_wgs;           /* workgroups of the main seeding form, >= 2 */
+  int32_t lds_hits;           /* 256..6144, a multiple of 256 */
+} sm_shape;
+
+/* Replaces the context's table of launch shapes (copied; n = 0 clears it).
+ * Each batched call (sm_run, sm_submit, sm_profile) takes the first entry
+ * whose class holds its batch, else the built-in choice (sm_config's
+ * seed_wgs and lds_hits, else four workgroups per CU and 1.5x the mean item
+ * size).  Per-workgroup scratch for the largest grid of the table is
+ * allocated here: SM_ERR_OOM if it does not fit, SM_ERR_BUSY while a serving
+ * slot is in use, SM_ERR_INVALID for an entry out of range.  Outputs do not
+ * depend on the shape. */
+sm_status sm_set_shapes(sm_ctx *ctx, const sm_shape *shapes, int32_t n);
+
+/* The launch shape a batched call would use for this batch (host-side: reads
+ * only batch->n_events and batch->n_hits).  max_mean_item_hits and
+ * max_events are set to the class bounds of the table entry taken, or to 0
+ * for the built-in choice. */
+sm_status sm_launch_shape(const sm_ctx *ctx, const sm_batch *batch, sm_shape *shape);
+
 /* Device bytes a batch with these totals needs in a serving slot (used for
  * admission by free memory). */
 int64_t sm_batch_bytes(const sm_ctx *ctx, int32_t n_events, int64_t n_hits, int64_t n_velo);

@@ -88,6 +88,7 @@ struct Desc {
   int32_t *long_off;
   long long seed_cap, long_cap;
   int n_events, n_items;
+  int grid, pad;   // workgroups of this batch's main seeding form (0: the context's)
 };
 
 // Parameters in the precision each kernel uses.
@@ -218,6 +219,7 @@ int smk_launch_seed_big(const smk::Desc *d, const smk::KCtx *k, int grid, int ld
                         hipStream_t st);
 int smk_launch_match(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 int smk_seed_big_lds_limit(int bytes);
+int smk_seed_lds_limit(int bytes);   // dynamic LDS allowed to the main seeding forms
 int smk_seed_big_static_lds();   // static LDS of the big form (its dynamic LDS comes on top)
 int smk_launch_copy(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 int smk_launch_validate(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);

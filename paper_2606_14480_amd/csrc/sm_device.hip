@@ -1643,7 +1643,8 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
     }
     float l_lo = __shfl_up(pre, 1, 64);
     if (b == 0) l_lo = 0.0f;
-    const float r = P.big_speedup, sb = (float)max(P.big_slots, 1), sm = (float)max(P.main_slots, 1);
+    const int grid = D->grid > 0 ? D->grid : P.main_slots;
+    const float r = P.big_speedup, sb = (float)max(P.big_slots, 1), sm = (float)max(grid, 1);
     const float t_none = fmaxf(lall, wtot / sm);
     float t = __builtin_inff();
     if (v && b >= kBigBucket && P.uv_mode == 0 && P.big_slots > 0 && wsuf > 0.0f)
@@ -1675,7 +1676,7 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
     // matching: in k_match after all seeding, unless big items are in the
     // batch or the main form takes more than four rounds of items; then
     // inside the seeding kernel, where it overlaps the seeding tail
-    const bool many = n > 4 * max(P.main_slots, 1);
+    const bool many = n > 4 * max(D->grid > 0 ? D->grid : P.main_slots, 1);
     S.cnt->fuse = P.match_mode < 0 ? 1u : P.match_mode > 0 ? 0u : ((best < 32 || many) ? 1u : 0u);
   }
   __syncthreads();
@@ -2104,6 +2105,15 @@ int smk_seed_big_static_lds() {
     return 1024;   // a margin above what the kernel declares
   }
   return (int)a.sharedSizeBytes;
+}
+int smk_seed_lds_limit(int bytes) {
+  int e = (int)hipFuncSetAttribute((const void *)k_seed<0, kSeedWG, false>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<0, kSeedWG, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<1, kSeedWG, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return e;
 }
 int smk_seed_big_lds_limit(int bytes) {
   return (int)hipFuncSetAttribute((const void *)k_seed<0, kBigWG>,

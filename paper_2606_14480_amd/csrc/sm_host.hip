@@ -47,12 +47,13 @@ struct Slot {
   // arguments are the slot's fixed descriptor and context pointers, so a
   // graph stays valid when scratch is reallocated
   struct Captured {
-    int lds_hits;
+    int lds_hits, grid;
     hipGraph_t graph;
     hipGraphExec_t exec;
   };
   std::vector<Captured> graphs;
   int lds_hits = 2048;  // LDS hit capacity of the seeding workgroup for this batch
+  int grid = 0;         // workgroups of the main seeding form for this batch
   hipEvent_t done = nullptr;
   // serving state
   bool busy = false;
@@ -71,7 +72,10 @@ struct sm_ctx {
   sm_params p{};
   sm_config cfg{};
   DevParams dp{};
-  int seed_wgs = 0, match_wgs = 0;
+  int seed_wgs = 0;   // workgroups with per-workgroup scratch: the largest grid in use
+  int base_wgs = 0;   // grid of the built-in launch shape
+  std::vector<sm_shape> shapes;   // launch shapes by batch class (sm_set_shapes)
+  size_t lds_limit = 65536;       // dynamic LDS the main seeding forms may take
   int big_wgs = 0, lds_big = 0;  // big-item form: workgroups (one per CU) and LDS hits
   std::vector<Slot> slots;  // slots[0]: blocking calls; 1..: serving
   int64_t next_ticket = 1;
@@ -303,6 +307,24 @@ int lds_hits_for(const sm_ctx *c, const sm_batch &b) {
   return h;
 }
 
+// The launch shape of a batch: the first table entry whose class holds it,
+// else the built-in one.
+sm_shape choose_shape(const sm_ctx *c, const sm_batch &b) {
+  const double mean = b.n_events > 0 ? (double)b.n_hits / (2.0 * b.n_events) : 0.0;
+  for (const sm_shape &e : c->shapes)
+    if (mean <= (double)e.max_mean_item_hits && b.n_events <= e.max_events) return e;
+  sm_shape d{};
+  d.seed_wgs = c->base_wgs;
+  d.lds_hits = lds_hits_for(c, b);
+  return d;
+}
+
+// Workgroups of the matching kernel for a seeding grid: the grid, or the
+// configured count (it uses the seeding workgroups' matching scratch).
+int match_grid(const sm_ctx *c, int grid) {
+  return c->cfg.match_wgs > 0 ? std::min(c->cfg.match_wgs, grid) : grid;
+}
+
 // Make the slot's batch-sized buffers large enough for this batch.
 sm_status fit_batch(sm_ctx *c, Slot &s, const sm_batch &b) {
   Caps &k = s.caps;
@@ -314,7 +336,9 @@ sm_status fit_batch(sm_ctx *c, Slot &s, const sm_batch &b) {
   if (pool > k.pool) { k.pool = std::max(pool, 2 * k.pool); re = true; }
   const long long lpool = b.n_velo + 1024;
   if (lpool > k.lpool) { k.lpool = std::max(lpool, 2 * k.lpool); re = true; }
-  s.lds_hits = lds_hits_for(c, b);
+  const sm_shape sh = choose_shape(c, b);
+  s.lds_hits = sh.lds_hits;
+  s.grid = sh.seed_wgs;
   if (!re && !s.allocs.empty()) return SM_OK;
   return alloc_slot(c, s);
 }
@@ -334,7 +358,7 @@ sm_status check_batch(const sm_batch *b, const sm_out *o) {
   return SM_OK;
 }
 
-void fill_desc(Desc &d, const sm_batch &b, const sm_out &o) {
+void fill_desc(Desc &d, const sm_batch &b, const sm_out &o, int grid) {
   d.b = b;
   d.seeds = o.seeds;
   d.longs = o.longs;
@@ -344,6 +368,8 @@ void fill_desc(Desc &d, const sm_batch &b, const sm_out &o) {
   d.long_cap = o.long_cap;
   d.n_events = b.n_events;
   d.n_items = 2 * b.n_events;
+  d.grid = grid;
+  d.pad = 0;
 }
 
 // The head of the batched sequence: the batch's preparation and the
@@ -371,18 +397,18 @@ sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
     int e = hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, q);
     if (!e) e = enqueue_prepare_big(c, s, q);
     if (!e && c->dp.match_mode >= 0 && c->p.uv_mode == 0)
-      e = smk_launch_seed_nomatch(d, S, c->seed_wgs, s.lds_hits, q);
-    if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
-    if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, c->match_wgs, q);
+      e = smk_launch_seed_nomatch(d, S, s.grid, s.lds_hits, q);
+    if (!e) e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, q);
+    if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, match_grid(c, s.grid), q);
     if (!e) e = smk_launch_copy(d, S, 1024, q);
     if (!e) e = hipMemcpyAsync(s.h_cnt, s.S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q);
     return (hipError_t)e;
   };
   for (const Slot::Captured &g : s.graphs)
-    if (g.lds_hits == s.lds_hits) return hip_status(hipGraphLaunch(g.exec, st));
+    if (g.lds_hits == s.lds_hits && g.grid == s.grid) return hip_status(hipGraphLaunch(g.exec, st));
   hipStream_t cap;
   if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return SM_ERR_DEVICE;
-  Slot::Captured g{s.lds_hits, nullptr, nullptr};
+  Slot::Captured g{s.lds_hits, s.grid, nullptr, nullptr};
   hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
   if (e == hipSuccess) {
     hipError_t e2 = seq(cap);
@@ -419,11 +445,11 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   if (!e) e = hipEventRecord(ev[1], q);
   if (!e) e = hipEventRecord(ev[2], q);
   if (!e && c->dp.match_mode >= 0 && c->p.uv_mode == 0)
-    e = smk_launch_seed_nomatch(d, S, c->seed_wgs, s.lds_hits, q);
+    e = smk_launch_seed_nomatch(d, S, s.grid, s.lds_hits, q);
   if (!e) e = hipEventRecord(ev[3], q);
-  if (!e) e = smk_launch_seed(d, S, 0, -1, 1, c->seed_wgs, s.lds_hits, 0, c->p.uv_mode, q);
+  if (!e) e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, q);
   if (!e) e = hipEventRecord(ev[4], q);
-  if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, c->match_wgs, q);
+  if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, match_grid(c, s.grid), q);
   if (!e) e = hipEventRecord(ev[5], q);
   if (!e) e = smk_launch_copy(d, S, 1024, q);   // offset scans and copy
   if (!e) e = hipEventRecord(ev[6], q);
@@ -484,7 +510,7 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
   hipStream_t q = (hipStream_t)stream;
   for (int tries = 0; tries < kMaxTries; ++tries) {
     if ((st = fit_batch(c, s, *b)) != SM_OK) return st;
-    fill_desc(*s.h_desc, *b, *o);
+    fill_desc(*s.h_desc, *b, *o, s.grid);
     // the batched graph uploads the descriptor and copies the counters back
     // itself; the plain and timed sequences do it here
     const bool graph = !times && !plain;
@@ -665,7 +691,7 @@ sm_status run_noalloc(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream) {
   const smk::KCtx *dk = reinterpret_cast<const smk::KCtx *>(base + kNaKctxOff);
   Desc *dd = reinterpret_cast<Desc *>(base + kNaDescOff);
   Counters *dc = reinterpret_cast<Counters *>(base + kNaCntOff);
-  fill_desc(*c->na_desc, *b, *o);
+  fill_desc(*c->na_desc, *b, *o, kNaWgs);
   hipStream_t q = (hipStream_t)stream;
   const int lds = lds_hits_for(c, *b);
   int e = hipMemcpyAsync((void *)dk, c->na_kctx, sizeof(smk::KCtx), hipMemcpyHostToDevice, q);
@@ -793,7 +819,17 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
   hipDeviceProp_t prop;
   hipGetDeviceProperties(&prop, c->device);
   const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-  c->seed_wgs = c->cfg.seed_wgs > 0 ? c->cfg.seed_wgs : cus * 4;
+  c->base_wgs = c->cfg.seed_wgs > 0 ? c->cfg.seed_wgs : cus * 4;
+  c->seed_wgs = c->base_wgs;
+  // the main seeding forms may take dynamic LDS beyond 64 KB where the device
+  // allows it (launch shapes of up to 6144 LDS hits)
+  {
+    const size_t want = smk_seed_lds_bytes(6144);
+    const size_t dev = prop.sharedMemPerBlock > 0 ? (size_t)prop.sharedMemPerBlock : 65536;
+    const size_t lim = std::min(want, dev);
+    if (lim > 65536 && smk_seed_lds_limit((int)lim) == 0) c->lds_limit = lim;
+    (void)hipGetLastError();
+  }
   // big-item form: one 1024-thread workgroup per CU, hits in LDS up to what
   // the per-workgroup LDS limit leaves after its shared state
   c->big_wgs = std::max(cus / 2, 1);
@@ -812,11 +848,10 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
       c->lds_big = (int)std::max<size_t>(b64, 256);
     }
   }
-  // matching kernel: its workgroups (at most seed_wgs: it uses their
-  // per-workgroup matching scratch); whether it or the seeding kernel
-  // matches is chosen per batch (match_wgs 0), or fixed (> 0: the matching
-  // kernel, < 0: the seeding kernel)
-  c->match_wgs = c->cfg.match_wgs > 0 ? std::min(c->cfg.match_wgs, c->seed_wgs) : c->seed_wgs;
+  // whether the matching kernel or the seeding kernel matches is chosen per
+  // batch (match_wgs 0), or fixed (> 0: the matching kernel, with at most the
+  // batch's seeding grid of workgroups, whose matching scratch it uses; < 0:
+  // the seeding kernel)
   c->dp = make_params(c->g, c->p);
   c->dp.match_mode = c->cfg.match_wgs > 0 ? 1 : (c->cfg.match_wgs < 0 ? -1 : 0);
   // the Hough-cluster form is built only with the matching code: its batches
@@ -825,7 +860,7 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
   if (c->p.uv_mode != 0) c->dp.match_mode = -1;
   // item latency on one 256-thread workgroup, fitted to phase timers on
   // min-bias (778 hits: 93 us) and stress items (12,011 hits: 13.9 ms)
-  c->dp.main_slots = c->seed_wgs;
+  c->dp.main_slots = c->base_wgs;
   c->dp.big_slots = c->big_wgs;
   c->dp.lat_a = 0.048f;
   c->dp.lat_b = 9.2e-5f;
@@ -893,7 +928,7 @@ sm_status sm_profile(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stre
 static sm_status start_slot(sm_ctx *c, Slot &s) {
   sm_status st = fit_batch(c, s, s.batch);
   if (st != SM_OK) return st;
-  fill_desc(*s.h_desc, s.batch, *s.out);
+  fill_desc(*s.h_desc, s.batch, *s.out, s.grid);
   // the graph uploads the descriptor and copies the counters back
   if ((st = enqueue_batched(c, s, s.stream)) != SM_OK) return st;
   return hip_status(hipEventRecord(s.done, s.stream));
@@ -950,6 +985,39 @@ sm_status sm_poll(sm_ctx *ctx, int64_t ticket, int wait) {
     }
   }
   return SM_ERR_INVALID;
+}
+
+sm_status sm_set_shapes(sm_ctx *ctx, const sm_shape *shapes, int32_t n) {
+  if (!ctx || n < 0 || (n > 0 && !shapes)) return SM_ERR_INVALID;
+  std::vector<sm_shape> t(shapes, shapes + n);
+  int grid = ctx->base_wgs;
+  for (const sm_shape &e : t) {
+    if (e.max_mean_item_hits < 0 || e.max_events < 0 || e.seed_wgs < 2 || e.seed_wgs > 65536 ||
+        e.lds_hits < 256 || e.lds_hits > 6144 || e.lds_hits % 256 != 0 ||
+        smk_seed_lds_bytes(e.lds_hits) > ctx->lds_limit)
+      return SM_ERR_INVALID;
+    grid = std::max(grid, e.seed_wgs);
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (const Slot &s : ctx->slots)
+    if (s.busy) return SM_ERR_BUSY;
+  if (hipSetDevice(ctx->device) != hipSuccess) return SM_ERR_DEVICE;
+  ctx->shapes = t;
+  if (grid > ctx->seed_wgs) {
+    // per-workgroup scratch for the larger grid (graphs are rebuilt)
+    ctx->seed_wgs = grid;
+    for (Slot &s : ctx->slots) {
+      const sm_status st = alloc_slot(ctx, s);
+      if (st != SM_OK) return st;
+    }
+  }
+  return SM_OK;
+}
+
+sm_status sm_launch_shape(const sm_ctx *ctx, const sm_batch *batch, sm_shape *shape) {
+  if (!ctx || !batch || !shape || batch->n_events < 0 || batch->n_hits < 0) return SM_ERR_INVALID;
+  *shape = choose_shape(ctx, *batch);
+  return SM_OK;
 }
 
 int64_t sm_batch_bytes(const sm_ctx *ctx, int32_t n_events, int64_t n_hits, int64_t n_velo) {

@@ -61,12 +61,45 @@ def pin(batch) -> Packed:
     return Packed(t, offsets, nbytes)
 
 
+class EventPool:
+    """Events packed once into one pinned host buffer (where a trigger's
+    network receive would leave them).  A request is a run of consecutive
+    events of the pool: its hits and VELO states are contiguous slices of
+    the pool's arrays, copied straight from there; only its zone and VELO
+    offsets are rebased on the host."""
+
+    def __init__(self, batch):
+        self.n_events = batch.n_events
+        self.offsets, self.nbytes = layout(batch.n_events, batch.n_hits, batch.n_velo)
+        self.packed = pin(batch)
+        self.zone_off = np.asarray(batch.zone_off, np.int64)
+        self.velo_off = np.asarray(batch.velo_off, np.int64)
+
+    def sizes(self, first: int, n: int):
+        """(events, hits, VELO states) of events [first, first + n)."""
+        h = self.zone_off[(first + n) * 24] - self.zone_off[first * 24]
+        v = self.velo_off[first + n] - self.velo_off[first]
+        return n, int(h), int(v)
+
+
 @dataclasses.dataclass
 class Request:
     rid: int
-    batch: object          # events.Batch (host)
+    batch: object          # events.Batch (host), or None for a slice of `pool`
     arrival: float         # seconds from the start of the run
     pinned: Packed | None = None
+    pool: EventPool | None = None
+    first: int = 0         # first event of the slice of `pool`
+    count: int = 0         # events of the slice of `pool`
+
+    @property
+    def n_events(self) -> int:
+        return self.batch.n_events if self.batch is not None else self.count
+
+    def sizes(self):
+        if self.batch is not None:
+            return self.batch.n_events, self.batch.n_hits, self.batch.n_velo
+        return self.pool.sizes(self.first, self.count)
 
 
 @dataclasses.dataclass
@@ -102,7 +135,7 @@ class SlotBuffers:
         _, nbytes = layout(max_events, max_hits, max_velo)
         self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.staging = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
-        seed_cap, long_cap = max_hits // 4 + 1024, max_velo + 1024
+        seed_cap, long_cap = max_hits // 8 + 1024, max_velo + 1024
         self.out = sm.DeviceOut(max_events, seed_cap, long_cap, device)
         self.h_seed_off = torch.empty(max_events + 1, dtype=torch.int32, pin_memory=True)
         self.h_long_off = torch.empty(max_events + 1, dtype=torch.int32, pin_memory=True)
@@ -141,6 +174,51 @@ class SlotBuffers:
                           velo_id=ptr["velo_id"])
         self.n_events = e
         self.out.n_events = e
+
+    def load_slice(self, pool: EventPool, first: int, n: int, stream):
+        """Copy events [first, first + n) of `pool` into the arena on `stream`:
+        the rebased offsets from this slot's pinned staging, every other array
+        straight from its slice of the pool."""
+        import torch
+        from . import sm
+        e, h, v = pool.sizes(first, n)
+        if e > self.cap[0] or h > self.cap[1] or v > self.cap[2]:
+            raise ValueError("request larger than the slot buffers")
+        offsets, _ = layout(e, h, v)
+        h0, v0 = int(pool.zone_off[first * 24]), int(pool.velo_off[first])
+        st = self.staging.numpy()
+        zo, zn = offsets["zone_off"]
+        st[zo:zo + 4 * zn] = (pool.zone_off[first * 24:(first + n) * 24 + 1] - h0) \
+            .astype(np.int32).view(np.uint8)
+        vo, vn = offsets["velo_off"]
+        st[vo:vo + 4 * vn] = (pool.velo_off[first:first + n + 1] - v0).astype(np.int32).view(np.uint8)
+        src = pool.packed.buf
+        with torch.cuda.stream(stream):
+            for f in _FIELDS:
+                o, cnt = offsets[f]
+                if cnt == 0:
+                    continue
+                if f in ("zone_off", "velo_off"):
+                    self.arena[o:o + 4 * cnt].copy_(self.staging[o:o + 4 * cnt], non_blocking=True)
+                else:
+                    po, _ = pool.offsets[f]
+                    start = po + 4 * (h0 if f.startswith("hit") else v0)
+                    self.arena[o:o + 4 * cnt].copy_(src[start:start + 4 * cnt], non_blocking=True)
+        base = self.arena.data_ptr()
+        ptr = {f: base + offsets[f][0] for f in _FIELDS}
+        self.c = sm.Batch(n_events=e, pad=0, n_hits=h, n_velo=v, zone_off=ptr["zone_off"],
+                          hit_x=ptr["hit_x"], hit_z=ptr["hit_z"], hit_id=ptr["hit_id"],
+                          velo_off=ptr["velo_off"], velo_x=ptr["velo_x"], velo_y=ptr["velo_y"],
+                          velo_z=ptr["velo_z"], velo_tx=ptr["velo_tx"], velo_ty=ptr["velo_ty"],
+                          velo_id=ptr["velo_id"])
+        self.n_events = e
+        self.out.n_events = e
+
+    def load_request(self, req, stream):
+        if req.batch is not None:
+            self.load(req.batch, stream, req.pinned)
+        else:
+            self.load_slice(req.pool, req.first, req.count, stream)
 
     def fetch(self, stream):
         """Start the copy of this slot's results into pinned host memory on
@@ -189,8 +267,8 @@ class Server:
         self.in_use = 0
         self.peak_in_use = 0
 
-    def _needs(self, b) -> int:
-        return self.ctx.batch_bytes(b.n_events, b.n_hits, b.n_velo)
+    def _needs(self, req) -> int:
+        return self.ctx.batch_bytes(*req.sizes())
 
     def serve(self, requests: list, clock=time.perf_counter, keep: bool = True) -> list:
         """Serve requests (sorted by arrival); returns Results in completion
@@ -214,12 +292,12 @@ class Server:
             # admit every arrived request that finds a free slot and memory
             while pending and pending[0].arrival <= now and self.free:
                 req = pending[0]
-                need = self._needs(req.batch)
+                need = self._needs(req)
                 if self.mem_budget is not None and self.in_use + need > self.mem_budget and busy:
                     break
                 pending.popleft()
                 si = self.free.popleft()
-                self.slots[si].load(req.batch, self.copy_stream, req.pinned)
+                self.slots[si].load_request(req, self.copy_stream)
                 ev = torch.cuda.Event()
                 ev.record(self.copy_stream)
                 self.in_use += need
@@ -270,7 +348,7 @@ class Server:
                     so = lo = np.zeros(0, np.int32)
                     seeds = np.zeros(0, sm.SEED_DTYPE)
                     longs = np.zeros(0, sm.LONG_DTYPE)
-                done.append(Result(req.rid, req.batch.n_events, req.arrival, adm, t_done,
+                done.append(Result(req.rid, req.n_events, req.arrival, adm, t_done,
                                    so, seeds, lo, longs))
                 self.free.append(si)
                 self.in_use -= need
@@ -293,11 +371,11 @@ def serve_plain(ctx, requests: list, max_events: int, max_hits: int, max_velo: i
         while clock() - t0 < req.arrival:
             pass
         adm = clock() - t0
-        slot.load(req.batch, stream, req.pinned)
+        slot.load_request(req, stream)
         ctx.run_c(slot.c, slot.out.c, plain=True)
         slot.fetch(stream).synchronize()
         so, seeds, lo, longs = slot.collect()
-        out.append(Result(req.rid, req.batch.n_events, req.arrival, adm, clock() - t0,
+        out.append(Result(req.rid, req.n_events, req.arrival, adm, clock() - t0,
                           so, seeds, lo, longs))
     return out
 

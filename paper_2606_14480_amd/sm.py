@@ -71,6 +71,14 @@ class Batch(C.Structure):
                 ("velo_tx", C.c_void_p), ("velo_ty", C.c_void_p), ("velo_id", C.c_void_p)]
 
 
+class Shape(C.Structure):
+    _fields_ = [("max_mean_item_hits", C.c_int32), ("max_events", C.c_int32),
+                ("seed_wgs", C.c_int32), ("lds_hits", C.c_int32)]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
 class KernelTimes(C.Structure):
     _fields_ = [(n, C.c_float) for n in ("prepare", "seed_big", "seed", "seed_fused", "match", "copy",
                                          "total")]
@@ -112,6 +120,10 @@ _lib.sm_poll.argtypes = [C.c_void_p, C.c_int64, C.c_int]
 _lib.sm_poll.restype = C.c_int
 _lib.sm_profile.argtypes = [C.c_void_p, _P(Batch), _P(Out), C.c_void_p, _P(KernelTimes)]
 _lib.sm_profile.restype = C.c_int
+_lib.sm_set_shapes.argtypes = [C.c_void_p, _P(Shape), C.c_int32]
+_lib.sm_set_shapes.restype = C.c_int
+_lib.sm_launch_shape.argtypes = [C.c_void_p, _P(Batch), _P(Shape)]
+_lib.sm_launch_shape.restype = C.c_int
 _lib.sm_batch_bytes.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int64]
 _lib.sm_batch_bytes.restype = C.c_int64
 _lib.sm_destroy.argtypes = [C.c_void_p]
@@ -120,7 +132,8 @@ _lib.sm_status_str.argtypes = [C.c_int]
 _lib.sm_status_str.restype = C.c_char_p
 
 EXPORTS = ("sm_default_geometry", "sm_default_params", "sm_create", "sm_run", "sm_run_plain",
-           "sm_run_noalloc", "sm_submit", "sm_poll", "sm_profile", "sm_batch_bytes", "sm_destroy", "sm_status_str")
+           "sm_run_noalloc", "sm_submit", "sm_poll", "sm_profile", "sm_set_shapes",
+           "sm_launch_shape", "sm_batch_bytes", "sm_destroy", "sm_status_str")
 
 
 def lib():
@@ -216,9 +229,16 @@ def _stream_ptr(stream):
 
 
 class Context:
+    """A library context.  shapes: the table of launch shapes by batch class
+    (list of dicts with max_mean_item_hits, max_events, seed_wgs, lds_hits);
+    "tuned" (the default) takes the autotuner's committed table for this
+    device, unless seed_wgs or lds_hits are given, which then fix the
+    launch shape of every batch; [] keeps the built-in choice."""
+
     def __init__(self, geometry: Geometry | None = None, params: Params | None = None,
                  device: int = 0, n_slots: int = 2, seed_wgs: int = 0, lds_hits: int = 0,
-                 validate: bool = False, mem_budget: int = 0, match_wgs: int = 0):
+                 validate: bool = False, mem_budget: int = 0, match_wgs: int = 0,
+                 shapes="tuned"):
         self.geometry = geometry or default_geometry()
         self.params = params or default_params()
         cfg = Config(device=device, n_slots=n_slots, seed_wgs=seed_wgs, match_wgs=match_wgs,
@@ -228,6 +248,35 @@ class Context:
         if st != OK:
             raise SmError(st, "sm_create")
         self.h = h
+        self.shape_source = "built-in"
+        if shapes == "tuned":
+            shapes = [] if (seed_wgs or lds_hits) else _tuned_shapes(device)
+            if shapes:
+                self.shape_source = "autotune"
+        elif shapes:
+            self.shape_source = "given"
+        if shapes:
+            self.set_shapes(shapes)
+
+    def set_shapes(self, shapes, check: bool = True) -> int:
+        arr = (Shape * max(len(shapes), 1))()
+        for i, e in enumerate(shapes):
+            arr[i] = Shape(**{k: int(e[k]) for k in ("max_mean_item_hits", "max_events",
+                                                      "seed_wgs", "lds_hits")})
+        st = _lib.sm_set_shapes(self.h, arr, len(shapes))
+        if check and st != OK:
+            raise SmError(st, "sm_set_shapes")
+        return st
+
+    def launch_shape(self, batch) -> dict:
+        """The launch shape a batched call takes for `batch` (a DeviceBatch,
+        or anything with n_events and n_hits)."""
+        b = Batch(n_events=int(batch.n_events), n_hits=int(batch.n_hits))
+        sh = Shape()
+        st = _lib.sm_launch_shape(self.h, C.byref(b), C.byref(sh))
+        if st != OK:
+            raise SmError(st, "sm_launch_shape")
+        return sh.as_dict()
 
     def close(self):
         if getattr(self, "h", None):
@@ -283,6 +332,17 @@ class Context:
 
     def batch_bytes(self, n_events, n_hits, n_velo) -> int:
         return _lib.sm_batch_bytes(self.h, n_events, n_hits, n_velo)
+
+
+def _tuned_shapes(device: int) -> list:
+    """The autotuner's committed launch shapes for this device (or none)."""
+    try:
+        import torch
+        name = torch.cuda.get_device_properties(device).name
+    except Exception:
+        return []
+    from . import autotune
+    return autotune.shapes_for(name)
 
 
 def reconstruct(ctx: Context, host_batch, plain: bool = False, seed_cap=None, long_cap=None):

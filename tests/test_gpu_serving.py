@@ -111,6 +111,9 @@ def test_submit_busy_and_poll(sm):
 
 
 def test_autotune_roundtrip(sm, tmp_path):
+    """The tuner's best shape comes back from its cache as the class's entry,
+    a context given the table takes it, and the bytes equal the built-in
+    shape's."""
     from paper_2606_14480_amd import autotune
     import torch
     b = ev.generate(ev.config(2, n_events=100))
@@ -118,16 +121,78 @@ def test_autotune_roundtrip(sm, tmp_path):
     path = str(tmp_path / "tune.json")
     best = autotune.tune(b, reps=2, path=path, wgs_per_cu=(2, 4), lds_hits=(1024, 2048), log=say)
     name = torch.cuda.get_device_properties(0).name
-    assert autotune.lookup(name, b, path) == (best["seed_wgs"], best["lds_hits"])
-    c = sm.Context(seed_wgs=best["seed_wgs"], lds_hits=best["lds_hits"])
+    e = autotune.lookup(name, b, path)
+    assert (e["seed_wgs"], e["lds_hits"]) == (best["seed_wgs"], best["lds_hits"])
+    c = sm.Context(shapes=autotune.shapes_for(name, path))
     try:
+        got = c.launch_shape(b)
+        assert (got["seed_wgs"], got["lds_hits"]) == (best["seed_wgs"], best["lds_hits"])
         g = sm.reconstruct(c, b)
     finally:
         c.close()
-    c2 = sm.Context()
+    c2 = sm.Context(shapes=[])
     try:
+        assert c2.launch_shape(b)["max_events"] == 0          # the built-in choice
         g2 = sm.reconstruct(c2, b)
     finally:
         c2.close()
     for x, y in zip(g, g2):
         assert x.tobytes() == y.tobytes()
+
+
+def test_shape_table_classes(sm):
+    """Batches take the first table entry whose class holds them; a grid
+    larger than the context's grows its scratch; entries out of range are
+    refused; outputs do not depend on the shape."""
+    small = ev.generate(ev.config(2, n_events=30))
+    big = ev.generate(ev.config(4, n_events=30))
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    table = [{"max_mean_item_hits": 1024, "max_events": 64, "seed_wgs": 5 * cus, "lds_hits": 1536},
+             {"max_mean_item_hits": 1 << 20, "max_events": 1 << 20, "seed_wgs": 2 * cus,
+              "lds_hits": 3072}]
+    say("[gpu] shape table")
+    c = sm.Context(shapes=table)
+    ref = sm.Context(shapes=[])
+    try:
+        assert c.launch_shape(small)["seed_wgs"] == 5 * cus       # min-bias items: first class
+        assert c.launch_shape(big)["lds_hits"] == 3072            # dense items: second class
+        for b in (small, big):
+            for x, y in zip(sm.reconstruct(c, b), sm.reconstruct(ref, b)):
+                assert x.tobytes() == y.tobytes()
+        for bad in ({"max_mean_item_hits": 1, "max_events": 1, "seed_wgs": 1, "lds_hits": 1024},
+                    {"max_mean_item_hits": 1, "max_events": 1, "seed_wgs": 64, "lds_hits": 1000},
+                    {"max_mean_item_hits": 1, "max_events": 1, "seed_wgs": 64, "lds_hits": 8192}):
+            assert c.set_shapes([bad], check=False) == sm.ERR_INVALID
+    finally:
+        c.close()
+        ref.close()
+
+
+def test_pool_slice_requests_equal_alone(sm):
+    """Requests that are runs of consecutive events of one pinned pool (the
+    serving leg's form: hits copied straight from the pool, offsets rebased)
+    give the same bytes as the same events run alone."""
+    from paper_2606_14480_amd import serving
+    host = ev.generate(ev.config(5, n_events=300))
+    pool = serving.EventPool(host)
+    rng = np.random.default_rng(9)
+    sizes = rng.integers(1, 200, 16)
+    firsts = [int(rng.integers(0, host.n_events - int(k) + 1)) for k in sizes]
+    arr = serving.poisson_arrivals(20000.0, len(sizes), seed=4)
+    reqs = [serving.Request(i, None, float(arr[i]), pool=pool, first=firsts[i], count=int(k))
+            for i, k in enumerate(sizes)]
+    say(f"[gpu] pool-slice serving: {len(reqs)} requests")
+    ctx = sm.Context(n_slots=3)
+    try:
+        srv = serving.Server(ctx, 3, host.n_events, host.n_hits, host.n_velo)
+        res = srv.serve(reqs)
+        by = {r.rid: r for r in res}
+        assert sorted(by) == list(range(len(reqs)))
+        for q in reqs:
+            alone = sm.reconstruct(ctx, host.subset(range(q.first, q.first + q.count)))
+            r = by[q.rid]
+            for a, b in zip(alone, (r.seed_off, r.seeds, r.long_off, r.longs)):
+                assert a.tobytes() == b.tobytes(), q.rid
+    finally:
+        ctx.close()
