@@ -415,7 +415,8 @@ def main():
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": None if fused else measured_traffic(),
-                     "alg_bytes_per_launch": alg_bytes},
+                     "alg_bytes_per_launch": alg_bytes,
+                     "counters": None if fused else measured_sq()},
         "roofline_match": {"bound": "hbm", "kernel": "k_match",
                            "achieved": round(m_achieved, 2) if m_achieved else None,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -426,6 +427,35 @@ def main():
         res["cpu_baseline"] = cpu_baseline(host, args.cpu_seconds)
     ctx.close()
     print(json.dumps(res), flush=True)
+
+
+def _profile_lines(name):
+    """The key: value lines of a committed rocprofv3 summary, or None when
+    the kernel sources differ from the ones it was taken on."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    for src_name in ("sm_device.hip", "sm_device.h"):
+        src = os.path.join(ROOT, "paper_2606_14480_amd", "csrc", src_name)
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if not re.search(re.escape(src_name) + r"` sha256\s*`" + digest + "`", text):
+            return None
+    return dict(re.findall(r"^([a-z_]+): ([0-9.]+)$", text, re.M))
+
+
+def measured_sq():
+    """VALU busy, active lanes, waves per CU and LDS use of the seeding
+    kernel from the committed SQ counter summary (None if stale)."""
+    kv = _profile_lines("k_seed_minbias1000_sq_counters.md")
+    if not kv:
+        return None
+    keys = ("valu_busy", "valu_active_lanes", "waves_per_cu", "lds_utilisation", "lds_bank_conflict")
+    out = {k: float(kv[k]) for k in keys if k in kv}
+    out["source"] = "profiles/k_seed_minbias1000_sq_counters.md"
+    return out
 
 
 def measured_traffic():

@@ -20,7 +20,10 @@ import numpy as np
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 WGS_PER_CU = (2, 3, 4)
-LDS_HITS = (1024, 1536, 2048, 3072, 4096, 6144)
+# LDS hit budgets: round sizes, and the largest ones that still fit 4, 3 and
+# 2 workgroups per CU (160 KB of LDS each, about 24.9 KB of shared state per
+# workgroup besides the hits)
+LDS_HITS = (1024, 1280, 1536, 2048, 2304, 3072, 4096, 4608, 6144)
 
 
 def _pow2(x: float) -> int:
