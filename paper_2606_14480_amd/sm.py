@@ -19,6 +19,12 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                       "or python paper_2606_14480_amd/build.py")
 
+# PyTorch ships its own HIP runtime.  Loading it first makes libsm.so bind to
+# that same runtime (the shared-object name matches), so device memory,
+# streams and the GPU itself are shared by one runtime in this process; a
+# second runtime loaded after torch's would not find the GPU.
+import torch  # noqa: E402,F401
+
 # limits of the allocation-free call (include/sm.h)
 NOALLOC_MAX_EVENTS = 1024
 NOALLOC_MAX_VELO = 262144
