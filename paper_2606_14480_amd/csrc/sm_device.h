@@ -95,6 +95,9 @@ struct Desc {
 struct DevParams {
   float zf[kNL];
   double zd[kNL], tand[kNL], inv_tand[kNL];
+  // per layer at its nominal z: u = z - z_ref, g(u) of eq. trackequation,
+  // z tan(alpha) and 1/z (the UV search evaluates these for every hypothesis)
+  double uz[kNL], gz[kNL], ztan[kNL], inv_z[kNL];
   double zref, d;
   float zreff, df;
   // XZ, FP32 search

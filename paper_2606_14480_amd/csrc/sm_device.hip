@@ -69,6 +69,10 @@ __device__ __forceinline__ double xm(double a, double b, double c, double z, con
   const double u = z - P.zref;
   return a + b * u + c * gd(u, P.d);
 }
+// x(z) at layer L's nominal z, from that layer's u and g(u)
+__device__ __forceinline__ double xm_layer(double a, double b, double c, int L, const DevParams &P) {
+  return a + b * P.uz[L] + c * P.gz[L];
+}
 
 // popcount of the set bits of m below this lane
 __device__ __forceinline__ unsigned lane_rank(unsigned long long m) {
@@ -262,8 +266,18 @@ __device__ __forceinline__ int zlower(const float *X, const SeedShared<NT> &sh, 
   if constexpr (kLds) {
     const int k = kbin((float)v);
     int i = lo + (k > 0 ? (int)sh.bins[L][k - 1] : 0);
-    while (i < hi && (T)X[i] < v) ++i;
-    return i;
+    // from the bin's first hit, four hits per LDS round trip: the hits are
+    // sorted, so the count of them below v is how far to move
+    for (;;) {
+      T x4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x4[q] = i + q < hi ? (T)X[i + q] : v;
+      int c = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) c += x4[q] < v;
+      i += c;
+      if (c < 4) return i;
+    }
   } else {
     int a = lo, b = hi;
     while (a < b) {
@@ -290,27 +304,30 @@ __device__ __forceinline__ int zclosest(const float *X, const float *Z, const Se
   xb = 0.0f;
   zb = 0.0f;
   if constexpr (kLds) {
-    // from the bin of pred - tol, four hits per LDS round trip; the same
-    // comparisons in the same order as the one-hit walk
+    // from the bin of pred - tol, four hits per LDS round trip, each tested
+    // with selects rather than branches, in ascending order as the one-hit
+    // walk does
     const int k = kbin((float)lo_v);
     int i = sh.zoff[L] + (k > 0 ? (int)sh.bins[L][k - 1] : 0);
-    for (; i < hi; i += 4) {
+    for (;; i += 4) {
       float x4[4], z4[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         x4[q] = i + q < hi ? X[i + q] : __builtin_inff();
         z4[q] = i + q < hi ? Z[i + q] : 0.0f;
       }
-      bool done = false;
+      double x;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const double x = x4[q];
-        if (done || x < lo_v) continue;
-        if (x > hi_v) { done = true; continue; }
+        x = x4[q];
         const double d = fabs(x - pred);
-        if (best < 0 || d < bd - kTieMm) { best = i + q; bd = d; xb = x4[q]; zb = z4[q]; }
+        const bool take = x >= lo_v && x <= hi_v && (best < 0 || d < bd - kTieMm);
+        best = take ? i + q : best;
+        bd = take ? d : bd;
+        xb = take ? x4[q] : xb;
+        zb = take ? z4[q] : zb;
       }
-      if (done) break;
+      if (!(x <= hi_v)) break;
     }
   } else {
     for (int i = zlower<kLds>(X, sh, L, lo_v); i < hi; ++i) {
@@ -460,7 +477,7 @@ __device__ __forceinline__ bool xz_candidate(const float *X, const float *Z, con
     else if (k == s3) pos[k] = i3;
     else if ((k & 1) != it) {
       const int L = xlayer(k);
-      const int h = zclosest<kLds>(X, Z, sh, L, xm(a, b, c, P.zd[L], P), P.ext_tol);
+      const int h = zclosest<kLds>(X, Z, sh, L, xm_layer(a, b, c, L, P), P.ext_tol);
       if (h >= 0) { pos[k] = h; ++n; }
     }
   }
@@ -494,8 +511,11 @@ __device__ __forceinline__ bool uv_combo(const float *X, const float *Z, const S
                                          int L0, int h0, Combo &r) {
   const double xh0 = X[h0], zh0 = Z[h0];
   const double t0 = P.tand[L0];
-  const double y0h = (xm(a, b, c, zh0, P) - xh0) * P.inv_tand[L0];
-  double ty = y0h / zh0;
+  // a hit at its layer's nominal z (as on the workloads) reuses the layer's
+  // x(z) and 1/z; y / z is taken as y * (1/z)
+  const bool nom0 = zh0 == P.zd[L0];
+  const double y0h = ((nom0 ? xm_layer(a, b, c, L0, P) : xm(a, b, c, zh0, P)) - xh0) * P.inv_tand[L0];
+  double ty = y0h * (nom0 ? P.inv_z[L0] : 1.0 / zh0);
   // weighted sums of the line fit, y taken relative to the initial hit's y
   double s0 = t0 * t0, s1 = s0 * (zh0 - P.zref), s2 = s1 * (zh0 - P.zref);
   double q0 = 0.0, q1 = 0.0, q2 = 0.0;
@@ -506,14 +526,16 @@ __device__ __forceinline__ bool uv_combo(const float *X, const float *Z, const S
   for (int k = 0; k < 6; ++k) {
     const int L = uvlayer(k);
     if (L == L0) continue;
-    const double zl = P.zd[L], tl = P.tand[L];
-    const double pred = xm(a, b, c, zl, P) - ty * zl * tl;
+    const double tl = P.tand[L];
+    const double xl = xm_layer(a, b, c, L, P);
+    const double pred = xl - ty * P.ztan[L];
     float xhf, zhf;
     const int h = zclosest<kLds>(X, Z, sh, L, pred, P.uv_tol, xhf, zhf);
     if (h < 0) continue;
     const double zh = zhf;
-    const double yl = (xm(a, b, c, zh, P) - (double)xhf) * P.inv_tand[L];
-    ty = 0.5 * (ty + yl / zh);
+    const bool nom = zh == P.zd[L];
+    const double yl = ((nom ? xl : xm(a, b, c, zh, P)) - (double)xhf) * P.inv_tand[L];
+    ty = 0.5 * (ty + yl * (nom ? P.inv_z[L] : 1.0 / zh));
     r.pos[k] = h;
     const double w = tl * tl, u = zh - P.zref, yr = yl - y0h;
     s0 += w; s1 += w * u; s2 += w * u * u;
@@ -941,7 +963,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
       for (int pass = 0; pass < 2; ++pass) {
         const int L0 = 1 + pass;
         const double t0 = P.tand[L0];
-        const double xp = xm(a, b, c, P.zd[L0], P);
+        const double xp = xm_layer(a, b, c, L0, P);
         const double e1 = xp - yhi * t0, e2 = xp - ylo * t0;
         const double lo = fmin(e1, e2), hi = fmax(e1, e2);
         const int s = zlower<kLds>(X, sh, L0, lo);
@@ -1062,11 +1084,13 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     // canonical place (rank of its (iteration, T1, T3, T2) key)
     const bool win = tid < ncb && is_winner(tid);
     unsigned slot = 0;
-    unsigned long long key = 0;
+    SeedStage st;
     if (win) {
-      key = gmem(cand)[key_c(tid)].key;
+      // the candidate and combination records in one round trip; the key
+      // (iteration, T1, T3, T2 positions) comes with them
+      st = make_seed(tid);
       slot = wave_append(&sh.nseed);
-      sh.u.skey[slot] = key;
+      sh.u.skey[slot] = st.key;
     }
     __syncthreads();
     const unsigned ns = sh.nseed;
@@ -1074,7 +1098,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     __syncthreads();
     const unsigned long long base = sh.pbase;
     if (win && base + ns <= (unsigned long long)S.pool_cap)
-      gstore(&S.pool[base + rank_of(sh.u.skey, ns, key, slot)], make_seed(tid).s);
+      gstore(&S.pool[base + rank_of(sh.u.skey, ns, st.key, slot)], st.s);
     return;
   }
   for (unsigned i = tid; i < ncb; i += NT) {

@@ -99,6 +99,11 @@ DevParams make_params(const sm_geometry &g, const sm_params &p) {
     d.zd[l] = g.z[l];
     d.tand[l] = g.tan_stereo[l];
     d.inv_tand[l] = g.tan_stereo[l] != 0.0 ? 1.0 / g.tan_stereo[l] : 0.0;
+    const double u = g.z[l] - g.z_ref;
+    d.uz[l] = u;
+    d.gz[l] = u * u * (1.0 + p.d_ratio * u);
+    d.ztan[l] = g.z[l] * g.tan_stereo[l];
+    d.inv_z[l] = 1.0 / g.z[l];
   }
   d.zref = g.z_ref;
   d.d = p.d_ratio;
