@@ -71,8 +71,8 @@ struct Counters {
   unsigned need_ms, need_vs, need_surv, need_combo;
   long long total_seeds, total_longs;
   unsigned big_queue, n_big;     // big-item queue: order positions [0, n_big)
-  unsigned prep_ready;           // the batch is prepared (big form with preparation); 0
-                                 // again after the copy kernel
+  unsigned prep_ready;           // 1 + n_big once the batch is prepared (big form with
+                                 // preparation); 0 again after the batch's last kernel
   unsigned stall;                // a wait for the preparation gave up (sticky until the
                                  // host clears the counters)
   unsigned need_big[8];          // needs of the big-item scratch, same order as need_trip..
@@ -88,7 +88,8 @@ struct Desc {
   int32_t *long_off;
   long long seed_cap, long_cap;
   int n_events, n_items;
-  int grid, pad;   // workgroups of this batch's main seeding form (0: the context's)
+  int grid;   // workgroups of this batch's main seeding form (0: the context's)
+  int fuse;   // 1: matching inside the seeding kernel; 0: in k_match (chosen by the host)
 };
 
 // Parameters in the precision each kernel uses.

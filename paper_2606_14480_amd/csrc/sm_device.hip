@@ -1549,15 +1549,22 @@ __device__ __forceinline__ int fine_class(int sz) {
 
 // Counters, per-event hand-off counts and (batched) the longest-first item
 // order with the big-form cut: one workgroup of 1024 threads.
-__device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
-                                              const KCtx *__restrict__ K, int plain) {
+__device__ __forceinline__ unsigned prepare_batch(const Desc *__restrict__ D,
+                                                  const KCtx *__restrict__ K, int plain) {
   const Scratch &S = K->S;
-  __shared__ int hist[32];
   __shared__ int fb[kFineCls];
   __shared__ int s_scan[16];
   __shared__ int s_best;
   const int ne = D->n_events, n = D->n_items;
   const auto *zo = gmem(D->b.zone_off);
+  // every parameter of the cut is read here, before the first store (after
+  // it the loads could not move ahead of the stores they might alias), so
+  // that their latency overlaps the zone-offset loads
+  const DevParams &P = K->P;
+  const float lat_a = P.lat_a, lat_b = P.lat_b, big_r = P.big_speedup;
+  const int big_slots = P.big_slots, uv_mode = P.uv_mode;
+  const int main_grid = max(D->grid > 0 ? D->grid : P.main_slots, 1);
+  const unsigned fuse = (unsigned)D->fuse;
   if (threadIdx.x == 0) {
     Counters *c = S.cnt;
     c->seed_queue = 0; c->match_queue = 0; c->flags = 0;
@@ -1567,12 +1574,12 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
     c->need_trip = c->need_cand = c->need_tbl = c->need_sst = 0;
     c->need_ms = c->need_vs = c->need_surv = c->need_combo = 0;
     c->total_seeds = 0; c->total_longs = 0;
-    c->fuse = 1;
+    c->fuse = plain ? 1u : fuse;
     if (plain) { D->seed_off[0] = 0; D->long_off[0] = 0; }
   }
   if (plain) {
     for (int e = threadIdx.x; e < ne; e += blockDim.x) gmem(S.ev_done)[e] = 0;
-    return;
+    return 0u;
   }
   // Size classes are log2 buckets.  The big-item form takes every class from
   // a cut B upwards; it runs before the main form.  B is chosen by a latency
@@ -1581,16 +1588,15 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
   // r the speed-up of the 16-wave form, S the workgroups of each form, W the
   // summed latencies; "no big form" is B = 32.  The Hough variant keeps every
   // item in the main form.  Order: big classes, then the rest, longest first.
-  __shared__ float wsum[32];
-  __shared__ int mx[32];
-  // the order itself uses finer classes: kFineSub per octave, so that items
-  // of one octave (most of a min-bias batch) are still taken longest first
+  // The order uses finer classes, kFineSub per octave, so that items of one
+  // octave (most of a min-bias batch) are still taken longest first; the
+  // model's per-octave sums are taken over these classes, each item counted at
+  // the top size of its class (one LDS atomic per item and nothing else: the
+  // wave reductions of exact sums cost more than the whole model).
   __shared__ int fh[kFineCls];
-  if (threadIdx.x < 32) { hist[threadIdx.x] = 0; wsum[threadIdx.x] = 0.0f; mx[threadIdx.x] = 0; }
   for (int f = threadIdx.x; f < kFineCls; f += blockDim.x) fh[f] = 0;
   __syncthreads();
-  const DevParams &P = K->P;
-  auto latency = [&](float nh) { return P.lat_a * nh + P.lat_b * nh * nh; };
+  auto latency = [&](float nh) { return lat_a * nh + lat_b * nh * nh; };
   // the zone offsets of the first kPrepCache * blockDim items stay in
   // registers from one load for both passes below; later items are reloaded
   constexpr int kPrepCache = 2;
@@ -1601,36 +1607,8 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
 #pragma unroll
     for (int k = 0; k <= kNL; ++k) zc[c][k] = i < n ? zo[i * kNL + k] : 0;
   }
-  // per-class count, summed latency and largest size; a wave whose items
-  // share one class (the common case) adds them up first and updates once
   auto stat = [&](int i, const int (&z)[kNL + 1]) {
-    const bool in = i < n;
-    const int sz = in ? max(z[kNL] - z[0], 0) : 0;
-    const int b = 31 - __clz(sz + 1);
-    const float w = in ? latency((float)sz) : 0.0f;
-    const unsigned long long act = __ballot(in);
-    if (act == 0ull) return;
-    if (in) atomicAdd(&fh[fine_class(sz)], 1);
-    const int b0 = __shfl(b, __builtin_ctzll(act), 64);
-    if (__ballot(in && b != b0) == 0ull) {
-      float ws = w;
-      int c = in ? 1 : 0, m = sz;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        ws += __shfl_xor(ws, o, 64);
-        c += __shfl_xor(c, o, 64);
-        m = max(m, __shfl_xor(m, o, 64));
-      }
-      if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&hist[b0], c);
-        atomicAdd(&wsum[b0], ws);
-        atomicMax(&mx[b0], m);
-      }
-    } else if (in) {
-      atomicAdd(&hist[b], 1);
-      atomicAdd(&wsum[b], w);
-      atomicMax(&mx[b], sz);
-    }
+    if (i < n) atomicAdd(&fh[fine_class(max(z[kNL] - z[0], 0))], 1);
   };
   auto reload = [&](int i, int (&z)[kNL + 1]) {
 #pragma unroll
@@ -1644,14 +1622,27 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
     stat(i0 + (int)threadIdx.x, z);
   }
   __syncthreads();
-  // the cut: wave 0, one lane per class; prefix maximum of the latencies
-  // below a class, suffix sum and maximum from it upwards, then the argmin
-  // of T over the lanes (ties to the higher cut)
+  // the cut: wave 0, one lane per octave; its count, summed latency and
+  // largest size from its fine classes; prefix maximum of the latencies below
+  // an octave, suffix sum and maximum from it upwards, then the argmin of T
+  // over the lanes (ties to the higher cut)
   if (threadIdx.x < 64) {
     const int b = threadIdx.x;
     const bool v = b < 32;
-    const float lm = v && hist[b] ? latency((float)mx[b]) : 0.0f;
-    const float ws = v ? wsum[b] : 0.0f;
+    float ws = 0.0f, lm = 0.0f;
+    if (v) {
+      for (int j = 0; j < kFineSub; ++j) {
+        const int c = fh[b * kFineSub + j];
+        if (c == 0) continue;
+        // largest size of fine class (b, j): sizes + 1 in [2^b (1 + j/16),
+        // 2^b (1 + (j+1)/16)) from octave 4 up, exact below
+        const float top = b >= 4 ? ldexpf(1.0f + (float)(j + 1) / kFineSub, b) - 2.0f
+                                 : (float)((1 << b) + (j >> (4 - b)) - 1);
+        const float l = latency(top);
+        ws += (float)c * l;
+        lm = l;   // classes ascend in size
+      }
+    }
     float wtot = ws, lall = lm, pre = lm, wsuf = ws, lsuf = lm;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -1667,12 +1658,11 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
     }
     float l_lo = __shfl_up(pre, 1, 64);
     if (b == 0) l_lo = 0.0f;
-    const int grid = D->grid > 0 ? D->grid : P.main_slots;
-    const float r = P.big_speedup, sb = (float)max(P.big_slots, 1), sm = (float)max(grid, 1);
+    const float sb = (float)max(big_slots, 1), sm = (float)main_grid;
     const float t_none = fmaxf(lall, wtot / sm);
     float t = __builtin_inff();
-    if (v && b >= kBigBucket && P.uv_mode == 0 && P.big_slots > 0 && wsuf > 0.0f)
-      t = fmaxf(lsuf / r, wsuf / (r * sb)) + fmaxf(l_lo, (wtot - wsuf) / sm);
+    if (v && b >= kBigBucket && uv_mode == 0 && big_slots > 0 && wsuf > 0.0f)
+      t = fmaxf(lsuf / big_r, wsuf / (big_r * sb)) + fmaxf(l_lo, (wtot - wsuf) / sm);
     float tb = t;
     int bb = t < t_none ? b : 32;
 #pragma unroll
@@ -1696,14 +1686,12 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
     const int best = s_best;
     // the big form takes the classes >= best: the positions before the
     // first fine class of octave best
-    S.cnt->n_big = best < 32 ? (unsigned)fb[kFineSub * best - 1] : 0u;
-    // matching: in k_match after all seeding, unless big items are in the
-    // batch or the main form takes more than four rounds of items; then
-    // inside the seeding kernel, where it overlaps the seeding tail
-    const bool many = n > 4 * max(D->grid > 0 ? D->grid : P.main_slots, 1);
-    S.cnt->fuse = P.match_mode < 0 ? 1u : P.match_mode > 0 ? 0u : ((best < 32 || many) ? 1u : 0u);
+    const unsigned nb = best < 32 ? (unsigned)fb[kFineSub * best - 1] : 0u;
+    S.cnt->n_big = nb;
+    s_best = (int)nb;
   }
   __syncthreads();
+  const unsigned n_big = (unsigned)s_best;
   // positions in the order, one LDS atomic per item on its fine class; each
   // position's record holds the item and its zone offsets
   auto place = [&](int i, const int (&z)[kNL + 1]) {
@@ -1725,8 +1713,11 @@ __device__ __forceinline__ void prepare_batch(const Desc *__restrict__ D,
     reload(i0 + (int)threadIdx.x, z);
     place(i0 + (int)threadIdx.x, z);
   }
-  // per-event hand-off counts, last: no barrier above waits for these stores
-  for (int e = threadIdx.x; e < ne; e += blockDim.x) gmem(S.ev_done)[e] = 0;
+  // per-event hand-off counts (matching inside seeding only), last: no
+  // barrier above waits for these stores
+  if (fuse)
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) gmem(S.ev_done)[e] = 0;
+  return n_big;
 }
 
 // Persistent Seeding (+ Matching): each workgroup pulls (event, half) items
@@ -1765,20 +1756,25 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
       // this launch also prepares the batch: workgroup 0 does what k_prepare
       // does and then releases the others, which poll for it (bounded: on
       // giving up they flag the batch and leave, and the call fails)
+      // The flag holds 1 + the number of big items: with none, every
+      // workgroup leaves at once, with no acquire (an L2 invalidate) and no
+      // counter loads behind it.
       __shared__ int s_stall;
       if (blockIdx.x == 0) {
-        prepare_batch(D, K, 0);
+        const unsigned nb = prepare_batch(D, K, 0);
         __syncthreads();
         if (tid == 0)
-          __hip_atomic_store(&S.cnt->prep_ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&S.cnt->prep_ready, nb + 1u, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        if (nb == 0u) return;
       } else {
         if (tid == 0) {
           s_stall = 0;
-          unsigned n = 0;
+          unsigned n = 0, f;
           // relaxed polls (an acquire per poll would invalidate caches that
           // workgroup 0 is reading through), one acquire after the flag
-          while (__hip_atomic_load(&S.cnt->prep_ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-                 0u) {
+          while ((f = __hip_atomic_load(&S.cnt->prep_ready, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT)) == 0u) {
             __builtin_amdgcn_s_sleep(16);
             if (++n == kPrepSpin) {
               atomicExch(&S.cnt->stall, 1u);
@@ -1786,7 +1782,8 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
               break;
             }
           }
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          if (f == 1u) s_stall = 2;   // prepared, no big items
+          else if (!s_stall) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
         if (s_stall) return;

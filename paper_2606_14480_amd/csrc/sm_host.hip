@@ -47,13 +47,14 @@ struct Slot {
   // arguments are the slot's fixed descriptor and context pointers, so a
   // graph stays valid when scratch is reallocated
   struct Captured {
-    int lds_hits, grid;
+    int lds_hits, grid, fuse;
     hipGraph_t graph;
     hipGraphExec_t exec;
   };
   std::vector<Captured> graphs;
   int lds_hits = 2048;  // LDS hit capacity of the seeding workgroup for this batch
   int grid = 0;         // workgroups of the main seeding form for this batch
+  int fuse = 0;         // this batch is matched inside the seeding kernel
   hipEvent_t done = nullptr;
   // serving state
   bool busy = false;
@@ -330,6 +331,20 @@ int match_grid(const sm_ctx *c, int grid) {
   return c->cfg.match_wgs > 0 ? std::min(c->cfg.match_wgs, grid) : grid;
 }
 
+// Where a batch is matched: inside the seeding kernel, by the workgroup that
+// completes an event, when the main form runs more than four rounds of items
+// (matching then overlaps the seeding tail) or when the batch's mean item
+// size marks it as one with big items (matching overlaps the big items'
+// tail); otherwise in k_match after all seeding, which needs no per-item
+// release and per-event acquire.  sm_config.match_wgs can force either.
+// Only the chosen main-form instantiation is launched.
+int fuse_for(const sm_ctx *c, const sm_batch &b, int grid) {
+  if (c->dp.match_mode != 0) return c->dp.match_mode < 0 ? 1 : 0;
+  const long long items = 2LL * b.n_events;
+  if (items > 4LL * std::max(grid, 1)) return 1;
+  return b.n_hits > 2048LL * b.n_events ? 1 : 0;
+}
+
 // Make the slot's batch-sized buffers large enough for this batch.
 sm_status fit_batch(sm_ctx *c, Slot &s, const sm_batch &b) {
   Caps &k = s.caps;
@@ -344,6 +359,7 @@ sm_status fit_batch(sm_ctx *c, Slot &s, const sm_batch &b) {
   const sm_shape sh = choose_shape(c, b);
   s.lds_hits = sh.lds_hits;
   s.grid = sh.seed_wgs;
+  s.fuse = fuse_for(c, b, s.grid);
   if (!re && !s.allocs.empty()) return SM_OK;
   return alloc_slot(c, s);
 }
@@ -363,7 +379,7 @@ sm_status check_batch(const sm_batch *b, const sm_out *o) {
   return SM_OK;
 }
 
-void fill_desc(Desc &d, const sm_batch &b, const sm_out &o, int grid) {
+void fill_desc(Desc &d, const sm_batch &b, const sm_out &o, int grid, int fuse) {
   d.b = b;
   d.seeds = o.seeds;
   d.longs = o.longs;
@@ -374,7 +390,7 @@ void fill_desc(Desc &d, const sm_batch &b, const sm_out &o, int grid) {
   d.n_events = b.n_events;
   d.n_items = 2 * b.n_events;
   d.grid = grid;
-  d.pad = 0;
+  d.fuse = fuse;
 }
 
 // The head of the batched sequence: the batch's preparation and the
@@ -401,19 +417,19 @@ sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
   auto seq = [&](hipStream_t q) -> hipError_t {
     int e = hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, q);
     if (!e) e = enqueue_prepare_big(c, s, q);
-    if (!e && c->dp.match_mode >= 0 && c->p.uv_mode == 0)
-      e = smk_launch_seed_nomatch(d, S, s.grid, s.lds_hits, q);
-    if (!e) e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, q);
-    if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, match_grid(c, s.grid), q);
+    if (!e && !s.fuse) e = smk_launch_seed_nomatch(d, S, s.grid, s.lds_hits, q);
+    if (!e && s.fuse) e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, q);
+    if (!e && !s.fuse) e = smk_launch_match(d, S, match_grid(c, s.grid), q);
     if (!e) e = smk_launch_copy(d, S, 1024, q);
     if (!e) e = hipMemcpyAsync(s.h_cnt, s.S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q);
     return (hipError_t)e;
   };
   for (const Slot::Captured &g : s.graphs)
-    if (g.lds_hits == s.lds_hits && g.grid == s.grid) return hip_status(hipGraphLaunch(g.exec, st));
+    if (g.lds_hits == s.lds_hits && g.grid == s.grid && g.fuse == s.fuse)
+      return hip_status(hipGraphLaunch(g.exec, st));
   hipStream_t cap;
   if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return SM_ERR_DEVICE;
-  Slot::Captured g{s.lds_hits, s.grid, nullptr, nullptr};
+  Slot::Captured g{s.lds_hits, s.grid, s.fuse, nullptr, nullptr};
   hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
   if (e == hipSuccess) {
     hipError_t e2 = seq(cap);
@@ -449,12 +465,11 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   if (!e) e = enqueue_prepare_big(c, s, q);   // preparation and big form
   if (!e) e = hipEventRecord(ev[1], q);
   if (!e) e = hipEventRecord(ev[2], q);
-  if (!e && c->dp.match_mode >= 0 && c->p.uv_mode == 0)
-    e = smk_launch_seed_nomatch(d, S, s.grid, s.lds_hits, q);
+  if (!e && !s.fuse) e = smk_launch_seed_nomatch(d, S, s.grid, s.lds_hits, q);
   if (!e) e = hipEventRecord(ev[3], q);
-  if (!e) e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, q);
+  if (!e && s.fuse) e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, q);
   if (!e) e = hipEventRecord(ev[4], q);
-  if (!e && c->dp.match_mode >= 0) e = smk_launch_match(d, S, match_grid(c, s.grid), q);
+  if (!e && !s.fuse) e = smk_launch_match(d, S, match_grid(c, s.grid), q);
   if (!e) e = hipEventRecord(ev[5], q);
   if (!e) e = smk_launch_copy(d, S, 1024, q);   // offset scans and copy
   if (!e) e = hipEventRecord(ev[6], q);
@@ -515,7 +530,7 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
   hipStream_t q = (hipStream_t)stream;
   for (int tries = 0; tries < kMaxTries; ++tries) {
     if ((st = fit_batch(c, s, *b)) != SM_OK) return st;
-    fill_desc(*s.h_desc, *b, *o, s.grid);
+    fill_desc(*s.h_desc, *b, *o, s.grid, s.fuse);
     // the batched graph uploads the descriptor and copies the counters back
     // itself; the plain and timed sequences do it here
     const bool graph = !times && !plain;
@@ -696,7 +711,7 @@ sm_status run_noalloc(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream) {
   const smk::KCtx *dk = reinterpret_cast<const smk::KCtx *>(base + kNaKctxOff);
   Desc *dd = reinterpret_cast<Desc *>(base + kNaDescOff);
   Counters *dc = reinterpret_cast<Counters *>(base + kNaCntOff);
-  fill_desc(*c->na_desc, *b, *o, kNaWgs);
+  fill_desc(*c->na_desc, *b, *o, kNaWgs, 0);
   hipStream_t q = (hipStream_t)stream;
   const int lds = lds_hits_for(c, *b);
   int e = hipMemcpyAsync((void *)dk, c->na_kctx, sizeof(smk::KCtx), hipMemcpyHostToDevice, q);
@@ -933,7 +948,7 @@ sm_status sm_profile(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stre
 static sm_status start_slot(sm_ctx *c, Slot &s) {
   sm_status st = fit_batch(c, s, s.batch);
   if (st != SM_OK) return st;
-  fill_desc(*s.h_desc, s.batch, *s.out, s.grid);
+  fill_desc(*s.h_desc, s.batch, *s.out, s.grid, s.fuse);
   // the graph uploads the descriptor and copies the counters back
   if ((st = enqueue_batched(c, s, s.stream)) != SM_OK) return st;
   return hip_status(hipEventRecord(s.done, s.stream));
