@@ -35,6 +35,8 @@ WORKLOADS = {
               "[10, 600], otherwise min-bias-like",
     "stress": "stress-{n}: {n} events per batch, negative-binomial(mean 240, k=1) tracks in "
               "[20, 3000], 5% inefficiency, 20% noise hits",
+    "ghost": "minbias-{n} with the network form of the final selection (Sec. 4.4: ghost "
+             "probability < 0.8, clone gap 0.05; weights trained on the generator's truth)",
 }
 
 
@@ -55,8 +57,8 @@ def match_kernel_bytes(b, n_seeds: int, n_longs: int) -> int:
     the two items' seed counts and pool offsets, two VELO offsets and its
     long-track count and pool offset (32 B), the VELO states (x, y, z, tx, ty,
     id: 24 B each), five fields of each seed (20 B), and per long track its
-    40 B record."""
-    return 32 * b.n_events + 24 * b.n_velo + 20 * n_seeds + 40 * n_longs
+    48 B record."""
+    return 32 * b.n_events + 24 * b.n_velo + 20 * n_seeds + 48 * n_longs
 
 
 def cpu_model() -> str:
@@ -264,9 +266,9 @@ def main():
                     help="min-bias events in the serving pool (requests are 1..this many)")
     ap.add_argument("--serve-plain", type=int, default=20,
                     help="requests of the 0.8 stream also run through the plain form")
-    ap.add_argument("--legs", default="uneven,stress",
+    ap.add_argument("--legs", default="uneven,stress,ghost",
                     help="further workloads at their stated sizes, timed beside the headline "
-                         "(comma list of uneven, stress; empty: none)")
+                         "(comma list of uneven, stress, ghost; empty: none)")
     ap.add_argument("--leg-steps", type=int, default=5)
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes generating the synthetic events")
@@ -290,7 +292,7 @@ def main():
     t0 = time.perf_counter()
     host = gen(ev.config(wl, n_events=args.events or None))
     legs = [x for x in args.legs.split(",") if x and x != args.workload]
-    leg_hosts = {x: gen(ev.config({"uneven": 3, "stress": 4}[x])) for x in legs}
+    leg_hosts = {x: gen(ev.config({"uneven": 3, "stress": 4}[x])) for x in legs if x != "ghost"}
     pool = gen(ev.config(5, n_events=args.serve_pool)) \
         if args.serve_requests > 0 and args.workload == "minbias" else None
     log(f"[bench] generated {host.n_events} events, {host.n_hits} hits, {host.n_velo} VELO "
@@ -351,6 +353,17 @@ def main():
     # further workloads at their stated sizes (uneven: all events against the
     # oracle; stress: events 0-499)
     leg_res = {}
+    if "ghost" in legs and args.workload == "minbias":
+        # the headline batch again, through a context with the network form
+        g_over = dict(over, final_sel=1)
+        gctx = sm.Context(params=sm.default_params(**g_over))
+        try:
+            leg_res["ghost"] = extra_leg(
+                gctx, sm, "ghost", host, args.leg_steps, 1,
+                0 if args.no_parity else host.n_events,
+                dict(g_over, ghost_nn=sm.ghost_nn_weights()))
+        finally:
+            gctx.close()
     for name, lh in leg_hosts.items():
         leg_res[name] = extra_leg(ctx, sm, name, lh, args.leg_steps, 1,
                                   0 if args.no_parity else (lh.n_events if name == "uneven" else 500),

@@ -56,6 +56,23 @@ typedef struct {
   double z_ref;
 } sm_geometry;
 
+/* Ghost-probability network of the final selection (Sec. 4.4).  Inputs, in
+ * this order: z_match (eq. z_match), dx, dy, dtx, dty, chi2_match, eta of the
+ * VELO state (asinh(1 / sqrt(tx^2 + ty^2)), the slope floored at 1e-9) and the
+ * seed's SciFi hit count (n_x + n_uv); each is standardised as
+ * (x - mean[i]) / scale[i].  One hidden layer of SM_NN_HIDDEN rectified units
+ * (h_j = max(0, b1[j] + sum_i w1[j][i] x_i)), a logistic output
+ * (1 / (1 + exp(-(b2 + sum_j w2[j] h_j)))).  Evaluated in FP64.  The paper
+ * gives the inputs and layer sizes only; the package's ghost_nn.json holds
+ * weights trained on the synthetic generator's truth. */
+#define SM_NN_INPUTS 8
+#define SM_NN_HIDDEN 32
+typedef struct {
+  double mean[SM_NN_INPUTS], scale[SM_NN_INPUTS];  /* scale must be non-zero */
+  double w1[SM_NN_HIDDEN][SM_NN_INPUTS], b1[SM_NN_HIDDEN];
+  double w2[SM_NN_HIDDEN], b2;
+} sm_ghost_nn;
+
 /* Every constant of the method.  sm_default_params() fills the paper's values
  * and the documented readings where the paper gives none. */
 typedef struct {
@@ -102,6 +119,19 @@ typedef struct {
   int32_t hough_fine;      /* >= 1 */
   int32_t hough_min;       /* >= 1 */
   int32_t pad2;
+  /* Final selection of Matching, Sec. 4.4.  final_sel 0 (default): a pair
+   * that passed the preselection and the chi2_match cut is kept when its
+   * chi2_match is the lowest among such pairs on its seed and among those on
+   * its VELO state (the reading used without network weights).  final_sel 1:
+   * pairs whose ghost probability (ghost_nn) is below ghost_cut are
+   * retained; a retained track is a clone, and dropped, when another retained
+   * track on its VELO state or on its seed has a ghost probability lower by
+   * clone_gap or more.  Any other value: SM_ERR_INVALID. */
+  int32_t final_sel;
+  int32_t pad3;
+  double ghost_cut;        /* 0.8 */
+  double clone_gap;        /* 0.05 */
+  sm_ghost_nn ghost_nn;    /* read when final_sel = 1 */
 } sm_params;
 
 /* Library resources; zero fields take defaults. */
@@ -164,7 +194,9 @@ typedef struct {
   float chi2;             /* chi2_match */
   float z_match;          /* eq. z_match */
   float dx, dy, dtx, dty; /* matching residuals */
-} sm_long;                /* 40 bytes */
+  float ghost_prob;       /* final_sel 1: the network's ghost probability; else -1 */
+  int32_t pad;
+} sm_long;                /* 48 bytes */
 
 /* Outputs, caller-allocated on the device.  Seeds of event e are
  * seeds[seed_off[e] .. seed_off[e+1]) in canonical order (half, iteration,

@@ -87,6 +87,9 @@ void orc_default_params(orc_params *p) {
   p->hough_best = 8;          /* Sec. 3.4: up to eight best bins */
   p->hough_fine = 4;          /* READING: "several finer bins" */
   p->hough_min = 2;           /* READING */
+  p->final_sel = 0;           /* READING: no network weights are published */
+  p->ghost_cut = 0.8;         /* Sec. 4.4: ghost probability < 0.8 */
+  p->clone_gap = 0.05;        /* Sec. 4.4: clone if at least 0.05 higher */
 }
 
 /* ---------------------------------------------------------- helpers ----- */
@@ -752,10 +755,77 @@ static pair_eval eval_pair(const orc_params *P, const orc_geom *g, const orc_see
   return r;
 }
 
-/* All VELO x seed combinations of one event; a combination is kept when its
- * chi2_match is the smallest both among the survivors sharing its seed and
- * among those sharing its VELO track (READING of the final clone removal of
- * Sec. 4.4, with chi2_match in place of the ghost probability). */
+/* The network's eight inputs for one surviving pair (Sec. 4.4).  eta of the
+ * VELO state from its slopes: eta = -ln tan(theta / 2) = asinh(1 / tan theta),
+ * tan theta = sqrt(tx^2 + ty^2) (floored at 1e-9); the SciFi hit count is the
+ * seed's hits on x and stereo layers. */
+static void nn_inputs(const pair_eval *r, const orc_seed *s, double txv, double tyv,
+                      double f[ORC_NN_IN]) {
+  f[0] = r->zm;
+  f[1] = r->dx;
+  f[2] = r->dy;
+  f[3] = r->dtx;
+  f[4] = r->dty;
+  f[5] = r->chi2;
+  f[6] = asinh(1.0 / fmax(sqrt(txv * txv + tyv * tyv), 1e-9));
+  f[7] = (double)(s->nx + s->nuv);
+}
+
+/* Ghost probability (Sec. 4.4): standardised inputs, one hidden layer of
+ * rectified units, logistic output. */
+double orc_ghost_prob(const orc_params *P, const double f[ORC_NN_IN]) {
+  const orc_ghost_nn *n = &P->ghost_nn;
+  double x[ORC_NN_IN];
+  for (int i = 0; i < ORC_NN_IN; ++i) x[i] = (f[i] - n->mean[i]) / n->scale[i];
+  double out = n->b2;
+  for (int j = 0; j < ORC_NN_HID; ++j) {
+    double h = n->b1[j];
+    for (int i = 0; i < ORC_NN_IN; ++i) h += n->w1[j][i] * x[i];
+    out += n->w2[j] * (h > 0.0 ? h : 0.0);
+  }
+  return 1.0 / (1.0 + exp(-out));
+}
+
+int orc_match_pairs(const orc_geom *g, const orc_params *P, const orc_seed *seeds, int ns,
+                    int nv, const float *vx, const float *vy, const float *vz,
+                    const float *vtx, const float *vty, orc_pair *out, int cap) {
+  int n = 0;
+  for (int v = 0; v < nv; ++v)
+    for (int s = 0; s < ns; ++s) {
+      const pair_eval r = eval_pair(P, g, &seeds[s], vx[v], vy[v], vz[v], vtx[v], vty[v], 0);
+      if (!r.ok) continue;
+      if (n < cap) {
+        orc_pair *q = &out[n];
+        q->velo_idx = v;
+        q->seed_idx = s;
+        nn_inputs(&r, &seeds[s], vtx[v], vty[v], q->f);
+        q->gp = P->final_sel == 1 ? orc_ghost_prob(P, q->f) : -1.0;
+      }
+      ++n;
+    }
+  return n;
+}
+
+/* Margin of one rival's part in the network form of the final selection: a
+ * rival t2 (another survivor on the same VELO state or seed) makes t a clone
+ * when t2 is retained (gp2 < cut) and gp - gp2 >= gap.  The distance of that
+ * verdict from flipping, in units of probability (the scale of both the cut
+ * and the gap, which is itself a difference of probabilities): with both
+ * conditions true either flip ends it, with both false both must flip, else
+ * the failing one must. */
+static double rival_flip(double gp, double gp2, double cut, double gap) {
+  const double mc = fabs(gp2 - cut), mg = fabs((gp - gp2) - gap);
+  const int ret = gp2 < cut, far = (gp - gp2) >= gap;
+  if (ret && far) return fmin(mc, mg);
+  if (!ret && !far) return fmax(mc, mg);
+  return ret ? mg : mc;
+}
+
+/* All VELO x seed combinations of one event.  final_sel 0: a combination is
+ * kept when its chi2_match is the smallest both among the survivors sharing
+ * its seed and among those sharing its VELO track (READING of the final clone
+ * removal of Sec. 4.4, with chi2_match in place of the ghost probability).
+ * final_sel 1: the ghost network and the clone rule of Sec. 4.4. */
 static int match_event(const orc_geom *g, const orc_params *P, const orc_seed *seeds, int ns,
                        int nv, const float *vx, const float *vy, const float *vz,
                        const float *vtx, const float *vty, const int32_t *vid, orc_long *out,
@@ -767,11 +837,98 @@ int orc_match(const orc_geom *g, const orc_params *P, const orc_seed *seeds, int
   return match_event(g, P, seeds, ns, nv, vx, vy, vz, vtx, vty, vid, out, cap, NULL, 0);
 }
 
+/* The network form of the final selection (Sec. 4.4): every surviving pair's
+ * ghost probability; pairs below ghost_cut are retained; a retained pair is
+ * dropped as a clone when a retained pair on its VELO state or on its seed has
+ * a ghost probability lower by clone_gap or more. */
+static int match_event_nn(const orc_geom *g, const orc_params *P, const orc_seed *seeds,
+                          int ns, int nv, const float *vx, const float *vy, const float *vz,
+                          const float *vtx, const float *vty, const int32_t *vid,
+                          orc_long *out, int cap, dyn *near, int event) {
+  const int logm = !g_nolog;
+  const double cut = P->ghost_cut, gap = P->clone_gap;
+  const size_t np = (size_t)ns * (size_t)nv;
+  pair_eval *pe = (pair_eval *)malloc(sizeof(pair_eval) * np);
+  double *gp = (double *)malloc(sizeof(double) * np);
+  double *min_v = (double *)malloc(sizeof(double) * (size_t)nv);
+  double *min_s = (double *)malloc(sizeof(double) * (size_t)ns);
+  for (int v = 0; v < nv; ++v) min_v[v] = INFINITY;
+  for (int s = 0; s < ns; ++s) min_s[s] = INFINITY;
+  for (int v = 0; v < nv; ++v)
+    for (int s = 0; s < ns; ++s) {
+      const size_t k = (size_t)v * ns + s;
+      pe[k] = eval_pair(P, g, &seeds[s], vx[v], vy[v], vz[v], vtx[v], vty[v], logm);
+      gp[k] = INFINITY;
+      if (!pe[k].ok) continue;
+      double f[ORC_NN_IN];
+      nn_inputs(&pe[k], &seeds[s], vtx[v], vty[v], f);
+      gp[k] = orc_ghost_prob(P, f);
+      if (gp[k] < cut) {
+        if (gp[k] < min_v[v]) min_v[v] = gp[k];
+        if (gp[k] < min_s[s]) min_s[s] = gp[k];
+      }
+    }
+  int n = 0;
+  for (int v = 0; v < nv; ++v)
+    for (int s = 0; s < ns; ++s) {
+      const size_t k = (size_t)v * ns + s;
+      const pair_eval *r = &pe[k];
+      const double q = gp[k];
+      const int kept = r->ok && q < cut && q - min_v[v] < gap && q - min_s[s] < gap;
+      /* margin: the cut itself, then every rival on the same VELO state or
+       * seed (kept: the closest flip; a clone: the clone-making rivals must
+       * all flip) */
+      double m = r->m;
+      if (r->ok && logm) {
+        const double mcut = fabs(q - cut);
+        if (q >= cut) {
+          m = mcut;
+        } else {
+          double lo = INFINITY, hi = 0.0;
+          for (int pass = 0; pass < 2; ++pass) {
+            const int n2 = pass ? nv : ns;
+            for (int o = 0; o < n2; ++o) {
+              const size_t k2 = pass ? (size_t)o * ns + s : (size_t)v * ns + o;
+              if (k2 == k || !pe[k2].ok) continue;
+              const double f2 = rival_flip(q, gp[k2], cut, gap);
+              lo = fmin(lo, f2);
+              if (gp[k2] < cut && q - gp[k2] >= gap) hi = fmax(hi, f2);
+            }
+          }
+          m = kept ? fmin(mcut, lo) : hi;
+        }
+      }
+      if (!kept) {
+        if (near && logm && m < ORC_NEAR) {
+          orc_near *nq = (orc_near *)dyn_push(near);
+          memset(nq, 0, sizeof(*nq));
+          nq->event = event; nq->kind = 4; nq->velo_idx = v; nq->it = seeds[s].it;
+          nq->margin = m;
+          memcpy(nq->id, seeds[s].id, sizeof(nq->id));
+        }
+        continue;
+      }
+      if (n < cap) {
+        orc_long *L = &out[n];
+        L->velo_idx = v; L->velo_id = vid[v]; L->seed_idx = s; L->pad = 0;
+        L->qop = r->qop; L->chi2 = r->chi2; L->zm = r->zm;
+        L->dx = r->dx; L->dy = r->dy; L->dtx = r->dtx; L->dty = r->dty;
+        L->gp = q;
+        L->margin = fmin(fmin(seeds[s].margin, r->m), m);
+      }
+      ++n;
+    }
+  free(pe); free(gp); free(min_v); free(min_s);
+  return n;
+}
+
 static int match_event(const orc_geom *g, const orc_params *P, const orc_seed *seeds, int ns,
                        int nv, const float *vx, const float *vy, const float *vz,
                        const float *vtx, const float *vty, const int32_t *vid, orc_long *out,
                        int cap, dyn *near, int event) {
   if (ns == 0 || nv == 0) return 0;
+  if (P->final_sel == 1)
+    return match_event_nn(g, P, seeds, ns, nv, vx, vy, vz, vtx, vty, vid, out, cap, near, event);
   const int logm = !g_nolog;
   pair_eval *pe = (pair_eval *)malloc(sizeof(pair_eval) * (size_t)ns * (size_t)nv);
   double *best_v = (double *)malloc(sizeof(double) * (size_t)nv);
@@ -839,6 +996,7 @@ static int match_event(const orc_geom *g, const orc_params *P, const orc_seed *s
         L->velo_idx = v; L->velo_id = vid[v]; L->seed_idx = s; L->pad = 0;
         L->qop = r->qop; L->chi2 = r->chi2; L->zm = r->zm;
         L->dx = r->dx; L->dy = r->dy; L->dtx = r->dtx; L->dty = r->dty;
+        L->gp = -1.0;
         const double sc = fmax(r->chi2, floor_m);
         L->margin = fmin(fmin(seeds[s].margin, r->m),
                          fmin((sec_v[v] - r->chi2) / sc, (sec_s[s] - r->chi2) / sc));

@@ -19,6 +19,19 @@ extern "C" {
 #endif
 
 #define ORC_NL 12
+#define ORC_NN_IN 8
+#define ORC_NN_HID 32
+
+/* Ghost-probability network of the final selection (Sec. 4.4): inputs
+ * z_match, dx, dy, dtx, dty, chi2_match, eta of the VELO state and the
+ * seed's SciFi hit count (in that order), each standardised as
+ * (x - mean) / scale; one hidden layer of ORC_NN_HID rectified units; a
+ * logistic output (READING: the paper gives the layer sizes only). */
+typedef struct {
+  double mean[ORC_NN_IN], scale[ORC_NN_IN];
+  double w1[ORC_NN_HID][ORC_NN_IN], b1[ORC_NN_HID];
+  double w2[ORC_NN_HID], b2;
+} orc_ghost_nn;
 
 typedef struct {
   double z[ORC_NL];      /* nominal layer z [mm] */
@@ -60,11 +73,23 @@ typedef struct {
   int32_t hough_fine;  /* fine bins per kept coarse bin */
   int32_t hough_min;   /* entries a coarse bin needs to be kept */
   int32_t pad2;
+  /* Final selection (Sec. 4.4).  final_sel 0: a surviving pair is kept when
+   * its chi2_match is the lowest among the survivors on its seed and among
+   * those on its VELO state (READING, used without a ghost network).
+   * final_sel 1: pairs with ghost probability < ghost_cut are retained; a
+   * retained track is a clone, and dropped, when another retained track on
+   * its VELO state or on its seed has a ghost probability at least clone_gap
+   * lower. */
+  int32_t final_sel;
+  int32_t pad3;
+  double ghost_cut, clone_gap;
+  orc_ghost_nn ghost_nn;
 } orc_params;
 
 /* Margins.  Every decision that shapes an output is logged with its
  * relative distance from going the other way: |q - cut| / cut for a window
- * or a cut, (second - best) / scale for a closest-hit choice (scale: the
+ * or a cut (for the ghost-probability cut and clone gap of the network form,
+ * the distance in units of probability), (second - best) / scale for a closest-hit choice (scale: the
  * window) or a best-candidate choice (scale: the larger of the best value and
  * 1e-3 of the cut), and the relative score gap to the nearest other score on
  * a shared hit for the clone vote.  A kept track carries the smallest margin
@@ -92,8 +117,18 @@ typedef struct {
 typedef struct {
   int32_t velo_idx, velo_id, seed_idx, pad;
   double qop, chi2, zm, dx, dy, dtx, dty;
+  double gp;                /* ghost probability (final_sel 1), else -1 */
   double margin;            /* smallest margin of its seed's and its matching decisions */
 } orc_long;
+
+/* A VELO-seed pair that passed the preselection and the chi2_match cut, with
+ * the network's inputs (unstandardised) and, for final_sel 1, its ghost
+ * probability (else -1). */
+typedef struct {
+  int32_t velo_idx, seed_idx;
+  double f[ORC_NN_IN];
+  double gp;
+} orc_pair;
 
 /* A near miss: a track or pair that a decision within ORC_NEAR of its
  * threshold rejected.  kind: 1 an x-z candidate (fit or x-hit count), 2 an
@@ -137,6 +172,14 @@ int orc_match(const orc_geom *g, const orc_params *p, const orc_seed *seeds, int
               int nv, const float *vx, const float *vy, const float *vz,
               const float *vtx, const float *vty, const int32_t *vid,
               orc_long *out, int cap);
+/* The pairs of one event that survive the preselection and the chi2_match
+ * cut (the candidates of the final selection), VELO-major; returns their
+ * count, writing at most cap. */
+int orc_match_pairs(const orc_geom *g, const orc_params *p, const orc_seed *seeds, int ns,
+                    int nv, const float *vx, const float *vy, const float *vz,
+                    const float *vtx, const float *vty, orc_pair *out, int cap);
+/* The network's ghost probability for one input vector (unstandardised). */
+double orc_ghost_prob(const orc_params *p, const double f[ORC_NN_IN]);
 
 /* Whole batch; returns 0 on success.  Results are malloc'd; free with
  * orc_free.  log_margins = 0 skips the margin bookkeeping that costs time of

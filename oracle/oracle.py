@@ -32,6 +32,29 @@ class Geom(C.Structure):
     _fields_ = [("z", C.c_double * NL), ("tan_a", C.c_double * NL), ("z_ref", C.c_double)]
 
 
+NN_IN, NN_HID = 8, 32
+
+
+class GhostNN(C.Structure):
+    _fields_ = [("mean", C.c_double * NN_IN), ("scale", C.c_double * NN_IN),
+                ("w1", (C.c_double * NN_IN) * NN_HID), ("b1", C.c_double * NN_HID),
+                ("w2", C.c_double * NN_HID), ("b2", C.c_double)]
+
+
+def set_ghost_nn(nn: GhostNN, w: dict) -> None:
+    """Fill the network from a dict (mean, scale [8]; w1 [32][8]; b1, w2 [32];
+    b2), as stored in the package's ghost_nn.json."""
+    for i in range(NN_IN):
+        nn.mean[i] = float(w["mean"][i])
+        nn.scale[i] = float(w["scale"][i])
+    for j in range(NN_HID):
+        for i in range(NN_IN):
+            nn.w1[j][i] = float(w["w1"][j][i])
+        nn.b1[j] = float(w["b1"][j])
+        nn.w2[j] = float(w["w2"][j])
+    nn.b2 = float(w["b2"])
+
+
 class Params(C.Structure):
     _fields_ = [("p_min", C.c_double), ("invp_a", C.c_double), ("invp_b", C.c_double),
                 ("alpha0", C.c_double), ("alpha1", C.c_double), ("d_ratio", C.c_double),
@@ -48,12 +71,13 @@ class Params(C.Structure):
                 ("tol_tx", C.c_double), ("tol_ty", C.c_double), ("chi2m_max", C.c_double),
                 ("polarity", C.c_double), ("uv_mode", C.c_int32), ("hough_bins", C.c_int32),
                 ("hough_best", C.c_int32), ("hough_fine", C.c_int32), ("hough_min", C.c_int32),
-                ("pad2", C.c_int32)]
+                ("pad2", C.c_int32), ("final_sel", C.c_int32), ("pad3", C.c_int32),
+                ("ghost_cut", C.c_double), ("clone_gap", C.c_double), ("ghost_nn", GhostNN)]
 
     def as_dict(self) -> dict:
         out = {}
         for name, _ in self._fields_:
-            if name.startswith("pad"):
+            if name.startswith("pad") or name == "ghost_nn":
                 continue
             v = getattr(self, name)
             out[name] = list(v) if name == "zm" else v
@@ -75,7 +99,9 @@ SEED_DTYPE = np.dtype([("a", "f8"), ("b", "f8"), ("c", "f8"), ("y0", "f8"), ("ty
 LONG_DTYPE = np.dtype([("velo_idx", "i4"), ("velo_id", "i4"), ("seed_idx", "i4"),
                        ("pad", "i4"), ("qop", "f8"), ("chi2", "f8"), ("zm", "f8"),
                        ("dx", "f8"), ("dy", "f8"), ("dtx", "f8"), ("dty", "f8"),
-                       ("margin", "f8")], align=True)
+                       ("gp", "f8"), ("margin", "f8")], align=True)
+PAIR_DTYPE = np.dtype([("velo_idx", "i4"), ("seed_idx", "i4"), ("f", "f8", NN_IN), ("gp", "f8")],
+                      align=True)
 NEAR_DTYPE = np.dtype([("event", "i4"), ("kind", "i4"), ("velo_idx", "i4"), ("it", "i4"),
                        ("id", "i4", NL), ("margin", "f8")], align=True)
 
@@ -108,6 +134,11 @@ def lib():
         L.orc_match.argtypes = [C.POINTER(Geom), C.POINTER(Params), vp, C.c_int, C.c_int,
                                 vp, vp, vp, vp, vp, vp, vp, C.c_int]
         L.orc_match.restype = C.c_int
+        L.orc_match_pairs.argtypes = [C.POINTER(Geom), C.POINTER(Params), vp, C.c_int, C.c_int,
+                                      vp, vp, vp, vp, vp, vp, C.c_int]
+        L.orc_match_pairs.restype = C.c_int
+        L.orc_ghost_prob.argtypes = [C.POINTER(Params), vp]
+        L.orc_ghost_prob.restype = C.c_double
         L.orc_run.argtypes = [C.POINTER(Geom), C.POINTER(Params), C.c_int] + [vp] * 11 + \
                              [C.c_int, C.c_int, C.POINTER(_Result)]
         L.orc_run.restype = C.c_int
@@ -130,6 +161,8 @@ def default_params(**over) -> Params:
         if k == "zm":
             for i, x in enumerate(v):
                 p.zm[i] = x
+        elif k == "ghost_nn":
+            set_ghost_nn(p.ghost_nn, v)
         else:
             setattr(p, k, v)
     return p
@@ -197,6 +230,28 @@ def match(seeds: np.ndarray, velo: dict, params: Params | None = None,
     out = np.zeros(n, LONG_DTYPE)
     lib().orc_match(*args, _ptr(out), n)
     return out
+
+
+def match_pairs(seeds: np.ndarray, velo: dict, params: Params | None = None,
+                geom: Geom | None = None) -> np.ndarray:
+    """The pairs that pass the preselection and the chi2_match cut, with the
+    network's eight inputs and (final_sel 1) their ghost probability."""
+    params = params or default_params()
+    geom = geom or default_geom()
+    s = _c(seeds, SEED_DTYPE)
+    arr = [_c(velo[k], np.float32) for k in ("x", "y", "z", "tx", "ty")]
+    nv = len(arr[0])
+    args = [C.byref(geom), C.byref(params), _ptr(s), len(s), nv] + [_ptr(a) for a in arr]
+    n = lib().orc_match_pairs(*args, None, 0)
+    out = np.zeros(n, PAIR_DTYPE)
+    lib().orc_match_pairs(*args, _ptr(out), n)
+    return out
+
+
+def ghost_prob(params: Params, f) -> float:
+    x = np.ascontiguousarray(f, np.float64)
+    assert x.shape == (NN_IN,)
+    return float(lib().orc_ghost_prob(C.byref(params), _ptr(x)))
 
 
 class Result:

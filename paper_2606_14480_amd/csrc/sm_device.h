@@ -123,6 +123,12 @@ struct DevParams {
   int match_mode;   // 0: automatic, 1: matching kernel, -1: matching inside the seeding kernel
   float lat_a, lat_b, big_speedup;
   double hough_lo[2], hough_hi[2];
+  // final selection (Sec. 4.4): 0 lowest chi2 of seed and VELO state, 1 the
+  // ghost network (weights as in sm_ghost_nn) and the clone rule
+  int final_sel;
+  double ghost_cut, clone_gap;
+  double nn_mean[SM_NN_INPUTS], nn_scale[SM_NN_INPUTS];
+  double nn_w1[SM_NN_HIDDEN][SM_NN_INPUTS], nn_b1[SM_NN_HIDDEN], nn_w2[SM_NN_HIDDEN], nn_b2;
 };
 
 // An x-z candidate (Sec. 3.2) in per-workgroup scratch.
@@ -212,16 +218,17 @@ size_t smk_seed_big_lds_bytes(int lds_hits);
 extern "C" {
 // Launchers (sm_device.hip); each returns the hipError_t of its launch.
 int smk_launch_prepare(const smk::Desc *d, const smk::KCtx *k, int plain, hipStream_t st);
+// net: the instantiation with the network form of the final selection
+// (final_sel 1); the chi2 form otherwise
 int smk_launch_seed(const smk::Desc *d, const smk::KCtx *k, int item_begin, int item_count,
-                    int use_queue, int grid, int lds_hits, int plain, int uv_mode,
+                    int use_queue, int grid, int lds_hits, int plain, int uv_mode, int net,
                     hipStream_t st);
 // the main form without the matching code, for batches matched by k_match
-// (returns at once otherwise); launched together with smk_launch_seed
 int smk_launch_seed_nomatch(const smk::Desc *d, const smk::KCtx *k, int grid, int lds_hits,
                             hipStream_t st);
 int smk_launch_seed_big(const smk::Desc *d, const smk::KCtx *k, int grid, int lds_hits, int prep,
-                        hipStream_t st);
-int smk_launch_match(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
+                        int net, hipStream_t st);
+int smk_launch_match(const smk::Desc *d, const smk::KCtx *k, int grid, int net, hipStream_t st);
 int smk_seed_big_lds_limit(int bytes);
 int smk_seed_lds_limit(int bytes);   // dynamic LDS allowed to the main seeding forms
 int smk_seed_big_static_lds();   // static LDS of the big form (its dynamic LDS comes on top)

@@ -1224,6 +1224,32 @@ __device__ __forceinline__ PairEval eval_pair(const MState &m, double xv, double
   return r;
 }
 
+// Ghost probability of one surviving pair (Sec. 4.4), FP64: the eight
+// inputs (z_match, dx, dy, dtx, dty, chi2_match, eta of the VELO state, the
+// seed's hit count) standardised, one hidden layer of rectified units, a
+// logistic output.  eta = asinh(1 / tan theta), tan theta = sqrt(tx^2 + ty^2)
+// floored at 1e-9.
+__device__ __forceinline__ double ghost_prob(const PairEval &r, double txv, double tyv,
+                                             int nhits, const DevParams &P) {
+  const double f[SM_NN_INPUTS] = {r.zm, r.dx, r.dy, r.dtx, r.dty, r.chi2,
+                                  asinh(1.0 / fmax(sqrt(txv * txv + tyv * tyv), 1e-9)),
+                                  (double)nhits};
+  double x[SM_NN_INPUTS];
+#pragma unroll
+  for (int i = 0; i < SM_NN_INPUTS; ++i) x[i] = (f[i] - P.nn_mean[i]) / P.nn_scale[i];
+  double out = P.nn_b2;
+  // one hidden unit per trip: unrolled, the 256 weights' loads and products
+  // would hold registers that the rest of the matching kernel needs
+#pragma unroll 1
+  for (int j = 0; j < SM_NN_HIDDEN; ++j) {
+    double h = P.nn_b1[j];
+#pragma unroll
+    for (int i = 0; i < SM_NN_INPUTS; ++i) h += P.nn_w1[j][i] * x[i];
+    out += P.nn_w2[j] * (h > 0.0 ? h : 0.0);
+  }
+  return 1.0 / (1.0 + exp(-out));
+}
+
 // from the seed's x-z parameters and its y line (the only fields read)
 __device__ __forceinline__ MState seed_state(const sm_seed *s, const DevParams &P) {
   MState m;
@@ -1284,8 +1310,10 @@ __global__ __launch_bounds__(256) void k_validate(const Desc *__restrict__ D, co
 // buffers at offsets chained from the previous event; batched: long tracks go
 // to the pool and the seeds stay in theirs until the offsets are known.
 // kSmallM: the event's seeds and VELO states fit the LDS arrays, which the
-// instantiation then addresses as LDS (not through generic pointers).
-template <bool kSmallM, int NT>
+// instantiation then addresses as LDS (not through generic pointers).  kNet:
+// the network form of the final selection (an instantiation of its own, so
+// that the chi2 form carries none of its registers).
+template <bool kSmallM, int NT, bool kNet>
 __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, const Scratch &S,
                                                  const DevParams &P, int e, int plain, size_t wg,
                                                  MatchShared &sh) {
@@ -1465,14 +1493,63 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     if (tid == 0) { raise_flag(cnt, F_SURV); atomicMax(&S.need[6], nsv - kSurvLds); }
     nsv = kSurvLds + S.surv_cap;
   }
-  // final selection: a pair survives if its chi2 is the best of its seed and
-  // of its VELO track
+  // the seed's hit count and the VELO state's slopes, for the network
+  auto nhits_of = [&](int si) {
+    const sm_seed *sd = si < n0 ? &S.pool[b0 + si] : &S.pool[b1 + si - n0];
+    return gmem(sd)->n_x + gmem(sd)->n_uv;
+  };
+  auto pair_of = [&](int vi, int si, double &txv, double &tyv) {
+    const int v = v0 + vi;
+    if (vlds) {
+      txv = sh.vtx[vi]; tyv = sh.vty[vi];
+      return eval_pair(gload(&ms[si]), sh.vx[vi], sh.vy[vi], sh.vz[vi], sh.vtx[vi], sh.vty[vi], P);
+    }
+    txv = gmem(D->b.velo_tx)[v]; tyv = gmem(D->b.velo_ty)[v];
+    return eval_pair(gload(&ms[si]), gmem(D->b.velo_x)[v], gmem(D->b.velo_y)[v],
+                     gmem(D->b.velo_z)[v], txv, tyv, P);
+  };
+  constexpr bool nnsel = kNet;
+  if (nnsel && fits) {
+    // the network form (Sec. 4.4): each survivor's ghost probability replaces
+    // its chi2 in the list; the retained ones (below the cut) give the lowest
+    // ghost probability on each seed and each VELO state
+    for (int i = tid; i < ns; i += NT) best_s[i] = ~0ull;
+    for (int i = tid; i < nv; i += NT) best_v[i] = ~0ull;
+    __syncthreads();
+    for (unsigned i = tid; i < nsv; i += NT) {
+      Surv sv = i < (unsigned)kSurvLds ? sh.surv[i] : gload(&surv[i - kSurvLds]);
+      double txv, tyv;
+      const PairEval pe = pair_of(sv.v, sv.s, txv, tyv);
+      sv.chi2 = ghost_prob(pe, txv, tyv, nhits_of(sv.s), P);
+      if (i < (unsigned)kSurvLds) sh.surv[i] = sv;
+      else gstore(&surv[i - kSurvLds], sv);
+      if (sv.chi2 < P.ghost_cut) {
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(sv.chi2);
+        atomicMin(&best_v[sv.v], bits);
+        atomicMin(&best_s[sv.s], bits);
+      }
+    }
+    __syncthreads();
+  }
+  // final selection.  chi2 form: a pair survives if its chi2 is the best of
+  // its seed and of its VELO track.  Network form: a retained pair survives
+  // unless a retained pair on its seed or its VELO track has a ghost
+  // probability lower by the clone gap or more.
   unsigned long long *kkey =
       nsv <= (unsigned)kSurvLds ? sh.kkey : (unsigned long long *)(surv + S.surv_cap);
   for (unsigned i = tid; i < nsv; i += NT) {
     const Surv sv = i < (unsigned)kSurvLds ? sh.surv[i] : gload(&surv[i - kSurvLds]);
     const unsigned long long bits = (unsigned long long)__double_as_longlong(sv.chi2);
-    if (best_v[sv.v] == bits && best_s[sv.s] == bits) {
+    bool keep;
+    if (nnsel) {
+      const double g = sv.chi2;
+      keep = g < P.ghost_cut &&
+             g - __longlong_as_double((long long)best_v[sv.v]) < P.clone_gap &&
+             g - __longlong_as_double((long long)best_s[sv.s]) < P.clone_gap;
+    } else {
+      keep = best_v[sv.v] == bits && best_s[sv.s] == bits;
+    }
+    if (keep) {
       const unsigned slot = atomicAdd(&sh.nkeep, 1u);
       kkey[slot] = ((unsigned long long)sv.v << 32) | (unsigned)sv.s;
     }
@@ -1508,14 +1585,14 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     if ((long long)(lb + r) >= cap) continue;
     const int vi = (int)(key >> 32), si = (int)(key & 0xffffffffu);
     const int v = v0 + vi;
-    const PairEval pe =
-        vlds ? eval_pair(gload(&ms[si]), sh.vx[vi], sh.vy[vi], sh.vz[vi], sh.vtx[vi], sh.vty[vi], P)
-             : eval_pair(gload(&ms[si]), gmem(D->b.velo_x)[v], gmem(D->b.velo_y)[v],
-                         gmem(D->b.velo_z)[v], gmem(D->b.velo_tx)[v], gmem(D->b.velo_ty)[v], P);
+    double txv, tyv;
+    const PairEval pe = pair_of(vi, si, txv, tyv);
     sm_long L;
     L.velo_idx = vi; L.seed_idx = si; L.velo_id = gmem(D->b.velo_id)[v];
     L.qop = (float)pe.qop; L.chi2 = (float)pe.chi2; L.z_match = (float)pe.zm;
     L.dx = (float)pe.dx; L.dy = (float)pe.dy; L.dtx = (float)pe.dtx; L.dty = (float)pe.dty;
+    L.ghost_prob = nnsel ? (float)ghost_prob(pe, txv, tyv, nhits_of(si), P) : -1.0f;
+    L.pad = 0;
     if (plain) dst[lb + r] = L;
     else gstore(&dst[lb + r], L);
   }
@@ -1524,16 +1601,16 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
 
 // ----------------------------------------------------- the fused kernel ----
 
-template <int NT>
+template <int NT, bool kNet>
 __device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Scratch &S,
                                             const DevParams &P, int e, int plain, size_t wg,
                                             MatchShared &sh) {
   const int ns = S.item_cnt[2 * e] + S.item_cnt[2 * e + 1];
   const int nv = D->b.velo_off[e + 1] - D->b.velo_off[e];
   if (ns <= kMsLds && nv <= kVsLds)
-    match_event_impl<true, NT>(D, S, P, e, plain, wg, sh);
+    match_event_impl<true, NT, kNet>(D, S, P, e, plain, wg, sh);
   else
-    match_event_impl<false, NT>(D, S, P, e, plain, wg, sh);
+    match_event_impl<false, NT, kNet>(D, S, P, e, plain, wg, sh);
 }
 
 // Size class of an item for the longest-first order: kFineSub classes per
@@ -1730,7 +1807,7 @@ __device__ __forceinline__ unsigned prepare_batch(const Desc *__restrict__ D,
 // waves per CU with its own scratch, over the big items (at the head of the
 // order); it runs first, so a big item gets a whole CU instead of holding one
 // 256-thread workgroup for the whole batch.
-template <int kUv, int NT, bool kFuse = true>
+template <int kUv, int NT, bool kFuse = true, bool kNet = false>
 __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *__restrict__ D,
                                                      const KCtx *__restrict__ K, int item_begin,
                                                      int item_count, int use_queue, int lds_hits,
@@ -1909,7 +1986,7 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
     }
     __syncthreads();
     if constexpr (kFuse) {
-      if (s_last) match_event<NT>(D, S, P, item >> 1, plain, wg, mh);
+      if (s_last) match_event<NT, kNet>(D, S, P, item >> 1, plain, wg, mh);
     }
     __syncthreads();
   }
@@ -1921,6 +1998,7 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
 // seeding kernel needs no per-event hand-off (one agent-scope release per
 // item and one acquire per event, each an L2 write-back or invalidate on a
 // chip with one L2 per XCD).
+template <bool kNet>
 __global__ __launch_bounds__(kSeedWG, 4) void k_match(const Desc *__restrict__ D,
                                                       const KCtx *__restrict__ K) {
   const Scratch &S = K->S;
@@ -1938,7 +2016,7 @@ __global__ __launch_bounds__(kSeedWG, 4) void k_match(const Desc *__restrict__ D
     __syncthreads();
     const int e = s_e;
     if (e >= D->n_events) break;
-    match_event<kSeedWG>(D, S, P, e, 0, blockIdx.x, mh);
+    match_event<kSeedWG, kNet>(D, S, P, e, 0, blockIdx.x, mh);
     __syncthreads();
   }
 }
@@ -2095,10 +2173,14 @@ int smk_launch_prepare(const Desc *d, const KCtx *k, int plain, hipStream_t st) 
   return (int)hipGetLastError();
 }
 int smk_launch_seed(const Desc *d, const KCtx *k, int item_begin, int item_count, int use_queue,
-                    int grid, int lds_hits, int plain, int uv_mode, hipStream_t st) {
+                    int grid, int lds_hits, int plain, int uv_mode, int net, hipStream_t st) {
   if (uv_mode == 1)
     hipLaunchKernelGGL((k_seed<1, kSeedWG>), dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits),
                        st, d, k, item_begin, item_count, use_queue, lds_hits, plain, 0);
+  else if (net)
+    hipLaunchKernelGGL((k_seed<0, kSeedWG, true, true>), dim3(grid), dim3(kSeedWG),
+                       smk_seed_lds_bytes(lds_hits), st, d, k, item_begin, item_count, use_queue,
+                       lds_hits, plain, 0);
   else
     hipLaunchKernelGGL((k_seed<0, kSeedWG>), dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits),
                        st, d, k, item_begin, item_count, use_queue, lds_hits, plain, 0);
@@ -2109,14 +2191,21 @@ int smk_launch_seed_nomatch(const Desc *d, const KCtx *k, int grid, int lds_hits
                      smk_seed_lds_bytes(lds_hits), st, d, k, 0, -1, 1, lds_hits, 0, 0);
   return (int)hipGetLastError();
 }
-int smk_launch_seed_big(const Desc *d, const KCtx *k, int grid, int lds_hits, int prep,
+int smk_launch_seed_big(const Desc *d, const KCtx *k, int grid, int lds_hits, int prep, int net,
                         hipStream_t st) {
-  hipLaunchKernelGGL((k_seed<0, kBigWG>), dim3(grid), dim3(kBigWG),
-                     smk_seed_big_lds_bytes(lds_hits), st, d, k, 0, -1, 1, lds_hits, 0, prep);
+  if (net)
+    hipLaunchKernelGGL((k_seed<0, kBigWG, true, true>), dim3(grid), dim3(kBigWG),
+                       smk_seed_big_lds_bytes(lds_hits), st, d, k, 0, -1, 1, lds_hits, 0, prep);
+  else
+    hipLaunchKernelGGL((k_seed<0, kBigWG>), dim3(grid), dim3(kBigWG),
+                       smk_seed_big_lds_bytes(lds_hits), st, d, k, 0, -1, 1, lds_hits, 0, prep);
   return (int)hipGetLastError();
 }
-int smk_launch_match(const Desc *d, const KCtx *k, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_match, dim3(grid), dim3(kSeedWG), sizeof(MatchShared), st, d, k);
+int smk_launch_match(const Desc *d, const KCtx *k, int grid, int net, hipStream_t st) {
+  if (net)
+    hipLaunchKernelGGL(k_match<true>, dim3(grid), dim3(kSeedWG), sizeof(MatchShared), st, d, k);
+  else
+    hipLaunchKernelGGL(k_match<false>, dim3(grid), dim3(kSeedWG), sizeof(MatchShared), st, d, k);
   return (int)hipGetLastError();
 }
 int smk_seed_big_static_lds() {
@@ -2132,13 +2221,18 @@ int smk_seed_lds_limit(int bytes) {
                                    hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<0, kSeedWG, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<0, kSeedWG, true, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<1, kSeedWG, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   return e;
 }
 int smk_seed_big_lds_limit(int bytes) {
-  return (int)hipFuncSetAttribute((const void *)k_seed<0, kBigWG>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  int e = (int)hipFuncSetAttribute((const void *)k_seed<0, kBigWG>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<0, kBigWG, true, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return e;
 }
 int smk_launch_copy(const Desc *d, const KCtx *k, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, st, d, k);

@@ -153,6 +153,19 @@ DevParams make_params(const sm_geometry &g, const sm_params &p) {
   d.hough_best = p.hough_best;
   d.hough_fine = p.hough_fine;
   d.hough_min = p.hough_min;
+  d.final_sel = p.final_sel;
+  d.ghost_cut = p.ghost_cut;
+  d.clone_gap = p.clone_gap;
+  for (int i = 0; i < SM_NN_INPUTS; ++i) {
+    d.nn_mean[i] = p.ghost_nn.mean[i];
+    d.nn_scale[i] = p.ghost_nn.scale[i];
+  }
+  for (int j = 0; j < SM_NN_HIDDEN; ++j) {
+    for (int i = 0; i < SM_NN_INPUTS; ++i) d.nn_w1[j][i] = p.ghost_nn.w1[j][i];
+    d.nn_b1[j] = p.ghost_nn.b1[j];
+    d.nn_w2[j] = p.ghost_nn.w2[j];
+  }
+  d.nn_b2 = p.ghost_nn.b2;
   double zmin = 1e300;
   for (int l = 0; l < smk::kNL; ++l)
     if (g.tan_stereo[l] != 0.0) zmin = std::min(zmin, g.z[l]);
@@ -400,10 +413,11 @@ int enqueue_prepare_big(sm_ctx *c, Slot &s, hipStream_t q) {
   const smk::KCtx *S = s.d_kctx;
   const Desc *d = s.d_desc;
   if (c->p.uv_mode == 0 && !c->cfg.validate)
-    return smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, 1, q);
+    return smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, 1, c->p.final_sel, q);
   int e = smk_launch_prepare(d, S, 0, q);
   if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
-  if (!e && c->p.uv_mode == 0) e = smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, 0, q);
+  if (!e && c->p.uv_mode == 0)
+    e = smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, 0, c->p.final_sel, q);
   return e;
 }
 
@@ -418,8 +432,9 @@ sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
     int e = hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, q);
     if (!e) e = enqueue_prepare_big(c, s, q);
     if (!e && !s.fuse) e = smk_launch_seed_nomatch(d, S, s.grid, s.lds_hits, q);
-    if (!e && s.fuse) e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, q);
-    if (!e && !s.fuse) e = smk_launch_match(d, S, match_grid(c, s.grid), q);
+    if (!e && s.fuse)
+      e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, c->p.final_sel, q);
+    if (!e && !s.fuse) e = smk_launch_match(d, S, match_grid(c, s.grid), c->p.final_sel, q);
     if (!e) e = smk_launch_copy(d, S, 1024, q);
     if (!e) e = hipMemcpyAsync(s.h_cnt, s.S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q);
     return (hipError_t)e;
@@ -452,7 +467,7 @@ sm_status enqueue_plain(sm_ctx *c, Slot &s, int n_events, hipStream_t st) {
   int e = smk_launch_prepare(d, S, 1, st);
   if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, st);
   for (int ev = 0; ev < n_events && !e; ++ev)
-    e = smk_launch_seed(d, S, 2 * ev, 2, 0, 2, s.lds_hits, 1, c->p.uv_mode, st);
+    e = smk_launch_seed(d, S, 2 * ev, 2, 0, 2, s.lds_hits, 1, c->p.uv_mode, c->p.final_sel, st);
   if (!e) e = smk_launch_plain_totals(d, S, st);
   return hip_status((hipError_t)e);
 }
@@ -467,9 +482,10 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   if (!e) e = hipEventRecord(ev[2], q);
   if (!e && !s.fuse) e = smk_launch_seed_nomatch(d, S, s.grid, s.lds_hits, q);
   if (!e) e = hipEventRecord(ev[3], q);
-  if (!e && s.fuse) e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, q);
+  if (!e && s.fuse)
+    e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, c->p.final_sel, q);
   if (!e) e = hipEventRecord(ev[4], q);
-  if (!e && !s.fuse) e = smk_launch_match(d, S, match_grid(c, s.grid), q);
+  if (!e && !s.fuse) e = smk_launch_match(d, S, match_grid(c, s.grid), c->p.final_sel, q);
   if (!e) e = hipEventRecord(ev[5], q);
   if (!e) e = smk_launch_copy(d, S, 1024, q);   // offset scans and copy
   if (!e) e = hipEventRecord(ev[6], q);
@@ -720,7 +736,7 @@ sm_status run_noalloc(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream) {
   if (!e) e = smk_launch_prepare(dd, dk, 0, q);
   if (!e && c->cfg.validate) e = smk_launch_validate(dd, dk, 1024, q);
   if (!e) e = smk_launch_seed_nomatch(dd, dk, kNaWgs, lds, q);
-  if (!e) e = smk_launch_match(dd, dk, kNaWgs, q);
+  if (!e) e = smk_launch_match(dd, dk, kNaWgs, c->p.final_sel, q);
   if (!e) e = smk_launch_copy(dd, dk, 1024, q);
   if (!e) e = hipMemcpyAsync(c->na_cnt, dc, sizeof(Counters), hipMemcpyDeviceToHost, q);
   if (!e) e = hipStreamSynchronize(q);
@@ -802,6 +818,23 @@ void sm_default_params(sm_params *p) {
   p->hough_best = 8;
   p->hough_fine = 4;
   p->hough_min = 2;
+  p->final_sel = 0;      // no network weights are published (reading)
+  p->ghost_cut = 0.8;    // Sec. 4.4
+  p->clone_gap = 0.05;   // Sec. 4.4
+}
+
+// A usable network: every standardisation scale non-zero and every weight
+// finite.
+static bool ghost_nn_ok(const sm_ghost_nn &n) {
+  for (int i = 0; i < SM_NN_INPUTS; ++i)
+    if (!(n.scale[i] != 0.0) || !std::isfinite(n.scale[i]) || !std::isfinite(n.mean[i]))
+      return false;
+  for (int j = 0; j < SM_NN_HIDDEN; ++j) {
+    for (int i = 0; i < SM_NN_INPUTS; ++i)
+      if (!std::isfinite(n.w1[j][i])) return false;
+    if (!std::isfinite(n.b1[j]) || !std::isfinite(n.w2[j])) return false;
+  }
+  return std::isfinite(n.b2);
 }
 
 sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *cfg, sm_ctx **out) {
@@ -817,6 +850,8 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
   if ((c->cfg.seed_wgs != 0 && c->cfg.seed_wgs < 2) ||
       c->p.p_min <= 0 || c->p.sigma_x <= 0 || c->p.min_x_hits < 4 || c->p.min_x_hits > 6 ||
       c->p.min_uv_hits < 3 || c->p.min_uv_hits > 6 ||
+      (c->p.final_sel != 0 && c->p.final_sel != 1) ||
+      (c->p.final_sel == 1 && (!ghost_nn_ok(c->p.ghost_nn) || !(c->p.clone_gap >= 0.0))) ||
       c->p.invp_a * c->p.invp_a + 4.0 * c->p.invp_b / c->p.p_min < 0 ||
       // the Hough-cluster UV kernel (uv_mode 1) is switched off: one run of
       // it under a 5-workgroup context ended in a GPU memory fault whose

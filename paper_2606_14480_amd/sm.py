@@ -44,6 +44,36 @@ class Geometry(C.Structure):
     _fields_ = [("z", C.c_double * NL), ("tan_stereo", C.c_double * NL), ("z_ref", C.c_double)]
 
 
+NN_INPUTS, NN_HIDDEN = 8, 32
+GHOST_NN_PATH = os.path.join(PKG, "ghost_nn.json")
+
+
+class GhostNN(C.Structure):
+    _fields_ = [("mean", C.c_double * NN_INPUTS), ("scale", C.c_double * NN_INPUTS),
+                ("w1", (C.c_double * NN_INPUTS) * NN_HIDDEN), ("b1", C.c_double * NN_HIDDEN),
+                ("w2", C.c_double * NN_HIDDEN), ("b2", C.c_double)]
+
+
+def ghost_nn_weights(path: str = GHOST_NN_PATH) -> dict:
+    """The ghost network's weights shipped with the package (trained on the
+    synthetic generator's truth; the paper publishes none)."""
+    import json
+    with open(path) as f:
+        return json.load(f)
+
+
+def _set_ghost_nn(nn: GhostNN, w: dict) -> None:
+    for i in range(NN_INPUTS):
+        nn.mean[i] = float(w["mean"][i])
+        nn.scale[i] = float(w["scale"][i])
+    for j in range(NN_HIDDEN):
+        for i in range(NN_INPUTS):
+            nn.w1[j][i] = float(w["w1"][j][i])
+        nn.b1[j] = float(w["b1"][j])
+        nn.w2[j] = float(w["w2"][j])
+    nn.b2 = float(w["b2"])
+
+
 class Params(C.Structure):
     _fields_ = [("p_min", C.c_double), ("invp_a", C.c_double), ("invp_b", C.c_double),
                 ("alpha0", C.c_double), ("alpha1", C.c_double), ("d_ratio", C.c_double),
@@ -60,7 +90,8 @@ class Params(C.Structure):
                 ("tol_tx", C.c_double), ("tol_ty", C.c_double), ("chi2m_max", C.c_double),
                 ("polarity", C.c_double), ("uv_mode", C.c_int32), ("hough_bins", C.c_int32),
                 ("hough_best", C.c_int32), ("hough_fine", C.c_int32), ("hough_min", C.c_int32),
-                ("pad2", C.c_int32)]
+                ("pad2", C.c_int32), ("final_sel", C.c_int32), ("pad3", C.c_int32),
+                ("ghost_cut", C.c_double), ("clone_gap", C.c_double), ("ghost_nn", GhostNN)]
 
 
 class Config(C.Structure):
@@ -105,8 +136,9 @@ SEED_DTYPE = np.dtype([("ax", "f4"), ("bx", "f4"), ("cx", "f4"), ("y0", "f4"), (
                        ("hits", "i4", NL)])
 LONG_DTYPE = np.dtype([("velo_idx", "i4"), ("seed_idx", "i4"), ("velo_id", "i4"),
                        ("qop", "f4"), ("chi2", "f4"), ("z_match", "f4"), ("dx", "f4"),
-                       ("dy", "f4"), ("dtx", "f4"), ("dty", "f4")])
-assert SEED_DTYPE.itemsize == 96 and LONG_DTYPE.itemsize == 40
+                       ("dy", "f4"), ("dtx", "f4"), ("dty", "f4"), ("ghost_prob", "f4"),
+                       ("pad", "i4")])
+assert SEED_DTYPE.itemsize == 96 and LONG_DTYPE.itemsize == 48
 
 _lib = C.CDLL(LIB_PATH)
 _P = C.POINTER
@@ -157,14 +189,20 @@ def default_geometry() -> Geometry:
 
 
 def default_params(**over) -> Params:
+    """The library's defaults with fields replaced.  ghost_nn takes a dict of
+    weights; final_sel=1 without ghost_nn takes the package's weights."""
     p = Params()
     _lib.sm_default_params(C.byref(p))
     for k, v in over.items():
         if k == "zm":
             for i, x in enumerate(v):
                 p.zm[i] = x
+        elif k == "ghost_nn":
+            _set_ghost_nn(p.ghost_nn, v)
         else:
             setattr(p, k, v)
+    if over.get("final_sel") == 1 and "ghost_nn" not in over:
+        _set_ghost_nn(p.ghost_nn, ghost_nn_weights())
     return p
 
 

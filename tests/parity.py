@@ -22,7 +22,8 @@ SEED_FIELDS = [("a", "ax", 1e-4, 1e-3), ("b", "bx", 1e-4, 1e-7), ("c", "cx", 1e-
                ("chi2x", "chi2_x", 1e-4, 1e-3), ("chi2y", "chi2_y", 1e-4, 1e-3)]
 LONG_FIELDS = [("qop", "qop", 1e-4, 1e-10), ("chi2", "chi2", 1e-4, 1e-3),
                ("zm", "z_match", 1e-4, 1e-2), ("dx", "dx", 1e-4, 2e-3),
-               ("dy", "dy", 1e-4, 2e-2), ("dtx", "dtx", 1e-4, 1e-6), ("dty", "dty", 1e-4, 1e-6)]
+               ("dy", "dy", 1e-4, 2e-2), ("dtx", "dtx", 1e-4, 1e-6), ("dty", "dty", 1e-4, 1e-6),
+               ("gp", "ghost_prob", 1e-4, 1e-4)]
 
 MARGIN = 1e-4
 

@@ -430,3 +430,62 @@ def test_validating_sequence_equals_default(sm, ctx):
             assert x.tobytes() == y.tobytes()
     finally:
         c.close()
+
+
+def _ghost_random_net(orc, b, loose):
+    """A random network standardised by the surviving pairs' own spread (from
+    the oracle), with small output weights: probabilities fall on both sides
+    of the cut and close to each other, so that many cut and clone decisions
+    occur."""
+    p = orc.default_params(**loose)
+    r0 = orc.run(b, params=p, threads=8)
+    F = []
+    for e in range(b.n_events):
+        v0, v1 = int(b.velo_off[e]), int(b.velo_off[e + 1])
+        velo = {"x": b.velo_x[v0:v1], "y": b.velo_y[v0:v1], "z": b.velo_z[v0:v1],
+                "tx": b.velo_tx[v0:v1], "ty": b.velo_ty[v0:v1]}
+        F.append(orc.match_pairs(r0.event_seeds(e), velo, params=p)["f"])
+    F = np.concatenate(F)
+    rng = np.random.default_rng(11)
+    return {"mean": F.mean(0).tolist(), "scale": F.std(0).tolist(),
+            "w1": rng.normal(0, 1, (32, 8)).tolist(), "b1": rng.normal(0, 0.5, 32).tolist(),
+            "w2": rng.normal(0, 0.125, 32).tolist(), "b2": 0.5}
+
+
+@pytest.mark.parametrize("net", ["shipped", "random"])
+def test_ghost_network_selection(orc, sm, ctx, net):
+    """The network form of the final selection (Sec. 4.4) against the oracle:
+    the shipped weights on 300 min-bias events, and a random network under
+    loose matching cuts (thousands of cut and clone decisions) on 100 events.
+    Long tracks and their ghost probabilities agree; the batched and the
+    per-event forms give the same bytes."""
+    if net == "shipped":
+        b = ev.generate(ev.config(2, n_events=300))
+        over = dict(final_sel=1, ghost_nn=sm.ghost_nn_weights())
+    else:
+        b = ev.generate(ev.config(2, n_events=100))
+        loose = dict(chi2m_max=500.0, max_dx=200.0, max_dy=600.0, max_dty=0.08)
+        over = dict(final_sel=1, ghost_nn=_ghost_random_net(orc, b, loose), **loose)
+    c = sm.Context(params=sm.default_params(**over))
+    try:
+        g, o, st = check(orc, sm, c, b, f"ghost network ({net})", params_over=over)
+        assert st["longs_common"] > 10000 if net == "shipped" else st["longs_common"] > 1000
+        dmax = 0.0
+        for e in range(b.n_events):
+            osd, old = PT.event_sets(o.seed_off, o.seeds, o.long_off, o.longs, e, "id")
+            gsd, gld = PT.event_sets(g[0], g[1], g[2], g[3], e, "hits")
+            for k in old.keys() & gld.keys():
+                dmax = max(dmax, abs(float(old[k]["gp"]) - float(gld[k]["ghost_prob"])))
+        say(f"[gpu] ghost network ({net}): largest ghost-probability difference {dmax:.3g}")
+        gp = g[3]["ghost_prob"]
+        assert np.all((gp >= 0) & (gp < 0.8))
+        gpl = gpu_run(sm, c, b, plain=True)
+        for x, y in zip(g, gpl):
+            assert x.tobytes() == y.tobytes()
+    finally:
+        c.close()
+    if net == "shipped":
+        # the chi2 form keeps at most one track per VELO state and seed; the
+        # network form may keep near-equal pairs on one segment
+        ref = gpu_run(sm, ctx, b)
+        assert np.all(ref[3]["ghost_prob"] == -1.0)

@@ -29,7 +29,8 @@ def test_exports_every_declared_symbol():
 def test_struct_layouts():
     from paper_2606_14480_amd import sm
     assert sm.SEED_DTYPE.itemsize == 96
-    assert sm.LONG_DTYPE.itemsize == 40
+    assert sm.LONG_DTYPE.itemsize == 48
+    assert ctypes.sizeof(sm.GhostNN) == 8 * (8 + 8 + 32 * 8 + 32 + 32 + 1)
     assert ctypes.sizeof(sm.Batch) == 8 + 16 + 11 * 8
     assert ctypes.sizeof(sm.Out) == 64
 
@@ -43,6 +44,8 @@ def test_defaults_agree_with_oracle(orc):
         a, b = getattr(p, name), getattr(q, name)
         if name == "zm":
             assert list(a) == list(b)
+        elif name == "ghost_nn":
+            assert bytes(a) == bytes(b)
         else:
             assert a == b, name
     g, h = sm.default_geometry(), orc.default_geom()
@@ -83,6 +86,23 @@ def test_create_rejects_bad_uv_settings():
         assert not h.value
 
 
+def test_create_rejects_bad_final_selection():
+    """final_sel outside {0, 1}, or the network form with an unusable network
+    (a zero standardisation scale, a non-finite weight), is refused before any
+    device call."""
+    from paper_2606_14480_amd import sm
+    lib = sm.lib()
+    w = sm.ghost_nn_weights()
+    zero_scale = dict(w, scale=[0.0] * 8)
+    nan_w = dict(w, b2=float("nan"))
+    for over in (dict(final_sel=2), dict(final_sel=-1), dict(final_sel=1, ghost_nn=zero_scale),
+                 dict(final_sel=1, ghost_nn=nan_w), dict(final_sel=1, clone_gap=-0.1)):
+        p = sm.default_params(**over)
+        h = ctypes.c_void_p()
+        assert lib.sm_create(None, ctypes.byref(p), None, ctypes.byref(h)) == sm.ERR_INVALID, over
+        assert not h.value
+
+
 def test_binding_structs_match_header(tmp_path):
     """Every ctypes mirror in the binding has the size and field offsets of
     its C struct in include/sm.h (compiled here with the host compiler)."""
@@ -91,7 +111,8 @@ def test_binding_structs_match_header(tmp_path):
 
     from paper_2606_14480_amd import sm
     pairs = {"sm_geometry": sm.Geometry, "sm_params": sm.Params, "sm_config": sm.Config,
-             "sm_batch": sm.Batch, "sm_kernel_times": sm.KernelTimes, "sm_out": sm.Out}
+             "sm_batch": sm.Batch, "sm_kernel_times": sm.KernelTimes, "sm_out": sm.Out,
+             "sm_ghost_nn": sm.GhostNN}
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "sm.h"', "int main(void) {"]
     for cname, py in pairs.items():

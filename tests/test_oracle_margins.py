@@ -37,10 +37,11 @@ def as_gpu(res):
     L = res.longs
     longs = np.zeros(len(L), dtype=[("velo_idx", "i4"), ("seed_idx", "i4"), ("velo_id", "i4"),
                                     ("qop", "f8"), ("chi2", "f8"), ("z_match", "f8"), ("dx", "f8"),
-                                    ("dy", "f8"), ("dtx", "f8"), ("dty", "f8")])
+                                    ("dy", "f8"), ("dtx", "f8"), ("dty", "f8"),
+                                    ("ghost_prob", "f8")])
     for a, b in (("velo_idx", "velo_idx"), ("seed_idx", "seed_idx"), ("velo_id", "velo_id"),
                  ("qop", "qop"), ("chi2", "chi2"), ("z_match", "zm"), ("dx", "dx"), ("dy", "dy"),
-                 ("dtx", "dtx"), ("dty", "dty")):
+                 ("dtx", "dtx"), ("dty", "dty"), ("ghost_prob", "gp")):
         longs[a] = L[b]
     return res.seed_off, seeds, res.long_off, longs
 
@@ -142,3 +143,40 @@ def test_closest_hit_tie_has_a_small_margin(orc):
     # 1e-3 mm over the 1 mm window
     k = [r for r in o2.seeds if h in r["pos"] or ins in r["pos"]]
     assert k and min(float(r["margin"]) for r in k) < 2e-3
+
+
+@pytest.mark.parametrize("eps", [9e-5, -9e-5])
+def test_log_explains_network_selection_flips(orc, eps):
+    """The network form of the final selection (Sec. 4.4): moving the ghost
+    cut or the clone gap by less than 1e-4 changes long tracks only where the
+    log puts a decision that close.  A random network under loose matching
+    cuts makes thousands of cut and clone decisions, so some do move."""
+    import test_oracle_ghost as G
+    b = ev.generate_parallel(ev.config(2, n_events=200), 8)
+    loose = dict(chi2m_max=500.0, max_dx=200.0, max_dy=600.0, max_dty=0.08)
+    p0 = orc.default_params(**loose)
+    r0 = orc.run(b, p0, threads=8)
+    F = np.concatenate([orc.match_pairs(r0.event_seeds(e), G._velo(b, e), params=p0)["f"]
+                        for e in range(b.n_events)])
+    w = dict(G._random_net(11, spread=0.5), mean=F.mean(0).tolist(), scale=F.std(0).tolist(),
+             b2=0.5)
+    over = dict(final_sel=1, ghost_nn=w, **loose)
+    o = orc.run(b, orc.default_params(**over), threads=8)
+    moved = 0
+    for name in ("ghost_cut", "clone_gap"):
+        p = orc.default_params(**over)
+        setattr(p, name, getattr(p, name) * (1.0 + eps))
+        r = orc.run(b, p, threads=8)
+        ev_diff = differing_events(o, r, b.n_events)
+        if not ev_diff:
+            continue
+        st = PT.compare(o, as_gpu(r), b.n_events, events=ev_diff)
+        moved += st["mismatches"]
+        assert not st["unexplained"], (name, st["unexplained"][:5])
+    # and a move far outside the band is not excused
+    p = orc.default_params(**over)
+    p.clone_gap *= 1.05
+    r = orc.run(b, p, threads=8)
+    st = PT.compare(o, as_gpu(r), b.n_events, events=differing_events(o, r, b.n_events))
+    assert st["mismatches"] > 0 and st["unexplained"]
+    assert moved > 0, "no decision moved: the check would be vacuous"
