@@ -37,6 +37,8 @@ WORKLOADS = {
               "[20, 3000], 5% inefficiency, 20% noise hits",
     "ghost": "minbias-{n} with the network form of the final selection (Sec. 4.4: ghost "
              "probability < 0.8, clone gap 0.05; weights trained on the generator's truth)",
+    "ut": "minbias-{n} with the UT hit search (Sec. 4.3; a synthetic four-layer UT, about 500 "
+          "UT hits per event; more than two UT hits per long track)",
 }
 
 
@@ -266,9 +268,9 @@ def main():
                     help="min-bias events in the serving pool (requests are 1..this many)")
     ap.add_argument("--serve-plain", type=int, default=20,
                     help="requests of the 0.8 stream also run through the plain form")
-    ap.add_argument("--legs", default="uneven,stress,ghost",
+    ap.add_argument("--legs", default="uneven,stress,ghost,ut",
                     help="further workloads at their stated sizes, timed beside the headline "
-                         "(comma list of uneven, stress, ghost; empty: none)")
+                         "(comma list of uneven, stress, ghost, ut; empty: none)")
     ap.add_argument("--leg-steps", type=int, default=5)
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes generating the synthetic events")
@@ -292,7 +294,8 @@ def main():
     t0 = time.perf_counter()
     host = gen(ev.config(wl, n_events=args.events or None))
     legs = [x for x in args.legs.split(",") if x and x != args.workload]
-    leg_hosts = {x: gen(ev.config({"uneven": 3, "stress": 4}[x])) for x in legs if x != "ghost"}
+    leg_hosts = {x: gen(ev.config({"uneven": 3, "stress": 4}[x])) for x in legs
+                 if x not in ("ghost", "ut")}
     pool = gen(ev.config(5, n_events=args.serve_pool)) \
         if args.serve_requests > 0 and args.workload == "minbias" else None
     log(f"[bench] generated {host.n_events} events, {host.n_hits} hits, {host.n_velo} VELO "
@@ -353,15 +356,16 @@ def main():
     # further workloads at their stated sizes (uneven: all events against the
     # oracle; stress: events 0-499)
     leg_res = {}
-    if "ghost" in legs and args.workload == "minbias":
-        # the headline batch again, through a context with the network form
-        g_over = dict(over, final_sel=1)
+    # the headline batch again, through a context with the network form of
+    # the final selection, and one with the UT search
+    for name, g_over in (("ghost", dict(over, final_sel=1)), ("ut", dict(over, ut_mode=1))):
+        if name not in legs or args.workload != "minbias":
+            continue
         gctx = sm.Context(params=sm.default_params(**g_over))
+        o_over = dict(g_over, ghost_nn=sm.ghost_nn_weights()) if name == "ghost" else g_over
         try:
-            leg_res["ghost"] = extra_leg(
-                gctx, sm, "ghost", host, args.leg_steps, 1,
-                0 if args.no_parity else host.n_events,
-                dict(g_over, ghost_nn=sm.ghost_nn_weights()))
+            leg_res[name] = extra_leg(gctx, sm, name, host, args.leg_steps, 1,
+                                      0 if args.no_parity else host.n_events, o_over)
         finally:
             gctx.close()
     for name, lh in leg_hosts.items():

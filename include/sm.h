@@ -32,6 +32,7 @@ extern "C" {
 
 #define SM_N_LAYERS 12
 #define SM_ZONES_PER_EVENT 24
+#define SM_N_UT 4   /* UT layers UTaX, UTaU, UTbV, UTbX */
 
 typedef enum {
   SM_OK = 0,
@@ -54,6 +55,11 @@ typedef struct {
   double z[SM_N_LAYERS];
   double tan_stereo[SM_N_LAYERS];
   double z_ref;
+  /* UT (Sec. 4.3): z of the four layers and tan of their stereo angles (a
+   * stereo hit measures x - y tan(alpha)); the paper prints neither, the
+   * defaults are 2327.5, 2372.5, 2597.5, 2642.5 mm and 0, +tan 5, -tan 5, 0 */
+  double ut_z[SM_N_UT];
+  double ut_tan[SM_N_UT];
 } sm_geometry;
 
 /* Ghost-probability network of the final selection (Sec. 4.4).  Inputs, in
@@ -132,6 +138,22 @@ typedef struct {
   double ghost_cut;        /* 0.8 */
   double clone_gap;        /* 0.05 */
   sm_ghost_nn ghost_nn;    /* read when final_sel = 1 */
+  /* UT hit search, Sec. 4.3.  ut_mode 0 (default): off.  ut_mode 1: every
+   * pair that passed the preselection and the chi2_match cut is extrapolated
+   * from its VELO state with eq. velo_ut_extrapolation, gamma_x = a_gamma +
+   * b_gamma q/p (eq. gamma_parametrisation; q/p of the pair, 1/MeV).  Layer
+   * by layer it takes the closest hit in the loose window until one is
+   * found, which refits gamma_x so that the parabola passes through it, then
+   * the closest hit in the tight window of each later layer.  A pair with
+   * fewer than ut_min_hits UT hits leaves the candidates before the final
+   * selection.  Windows (Table 2): min(max(a + b / p, lo), hi), p in GeV/c,
+   * per layer; hi = 0 marks a layer without that window.  The batch must then
+   * carry UT hits (sm_batch.ut_off non-NULL), else SM_ERR_INVALID. */
+  int32_t ut_mode;
+  int32_t ut_min_hits;     /* 3 ("more than two"), 1..4 */
+  double a_gamma, b_gamma; /* Table 1: 7.707063e-11, -7.817364e-3 */
+  double ut_loose_a[SM_N_UT], ut_loose_b[SM_N_UT], ut_loose_lo[SM_N_UT], ut_loose_hi[SM_N_UT];
+  double ut_tight_a[SM_N_UT], ut_tight_b[SM_N_UT], ut_tight_lo[SM_N_UT], ut_tight_hi[SM_N_UT];
 } sm_params;
 
 /* Library resources; zero fields take defaults. */
@@ -171,6 +193,14 @@ typedef struct {
   const int32_t *velo_off; /* [n_events + 1] */
   const float *velo_x, *velo_y, *velo_z, *velo_tx, *velo_ty;
   const int32_t *velo_id;
+  /* UT hits (Sec. 4.3), read only with ut_mode 1; NULL when there are none.
+   * Hits of event e, layer l (0..3: UTaX, UTaU, UTbV, UTbX) occupy
+   * [ut_off[e*4 + l], ut_off[e*4 + l + 1]), x-sorted ascending; ut_x is the
+   * measured coordinate (x - y tan(alpha) on stereo layers). */
+  int64_t n_ut;            /* = ut_off[n_events*4] */
+  const int32_t *ut_off;   /* [n_events*4 + 1], non-decreasing, ut_off[0] = 0 */
+  const float *ut_x;
+  const int32_t *ut_id;    /* caller's id, reported back in long tracks */
 } sm_batch;
 
 /* A T-track (Sec. 3): x(z) = ax + bx u + cx u^2 (1 + d_ratio u) and
@@ -195,8 +225,9 @@ typedef struct {
   float z_match;          /* eq. z_match */
   float dx, dy, dtx, dty; /* matching residuals */
   float ghost_prob;       /* final_sel 1: the network's ghost probability; else -1 */
-  int32_t pad;
-} sm_long;                /* 48 bytes */
+  int32_t n_ut;           /* ut_mode 1: UT hits attached; else 0 */
+  int32_t ut_hits[SM_N_UT]; /* their ut_id per layer, -1 where none */
+} sm_long;                /* 64 bytes */
 
 /* Outputs, caller-allocated on the device.  Seeds of event e are
  * seeds[seed_off[e] .. seed_off[e+1]) in canonical order (half, iteration,

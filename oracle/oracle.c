@@ -40,6 +40,12 @@ void orc_default_geom(orc_geom *g) {
     g->tan_a[l] = kind == 1 ? t5 : (kind == 2 ? -t5 : 0.0);
   }
   g->z_ref = 8525.0; /* Sec. 3.1 */
+  /* READING: UT layer positions and stereo angles (the paper gives none) */
+  static const double uz[ORC_NUT] = {2327.5, 2372.5, 2597.5, 2642.5};
+  for (int i = 0; i < ORC_NUT; ++i) {
+    g->ut_z[i] = uz[i];
+    g->ut_tan[i] = (i == 1) ? t5 : (i == 2 ? -t5 : 0.0);
+  }
 }
 
 void orc_default_params(orc_params *p) {
@@ -90,6 +96,26 @@ void orc_default_params(orc_params *p) {
   p->final_sel = 0;           /* READING: no network weights are published */
   p->ghost_cut = 0.8;         /* Sec. 4.4: ghost probability < 0.8 */
   p->clone_gap = 0.05;        /* Sec. 4.4: clone if at least 0.05 higher */
+  p->ut_mode = 0;             /* Sec. 4.3: UT hits are optional */
+  p->ut_min_hits = 3;         /* Sec. 4.3: more than two UT hits */
+  p->a_gamma = 7.707063e-11;  /* Table 1 */
+  p->b_gamma = -7.817364e-3;
+  /* Table 2, layers UTaX, UTaU, UTbV, UTbX; no loose window is printed for
+   * UTbX and no tight one for UTaX (hi = 0) */
+  static const double la[ORC_NUT] = {0.8333, 0.8333, 1.3333, 0.0};
+  static const double lb[ORC_NUT] = {3.3333, 3.3333, 3.3333, 0.0};
+  static const double llo[ORC_NUT] = {1.2, 1.2, 1.5, 0.0};
+  static const double lhi[ORC_NUT] = {8.5, 8.5, 9.5, 0.0};
+  static const double ta[ORC_NUT] = {0.0, 0.2, 0.4, 0.4};
+  static const double tb[ORC_NUT] = {0.0, 0.6, 1.2, 1.2};
+  static const double tlo[ORC_NUT] = {0.0, 0.5, 1.0, 1.0};
+  static const double thi[ORC_NUT] = {0.0, 2.0, 4.0, 4.0};
+  for (int i = 0; i < ORC_NUT; ++i) {
+    p->ut_loose_a[i] = la[i]; p->ut_loose_b[i] = lb[i];
+    p->ut_loose_lo[i] = llo[i]; p->ut_loose_hi[i] = lhi[i];
+    p->ut_tight_a[i] = ta[i]; p->ut_tight_b[i] = tb[i];
+    p->ut_tight_lo[i] = tlo[i]; p->ut_tight_hi[i] = thi[i];
+  }
 }
 
 /* ---------------------------------------------------------- helpers ----- */
@@ -701,7 +727,82 @@ typedef struct {
   double chi2, zm, dx, dy, dtx, dty, qop;
   int ok;
   double m;   /* accepted: smallest margin of its cuts; rejected: margin to acceptance */
+  int n_ut;
+  int32_t ut_id[ORC_NUT];
 } pair_eval;
+
+/* One event's UT hits: layer offsets [5] into x and id (NULL off: none). */
+typedef struct {
+  const int32_t *off;
+  const float *x;
+  const int32_t *id;
+} ut_event;
+
+/* UT hit search of one pair (Sec. 4.3).  gamma_x starts from eq.
+ * gamma_parametrisation with the pair's q/p.  Layer by layer, the VELO state
+ * is extrapolated with eq. velo_ut_extrapolation (z_ref: the state's z) and
+ * compared in the layer's measured coordinate x - y tan(alpha).  Until a hit
+ * is found, the loose window of the layer is searched (layers without one are
+ * passed over); the closest hit inside is attached, and gamma_x is refitted
+ * so that the trajectory goes through it (READING: the text does not say how
+ * several hits in the window refine gamma_x; the closest one is used).  In
+ * every later layer the closest hit inside the tight window is attached.
+ * Windows are inclusive, ties as for SciFi hits.  Returns the number of hits
+ * attached; *margin: the smallest closest-hit margin of the layers searched. */
+double orc_ut_window(const orc_params *P, int layer, int tight, double qop) {
+  const double a = tight ? P->ut_tight_a[layer] : P->ut_loose_a[layer];
+  const double b = tight ? P->ut_tight_b[layer] : P->ut_loose_b[layer];
+  const double lo = tight ? P->ut_tight_lo[layer] : P->ut_loose_lo[layer];
+  const double hi = tight ? P->ut_tight_hi[layer] : P->ut_loose_hi[layer];
+  if (!(hi > 0.0)) return 0.0;
+  return fmin(fmax(a + b * 1000.0 * fabs(qop), lo), hi);   /* B / p, p in GeV/c */
+}
+
+static int ut_search(const orc_geom *g, const orc_params *P, const ut_event *ut, double xv,
+                     double yv, double zv, double txv, double tyv, double qop,
+                     int32_t ids[ORC_NUT], double *margin) {
+  double gam = P->a_gamma + P->b_gamma * qop;
+  int loose = 1, n = 0;
+  double m = INFINITY;
+  for (int i = 0; i < ORC_NUT; ++i) ids[i] = -1;
+  if (!ut->off) { *margin = m; return 0; }
+  for (int i = 0; i < ORC_NUT; ++i) {
+    const double w = orc_ut_window(P, i, !loose, qop);
+    if (!(w > 0.0)) continue;
+    const double dz = g->ut_z[i] - zv;
+    const double yp = yv + tyv * dz;
+    const double mp = xv + txv * dz + gam * dz * dz - yp * g->ut_tan[i];
+    const int h = closest_in_window(ut->x, ut->off[i], ut->off[i + 1], mp, w);
+    if (!g_nolog) m = fmin(m, closest_margin(ut->x, ut->off[i], ut->off[i + 1], mp, w, h));
+    if (h < 0) continue;
+    ids[i] = ut->id[h];
+    ++n;
+    if (loose) {
+      const double xh = (double)ut->x[h] + yp * g->ut_tan[i];
+      gam = (xh - xv - txv * dz) / (dz * dz);
+      loose = 0;
+    }
+  }
+  *margin = m;
+  return n;
+}
+
+/* A pair that passed the chi2_match cut also needs its UT hits (ut_mode 1):
+ * with fewer than ut_min_hits it leaves the candidates. */
+static void apply_ut(const orc_geom *g, const orc_params *P, const ut_event *ut, double xv,
+                     double yv, double zv, double txv, double tyv, pair_eval *r) {
+  r->n_ut = 0;
+  for (int i = 0; i < ORC_NUT; ++i) r->ut_id[i] = -1;
+  if (!r->ok || P->ut_mode != 1) return;
+  double m;
+  r->n_ut = ut_search(g, P, ut, xv, yv, zv, txv, tyv, r->qop, r->ut_id, &m);
+  if (r->n_ut < P->ut_min_hits) {
+    r->ok = 0;
+    r->m = m;
+  } else {
+    r->m = fmin(r->m, m);
+  }
+}
 
 /* One VELO-seed combination (Sec. 4.1, 4.2). */
 static pair_eval eval_pair(const orc_params *P, const orc_geom *g, const orc_seed *s,
@@ -788,11 +889,14 @@ double orc_ghost_prob(const orc_params *P, const double f[ORC_NN_IN]) {
 
 int orc_match_pairs(const orc_geom *g, const orc_params *P, const orc_seed *seeds, int ns,
                     int nv, const float *vx, const float *vy, const float *vz,
-                    const float *vtx, const float *vty, orc_pair *out, int cap) {
+                    const float *vtx, const float *vty, const int32_t *ut_off,
+                    const float *ut_x, const int32_t *ut_id, orc_pair *out, int cap) {
+  const ut_event ut = {ut_off, ut_x, ut_id};
   int n = 0;
   for (int v = 0; v < nv; ++v)
     for (int s = 0; s < ns; ++s) {
-      const pair_eval r = eval_pair(P, g, &seeds[s], vx[v], vy[v], vz[v], vtx[v], vty[v], 0);
+      pair_eval r = eval_pair(P, g, &seeds[s], vx[v], vy[v], vz[v], vtx[v], vty[v], 0);
+      apply_ut(g, P, &ut, vx[v], vy[v], vz[v], vtx[v], vty[v], &r);
       if (!r.ok) continue;
       if (n < cap) {
         orc_pair *q = &out[n];
@@ -828,13 +932,15 @@ static double rival_flip(double gp, double gp2, double cut, double gap) {
  * final_sel 1: the ghost network and the clone rule of Sec. 4.4. */
 static int match_event(const orc_geom *g, const orc_params *P, const orc_seed *seeds, int ns,
                        int nv, const float *vx, const float *vy, const float *vz,
-                       const float *vtx, const float *vty, const int32_t *vid, orc_long *out,
-                       int cap, dyn *near, int event);
+                       const float *vtx, const float *vty, const int32_t *vid,
+                       const ut_event *ut, orc_long *out, int cap, dyn *near, int event);
 
 int orc_match(const orc_geom *g, const orc_params *P, const orc_seed *seeds, int ns, int nv,
               const float *vx, const float *vy, const float *vz, const float *vtx,
-              const float *vty, const int32_t *vid, orc_long *out, int cap) {
-  return match_event(g, P, seeds, ns, nv, vx, vy, vz, vtx, vty, vid, out, cap, NULL, 0);
+              const float *vty, const int32_t *vid, const int32_t *ut_off, const float *ut_x,
+              const int32_t *ut_id, orc_long *out, int cap) {
+  const ut_event ut = {ut_off, ut_x, ut_id};
+  return match_event(g, P, seeds, ns, nv, vx, vy, vz, vtx, vty, vid, &ut, out, cap, NULL, 0);
 }
 
 /* The network form of the final selection (Sec. 4.4): every surviving pair's
@@ -844,7 +950,7 @@ int orc_match(const orc_geom *g, const orc_params *P, const orc_seed *seeds, int
 static int match_event_nn(const orc_geom *g, const orc_params *P, const orc_seed *seeds,
                           int ns, int nv, const float *vx, const float *vy, const float *vz,
                           const float *vtx, const float *vty, const int32_t *vid,
-                          orc_long *out, int cap, dyn *near, int event) {
+                          const ut_event *ut, orc_long *out, int cap, dyn *near, int event) {
   const int logm = !g_nolog;
   const double cut = P->ghost_cut, gap = P->clone_gap;
   const size_t np = (size_t)ns * (size_t)nv;
@@ -858,6 +964,7 @@ static int match_event_nn(const orc_geom *g, const orc_params *P, const orc_seed
     for (int s = 0; s < ns; ++s) {
       const size_t k = (size_t)v * ns + s;
       pe[k] = eval_pair(P, g, &seeds[s], vx[v], vy[v], vz[v], vtx[v], vty[v], logm);
+      apply_ut(g, P, ut, vx[v], vy[v], vz[v], vtx[v], vty[v], &pe[k]);
       gp[k] = INFINITY;
       if (!pe[k].ok) continue;
       double f[ORC_NN_IN];
@@ -910,7 +1017,8 @@ static int match_event_nn(const orc_geom *g, const orc_params *P, const orc_seed
       }
       if (n < cap) {
         orc_long *L = &out[n];
-        L->velo_idx = v; L->velo_id = vid[v]; L->seed_idx = s; L->pad = 0;
+        L->velo_idx = v; L->velo_id = vid[v]; L->seed_idx = s; L->n_ut = r->n_ut;
+        memcpy(L->ut_id, r->ut_id, sizeof(L->ut_id));
         L->qop = r->qop; L->chi2 = r->chi2; L->zm = r->zm;
         L->dx = r->dx; L->dy = r->dy; L->dtx = r->dtx; L->dty = r->dty;
         L->gp = q;
@@ -924,11 +1032,12 @@ static int match_event_nn(const orc_geom *g, const orc_params *P, const orc_seed
 
 static int match_event(const orc_geom *g, const orc_params *P, const orc_seed *seeds, int ns,
                        int nv, const float *vx, const float *vy, const float *vz,
-                       const float *vtx, const float *vty, const int32_t *vid, orc_long *out,
-                       int cap, dyn *near, int event) {
+                       const float *vtx, const float *vty, const int32_t *vid,
+                       const ut_event *ut, orc_long *out, int cap, dyn *near, int event) {
   if (ns == 0 || nv == 0) return 0;
   if (P->final_sel == 1)
-    return match_event_nn(g, P, seeds, ns, nv, vx, vy, vz, vtx, vty, vid, out, cap, near, event);
+    return match_event_nn(g, P, seeds, ns, nv, vx, vy, vz, vtx, vty, vid, ut, out, cap, near,
+                          event);
   const int logm = !g_nolog;
   pair_eval *pe = (pair_eval *)malloc(sizeof(pair_eval) * (size_t)ns * (size_t)nv);
   double *best_v = (double *)malloc(sizeof(double) * (size_t)nv);
@@ -938,6 +1047,7 @@ static int match_event(const orc_geom *g, const orc_params *P, const orc_seed *s
   for (int v = 0; v < nv; ++v)
     for (int s = 0; s < ns; ++s) {
       pair_eval r = eval_pair(P, g, &seeds[s], vx[v], vy[v], vz[v], vtx[v], vty[v], logm);
+      apply_ut(g, P, ut, vx[v], vy[v], vz[v], vtx[v], vty[v], &r);
       pe[(size_t)v * ns + s] = r;
       if (r.ok) {
         if (r.chi2 < best_v[v]) best_v[v] = r.chi2;
@@ -993,7 +1103,8 @@ static int match_event(const orc_geom *g, const orc_params *P, const orc_seed *s
       }
       if (n < cap) {
         orc_long *L = &out[n];
-        L->velo_idx = v; L->velo_id = vid[v]; L->seed_idx = s; L->pad = 0;
+        L->velo_idx = v; L->velo_id = vid[v]; L->seed_idx = s; L->n_ut = r->n_ut;
+        memcpy(L->ut_id, r->ut_id, sizeof(L->ut_id));
         L->qop = r->qop; L->chi2 = r->chi2; L->zm = r->zm;
         L->dx = r->dx; L->dy = r->dy; L->dtx = r->dtx; L->dty = r->dty;
         L->gp = -1.0;
@@ -1014,7 +1125,8 @@ typedef struct { dyn seeds, longs, near; } ev_out;
 static void run_event(const orc_geom *g, const orc_params *P, const int32_t *off,
                       const float *X, const float *Z, const int32_t *ID, int nv,
                       const float *vx, const float *vy, const float *vz, const float *vtx,
-                      const float *vty, const int32_t *vid, int event, ev_out *o) {
+                      const float *vty, const int32_t *vid, const ut_event *ut, int event,
+                      ev_out *o) {
   o->seeds = (dyn){NULL, 0, 0, sizeof(orc_seed)};
   o->longs = (dyn){NULL, 0, 0, sizeof(orc_long)};
   o->near = (dyn){NULL, 0, 0, sizeof(orc_near)};
@@ -1068,13 +1180,13 @@ static void run_event(const orc_geom *g, const orc_params *P, const int32_t *off
     cap = cap * 4 + 16;
     orc_long *tmp = (orc_long *)malloc(sizeof(orc_long) * (size_t)cap);
     const int near0 = o->near.n;
-    int n = match_event(g, P, (orc_seed *)o->seeds.p, ns, nv, vx, vy, vz, vtx, vty, vid, tmp, cap,
-                        &o->near, event);
+    int n = match_event(g, P, (orc_seed *)o->seeds.p, ns, nv, vx, vy, vz, vtx, vty, vid, ut,
+                        tmp, cap, &o->near, event);
     if (n > cap) {
       free(tmp);
       o->near.n = near0;
       tmp = (orc_long *)malloc(sizeof(orc_long) * (size_t)n);
-      match_event(g, P, (orc_seed *)o->seeds.p, ns, nv, vx, vy, vz, vtx, vty, vid, tmp, n,
+      match_event(g, P, (orc_seed *)o->seeds.p, ns, nv, vx, vy, vz, vtx, vty, vid, ut, tmp, n,
                   &o->near, event);
     }
     for (int i = 0; i < n; ++i) *(orc_long *)dyn_push(&o->longs) = tmp[i];
@@ -1092,6 +1204,9 @@ typedef struct {
   const int32_t *velo_off;
   const float *vx, *vy, *vz, *vtx, *vty;
   const int32_t *vid;
+  const int32_t *ut_off;
+  const float *ut_x;
+  const int32_t *ut_id;
   ev_out *outs;
   int next;
   int log_margins;
@@ -1110,9 +1225,10 @@ static void *worker(void *arg) {
     const int base = J->zone_off[e * 24];
     for (int k = 0; k <= 24; ++k) off[k] = J->zone_off[e * 24 + k] - base;
     const int v0 = J->velo_off[e], nv = J->velo_off[e + 1] - v0;
+    const ut_event ut = {J->ut_off ? J->ut_off + (size_t)e * ORC_NUT : NULL, J->ut_x, J->ut_id};
     run_event(J->g, J->P, off, J->hx + base, J->hz + base, J->hid + base, nv,
               J->vx + v0, J->vy + v0, J->vz + v0, J->vtx + v0, J->vty + v0, J->vid + v0,
-              e, &J->outs[e]);
+              &ut, e, &J->outs[e]);
   }
   return NULL;
 }
@@ -1120,12 +1236,12 @@ static void *worker(void *arg) {
 int orc_run(const orc_geom *g, const orc_params *p, int n_events, const int32_t *zone_off,
             const float *hx, const float *hz, const int32_t *hid, const int32_t *velo_off,
             const float *vx, const float *vy, const float *vz, const float *vtx,
-            const float *vty, const int32_t *vid, int n_threads, int log_margins,
-            orc_result *res) {
+            const float *vty, const int32_t *vid, const int32_t *ut_off, const float *ut_x,
+            const int32_t *ut_id, int n_threads, int log_margins, orc_result *res) {
   memset(res, 0, sizeof(*res));
   if (n_events < 0) return -1;
   job J = {g, p, n_events, zone_off, hx, hz, hid, velo_off, vx, vy, vz, vtx, vty, vid,
-           NULL, 0, log_margins, PTHREAD_MUTEX_INITIALIZER};
+           ut_off, ut_x, ut_id, NULL, 0, log_margins, PTHREAD_MUTEX_INITIALIZER};
   J.outs = (ev_out *)calloc((size_t)(n_events > 0 ? n_events : 1), sizeof(ev_out));
   if (n_threads < 1) n_threads = 1;
   if (n_threads > 256) n_threads = 256;

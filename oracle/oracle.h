@@ -19,6 +19,7 @@ extern "C" {
 #endif
 
 #define ORC_NL 12
+#define ORC_NUT 4
 #define ORC_NN_IN 8
 #define ORC_NN_HID 32
 
@@ -37,6 +38,8 @@ typedef struct {
   double z[ORC_NL];      /* nominal layer z [mm] */
   double tan_a[ORC_NL];  /* tan of the stereo angle (0 for x-layers) */
   double z_ref;          /* eq. trackequation reference point */
+  /* UT layers UTaX, UTaU, UTbV, UTbX (Sec. 4.3; positions are a reading) */
+  double ut_z[ORC_NUT], ut_tan[ORC_NUT];
 } orc_geom;
 
 typedef struct {
@@ -84,6 +87,18 @@ typedef struct {
   int32_t pad3;
   double ghost_cut, clone_gap;
   orc_ghost_nn ghost_nn;
+  /* UT hit search (Sec. 4.3).  ut_mode 0: off; 1: every pair that passed the
+   * preselection and the chi2_match cut is extrapolated to the UT layers
+   * with gamma_x = a_gamma + b_gamma q/p (eq. gamma_parametrisation), takes
+   * the closest hit in a loose window until one is found (which then fixes
+   * gamma_x), then the closest hit in a tight window in each later layer;
+   * pairs with fewer than ut_min_hits UT hits leave the candidates before
+   * the final selection.  Windows (Table 2): min(max(A + B/p, lo), hi), p in
+   * GeV/c; hi = 0 marks a layer without that window. */
+  int32_t ut_mode, ut_min_hits;
+  double a_gamma, b_gamma;
+  double ut_loose_a[ORC_NUT], ut_loose_b[ORC_NUT], ut_loose_lo[ORC_NUT], ut_loose_hi[ORC_NUT];
+  double ut_tight_a[ORC_NUT], ut_tight_b[ORC_NUT], ut_tight_lo[ORC_NUT], ut_tight_hi[ORC_NUT];
 } orc_params;
 
 /* Margins.  Every decision that shapes an output is logged with its
@@ -115,7 +130,8 @@ typedef struct {
 } orc_seed;
 
 typedef struct {
-  int32_t velo_idx, velo_id, seed_idx, pad;
+  int32_t velo_idx, velo_id, seed_idx, n_ut;
+  int32_t ut_id[ORC_NUT];   /* UT hit id per layer, -1 where none (ut_mode 1) */
   double qop, chi2, zm, dx, dy, dtx, dty;
   double gp;                /* ghost probability (final_sel 1), else -1 */
   double margin;            /* smallest margin of its seed's and its matching decisions */
@@ -168,16 +184,22 @@ void orc_clone_vote(const orc_cand *c, int n, int n_pos, int32_t *keep);
 int orc_uv(const orc_geom *g, const orc_params *p, const int32_t *zone_off,
            const float *x, const float *z, const int32_t *id, const orc_cand *cand,
            orc_seed *out);
+/* ut_off: the event's UT layer offsets [5] into ut_x / ut_id (NULL: none) */
 int orc_match(const orc_geom *g, const orc_params *p, const orc_seed *seeds, int ns,
               int nv, const float *vx, const float *vy, const float *vz,
               const float *vtx, const float *vty, const int32_t *vid,
+              const int32_t *ut_off, const float *ut_x, const int32_t *ut_id,
               orc_long *out, int cap);
 /* The pairs of one event that survive the preselection and the chi2_match
  * cut (the candidates of the final selection), VELO-major; returns their
  * count, writing at most cap. */
 int orc_match_pairs(const orc_geom *g, const orc_params *p, const orc_seed *seeds, int ns,
                     int nv, const float *vx, const float *vy, const float *vz,
-                    const float *vtx, const float *vty, orc_pair *out, int cap);
+                    const float *vtx, const float *vty, const int32_t *ut_off,
+                    const float *ut_x, const int32_t *ut_id, orc_pair *out, int cap);
+/* Half-width of the UT search window (Table 2) of layer 0..3 for a track of
+ * this q/p (1/MeV), loose (tight = 0) or tight; 0 where Table 2 gives none. */
+double orc_ut_window(const orc_params *p, int layer, int tight, double qop);
 /* The network's ghost probability for one input vector (unstandardised). */
 double orc_ghost_prob(const orc_params *p, const double f[ORC_NN_IN]);
 
@@ -186,11 +208,13 @@ double orc_ghost_prob(const orc_params *p, const double f[ORC_NN_IN]);
  * its own (closest-hit rescans, vote margins, near misses): the tracks are
  * the same, their margins are then only partly filled and no near misses are
  * listed (for timing the method alone). */
+/* ut_off [n_events*4 + 1], ut_x, ut_id: the UT hits (NULL: none; then a
+ * ut_mode 1 run finds no UT hits). */
 int orc_run(const orc_geom *g, const orc_params *p, int n_events, const int32_t *zone_off,
             const float *hx, const float *hz, const int32_t *hid, const int32_t *velo_off,
             const float *vx, const float *vy, const float *vz, const float *vtx,
-            const float *vty, const int32_t *vid, int n_threads, int log_margins,
-            orc_result *res);
+            const float *vty, const int32_t *vid, const int32_t *ut_off, const float *ut_x,
+            const int32_t *ut_id, int n_threads, int log_margins, orc_result *res);
 void orc_free(orc_result *res);
 
 #ifdef __cplusplus

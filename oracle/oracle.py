@@ -14,6 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 NL = 12
+NUT = 4
 
 
 def build(force: bool = True) -> str:
@@ -29,7 +30,8 @@ def build(force: bool = True) -> str:
 
 
 class Geom(C.Structure):
-    _fields_ = [("z", C.c_double * NL), ("tan_a", C.c_double * NL), ("z_ref", C.c_double)]
+    _fields_ = [("z", C.c_double * NL), ("tan_a", C.c_double * NL), ("z_ref", C.c_double),
+                ("ut_z", C.c_double * NUT), ("ut_tan", C.c_double * NUT)]
 
 
 NN_IN, NN_HID = 8, 32
@@ -72,7 +74,13 @@ class Params(C.Structure):
                 ("polarity", C.c_double), ("uv_mode", C.c_int32), ("hough_bins", C.c_int32),
                 ("hough_best", C.c_int32), ("hough_fine", C.c_int32), ("hough_min", C.c_int32),
                 ("pad2", C.c_int32), ("final_sel", C.c_int32), ("pad3", C.c_int32),
-                ("ghost_cut", C.c_double), ("clone_gap", C.c_double), ("ghost_nn", GhostNN)]
+                ("ghost_cut", C.c_double), ("clone_gap", C.c_double), ("ghost_nn", GhostNN),
+                ("ut_mode", C.c_int32), ("ut_min_hits", C.c_int32),
+                ("a_gamma", C.c_double), ("b_gamma", C.c_double)] + \
+               [(f"ut_{k}_{w}", C.c_double * NUT) for k in ("loose", "tight")
+                for w in ("a", "b", "lo", "hi")]
+
+    ARRAYS = ("zm",) + tuple(f"ut_{k}_{w}" for k in ("loose", "tight") for w in ("a", "b", "lo", "hi"))
 
     def as_dict(self) -> dict:
         out = {}
@@ -80,7 +88,7 @@ class Params(C.Structure):
             if name.startswith("pad") or name == "ghost_nn":
                 continue
             v = getattr(self, name)
-            out[name] = list(v) if name == "zm" else v
+            out[name] = list(v) if name in self.ARRAYS else v
         return out
 
 
@@ -97,7 +105,7 @@ SEED_DTYPE = np.dtype([("a", "f8"), ("b", "f8"), ("c", "f8"), ("y0", "f8"), ("ty
                        ("nx", "i4"), ("nuv", "i4"), ("half", "i4"), ("it", "i4"),
                        ("pos", "i4", NL), ("id", "i4", NL), ("margin", "f8")], align=True)
 LONG_DTYPE = np.dtype([("velo_idx", "i4"), ("velo_id", "i4"), ("seed_idx", "i4"),
-                       ("pad", "i4"), ("qop", "f8"), ("chi2", "f8"), ("zm", "f8"),
+                       ("n_ut", "i4"), ("ut_id", "i4", NUT), ("qop", "f8"), ("chi2", "f8"), ("zm", "f8"),
                        ("dx", "f8"), ("dy", "f8"), ("dtx", "f8"), ("dty", "f8"),
                        ("gp", "f8"), ("margin", "f8")], align=True)
 PAIR_DTYPE = np.dtype([("velo_idx", "i4"), ("seed_idx", "i4"), ("f", "f8", NN_IN), ("gp", "f8")],
@@ -132,14 +140,16 @@ def lib():
         L.orc_uv.argtypes = [C.POINTER(Geom), C.POINTER(Params), vp, vp, vp, vp, vp, vp]
         L.orc_uv.restype = C.c_int
         L.orc_match.argtypes = [C.POINTER(Geom), C.POINTER(Params), vp, C.c_int, C.c_int,
-                                vp, vp, vp, vp, vp, vp, vp, C.c_int]
+                                vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]
         L.orc_match.restype = C.c_int
         L.orc_match_pairs.argtypes = [C.POINTER(Geom), C.POINTER(Params), vp, C.c_int, C.c_int,
-                                      vp, vp, vp, vp, vp, vp, C.c_int]
+                                      vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]
         L.orc_match_pairs.restype = C.c_int
+        L.orc_ut_window.argtypes = [C.POINTER(Params), C.c_int, C.c_int, C.c_double]
+        L.orc_ut_window.restype = C.c_double
         L.orc_ghost_prob.argtypes = [C.POINTER(Params), vp]
         L.orc_ghost_prob.restype = C.c_double
-        L.orc_run.argtypes = [C.POINTER(Geom), C.POINTER(Params), C.c_int] + [vp] * 11 + \
+        L.orc_run.argtypes = [C.POINTER(Geom), C.POINTER(Params), C.c_int] + [vp] * 14 + \
                              [C.c_int, C.c_int, C.POINTER(_Result)]
         L.orc_run.restype = C.c_int
         L.orc_free.argtypes = [C.POINTER(_Result)]
@@ -158,9 +168,9 @@ def default_params(**over) -> Params:
     p = Params()
     lib().orc_default_params(C.byref(p))
     for k, v in over.items():
-        if k == "zm":
+        if k in Params.ARRAYS:
             for i, x in enumerate(v):
-                p.zm[i] = x
+                getattr(p, k)[i] = x
         elif k == "ghost_nn":
             set_ghost_nn(p.ghost_nn, v)
         else:
@@ -217,15 +227,28 @@ def uv(ev, cand, params: Params | None = None, geom: Geom | None = None):
     return out[0] if ok else None
 
 
+def _ut_args(ut):
+    """(off [5], x, id) of one event's UT hits as pointers, or three NULLs;
+    the arrays are returned too, so that they outlive the call."""
+    if ut is None:
+        return [None, None, None], []
+    a = [_c(ut["off"], np.int32), _c(ut["x"], np.float32), _c(ut["id"], np.int32)]
+    assert len(a[0]) == NUT + 1
+    return [_ptr(x) for x in a], a
+
+
 def match(seeds: np.ndarray, velo: dict, params: Params | None = None,
-          geom: Geom | None = None) -> np.ndarray:
+          geom: Geom | None = None, ut: dict | None = None) -> np.ndarray:
+    """Matching of one event; ut: its UT hits {off [5], x, id} or None."""
     params = params or default_params()
     geom = geom or default_geom()
     s = _c(seeds, SEED_DTYPE)
     arr = [_c(velo[k], np.float32) for k in ("x", "y", "z", "tx", "ty")]
     vid = _c(velo["id"], np.int32)
     nv = len(vid)
-    args = [C.byref(geom), C.byref(params), _ptr(s), len(s), nv] + [_ptr(a) for a in arr] + [_ptr(vid)]
+    up, keep = _ut_args(ut)
+    args = [C.byref(geom), C.byref(params), _ptr(s), len(s), nv] + [_ptr(a) for a in arr] + \
+        [_ptr(vid)] + up
     n = lib().orc_match(*args, None, 0)
     out = np.zeros(n, LONG_DTYPE)
     lib().orc_match(*args, _ptr(out), n)
@@ -233,19 +256,26 @@ def match(seeds: np.ndarray, velo: dict, params: Params | None = None,
 
 
 def match_pairs(seeds: np.ndarray, velo: dict, params: Params | None = None,
-                geom: Geom | None = None) -> np.ndarray:
-    """The pairs that pass the preselection and the chi2_match cut, with the
-    network's eight inputs and (final_sel 1) their ghost probability."""
+                geom: Geom | None = None, ut: dict | None = None) -> np.ndarray:
+    """The pairs that pass the preselection, the chi2_match cut and (ut_mode
+    1) the UT hit count, with the network's eight inputs and (final_sel 1)
+    their ghost probability."""
     params = params or default_params()
     geom = geom or default_geom()
     s = _c(seeds, SEED_DTYPE)
     arr = [_c(velo[k], np.float32) for k in ("x", "y", "z", "tx", "ty")]
     nv = len(arr[0])
-    args = [C.byref(geom), C.byref(params), _ptr(s), len(s), nv] + [_ptr(a) for a in arr]
+    up, keep = _ut_args(ut)
+    args = [C.byref(geom), C.byref(params), _ptr(s), len(s), nv] + [_ptr(a) for a in arr] + up
     n = lib().orc_match_pairs(*args, None, 0)
     out = np.zeros(n, PAIR_DTYPE)
     lib().orc_match_pairs(*args, _ptr(out), n)
     return out
+
+
+def ut_window(layer: int, tight: bool, qop: float, params: Params | None = None) -> float:
+    return float(lib().orc_ut_window(C.byref(params or default_params()), int(layer),
+                                     int(bool(tight)), float(qop)))
 
 
 def ghost_prob(params: Params, f) -> float:
@@ -282,12 +312,18 @@ def run(batch, params: Params | None = None, geom: Geom | None = None,
             _c(batch.velo_y, np.float32), _c(batch.velo_z, np.float32),
             _c(batch.velo_tx, np.float32), _c(batch.velo_ty, np.float32),
             _c(batch.velo_id, np.int32)]
+    has_ut = getattr(batch, "ut_off", None) is not None
+    if params.ut_mode == 1 and not has_ut:
+        raise ValueError("ut_mode 1 needs a batch with UT hits")
+    ut = [_c(batch.ut_off, np.int32), _c(batch.ut_x, np.float32), _c(batch.ut_id, np.int32)] \
+        if has_ut else None
     res = _Result()
     n_ev = batch.n_events
     rc = lib().orc_run(C.byref(geom), C.byref(params), n_ev, _ptr(arrs[0]), _ptr(arrs[1]),
                        _ptr(arrs[2]), _ptr(arrs[3]), _ptr(arrs[4]), _ptr(arrs[5]),
                        _ptr(arrs[6]), _ptr(arrs[7]), _ptr(arrs[8]), _ptr(arrs[9]),
-                       _ptr(arrs[10]), int(threads), int(bool(margins)), C.byref(res))
+                       _ptr(arrs[10]), *([_ptr(a) for a in ut] if ut else [None] * 3),
+                       int(threads), int(bool(margins)), C.byref(res))
     if rc != 0:
         raise RuntimeError(f"orc_run failed: {rc}")
     try:

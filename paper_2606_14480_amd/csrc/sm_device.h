@@ -35,6 +35,7 @@ constexpr int kVflat = 256;         // VELO states per event for the flattened p
 constexpr int kPvLds = 2048;        // flattened pairs whose VELO state is looked up in LDS
 constexpr int kVsLds = 512;         // VELO states per event with LDS best-chi2 entries
 constexpr int kSurvLds = 512;       // matching survivors kept in LDS
+constexpr int kUtLds = 1024;        // UT hits per event staged in LDS (UT search)
 constexpr int kPosBits = 21;        // item-relative hit positions < 2^21
 constexpr int kPoolPerItem = 128;   // seed-pool slots of each item (more: the overflow area)
 constexpr int kMaxItemHits = 1 << kPosBits;
@@ -129,6 +130,11 @@ struct DevParams {
   double ghost_cut, clone_gap;
   double nn_mean[SM_NN_INPUTS], nn_scale[SM_NN_INPUTS];
   double nn_w1[SM_NN_HIDDEN][SM_NN_INPUTS], nn_b1[SM_NN_HIDDEN], nn_w2[SM_NN_HIDDEN], nn_b2;
+  // UT hit search (Sec. 4.3): layer z and stereo tan, gamma_x constants, and
+  // the windows of Table 2 by kind (0 loose, 1 tight) and layer
+  int ut_mode, ut_min_hits;
+  double ut_z[SM_N_UT], ut_tan[SM_N_UT], a_gamma, b_gamma;
+  double ut_a[2][SM_N_UT], ut_b[2][SM_N_UT], ut_lo[2][SM_N_UT], ut_hi[2][SM_N_UT];
 };
 
 // An x-z candidate (Sec. 3.2) in per-workgroup scratch.
@@ -212,23 +218,26 @@ struct KCtx {
 }  // namespace smk
 
 // Dynamic LDS bytes of k_seed for a given LDS hit capacity.
-size_t smk_seed_lds_bytes(int lds_hits);
-size_t smk_seed_big_lds_bytes(int lds_hits);
+// dynamic LDS of a seeding form; sel: the matching variant it carries (bit 0
+// the ghost network, bit 1 the UT search, whose hits are staged after the
+// matching state)
+size_t smk_seed_lds_bytes(int lds_hits, int sel = 0);
+size_t smk_seed_big_lds_bytes(int lds_hits, int sel = 0);
 
 extern "C" {
 // Launchers (sm_device.hip); each returns the hipError_t of its launch.
 int smk_launch_prepare(const smk::Desc *d, const smk::KCtx *k, int plain, hipStream_t st);
-// net: the instantiation with the network form of the final selection
-// (final_sel 1); the chi2 form otherwise
+// sel: the matching variant (bit 0: the network form of the final selection,
+// final_sel 1; bit 1: the UT search, ut_mode 1), one instantiation each
 int smk_launch_seed(const smk::Desc *d, const smk::KCtx *k, int item_begin, int item_count,
-                    int use_queue, int grid, int lds_hits, int plain, int uv_mode, int net,
+                    int use_queue, int grid, int lds_hits, int plain, int uv_mode, int sel,
                     hipStream_t st);
 // the main form without the matching code, for batches matched by k_match
 int smk_launch_seed_nomatch(const smk::Desc *d, const smk::KCtx *k, int grid, int lds_hits,
                             hipStream_t st);
 int smk_launch_seed_big(const smk::Desc *d, const smk::KCtx *k, int grid, int lds_hits, int prep,
-                        int net, hipStream_t st);
-int smk_launch_match(const smk::Desc *d, const smk::KCtx *k, int grid, int net, hipStream_t st);
+                        int sel, hipStream_t st);
+int smk_launch_match(const smk::Desc *d, const smk::KCtx *k, int grid, int sel, hipStream_t st);
 int smk_seed_big_lds_limit(int bytes);
 int smk_seed_lds_limit(int bytes);   // dynamic LDS allowed to the main seeding forms
 int smk_seed_big_static_lds();   // static LDS of the big form (its dynamic LDS comes on top)

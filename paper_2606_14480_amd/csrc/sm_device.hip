@@ -1265,6 +1265,75 @@ __device__ __forceinline__ MState seed_state(const sm_seed *s, const DevParams &
   return m;
 }
 
+// ---------------------------------------------------------- UT search ----
+
+// Half-width of a UT window (Table 2): kind 0 loose, 1 tight; 0 where the
+// layer has none.  min(max(a + b / p, lo), hi), p in GeV/c.
+__device__ __forceinline__ double ut_window(const DevParams &P, int kind, int i, double qop) {
+  const double hi = P.ut_hi[kind][i];
+  if (!(hi > 0.0)) return 0.0;
+  return fmin(fmax(P.ut_a[kind][i] + P.ut_b[kind][i] * 1000.0 * fabs(qop), P.ut_lo[kind][i]), hi);
+}
+
+// Closest hit to pred among positions [lo, hi) of an x-sorted layer, inside
+// [pred - w, pred + w]; distances within kTieMm are a tie won by the lower
+// position.  X(h): the hit's x.  -1 if none.
+template <class FX>
+__device__ __forceinline__ int ut_closest(FX X, int lo, int hi, double pred, double w) {
+  const double xlo = pred - w, xhi = pred + w;
+  int a = lo, b = hi;
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if ((double)X(m) < xlo) a = m + 1; else b = m;
+  }
+  int best = -1;
+  double bd = 0.0;
+  for (int h = a; h < hi; ++h) {
+    const double x = (double)X(h);
+    if (!(x <= xhi)) break;
+    const double d = fabs(x - pred);
+    if (best < 0 || d < bd - kTieMm) { best = h; bd = d; }
+  }
+  return best;
+}
+
+// UT hits of one VELO-seed pair (Sec. 4.3): the VELO state extrapolated with
+// eq. velo_ut_extrapolation (from the state's own z), gamma_x from eq.
+// gamma_parametrisation with the pair's q/p, compared with the layer's
+// measured coordinate x - y tan(alpha).  Until a hit is found each layer's
+// loose window is searched; the closest hit found there refits gamma_x so
+// that the parabola passes through it, and every later layer takes the
+// closest hit in its tight window.  uo: the event's layer offsets into X/ID.
+// Returns the number of hits attached, their ids in ids (-1 where none).
+template <class FX, class FI>
+__device__ __forceinline__ int ut_search(const DevParams &P, FX X, FI ID,
+                                         const int (&uo)[SM_N_UT + 1], double xv, double yv,
+                                         double zv, double txv, double tyv, double qop,
+                                         int32_t (&ids)[SM_N_UT]) {
+  double gam = P.a_gamma + P.b_gamma * qop;
+  bool loose = true;
+  int n = 0;
+#pragma unroll
+  for (int i = 0; i < SM_N_UT; ++i) {
+    ids[i] = -1;
+    const double w = ut_window(P, loose ? 0 : 1, i, qop);
+    if (!(w > 0.0)) continue;
+    const double dz = P.ut_z[i] - zv;
+    const double yp = yv + tyv * dz;
+    const double mp = xv + txv * dz + gam * dz * dz - yp * P.ut_tan[i];
+    const int h = ut_closest(X, uo[i], uo[i + 1], mp, w);
+    if (h < 0) continue;
+    ids[i] = ID(h);
+    ++n;
+    if (loose) {
+      const double xh = (double)X(h) + yp * P.ut_tan[i];
+      gam = (xh - xv - txv * dz) / (dz * dz);
+      loose = false;
+    }
+  }
+  return n;
+}
+
 struct MatchShared {
   float xsf[kMsLds], txsf[kMsLds], ymf[kMsLds], tyf[kMsLds], sty[kMsLds];
   int sidx[kMsLds];
@@ -1310,10 +1379,11 @@ __global__ __launch_bounds__(256) void k_validate(const Desc *__restrict__ D, co
 // buffers at offsets chained from the previous event; batched: long tracks go
 // to the pool and the seeds stay in theirs until the offsets are known.
 // kSmallM: the event's seeds and VELO states fit the LDS arrays, which the
-// instantiation then addresses as LDS (not through generic pointers).  kNet:
-// the network form of the final selection (an instantiation of its own, so
-// that the chi2 form carries none of its registers).
-template <bool kSmallM, int NT, bool kNet>
+// instantiation then addresses as LDS (not through generic pointers).  kSel:
+// bit 0 the network form of the final selection, bit 1 the UT search (each
+// variant an instantiation of its own, so that the default one carries none
+// of their registers or LDS).
+template <bool kSmallM, int NT, int kSel>
 __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, const Scratch &S,
                                                  const DevParams &P, int e, int plain, size_t wg,
                                                  MatchShared &sh) {
@@ -1359,6 +1429,38 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     vtxr = gmem(D->b.velo_tx)[v0 + tid];
     vtyr = gmem(D->b.velo_ty)[v0 + tid];
   }
+  // UT search variant: the event's UT layer offsets and, when they fit, its UT
+  // hits in LDS after the matching state (offsets then relative to the first)
+  constexpr bool kUt = (kSel & 2) != 0;
+  int ut_o[SM_N_UT + 1] = {};
+  bool ut_lds = false;
+  float *ut_xs = reinterpret_cast<float *>(reinterpret_cast<unsigned char *>(&sh) + sizeof(MatchShared));
+  int32_t *ut_ids = reinterpret_cast<int32_t *>(ut_xs + kUtLds);
+  if constexpr (kUt) {
+#pragma unroll
+    for (int k = 0; k <= SM_N_UT; ++k) ut_o[k] = gmem(D->b.ut_off)[(size_t)e * SM_N_UT + k];
+    const int nu = ut_o[SM_N_UT] - ut_o[0];
+    ut_lds = nu <= kUtLds;
+    if (ut_lds) {
+      const int u0 = ut_o[0];
+      for (int i = tid; i < nu; i += NT) {
+        ut_xs[i] = gmem(D->b.ut_x)[u0 + i];
+        ut_ids[i] = gmem(D->b.ut_id)[u0 + i];
+      }
+#pragma unroll
+      for (int k = 0; k <= SM_N_UT; ++k) ut_o[k] -= u0;
+    }
+  }
+  // UT hits of a pair (its q/p from the evaluation)
+  auto ut_of = [&](double xv, double yv, double zv, double txv, double tyv, double qop,
+                   int32_t (&ids)[SM_N_UT]) {
+    if (ut_lds)
+      return ut_search(P, [&](int h) { return ut_xs[h]; }, [&](int h) { return ut_ids[h]; }, ut_o,
+                       xv, yv, zv, txv, tyv, qop, ids);
+    return ut_search(P, [&](int h) { return gmem(D->b.ut_x)[h]; },
+                     [&](int h) { return gmem(D->b.ut_id)[h]; }, ut_o, xv, yv, zv, txv, tyv, qop,
+                     ids);
+  };
   // the event's seeds in canonical order (half 0 then half 1); the plain form
   // copies whole records to the caller, matching reads five fields of each
   if (plain)
@@ -1397,6 +1499,11 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
                       unsigned long long &bits) {
     const PairEval r = eval_pair(gload(&ms[s]), xvf, yvf, zvf, txvf, tyvf, P);
     if (!r.ok) return false;
+    if constexpr (kUt) {
+      // Sec. 4.3: more than two UT hits (ut_min_hits) or the pair leaves
+      int32_t ids[SM_N_UT];
+      if (ut_of(xvf, yvf, zvf, txvf, tyvf, r.qop, ids) < P.ut_min_hits) return false;
+    }
     bits = (unsigned long long)__double_as_longlong(r.chi2);
     atomicMin(&best_s[s], bits);
     const unsigned slot = atomicAdd(&sh.nsurv, 1u);
@@ -1498,17 +1605,18 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     const sm_seed *sd = si < n0 ? &S.pool[b0 + si] : &S.pool[b1 + si - n0];
     return gmem(sd)->n_x + gmem(sd)->n_uv;
   };
-  auto pair_of = [&](int vi, int si, double &txv, double &tyv) {
+  // a pair's evaluation and its VELO state (x, y, z, tx, ty)
+  auto pair_of = [&](int vi, int si, double (&vs)[5]) {
     const int v = v0 + vi;
     if (vlds) {
-      txv = sh.vtx[vi]; tyv = sh.vty[vi];
-      return eval_pair(gload(&ms[si]), sh.vx[vi], sh.vy[vi], sh.vz[vi], sh.vtx[vi], sh.vty[vi], P);
+      vs[0] = sh.vx[vi]; vs[1] = sh.vy[vi]; vs[2] = sh.vz[vi]; vs[3] = sh.vtx[vi]; vs[4] = sh.vty[vi];
+    } else {
+      vs[0] = gmem(D->b.velo_x)[v]; vs[1] = gmem(D->b.velo_y)[v]; vs[2] = gmem(D->b.velo_z)[v];
+      vs[3] = gmem(D->b.velo_tx)[v]; vs[4] = gmem(D->b.velo_ty)[v];
     }
-    txv = gmem(D->b.velo_tx)[v]; tyv = gmem(D->b.velo_ty)[v];
-    return eval_pair(gload(&ms[si]), gmem(D->b.velo_x)[v], gmem(D->b.velo_y)[v],
-                     gmem(D->b.velo_z)[v], txv, tyv, P);
+    return eval_pair(gload(&ms[si]), vs[0], vs[1], vs[2], vs[3], vs[4], P);
   };
-  constexpr bool nnsel = kNet;
+  constexpr bool nnsel = (kSel & 1) != 0;
   if (nnsel && fits) {
     // the network form (Sec. 4.4): each survivor's ghost probability replaces
     // its chi2 in the list; the retained ones (below the cut) give the lowest
@@ -1518,9 +1626,9 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     __syncthreads();
     for (unsigned i = tid; i < nsv; i += NT) {
       Surv sv = i < (unsigned)kSurvLds ? sh.surv[i] : gload(&surv[i - kSurvLds]);
-      double txv, tyv;
-      const PairEval pe = pair_of(sv.v, sv.s, txv, tyv);
-      sv.chi2 = ghost_prob(pe, txv, tyv, nhits_of(sv.s), P);
+      double vs[5];
+      const PairEval pe = pair_of(sv.v, sv.s, vs);
+      sv.chi2 = ghost_prob(pe, vs[3], vs[4], nhits_of(sv.s), P);
       if (i < (unsigned)kSurvLds) sh.surv[i] = sv;
       else gstore(&surv[i - kSurvLds], sv);
       if (sv.chi2 < P.ghost_cut) {
@@ -1585,14 +1693,22 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     if ((long long)(lb + r) >= cap) continue;
     const int vi = (int)(key >> 32), si = (int)(key & 0xffffffffu);
     const int v = v0 + vi;
-    double txv, tyv;
-    const PairEval pe = pair_of(vi, si, txv, tyv);
+    double vs[5];
+    const PairEval pe = pair_of(vi, si, vs);
     sm_long L;
     L.velo_idx = vi; L.seed_idx = si; L.velo_id = gmem(D->b.velo_id)[v];
     L.qop = (float)pe.qop; L.chi2 = (float)pe.chi2; L.z_match = (float)pe.zm;
     L.dx = (float)pe.dx; L.dy = (float)pe.dy; L.dtx = (float)pe.dtx; L.dty = (float)pe.dty;
-    L.ghost_prob = nnsel ? (float)ghost_prob(pe, txv, tyv, nhits_of(si), P) : -1.0f;
-    L.pad = 0;
+    L.ghost_prob = nnsel ? (float)ghost_prob(pe, vs[3], vs[4], nhits_of(si), P) : -1.0f;
+    L.n_ut = 0;
+#pragma unroll
+    for (int k = 0; k < SM_N_UT; ++k) L.ut_hits[k] = -1;
+    if constexpr (kUt) {
+      int32_t ids[SM_N_UT];
+      L.n_ut = ut_of(vs[0], vs[1], vs[2], vs[3], vs[4], pe.qop, ids);
+#pragma unroll
+      for (int k = 0; k < SM_N_UT; ++k) L.ut_hits[k] = ids[k];
+    }
     if (plain) dst[lb + r] = L;
     else gstore(&dst[lb + r], L);
   }
@@ -1601,16 +1717,16 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
 
 // ----------------------------------------------------- the fused kernel ----
 
-template <int NT, bool kNet>
+template <int NT, int kSel>
 __device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Scratch &S,
                                             const DevParams &P, int e, int plain, size_t wg,
                                             MatchShared &sh) {
   const int ns = S.item_cnt[2 * e] + S.item_cnt[2 * e + 1];
   const int nv = D->b.velo_off[e + 1] - D->b.velo_off[e];
   if (ns <= kMsLds && nv <= kVsLds)
-    match_event_impl<true, NT, kNet>(D, S, P, e, plain, wg, sh);
+    match_event_impl<true, NT, kSel>(D, S, P, e, plain, wg, sh);
   else
-    match_event_impl<false, NT, kNet>(D, S, P, e, plain, wg, sh);
+    match_event_impl<false, NT, kSel>(D, S, P, e, plain, wg, sh);
 }
 
 // Size class of an item for the longest-first order: kFineSub classes per
@@ -1807,7 +1923,7 @@ __device__ __forceinline__ unsigned prepare_batch(const Desc *__restrict__ D,
 // waves per CU with its own scratch, over the big items (at the head of the
 // order); it runs first, so a big item gets a whole CU instead of holding one
 // 256-thread workgroup for the whole batch.
-template <int kUv, int NT, bool kFuse = true, bool kNet = false>
+template <int kUv, int NT, bool kFuse = true, int kSel = 0>
 __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *__restrict__ D,
                                                      const KCtx *__restrict__ K, int item_begin,
                                                      int item_count, int use_queue, int lds_hits,
@@ -1986,7 +2102,7 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
     }
     __syncthreads();
     if constexpr (kFuse) {
-      if (s_last) match_event<NT, kNet>(D, S, P, item >> 1, plain, wg, mh);
+      if (s_last) match_event<NT, kSel>(D, S, P, item >> 1, plain, wg, mh);
     }
     __syncthreads();
   }
@@ -1998,7 +2114,7 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
 // seeding kernel needs no per-event hand-off (one agent-scope release per
 // item and one acquire per event, each an L2 write-back or invalidate on a
 // chip with one L2 per XCD).
-template <bool kNet>
+template <int kSel>
 __global__ __launch_bounds__(kSeedWG, 4) void k_match(const Desc *__restrict__ D,
                                                       const KCtx *__restrict__ K) {
   const Scratch &S = K->S;
@@ -2016,7 +2132,7 @@ __global__ __launch_bounds__(kSeedWG, 4) void k_match(const Desc *__restrict__ D
     __syncthreads();
     const int e = s_e;
     if (e >= D->n_events) break;
-    match_event<kSeedWG, kNet>(D, S, P, e, 0, blockIdx.x, mh);
+    match_event<kSeedWG, kSel>(D, S, P, e, 0, blockIdx.x, mh);
     __syncthreads();
   }
 }
@@ -2158,13 +2274,30 @@ __global__ void k_plain_totals(const Desc *__restrict__ D, const KCtx *__restric
 
 using namespace smk;
 
-size_t smk_seed_lds_bytes(int lds_hits) {
-  const size_t a = sizeof(SeedShared<kSeedWG>) + (size_t)lds_hits * 3 * sizeof(float);
-  return a > sizeof(MatchShared) ? a : sizeof(MatchShared);
+static size_t match_lds_bytes(int sel) {
+  return sizeof(MatchShared) + ((sel & 2) ? (size_t)kUtLds * (sizeof(float) + sizeof(int32_t)) : 0);
 }
-size_t smk_seed_big_lds_bytes(int lds_hits) {
+size_t smk_seed_lds_bytes(int lds_hits, int sel) {
+  const size_t a = sizeof(SeedShared<kSeedWG>) + (size_t)lds_hits * 3 * sizeof(float);
+  return a > match_lds_bytes(sel) ? a : match_lds_bytes(sel);
+}
+size_t smk_seed_big_lds_bytes(int lds_hits, int sel) {
   const size_t a = sizeof(SeedShared<kBigWG>) + (size_t)lds_hits * 3 * sizeof(float);
-  return a > sizeof(MatchShared) ? a : sizeof(MatchShared);
+  return a > match_lds_bytes(sel) ? a : match_lds_bytes(sel);
+}
+
+template <int kSel>
+static void launch_seed_sel(const Desc *d, const KCtx *k, int item_begin, int item_count,
+                            int use_queue, int grid, int lds_hits, int plain, hipStream_t st) {
+  hipLaunchKernelGGL((k_seed<0, kSeedWG, true, kSel>), dim3(grid), dim3(kSeedWG),
+                     smk_seed_lds_bytes(lds_hits, kSel), st, d, k, item_begin, item_count,
+                     use_queue, lds_hits, plain, 0);
+}
+template <int kSel>
+static void launch_big_sel(const Desc *d, const KCtx *k, int grid, int lds_hits, int prep,
+                           hipStream_t st) {
+  hipLaunchKernelGGL((k_seed<0, kBigWG, true, kSel>), dim3(grid), dim3(kBigWG),
+                     smk_seed_big_lds_bytes(lds_hits, kSel), st, d, k, 0, -1, 1, lds_hits, 0, prep);
 }
 
 extern "C" {
@@ -2173,17 +2306,18 @@ int smk_launch_prepare(const Desc *d, const KCtx *k, int plain, hipStream_t st) 
   return (int)hipGetLastError();
 }
 int smk_launch_seed(const Desc *d, const KCtx *k, int item_begin, int item_count, int use_queue,
-                    int grid, int lds_hits, int plain, int uv_mode, int net, hipStream_t st) {
+                    int grid, int lds_hits, int plain, int uv_mode, int sel, hipStream_t st) {
   if (uv_mode == 1)
     hipLaunchKernelGGL((k_seed<1, kSeedWG>), dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits),
                        st, d, k, item_begin, item_count, use_queue, lds_hits, plain, 0);
-  else if (net)
-    hipLaunchKernelGGL((k_seed<0, kSeedWG, true, true>), dim3(grid), dim3(kSeedWG),
-                       smk_seed_lds_bytes(lds_hits), st, d, k, item_begin, item_count, use_queue,
-                       lds_hits, plain, 0);
+  else if (sel == 1)
+    launch_seed_sel<1>(d, k, item_begin, item_count, use_queue, grid, lds_hits, plain, st);
+  else if (sel == 2)
+    launch_seed_sel<2>(d, k, item_begin, item_count, use_queue, grid, lds_hits, plain, st);
+  else if (sel == 3)
+    launch_seed_sel<3>(d, k, item_begin, item_count, use_queue, grid, lds_hits, plain, st);
   else
-    hipLaunchKernelGGL((k_seed<0, kSeedWG>), dim3(grid), dim3(kSeedWG), smk_seed_lds_bytes(lds_hits),
-                       st, d, k, item_begin, item_count, use_queue, lds_hits, plain, 0);
+    launch_seed_sel<0>(d, k, item_begin, item_count, use_queue, grid, lds_hits, plain, st);
   return (int)hipGetLastError();
 }
 int smk_launch_seed_nomatch(const Desc *d, const KCtx *k, int grid, int lds_hits, hipStream_t st) {
@@ -2191,21 +2325,20 @@ int smk_launch_seed_nomatch(const Desc *d, const KCtx *k, int grid, int lds_hits
                      smk_seed_lds_bytes(lds_hits), st, d, k, 0, -1, 1, lds_hits, 0, 0);
   return (int)hipGetLastError();
 }
-int smk_launch_seed_big(const Desc *d, const KCtx *k, int grid, int lds_hits, int prep, int net,
+int smk_launch_seed_big(const Desc *d, const KCtx *k, int grid, int lds_hits, int prep, int sel,
                         hipStream_t st) {
-  if (net)
-    hipLaunchKernelGGL((k_seed<0, kBigWG, true, true>), dim3(grid), dim3(kBigWG),
-                       smk_seed_big_lds_bytes(lds_hits), st, d, k, 0, -1, 1, lds_hits, 0, prep);
-  else
-    hipLaunchKernelGGL((k_seed<0, kBigWG>), dim3(grid), dim3(kBigWG),
-                       smk_seed_big_lds_bytes(lds_hits), st, d, k, 0, -1, 1, lds_hits, 0, prep);
+  if (sel == 1) launch_big_sel<1>(d, k, grid, lds_hits, prep, st);
+  else if (sel == 2) launch_big_sel<2>(d, k, grid, lds_hits, prep, st);
+  else if (sel == 3) launch_big_sel<3>(d, k, grid, lds_hits, prep, st);
+  else launch_big_sel<0>(d, k, grid, lds_hits, prep, st);
   return (int)hipGetLastError();
 }
-int smk_launch_match(const Desc *d, const KCtx *k, int grid, int net, hipStream_t st) {
-  if (net)
-    hipLaunchKernelGGL(k_match<true>, dim3(grid), dim3(kSeedWG), sizeof(MatchShared), st, d, k);
-  else
-    hipLaunchKernelGGL(k_match<false>, dim3(grid), dim3(kSeedWG), sizeof(MatchShared), st, d, k);
+int smk_launch_match(const Desc *d, const KCtx *k, int grid, int sel, hipStream_t st) {
+  const size_t lds = match_lds_bytes(sel);
+  if (sel == 1) hipLaunchKernelGGL(k_match<1>, dim3(grid), dim3(kSeedWG), lds, st, d, k);
+  else if (sel == 2) hipLaunchKernelGGL(k_match<2>, dim3(grid), dim3(kSeedWG), lds, st, d, k);
+  else if (sel == 3) hipLaunchKernelGGL(k_match<3>, dim3(grid), dim3(kSeedWG), lds, st, d, k);
+  else hipLaunchKernelGGL(k_match<0>, dim3(grid), dim3(kSeedWG), lds, st, d, k);
   return (int)hipGetLastError();
 }
 int smk_seed_big_static_lds() {
@@ -2221,7 +2354,11 @@ int smk_seed_lds_limit(int bytes) {
                                    hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<0, kSeedWG, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<0, kSeedWG, true, true>,
+  if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<0, kSeedWG, true, 1>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<0, kSeedWG, true, 2>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<0, kSeedWG, true, 3>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<1, kSeedWG, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -2230,7 +2367,11 @@ int smk_seed_lds_limit(int bytes) {
 int smk_seed_big_lds_limit(int bytes) {
   int e = (int)hipFuncSetAttribute((const void *)k_seed<0, kBigWG>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<0, kBigWG, true, true>,
+  if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<0, kBigWG, true, 1>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<0, kBigWG, true, 2>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (!e) e = (int)hipFuncSetAttribute((const void *)k_seed<0, kBigWG, true, 3>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   return e;
 }

@@ -166,6 +166,18 @@ DevParams make_params(const sm_geometry &g, const sm_params &p) {
     d.nn_w2[j] = p.ghost_nn.w2[j];
   }
   d.nn_b2 = p.ghost_nn.b2;
+  d.ut_mode = p.ut_mode;
+  d.ut_min_hits = p.ut_min_hits;
+  d.a_gamma = p.a_gamma;
+  d.b_gamma = p.b_gamma;
+  for (int i = 0; i < SM_N_UT; ++i) {
+    d.ut_z[i] = g.ut_z[i];
+    d.ut_tan[i] = g.ut_tan[i];
+    d.ut_a[0][i] = p.ut_loose_a[i]; d.ut_b[0][i] = p.ut_loose_b[i];
+    d.ut_lo[0][i] = p.ut_loose_lo[i]; d.ut_hi[0][i] = p.ut_loose_hi[i];
+    d.ut_a[1][i] = p.ut_tight_a[i]; d.ut_b[1][i] = p.ut_tight_b[i];
+    d.ut_lo[1][i] = p.ut_tight_lo[i]; d.ut_hi[1][i] = p.ut_tight_hi[i];
+  }
   double zmin = 1e300;
   for (int l = 0; l < smk::kNL; ++l)
     if (g.tan_stereo[l] != 0.0) zmin = std::min(zmin, g.z[l]);
@@ -344,6 +356,12 @@ int match_grid(const sm_ctx *c, int grid) {
   return c->cfg.match_wgs > 0 ? std::min(c->cfg.match_wgs, grid) : grid;
 }
 
+// The matching variant of the kernels: bit 0 the network form of the final
+// selection, bit 1 the UT search; each is an instantiation of its own.
+int sel_of(const sm_ctx *c) {
+  return (c->p.final_sel == 1 ? 1 : 0) | (c->p.ut_mode == 1 ? 2 : 0);
+}
+
 // Where a batch is matched: inside the seeding kernel, by the workgroup that
 // completes an event, when the main form runs more than four rounds of items
 // (matching then overlaps the seeding tail) or when the batch's mean item
@@ -377,8 +395,13 @@ sm_status fit_batch(sm_ctx *c, Slot &s, const sm_batch &b) {
   return alloc_slot(c, s);
 }
 
-sm_status check_batch(const sm_batch *b, const sm_out *o) {
+sm_status check_batch(const sm_ctx *c, const sm_batch *b, const sm_out *o) {
   if (!b || !o) return SM_ERR_INVALID;
+  // the UT search needs the batch's UT hits (an event may have none)
+  if (c->p.ut_mode == 1 && b->n_events > 0 && !b->ut_off) return SM_ERR_INVALID;
+  if (b->n_ut < 0 || (b->n_ut > 0 && (!b->ut_x || !b->ut_id)) ||
+      (b->n_events > 0 && b->ut_off == nullptr && b->n_ut > 0))
+    return SM_ERR_INVALID;
   if (b->n_events < 0 || b->n_hits < 0 || b->n_velo < 0) return SM_ERR_INVALID;
   if (o->seed_cap < 0 || o->long_cap < 0) return SM_ERR_INVALID;
   if (!o->seed_off || !o->long_off) return SM_ERR_INVALID;
@@ -413,11 +436,11 @@ int enqueue_prepare_big(sm_ctx *c, Slot &s, hipStream_t q) {
   const smk::KCtx *S = s.d_kctx;
   const Desc *d = s.d_desc;
   if (c->p.uv_mode == 0 && !c->cfg.validate)
-    return smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, 1, c->p.final_sel, q);
+    return smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, 1, sel_of(c), q);
   int e = smk_launch_prepare(d, S, 0, q);
   if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
   if (!e && c->p.uv_mode == 0)
-    e = smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, 0, c->p.final_sel, q);
+    e = smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, 0, sel_of(c), q);
   return e;
 }
 
@@ -433,8 +456,8 @@ sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
     if (!e) e = enqueue_prepare_big(c, s, q);
     if (!e && !s.fuse) e = smk_launch_seed_nomatch(d, S, s.grid, s.lds_hits, q);
     if (!e && s.fuse)
-      e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, c->p.final_sel, q);
-    if (!e && !s.fuse) e = smk_launch_match(d, S, match_grid(c, s.grid), c->p.final_sel, q);
+      e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, sel_of(c), q);
+    if (!e && !s.fuse) e = smk_launch_match(d, S, match_grid(c, s.grid), sel_of(c), q);
     if (!e) e = smk_launch_copy(d, S, 1024, q);
     if (!e) e = hipMemcpyAsync(s.h_cnt, s.S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q);
     return (hipError_t)e;
@@ -467,7 +490,7 @@ sm_status enqueue_plain(sm_ctx *c, Slot &s, int n_events, hipStream_t st) {
   int e = smk_launch_prepare(d, S, 1, st);
   if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, st);
   for (int ev = 0; ev < n_events && !e; ++ev)
-    e = smk_launch_seed(d, S, 2 * ev, 2, 0, 2, s.lds_hits, 1, c->p.uv_mode, c->p.final_sel, st);
+    e = smk_launch_seed(d, S, 2 * ev, 2, 0, 2, s.lds_hits, 1, c->p.uv_mode, sel_of(c), st);
   if (!e) e = smk_launch_plain_totals(d, S, st);
   return hip_status((hipError_t)e);
 }
@@ -483,9 +506,9 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   if (!e && !s.fuse) e = smk_launch_seed_nomatch(d, S, s.grid, s.lds_hits, q);
   if (!e) e = hipEventRecord(ev[3], q);
   if (!e && s.fuse)
-    e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, c->p.final_sel, q);
+    e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, sel_of(c), q);
   if (!e) e = hipEventRecord(ev[4], q);
-  if (!e && !s.fuse) e = smk_launch_match(d, S, match_grid(c, s.grid), c->p.final_sel, q);
+  if (!e && !s.fuse) e = smk_launch_match(d, S, match_grid(c, s.grid), sel_of(c), q);
   if (!e) e = hipEventRecord(ev[5], q);
   if (!e) e = smk_launch_copy(d, S, 1024, q);   // offset scans and copy
   if (!e) e = hipEventRecord(ev[6], q);
@@ -538,7 +561,7 @@ bool needs_rerun(sm_ctx *c, Slot &s, sm_status &st) {
 
 sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bool plain,
                        sm_kernel_times *times = nullptr) {
-  sm_status st = check_batch(b, o);
+  sm_status st = check_batch(c, b, o);
   if (st != SM_OK) return st;
   std::lock_guard<std::mutex> lk(c->mu);
   if (hipSetDevice(c->device) != hipSuccess) return SM_ERR_DEVICE;
@@ -717,7 +740,7 @@ void na_fill_kctx(const sm_ctx *c, void *ptr, smk::KCtx &kc) {
 }
 
 sm_status run_noalloc(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream) {
-  sm_status st = check_batch(b, o);
+  sm_status st = check_batch(c, b, o);
   if (st != SM_OK) return st;
   if (b->n_events > kNaEvents || b->n_velo > kNaVelo) return SM_ERR_LIMIT;
   std::lock_guard<std::mutex> lk(c->mu);
@@ -736,7 +759,7 @@ sm_status run_noalloc(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream) {
   if (!e) e = smk_launch_prepare(dd, dk, 0, q);
   if (!e && c->cfg.validate) e = smk_launch_validate(dd, dk, 1024, q);
   if (!e) e = smk_launch_seed_nomatch(dd, dk, kNaWgs, lds, q);
-  if (!e) e = smk_launch_match(dd, dk, kNaWgs, c->p.final_sel, q);
+  if (!e) e = smk_launch_match(dd, dk, kNaWgs, sel_of(c), q);
   if (!e) e = smk_launch_copy(dd, dk, 1024, q);
   if (!e) e = hipMemcpyAsync(c->na_cnt, dc, sizeof(Counters), hipMemcpyDeviceToHost, q);
   if (!e) e = hipStreamSynchronize(q);
@@ -774,6 +797,12 @@ void sm_default_geometry(sm_geometry *g) {
     g->tan_stereo[l] = kind == 1 ? t : (kind == 2 ? -t : 0.0);
   }
   g->z_ref = 8525.0;
+  // UT layers UTaX, UTaU, UTbV, UTbX (positions are a reading: none printed)
+  static const double uz[SM_N_UT] = {2327.5, 2372.5, 2597.5, 2642.5};
+  for (int i = 0; i < SM_N_UT; ++i) {
+    g->ut_z[i] = uz[i];
+    g->ut_tan[i] = i == 1 ? t : (i == 2 ? -t : 0.0);
+  }
 }
 
 void sm_default_params(sm_params *p) {
@@ -821,6 +850,20 @@ void sm_default_params(sm_params *p) {
   p->final_sel = 0;      // no network weights are published (reading)
   p->ghost_cut = 0.8;    // Sec. 4.4
   p->clone_gap = 0.05;   // Sec. 4.4
+  p->ut_mode = 0;        // Sec. 4.3: UT hits are optional
+  p->ut_min_hits = 3;    // more than two
+  p->a_gamma = 7.707063e-11;   // Table 1
+  p->b_gamma = -7.817364e-3;
+  // Table 2 by layer UTaX, UTaU, UTbV, UTbX; UTbX has no loose window and
+  // UTaX no tight one (hi = 0)
+  const double la[SM_N_UT] = {0.8333, 0.8333, 1.3333, 0.0}, lb[SM_N_UT] = {3.3333, 3.3333, 3.3333, 0.0};
+  const double llo[SM_N_UT] = {1.2, 1.2, 1.5, 0.0}, lhi[SM_N_UT] = {8.5, 8.5, 9.5, 0.0};
+  const double ta[SM_N_UT] = {0.0, 0.2, 0.4, 0.4}, tb[SM_N_UT] = {0.0, 0.6, 1.2, 1.2};
+  const double tlo[SM_N_UT] = {0.0, 0.5, 1.0, 1.0}, thi[SM_N_UT] = {0.0, 2.0, 4.0, 4.0};
+  for (int i = 0; i < SM_N_UT; ++i) {
+    p->ut_loose_a[i] = la[i]; p->ut_loose_b[i] = lb[i]; p->ut_loose_lo[i] = llo[i]; p->ut_loose_hi[i] = lhi[i];
+    p->ut_tight_a[i] = ta[i]; p->ut_tight_b[i] = tb[i]; p->ut_tight_lo[i] = tlo[i]; p->ut_tight_hi[i] = thi[i];
+  }
 }
 
 // A usable network: every standardisation scale non-zero and every weight
@@ -851,6 +894,8 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
       c->p.p_min <= 0 || c->p.sigma_x <= 0 || c->p.min_x_hits < 4 || c->p.min_x_hits > 6 ||
       c->p.min_uv_hits < 3 || c->p.min_uv_hits > 6 ||
       (c->p.final_sel != 0 && c->p.final_sel != 1) ||
+      (c->p.ut_mode != 0 && c->p.ut_mode != 1) ||
+      (c->p.ut_mode == 1 && (c->p.ut_min_hits < 1 || c->p.ut_min_hits > SM_N_UT)) ||
       (c->p.final_sel == 1 && (!ghost_nn_ok(c->p.ghost_nn) || !(c->p.clone_gap >= 0.0))) ||
       c->p.invp_a * c->p.invp_a + 4.0 * c->p.invp_b / c->p.p_min < 0 ||
       // the Hough-cluster UV kernel (uv_mode 1) is switched off: one run of
@@ -991,7 +1036,7 @@ static sm_status start_slot(sm_ctx *c, Slot &s) {
 
 sm_status sm_submit(sm_ctx *ctx, const sm_batch *batch, sm_out *out, int64_t *ticket) {
   if (!ctx || !ticket) return SM_ERR_INVALID;
-  sm_status st = check_batch(batch, out);
+  sm_status st = check_batch(ctx, batch, out);
   if (st != SM_OK) return st;
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (hipSetDevice(ctx->device) != hipSuccess) return SM_ERR_DEVICE;

@@ -34,6 +34,17 @@ half 1: y < 0), sorted by x inside each zone.  Hit ids are a seeded
 permutation of 0..n-1 inside each event, so an id never equals a position by
 accident.
 
+UT (Sec. 4.3; a synthetic layer model, the paper gives none): four planar
+layers UTaX, UTaU, UTbV, UTbX at z = 2327.5, 2372.5, 2597.5, 2642.5 mm, with
+stereo angles 0, +5, -5, 0 deg, measuring x - y tan(alpha) + N(0, 0.055 mm)
+(a 190 um pitch).  Between the VELO end-state and the UT a track follows the
+parabola of eq. velo_ut_extrapolation with gamma_x = A_gamma + B_gamma q/p
+(eq. gamma_parametrisation, Table 1), read forwards.  |x| <= 860 mm and
+|y| <= 700 mm at each layer; the same inefficiency and noise fraction as the
+SciFi.  UT hits are grouped by (event, layer), x-sorted, ids a permutation
+inside the event.  They come from a second random stream of the event, so
+every SciFi and VELO array is the same with or without them.
+
 Every event has its own PCG64 stream seeded with
 ``1_000_000 * config + event_index``, so any subset regenerates identically.
 """
@@ -60,6 +71,15 @@ X_ACC = 3200.0           # |x| acceptance at every layer
 Y_ACC_MIN = 2.5          # |y| acceptance (beam hole)
 Y_ACC_MAX = 2500.0
 Z_VELO = 770.0           # z of the VELO end-state
+# UT: UTaX, UTaU, UTbV, UTbX
+N_UT = 4
+UT_Z = np.array([2327.5, 2372.5, 2597.5, 2642.5])
+UT_TAN = np.array([0.0, _T5, -_T5, 0.0])
+UT_SIGMA = 0.055
+UT_X_ACC = 860.0
+UT_Y_ACC = 700.0
+A_GAMMA = 7.707063e-11   # Table 1
+B_GAMMA = -7.817364e-3
 
 # physics constants of the forward model (Sec. 3.3.1 eq. invp, Table 1)
 INVP_A = 1.6322e-7
@@ -127,6 +147,10 @@ class Batch:
     velo_ty: np.ndarray
     velo_id: np.ndarray      # int32 [n_velo]
     truth: dict | None = None
+    # UT hits, grouped by (event, layer) and x-sorted; None: no UT
+    ut_off: np.ndarray | None = None    # int32 [n_events*4 + 1]
+    ut_x: np.ndarray | None = None      # float32 [n_ut]
+    ut_id: np.ndarray | None = None     # int32 [n_ut]
 
     @property
     def n_events(self) -> int:
@@ -139,6 +163,14 @@ class Batch:
     @property
     def n_velo(self) -> int:
         return int(self.velo_off[-1])
+
+    @property
+    def n_ut(self) -> int:
+        return int(self.ut_off[-1]) if self.ut_off is not None else 0
+
+    @property
+    def has_ut(self) -> bool:
+        return self.ut_off is not None
 
     def event_hits(self) -> np.ndarray:
         o = self.zone_off[::ZONES_PER_EVENT]
@@ -156,13 +188,21 @@ class Batch:
             t0, t1 = self.truth["track_off"][e], self.truth["track_off"][e + 1]
             truth = {k: (v[t0:t1] if k != "track_off" else np.array([0, t1 - t0]))
                      for k, v in self.truth.items()}
+        ut = {}
+        if self.ut_off is not None:
+            u0, u1 = int(self.ut_off[e * N_UT]), int(self.ut_off[(e + 1) * N_UT])
+            ut = dict(ut_off=(self.ut_off[e * N_UT:(e + 1) * N_UT + 1] - u0).astype(np.int32),
+                      ut_x=self.ut_x[u0:u1], ut_id=self.ut_id[u0:u1])
         return Batch(
             zone_off=(self.zone_off[z0:z0 + ZONES_PER_EVENT + 1] - h0).astype(np.int32),
             hit_x=self.hit_x[h0:h1], hit_z=self.hit_z[h0:h1], hit_id=self.hit_id[h0:h1],
             velo_off=np.array([0, v1 - v0], np.int32),
             velo_x=self.velo_x[v0:v1], velo_y=self.velo_y[v0:v1],
             velo_z=self.velo_z[v0:v1], velo_tx=self.velo_tx[v0:v1],
-            velo_ty=self.velo_ty[v0:v1], velo_id=self.velo_id[v0:v1], truth=truth)
+            velo_ty=self.velo_ty[v0:v1], velo_id=self.velo_id[v0:v1], truth=truth, **ut)
+
+    def without_ut(self) -> "Batch":
+        return dataclasses.replace(self, ut_off=None, ut_x=None, ut_id=None)
 
 
 def concat(events: list) -> Batch:
@@ -186,6 +226,14 @@ def concat(events: list) -> Batch:
             offs.append(np.asarray(b.truth["track_off"][1:], np.int64) + tbase)
             tbase += len(b.truth["p"])
         truth["track_off"] = np.concatenate(offs)
+    ut = {}
+    if events and all(b.ut_off is not None for b in events):
+        uo, ubase = [np.zeros(1, np.int64)], 0
+        for b in events:
+            uo.append(b.ut_off[1:].astype(np.int64) + ubase)
+            ubase += b.n_ut
+        ut = dict(ut_off=np.concatenate(uo).astype(np.int32), ut_x=cat("ut_x", np.float32),
+                  ut_id=cat("ut_id", np.int32))
     return Batch(zone_off=np.concatenate(zo).astype(np.int32),
                  hit_x=cat("hit_x", np.float32), hit_z=cat("hit_z", np.float32),
                  hit_id=cat("hit_id", np.int32),
@@ -193,7 +241,7 @@ def concat(events: list) -> Batch:
                  velo_x=cat("velo_x", np.float32), velo_y=cat("velo_y", np.float32),
                  velo_z=cat("velo_z", np.float32), velo_tx=cat("velo_tx", np.float32),
                  velo_ty=cat("velo_ty", np.float32), velo_id=cat("velo_id", np.int32),
-                 truth=truth)
+                 truth=truth, **ut)
 
 
 # ------------------------------------------------------------- the physics --
@@ -340,15 +388,51 @@ def generate_event(cfg: GenConfig, e: int, pol: float = POLARITY) -> Batch:
     velo_of_track = np.full(n, -1, np.int64)
     velo_of_track[vtrk[vtrk >= 0]] = np.nonzero(vtrk >= 0)[0]
 
+    ut_off, ut_x, ut_id, ut_hits = _ut_hits(cfg, e, t)
     truth = dict(p=t["p"], q=t["q"], a=t["a"], b=t["b"], c=t["c"], y0=t["y0"],
                  ty=t["ty"], tx=t["tx"], zk=t["zk"], dtx=t["dtx"], hits=thits,
-                 velo=velo_of_track, track_off=np.array([0, n], np.int64))
+                 velo=velo_of_track, ut_hits=ut_hits, track_off=np.array([0, n], np.int64))
     return Batch(zone_off=zone_off, hit_x=hx32, hit_z=hit_z, hit_id=hit_id,
                  velo_off=np.array([0, nv], np.int32),
                  velo_x=vx.astype(np.float32), velo_y=vy.astype(np.float32),
                  velo_z=np.full(nv, Z_VELO, np.float32),
                  velo_tx=vtx.astype(np.float32), velo_ty=vty.astype(np.float32),
-                 velo_id=velo_id, truth=truth)
+                 velo_id=velo_id, truth=truth, ut_off=ut_off, ut_x=ut_x, ut_id=ut_id)
+
+
+def _ut_hits(cfg: GenConfig, e: int, t: dict):
+    """UT hits of one event's tracks (second random stream of the event)."""
+    rng = np.random.Generator(np.random.PCG64(
+        np.random.SeedSequence(1_000_000 * cfg.config_id + e, spawn_key=(1,))))
+    n = len(t["p"])
+    dz = UT_Z[None, :] - Z_VELO
+    xv = t["xo"] + t["tx"] * (Z_VELO - t["zo"])
+    yv = t["yo"] + t["ty"] * (Z_VELO - t["zo"])
+    gam = A_GAMMA + B_GAMMA * t["q"] / t["p"]
+    x = xv[:, None] + t["tx"][:, None] * dz + gam[:, None] * dz * dz
+    y = yv[:, None] + t["ty"][:, None] * dz
+    meas = x - y * UT_TAN[None, :]
+    meas = meas + rng.normal(0.0, UT_SIGMA, meas.shape)
+    keep = (np.abs(x) <= UT_X_ACC) & (np.abs(y) <= UT_Y_ACC)
+    if cfg.ineff > 0:
+        keep &= rng.random(meas.shape) >= cfg.ineff
+    trk = np.repeat(np.arange(n), N_UT).reshape(n, N_UT)
+    lay = np.tile(np.arange(N_UT), (n, 1))
+    hx, hl, ht = meas[keep], lay[keep], trk[keep]
+    n_noise = int(round(cfg.noise * len(hx)))
+    if n_noise:
+        hx = np.concatenate([hx, rng.uniform(-UT_X_ACC, UT_X_ACC, n_noise)])
+        hl = np.concatenate([hl, rng.integers(0, N_UT, n_noise)])
+        ht = np.concatenate([ht, np.full(n_noise, -1)])
+    hx32 = hx.astype(np.float32)
+    order = np.lexsort((np.arange(len(hx32)), hx32, hl))
+    hx32, hl, ht = hx32[order], hl[order], ht[order]
+    ut_off = np.concatenate([[0], np.cumsum(np.bincount(hl, minlength=N_UT))]).astype(np.int32)
+    ut_id = rng.permutation(len(hx32)).astype(np.int32)
+    ut_hits = np.full((n, N_UT), -1, np.int32)
+    sig = ht >= 0
+    ut_hits[ht[sig], hl[sig]] = ut_id[sig]
+    return ut_off, hx32, ut_id, ut_hits
 
 
 def generate(cfg: GenConfig, pol: float = POLARITY) -> Batch:
@@ -391,10 +475,16 @@ def tile(b: Batch, times: int) -> Batch:
     if zo[-1] >= 2 ** 31 or vo[-1] >= 2 ** 31:
         raise ValueError("tiled batch exceeds the int32 offsets of the batch layout")
     rep = lambda a: np.tile(a, times)
+    ut = {}
+    if b.ut_off is not None:
+        nu = b.n_ut
+        uo = np.concatenate([np.zeros(1, np.int64)] +
+                            [b.ut_off[1:].astype(np.int64) + k * nu for k in range(times)])
+        ut = dict(ut_off=uo.astype(np.int32), ut_x=rep(b.ut_x), ut_id=rep(b.ut_id))
     return Batch(zone_off=zo.astype(np.int32), hit_x=rep(b.hit_x), hit_z=rep(b.hit_z),
                  hit_id=rep(b.hit_id), velo_off=vo.astype(np.int32), velo_x=rep(b.velo_x),
                  velo_y=rep(b.velo_y), velo_z=rep(b.velo_z), velo_tx=rep(b.velo_tx),
-                 velo_ty=rep(b.velo_ty), velo_id=rep(b.velo_id), truth=None)
+                 velo_ty=rep(b.velo_ty), velo_id=rep(b.velo_id), truth=None, **ut)
 
 
 def empty_event() -> Batch:
@@ -404,6 +494,8 @@ def empty_event() -> Batch:
                  velo_x=np.zeros(0, np.float32), velo_y=np.zeros(0, np.float32),
                  velo_z=np.zeros(0, np.float32), velo_tx=np.zeros(0, np.float32),
                  velo_ty=np.zeros(0, np.float32), velo_id=np.zeros(0, np.int32),
-                 truth={k: np.zeros((0, 12) if k == "hits" else 0)
+                 truth={k: np.zeros((0, 12) if k == "hits" else ((0, 4) if k == "ut_hits" else 0))
                         for k in ("p", "q", "a", "b", "c", "y0", "ty", "tx", "zk",
-                                  "dtx", "hits", "velo")} | {"track_off": np.array([0, 0])})
+                                  "dtx", "hits", "velo", "ut_hits")} | {"track_off": np.array([0, 0])},
+                 ut_off=np.zeros(N_UT + 1, np.int32), ut_x=np.zeros(0, np.float32),
+                 ut_id=np.zeros(0, np.int32))

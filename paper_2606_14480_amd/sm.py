@@ -14,6 +14,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsm.so")
 NL = 12
+NUT = 4
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -41,7 +42,8 @@ class SmError(RuntimeError):
 
 
 class Geometry(C.Structure):
-    _fields_ = [("z", C.c_double * NL), ("tan_stereo", C.c_double * NL), ("z_ref", C.c_double)]
+    _fields_ = [("z", C.c_double * NL), ("tan_stereo", C.c_double * NL), ("z_ref", C.c_double),
+                ("ut_z", C.c_double * NUT), ("ut_tan", C.c_double * NUT)]
 
 
 NN_INPUTS, NN_HIDDEN = 8, 32
@@ -91,7 +93,13 @@ class Params(C.Structure):
                 ("polarity", C.c_double), ("uv_mode", C.c_int32), ("hough_bins", C.c_int32),
                 ("hough_best", C.c_int32), ("hough_fine", C.c_int32), ("hough_min", C.c_int32),
                 ("pad2", C.c_int32), ("final_sel", C.c_int32), ("pad3", C.c_int32),
-                ("ghost_cut", C.c_double), ("clone_gap", C.c_double), ("ghost_nn", GhostNN)]
+                ("ghost_cut", C.c_double), ("clone_gap", C.c_double), ("ghost_nn", GhostNN),
+                ("ut_mode", C.c_int32), ("ut_min_hits", C.c_int32),
+                ("a_gamma", C.c_double), ("b_gamma", C.c_double)] + \
+               [(f"ut_{k}_{w}", C.c_double * NUT) for k in ("loose", "tight")
+                for w in ("a", "b", "lo", "hi")]
+
+    ARRAYS = ("zm",) + tuple(f"ut_{k}_{w}" for k in ("loose", "tight") for w in ("a", "b", "lo", "hi"))
 
 
 class Config(C.Structure):
@@ -105,7 +113,9 @@ class Batch(C.Structure):
                 ("n_velo", C.c_int64), ("zone_off", C.c_void_p), ("hit_x", C.c_void_p),
                 ("hit_z", C.c_void_p), ("hit_id", C.c_void_p), ("velo_off", C.c_void_p),
                 ("velo_x", C.c_void_p), ("velo_y", C.c_void_p), ("velo_z", C.c_void_p),
-                ("velo_tx", C.c_void_p), ("velo_ty", C.c_void_p), ("velo_id", C.c_void_p)]
+                ("velo_tx", C.c_void_p), ("velo_ty", C.c_void_p), ("velo_id", C.c_void_p),
+                ("n_ut", C.c_int64), ("ut_off", C.c_void_p), ("ut_x", C.c_void_p),
+                ("ut_id", C.c_void_p)]
 
 
 class Shape(C.Structure):
@@ -137,8 +147,8 @@ SEED_DTYPE = np.dtype([("ax", "f4"), ("bx", "f4"), ("cx", "f4"), ("y0", "f4"), (
 LONG_DTYPE = np.dtype([("velo_idx", "i4"), ("seed_idx", "i4"), ("velo_id", "i4"),
                        ("qop", "f4"), ("chi2", "f4"), ("z_match", "f4"), ("dx", "f4"),
                        ("dy", "f4"), ("dtx", "f4"), ("dty", "f4"), ("ghost_prob", "f4"),
-                       ("pad", "i4")])
-assert SEED_DTYPE.itemsize == 96 and LONG_DTYPE.itemsize == 48
+                       ("n_ut", "i4"), ("ut_hits", "i4", NUT)])
+assert SEED_DTYPE.itemsize == 96 and LONG_DTYPE.itemsize == 64
 
 _lib = C.CDLL(LIB_PATH)
 _P = C.POINTER
@@ -194,9 +204,9 @@ def default_params(**over) -> Params:
     p = Params()
     _lib.sm_default_params(C.byref(p))
     for k, v in over.items():
-        if k == "zm":
+        if k in Params.ARRAYS:
             for i, x in enumerate(v):
-                p.zm[i] = x
+                getattr(p, k)[i] = x
         elif k == "ghost_nn":
             _set_ghost_nn(p.ghost_nn, v)
         else:
@@ -226,13 +236,21 @@ class DeviceBatch:
         self.velo_id = t(host.velo_id, torch.int32)
         self.n_hits = int(host.n_hits)
         self.n_velo = int(host.n_velo)
+        # UT hits, when the host batch has them (read only with ut_mode 1)
+        has_ut = getattr(host, "ut_off", None) is not None
+        self.ut_off = t(host.ut_off, torch.int32) if has_ut else None
+        self.ut_x = t(host.ut_x, torch.float32) if has_ut else None
+        self.ut_id = t(host.ut_id, torch.int32) if has_ut else None
+        self.n_ut = int(host.ut_off[-1]) if has_ut else 0
+        ptr = lambda a: a.data_ptr() if a is not None else None
         self.c = Batch(n_events=self.n_events, pad=0, n_hits=self.n_hits, n_velo=self.n_velo,
                        zone_off=self.zone_off.data_ptr(), hit_x=self.hit_x.data_ptr(),
                        hit_z=self.hit_z.data_ptr(), hit_id=self.hit_id.data_ptr(),
                        velo_off=self.velo_off.data_ptr(), velo_x=self.velo_x.data_ptr(),
                        velo_y=self.velo_y.data_ptr(), velo_z=self.velo_z.data_ptr(),
                        velo_tx=self.velo_tx.data_ptr(), velo_ty=self.velo_ty.data_ptr(),
-                       velo_id=self.velo_id.data_ptr())
+                       velo_id=self.velo_id.data_ptr(), n_ut=self.n_ut, ut_off=ptr(self.ut_off),
+                       ut_x=ptr(self.ut_x), ut_id=ptr(self.ut_id))
 
 
 class DeviceOut:

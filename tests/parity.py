@@ -136,6 +136,14 @@ def compare(orc_res, gpu, n_events, band=None, events=None):
                     st["param_fail"].append(("long", e, fo, float(old[k][fo]), float(gld[k][fg])))
             if int(old[k]["velo_id"]) != int(gld[k]["velo_id"]):
                 st["param_fail"].append(("long", e, "velo_id", 0, 0))
+            # UT hits (ut_mode 1): the same hits, unless a UT choice of the
+            # track was within MARGIN of going the other way
+            if "ut_hits" in gld[k].dtype.names:
+                same = int(old[k]["n_ut"]) == int(gld[k]["n_ut"]) and \
+                    list(old[k]["ut_id"]) == list(gld[k]["ut_hits"])
+                if not same and not float(old[k]["margin"]) < MARGIN:
+                    st["param_fail"].append(("long", e, "ut_hits", list(old[k]["ut_id"]),
+                                             list(gld[k]["ut_hits"])))
         diff_s = (osd.keys() ^ gsd.keys())
         diff_l = (old.keys() ^ gld.keys())
         st["mismatches"] += len(diff_s) + len(diff_l)

@@ -489,3 +489,40 @@ def test_ghost_network_selection(orc, sm, ctx, net):
         # network form may keep near-equal pairs on one segment
         ref = gpu_run(sm, ctx, b)
         assert np.all(ref[3]["ghost_prob"] == -1.0)
+
+
+@pytest.mark.parametrize("variant", ["ut", "ut+ghost"])
+def test_ut_search_parity(orc, sm, ctx, variant):
+    """The UT hit search (Sec. 4.3) against the oracle on 300 min-bias events
+    with UT hits: long tracks, their UT hit ids and counts; alone and with the
+    network form of the final selection.  Matching in its own kernel and
+    inside the seeding kernel, and the per-event form, give the same bytes.
+    Without UT hits in the batch the call is refused."""
+    b = ev.generate(ev.config(2, n_events=300))
+    over = dict(ut_mode=1)
+    if variant == "ut+ghost":
+        over.update(final_sel=1, ghost_nn=sm.ghost_nn_weights())
+    c = sm.Context(params=sm.default_params(**over))
+    try:
+        g, o, st = check(orc, sm, c, b, f"UT search ({variant})", params_over=over)
+        assert st["longs_common"] > 10000
+        assert np.all(g[3]["n_ut"] >= 3)
+        assert np.all((g[3]["ut_hits"] >= 0).sum(axis=1) == g[3]["n_ut"])
+        gpl = gpu_run(sm, c, b, plain=True)
+        for x, y in zip(g, gpl):
+            assert x.tobytes() == y.tobytes()
+        with pytest.raises(sm.SmError):
+            gpu_run(sm, c, b.without_ut())
+    finally:
+        c.close()
+    cf = sm.Context(params=sm.default_params(**over), match_wgs=-1)
+    try:
+        gf = gpu_run(sm, cf, b)
+        for x, y in zip(g, gf):
+            assert x.tobytes() == y.tobytes()
+    finally:
+        cf.close()
+    # the default context ignores the UT hits
+    ref = gpu_run(sm, ctx, b)
+    assert np.all(ref[3]["n_ut"] == 0) and np.all(ref[3]["ut_hits"] == -1)
+    assert len(ref[3]) > len(g[3])

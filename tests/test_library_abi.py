@@ -29,9 +29,9 @@ def test_exports_every_declared_symbol():
 def test_struct_layouts():
     from paper_2606_14480_amd import sm
     assert sm.SEED_DTYPE.itemsize == 96
-    assert sm.LONG_DTYPE.itemsize == 48
+    assert sm.LONG_DTYPE.itemsize == 64
     assert ctypes.sizeof(sm.GhostNN) == 8 * (8 + 8 + 32 * 8 + 32 + 32 + 1)
-    assert ctypes.sizeof(sm.Batch) == 8 + 16 + 11 * 8
+    assert ctypes.sizeof(sm.Batch) == 8 + 16 + 11 * 8 + 8 + 3 * 8
     assert ctypes.sizeof(sm.Out) == 64
 
 
@@ -42,8 +42,8 @@ def test_defaults_agree_with_oracle(orc):
         if name.startswith("pad"):
             continue
         a, b = getattr(p, name), getattr(q, name)
-        if name == "zm":
-            assert list(a) == list(b)
+        if name in sm.Params.ARRAYS:
+            assert list(a) == list(b), name
         elif name == "ghost_nn":
             assert bytes(a) == bytes(b)
         else:
@@ -51,6 +51,9 @@ def test_defaults_agree_with_oracle(orc):
     g, h = sm.default_geometry(), orc.default_geom()
     assert list(g.z) == list(h.z) == list(events.LAYER_Z)
     assert list(g.tan_stereo) == list(h.tan_a)
+    assert list(g.ut_z) == list(h.ut_z) == list(events.UT_Z)
+    assert list(g.ut_tan) == list(h.ut_tan)
+    np.testing.assert_allclose(list(g.ut_tan), events.UT_TAN, rtol=1e-15)
     np.testing.assert_allclose(list(g.tan_stereo), events.LAYER_TAN, rtol=1e-15)
     assert g.z_ref == h.z_ref == events.Z_REF
 
@@ -80,6 +83,16 @@ def test_create_rejects_bad_uv_settings():
     for over in (dict(uv_mode=2), dict(uv_mode=1), dict(uv_mode=1, hough_bins=0), dict(uv_mode=1, hough_bins=129),
                  dict(uv_mode=1, hough_best=16, hough_fine=8), dict(uv_mode=1, hough_min=0),
                  dict(uv_mode=1, hough_fine=0)):
+        p = sm.default_params(**over)
+        h = ctypes.c_void_p()
+        assert lib.sm_create(None, ctypes.byref(p), None, ctypes.byref(h)) == sm.ERR_INVALID, over
+        assert not h.value
+
+
+def test_create_rejects_bad_ut_settings():
+    from paper_2606_14480_amd import sm
+    lib = sm.lib()
+    for over in (dict(ut_mode=2), dict(ut_mode=1, ut_min_hits=0), dict(ut_mode=1, ut_min_hits=5)):
         p = sm.default_params(**over)
         h = ctypes.c_void_p()
         assert lib.sm_create(None, ctypes.byref(p), None, ctypes.byref(h)) == sm.ERR_INVALID, over
