@@ -35,7 +35,8 @@ constexpr int kVflat = 256;         // VELO states per event for the flattened p
 constexpr int kPvLds = 2048;        // flattened pairs whose VELO state is looked up in LDS
 constexpr int kVsLds = 512;         // VELO states per event with LDS best-chi2 entries
 constexpr int kSurvLds = 512;       // matching survivors kept in LDS
-constexpr int kUtLds = 1024;        // UT hits per event staged in LDS (UT search)
+constexpr int kUtLds = 3 * kMsLds;  // UT hits per event staged in LDS (UT search), in the
+                                    // six per-seed prefilter arrays of the matching state
 constexpr int kPosBits = 21;        // item-relative hit positions < 2^21
 constexpr int kPoolPerItem = 128;   // seed-pool slots of each item (more: the overflow area)
 constexpr int kMaxItemHits = 1 << kPosBits;

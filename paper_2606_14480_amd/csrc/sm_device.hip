@@ -1335,6 +1335,8 @@ __device__ __forceinline__ int ut_search(const DevParams &P, FX X, FI ID,
 }
 
 struct MatchShared {
+  // per-seed prefilter state; after the prefilter pass it holds the event's
+  // UT hits (x, then id) in the UT search variant
   float xsf[kMsLds], txsf[kMsLds], ymf[kMsLds], tyf[kMsLds], sty[kMsLds];
   int sidx[kMsLds];
   unsigned long long best_s[kMsLds];
@@ -1351,6 +1353,10 @@ struct MatchShared {
   unsigned nsurv, nkeep, nplist;
   unsigned long long lbase;
 };
+// the UT hits' LDS home: the six per-seed prefilter arrays, contiguous
+static_assert(offsetof(MatchShared, sidx) == offsetof(MatchShared, xsf) + 5 * kMsLds * sizeof(float) &&
+                  2 * kUtLds * sizeof(float) == 6 * kMsLds * sizeof(float),
+              "the UT hits overlay xsf .. sidx");
 
 // zone offsets non-decreasing from 0, hits x-sorted inside each zone
 __global__ __launch_bounds__(256) void k_validate(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
@@ -1429,27 +1435,16 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     vtxr = gmem(D->b.velo_tx)[v0 + tid];
     vtyr = gmem(D->b.velo_ty)[v0 + tid];
   }
-  // UT search variant: the event's UT layer offsets and, when they fit, its UT
-  // hits in LDS after the matching state (offsets then relative to the first)
+  // UT search variant: the event's UT layer offsets (into the batch's UT
+  // arrays until the hits are staged in LDS, see below)
   constexpr bool kUt = (kSel & 2) != 0;
   int ut_o[SM_N_UT + 1] = {};
   bool ut_lds = false;
-  float *ut_xs = reinterpret_cast<float *>(reinterpret_cast<unsigned char *>(&sh) + sizeof(MatchShared));
-  int32_t *ut_ids = reinterpret_cast<int32_t *>(ut_xs + kUtLds);
+  float *ut_xs = sh.xsf;
+  int32_t *ut_ids = reinterpret_cast<int32_t *>(sh.xsf + kUtLds);
   if constexpr (kUt) {
 #pragma unroll
     for (int k = 0; k <= SM_N_UT; ++k) ut_o[k] = gmem(D->b.ut_off)[(size_t)e * SM_N_UT + k];
-    const int nu = ut_o[SM_N_UT] - ut_o[0];
-    ut_lds = nu <= kUtLds;
-    if (ut_lds) {
-      const int u0 = ut_o[0];
-      for (int i = tid; i < nu; i += NT) {
-        ut_xs[i] = gmem(D->b.ut_x)[u0 + i];
-        ut_ids[i] = gmem(D->b.ut_id)[u0 + i];
-      }
-#pragma unroll
-      for (int k = 0; k <= SM_N_UT; ++k) ut_o[k] -= u0;
-    }
   }
   // UT hits of a pair (its q/p from the evaluation)
   auto ut_of = [&](double xv, double yv, double zv, double txv, double tyv, double qop,
@@ -1571,6 +1566,23 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
         atomicMin(&best_v[v], bits);
     }
     __syncthreads();
+    if constexpr (kUt) {
+      // the prefilter's per-seed arrays are dead from here on: the event's UT
+      // hits move into them when they fit (offsets then relative to the
+      // first), so that the searches of pass 2 and of the output read LDS
+      const int nu = ut_o[SM_N_UT] - ut_o[0];
+      if (nu <= kUtLds) {
+        const int u0 = ut_o[0];
+        for (int i = tid; i < nu; i += NT) {
+          ut_xs[i] = gmem(D->b.ut_x)[u0 + i];
+          ut_ids[i] = gmem(D->b.ut_id)[u0 + i];
+        }
+#pragma unroll
+        for (int k = 0; k <= SM_N_UT; ++k) ut_o[k] -= u0;
+        ut_lds = true;
+        __syncthreads();
+      }
+    }
     // pass 2: the FP64 evaluation of the listed pairs
     const unsigned np = sh.nplist < kPlist ? sh.nplist : kPlist;
     for (unsigned i = tid; i < np; i += NT) {
@@ -2274,9 +2286,7 @@ __global__ void k_plain_totals(const Desc *__restrict__ D, const KCtx *__restric
 
 using namespace smk;
 
-static size_t match_lds_bytes(int sel) {
-  return sizeof(MatchShared) + ((sel & 2) ? (size_t)kUtLds * (sizeof(float) + sizeof(int32_t)) : 0);
-}
+static size_t match_lds_bytes(int) { return sizeof(MatchShared); }
 size_t smk_seed_lds_bytes(int lds_hits, int sel) {
   const size_t a = sizeof(SeedShared<kSeedWG>) + (size_t)lds_hits * 3 * sizeof(float);
   return a > match_lds_bytes(sel) ? a : match_lds_bytes(sel);
