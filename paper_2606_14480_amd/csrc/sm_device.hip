@@ -1802,29 +1802,42 @@ __device__ __forceinline__ unsigned prepare_batch(const Desc *__restrict__ D,
   for (int f = threadIdx.x; f < kFineCls; f += blockDim.x) fh[f] = 0;
   __syncthreads();
   auto latency = [&](float nh) { return lat_a * nh + lat_b * nh * nh; };
-  // the zone offsets of the first kPrepCache * blockDim items stay in
-  // registers from one load for both passes below; later items are reloaded
+  // The zone offsets of the first kPrepCache * blockDim items stay in
+  // registers for both passes below; later items are reloaded.  The item
+  // sizes need only the first and last offset: those two loads go first, and
+  // the eleven in between only after the histogram, so that the statistics
+  // do not wait behind them (thirteen loads 48 B apart per thread queue up
+  // in the workgroup's memory path) and the middle ones stream in while the
+  // cut and the order's scan run.
   constexpr int kPrepCache = 2;
   int zc[kPrepCache][kNL + 1];
 #pragma unroll
   for (int c = 0; c < kPrepCache; ++c) {
     const int i = c * (int)blockDim.x + (int)threadIdx.x;
-#pragma unroll
-    for (int k = 0; k <= kNL; ++k) zc[c][k] = i < n ? zo[i * kNL + k] : 0;
+    zc[c][0] = i < n ? zo[i * kNL] : 0;
+    zc[c][kNL] = i < n ? zo[i * kNL + kNL] : 0;
   }
-  auto stat = [&](int i, const int (&z)[kNL + 1]) {
-    if (i < n) atomicAdd(&fh[fine_class(max(z[kNL] - z[0], 0))], 1);
+  auto stat = [&](int i, int z0, int z1) {
+    if (i < n) atomicAdd(&fh[fine_class(max(z1 - z0, 0))], 1);
   };
   auto reload = [&](int i, int (&z)[kNL + 1]) {
 #pragma unroll
     for (int k = 0; k <= kNL; ++k) z[k] = i < n ? zo[i * kNL + k] : 0;
   };
 #pragma unroll
-  for (int c = 0; c < kPrepCache; ++c) stat(c * (int)blockDim.x + (int)threadIdx.x, zc[c]);
+  for (int c = 0; c < kPrepCache; ++c)
+    stat(c * (int)blockDim.x + (int)threadIdx.x, zc[c][0], zc[c][kNL]);
   for (int i0 = kPrepCache * (int)blockDim.x; i0 < n; i0 += blockDim.x) {
-    int z[kNL + 1];
-    reload(i0 + (int)threadIdx.x, z);
-    stat(i0 + (int)threadIdx.x, z);
+    const int i = i0 + (int)threadIdx.x;
+    stat(i, i < n ? zo[i * kNL] : 0, i < n ? zo[i * kNL + kNL] : 0);
+  }
+  // no memory access moves above this point
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int c = 0; c < kPrepCache; ++c) {
+    const int i = c * (int)blockDim.x + (int)threadIdx.x;
+#pragma unroll
+    for (int k = 1; k < kNL; ++k) zc[c][k] = i < n ? zo[i * kNL + k] : 0;
   }
   __syncthreads();
   // the cut: wave 0, one lane per octave; its count, summed latency and
@@ -1836,16 +1849,19 @@ __device__ __forceinline__ unsigned prepare_batch(const Desc *__restrict__ D,
     const bool v = b < 32;
     float ws = 0.0f, lm = 0.0f;
     if (v) {
+      // the octave's sixteen counts in one go (independent LDS reads)
+      int cnt[kFineSub];
+#pragma unroll
+      for (int j = 0; j < kFineSub; ++j) cnt[j] = fh[b * kFineSub + j];
+#pragma unroll
       for (int j = 0; j < kFineSub; ++j) {
-        const int c = fh[b * kFineSub + j];
-        if (c == 0) continue;
         // largest size of fine class (b, j): sizes + 1 in [2^b (1 + j/16),
         // 2^b (1 + (j+1)/16)) from octave 4 up, exact below
         const float top = b >= 4 ? ldexpf(1.0f + (float)(j + 1) / kFineSub, b) - 2.0f
                                  : (float)((1 << b) + (j >> (4 - b)) - 1);
         const float l = latency(top);
-        ws += (float)c * l;
-        lm = l;   // classes ascend in size
+        ws += (float)cnt[j] * l;
+        lm = cnt[j] ? l : lm;   // classes ascend in size
       }
     }
     float wtot = ws, lall = lm, pre = lm, wsuf = ws, lsuf = lm;
