@@ -427,14 +427,14 @@ def main():
         "gpu_events_per_s": round(host.n_events / (kern["total"] * 1e-3), 1),
         "parity": parity,
         "roofline": {"bound": "hbm",
-                     "kernel": "k_seed<0, 256, %s> (seeding, main form%s)"
+                     "kernel": "k_seed<0, 256, %s, 0> (seeding, main form%s)"
                                % (("true", ", matching inside") if fused else ("false", "")),
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": None if fused else measured_traffic(),
                      "alg_bytes_per_launch": alg_bytes,
                      "counters": None if fused else measured_sq()},
-        "roofline_match": {"bound": "hbm", "kernel": "k_match",
+        "roofline_match": {"bound": "hbm", "kernel": "k_match<0>",
                            "achieved": round(m_achieved, 2) if m_achieved else None,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(m_achieved / HBM_PEAK_GBS, 5) if m_achieved else None,
