@@ -26,9 +26,11 @@
 static const int X_LAYERS[6] = {0, 3, 4, 7, 8, 11};
 static const int UV_LAYERS[6] = {1, 2, 5, 6, 9, 10};
 /* READING: iteration 0 starts from the first x-layer of each station,
- * iteration 1 from the last one (disjoint sets, Sec. 3.3). Order T1, T2, T3. */
-static const int INIT_LAYERS[2][3] = {{0, 4, 8}, {3, 7, 11}};
-static const int EXT_LAYERS[2][3] = {{3, 7, 11}, {0, 4, 8}};
+ * iteration 1 from the last one (disjoint sets, Sec. 3.3). Order T1, T2, T3.
+ * The optional third iteration (after the clean-up) uses iteration 0's
+ * layers. */
+static const int INIT_LAYERS[3][3] = {{0, 4, 8}, {3, 7, 11}, {0, 4, 8}};
+static const int EXT_LAYERS[3][3] = {{3, 7, 11}, {0, 4, 8}, {3, 7, 11}};
 
 void orc_default_geom(orc_geom *g) {
   static const double z[ORC_NL] = {7826.0, 7896.0, 7966.0, 8036.0, 8527.5, 8597.5,
@@ -96,6 +98,8 @@ void orc_default_params(orc_params *p) {
   p->final_sel = 0;           /* READING: no network weights are published */
   p->ghost_cut = 0.8;         /* Sec. 4.4: ghost probability < 0.8 */
   p->clone_gap = 0.05;        /* Sec. 4.4: clone if at least 0.05 higher */
+  p->third_iter = 0;          /* Sec. 3: the HLT1 form runs two iterations */
+  p->p_min3 = 1500.0;         /* READING: the third iteration's windows open for 1.5 GeV/c */
   p->ut_mode = 0;             /* Sec. 4.3: UT hits are optional */
   p->ut_min_hits = 3;         /* Sec. 4.3: more than two UT hits */
   p->a_gamma = 7.707063e-11;  /* Table 1 */
@@ -254,9 +258,10 @@ static void fit_line(const double *z, const double *y, const double *w, int n, d
 static void window_constants(const orc_geom *g, const orc_params *P, int it, double out[2]) {
   const double z1 = g->z[INIT_LAYERS[it][0]], z3 = g->z[INIT_LAYERS[it][2]];
   const double a = P->invp_a, b = P->invp_b;
-  out[0] = (z3 - z1) / (2.0 * z1 * b) * (-a + sqrt(a * a + 4.0 * b / P->p_min));
+  const double pm = it == 2 ? P->p_min3 : P->p_min;
+  out[0] = (z3 - z1) / (2.0 * z1 * b) * (-a + sqrt(a * a + 4.0 * b / pm));
   const double k = z1 / (z3 - z1);
-  out[1] = P->alpha0 / (k * (P->p_min - P->alpha1));
+  out[1] = P->alpha0 / (k * (pm - P->alpha1));
 }
 
 /* Geometric factor of the third hit (Sec. 3.3.3), READING: the exact one of
@@ -1122,6 +1127,54 @@ static int match_event(const orc_geom *g, const orc_params *P, const orc_seed *s
 
 typedef struct { dyn seeds, longs, near; } ev_out;
 
+/* Seeding of one event half with the x-z iterations it0..it1 (Sec. 3.3):
+ * candidates, the clone vote over all of them (which also drops a repeated
+ * iteration-1 track), UV seeding of the survivors; seeds are appended to
+ * o->seeds. */
+static void seed_half(const orc_geom *g, const orc_params *P, const int32_t *off, const float *X,
+                      const float *Z, const int32_t *ID, int half, int it0, int it1, int event,
+                      ev_out *o) {
+  const int n_pos = off[24];
+  dyn c = {NULL, 0, 0, sizeof(orc_cand)};
+  for (int it = it0; it <= it1; ++it) xz_iteration(g, P, off, X, Z, half, it, &c);
+  /* the clone vote sees the candidates that passed the fit; those the fit
+   * or the x-hit count rejected by a narrow margin are near misses, and
+   * the fit's near misses are also rivals in the vote margins */
+  const orc_cand *all = (const orc_cand *)c.p;
+  orc_cand *rv = (orc_cand *)malloc(sizeof(orc_cand) * (size_t)(c.n > 0 ? c.n : 1));
+  double *xzm = (double *)malloc(sizeof(double) * (size_t)(c.n > 0 ? c.n : 1));
+  int m = 0, nr;
+  for (int i = 0; i < c.n; ++i)
+    if (all[i].status == 0) { rv[m] = all[i]; xzm[m] = all[i].margin; ++m; }
+  nr = m;
+  for (int i = 0; i < c.n; ++i) {
+    if (all[i].status == 0 || !(all[i].margin < ORC_NEAR)) continue;
+    push_near(&o->near, event, 1, -1, &all[i], NULL, ID, all[i].margin);
+    if (all[i].status == 2) { rv[nr] = all[i]; xzm[nr] = all[i].margin; ++nr; }
+  }
+  orc_cand *cs = rv;   /* the voters: rv[0, m) */
+  int32_t *keep = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+  double *vm = (double *)malloc(sizeof(double) * (size_t)(nr > 0 ? nr : 1));
+  orc_clone_vote(cs, m, n_pos, keep);
+  vote_margins(rv, nr, m, n_pos, xzm, vm);
+  for (int i = 0; i < m; ++i) {
+    cs[i].margin = fmin(cs[i].margin, vm[i]);
+    if (!keep[i]) {
+      if (cs[i].margin < ORC_NEAR) push_near(&o->near, event, 2, -1, &cs[i], NULL, ID, cs[i].margin);
+      continue;
+    }
+    orc_seed sd;
+    const int made = P->uv_mode == 1 ? orc_uv(g, P, off, X, Z, ID, &cs[i], &sd)
+                                     : uv_iterative(g, P, off, X, Z, ID, &cs[i], &sd, &o->near, event);
+    if (made) *(orc_seed *)dyn_push(&o->seeds) = sd;
+  }
+  free(keep);
+  free(vm);
+  free(xzm);
+  free(rv);
+  free(c.p);
+}
+
 static void run_event(const orc_geom *g, const orc_params *P, const int32_t *off,
                       const float *X, const float *Z, const int32_t *ID, int nv,
                       const float *vx, const float *vy, const float *vz, const float *vtx,
@@ -1131,46 +1184,38 @@ static void run_event(const orc_geom *g, const orc_params *P, const int32_t *off
   o->longs = (dyn){NULL, 0, 0, sizeof(orc_long)};
   o->near = (dyn){NULL, 0, 0, sizeof(orc_near)};
   const int n_pos = off[24];
-  for (int half = 0; half < 2; ++half) {
-    dyn c = {NULL, 0, 0, sizeof(orc_cand)};
-    xz_iteration(g, P, off, X, Z, half, 0, &c);
-    xz_iteration(g, P, off, X, Z, half, 1, &c);
-    /* the clone vote sees the candidates that passed the fit; those the fit
-     * or the x-hit count rejected by a narrow margin are near misses, and
-     * the fit's near misses are also rivals in the vote margins */
-    const orc_cand *all = (const orc_cand *)c.p;
-    orc_cand *rv = (orc_cand *)malloc(sizeof(orc_cand) * (size_t)(c.n > 0 ? c.n : 1));
-    double *xzm = (double *)malloc(sizeof(double) * (size_t)(c.n > 0 ? c.n : 1));
-    int m = 0, nr;
-    for (int i = 0; i < c.n; ++i)
-      if (all[i].status == 0) { rv[m] = all[i]; xzm[m] = all[i].margin; ++m; }
-    nr = m;
-    for (int i = 0; i < c.n; ++i) {
-      if (all[i].status == 0 || !(all[i].margin < ORC_NEAR)) continue;
-      push_near(&o->near, event, 1, -1, &all[i], NULL, ID, all[i].margin);
-      if (all[i].status == 2) { rv[nr] = all[i]; xzm[nr] = all[i].margin; ++nr; }
+  for (int half = 0; half < 2; ++half) seed_half(g, P, off, X, Z, ID, half, 0, 1, event, o);
+  if (P->third_iter == 1) {
+    /* Clean-up (Sec. 3): the hits of every seed found so far leave the
+     * event; the third iteration runs on what is left, in arrays of their
+     * own (zones and x order kept), and its seeds' positions are mapped back
+     * to the event's. */
+    const int ns1 = o->seeds.n;
+    char *used = (char *)calloc((size_t)(n_pos > 0 ? n_pos : 1), 1);
+    for (int i = 0; i < ns1; ++i) {
+      const orc_seed *sd = &((const orc_seed *)o->seeds.p)[i];
+      for (int l = 0; l < ORC_NL; ++l)
+        if (sd->pos[l] >= 0) used[sd->pos[l]] = 1;
     }
-    orc_cand *cs = rv;   /* the voters: rv[0, m) */
-    int32_t *keep = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
-    double *vm = (double *)malloc(sizeof(double) * (size_t)(nr > 0 ? nr : 1));
-    orc_clone_vote(cs, m, n_pos, keep);
-    vote_margins(rv, nr, m, n_pos, xzm, vm);
-    for (int i = 0; i < m; ++i) {
-      cs[i].margin = fmin(cs[i].margin, vm[i]);
-      if (!keep[i]) {
-        if (cs[i].margin < ORC_NEAR) push_near(&o->near, event, 2, -1, &cs[i], NULL, ID, cs[i].margin);
-        continue;
-      }
-      orc_seed sd;
-      const int made = P->uv_mode == 1 ? orc_uv(g, P, off, X, Z, ID, &cs[i], &sd)
-                                       : uv_iterative(g, P, off, X, Z, ID, &cs[i], &sd, &o->near, event);
-      if (made) *(orc_seed *)dyn_push(&o->seeds) = sd;
+    float *X2 = (float *)malloc(sizeof(float) * (size_t)(n_pos > 0 ? n_pos : 1));
+    float *Z2 = (float *)malloc(sizeof(float) * (size_t)(n_pos > 0 ? n_pos : 1));
+    int32_t *ID2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_pos > 0 ? n_pos : 1));
+    int32_t *from = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_pos > 0 ? n_pos : 1));
+    int32_t off2[25];
+    int k = 0;
+    for (int zn = 0; zn < 24; ++zn) {
+      off2[zn] = k;
+      for (int i = off[zn]; i < off[zn + 1]; ++i)
+        if (!used[i]) { X2[k] = X[i]; Z2[k] = Z[i]; ID2[k] = ID[i]; from[k] = i; ++k; }
     }
-    free(keep);
-    free(vm);
-    free(xzm);
-    free(rv);
-    free(c.p);
+    off2[24] = k;
+    for (int half = 0; half < 2; ++half) seed_half(g, P, off2, X2, Z2, ID2, half, 2, 2, event, o);
+    for (int i = ns1; i < o->seeds.n; ++i) {
+      orc_seed *sd = &((orc_seed *)o->seeds.p)[i];
+      for (int l = 0; l < ORC_NL; ++l)
+        if (sd->pos[l] >= 0) sd->pos[l] = from[sd->pos[l]];
+    }
+    free(used); free(X2); free(Z2); free(ID2); free(from);
   }
   const int ns = o->seeds.n;
   if (ns > 0 && nv > 0) {

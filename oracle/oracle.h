@@ -99,6 +99,16 @@ typedef struct {
   double a_gamma, b_gamma;
   double ut_loose_a[ORC_NUT], ut_loose_b[ORC_NUT], ut_loose_lo[ORC_NUT], ut_loose_hi[ORC_NUT];
   double ut_tight_a[ORC_NUT], ut_tight_b[ORC_NUT], ut_tight_lo[ORC_NUT], ut_tight_hi[ORC_NUT];
+  /* Third x-z iteration with clean-up (Sec. 3: the HLT2 form cleans the
+   * environment between iterations and opens wider windows for lower
+   * momenta; the HLT1 form runs two).  third_iter 1: after iterations 0 and
+   * 1, every hit on one of their seeds is removed from its event half, and
+   * iteration 2 runs on the rest: iteration 0's layers, windows opened for
+   * p_min3, its own clone vote, UV search and best choice; its seeds carry
+   * it = 2 and join the others before Matching. */
+  int32_t third_iter;
+  int32_t pad4;
+  double p_min3;           /* MeV */
 } orc_params;
 
 /* Margins.  Every decision that shapes an output is logged with its
@@ -173,7 +183,8 @@ void orc_default_geom(orc_geom *g);
 void orc_default_params(orc_params *p);
 
 /* out[0] = Delta x3^max, out[1] = alpha_corr, out[2] = K3 of iteration `it`
- * at the nominal layer z. */
+ * (0, 1, or 2: the third iteration's layers and p_min3) at the nominal layer
+ * z. */
 void orc_window_constants(const orc_geom *g, const orc_params *p, int it, double out[3]);
 
 /* Stage entry points on ONE event (event-local zone offsets [25], hits). */
