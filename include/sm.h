@@ -154,6 +154,19 @@ typedef struct {
   double a_gamma, b_gamma; /* Table 1: 7.707063e-11, -7.817364e-3 */
   double ut_loose_a[SM_N_UT], ut_loose_b[SM_N_UT], ut_loose_lo[SM_N_UT], ut_loose_hi[SM_N_UT];
   double ut_tight_a[SM_N_UT], ut_tight_b[SM_N_UT], ut_tight_lo[SM_N_UT], ut_tight_hi[SM_N_UT];
+  /* Third x-z iteration with clean-up (Sec. 3: the HLT2 form finds high
+   * momenta first, cleans the environment and searches again with wider
+   * windows for lower momenta; the HLT1 form runs two iterations).
+   * third_iter 0 (default): two iterations.  third_iter 1: after iterations
+   * 0 and 1 of the whole batch, every hit on one of their seeds is removed,
+   * and iteration 2 runs on the hits left: iteration 0's layers, windows
+   * opened for p_min3, its own clone vote, UV search and best choice.  Its
+   * seeds (iter = 2) follow the event's other seeds and join Matching.  Only
+   * the batched calls (sm_run, sm_submit, sm_profile) run it: sm_run_plain
+   * and sm_run_noalloc return SM_ERR_INVALID. */
+  int32_t third_iter;
+  int32_t pad4;
+  double p_min3;           /* MeV/c, default 1500 */
 } sm_params;
 
 /* Library resources; zero fields take defaults. */

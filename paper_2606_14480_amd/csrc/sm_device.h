@@ -92,6 +92,11 @@ struct Desc {
   int n_events, n_items;
   int grid;   // workgroups of this batch's main seeding form (0: the context's)
   int fuse;   // 1: matching inside the seeding kernel; 0: in k_match (chosen by the host)
+  // third x-z iteration: 0 none; 1 the first two iterations, which mark the
+  // hits of their seeds with `serial`; 2 the third iteration on the cleaned
+  // batch (b then holds the hits left)
+  int pass;
+  unsigned serial;
 };
 
 // Parameters in the precision each kernel uses.
@@ -103,8 +108,9 @@ struct DevParams {
   double uz[kNL], gz[kNL], ztan[kNL], inv_z[kNL];
   double zref, d;
   float zreff, df;
-  // XZ, FP32 search
-  float dx3f[2], alphaf[2];
+  // XZ, FP32 search; index 2: the third iteration (iteration 0's layers, its
+  // own momentum floor)
+  float dx3f[3], alphaf[3];
   float invp_af, invp_bf, kappa_cf, t2_tol0f, t2_tol1f;
   // XZ, FP64 extension + fit
   double ext_tol, inv_sigma2, chi2x_max;
@@ -206,6 +212,22 @@ struct Scratch {
   Counters *cnt;
   unsigned *need;             // 8 overflow needs of this scratch (trip, cand, tbl, sst,
                               // ms, vs, surv, combo), inside *cnt
+  uint32_t *used;             // third iteration: per hit of the batch, the serial of the
+                              // last batch whose first two iterations used it
+  int *item_cnt3, *item_base3;  // third iteration: its seeds per item, in pool3 (read by
+  sm_seed *pool3;               // Matching and the copy beside the first two's)
+};
+
+// The third x-z iteration's batch-sized arrays: the cleaned batch, and its
+// seeds, which Matching and the copy read beside the first two iterations'.
+struct Third {
+  int *zcnt;                  // [zones] hits left per zone
+  int32_t *zone_off;          // [zones + 1] the cleaned batch's zone offsets
+  float *hx, *hz;             // [hits] the hits left, zone by zone, x order kept
+  int32_t *hid;
+  int *item_cnt, *item_base;  // [items] third-iteration seeds per item, in pool
+  sm_seed *pool;
+  Counters *cnt;              // the third pass's counters
 };
 
 // Per-slot kernel context in device memory: kernels read scratch pointers and
@@ -214,6 +236,7 @@ struct KCtx {
   Scratch S;   // main form: per-workgroup arrays for seed_wgs workgroups
   Scratch SB;  // big-item form: own per-workgroup arrays, shared pools and counters
   DevParams P;
+  Third T;     // third iteration (null pointers when off)
 };
 
 }  // namespace smk
@@ -246,4 +269,7 @@ int smk_launch_copy(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_
 int smk_launch_validate(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 int smk_launch_plain_totals(const smk::Desc *d, const smk::KCtx *k, hipStream_t st);
 int smk_launch_zero(void *p, int n_words, hipStream_t st);   // clears n_words 32-bit words
+// the third iteration's clean-up: the hits the first two iterations left, as
+// a batch of their own (three launches: counts per zone, offsets, copy)
+int smk_launch_clean(const smk::Desc *d, const smk::KCtx *k, int grid, hipStream_t st);
 }

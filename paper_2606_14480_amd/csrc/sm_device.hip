@@ -254,6 +254,8 @@ struct SeedShared {
   int zlo[kNL], zhi[kNL];                // z span of each layer (Hough UV), as zkey
   int xb[7];                             // first compact x index of each x slot
   int item;
+  int pass;                              // the batch's pass (third iteration): 0, 1 or 2
+  unsigned serial;                       // the batch's serial (hit marks of pass 1)
   unsigned ntrip, ncand, nseed, ncombo, nkept;
   unsigned long long pbase;
 };
@@ -358,7 +360,9 @@ __device__ __forceinline__ void xz_triplets(const float *X, const float *Z, Seed
                                             const DevParams &P, unsigned long long *trip,
                                             int trip_cap) {
   const int *zoff = sh.zoff;
-  const int n1a = zoff[1] - zoff[0], n1b = zoff[4] - zoff[3];
+  // the third iteration (pass 2) starts from iteration 0's T1 layer only
+  const bool third = sh.pass == 2;
+  const int n1a = zoff[1] - zoff[0], n1b = third ? 0 : zoff[4] - zoff[3];
   const int N1 = n1a + n1b;
   const float zr = P.zreff, dd = P.df;
   for (int c0 = 0; c0 < N1; c0 += NT) {
@@ -370,8 +374,10 @@ __device__ __forceinline__ void xz_triplets(const float *X, const float *Z, Seed
       const int L3 = it ? 11 : 8;
       const float x1 = X[i1], z1 = Z[i1];
       // window around x1 (z3 + alpha_corr) / z1, half-width Delta x3^max
-      const float centre = (P.zf[L3] + P.alphaf[it]) / z1 * x1;
-      const float dx3 = P.dx3f[it];
+      // window constants: the iteration's, or the third iteration's
+      const int ic = third ? 2 : it;
+      const float centre = (P.zf[L3] + P.alphaf[ic]) / z1 * x1;
+      const float dx3 = P.dx3f[ic];
       st = zlower<kLds>(X, sh, L3, centre - dx3);
       const float hi3 = centre + dx3;
       int en = st;
@@ -1056,11 +1062,22 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     st.s.y0 = (float)r.y0; st.s.ty = (float)r.ty;
     st.s.chi2_x = (float)cd.chi2; st.s.chi2_y = (float)r.chi2;
     st.s.score = (float)__longlong_as_double((long long)cd.score);
-    st.s.n_x = cd.n; st.s.n_uv = r.n; st.s.half = half; st.s.iter = cd.it;
+    // the third iteration's seeds carry iteration 2 (its x-z search runs
+    // with iteration 0's layers)
+    st.s.n_x = cd.n; st.s.n_uv = r.n; st.s.half = half; st.s.iter = cd.it + (sh.pass == 2 ? 2 : 0);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       st.s.hits[xlayer(k)] = cd.pos[k] >= 0 ? hid[cd.pos[k]] : -1;
       st.s.hits[uvlayer(k)] = r.pos[k] >= 0 ? hid[r.pos[k]] : -1;
+    }
+    if (sh.pass == 1) {
+      // clean-up for the third iteration: this seed's hits are used
+      auto *u = gmem(S.used) + sh.zabs[0];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        if (cd.pos[k] >= 0) u[cd.pos[k]] = sh.serial;
+        if (r.pos[k] >= 0) u[r.pos[k]] = sh.serial;
+      }
     }
     return st;
   };
@@ -1074,7 +1091,9 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
       const bool ok = b + ns <= (unsigned long long)S.pool_cap;
       if (!ok) raise_flag(cnt, F_POOL);
       sh.pbase = ok ? b : (unsigned long long)S.pool_cap;   // no writes when full
-      S.item_cnt[item] = (int)ns;
+      // a full pool keeps no seeds of the item (the call grows it and runs
+      // the batch again), so no reader looks past it
+      S.item_cnt[item] = ok ? (int)ns : 0;
       S.item_base[item] = ok ? (int)b : 0;
     }
   };
@@ -1404,7 +1423,19 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   }
   const int n0 = gmem(S.item_cnt)[2 * e], n1 = gmem(S.item_cnt)[2 * e + 1];
   const int b0 = gmem(S.item_base)[2 * e], b1 = gmem(S.item_base)[2 * e + 1];
-  const int ns = n0 + n1;
+  // with the third iteration, its seeds of the event follow (both halves)
+  const bool t3 = D->pass == 1;
+  const int n2 = t3 ? gmem(S.item_cnt3)[2 * e] : 0, n3 = t3 ? gmem(S.item_cnt3)[2 * e + 1] : 0;
+  const int b2 = t3 ? gmem(S.item_base3)[2 * e] : 0, b3 = t3 ? gmem(S.item_base3)[2 * e + 1] : 0;
+  const int ns = n0 + n1 + n2 + n3;
+  // the event's seed i, in this order: half 0, half 1, then the third
+  // iteration's half 0, half 1
+  auto seed_at = [&](int i) -> const sm_seed * {
+    if (i < n0) return &S.pool[b0 + i];
+    if (i < n0 + n1) return &S.pool[b1 + i - n0];
+    if (i < n0 + n1 + n2) return &S.pool3[b2 + i - n0 - n1];
+    return &S.pool3[b3 + i - n0 - n1 - n2];
+  };
   const int v0 = gmem(D->b.velo_off)[e], nv = gmem(D->b.velo_off)[e + 1] - v0;
   const bool pool_ok = !(cnt->flags & F_POOL);
   const int so = plain ? D->seed_off[e] : 0;
@@ -1460,9 +1491,9 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   // copies whole records to the caller, matching reads five fields of each
   if (plain)
     for (int i = tid; i < ns && pool_ok; i += NT)
-      if ((long long)so + i < D->seed_cap) D->seeds[so + i] = i < n0 ? S.pool[b0 + i] : S.pool[b1 + i - n0];
+      if ((long long)so + i < D->seed_cap) D->seeds[so + i] = *seed_at(i);
   for (int i = tid; i < ns && pool_ok && fits; i += NT) {
-    const MState m = seed_state(i < n0 ? &S.pool[b0 + i] : &S.pool[b1 + i - n0], P);
+    const MState m = seed_state(seed_at(i), P);
     gstore(&ms[i], m);
     xsf[i] = m.xsf; txsf[i] = m.txsf; ymf[i] = m.y_mf; tyf[i] = m.tyf;
     best_s[i] = ~0ull;
@@ -1614,7 +1645,7 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   }
   // the seed's hit count and the VELO state's slopes, for the network
   auto nhits_of = [&](int si) {
-    const sm_seed *sd = si < n0 ? &S.pool[b0 + si] : &S.pool[b1 + si - n0];
+    const sm_seed *sd = seed_at(si);
     return gmem(sd)->n_x + gmem(sd)->n_uv;
   };
   // a pair's evaluation and its VELO state (x, y, z, tx, ty)
@@ -1733,7 +1764,8 @@ template <int NT, int kSel>
 __device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Scratch &S,
                                             const DevParams &P, int e, int plain, size_t wg,
                                             MatchShared &sh) {
-  const int ns = S.item_cnt[2 * e] + S.item_cnt[2 * e + 1];
+  int ns = S.item_cnt[2 * e] + S.item_cnt[2 * e + 1];
+  if (D->pass == 1) ns += S.item_cnt3[2 * e] + S.item_cnt3[2 * e + 1];
   const int nv = D->b.velo_off[e + 1] - D->b.velo_off[e];
   if (ns <= kMsLds && nv <= kVsLds)
     match_event_impl<true, NT, kSel>(D, S, P, e, plain, wg, sh);
@@ -2052,6 +2084,8 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
         for (int k = 0; k <= kNL; ++k) sh.zabs[k] = z[k];
       }
       sh.item = it;
+      sh.pass = D->pass;
+      sh.serial = D->serial;
       sh.ntrip = 0; sh.ncand = 0; sh.nseed = 0; sh.ncombo = 0; sh.nkept = 0;
     }
     // the last quarter of the workgroups is the youngest on its CU, whose
@@ -2193,6 +2227,12 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
   // pool or input errors of the earlier kernels: no copy (read first, so
   // that the load overlaps the others)
   const bool bad = (S.cnt->flags & (F_POOL | F_LPOOL | F_INVALID | F_UNSORTED)) != 0u;
+  // with the third iteration, each event's seeds also come from its two
+  // items in the third pool, after the first two iterations' ones
+  const bool t3 = D->pass == 1;
+  auto seeds3 = [&](int e) {
+    return t3 ? gmem(S.item_cnt3)[2 * e] + gmem(S.item_cnt3)[2 * e + 1] : 0;
+  };
   __shared__ long long s_part[2][4];
   __shared__ int s_tmp[16];
   // the counts of the events before this range, four loads in flight per
@@ -2204,7 +2244,7 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
     for (int u = 0; u < 4; ++u) {
       const int e = min(e0 + 256 * u, e_lo - 1);
       a[u] = gmem(S.item_cnt)[2 * e];
-      b[u] = gmem(S.item_cnt)[2 * e + 1];
+      b[u] = gmem(S.item_cnt)[2 * e + 1] + seeds3(e);
       c[u] = gmem(S.ev_lcnt)[e];
     }
 #pragma unroll
@@ -2233,8 +2273,9 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
       n0 = gmem(S.item_cnt)[2 * e]; n1 = gmem(S.item_cnt)[2 * e + 1]; m = gmem(S.ev_lcnt)[e];
       b0 = gmem(S.item_base)[2 * e]; b1 = gmem(S.item_base)[2 * e + 1]; src = gmem(S.ev_lbase)[e];
     }
+    const int n3 = e < e_hi ? seeds3(e) : 0;
     int ts, tl;
-    const int xs = block_excl_scan<256>(n0 + n1, s_tmp, ts);
+    const int xs = block_excl_scan<256>(n0 + n1 + n3, s_tmp, ts);
     __syncthreads();
     const int xl = block_excl_scan<256>(m, s_tmp, tl);
     if (e < e_hi) {
@@ -2275,8 +2316,86 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
     if (so + n0 + n1 <= D->seed_cap)
       for (int i = tid; i < n0 + n1; i += 256)
         D->seeds[so + i] = gload(i < n0 ? &S.pool[b0 + i] : &S.pool[b1 + i - n0]);
+    if (t3) {
+      // the third iteration's seeds of the event: half 0, then half 1
+      const int m0 = gmem(S.item_cnt3)[2 * e], m1 = gmem(S.item_cnt3)[2 * e + 1];
+      const int c0 = gmem(S.item_base3)[2 * e], c1 = gmem(S.item_base3)[2 * e + 1];
+      const long long s3 = so + n0 + n1;
+      if (s3 + m0 + m1 <= D->seed_cap)
+        for (int i = tid; i < m0 + m1; i += 256)
+          D->seeds[s3 + i] = gload(i < m0 ? &S.pool3[c0 + i] : &S.pool3[c1 + i - m0]);
+    }
     if (dst + m <= D->long_cap)
       for (int i = tid; i < m; i += 256) D->longs[dst + i] = gload(&S.lpool[src + i]);
+  }
+}
+
+// ------------------------------------------ third-iteration clean-up ----
+
+// Hits left per zone of each (event, half) item: those the first two
+// iterations' seeds did not mark with this batch's serial.  Workgroup per
+// item (persistent over the items); one wave per zone.  Workgroup 0 also
+// clears the third pass's preparation flag (its preparing launch comes next).
+__global__ __launch_bounds__(256) void k_clean_count(const Desc *__restrict__ D,
+                                                      const KCtx *__restrict__ K) {
+  const Third &T = K->T;
+  if (blockIdx.x == 0 && threadIdx.x == 0) T.cnt->prep_ready = 0u;
+  const int nz = D->n_events * 24;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t serial = D->serial;
+  for (int z = (int)blockIdx.x * 4 + w; z < nz; z += (int)gridDim.x * 4) {
+    const int lo = gmem(D->b.zone_off)[z], hi = gmem(D->b.zone_off)[z + 1];
+    int n = 0;
+    for (int i = lo + lane; i < hi; i += 64) n += gmem(K->S.used)[i] != serial;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
+    if (lane == 0) gmem(T.zcnt)[z] = n;
+  }
+}
+
+// The cleaned batch's zone offsets: an exclusive scan of the zone counts, one
+// 1024-thread workgroup.
+__global__ __launch_bounds__(1024) void k_clean_scan(const Desc *__restrict__ D,
+                                                     const KCtx *__restrict__ K) {
+  const Third &T = K->T;
+  __shared__ int s_tmp[16];
+  const int nz = D->n_events * 24;
+  int carry = 0;
+  for (int z0 = 0; z0 < nz; z0 += 1024) {
+    const int z = z0 + (int)threadIdx.x;
+    const int v = z < nz ? gmem(T.zcnt)[z] : 0;
+    int total;
+    const int ex = block_excl_scan<1024>(v, s_tmp, total);
+    if (z < nz) gmem(T.zone_off)[z] = carry + ex;
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gmem(T.zone_off)[nz] = carry;
+}
+
+// The hits left, zone by zone in x order, into the cleaned batch: one wave
+// per zone, a ballot prefix per 64 hits.
+__global__ __launch_bounds__(256) void k_clean_copy(const Desc *__restrict__ D,
+                                                     const KCtx *__restrict__ K) {
+  const Third &T = K->T;
+  const int nz = D->n_events * 24;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t serial = D->serial;
+  for (int z = (int)blockIdx.x * 4 + w; z < nz; z += (int)gridDim.x * 4) {
+    const int lo = gmem(D->b.zone_off)[z], hi = gmem(D->b.zone_off)[z + 1];
+    int out = gmem(T.zone_off)[z];
+    for (int i0 = lo; i0 < hi; i0 += 64) {
+      const int i = i0 + lane;
+      const bool keep = i < hi && gmem(K->S.used)[i] != serial;
+      const unsigned long long m = __ballot(keep);
+      if (keep) {
+        const int o = out + (int)__popcll(m & ((1ull << lane) - 1ull));
+        gmem(T.hx)[o] = gmem(D->b.hit_x)[i];
+        gmem(T.hz)[o] = gmem(D->b.hit_z)[i];
+        gmem(T.hid)[o] = gmem(D->b.hit_id)[i];
+      }
+      out += (int)__popcll(m);
+    }
   }
 }
 
@@ -2408,6 +2527,19 @@ int smk_launch_copy(const Desc *d, const KCtx *k, int grid, hipStream_t st) {
 int smk_launch_validate(const Desc *d, const KCtx *k, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_validate, dim3(grid), dim3(256), 0, st, d, k);
   return (int)hipGetLastError();
+}
+int smk_launch_clean(const Desc *d, const KCtx *k, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_clean_count, dim3(grid), dim3(256), 0, st, d, k);
+  int e = (int)hipGetLastError();
+  if (!e) {
+    hipLaunchKernelGGL(k_clean_scan, dim3(1), dim3(1024), 0, st, d, k);
+    e = (int)hipGetLastError();
+  }
+  if (!e) {
+    hipLaunchKernelGGL(k_clean_copy, dim3(grid), dim3(256), 0, st, d, k);
+    e = (int)hipGetLastError();
+  }
+  return e;
 }
 int smk_launch_zero(void *p, int n_words, hipStream_t st) {
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, st, (unsigned *)p, n_words);

@@ -31,6 +31,7 @@ struct Caps {
   int ms = 1024, vs = 1024, surv = 2048;
   int items = 0, events = 0;
   long long pool = 0, lpool = 0;
+  long long hits = 0, pool3 = 0;   // third iteration: the cleaned batch, its pool's overflow
 };
 
 struct Slot {
@@ -39,6 +40,13 @@ struct Slot {
   Desc *h_desc = nullptr;     // pinned
   smk::KCtx *d_kctx = nullptr;  // scratch pointers + parameters, device copy
   Counters *h_cnt = nullptr;  // pinned
+  // third iteration: its pass's descriptor (the cleaned batch), context and
+  // counters
+  Desc *d_desc3 = nullptr;
+  Desc *h_desc3 = nullptr;    // pinned
+  smk::KCtx *d_kctx3 = nullptr;
+  Counters *h_cnt3 = nullptr; // pinned
+  smk::Third T{};
   Scratch S{};
   Scratch SB{};     // big-item form
   Caps caps;
@@ -69,6 +77,7 @@ struct Slot {
 
 struct sm_ctx {
   int device = 0;
+  unsigned serial = 0;   // batches run (the third iteration's hit marks)
   sm_geometry g{};
   sm_params p{};
   sm_config cfg{};
@@ -111,14 +120,17 @@ DevParams make_params(const sm_geometry &g, const sm_params &p) {
   d.zreff = (float)g.z_ref;
   d.df = (float)p.d_ratio;
   // per-iteration window constants: eq. tolHp and eq. alphacorr at the
-  // nominal z of the iteration's T1 and T3 layers
-  const int l1[2] = {0, 3}, l3[2] = {8, 11};
-  for (int it = 0; it < 2; ++it) {
+  // nominal z of the iteration's T1 and T3 layers; index 2: the third
+  // iteration (iteration 0's layers, momentum floor p_min3)
+  const int l1[3] = {0, 3, 0}, l3[3] = {8, 11, 8};
+  for (int it = 0; it < 3; ++it) {
     const double z1 = g.z[l1[it]], z3 = g.z[l3[it]];
     const double a = p.invp_a, b = p.invp_b;
-    const double x0max = (-a + std::sqrt(a * a + 4.0 * b / p.p_min)) / (2.0 * b);
+    const double pm = it == 2 ? p.p_min3 : p.p_min;
+    const double disc = a * a + 4.0 * b / pm;
+    const double x0max = disc >= 0.0 && pm > 0.0 ? (-a + std::sqrt(disc)) / (2.0 * b) : 0.0;
     d.dx3f[it] = (float)((z3 - z1) / z1 * x0max);
-    d.alphaf[it] = (float)(p.alpha0 / ((z1 / (z3 - z1)) * (p.p_min - p.alpha1)));
+    d.alphaf[it] = (float)(p.alpha0 / ((z1 / (z3 - z1)) * (pm - p.alpha1)));
   }
   d.invp_af = (float)p.invp_a;
   d.invp_bf = (float)p.invp_b;
@@ -301,12 +313,60 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
   // device addresses inside the counters (address arithmetic only)
   S.need = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(S.cnt) + offsetof(Counters, need_trip));
   B.need = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(S.cnt) + offsetof(Counters, need_big));
+  // third iteration: the hit marks, the cleaned batch, its seeds' pool and
+  // counters; its pass runs on a context whose pools, per-item counts and
+  // counters are these (the per-workgroup scratch is the first pass's)
+  smk::Third &T = s.T;
+  memset(&T, 0, sizeof(T));
+  smk::KCtx k3{};
+  if (c->p.third_iter == 1) {
+    const size_t zones = (size_t)k.events * 24 + 1;
+    const long long pool3_static = (long long)k.items * smk::kPoolPerItem;
+#define A3(ptr, n)                                  \
+  if ((st = dalloc(s, &(ptr), (n), bytes)) != SM_OK) \
+    return st;
+    A3(S.used, (size_t)k.hits);
+    A3(T.zcnt, zones);
+    A3(T.zone_off, zones);
+    A3(T.hx, (size_t)k.hits);
+    A3(T.hz, (size_t)k.hits);
+    A3(T.hid, (size_t)k.hits);
+    A3(T.item_cnt, k.items);
+    A3(T.item_base, k.items);
+    A3(T.pool, (size_t)(pool3_static + k.pool3));
+    A3(T.cnt, 1);
+#undef A3
+    // serials start at 1: no hit is marked by a batch yet
+    if (hipMemset(S.used, 0, sizeof(uint32_t) * (size_t)k.hits) != hipSuccess ||
+        hipMemset(T.cnt, 0, sizeof(Counters)) != hipSuccess)
+      return SM_ERR_DEVICE;
+    S.item_cnt3 = T.item_cnt; S.item_base3 = T.item_base; S.pool3 = T.pool;
+    B.used = S.used; B.item_cnt3 = T.item_cnt; B.item_base3 = T.item_base; B.pool3 = T.pool;
+    k3.S = S;
+    k3.SB = B;
+    for (Scratch *x : {&k3.S, &k3.SB}) {
+      x->item_cnt = T.item_cnt;
+      x->item_base = T.item_base;
+      x->pool = T.pool;
+      x->pool_static = pool3_static;
+      x->pool_cap = pool3_static + k.pool3;
+      x->cnt = T.cnt;
+    }
+    k3.S.need = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(T.cnt) + offsetof(Counters, need_trip));
+    k3.SB.need = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(T.cnt) + offsetof(Counters, need_big));
+    k3.P = c->dp;
+    k3.T = T;
+  }
   c->bytes += bytes;
   smk::KCtx kc;
   kc.S = S;
   kc.SB = B;
   kc.P = c->dp;
+  kc.T = T;
   if (hipMemcpy(s.d_kctx, &kc, sizeof(kc), hipMemcpyHostToDevice) != hipSuccess) return SM_ERR_DEVICE;
+  if (c->p.third_iter == 1 &&
+      hipMemcpy(s.d_kctx3, &k3, sizeof(k3), hipMemcpyHostToDevice) != hipSuccess)
+    return SM_ERR_DEVICE;
   if (c->cfg.mem_budget > 0 && bytes > c->cfg.mem_budget) return SM_ERR_OOM;
   return SM_OK;
 }
@@ -387,10 +447,15 @@ sm_status fit_batch(sm_ctx *c, Slot &s, const sm_batch &b) {
   if (pool > k.pool) { k.pool = std::max(pool, 2 * k.pool); re = true; }
   const long long lpool = b.n_velo + 1024;
   if (lpool > k.lpool) { k.lpool = std::max(lpool, 2 * k.lpool); re = true; }
+  if (c->p.third_iter == 1) {
+    if (b.n_hits > k.hits) { k.hits = std::max<long long>(b.n_hits, 2 * k.hits); re = true; }
+    if (pool > k.pool3) { k.pool3 = std::max(pool, 2 * k.pool3); re = true; }
+  }
   const sm_shape sh = choose_shape(c, b);
   s.lds_hits = sh.lds_hits;
   s.grid = sh.seed_wgs;
-  s.fuse = fuse_for(c, b, s.grid);
+  // with the third iteration, matching waits for all three iterations' seeds
+  s.fuse = c->p.third_iter == 1 ? 0 : fuse_for(c, b, s.grid);
   if (!re && !s.allocs.empty()) return SM_OK;
   return alloc_slot(c, s);
 }
@@ -415,7 +480,8 @@ sm_status check_batch(const sm_ctx *c, const sm_batch *b, const sm_out *o) {
   return SM_OK;
 }
 
-void fill_desc(Desc &d, const sm_batch &b, const sm_out &o, int grid, int fuse) {
+void fill_desc(Desc &d, const sm_batch &b, const sm_out &o, int grid, int fuse, int pass = 0,
+               unsigned serial = 0) {
   d.b = b;
   d.seeds = o.seeds;
   d.longs = o.longs;
@@ -427,6 +493,43 @@ void fill_desc(Desc &d, const sm_batch &b, const sm_out &o, int grid, int fuse) 
   d.n_items = 2 * b.n_events;
   d.grid = grid;
   d.fuse = fuse;
+  d.pass = pass;
+  d.serial = serial;
+}
+
+// The slot's descriptors for one batch: the batch itself and, with the third
+// iteration, its pass over the cleaned batch (the hits left after the first
+// two iterations, built on the device by the clean-up launches).
+void fill_descs(sm_ctx *c, Slot &s, const sm_batch &b, const sm_out &o) {
+  const bool third = c->p.third_iter == 1;
+  unsigned serial = 0;
+  if (third) {
+    serial = ++c->serial;
+    if (serial == 0) serial = ++c->serial;   // 0 is the marks' initial value
+  }
+  fill_desc(*s.h_desc, b, o, s.grid, s.fuse, third ? 1 : 0, serial);
+  if (third) {
+    Desc &d3 = *s.h_desc3;
+    d3 = *s.h_desc;
+    d3.b.zone_off = s.T.zone_off;
+    d3.b.hit_x = s.T.hx;
+    d3.b.hit_z = s.T.hz;
+    d3.b.hit_id = s.T.hid;
+    d3.pass = 2;
+    d3.fuse = 0;
+  }
+}
+
+// The third iteration's launches: its descriptor, the clean-up (hits left
+// per zone, their offsets, their copy) and its seeding pass (preparation and
+// big form, then the main form), on its own context (pools, counts,
+// counters).
+int enqueue_third(sm_ctx *c, Slot &s, hipStream_t q) {
+  int e = hipMemcpyAsync(s.d_desc3, s.h_desc3, sizeof(Desc), hipMemcpyHostToDevice, q);
+  if (!e) e = smk_launch_clean(s.d_desc, s.d_kctx, 1024, q);
+  if (!e) e = smk_launch_seed_big(s.d_desc3, s.d_kctx3, c->big_wgs, c->lds_big, 1, sel_of(c), q);
+  if (!e) e = smk_launch_seed_nomatch(s.d_desc3, s.d_kctx3, s.grid, s.lds_hits, q);
+  return e;
 }
 
 // The head of the batched sequence: the batch's preparation and the
@@ -457,9 +560,12 @@ sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
     if (!e && !s.fuse) e = smk_launch_seed_nomatch(d, S, s.grid, s.lds_hits, q);
     if (!e && s.fuse)
       e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, sel_of(c), q);
+    if (!e && c->p.third_iter == 1) e = enqueue_third(c, s, q);
     if (!e && !s.fuse) e = smk_launch_match(d, S, match_grid(c, s.grid), sel_of(c), q);
     if (!e) e = smk_launch_copy(d, S, 1024, q);
     if (!e) e = hipMemcpyAsync(s.h_cnt, s.S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q);
+    if (!e && c->p.third_iter == 1)
+      e = hipMemcpyAsync(s.h_cnt3, s.T.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q);
     return (hipError_t)e;
   };
   for (const Slot::Captured &g : s.graphs)
@@ -504,6 +610,7 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   if (!e) e = hipEventRecord(ev[1], q);
   if (!e) e = hipEventRecord(ev[2], q);
   if (!e && !s.fuse) e = smk_launch_seed_nomatch(d, S, s.grid, s.lds_hits, q);
+  if (!e && c->p.third_iter == 1) e = enqueue_third(c, s, q);   // timed with seeding
   if (!e) e = hipEventRecord(ev[3], q);
   if (!e && s.fuse)
     e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, sel_of(c), q);
@@ -519,11 +626,16 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
 // or map the flags to a status.
 bool needs_rerun(sm_ctx *c, Slot &s, sm_status &st) {
   const Counters &k = *s.h_cnt;
+  // the third iteration's pass has counters of its own
+  static const Counters none{};
+  const bool third = c->p.third_iter == 1;
+  const Counters &k3 = third ? *s.h_cnt3 : none;
   st = SM_OK;
-  const unsigned f = k.flags;
-  if (k.stall) {
+  const unsigned f = k.flags | k3.flags;
+  if (k.stall || k3.stall) {
     // a wait for the batch's preparation gave up: clear the counters
     (void)hipMemset(s.S.cnt, 0, sizeof(Counters));
+    if (third) (void)hipMemset(s.T.cnt, 0, sizeof(Counters));
     st = SM_ERR_DEVICE;
     return false;
   }
@@ -547,8 +659,13 @@ bool needs_rerun(sm_ctx *c, Slot &s, sm_status &st) {
   };
   re |= grow_caps(cp, &k.need_trip);
   re |= grow_caps(s.caps_big, k.need_big);
+  if (third) {
+    re |= grow_caps(cp, &k3.need_trip);
+    re |= grow_caps(s.caps_big, k3.need_big);
+  }
   // seed pool: pool_top is what the overflow area needed
-  if (f & smk::F_POOL) { cp.pool = std::max<long long>(2 * cp.pool, (long long)k.pool_top + 1024); re = true; }
+  if (k.flags & smk::F_POOL) { cp.pool = std::max<long long>(2 * cp.pool, (long long)k.pool_top + 1024); re = true; }
+  if (k3.flags & smk::F_POOL) { cp.pool3 = std::max<long long>(2 * cp.pool3, (long long)k3.pool_top + 1024); re = true; }
   // long-track pool: every VELO state's slot, then the overflow area
   if (f & smk::F_LPOOL) { cp.lpool = std::max<long long>(2 * cp.lpool, cp.lpool + (long long)k.lpool_top + 1024); re = true; }
   if (re) {
@@ -563,13 +680,16 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
                        sm_kernel_times *times = nullptr) {
   sm_status st = check_batch(c, b, o);
   if (st != SM_OK) return st;
+  // the per-event form matches each event as soon as it is seeded; the third
+  // iteration needs the batch's clean-up between seeding and matching
+  if (plain && c->p.third_iter == 1) return SM_ERR_INVALID;
   std::lock_guard<std::mutex> lk(c->mu);
   if (hipSetDevice(c->device) != hipSuccess) return SM_ERR_DEVICE;
   Slot &s = c->slots[0];
   hipStream_t q = (hipStream_t)stream;
   for (int tries = 0; tries < kMaxTries; ++tries) {
     if ((st = fit_batch(c, s, *b)) != SM_OK) return st;
-    fill_desc(*s.h_desc, *b, *o, s.grid, s.fuse);
+    fill_descs(c, s, *b, *o);
     // the batched graph uploads the descriptor and copies the counters back
     // itself; the plain and timed sequences do it here
     const bool graph = !times && !plain;
@@ -586,6 +706,9 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
     }
     if (st == SM_OK && !graph &&
         hipMemcpyAsync(s.h_cnt, s.S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q) != hipSuccess)
+      st = SM_ERR_DEVICE;
+    if (st == SM_OK && !graph && c->p.third_iter == 1 &&
+        hipMemcpyAsync(s.h_cnt3, s.T.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q) != hipSuccess)
       st = SM_ERR_DEVICE;
     if (st == SM_OK && hipStreamSynchronize(q) != hipSuccess) st = SM_ERR_DEVICE;
     if (times) {
@@ -742,6 +865,8 @@ void na_fill_kctx(const sm_ctx *c, void *ptr, smk::KCtx &kc) {
 sm_status run_noalloc(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream) {
   sm_status st = check_batch(c, b, o);
   if (st != SM_OK) return st;
+  // the third iteration's clean-up needs batch-sized arrays of its own
+  if (c->p.third_iter == 1) return SM_ERR_INVALID;
   if (b->n_events > kNaEvents || b->n_velo > kNaVelo) return SM_ERR_LIMIT;
   std::lock_guard<std::mutex> lk(c->mu);
   if (hipSetDevice(c->device) != hipSuccess) return SM_ERR_DEVICE;
@@ -850,6 +975,8 @@ void sm_default_params(sm_params *p) {
   p->final_sel = 0;      // no network weights are published (reading)
   p->ghost_cut = 0.8;    // Sec. 4.4
   p->clone_gap = 0.05;   // Sec. 4.4
+  p->third_iter = 0;     // Sec. 3: the HLT1 form runs two x-z iterations
+  p->p_min3 = 1500.0;    // reading: the third iteration opens its windows for 1.5 GeV/c
   p->ut_mode = 0;        // Sec. 4.3: UT hits are optional
   p->ut_min_hits = 3;    // more than two
   p->a_gamma = 7.707063e-11;   // Table 1
@@ -895,6 +1022,10 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
       c->p.min_uv_hits < 3 || c->p.min_uv_hits > 6 ||
       (c->p.final_sel != 0 && c->p.final_sel != 1) ||
       (c->p.ut_mode != 0 && c->p.ut_mode != 1) ||
+      (c->p.third_iter != 0 && c->p.third_iter != 1) ||
+      (c->p.third_iter == 1 &&
+       (!(c->p.p_min3 > 0) ||
+        c->p.invp_a * c->p.invp_a + 4.0 * c->p.invp_b / c->p.p_min3 < 0)) ||
       (c->p.ut_mode == 1 && (c->p.ut_min_hits < 1 || c->p.ut_min_hits > SM_N_UT)) ||
       (c->p.final_sel == 1 && (!ghost_nn_ok(c->p.ghost_nn) || !(c->p.clone_gap >= 0.0))) ||
       c->p.invp_a * c->p.invp_a + 4.0 * c->p.invp_b / c->p.p_min < 0 ||
@@ -983,8 +1114,12 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
         hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
         hipMalloc(&s.d_desc, sizeof(Desc)) != hipSuccess ||
         hipMalloc(&s.d_kctx, sizeof(smk::KCtx)) != hipSuccess ||
+        hipMalloc(&s.d_desc3, sizeof(Desc)) != hipSuccess ||
+        hipMalloc(&s.d_kctx3, sizeof(smk::KCtx)) != hipSuccess ||
         hipHostMalloc(&s.h_desc, sizeof(Desc), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&s.h_cnt, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&s.h_desc3, sizeof(Desc), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&s.h_cnt, sizeof(Counters), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&s.h_cnt3, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
       hipGetLastError();
       sm_destroy(c);
       return SM_ERR_DEVICE;
@@ -993,6 +1128,10 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
     s.caps.events = 1024;
     s.caps.pool = 1 << 16;
     s.caps.lpool = 1 << 15;
+    if (c->p.third_iter == 1) {
+      s.caps.hits = 1 << 20;
+      s.caps.pool3 = 1 << 16;
+    }
     sm_status st = alloc_slot(c, s);
     if (st != SM_OK) {
       sm_destroy(c);
@@ -1028,7 +1167,7 @@ sm_status sm_profile(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stre
 static sm_status start_slot(sm_ctx *c, Slot &s) {
   sm_status st = fit_batch(c, s, s.batch);
   if (st != SM_OK) return st;
-  fill_desc(*s.h_desc, s.batch, *s.out, s.grid, s.fuse);
+  fill_descs(c, s, s.batch, *s.out);
   // the graph uploads the descriptor and copies the counters back
   if ((st = enqueue_batched(c, s, s.stream)) != SM_OK) return st;
   return hip_status(hipEventRecord(s.done, s.stream));
@@ -1139,8 +1278,12 @@ sm_status sm_destroy(sm_ctx *ctx) {
     if (s.stream) hipStreamDestroy(s.stream);
     if (s.d_desc) hipFree(s.d_desc);
     if (s.d_kctx) hipFree(s.d_kctx);
+    if (s.d_desc3) hipFree(s.d_desc3);
+    if (s.d_kctx3) hipFree(s.d_kctx3);
     if (s.h_desc) hipHostFree(s.h_desc);
+    if (s.h_desc3) hipHostFree(s.h_desc3);
     if (s.h_cnt) hipHostFree(s.h_cnt);
+    if (s.h_cnt3) hipHostFree(s.h_cnt3);
   }
   if (ctx->na_kctx) hipHostFree(ctx->na_kctx);
   if (ctx->na_desc) hipHostFree(ctx->na_desc);

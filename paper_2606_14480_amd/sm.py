@@ -97,7 +97,8 @@ class Params(C.Structure):
                 ("ut_mode", C.c_int32), ("ut_min_hits", C.c_int32),
                 ("a_gamma", C.c_double), ("b_gamma", C.c_double)] + \
                [(f"ut_{k}_{w}", C.c_double * NUT) for k in ("loose", "tight")
-                for w in ("a", "b", "lo", "hi")]
+                for w in ("a", "b", "lo", "hi")] + \
+               [("third_iter", C.c_int32), ("pad4", C.c_int32), ("p_min3", C.c_double)]
 
     ARRAYS = ("zm",) + tuple(f"ut_{k}_{w}" for k in ("loose", "tight") for w in ("a", "b", "lo", "hi"))
 

@@ -150,7 +150,14 @@ def compare(orc_res, gpu, n_events, band=None, events=None):
         if diff_s or diff_l:
             if hasattr(orc_res, "near"):
                 ms = {k for k in diff_s if margin_explains(orc_res, e, osd, old, gsd, gld, k, "seed")}
-                ml = {k for k in diff_l if margin_explains(orc_res, e, osd, old, gsd, gld, k, "long")}
+                # the third iteration runs on the hits the first two left in
+                # the half: a change among their seeds there carries over
+                it_half = lambda k: ((int(osd[k]["it"]), int(osd[k]["half"])) if k in osd
+                                     else (int(gsd[k]["iter"]), int(gsd[k]["half"])))
+                moved = {it_half(k)[1] for k in ms if it_half(k)[0] < 2}
+                ms |= {k for k in diff_s - ms if it_half(k)[0] == 2 and it_half(k)[1] in moved}
+                ml = {k for k in diff_l
+                      if k[1] in ms or margin_explains(orc_res, e, osd, old, gsd, gld, k, "long")}
                 st["explained_by_margin"] = st.get("explained_by_margin", 0) + len(ms) + len(ml)
                 diff_s, diff_l = diff_s - ms, diff_l - ml
             if not (diff_s or diff_l):

@@ -526,3 +526,27 @@ def test_ut_search_parity(orc, sm, ctx, variant):
     ref = gpu_run(sm, ctx, b)
     assert np.all(ref[3]["n_ut"] == 0) and np.all(ref[3]["ut_hits"] == -1)
     assert len(ref[3]) > len(g[3])
+
+
+def test_third_iteration_parity(orc, sm):
+    """The third x-z iteration with clean-up against the oracle on 300
+    min-bias events: the first two iterations' seeds, the third's (iteration
+    2, on the hits they left), and the long tracks over all of them; the same
+    bytes on another grid and LDS budget; the per-event form refuses it."""
+    b = ev.generate(ev.config(2, n_events=300))
+    over = dict(third_iter=1)
+    c = sm.Context(params=sm.default_params(**over))
+    try:
+        g, o, st = check(orc, sm, c, b, "third iteration", params_over=over)
+        assert (g[1]["iter"] == 2).sum() > 1000
+        with pytest.raises(sm.SmError):
+            gpu_run(sm, c, b, plain=True)
+    finally:
+        c.close()
+    c2 = sm.Context(params=sm.default_params(**over), seed_wgs=300, lds_hits=1024)
+    try:
+        g2 = gpu_run(sm, c2, b)
+        for x, y in zip(g, g2):
+            assert x.tobytes() == y.tobytes()
+    finally:
+        c2.close()

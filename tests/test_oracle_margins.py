@@ -28,11 +28,11 @@ def as_gpu(res):
     S = res.seeds
     seeds = np.zeros(len(S), dtype=[("hits", "i4", 12), ("ax", "f8"), ("bx", "f8"), ("cx", "f8"),
                                     ("y0", "f8"), ("ty", "f8"), ("chi2_x", "f8"), ("chi2_y", "f8"),
-                                    ("n_x", "i4"), ("n_uv", "i4"), ("iter", "i4")])
+                                    ("n_x", "i4"), ("n_uv", "i4"), ("iter", "i4"), ("half", "i4")])
     seeds["hits"] = S["id"]
     for a, b in (("ax", "a"), ("bx", "b"), ("cx", "c"), ("y0", "y0"), ("ty", "ty"),
                  ("chi2_x", "chi2x"), ("chi2_y", "chi2y"), ("n_x", "nx"), ("n_uv", "nuv"),
-                 ("iter", "it")):
+                 ("iter", "it"), ("half", "half")):
         seeds[a] = S[b]
     L = res.longs
     longs = np.zeros(len(L), dtype=[("velo_idx", "i4"), ("seed_idx", "i4"), ("velo_id", "i4"),
