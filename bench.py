@@ -37,6 +37,8 @@ WORKLOADS = {
               "[20, 3000], 5% inefficiency, 20% noise hits",
     "ghost": "minbias-{n} with the network form of the final selection (Sec. 4.4: ghost "
              "probability < 0.8, clone gap 0.05; weights trained on the generator's truth)",
+    "third": "minbias-{n} with the third x-z iteration after the clean-up (Sec. 3; windows "
+             "opened for 1.5 GeV/c on the hits the first two iterations left)",
     "ut": "minbias-{n} with the UT hit search (Sec. 4.3; a synthetic four-layer UT, about 500 "
           "UT hits per event; more than two UT hits per long track)",
 }
@@ -268,9 +270,9 @@ def main():
                     help="min-bias events in the serving pool (requests are 1..this many)")
     ap.add_argument("--serve-plain", type=int, default=20,
                     help="requests of the 0.8 stream also run through the plain form")
-    ap.add_argument("--legs", default="uneven,stress,ghost,ut",
+    ap.add_argument("--legs", default="uneven,stress,ghost,ut,third",
                     help="further workloads at their stated sizes, timed beside the headline "
-                         "(comma list of uneven, stress, ghost, ut; empty: none)")
+                         "(comma list of uneven, stress, ghost, ut, third; empty: none)")
     ap.add_argument("--leg-steps", type=int, default=5)
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes generating the synthetic events")
@@ -295,7 +297,7 @@ def main():
     host = gen(ev.config(wl, n_events=args.events or None))
     legs = [x for x in args.legs.split(",") if x and x != args.workload]
     leg_hosts = {x: gen(ev.config({"uneven": 3, "stress": 4}[x])) for x in legs
-                 if x not in ("ghost", "ut")}
+                 if x not in ("ghost", "ut", "third")}
     pool = gen(ev.config(5, n_events=args.serve_pool)) \
         if args.serve_requests > 0 and args.workload == "minbias" else None
     log(f"[bench] generated {host.n_events} events, {host.n_hits} hits, {host.n_velo} VELO "
@@ -358,7 +360,8 @@ def main():
     leg_res = {}
     # the headline batch again, through a context with the network form of
     # the final selection, and one with the UT search
-    for name, g_over in (("ghost", dict(over, final_sel=1)), ("ut", dict(over, ut_mode=1))):
+    for name, g_over in (("ghost", dict(over, final_sel=1)), ("ut", dict(over, ut_mode=1)),
+                         ("third", dict(over, third_iter=1))):
         if name not in legs or args.workload != "minbias":
             continue
         gctx = sm.Context(params=sm.default_params(**g_over))
