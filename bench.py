@@ -61,8 +61,8 @@ def match_kernel_bytes(b, n_seeds: int, n_longs: int) -> int:
     the two items' seed counts and pool offsets, two VELO offsets and its
     long-track count and pool offset (32 B), the VELO states (x, y, z, tx, ty,
     id: 24 B each), five fields of each seed (20 B), and per long track its
-    48 B record."""
-    return 32 * b.n_events + 24 * b.n_velo + 20 * n_seeds + 48 * n_longs
+    64 B record."""
+    return 32 * b.n_events + 24 * b.n_velo + 20 * n_seeds + 64 * n_longs
 
 
 def cpu_model() -> str:
