@@ -180,6 +180,30 @@ def serve_stream(ctx, sm, pool_batch, n_req, loads, n_plain):
     return out
 
 
+def run_in_flight(ctx, sm, db, outs, n):
+    """n resident batches through the context's submit/poll slots with
+    len(outs) of them in flight (each slot its own stream and graph; a new
+    batch takes the output buffers of the one that just completed).  Returns
+    the wall time and each batch's latency from submit to its results."""
+    k = len(outs)
+    pending, lat = [], []
+    nxt = 0
+    t0 = time.perf_counter()
+    while len(lat) < n:
+        while nxt < n and len(pending) < k:
+            st, t = ctx.submit(db, outs[nxt % k])
+            if st != sm.OK:
+                raise sm.SmError(st, "sm_submit")
+            pending.append((t, time.perf_counter()))
+            nxt += 1
+        t, ts = pending.pop(0)
+        st = ctx.poll(t, True)
+        if st != sm.OK:
+            raise sm.SmError(st, "sm_poll")
+        lat.append(time.perf_counter() - ts)
+    return time.perf_counter() - t0, lat
+
+
 def run_sized(ctx, sm, db, host, stream):
     """One run with outputs sized from the first guess, or from the sizes the
     library reports if they do not fit."""
@@ -274,6 +298,9 @@ def main():
                     help="further workloads at their stated sizes, timed beside the headline "
                          "(comma list of uneven, stress, ghost, ut, third; empty: none)")
     ap.add_argument("--leg-steps", type=int, default=5)
+    ap.add_argument("--in-flight", type=int, default=2,
+                    help="resident batches on the device at once in the timed region "
+                         "(continuous batching over the context's slots)")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="processes generating the synthetic events")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -322,7 +349,7 @@ def main():
         parity = oracle_parity(host, gpu, args.parity_events, over)
         log(f"[bench] parity vs oracle: {parity}")
 
-    # ---- batched form: the timed region
+    # ---- batched form, one batch at a time (blocking call per batch)
     for _ in range(args.warmup):
         ctx.run(db, out, stream)
     torch.cuda.synchronize()
@@ -333,10 +360,31 @@ def main():
         ctx.run(db, out, stream)
         lat.append(time.perf_counter() - t1)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+    seq_elapsed = time.perf_counter() - t_start
+    seq_value = args.steps * host.n_events / seq_elapsed
+    seq_lat_ms = np.array(lat) * 1e3
+    log(f"[bench] batched, one at a time: {seq_value:.0f} events/s, "
+        f"{seq_elapsed / args.steps * 1e3:.3f} ms/step")
+
+    # ---- the timed region: a continuous stream of resident batches, each a
+    # full pass of the path, args.in_flight of them on the device at once
+    # (continuous batching on the context's slots)
+    k_in = max(1, min(args.in_flight, SERVE_SLOTS - 1))
+    outs = [out] + [sm.DeviceOut(host.n_events, host.n_hits // 4 + 1024, host.n_velo + 1024)
+                    for _ in range(k_in - 1)]
+    run_in_flight(ctx, sm, db, outs, max(args.warmup, 2 * k_in))
+    torch.cuda.synchronize()
+    elapsed, lat = run_in_flight(ctx, sm, db, outs, args.steps)
+    torch.cuda.synchronize()
     value = args.steps * host.n_events / elapsed
     lat_ms = np.array(lat) * 1e3
-    log(f"[bench] batched: {value:.0f} events/s, {elapsed / args.steps * 1e3:.3f} ms/step")
+    # every slot's last outputs equal the first run's
+    same = True
+    for o in outs:
+        same = same and all(a.tobytes() == b.tobytes() for a, b in zip(o.to_host(), gpu))
+    log(f"[bench] batched, {k_in} in flight: {value:.0f} events/s, "
+        f"{elapsed / args.steps * 1e3:.3f} ms/step, outputs identical: {same}")
+    del outs
 
     # ---- per-kernel device time from HIP events on the launch stream
     kt = [ctx.profile(db, out, stream) for _ in range(max(5, args.steps // 5))]
@@ -415,14 +463,25 @@ def main():
         "config": {"workload": WORKLOADS[args.workload].format(n=host.n_events),
                    "events_per_batch": host.n_events, "hits": host.n_hits,
                    "velo_states": host.n_velo, "seeds": n_seeds, "long_tracks": n_longs,
-                   "form": "batched: captured graph, persistent kernels, LPT work queue",
+                   "form": "batched: captured graph, persistent kernels, LPT work queue; "
+                           "%d batches in flight" % k_in,
                    "search_dtype": "f32", "fit_dtype": "f64",
                    "p_min_mev": float(args.p_min) if args.p_min > 0 else 3000.0},
         "plain_events_per_s": round(plain, 1) if plain else None,
         "batched_over_plain": round(value / plain, 2) if plain else None,
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                        "p99": round(float(np.percentile(lat_ms, 99)), 4),
-                       "what": "per-batch latency of the batched form, call to results"},
+                       "what": "per-batch latency with %d batches in flight, submit to results"
+                               % k_in},
+        "in_flight": {"batches": k_in, "outputs_identical": bool(same),
+                      "what": "a continuous stream of resident batches on the context's "
+                              "slots (each its own stream and captured graph); a batch "
+                              "starts when an earlier one completes"},
+        "one_at_a_time": {"events_per_s": round(seq_value, 1),
+                          "ms_per_batch": round(seq_elapsed / args.steps * 1e3, 4),
+                          "latency_ms": {"p50": round(float(np.percentile(seq_lat_ms, 50)), 4),
+                                         "p99": round(float(np.percentile(seq_lat_ms, 99)), 4)},
+                          "what": "one blocking call per batch, call to results"},
         "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
         "launch": dict(ctx.launch_shape(host), source=ctx.shape_source),
         "served": serve,
