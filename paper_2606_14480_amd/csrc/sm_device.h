@@ -232,11 +232,24 @@ struct Third {
 
 // Per-slot kernel context in device memory: kernels read scratch pointers and
 // parameters through one pointer, so no argument has to stay in registers.
+// A slot's links between its pinned host memory and the batched sequence:
+// the preparing launch gets the batch descriptor in pinned host memory as
+// its D and writes the device copy that every later launch reads; the copy
+// kernel's workgroup that writes the totals also writes the counters back to
+// pinned host memory.  Null pointers: the host moves these itself.
+struct Link {
+  Desc *desc;             // device descriptor written by the preparing launch
+  Counters *hcnt;         // pinned host copy of the counters
+  const Counters *cnt3;   // third iteration's counters (device), when on
+  Counters *hcnt3;        // their pinned host copy
+};
+
 struct KCtx {
   Scratch S;   // main form: per-workgroup arrays for seed_wgs workgroups
   Scratch SB;  // big-item form: own per-workgroup arrays, shared pools and counters
   DevParams P;
   Third T;     // third iteration (null pointers when off)
+  Link L;
 };
 
 }  // namespace smk

@@ -1773,6 +1773,18 @@ __device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Sc
     match_event_impl<false, NT, kSel>(D, S, P, e, plain, wg, sh);
 }
 
+// The preparing launch's copy of the batch descriptor from pinned host
+// memory (its D) to the device copy that the later launches read; nothing
+// when D is that copy already.
+__device__ __forceinline__ void link_desc(const Desc *__restrict__ D, const KCtx *__restrict__ K) {
+  static_assert(sizeof(Desc) % 4 == 0, "the descriptor is copied in 4-byte words");
+  Desc *dst = K->L.desc;
+  if (dst == nullptr || dst == D) return;
+  const unsigned *src = reinterpret_cast<const unsigned *>(D);
+  auto *out = gmem(reinterpret_cast<unsigned *>(dst));
+  for (int i = threadIdx.x; i < (int)(sizeof(Desc) / 4); i += blockDim.x) out[i] = src[i];
+}
+
 // Size class of an item for the longest-first order: kFineSub classes per
 // octave of (hits + 1), from its leading four bits; monotone in the size.
 constexpr int kFineSub = 16;
@@ -2001,6 +2013,8 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
 
   const int tid = tidx();
   const size_t wg = blockIdx.x;
+  // a preparing launch's D is the pinned host copy of the descriptor (same
+  // contents as the device copy it writes; its reads stay in the scalar cache)
   const int32_t *zone_off = D->b.zone_off;
   const float *hx = D->b.hit_x, *hz = D->b.hit_z;
   const int32_t *hid = D->b.hit_id;
@@ -2014,6 +2028,9 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
       // counter loads behind it.
       __shared__ int s_stall;
       if (blockIdx.x == 0) {
+        // the device copy of the descriptor for the later launches first,
+        // then the preparation
+        link_desc(D, K);
         const unsigned nb = prepare_batch(D, K, 0);
         __syncthreads();
         if (tid == 0)
@@ -2206,6 +2223,7 @@ __global__ __launch_bounds__(kSeedWG, 4) void k_match(const Desc *__restrict__ D
 // so the longest items start first and the persistent grid drains evenly.
 __global__ __launch_bounds__(1024) void k_prepare(const Desc *__restrict__ D,
                                                   const KCtx *__restrict__ K, int plain) {
+  link_desc(D, K);
   prepare_batch(D, K, plain);
 }
 
@@ -2299,6 +2317,26 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
     S.cnt->total_longs = cl;
     if (cs > D->seed_cap) raise_flag(S.cnt, F_OUT_SEED);
     if (cl > D->long_cap) raise_flag(S.cnt, F_OUT_LONG);
+    __threadfence();
+  }
+  if (last && K->L.hcnt != nullptr) {
+    // the counters are final: this workgroup writes them to the slot's
+    // pinned host memory, a word per thread, read through L2 (this
+    // workgroup read the flags above)
+    static_assert(sizeof(Counters) % 4 == 0 && sizeof(Counters) / 4 <= 128,
+                  "the counters are copied in 4-byte words, two structs per workgroup");
+    constexpr int kW = (int)(sizeof(Counters) / 4);
+    __syncthreads();
+    const bool second = tid >= 128;
+    const int i = tid & 127;
+    const Counters *src = second ? K->L.cnt3 : S.cnt;
+    Counters *dst = second ? K->L.hcnt3 : K->L.hcnt;
+    if (i < kW && src != nullptr && dst != nullptr) {
+      reinterpret_cast<unsigned *>(dst)[i] =
+          __hip_atomic_load(reinterpret_cast<const unsigned *>(src) + i, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence_system();
+    }
   }
   if (bad) return;
   for (int e = e_lo; e < e_hi; ++e) {

@@ -363,6 +363,11 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
   kc.SB = B;
   kc.P = c->dp;
   kc.T = T;
+  // the preparing launch writes the device descriptor, the copy kernel the
+  // counters in pinned memory (both passes' with the third iteration)
+  const bool third = c->p.third_iter == 1;
+  kc.L = smk::Link{s.d_desc, s.h_cnt, third ? T.cnt : nullptr, third ? s.h_cnt3 : nullptr};
+  k3.L = smk::Link{s.d_desc3, nullptr, nullptr, nullptr};
   if (hipMemcpy(s.d_kctx, &kc, sizeof(kc), hipMemcpyHostToDevice) != hipSuccess) return SM_ERR_DEVICE;
   if (c->p.third_iter == 1 &&
       hipMemcpy(s.d_kctx3, &k3, sizeof(k3), hipMemcpyHostToDevice) != hipSuccess)
@@ -525,9 +530,10 @@ void fill_descs(sm_ctx *c, Slot &s, const sm_batch &b, const sm_out &o) {
 // big form, then the main form), on its own context (pools, counts,
 // counters).
 int enqueue_third(sm_ctx *c, Slot &s, hipStream_t q) {
-  int e = hipMemcpyAsync(s.d_desc3, s.h_desc3, sizeof(Desc), hipMemcpyHostToDevice, q);
-  if (!e) e = smk_launch_clean(s.d_desc, s.d_kctx, 1024, q);
-  if (!e) e = smk_launch_seed_big(s.d_desc3, s.d_kctx3, c->big_wgs, c->lds_big, 1, sel_of(c), q);
+  int e = smk_launch_clean(s.d_desc, s.d_kctx, 1024, q);
+  // its preparing launch reads the pass's descriptor from pinned memory and
+  // writes the device copy
+  if (!e) e = smk_launch_seed_big(s.h_desc3, s.d_kctx3, c->big_wgs, c->lds_big, 1, sel_of(c), q);
   if (!e) e = smk_launch_seed_nomatch(s.d_desc3, s.d_kctx3, s.grid, s.lds_hits, q);
   return e;
 }
@@ -535,37 +541,37 @@ int enqueue_third(sm_ctx *c, Slot &s, hipStream_t q) {
 // The head of the batched sequence: the batch's preparation and the
 // big-item form in one launch (its workgroup 0 prepares), or, with input
 // validation or the Hough variant, k_prepare, k_validate and the big form.
-int enqueue_prepare_big(sm_ctx *c, Slot &s, hipStream_t q) {
+// The preparing launch reads the descriptor at src: the slot's pinned copy
+// (it then writes the device copy for the launches after it) or the device
+// copy itself.
+int enqueue_prepare_big(sm_ctx *c, Slot &s, hipStream_t q, const Desc *src) {
   const smk::KCtx *S = s.d_kctx;
   const Desc *d = s.d_desc;
   if (c->p.uv_mode == 0 && !c->cfg.validate)
-    return smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, 1, sel_of(c), q);
-  int e = smk_launch_prepare(d, S, 0, q);
+    return smk_launch_seed_big(src, S, c->big_wgs, c->lds_big, 1, sel_of(c), q);
+  int e = smk_launch_prepare(src, S, 0, q);
   if (!e && c->cfg.validate) e = smk_launch_validate(d, S, 1024, q);
   if (!e && c->p.uv_mode == 0)
     e = smk_launch_seed_big(d, S, c->big_wgs, c->lds_big, 0, sel_of(c), q);
   return e;
 }
 
-// The batched sequence, replayed from a captured graph: the batch
-// descriptor's upload from the slot's pinned copy, the kernels, and the
-// counters' copy back to pinned memory (read when the graph runs, so one
-// graph serves every batch of the slot).
+// The batched sequence, replayed from a captured graph: kernels only.  The
+// preparing launch reads the batch descriptor from the slot's pinned copy
+// when the graph runs (so one graph serves every batch of the slot) and
+// writes its device copy; the copy kernel writes the counters back to pinned
+// memory.
 sm_status enqueue_batched(sm_ctx *c, Slot &s, hipStream_t st) {
   const smk::KCtx *S = s.d_kctx;
   const Desc *d = s.d_desc;
   auto seq = [&](hipStream_t q) -> hipError_t {
-    int e = hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, q);
-    if (!e) e = enqueue_prepare_big(c, s, q);
+    int e = enqueue_prepare_big(c, s, q, s.h_desc);
     if (!e && !s.fuse) e = smk_launch_seed_nomatch(d, S, s.grid, s.lds_hits, q);
     if (!e && s.fuse)
       e = smk_launch_seed(d, S, 0, -1, 1, s.grid, s.lds_hits, 0, c->p.uv_mode, sel_of(c), q);
     if (!e && c->p.third_iter == 1) e = enqueue_third(c, s, q);
     if (!e && !s.fuse) e = smk_launch_match(d, S, match_grid(c, s.grid), sel_of(c), q);
     if (!e) e = smk_launch_copy(d, S, 1024, q);
-    if (!e) e = hipMemcpyAsync(s.h_cnt, s.S.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q);
-    if (!e && c->p.third_iter == 1)
-      e = hipMemcpyAsync(s.h_cnt3, s.T.cnt, sizeof(Counters), hipMemcpyDeviceToHost, q);
     return (hipError_t)e;
   };
   for (const Slot::Captured &g : s.graphs)
@@ -606,7 +612,7 @@ sm_status enqueue_timed(sm_ctx *c, Slot &s, hipStream_t q, hipEvent_t *ev) {
   const smk::KCtx *S = s.d_kctx;
   const Desc *d = s.d_desc;
   int e = hipEventRecord(ev[0], q);
-  if (!e) e = enqueue_prepare_big(c, s, q);   // preparation and big form
+  if (!e) e = enqueue_prepare_big(c, s, q, d);   // preparation and big form
   if (!e) e = hipEventRecord(ev[1], q);
   if (!e) e = hipEventRecord(ev[2], q);
   if (!e && !s.fuse) e = smk_launch_seed_nomatch(d, S, s.grid, s.lds_hits, q);
@@ -690,8 +696,8 @@ sm_status run_blocking(sm_ctx *c, const sm_batch *b, sm_out *o, void *stream, bo
   for (int tries = 0; tries < kMaxTries; ++tries) {
     if ((st = fit_batch(c, s, *b)) != SM_OK) return st;
     fill_descs(c, s, *b, *o);
-    // the batched graph uploads the descriptor and copies the counters back
-    // itself; the plain and timed sequences do it here
+    // the batched graph reads the pinned descriptor and writes the pinned
+    // counters from its kernels; the plain and timed sequences move them here
     const bool graph = !times && !plain;
     if (!graph &&
         hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(Desc), hipMemcpyHostToDevice, q) != hipSuccess)
@@ -1116,10 +1122,12 @@ sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *c
         hipMalloc(&s.d_kctx, sizeof(smk::KCtx)) != hipSuccess ||
         hipMalloc(&s.d_desc3, sizeof(Desc)) != hipSuccess ||
         hipMalloc(&s.d_kctx3, sizeof(smk::KCtx)) != hipSuccess ||
-        hipHostMalloc(&s.h_desc, sizeof(Desc), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&s.h_desc3, sizeof(Desc), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&s.h_cnt, sizeof(Counters), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&s.h_cnt3, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
+        // coherent: the batched sequence's kernels read the descriptors and
+        // write the counters here directly
+        hipHostMalloc(&s.h_desc, sizeof(Desc), hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc(&s.h_desc3, sizeof(Desc), hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc(&s.h_cnt, sizeof(Counters), hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc(&s.h_cnt3, sizeof(Counters), hipHostMallocCoherent) != hipSuccess) {
       hipGetLastError();
       sm_destroy(c);
       return SM_ERR_DEVICE;
@@ -1168,7 +1176,7 @@ static sm_status start_slot(sm_ctx *c, Slot &s) {
   sm_status st = fit_batch(c, s, s.batch);
   if (st != SM_OK) return st;
   fill_descs(c, s, s.batch, *s.out);
-  // the graph uploads the descriptor and copies the counters back
+  // the graph's kernels read the pinned descriptor and write the pinned counters
   if ((st = enqueue_batched(c, s, s.stream)) != SM_OK) return st;
   return hip_status(hipEventRecord(s.done, s.stream));
 }
