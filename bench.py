@@ -270,6 +270,94 @@ def extra_leg(ctx, sm, name, host, steps, warmup, parity_events, over):
     return res
 
 
+class TiledBatch:
+    """A device batch holding the events of another r times over (hit and
+    VELO offsets shifted per copy): batches far larger than the host can
+    generate, of the same events."""
+
+    def __init__(self, sm, db, r):
+        import torch
+        nh, nv = db.n_hits, db.n_velo
+        assert r * nh < 2 ** 31 and r * nv < 2 ** 31, "offsets are int32"
+        self.n_events, self.n_hits, self.n_velo = r * db.n_events, r * nh, r * nv
+
+        def offs(o, n):
+            o = o.to(torch.int64)
+            return torch.cat([o[:-1] + k * n for k in range(r)] + [o[-1:] + (r - 1) * n]) \
+                .to(torch.int32)
+
+        self.zone_off = offs(db.zone_off, nh)
+        self.velo_off = offs(db.velo_off, nv)
+        rep = lambda a: a.repeat(r)
+        self.hit_x, self.hit_z, self.hit_id = rep(db.hit_x), rep(db.hit_z), rep(db.hit_id)
+        self.velo = [rep(getattr(db, "velo_" + k)) for k in ("x", "y", "z", "tx", "ty", "id")]
+        v = [a.data_ptr() for a in self.velo]
+        self.c = sm.Batch(n_events=self.n_events, pad=0, n_hits=self.n_hits, n_velo=self.n_velo,
+                          zone_off=self.zone_off.data_ptr(), hit_x=self.hit_x.data_ptr(),
+                          hit_z=self.hit_z.data_ptr(), hit_id=self.hit_id.data_ptr(),
+                          velo_off=self.velo_off.data_ptr(), velo_x=v[0], velo_y=v[1],
+                          velo_z=v[2], velo_tx=v[3], velo_ty=v[4], velo_id=v[5], n_ut=0,
+                          ut_off=None, ut_x=None, ut_id=None)
+
+
+def stress_sweep(ctx, sm, host, reps, steps):
+    """Batch-size sweep of the stress workload: its events tiled r times in
+    one batch, for each r while the device holds it; every copy's outputs
+    must equal the single batch's, byte for byte."""
+    import torch
+    stream = torch.cuda.current_stream()
+    db = sm.DeviceBatch(host)
+    base = run_sized(ctx, sm, db, host, stream)
+    bs, bl = base.n_seeds, base.n_longs
+    seed_rec = base.seeds[: bs * sm.SEED_DTYPE.itemsize]
+    long_rec = base.longs[: bl * sm.LONG_DTYPE.itemsize]
+    total = torch.cuda.mem_get_info()[1]
+    rows, per_event = [], None
+    for r in reps:
+        if r * db.n_hits >= 2 ** 31:
+            rows.append({"copies": r, "events": r * host.n_events, "skipped": "more than 2^31 hits "
+                         "(int32 hit offsets)"})
+            continue
+        if per_event is not None and per_event * r * host.n_events > 0.8 * total:
+            rows.append({"copies": r, "events": r * host.n_events,
+                         "skipped": "projected device memory above 80 % of the device"})
+            continue
+        tb = TiledBatch(sm, db, r)
+        out = sm.DeviceOut(tb.n_events, r * bs + 1024, r * bl + 1024)
+        if ctx.run(tb, out, stream, check=False) == sm.ERR_CAPACITY:
+            raise RuntimeError("tiled stress batch: outputs sized from the single batch overflowed")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.run(tb, out, stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        used = total - torch.cuda.mem_get_info()[0]
+        same = out.n_seeds == r * bs and out.n_longs == r * bl and all(
+            torch.equal(out.seeds[k * seed_rec.numel():(k + 1) * seed_rec.numel()], seed_rec) and
+            torch.equal(out.longs[k * long_rec.numel():(k + 1) * long_rec.numel()], long_rec)
+            for k in range(r))
+        per_event = used / tb.n_events
+        rows.append({"copies": r, "events": tb.n_events, "hits": tb.n_hits,
+                     "events_per_s": round(tb.n_events / dt, 1), "ms_per_batch": round(dt * 1e3, 2),
+                     "device_bytes_in_use": int(used), "copies_identical": bool(same)})
+        log(f"[bench] stress sweep: {rows[-1]}")
+        del tb, out
+        torch.cuda.empty_cache()
+    del db, base
+    torch.cuda.empty_cache()
+    hit_bytes = 12 * host.n_hits / host.n_events
+    return {"what": "the stress batch's events tiled r times in one batch; each copy's outputs "
+                    "compared byte for byte with the single batch's (itself checked against the "
+                    "oracle on events 0-499)",
+            "device_bytes": int(total),
+            "limit": "int32 hit offsets: at most 2^31 hits per batch (about %d stress events); "
+                     "device memory would hold about %d at the largest run's bytes per event"
+                     % (2 ** 31 / (host.n_hits / host.n_events),
+                        0.8 * total / per_event if per_event else 0),
+            "hit_bytes_per_event": round(hit_bytes, 1), "batches": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,6 +386,9 @@ def main():
                     help="further workloads at their stated sizes, timed beside the headline "
                          "(comma list of uneven, stress, ghost, ut, third; empty: none)")
     ap.add_argument("--leg-steps", type=int, default=5)
+    ap.add_argument("--stress-sweep", default="1,2,4,8,12",
+                    help="batch-size sweep of the stress leg: copies of its events per batch "
+                         "(empty: none)")
     ap.add_argument("--in-flight", type=int, default=2,
                     help="resident batches on the device at once in the timed region "
                          "(continuous batching over the context's slots)")
@@ -423,6 +514,9 @@ def main():
         leg_res[name] = extra_leg(ctx, sm, name, lh, args.leg_steps, 1,
                                   0 if args.no_parity else (lh.n_events if name == "uneven" else 500),
                                   over)
+        reps = [int(x) for x in args.stress_sweep.split(",") if x]
+        if name == "stress" and reps:
+            leg_res[name]["batch_size_sweep"] = stress_sweep(ctx, sm, lh, reps, 2)
         del lh
     leg_hosts.clear()
 

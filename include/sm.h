@@ -349,9 +349,10 @@ typedef struct {
 
 /* Replaces the context's table of launch shapes (copied; n = 0 clears it).
  * Each batched call (sm_run, sm_submit, sm_profile) takes the first entry
- * whose class holds its batch, else the built-in choice (sm_config's
- * seed_wgs and lds_hits, else four workgroups per CU and 1.5x the mean item
- * size).  Per-workgroup scratch for the largest grid of the table is
+ * whose class holds its batch; a batch with more events than every class of
+ * its item size takes the entry of the smallest such item size with the
+ * most events; else the built-in choice (sm_config's seed_wgs and lds_hits,
+ * else four workgroups per CU and 1.5x the mean item size).  Per-workgroup scratch for the largest grid of the table is
  * allocated here: SM_ERR_OOM if it does not fit, SM_ERR_BUSY while a serving
  * slot is in use, SM_ERR_INVALID for an entry out of range.  Outputs do not
  * depend on the shape. */

@@ -407,8 +407,18 @@ int lds_hits_for(const sm_ctx *c, const sm_batch &b) {
 // else the built-in one.
 sm_shape choose_shape(const sm_ctx *c, const sm_batch &b) {
   const double mean = b.n_events > 0 ? (double)b.n_hits / (2.0 * b.n_events) : 0.0;
-  for (const sm_shape &e : c->shapes)
-    if (mean <= (double)e.max_mean_item_hits && b.n_events <= e.max_events) return e;
+  // a batch beyond every class of its item size runs in the largest class
+  // of the smallest item size that holds it (the same regime: many rounds of
+  // items per workgroup)
+  const sm_shape *far = nullptr;
+  for (const sm_shape &e : c->shapes) {
+    if (mean > (double)e.max_mean_item_hits) continue;
+    if (b.n_events <= e.max_events) return e;
+    if (!far || e.max_mean_item_hits < far->max_mean_item_hits ||
+        (e.max_mean_item_hits == far->max_mean_item_hits && e.max_events > far->max_events))
+      far = &e;
+  }
+  if (far) return *far;
   sm_shape d{};
   d.seed_wgs = c->base_wgs;
   d.lds_hits = lds_hits_for(c, b);

@@ -141,9 +141,10 @@ def test_autotune_roundtrip(sm, tmp_path):
 
 
 def test_shape_table_classes(sm):
-    """Batches take the first table entry whose class holds them; a grid
-    larger than the context's grows its scratch; entries out of range are
-    refused; outputs do not depend on the shape."""
+    """Batches take the first table entry whose class holds them (a batch
+    beyond every class of its item size the largest of the smallest item
+    size); a grid larger than the context's grows its scratch; entries out of
+    range are refused; outputs do not depend on the shape."""
     small = ev.generate(ev.config(2, n_events=30))
     big = ev.generate(ev.config(4, n_events=30))
     import torch
@@ -160,6 +161,20 @@ def test_shape_table_classes(sm):
         for b in (small, big):
             for x, y in zip(sm.reconstruct(c, b), sm.reconstruct(ref, b)):
                 assert x.tobytes() == y.tobytes()
+        # a batch with more events than every class of its item size: the
+        # class of the smallest item size that holds it, with the most events
+        from types import SimpleNamespace as NS
+        far = [{"max_mean_item_hits": 1024, "max_events": 64, "seed_wgs": 5 * cus, "lds_hits": 1536},
+               {"max_mean_item_hits": 1024, "max_events": 512, "seed_wgs": 4 * cus,
+                "lds_hits": 1280},
+               {"max_mean_item_hits": 2048, "max_events": 128, "seed_wgs": 3 * cus,
+                "lds_hits": 2048}]
+        c.set_shapes(far)
+        assert c.launch_shape(NS(n_events=1000, n_hits=1000 * 1000))["seed_wgs"] == 4 * cus
+        assert c.launch_shape(NS(n_events=100, n_hits=100 * 1000))["seed_wgs"] == 4 * cus
+        assert c.launch_shape(NS(n_events=50, n_hits=50 * 1000))["seed_wgs"] == 5 * cus
+        assert c.launch_shape(NS(n_events=1000, n_hits=1000 * 3000))["seed_wgs"] == 3 * cus
+        assert c.launch_shape(NS(n_events=1000, n_hits=1000 * 5000))["max_events"] == 0
         for bad in ({"max_mean_item_hits": 1, "max_events": 1, "seed_wgs": 1, "lds_hits": 1024},
                     {"max_mean_item_hits": 1, "max_events": 1, "seed_wgs": 64, "lds_hits": 1000},
                     {"max_mean_item_hits": 1, "max_events": 1, "seed_wgs": 64, "lds_hits": 8192}):
