@@ -231,6 +231,60 @@ def test_stress_batch_with_oracle_subset(orc, sm, ctx):
     PT.assert_parity(st)
 
 
+def test_stress_full_size_and_tiled(orc, sm, ctx):
+    """The stress workload at its stated size: 50,000 events in one batch,
+    the oracle on events 0..499; then the same events twice over in one
+    100,000-event batch (offsets shifted on the device), whose two copies
+    must each equal the single batch's outputs byte for byte."""
+    import torch
+    b = ev.generate_parallel(ev.config(4), 16)
+    assert b.n_events == 50000
+    say("[gpu] stress 50000, hits", b.n_hits, "max per event", int(b.event_hits().max()))
+    db = sm.DeviceBatch(b)
+    out = sm.DeviceOut(b.n_events, b.n_hits // 8 + 1024, b.n_velo + 1024)
+    assert ctx.run(db, out) == sm.OK
+    g = out.to_host()
+    n = 500
+    sub = b.subset(range(n))
+    gs = (g[0][:n + 1], g[1][:g[0][n]], g[2][:n + 1], g[3][:g[2][n]])
+    o = orc.run(sub, threads=8)
+    st = PT.compare(o, gs, n)
+    if st["mismatches"]:
+        st = PT.compare(o, gs, n, band=(orc.run(sub, PT.eps_params(orc, 1e-4), threads=8),
+                                        orc.run(sub, PT.eps_params(orc, -1e-4), threads=8)))
+    say(f"[gpu] stress 50000 subset: seeds {st['seeds_o']}/{st['seeds_g']} "
+        f"mismatches {st['mismatches']}")
+    PT.assert_parity(st)
+    # two copies of the batch in one
+    nh, nv = db.n_hits, db.n_velo
+
+    def twice(a):
+        return torch.cat([a, a])
+
+    def offs(a, step):
+        a = a.to(torch.int64)
+        return torch.cat([a[:-1], a + step]).to(torch.int32)
+
+    t = dict(zone_off=offs(db.zone_off, nh), velo_off=offs(db.velo_off, nv),
+             hit_x=twice(db.hit_x), hit_z=twice(db.hit_z), hit_id=twice(db.hit_id),
+             **{"velo_" + k: twice(getattr(db, "velo_" + k)) for k in ("x", "y", "z", "tx", "ty", "id")})
+    tb = sm.Batch(n_events=2 * b.n_events, pad=0, n_hits=2 * nh, n_velo=2 * nv, n_ut=0,
+                  ut_off=None, ut_x=None, ut_id=None, **{k: v.data_ptr() for k, v in t.items()})
+    out2 = sm.DeviceOut(2 * b.n_events, 2 * out.n_seeds + 1024, 2 * out.n_longs + 1024)
+    ctx.run_c(tb, out2.c)
+    say(f"[gpu] stress 100000 (two copies): seeds {out2.n_seeds} longs {out2.n_longs}")
+    assert out2.n_seeds == 2 * out.n_seeds and out2.n_longs == 2 * out.n_longs
+    g2 = out2.to_host()
+    for k in range(2):
+        for a, a2, cnt in ((g[1], g2[1], out.n_seeds), (g[3], g2[3], out.n_longs)):
+            assert a2[k * cnt:(k + 1) * cnt].tobytes() == a.tobytes()
+        for off, off2 in ((g[0], g2[0]), (g[2], g2[2])):
+            seg = off2[k * b.n_events:(k + 1) * b.n_events + 1].astype(np.int64)
+            assert np.array_equal(seg - seg[0], off.astype(np.int64))
+    del db, out, out2, t
+    torch.cuda.empty_cache()
+
+
 def test_tied_hit_positions(orc, sm, ctx):
     """Hits with identical x in a zone: window and closest-hit choices follow
     the lower position, as in the oracle."""
