@@ -300,10 +300,22 @@ class TiledBatch:
                           ut_off=None, ut_x=None, ut_id=None)
 
 
-def stress_sweep(ctx, sm, host, reps, steps):
+def stress_sweep(sm, params, host, reps, steps):
     """Batch-size sweep of the stress workload: its events tiled r times in
     one batch, for each r while the device holds it; every copy's outputs
-    must equal the single batch's, byte for byte."""
+    must equal the single batch's, byte for byte.  It runs on a context of
+    its own, closed at the end, so that the largest batch's scratch does not
+    stay with the bench's context."""
+    import torch
+    ctx = sm.Context(params=params)
+    try:
+        return _stress_sweep(ctx, sm, host, reps, steps)
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
+
+
+def _stress_sweep(ctx, sm, host, reps, steps):
     import torch
     stream = torch.cuda.current_stream()
     db = sm.DeviceBatch(host)
@@ -516,7 +528,8 @@ def main():
                                   over)
         reps = [int(x) for x in args.stress_sweep.split(",") if x]
         if name == "stress" and reps:
-            leg_res[name]["batch_size_sweep"] = stress_sweep(ctx, sm, lh, reps, 2)
+            leg_res[name]["batch_size_sweep"] = stress_sweep(sm, sm.default_params(**over), lh,
+                                                             reps, 2)
         del lh
     leg_hosts.clear()
 
