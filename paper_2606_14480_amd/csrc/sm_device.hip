@@ -308,28 +308,34 @@ __device__ __forceinline__ int zclosest(const float *X, const float *Z, const Se
   if constexpr (kLds) {
     // from the bin of pred - tol, four hits per LDS round trip, each tested
     // with selects rather than branches, in ascending order as the one-hit
-    // walk does
+    // walk does.  The distance to beat starts at +inf, so the first hit in
+    // the window is taken as the walk takes it.  The four loads are not
+    // guarded: past the zone's end (at most three hits) they stay inside the
+    // item's LDS hit arrays, and those x are replaced by +inf.  The walk ends
+    // past the window or at the zone's end.
     const int k = kbin((float)lo_v);
     int i = sh.zoff[L] + (k > 0 ? (int)sh.bins[L][k - 1] : 0);
+    bd = __builtin_inf();
     for (;; i += 4) {
       float x4[4], z4[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        x4[q] = i + q < hi ? X[i + q] : __builtin_inff();
-        z4[q] = i + q < hi ? Z[i + q] : 0.0f;
+        const float xv = X[i + q];
+        x4[q] = i + q < hi ? xv : __builtin_inff();
+        z4[q] = Z[i + q];
       }
       double x;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         x = x4[q];
         const double d = fabs(x - pred);
-        const bool take = x >= lo_v && x <= hi_v && (best < 0 || d < bd - kTieMm);
+        const bool take = x >= lo_v && x <= hi_v && d < bd - kTieMm;
         best = take ? i + q : best;
         bd = take ? d : bd;
         xb = take ? x4[q] : xb;
         zb = take ? z4[q] : zb;
       }
-      if (!(x <= hi_v)) break;
+      if (!(x <= hi_v) || i + 4 >= hi) break;
     }
   } else {
     for (int i = zlower<kLds>(X, sh, L, lo_v); i < hi; ++i) {
