@@ -269,11 +269,16 @@ __device__ __forceinline__ int zlower(const float *X, const SeedShared<NT> &sh, 
     const int k = kbin((float)v);
     int i = lo + (k > 0 ? (int)sh.bins[L][k - 1] : 0);
     // from the bin's first hit, four hits per LDS round trip: the hits are
-    // sorted, so the count of them below v is how far to move
+    // sorted, so the count of them below v is how far to move.  The loads
+    // are not guarded: i never passes the zone's end, so they reach at most
+    // three hits past it, inside the item's LDS hit arrays, and those read as v
     for (;;) {
       T x4[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) x4[q] = i + q < hi ? (T)X[i + q] : v;
+      for (int q = 0; q < 4; ++q) {
+        const T xv = (T)X[i + q];
+        x4[q] = i + q < hi ? xv : v;
+      }
       int c = 0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) c += x4[q] < v;
