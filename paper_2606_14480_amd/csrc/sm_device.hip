@@ -90,8 +90,19 @@ __device__ __forceinline__ unsigned wave_append(unsigned *counter) {
   return base + r;
 }
 
-// Exclusive scan of one int per thread over a workgroup of NT threads.
-template <int NT>
+// A workgroup barrier that orders LDS accesses only: unlike __syncthreads it
+// does not wait for the waves' outstanding global loads and stores, so loads
+// issued before it keep streaming in.  Only for code that passes nothing
+// through global memory between the workgroup's threads across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Exclusive scan of one int per thread over a workgroup of NT threads
+// (kLdsOnly: its barriers are lds_barrier).
+template <int NT, bool kLdsOnly = false>
 __device__ __forceinline__ int block_excl_scan(int v, int *s_tmp, int &total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int x = v;
@@ -101,7 +112,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int *s_tmp, int &total) {
     if (lane >= o) x += y;
   }
   if (lane == 63) s_tmp[w] = x;
-  __syncthreads();
+  if constexpr (kLdsOnly) lds_barrier(); else __syncthreads();
   int pre = 0, tot = 0;
 #pragma unroll
   for (int i = 0; i < NT / 64; ++i) {
@@ -109,7 +120,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int *s_tmp, int &total) {
     pre += i < w ? t : 0;
     tot += t;
   }
-  __syncthreads();
+  if constexpr (kLdsOnly) lds_barrier(); else __syncthreads();
   total = tot;
   return pre + x - v;
 }
@@ -406,13 +417,15 @@ __device__ __forceinline__ void xz_triplets(const float *X, const float *Z, Seed
       cnt_j = en > st ? en - st : 0;
     }
     int total;
-    const int excl = block_excl_scan<NT>(cnt_j, sh.tmp, total);
+    // LDS-only barriers up to the round's end; the triplets beyond the LDS
+    // list go to global memory and are read after the round's __syncthreads
+    const int excl = block_excl_scan<NT, true>(cnt_j, sh.tmp, total);
     sh.scan[threadIdx.x] = excl;
     sh.a0[threadIdx.x] = st;
     sh.a1[threadIdx.x] = i1 | (it << 30);
     SlotMap<NT> *dmap = reinterpret_cast<SlotMap<NT> *>(sh.u.xtab + kTripLds);
     for (int d = excl; d < excl + cnt_j && d < kDmap<NT>; ++d) dmap[d] = (SlotMap<NT>)threadIdx.x;
-    __syncthreads();
+    lds_barrier();
     const int nj = min(NT, N1 - c0);
     for (int d0 = 0; d0 < total; d0 += NT) {
       const int d = d0 + (int)threadIdx.x;
@@ -838,6 +851,14 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
   unsigned long long *cscore = small ? sh.cscore : S.cscore + co;
   int *cinfo = small ? sh.cinfo : S.cinfo + co;
   unsigned long long *xt = small ? sh.u.xtab : S.tbl + wg * (size_t)S.tbl_cap;
+  // barriers: in the LDS form the vote records and tables are in LDS, so the
+  // barriers up to the UV search order LDS only; the global form keeps
+  // __syncthreads throughout
+  auto bar = [&]() {
+    if constexpr (kSmall) lds_barrier(); else __syncthreads();
+  };
+  // the global form reads the candidate records written by other threads
+  if constexpr (!kSmall) __syncthreads();
   if (!small && nx > S.tbl_cap) {
     if (tid == 0) { raise_flag(cnt, F_TBL); atomicMax(&S.need[2], (unsigned)nx); }
     nc = 0;
@@ -849,7 +870,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     }
   }
   for (int i = tid; i < nx && nc > 0; i += NT) xt[i] = ~0ull;
-  __syncthreads();
+  bar();
   // compact x index of the hit in slot k of candidate i, or -1
   auto xidx = [&](unsigned i, int k) -> int {
     const int p = small ? (int)sh.cpos[i][k] - 1 : gmem(cand)[i].pos[k];
@@ -865,7 +886,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
       if (p >= 0) atomicMin(&xt[p], sc);
     }
   }
-  __syncthreads();
+  bar();
   for (unsigned i = tid; i < nc; i += NT) {
     const unsigned long long sc = cscore[i];
     int own = 0;
@@ -880,7 +901,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     const unsigned long long km = __ballot(kept);
     if (kept && lane_rank(km) == 0) atomicAdd(&sh.nkept, (unsigned)__popcll(km));
   }
-  __syncthreads();
+  bar();
   // the item's pool range, for the tracks that survived the vote (at least
   // as many as its seeds): its own kPoolPerItem slots, or, for an item with
   // more, a range of the overflow area claimed now (the atomic's latency
@@ -911,7 +932,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     };
     static_assert(kHT == 512, "slot_of takes 9 bits");
     for (int i = tid; i < kHT; i += NT) hk[i] = ~0ull;
-    __syncthreads();
+    lds_barrier();
     for (unsigned j = tid; j < nc; j += NT) {
       if (cinfo[j] & ((1 << 3) | (1 << 4))) continue;   // kept iteration-0 only
       const unsigned long long sc = cscore[j];
@@ -919,7 +940,7 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
         if (atomicCAS(&hk[h], ~0ull, sc) == ~0ull) { hv[h] = (int)j; break; }
       }
     }
-    __syncthreads();
+    lds_barrier();
     for (unsigned i = tid; i < nc; i += NT) {
       const int ci = cinfo[i];
       if ((ci & (1 << 4)) || !(ci & (1 << 3))) continue;   // kept iteration-1 only
@@ -995,13 +1016,13 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
       bestidx[ci] = 0x7fffffff;
     }
     int total;
-    const int excl = block_excl_scan<NT>(cnt0 + cnt1, sh.tmp, total);
+    const int excl = block_excl_scan<NT, kSmall>(cnt0 + cnt1, sh.tmp, total);
     sh.scan[tid] = excl;
     sh.a0[tid] = st0;
     sh.a1[tid] = cnt0;
     sh.a2[tid] = st1;
     for (int d = excl; d < excl + cnt0 + cnt1 && d < kCmap<NT>; ++d) sh.cmap[d] = (SlotMap<NT>)tid;
-    __syncthreads();
+    bar();
     const int nj = min((int)NT, (int)(nc - c0));
     for (int d0 = 0; d0 < total; d0 += NT) {
       const int d = d0 + tid;
@@ -1032,9 +1053,14 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
       push_combo(sh, combo, S.combo_cap, r);
       atomicMax(&bestn[c], r.n);
     }
-    __syncthreads();
+    bar();
   }
   unsigned ncb = sh.ncombo;
+  // the combinations beyond the LDS key list are read from their global
+  // records by other threads below
+  if constexpr (kSmall) {
+    if (ncb > (unsigned)kComboLds) __syncthreads();
+  }
   if (ncb > (unsigned)S.combo_cap) {
     if (tid == 0) { raise_flag(cnt, F_COMBO); atomicMax(&S.need[7], ncb); }
     ncb = S.combo_cap;
@@ -1055,12 +1081,13 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
     const int c = key_c(i);
     if (key_n(i) == bestn[c]) atomicMin(&bestchi[c], key_chi(i));
   }
+  // __syncthreads: the winners' records are read by other threads below
   __syncthreads();
   for (unsigned i = tid; i < ncb; i += NT) {
     const int c = key_c(i);
     if (key_n(i) == bestn[c] && key_chi(i) == bestchi[c]) atomicMin(&bestidx[c], key_tb(i));
   }
-  __syncthreads();
+  bar();
   // the seed record of winning combination i
   auto make_seed = [&](unsigned i) {
     // the track index from the key list, so that the candidate and the
@@ -1122,10 +1149,12 @@ __device__ __forceinline__ void seed_rest(const float *X, const float *Z, const 
       slot = wave_append(&sh.nseed);
       sh.u.skey[slot] = st.key;
     }
-    __syncthreads();
+    // LDS only: the keys and the pool range pass through LDS; the records
+    // go to the pool for later launches
+    lds_barrier();
     const unsigned ns = sh.nseed;
     claim_pool(ns);
-    __syncthreads();
+    lds_barrier();
     const unsigned long long base = sh.pbase;
     if (win && base + ns <= (unsigned long long)S.pool_cap)
       gstore(&S.pool[base + rank_of(sh.u.skey, ns, st.key, slot)], st.s);
@@ -1198,7 +1227,11 @@ __device__ __forceinline__ void seed_item(const float *X, const float *Z, const 
       }
     }
   }
-  __syncthreads();
+  // LDS only: the candidate records in global memory are read by other
+  // threads only after a __syncthreads (the vote's in the global form, the
+  // one before the UV search in the LDS form), so their stores complete
+  // behind the vote
+  lds_barrier();
   unsigned nc = sh.ncand;
   if (nc > (unsigned)S.cand_cap) {
     if (tid == 0) { raise_flag(cnt, F_CAND); atomicMax(&S.need[1], nc); }
@@ -1886,15 +1919,15 @@ __device__ __forceinline__ unsigned prepare_batch(const Desc *__restrict__ D,
     const int i = i0 + (int)threadIdx.x;
     stat(i, i < n ? zo[i * kNL] : 0, i < n ? zo[i * kNL + kNL] : 0);
   }
-  // no memory access moves above this point
+  // From here to the order's records nothing passes through global memory
+  // between threads: the barriers order LDS only.  The middle offsets are
+  // needed only for those records; their loads (eleven per item, 48 B apart)
+  // take the workgroup's memory path several microseconds to issue, so they
+  // are issued after the histogram's barrier (by wave 0 after the cut) and
+  // stream in behind the cut and the scan; with a 16-byte aligned offset
+  // array they are three 16-byte loads per item.
+  lds_barrier();
   __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int c = 0; c < kPrepCache; ++c) {
-    const int i = c * (int)blockDim.x + (int)threadIdx.x;
-#pragma unroll
-    for (int k = 1; k < kNL; ++k) zc[c][k] = i < n ? zo[i * kNL + k] : 0;
-  }
-  __syncthreads();
   // the cut: wave 0, one lane per octave; its count, summed latency and
   // largest size from its fine classes; prefix maximum of the latencies below
   // an octave, suffix sum and maximum from it upwards, then the argmin of T
@@ -1949,15 +1982,41 @@ __device__ __forceinline__ unsigned prepare_batch(const Desc *__restrict__ D,
     }
     if (b == 0) s_best = tb < t_none ? bb : 32;
   }
+  __builtin_amdgcn_sched_barrier(0);
+  if ((reinterpret_cast<uintptr_t>(D->b.zone_off) & 15u) == 0u) {
+    // an item's offsets start 48 B apart: three 16-byte loads each
+    static_assert(kNL == 12, "an item's twelve zone offsets are three 16-byte pieces");
+    const auto *z4 = (const __attribute__((address_space(1))) gvec4 *)D->b.zone_off;
+#pragma unroll
+    for (int c = 0; c < kPrepCache; ++c) {
+      const int i = c * (int)blockDim.x + (int)threadIdx.x;
+      gvec4 q0 = {0, 0, 0, 0}, q1 = q0, q2 = q0;
+      if (i < n) {
+        q0 = z4[3 * i];
+        q1 = z4[3 * i + 1];
+        q2 = z4[3 * i + 2];
+      }
+      zc[c][1] = q0.y; zc[c][2] = q0.z; zc[c][3] = q0.w;
+      zc[c][4] = q1.x; zc[c][5] = q1.y; zc[c][6] = q1.z; zc[c][7] = q1.w;
+      zc[c][8] = q2.x; zc[c][9] = q2.y; zc[c][10] = q2.z; zc[c][11] = q2.w;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < kPrepCache; ++c) {
+      const int i = c * (int)blockDim.x + (int)threadIdx.x;
+#pragma unroll
+      for (int k = 1; k < kNL; ++k) zc[c][k] = i < n ? zo[i * kNL + k] : 0;
+    }
+  }
   // first position of each fine class: the items of all larger classes
   {
     const int f = kFineCls - 1 - (int)threadIdx.x;   // descending
     const int v = f >= 0 ? fh[f] : 0;
     int total;
-    const int ex = block_excl_scan<1024>(v, s_scan, total);
+    const int ex = block_excl_scan<1024, true>(v, s_scan, total);
     if (f >= 0) fb[f] = ex;
   }
-  __syncthreads();
+  lds_barrier();
   if (threadIdx.x == 0) {
     const int best = s_best;
     // the big form takes the classes >= best: the positions before the
@@ -1966,7 +2025,7 @@ __device__ __forceinline__ unsigned prepare_batch(const Desc *__restrict__ D,
     S.cnt->n_big = nb;
     s_best = (int)nb;
   }
-  __syncthreads();
+  lds_barrier();
   const unsigned n_big = (unsigned)s_best;
   // positions in the order, one LDS atomic per item on its fine class; each
   // position's record holds the item and its zone offsets
@@ -2124,7 +2183,9 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
       if (!first) __builtin_amdgcn_s_setprio(0);
     }
     first = false;
-    __syncthreads();
+    // LDS only: what the workgroup's last item left in global memory (its
+    // seeds) is read by later launches, not by this workgroup
+    lds_barrier();
     const int item = sh.item;
     if (item < 0) break;
     const int base = sh.zabs[0];
@@ -2145,7 +2206,7 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
         S.item_cnt[item] = 0;
         S.item_base[item] = 0;
       }
-      __syncthreads();
+      lds_barrier();
     } else if (nh <= lds_hits) {
       // stage the item's hits; every bin entry starts at its zone's size
       for (int i = tid; i < nh; i += NT) {
@@ -2157,7 +2218,7 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
         const int L = i / kBins;
         sh.bins[L][i % kBins] = (unsigned short)(sh.zabs[L + 1] - sh.zabs[L]);
       }
-      __syncthreads();
+      lds_barrier();
       // hit i opens the bins in (kbin(previous hit), kbin(hit i)]
       int zb[kNL];
 #pragma unroll
@@ -2171,10 +2232,10 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
         const int kp = li > 0 ? kbin(s_x[i - 1]) : 0;
         for (int b = kp; b < kc; ++b) sh.bins[L][b] = (unsigned short)li;
       }
-      __syncthreads();
+      lds_barrier();
       seed_item<true, kUv>(s_x, s_z, s_id, item, nh, P, S, wg, sh);
     } else {
-      __syncthreads();
+      lds_barrier();
       seed_item<false, kUv>(hx + base, hz + base, hid + base, item, nh, P, S, wg, sh);
     }
     // hand-off: after the barrier, one release increment of the per-event
@@ -2182,7 +2243,8 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
     // and the release compose); the workgroup that completes the event's
     // second half acquires once and matches.  One L2 write-back per item and
     // one invalidate per event, instead of a device-wide fence per wave.
-    __syncthreads();
+    // Without the hand-off the next item only reuses the LDS.
+    if (kFuse && fuse) __syncthreads(); else lds_barrier();
     if (!kFuse || !fuse) continue;
     if (tid == 0) {
       const int prev = __hip_atomic_fetch_add(&S.ev_done[item >> 1], 1, __ATOMIC_RELEASE,
