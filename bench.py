@@ -506,6 +506,16 @@ def main():
         plain = args.plain_steps * host.n_events / (time.perf_counter() - tp)
         log(f"[bench] plain: {plain:.0f} events/s")
 
+    # serving before the large legs: after the stress batch-size sweep has
+    # taken and released most of the device's memory, the served capacity
+    # measured lower (1.2-1.3 M against 1.74 M events/s)
+    serve = None
+    if pool is not None:
+        loads = [float(x) for x in args.serve_loads.split(",") if x]
+        serve = serve_stream(ctx, sm, pool, args.serve_requests, loads, args.serve_plain)
+        log(f"[bench] served: capacity {serve['capacity_events_per_s']:.0f} events/s, "
+            f"copies {serve['copy_bandwidth']}")
+
     # further workloads at their stated sizes (uneven: all events against the
     # oracle; stress: events 0-499)
     leg_res = {}
@@ -533,12 +543,6 @@ def main():
         del lh
     leg_hosts.clear()
 
-    serve = None
-    if pool is not None:
-        loads = [float(x) for x in args.serve_loads.split(",") if x]
-        serve = serve_stream(ctx, sm, pool, args.serve_requests, loads, args.serve_plain)
-        log(f"[bench] served: capacity {serve['capacity_events_per_s']:.0f} events/s, "
-            f"copies {serve['copy_bandwidth']}")
     if args.calib_copy_mb > 0:
         n = args.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
