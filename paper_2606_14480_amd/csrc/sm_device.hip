@@ -1732,6 +1732,15 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   // probability lower by the clone gap or more.
   unsigned long long *kkey =
       nsv <= (unsigned)kSurvLds ? sh.kkey : (unsigned long long *)(surv + S.surv_cap);
+  // The long tracks go out in (VELO state, seed) order.  When the event's
+  // VELO states fit one per thread, a key's place is the count of kept pairs
+  // on lower VELO states (a count per state and its scan, in the pair
+  // search's window arrays, free now) plus, on a state with several (exact
+  // chi2 ties, or the network form), the count of its lower seeds; else the
+  // key's rank among all keys.
+  const bool vrank = nv <= kVflat && nv <= NT;
+  int *vcnt = sh.vk0, *vbase = sh.vscan;
+  if (vrank && tid < nv) vcnt[tid] = 0;
   for (unsigned i = tid; i < nsv; i += NT) {
     const Surv sv = i < (unsigned)kSurvLds ? sh.surv[i] : gload(&surv[i - kSurvLds]);
     const unsigned long long bits = (unsigned long long)__double_as_longlong(sv.chi2);
@@ -1751,6 +1760,8 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
   }
   __syncthreads();
   const unsigned nk = sh.nkeep;
+  if (vrank)
+    for (unsigned i = tid; i < nk; i += NT) atomicAdd(&vcnt[(int)(kkey[i] >> 32)], 1);
   if (tid == 0) {
     if (plain) {
       const long long lo = D->long_off[e];
@@ -1771,12 +1782,29 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     }
   }
   __syncthreads();
+  if (vrank) {
+    int total;
+    const int ex = block_excl_scan<NT, true>(tid < nv ? vcnt[tid] : 0, sh.tmp, total);
+    if (tid < nv) vbase[tid] = ex;
+    lds_barrier();
+  }
   const unsigned long long lb = sh.lbase;
   const long long cap = plain ? D->long_cap : S.lpool_cap;
   sm_long *dst = plain ? D->longs : S.lpool;
   for (unsigned i = tid; i < nk; i += NT) {
     const unsigned long long key = kkey[i];
-    const unsigned r = rank_of(kkey, nk, key, i);
+    unsigned r;
+    if (vrank) {
+      const unsigned vk = (unsigned)(key >> 32);
+      r = (unsigned)vbase[vk];
+      if (vcnt[vk] > 1)
+        for (unsigned j = 0; j < nk; ++j) {
+          const unsigned long long u = kkey[j];
+          r += (unsigned)((u >> 32) == vk && u < key);
+        }
+    } else {
+      r = rank_of(kkey, nk, key, i);
+    }
     if ((long long)(lb + r) >= cap) continue;
     const int vi = (int)(key >> 32), si = (int)(key & 0xffffffffu);
     const int v = v0 + vi;
