@@ -1543,8 +1543,61 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     best_s[i] = ~0ull;
   }
   __syncthreads();
-  // seeds sorted by t_y, so each VELO state visits only its |dty| window
-  if (fits) {
+  // seeds sorted by t_y (ties by index), so each VELO state visits only its
+  // |dty| window.  Up to 256 seeds: each wave sorts 64 (t_y, index) keys in
+  // registers (bitonic, lane exchanges), and a key's place is its place in
+  // its wave plus, by binary search, the keys below it in the other waves'
+  // sorted runs (in the final selection's key space, free until then).  More
+  // seeds: each seed's rank among all.
+  if (fits && ns <= 256) {
+    unsigned long long *run = sh.kkey;
+    static_assert(kSurvLds >= 256, "four sorted runs of 64 keys");
+    const int lane = tid & 63, w = tid >> 6, nrun = (ns + 63) >> 6;
+    if (tid < 256) {
+      unsigned long long k = ~0ull;   // past the seeds: sorts last
+      if (tid < ns) {
+        float t = tyf[tid];
+        if (t == 0.0f) t = 0.0f;      // -0 and +0 tie, as they compare
+        unsigned b = __float_as_uint(t);
+        b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);   // float order as unsigned order
+        k = ((unsigned long long)b << 32) | (unsigned)tid;
+      }
+#pragma unroll
+      for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+          const unsigned long long o = __shfl_xor(k, stride, 64);
+          const bool keep_min = ((lane & stride) == 0) == ((lane & size) == 0);
+          k = keep_min ? (o < k ? o : k) : (o > k ? o : k);
+        }
+      }
+      if (w < nrun) run[tid] = k;
+    }
+    lds_barrier();
+    if (tid < 256 && w < nrun) {
+      const unsigned long long k = run[tid];
+      if (k != ~0ull) {
+        unsigned r = (unsigned)lane;
+        int lo[4] = {0, 0, 0, 0}, hi[4] = {64, 64, 64, 64};
+        // lower bound in each other run: seven halvings of 64
+#pragma unroll
+        for (int step = 0; step < 7; ++step) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            if (c < nrun && c != w && lo[c] < hi[c]) {
+              const int m = (lo[c] + hi[c]) >> 1;
+              if (run[c * 64 + m] < k) lo[c] = m + 1; else hi[c] = m;
+            }
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) r += (c < nrun && c != w) ? (unsigned)lo[c] : 0u;
+        const unsigned b = (unsigned)(k >> 32);
+        sty[r] = __uint_as_float((b & 0x80000000u) ? (b & 0x7fffffffu) : ~b);
+        sidx[r] = (int)(unsigned)k;
+      }
+    }
+  } else if (fits) {
     for (int i = tid; i < ns; i += NT) {
       const float t = tyf[i];
       const int r = (int)rank_of(tyf, (unsigned)ns, t, (unsigned)i);
