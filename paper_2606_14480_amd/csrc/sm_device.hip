@@ -1542,7 +1542,10 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     xsf[i] = m.xsf; txsf[i] = m.txsf; ymf[i] = m.y_mf; tyf[i] = m.tyf;
     best_s[i] = ~0ull;
   }
-  __syncthreads();
+  // LDS only when the per-seed arrays are in LDS: the seed states' global
+  // records are read by other threads only after the __syncthreads that ends
+  // the t_y order, so their stores complete behind the sort
+  if (sm_s) lds_barrier(); else __syncthreads();
   // seeds sorted by t_y (ties by index), so each VELO state visits only its
   // |dty| window.  Up to 256 seeds: each wave sorts 64 (t_y, index) keys in
   // registers (bitonic, lane exchanges), and a key's place is its place in
