@@ -262,24 +262,30 @@ void sm_default_geometry(sm_geometry *g);
 void sm_default_params(sm_params *p);
 
 /* Creates a context on cfg->device (NULL cfg: all defaults).  Allocates the
- * scratch, serving slots and streams it owns.  SM_ERR_OOM if the device
- * memory or cfg->mem_budget is too small. */
+ * scratch, serving slots and streams it owns (the hits stay resident in
+ * device memory across the steps of a batch, Sec. 5.2).  SM_ERR_OOM if the
+ * device memory or cfg->mem_budget is too small. */
 sm_status sm_create(const sm_geometry *g, const sm_params *p, const sm_config *cfg,
                     sm_ctx **out);
 
-/* Seeding + Matching of a whole batch as ONE persistent launch per kernel,
- * replayed from a captured HIP graph, with workgroups pulling (event, half)
- * items longest-first from a device work queue.  Blocks until done
- * (stream-ordered after prior work on `stream`). */
+/* Seeding (Sec. 3) + Matching (Sec. 4) of a whole batch: events processed
+ * together, as the batches of about a thousand events of Sec. 5.3, here as
+ * ONE persistent launch per kernel, replayed from a captured HIP graph, with
+ * workgroups pulling (event, half) items longest-first from a device work
+ * queue.  Blocks until done (stream-ordered after prior work on `stream`). */
 sm_status sm_run(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream);
 
 /* The same computation launched as one kernel sequence per event (the plain
- * form); bit-identical results to sm_run.  Blocks until done. */
+ * form: Sec. 5.3's event-level parallelism left out, thread-level kept);
+ * bit-identical results to sm_run.  Blocks until done. */
 sm_status sm_run_plain(sm_ctx *ctx, const sm_batch *batch, sm_out *out, void *stream);
 
 /* Serving: starts the batch on a free slot (its own stream) and returns at
  * once with a ticket; SM_ERR_BUSY if no slot is free.  batch and out must stay
- * valid until sm_poll reports completion. */
+ * valid until sm_poll reports completion.  Batches on different slots run on
+ * the device at the same time (continuous batching of arriving batches; the
+ * paper's trigger feeds its cards batches of events, Sec. 5.3, and states no
+ * serving loop). */
 sm_status sm_submit(sm_ctx *ctx, const sm_batch *batch, sm_out *out, int64_t *ticket);
 
 /* SM_OK once the ticket's batch is done (out->n_seeds / n_longs filled),
@@ -291,10 +297,10 @@ sm_status sm_poll(sm_ctx *ctx, int64_t ticket, int wait);
  * `stream` between the kernels (milliseconds): counters and item order,
  * with the big-item form when one launch does both (then seed_big is 0);
  * the big-item seeding form; the main seeding form built without the
- * matching code (seed) and the one with it (seed_fused), of which the one
- * that does not fit the batch returns at once; the matching kernel (which
- * returns at once when Matching ran inside seeding); the offset scans and
- * copy to the caller's buffers; and the whole sequence. */
+ * matching code (seed) and the one with it (seed_fused), of which only the
+ * one that fits the batch is launched (the other's interval is empty); the
+ * matching kernel (not launched when Matching runs inside seeding); the
+ * offset scans and copy to the caller's buffers; and the whole sequence. */
 typedef struct {
   float prepare, seed_big, seed, seed_fused, match, copy, total;
 } sm_kernel_times;
