@@ -2219,8 +2219,9 @@ __global__ __launch_bounds__(NT, NT == kSeedWG ? 4 : 1) void k_seed(const Desc *
   const int n_big = use_queue ? (int)S.cnt->n_big : 0;
   // matching here (hand-off to the workgroup completing an event) or in
   // k_match; the main form has one instantiation with the matching code and
-  // one without (which keeps the seeding phases' registers free of it), and
-  // the one that does not fit the batch returns at once
+  // one without (which keeps the seeding phases' registers free of it); the
+  // host launches the one that fits the batch, and the other would return
+  // at once
   const bool fuse = use_queue ? S.cnt->fuse != 0u : true;
   if (!kBig && fuse != kFuse) return;
   // queue of this form: the big items [0, n_big) or the rest of the order

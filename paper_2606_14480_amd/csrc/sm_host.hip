@@ -239,7 +239,7 @@ sm_status dalloc(Slot &s, T **p, size_t n, int64_t &bytes) {
 
 // (Re)allocate all scratch of a slot for its current caps.
 sm_status alloc_slot(sm_ctx *c, Slot &s) {
-  destroy_graphs(s);   // their counter copy-back names the old counters
+  destroy_graphs(s);   // no graph outlives the scratch it was captured with
   free_slot_scratch(s);
   int64_t bytes = 0;
   const size_t G = (size_t)c->seed_wgs;
