@@ -97,6 +97,10 @@ struct Desc {
   // batch (b then holds the hits left)
   int pass;
   unsigned serial;
+  // 1: the matching kernel writes each event's seeds and seed offset (its
+  // first seed follows every earlier event's: their counts are known once
+  // seeding is done) and the copy kernel only the long tracks and totals
+  int mseeds, pad5;
 };
 
 // Parameters in the precision each kernel uses.

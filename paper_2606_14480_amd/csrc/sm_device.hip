@@ -1452,7 +1452,7 @@ __global__ __launch_bounds__(256) void k_validate(const Desc *__restrict__ D, co
 // bit 0 the network form of the final selection, bit 1 the UT search (each
 // variant an instantiation of its own, so that the default one carries none
 // of their registers or LDS).
-template <bool kSmallM, int NT, int kSel>
+template <bool kSmallM, int NT, int kSel, bool kMk = false>
 __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, const Scratch &S,
                                                  const DevParams &P, int e, int plain, size_t wg,
                                                  MatchShared &sh) {
@@ -1481,6 +1481,21 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     return &S.pool3[b3 + i - n0 - n1 - n2];
   };
   const int v0 = gmem(D->b.velo_off)[e], nv = gmem(D->b.velo_off)[e + 1] - v0;
+  // the matching kernel (kMk) with mseeds: the event's seeds go to the
+  // caller from here, after every earlier event's seeds; each wave's share
+  // of that count is in sh.tmp[8 + wave] (free of the block scans) until the
+  // end
+  const bool mseeds = kMk && NT <= 512 && !plain && D->mseeds != 0;
+  if (mseeds) {
+    int sp = 0;
+    for (int j = tid; j < e; j += NT) {
+      sp += gmem(S.item_cnt)[2 * j] + gmem(S.item_cnt)[2 * j + 1];
+      if (t3) sp += gmem(S.item_cnt3)[2 * j] + gmem(S.item_cnt3)[2 * j + 1];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sp += __shfl_xor(sp, o, 64);
+    if ((tid & 63) == 0) sh.tmp[8 + (tid >> 6)] = sp;
+  }
   const bool pool_ok = !(cnt->flags & F_POOL);
   const int so = plain ? D->seed_off[e] : 0;
   if (tid == 0 && plain) D->seed_off[e + 1] = so + ns;
@@ -1884,11 +1899,20 @@ __device__ __forceinline__ void match_event_impl(const Desc *__restrict__ D, con
     else gstore(&dst[lb + r], L);
   }
   if (plain && tid == 0 && (long long)(lb + nk) > D->long_cap) raise_flag(cnt, F_OUT_LONG);
+  if (mseeds) {
+    int sb = 0;   // the event's first seed
+#pragma unroll
+    for (int i = 0; i < (NT <= 512 ? NT / 64 : 1); ++i) sb += sh.tmp[8 + i];
+    if (tid == 0) D->seed_off[e] = (int32_t)sb;
+    if (pool_ok && (long long)sb + ns <= D->seed_cap)
+      for (int i = tid; i < ns; i += NT) D->seeds[sb + i] = gload(seed_at(i));
+  }
 }
 
 // ----------------------------------------------------- the fused kernel ----
 
-template <int NT, int kSel>
+// (kMk: called by the matching kernel, which may also write the seeds)
+template <int NT, int kSel, bool kMk = false>
 __device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Scratch &S,
                                             const DevParams &P, int e, int plain, size_t wg,
                                             MatchShared &sh) {
@@ -1896,9 +1920,9 @@ __device__ __forceinline__ void match_event(const Desc *__restrict__ D, const Sc
   if (D->pass == 1) ns += S.item_cnt3[2 * e] + S.item_cnt3[2 * e + 1];
   const int nv = D->b.velo_off[e + 1] - D->b.velo_off[e];
   if (ns <= kMsLds && nv <= kVsLds)
-    match_event_impl<true, NT, kSel>(D, S, P, e, plain, wg, sh);
+    match_event_impl<true, NT, kSel, kMk>(D, S, P, e, plain, wg, sh);
   else
-    match_event_impl<false, NT, kSel>(D, S, P, e, plain, wg, sh);
+    match_event_impl<false, NT, kSel, kMk>(D, S, P, e, plain, wg, sh);
 }
 
 // The preparing launch's copy of the batch descriptor from pinned host
@@ -2369,7 +2393,7 @@ __global__ __launch_bounds__(kSeedWG, 4) void k_match(const Desc *__restrict__ D
     __syncthreads();
     const int e = s_e;
     if (e >= D->n_events) break;
-    match_event<kSeedWG, kSel>(D, S, P, e, 0, blockIdx.x, mh);
+    match_event<kSeedWG, kSel, true>(D, S, P, e, 0, blockIdx.x, mh);
     __syncthreads();
   }
 }
@@ -2406,6 +2430,9 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
   // with the third iteration, each event's seeds also come from its two
   // items in the third pool, after the first two iterations' ones
   const bool t3 = D->pass == 1;
+  // the matching kernel wrote the seeds and their offsets (mseeds), unless
+  // the input was rejected before matching
+  const bool ms = D->mseeds != 0 && !(S.cnt->flags & (F_INVALID | F_UNSORTED));
   auto seeds3 = [&](int e) {
     return t3 ? gmem(S.item_cnt3)[2 * e] + gmem(S.item_cnt3)[2 * e + 1] : 0;
   };
@@ -2455,7 +2482,7 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
     __syncthreads();
     const int xl = block_excl_scan<256>(m, s_tmp, tl);
     if (e < e_hi) {
-      D->seed_off[e] = (int32_t)(cs + xs);
+      if (!ms) D->seed_off[e] = (int32_t)(cs + xs);
       D->long_off[e] = (int32_t)(cl + xl);
       if (one) {
         s_n0[tid] = n0; s_n1[tid] = n1; s_m[tid] = m;
@@ -2509,10 +2536,10 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
       b0 = gmem(S.item_base)[2 * e]; b1 = gmem(S.item_base)[2 * e + 1]; src = gmem(S.ev_lbase)[e];
       so = D->seed_off[e]; dst = D->long_off[e];
     }
-    if (so + n0 + n1 <= D->seed_cap)
+    if (!ms && so + n0 + n1 <= D->seed_cap)
       for (int i = tid; i < n0 + n1; i += 256)
         D->seeds[so + i] = gload(i < n0 ? &S.pool[b0 + i] : &S.pool[b1 + i - n0]);
-    if (t3) {
+    if (t3 && !ms) {
       // the third iteration's seeds of the event: half 0, then half 1
       const int m0 = gmem(S.item_cnt3)[2 * e], m1 = gmem(S.item_cnt3)[2 * e + 1];
       const int c0 = gmem(S.item_base3)[2 * e], c1 = gmem(S.item_base3)[2 * e + 1];

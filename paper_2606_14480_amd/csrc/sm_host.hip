@@ -380,6 +380,10 @@ sm_status alloc_slot(sm_ctx *c, Slot &s) {
 // a call gives up with SM_ERR_CAPACITY.
 constexpr int kMaxTries = 8;
 
+// Batches of up to this many events have their seeds written by the matching
+// kernel (and only their long tracks by the copy kernel).
+constexpr int kMatchSeedsEvents = 4096;
+
 bool grow(int &cap, unsigned need) {
   if (need == 0) need = (unsigned)cap + 1;
   long long n = cap;
@@ -510,6 +514,7 @@ void fill_desc(Desc &d, const sm_batch &b, const sm_out &o, int grid, int fuse, 
   d.fuse = fuse;
   d.pass = pass;
   d.serial = serial;
+  d.mseeds = 0;
 }
 
 // The slot's descriptors for one batch: the batch itself and, with the third
@@ -523,6 +528,9 @@ void fill_descs(sm_ctx *c, Slot &s, const sm_batch &b, const sm_out &o) {
     if (serial == 0) serial = ++c->serial;   // 0 is the marks' initial value
   }
   fill_desc(*s.h_desc, b, o, s.grid, s.fuse, third ? 1 : 0, serial);
+  // the matching kernel writes the seeds itself: each event adds up the
+  // earlier events' seed counts, so only for batches of a few thousand
+  s.h_desc->mseeds = !s.fuse && b.n_events <= kMatchSeedsEvents ? 1 : 0;
   if (third) {
     Desc &d3 = *s.h_desc3;
     d3 = *s.h_desc;
@@ -532,6 +540,7 @@ void fill_descs(sm_ctx *c, Slot &s, const sm_batch &b, const sm_out &o) {
     d3.b.hit_id = s.T.hid;
     d3.pass = 2;
     d3.fuse = 0;
+    d3.mseeds = 0;
   }
 }
 
