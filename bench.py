@@ -56,13 +56,20 @@ def seed_kernel_bytes(b, n_seeds: int) -> int:
     return 12 * b.n_hits + (64 + 8) * 2 * b.n_events + 96 * n_seeds
 
 
+# batches of up to this many events have their seeds written to the outputs by
+# the matching kernel (the copy kernel then moves only the long tracks)
+MATCH_SEEDS_EVENTS = 4096
+
+
 def match_kernel_bytes(b, n_seeds: int, n_longs: int) -> int:
     """Algorithmic HBM bytes of one launch of the matching kernel: per event
     the two items' seed counts and pool offsets, two VELO offsets and its
     long-track count and pool offset (32 B), the VELO states (x, y, z, tx, ty,
-    id: 24 B each), five fields of each seed (20 B), and per long track its
-    64 B record."""
-    return 32 * b.n_events + 24 * b.n_velo + 20 * n_seeds + 64 * n_longs
+    id: 24 B each), per long track its 64 B record, and per seed five fields
+    (20 B), or, when the kernel also writes the seeds to the outputs, its
+    96 B record read and written."""
+    per_seed = 2 * 96 if b.n_events <= MATCH_SEEDS_EVENTS else 20
+    return 32 * b.n_events + 24 * b.n_velo + per_seed * n_seeds + 64 * n_longs
 
 
 def cpu_model() -> str:
