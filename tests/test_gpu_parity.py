@@ -582,6 +582,26 @@ def test_ut_search_parity(orc, sm, ctx, variant):
     assert len(ref[3]) > len(g[3])
 
 
+def test_large_batch_matching_kernel(orc, sm):
+    """Batches of up to 4096 events have their seeds written by the matching
+    kernel, larger ones by the copy kernel: 4200 min-bias events forced
+    through the matching kernel against the oracle, and the same bytes with
+    matching inside the seeding kernel."""
+    b = ev.generate(ev.config(2, n_events=4200))
+    c = sm.Context(match_wgs=1024)
+    try:
+        g, _, _ = check(orc, sm, c, b, "4200 events, matching kernel")
+    finally:
+        c.close()
+    c = sm.Context(match_wgs=-1)
+    try:
+        g2 = gpu_run(sm, c, b)
+    finally:
+        c.close()
+    for x, y in zip(g, g2):
+        assert x.tobytes() == y.tobytes()
+
+
 def test_third_iteration_parity(orc, sm):
     """The third x-z iteration with clean-up against the oracle on 300
     min-bias events: the first two iterations' seeds, the third's (iteration
