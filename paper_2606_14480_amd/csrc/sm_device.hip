@@ -2438,6 +2438,17 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
   };
   __shared__ long long s_part[2][4];
   __shared__ int s_tmp[16];
+  // the first pass's counts and pool bases of this range, issued with the
+  // loads below (one round trip for both: clamped addresses, no branch, and
+  // nothing computed from them before the prefix is reduced)
+  int f_n0 = 0, f_n1 = 0, f_m = 0, f_n3a = 0, f_n3b = 0, f_b0 = 0, f_b1 = 0, f_src = 0;
+  if (e_lo < e_hi) {
+    const int e = min(e_lo + tid, e_hi - 1);
+    f_n0 = gmem(S.item_cnt)[2 * e]; f_n1 = gmem(S.item_cnt)[2 * e + 1]; f_m = gmem(S.ev_lcnt)[e];
+    f_b0 = gmem(S.item_base)[2 * e]; f_b1 = gmem(S.item_base)[2 * e + 1];
+    f_src = gmem(S.ev_lbase)[e];
+    if (t3) { f_n3a = gmem(S.item_cnt3)[2 * e]; f_n3b = gmem(S.item_cnt3)[2 * e + 1]; }
+  }
   // the counts of the events before this range, four loads in flight per
   // thread at a time (independent accumulators, clamped addresses)
   long long ps = 0, pl = 0;
@@ -2470,13 +2481,19 @@ __global__ __launch_bounds__(256) void k_copy(const Desc *__restrict__ D,
   const bool one = e_hi - e_lo <= 256;
   for (int c0 = e_lo; c0 < e_hi; c0 += 256) {
     const int e = c0 + tid;
-    int n0 = 0, n1 = 0, m = 0;
-    long long b0 = 0, b1 = 0, src = 0;
-    if (e < e_hi) {
-      n0 = gmem(S.item_cnt)[2 * e]; n1 = gmem(S.item_cnt)[2 * e + 1]; m = gmem(S.ev_lcnt)[e];
-      b0 = gmem(S.item_base)[2 * e]; b1 = gmem(S.item_base)[2 * e + 1]; src = gmem(S.ev_lbase)[e];
+    const bool in = e < e_hi;
+    int n0 = in ? f_n0 : 0, n1 = in ? f_n1 : 0, m = in ? f_m : 0, n3 = in ? f_n3a + f_n3b : 0;
+    long long b0 = in ? f_b0 : 0, b1 = in ? f_b1 : 0, src = in ? f_src : 0;
+    if (c0 != e_lo) {
+      n0 = n1 = m = n3 = 0;
+      b0 = b1 = src = 0;
+      if (e < e_hi) {
+        n0 = gmem(S.item_cnt)[2 * e]; n1 = gmem(S.item_cnt)[2 * e + 1]; m = gmem(S.ev_lcnt)[e];
+        b0 = gmem(S.item_base)[2 * e]; b1 = gmem(S.item_base)[2 * e + 1];
+        src = gmem(S.ev_lbase)[e];
+        n3 = seeds3(e);
+      }
     }
-    const int n3 = e < e_hi ? seeds3(e) : 0;
     int ts, tl;
     const int xs = block_excl_scan<256>(n0 + n1 + n3, s_tmp, ts);
     __syncthreads();
