@@ -299,8 +299,10 @@ sm_status sm_poll(sm_ctx *ctx, int64_t ticket, int wait);
  * the big-item seeding form; the main seeding form built without the
  * matching code (seed) and the one with it (seed_fused), of which only the
  * one that fits the batch is launched (the other's interval is empty); the
- * matching kernel (not launched when Matching runs inside seeding); the
- * offset scans and copy to the caller's buffers; and the whole sequence. */
+ * matching kernel (not launched when Matching runs inside seeding; for
+ * batches of up to 4096 events it also writes the seeds to the caller's
+ * buffers); the offset scans and the copy of the rest to the caller's
+ * buffers; and the whole sequence. */
 typedef struct {
   float prepare, seed_big, seed, seed_fused, match, copy, total;
 } sm_kernel_times;
